@@ -1,0 +1,187 @@
+"""Seeded synthetic workloads (problem data only; no arithmetic of the method).
+
+This is the one module that both the HIP path and the CPU oracle use.  It
+draws the random parameters of each workload from NumPy's PCG64 generator and
+evaluates closed-form coefficient fields, initial data, exact solutions and
+manufactured sources at caller-supplied coordinates.  It never computes
+collocation nodes, derivative matrices or anything else of the solver.
+
+Workloads (all on the unit square, Dirichlet data):
+  heat        u_t = Lap u + q, exact u = sin(pi x) sin(pi y) e^{-t} (1 + 0.1 F(x,y)),
+              F a seeded mix of 8 Fourier modes, q = e^{-t} (-phi - Lap phi)
+              (the manufactured-solution setting of the paper's 2-D heat tests).
+  allen_cahn  u_t = div(a grad u) + u - u^3, a = 1 + 0.5 sin(2 pi x) cos(2 pi y),
+              u0 = seeded sine modes k, l <= 8 normalised to max |u0| = 1, f = 0.
+  batched     a seeded mix of heat / reaction problems with smooth a in [0.5, 1.5].
+"""
+import math
+
+import numpy as np
+
+SEED_BASE = 2306025260
+
+
+def rng_for(config_index, offset=0):
+    return np.random.default_rng(SEED_BASE + int(config_index) + int(offset))
+
+
+# ---------------------------------------------------------------------------------------
+# heat equation with a manufactured solution
+# ---------------------------------------------------------------------------------------
+class HeatManufactured:
+    """u(t,x,y) = e^{-t} phi(x,y), phi = sin(pi x) sin(pi y) (1 + 0.1 F),
+    F = sum_m alpha_m sin(pi (k_m x + l_m y) + ph_m); L = Laplacian, g = 0."""
+
+    def __init__(self, rng, n_modes=8, amp=0.1, kmax=4, coef=None):
+        self.k = rng.integers(1, kmax + 1, size=n_modes).astype(np.float64)
+        self.l = rng.integers(1, kmax + 1, size=n_modes).astype(np.float64)
+        self.ph = rng.uniform(0.0, 2.0 * math.pi, size=n_modes)
+        al = rng.uniform(-1.0, 1.0, size=n_modes)
+        self.alpha = al / np.sum(np.abs(al))
+        self.amp = amp
+        # optional variable diffusivity a(x,y) (None -> a = 1): L u = div(a grad u)
+        self.coef = coef
+
+    def _F(self, x, y):
+        th = math.pi * (np.multiply.outer(x, self.k) + np.multiply.outer(y, self.l)) + self.ph
+        F = np.sin(th) @ self.alpha
+        Fx = (np.cos(th) * (math.pi * self.k)) @ self.alpha
+        Fy = (np.cos(th) * (math.pi * self.l)) @ self.alpha
+        lapF = -(np.sin(th) * (math.pi ** 2) * (self.k ** 2 + self.l ** 2)) @ self.alpha
+        return F, Fx, Fy, lapF
+
+    def phi_parts(self, x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        pi = math.pi
+        s = np.sin(pi * x) * np.sin(pi * y)
+        sx = pi * np.cos(pi * x) * np.sin(pi * y)
+        sy = pi * np.sin(pi * x) * np.cos(pi * y)
+        lap_s = -2.0 * pi * pi * s
+        F, Fx, Fy, lapF = self._F(x, y)
+        m = 1.0 + self.amp * F
+        phi = s * m
+        phix = sx * m + s * self.amp * Fx
+        phiy = sy * m + s * self.amp * Fy
+        lap_phi = lap_s * m + 2.0 * self.amp * (sx * Fx + sy * Fy) + s * self.amp * lapF
+        return phi, phix, phiy, lap_phi
+
+    def phi(self, x, y):
+        return self.phi_parts(x, y)[0]
+
+    def exact(self, t, x, y):
+        return math.exp(-t) * self.phi(x, y)
+
+    def q_space(self, x, y):
+        """q(t,x,y) = q_time(t) * q_space(x,y) with q_time(t) = e^{-t}."""
+        phi, phix, phiy, lap_phi = self.phi_parts(x, y)
+        if self.coef is None:
+            Lphi = lap_phi
+        else:
+            a, ax, ay = self.coef(x, y)
+            Lphi = a * lap_phi + ax * phix + ay * phiy
+        return -phi - Lphi
+
+    @staticmethod
+    def q_time(t):
+        return math.exp(-t)
+
+    def L_coeffs(self, x, y):
+        """Coefficients (cxx, cyy, cx, cy, c0) of L u = cxx u_xx + cyy u_yy + cx u_x + cy u_y + c0 u."""
+        x = np.asarray(x, dtype=np.float64)
+        if self.coef is None:
+            one = np.ones_like(x)
+            zero = np.zeros_like(x)
+            return one, one.copy(), zero, zero.copy(), zero.copy()
+        a, ax, ay = self.coef(x, y)
+        return a, a.copy(), ax, ay, np.zeros_like(a)
+
+
+# ---------------------------------------------------------------------------------------
+# variable-coefficient Allen-Cahn
+# ---------------------------------------------------------------------------------------
+def allen_cahn_a(x, y):
+    """a = 1 + 0.5 sin(2 pi x) cos(2 pi y) and its exact gradient."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    tp = 2.0 * math.pi
+    a = 1.0 + 0.5 * np.sin(tp * x) * np.cos(tp * y)
+    ax = 0.5 * tp * np.cos(tp * x) * np.cos(tp * y)
+    ay = -0.5 * tp * np.sin(tp * x) * np.sin(tp * y)
+    return a, ax, ay
+
+
+class AllenCahn:
+    """u_t = div(a grad u) + u - u^3 on [0,1]^2, u = 0 on the boundary.
+    L u = a u_xx + a u_yy + a_x u_x + a_y u_y (non-divergence form of the same operator)."""
+
+    gpoly = (0.0, 1.0, 0.0, -1.0)
+
+    def __init__(self, rng, kmax=8):
+        self.c = rng.standard_normal((kmax, kmax))
+        self.kmax = kmax
+        xs = np.linspace(0.0, 1.0, 257)
+        X, Y = np.meshgrid(xs, xs, indexing="ij")
+        self.scale = 1.0 / np.max(np.abs(self._raw(X.ravel(), Y.ravel())))
+
+    def _raw(self, x, y):
+        k = np.arange(1, self.kmax + 1, dtype=np.float64)
+        sx = np.sin(math.pi * np.multiply.outer(x, k))
+        sy = np.sin(math.pi * np.multiply.outer(y, k))
+        return np.einsum("nk,kl,nl->n", sx, self.c, sy)
+
+    def u0(self, x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        return self.scale * self._raw(x.ravel(), y.ravel()).reshape(x.shape)
+
+    @staticmethod
+    def L_coeffs(x, y):
+        a, ax, ay = allen_cahn_a(x, y)
+        return a, a.copy(), ax, ay, np.zeros_like(a)
+
+
+# ---------------------------------------------------------------------------------------
+# smooth random diffusivity for the batched mix
+# ---------------------------------------------------------------------------------------
+class SmoothDiffusivity:
+    """a = 1 + 0.5 sum_m beta_m sin(2 pi (k_m x + l_m y) + ph_m), sum |beta| = 1, so a in [0.5, 1.5]."""
+
+    def __init__(self, rng, n_modes=4):
+        kl = []
+        while len(kl) < n_modes:
+            k, l = rng.integers(0, 3, size=2)
+            if k or l:
+                kl.append((float(k), float(l)))
+        self.k = np.array([v[0] for v in kl])
+        self.l = np.array([v[1] for v in kl])
+        self.ph = rng.uniform(0.0, 2.0 * math.pi, size=n_modes)
+        be = rng.uniform(-1.0, 1.0, size=n_modes)
+        self.beta = be / np.sum(np.abs(be))
+
+    def __call__(self, x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        tp = 2.0 * math.pi
+        th = tp * (np.multiply.outer(x, self.k) + np.multiply.outer(y, self.l)) + self.ph
+        a = 1.0 + 0.5 * (np.sin(th) @ self.beta)
+        ax = 0.5 * (np.cos(th) * (tp * self.k)) @ self.beta
+        ay = 0.5 * (np.cos(th) * (tp * self.l)) @ self.beta
+        return a, ax, ay
+
+
+def batched_mix(n_problems=256, config_index=4):
+    """Per-problem sizes and data for the batched workload: n in {8,16,32,64} per side,
+    p in {8,12,16}, gamma*dt in {1e-3,1e-2}, heat or Allen-Cahn type 50/50."""
+    out = []
+    for b in range(n_problems):
+        rng = rng_for(config_index, b)
+        n1 = int(rng.choice([8, 16, 32, 64]))
+        n2 = int(rng.choice([8, 16, 32, 64]))
+        p = int(rng.choice([8, 12, 16]))
+        gdt = float(rng.choice([1e-3, 1e-2]))
+        kind = "heat" if rng.uniform() < 0.5 else "allen_cahn"
+        coef = SmoothDiffusivity(rng)
+        out.append({"n1": n1, "n2": n2, "p": p, "gamma_dt": gdt, "kind": kind,
+                    "coef": coef, "rng": rng})
+    return out
