@@ -1,0 +1,161 @@
+/*
+ * hps.h - C ABI of the MI355X (gfx950) RKHPS per-stage solver.
+ *
+ * Method: Chen, Appelo, Babb & Martinsson, "Fast and high-order approximation
+ * of parabolic equations using hierarchical direct solvers and implicit
+ * Runge-Kutta methods" (arXiv 2306.02526).
+ *
+ *   u_t = L u + q + g(u)  in (0,T) x Omega,  u = f on the boundary      (eq. 1)
+ *   L u = cxx u_xx + cyy u_yy + cx u_x + cy u_y + c0 u   (eq. 3 with c12 = 0)
+ *
+ * Omega = [x0,x1] x [y0,y1] is split into n1 x n2 equal squares carrying p x p
+ * Chebyshev nodes each; corner nodes are dropped (Sec. 2.1).  Every implicit
+ * ESDIRK stage solves (I - gamma*dt*L) u_i = rhs_i (eq. 10) with the HPS
+ * direct solver, built once for the fixed gamma*dt and then reused.
+ *
+ * Conventions for every entry point
+ *   - Return value: HPS_OK (0) or a negative HPS_E* code; hps_last_error()
+ *     returns a thread-local message describing the last failure.
+ *   - "device" arrays are HIP device allocations (hipMalloc, or PyTorch CUDA
+ *     tensors); a host pointer where a device pointer is required is rejected
+ *     with HPS_EINVAL.  "host" arrays are ordinary host memory.
+ *   - All arrays are owned by the caller and only read or written during the
+ *     call (stream-ordered calls: until the given stream reaches that point).
+ *     Handles (hps_op, ark_ctx) are owned by the library; release them with
+ *     hps_free / ark_free.  One handle serves one stream at a time; calls on a
+ *     handle from two streams at once race.
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
+ *     enqueued on it; hps_build returns after the build has finished.
+ *   - Canonical node order of every length-N vector (N = n_int + n_edge):
+ *       1. leaf interiors: leaf (i, j) in order j*n1 + i, then its (p-2)^2
+ *          interior nodes row-major with x fastest;
+ *       2. vertical edges: grid line k = 0..n1, leaf row j, node ascending in y;
+ *       3. horizontal edges: grid line k = 0..n2, leaf column i, node
+ *          ascending in x.
+ *     Local Chebyshev nodes on a leaf [a, a+h] are a + h (1 - cos(m pi/(p-1)))/2.
+ *     n_int = n1 n2 (p-2)^2, n_edge = (p-2)(2 n1 n2 + n1 + n2)  (Sec. 2.1).
+ *     "boundary" vectors (length n_bdry = 2 (p-2)(n1+n2)) list the edge nodes on
+ *     the outer boundary in canonical order; "interface" vectors (length
+ *     n_iface = n_edge - n_bdry) list the remaining edge nodes in canonical order.
+ */
+#ifndef HPS_MI355X_H
+#define HPS_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HPS_API __attribute__((visibility("default")))
+
+#define HPS_OK              0
+#define HPS_EINVAL         -1   /* invalid argument (sizes, pointers, flags)        */
+#define HPS_ENOMEM         -2   /* device allocation failed                          */
+#define HPS_EDEVICE        -3   /* HIP runtime or kernel launch error                */
+#define HPS_ESINGULAR      -4   /* zero pivot while building an inverse              */
+#define HPS_ENOTCONVERGED  -5   /* iterative refinement did not reach its tolerance  */
+
+/* hps_build flags */
+#define HPS_FP64     0   /* stored operators and their application in FP64          */
+#define HPS_FP32_IR  1   /* FP64 build; operators applied in FP32 inside an FP64
+                            iterative-refinement loop (residual in FP64)           */
+
+typedef struct {
+    double x0, x1, y0, y1;   /* domain; (x1-x0)/n1 must equal (y1-y0)/n2 (square leaves) */
+    int32_t n1, n2;          /* leaves per direction, powers of two, n1*n2 <= 2^14      */
+    int32_t p;               /* Chebyshev nodes per leaf side, 3 <= p <= 24             */
+} hps_grid;
+
+/* Coefficients of L sampled at the n_int interior nodes (canonical order);
+ * device arrays.  A NULL member means that coefficient is zero. */
+typedef struct {
+    const double *cxx, *cyy, *cx, *cy, *c0;
+} hps_coeffs;
+
+typedef struct {
+    int32_t ir_iterations;    /* FP32_IR: correction solves used by the last call       */
+    double  last_correction;  /* FP32_IR: ||delta||_inf / ||u||_inf of the last one     */
+} hps_info;
+
+typedef struct hps_op  hps_op;
+typedef struct ark_ctx ark_ctx;
+
+/* Thread-local text of the last error (never NULL). */
+HPS_API const char *hps_last_error(void);
+
+/* Node counts of a grid (Sec. 2.1).  Returns N, or a negative error code.
+ * n_int / n_iface / n_bdry may be NULL. */
+HPS_API int64_t hps_num_nodes(const hps_grid *grid, int64_t *n_int, int64_t *n_iface, int64_t *n_bdry);
+
+/* Coordinates of the N nodes in canonical order; x, y are host arrays of N. */
+HPS_API int hps_nodes(const hps_grid *grid, double *x, double *y);
+
+/* Build the HPS solver for A = I - gamma_dt * L (eq. 10): leaf operators
+ * S = -A_ii^{-1} A_ib and DtN maps T (eqs. 5-6), then the merges
+ * S_tau = (T^a_33 - T^b_33)^{-1} [-T^a_31 | T^b_32] and
+ * T_tau = diag(T^a_11, T^b_22) + [T^a_13; T^b_23] S_tau up the tree (Sec. 2.1),
+ * all on the GPU in FP64.  gamma_dt > 0.  coeffs: device arrays (see above).
+ * Returns HPS_ESINGULAR if a pivot vanishes.  *out receives the handle. */
+HPS_API int hps_build(const hps_grid *grid, const hps_coeffs *coeffs, double gamma_dt, int flags,
+              void *stream, hps_op **out);
+
+/* Bytes of device memory held by the operator (stored operators + workspace). */
+HPS_API int64_t hps_op_bytes(const hps_op *op, int64_t *operator_bytes);
+
+/* Solve A u = body at interior nodes, u = dirichlet on the outer boundary and
+ * flux_alpha - flux_beta = jump on interface edge nodes (alpha the left/bottom
+ * leaf; flux in the coordinate direction), for nrhs right-hand sides:
+ * Algorithm 1 of Sec. 2.1 with the body load and jump added to the sweeps.
+ *   body      device [nrhs][n_int]
+ *   dirichlet device [nrhs][n_bdry] or NULL (zero)
+ *   jump      device [nrhs][n_iface] or NULL (zero)
+ *   u         device [nrhs][N] (output, canonical order)
+ * info may be NULL; when given, the call waits for the stream to finish. */
+HPS_API int hps_solve(hps_op *op, int nrhs, const double *body, const double *dirichlet,
+              const double *jump, double *u, void *stream, hps_info *info);
+
+HPS_API void hps_free(hps_op *op);
+
+/* Additive Runge-Kutta tableau (Sec. 3.1, Table 1): ESDIRK (A, b, c) with
+ * A[0][0] = 0 and A[i][i] = gamma for i >= 1, ERK (Ahat, bhat, c), row-major
+ * s x s host arrays, 2 <= s <= 8. */
+typedef struct {
+    int32_t s;
+    const double *A, *b, *c, *Ahat, *bhat;
+} ark_tableau;
+
+/* Explicit nonlinearity g(u) = g0 + g1 u + g2 u^2 + g3 u^3 (kind = 1), or none (kind = 0). */
+typedef struct {
+    int32_t kind;
+    double g0, g1, g2, g3;
+} ark_g;
+
+/* Time-stepping context for the stage formulation (eqs. 9-11) on a built
+ * operator.  Requires |A[1][1]*dt - gamma_dt| <= 1e-14 |gamma_dt|; g may be NULL. */
+HPS_API int ark_create(hps_op *op, const ark_tableau *tab, double dt, const ark_g *g, ark_ctx **out);
+
+/* One step t -> t + dt of the stage formulation, in place on u (device [N]):
+ *   stage 1: L u^n and F_1 = q(t) + g(u^n);
+ *   stages i = 2..s: solve (I - gamma dt L) u_i = u^n + dt sum_{j<i} a_ij L u_j
+ *                    + dt sum_{j<i} ahat_ij F_j with u_i = f(t + c_i dt) on the
+ *                    boundary, then L u_i and F_i = q(t + c_i dt) + g(u_i);
+ *   completion:      interior u^{n+1} = u^n + dt sum_j (b_j L u_j + bhat_j F_j),
+ *                    boundary f(t + dt), interface nodes from flux continuity.
+ * Source q, by one of (or none: q = 0):
+ *   q_stages  device [s][n_int]: q at t + c_i dt;
+ *   q_space   device [n_int] with q_time host [s]: q = q_time[i] * q_space.
+ * f_stages: device [s+1][n_bdry], f at t + c_i dt (i < s) and at t + dt; NULL = 0. */
+HPS_API int ark_step(ark_ctx *ctx, double t, double *u, const double *q_stages,
+             const double *q_space, const double *q_time, const double *f_stages, void *stream);
+
+/* Number of implicit stage solves performed per ark_step (s - 1). */
+HPS_API int ark_stage_solves_per_step(const ark_ctx *ctx);
+
+HPS_API void ark_free(ark_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HPS_MI355X_H */

@@ -1,0 +1,876 @@
+// Host side of the C ABI: argument checking, the tree plan, the GPU build and the
+// stage-solve / time-step drivers.  Every arithmetic step of the build and of the solves
+// runs in the kernels of hps_kernels.hip; this file only plans, allocates and enqueues.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "hps_internal.h"
+
+using namespace hps;
+
+// ---------------------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------------------
+static thread_local char g_err[1024] = "no error";
+
+void hps_set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+extern "C" const char *hps_last_error(void) { return g_err; }
+
+#define CHECK_ARG(cond, ...)          \
+    do {                              \
+        if (!(cond)) {                \
+            hps_set_error(__VA_ARGS__); \
+            return HPS_EINVAL;        \
+        }                             \
+    } while (0)
+
+#define TRY(x)                 \
+    do {                       \
+        int rc_ = (x);         \
+        if (rc_) return rc_;   \
+    } while (0)
+
+// ---------------------------------------------------------------------------------------
+// grid
+// ---------------------------------------------------------------------------------------
+static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+static int check_grid(const hps_grid *g) {
+    CHECK_ARG(g != nullptr, "grid is NULL");
+    CHECK_ARG(is_pow2(g->n1) && is_pow2(g->n2), "n1 and n2 must be powers of two (got %d, %d)", g->n1, g->n2);
+    CHECK_ARG((int64_t)g->n1 * g->n2 <= (1 << 14), "at most 2^14 leaves are supported");
+    CHECK_ARG(g->p >= 3 && g->p <= PMAX, "p must be in [3, %d] (got %d)", PMAX, g->p);
+    CHECK_ARG(std::isfinite(g->x0) && std::isfinite(g->x1) && std::isfinite(g->y0) && std::isfinite(g->y1),
+              "domain bounds must be finite");
+    CHECK_ARG(g->x1 > g->x0 && g->y1 > g->y0, "empty domain");
+    const double hx = (g->x1 - g->x0) / g->n1, hy = (g->y1 - g->y0) / g->n2;
+    CHECK_ARG(std::fabs(hx - hy) <= 1e-12 * std::max(std::fabs(hx), std::fabs(hy)),
+              "leaves must be square: (x1-x0)/n1 = %.17g, (y1-y0)/n2 = %.17g", hx, hy);
+    return HPS_OK;
+}
+
+struct Counts {
+    int64_t N, n_int, n_vert, n_horz, n_edge, n_bdry, n_iface;
+};
+
+static Counts counts(const hps_grid *g) {
+    Counts c{};
+    const int64_t q = g->p - 2, n1 = g->n1, n2 = g->n2;
+    c.n_int = n1 * n2 * q * q;
+    c.n_vert = (n1 + 1) * n2 * q;
+    c.n_horz = (n2 + 1) * n1 * q;
+    c.n_edge = c.n_vert + c.n_horz;
+    c.N = c.n_int + c.n_edge;
+    c.n_bdry = 2 * q * (n1 + n2);
+    c.n_iface = c.n_edge - c.n_bdry;
+    return c;
+}
+
+extern "C" int64_t hps_num_nodes(const hps_grid *grid, int64_t *n_int, int64_t *n_iface, int64_t *n_bdry) {
+    int rc = check_grid(grid);
+    if (rc) return rc;
+    Counts c = counts(grid);
+    if (n_int) *n_int = c.n_int;
+    if (n_iface) *n_iface = c.n_iface;
+    if (n_bdry) *n_bdry = c.n_bdry;
+    return c.N;
+}
+
+// Chebyshev-Lobatto offsets on [0, h]: h (1 - cos(m pi / (p-1))) / 2, ascending in m.
+static double cheb_offset(double h, int m, int p) {
+    return h * (1.0 - std::cos(M_PI * m / (p - 1))) / 2.0;
+}
+
+extern "C" int hps_nodes(const hps_grid *g, double *x, double *y) {
+    TRY(check_grid(g));
+    CHECK_ARG(x && y, "x and y must be host arrays of N doubles");
+    const Counts c = counts(g);
+    const int q = g->p - 2, n1 = g->n1, n2 = g->n2, p = g->p;
+    const double h = (g->x1 - g->x0) / n1;
+    for (int j = 0; j < n2; ++j)
+        for (int i = 0; i < n1; ++i)
+            for (int b = 1; b <= q; ++b)
+                for (int a = 1; a <= q; ++a) {
+                    const int64_t k = ((int64_t)(j * n1 + i) * q + (b - 1)) * q + (a - 1);
+                    x[k] = (g->x0 + i * h) + cheb_offset(h, a, p);
+                    y[k] = (g->y0 + j * h) + cheb_offset(h, b, p);
+                }
+    for (int k = 0; k <= n1; ++k)
+        for (int j = 0; j < n2; ++j)
+            for (int m = 0; m < q; ++m) {
+                const int64_t idx = c.n_int + ((int64_t)k * n2 + j) * q + m;
+                x[idx] = g->x0 + k * h;
+                y[idx] = (g->y0 + j * h) + cheb_offset(h, m + 1, p);
+            }
+    for (int k = 0; k <= n2; ++k)
+        for (int i = 0; i < n1; ++i)
+            for (int m = 0; m < q; ++m) {
+                const int64_t idx = c.n_int + c.n_vert + ((int64_t)k * n1 + i) * q + m;
+                x[idx] = (g->x0 + i * h) + cheb_offset(h, m + 1, p);
+                y[idx] = g->y0 + k * h;
+            }
+    return HPS_OK;
+}
+
+// Derivative on the physical nodes of one leaf (side h), row-major D[a*p + m]:
+// Chebyshev-Gauss-Lobatto collocation derivative on xi_m = cos(m pi/(p-1)) scaled by
+// dxi/dx = -2/h; off-diagonal (k_i/k_j)(-1)^(i+j)/(xi_i - xi_j), k = 2 at the ends,
+// diagonal = minus the off-diagonal row sum.
+static void leaf_derivative(int p, double h, std::vector<double> &D, std::vector<double> &D2) {
+    std::vector<double> xi(p);
+    for (int m = 0; m < p; ++m) xi[m] = std::cos(M_PI * m / (p - 1));
+    D.assign((size_t)p * p, 0.0);
+    for (int i = 0; i < p; ++i) {
+        double rs = 0.0;
+        for (int j = 0; j < p; ++j) {
+            if (i == j) continue;
+            const double ki = (i == 0 || i == p - 1) ? 2.0 : 1.0;
+            const double kj = (j == 0 || j == p - 1) ? 2.0 : 1.0;
+            const double sgn = ((i + j) % 2) ? -1.0 : 1.0;
+            const double v = (ki / kj) * sgn / (xi[i] - xi[j]);
+            D[(size_t)i * p + j] = v;
+            rs += v;
+        }
+        D[(size_t)i * p + i] = -rs;
+    }
+    for (auto &v : D) v *= -2.0 / h;
+    D2.assign((size_t)p * p, 0.0);
+    for (int i = 0; i < p; ++i)
+        for (int j = 0; j < p; ++j) {
+            double s = 0.0;
+            for (int m = 0; m < p; ++m) s += D[(size_t)i * p + m] * D[(size_t)m * p + j];
+            D2[(size_t)i * p + j] = s;
+        }
+}
+
+// ---------------------------------------------------------------------------------------
+// panel planning
+// ---------------------------------------------------------------------------------------
+namespace hps {
+Panel plan_panel(int R, int C, int vw, int nodes, int rp_max, int min_wg) {
+    constexpr int XS_MAX = 1024;
+    Panel p;
+    p.R = R; p.C = C; p.vw = vw; p.nodes = nodes;
+    const int RV = (R + vw - 1) / vw;
+    p.ntile = (RV + rp_max - 1) / rp_max;
+    p.rp = (RV + p.ntile - 1) / p.ntile;
+    const int Gmax = std::max(1, NT / p.rp);
+    // column groups: fewest padded columns, then most groups
+    int bestG = Gmax;
+    int64_t bestPad = -1;
+    for (int G = Gmax; G >= std::max(1, Gmax / 2); --G) {
+        const int64_t pad = (int64_t)((C + G - 1) / G) * G - C;
+        if (bestPad < 0 || pad < bestPad) {
+            bestPad = pad;
+            bestG = G;
+        }
+    }
+    p.G = bestG;
+    p.kch = 1;
+    const int64_t wgs = (int64_t)nodes * p.ntile;
+    if (min_wg > 0 && wgs < min_wg) {
+        const int want = (int)((min_wg + wgs - 1) / wgs);
+        const int maxk = std::max(1, C / (p.G * 16));
+        p.kch = std::min(want, maxk);
+    }
+    while ((int64_t)((C + p.G * p.kch - 1) / (p.G * p.kch)) * p.G > XS_MAX) ++p.kch;
+    p.S = (C + p.G * p.kch - 1) / (p.G * p.kch);
+    p.tile_elems = (int64_t)p.S * p.G * p.rp * vw;
+    p.node_elems = (int64_t)p.ntile * p.kch * p.tile_elems;
+    return p;
+}
+}  // namespace hps
+
+// ---------------------------------------------------------------------------------------
+// allocation helpers
+// ---------------------------------------------------------------------------------------
+template <typename T>
+static int dev_alloc(hps_op *op, T **ptr, int64_t n, bool track = true) {
+    *ptr = nullptr;
+    if (n <= 0) n = 1;
+    hipError_t e = hipMalloc((void **)ptr, sizeof(T) * (size_t)n);
+    if (e != hipSuccess) {
+        hps_set_error("hipMalloc of %lld bytes failed: %s", (long long)(sizeof(T) * n), hipGetErrorString(e));
+        *ptr = nullptr;
+        return HPS_ENOMEM;
+    }
+    if (track && op) {
+        op->allocs.push_back(*ptr);
+        op->total_bytes += (int64_t)sizeof(T) * n;
+    }
+    return HPS_OK;
+}
+
+template <typename T>
+static int upload(hps_op *op, T **ptr, const std::vector<T> &v, hipStream_t st) {
+    TRY(dev_alloc(op, ptr, (int64_t)v.size()));
+    if (!v.empty())
+        HPS_HIP(hipMemcpyAsync(*ptr, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+    return HPS_OK;
+}
+
+struct TempBuf {   // device scratch freed at scope exit
+    std::vector<void *> ptrs;
+    ~TempBuf() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    template <typename T>
+    int get(T **ptr, int64_t n) {
+        TRY(dev_alloc<T>(nullptr, ptr, n, false));
+        ptrs.push_back(*ptr);
+        return HPS_OK;
+    }
+    void release(void *p) {
+        auto it = std::find(ptrs.begin(), ptrs.end(), p);
+        if (it != ptrs.end()) {
+            (void)hipFree(*it);
+            ptrs.erase(it);
+        }
+    }
+};
+
+static int check_device_ptr(const void *p, const char *name) {
+    if (!p) return HPS_OK;
+    hipPointerAttribute_t attr;
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess || (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)) {
+        (void)hipGetLastError();
+        hps_set_error("%s must be a device pointer", name);
+        return HPS_EINVAL;
+    }
+    return HPS_OK;
+}
+
+static int alloc_panel(hps_op *op, Panel &pn) {
+    if (pn.vw == 2) {
+        double *d;
+        TRY(dev_alloc(op, &d, pn.node_elems * pn.nodes));
+        pn.data = d;
+    } else {
+        float *f;
+        TRY(dev_alloc(op, &f, pn.node_elems * pn.nodes));
+        pn.data = f;
+    }
+    op->operator_bytes += pn.bytes();
+    return HPS_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// tree plan (host): boxes, boundaries in node order, J1/J2/J3 maps per level
+// ---------------------------------------------------------------------------------------
+struct Box {
+    int i0, i1, j0, j1;
+};
+
+struct HostLevel {
+    int n1 = 0, n2 = 0, n3 = 0, nbc = 0;
+    std::vector<int> a1, a3, b2, b3;
+    std::vector<int> j3i;   // [nodes][n3]
+};
+
+static int plan_tree(const hps_op *op, std::vector<int> &leaf_ij, std::vector<HostLevel> &hl,
+                     std::vector<int> &root_map, std::vector<int> &bnd_glob) {
+    const hps_grid &g = op->grid;
+    const int n1 = g.n1, n2 = g.n2, q = op->q, L = op->L;
+    // boxes, heap order per level
+    std::vector<std::vector<Box>> boxes(L + 1);
+    boxes[0].push_back(Box{0, n1, 0, n2});
+    for (int l = 0; l < L; ++l) {
+        for (const Box &b : boxes[l]) {
+            if (b.i1 - b.i0 >= b.j1 - b.j0) {   // halve the longer side, ties cut vertically
+                const int im = (b.i0 + b.i1) / 2;
+                boxes[l + 1].push_back(Box{b.i0, im, b.j0, b.j1});
+                boxes[l + 1].push_back(Box{im, b.i1, b.j0, b.j1});
+            } else {
+                const int jm = (b.j0 + b.j1) / 2;
+                boxes[l + 1].push_back(Box{b.i0, b.i1, b.j0, jm});
+                boxes[l + 1].push_back(Box{b.i0, b.i1, jm, b.j1});
+            }
+        }
+    }
+    leaf_ij.resize(2 * (size_t)op->nleaves);
+    for (int k = 0; k < op->nleaves; ++k) {
+        const Box &b = boxes[L][k];
+        if (b.i1 - b.i0 != 1 || b.j1 - b.j0 != 1) {
+            hps_set_error("internal: tree leaves are not single squares");
+            return HPS_EINVAL;
+        }
+        leaf_ij[2 * k] = b.i0;
+        leaf_ij[2 * k + 1] = b.j0;
+    }
+    auto vert = [&](int k, int j, int m) { return op->n_int + ((int64_t)k * n2 + j) * q + m; };
+    auto horz = [&](int k, int i, int m) { return op->n_int + op->n_vert + ((int64_t)k * n1 + i) * q + m; };
+    // interface / boundary index of every edge node (or -1)
+    std::vector<int> iface(op->n_edge, -1), bpos(op->n_edge, -1);
+    bnd_glob.assign(op->n_bdry, 0);
+    {
+        int64_t ni = 0, nb = 0;
+        for (int k = 0; k <= n1; ++k)
+            for (int j = 0; j < n2; ++j)
+                for (int m = 0; m < q; ++m) {
+                    const int64_t e = vert(k, j, m) - op->n_int;
+                    if (k == 0 || k == n1) {
+                        bpos[e] = (int)nb;
+                        bnd_glob[nb++] = (int)(e + op->n_int);
+                    } else {
+                        iface[e] = (int)ni++;
+                    }
+                }
+        for (int k = 0; k <= n2; ++k)
+            for (int i = 0; i < n1; ++i)
+                for (int m = 0; m < q; ++m) {
+                    const int64_t e = horz(k, i, m) - op->n_int;
+                    if (k == 0 || k == n2) {
+                        bpos[e] = (int)nb;
+                        bnd_glob[nb++] = (int)(e + op->n_int);
+                    } else {
+                        iface[e] = (int)ni++;
+                    }
+                }
+        if (ni != op->n_iface || nb != op->n_bdry) {
+            hps_set_error("internal: edge classification mismatch");
+            return HPS_EINVAL;
+        }
+    }
+    // boundaries in node order, bottom-up; leaf order [left, right, bottom, top]
+    std::vector<std::vector<int64_t>> cur(op->nleaves), nxt;
+    for (int k = 0; k < op->nleaves; ++k) {
+        const int i = leaf_ij[2 * k], j = leaf_ij[2 * k + 1];
+        auto &v = cur[k];
+        v.reserve(4 * q);
+        for (int m = 0; m < q; ++m) v.push_back(vert(i, j, m));
+        for (int m = 0; m < q; ++m) v.push_back(vert(i + 1, j, m));
+        for (int m = 0; m < q; ++m) v.push_back(horz(j, i, m));
+        for (int m = 0; m < q; ++m) v.push_back(horz(j + 1, i, m));
+    }
+    hl.assign(L, HostLevel{});
+    std::vector<int> posB(op->n_edge, -1);
+    std::vector<char> in3(op->n_edge, 0);
+    for (int l = L - 1; l >= 0; --l) {
+        const int nodes = 1 << l;
+        nxt.assign(nodes, {});
+        HostLevel &H = hl[l];
+        for (int k = 0; k < nodes; ++k) {
+            const auto &A = cur[2 * k], &B = cur[2 * k + 1];
+            if (A.size() != B.size()) {
+                hps_set_error("internal: children of one node differ in boundary length");
+                return HPS_EINVAL;
+            }
+            for (size_t t = 0; t < B.size(); ++t) posB[B[t] - op->n_int] = (int)t;
+            std::vector<int> a1, a3, b2, b3;
+            std::vector<int64_t> J3;
+            for (size_t t = 0; t < A.size(); ++t) {
+                const int64_t e = A[t] - op->n_int;
+                if (posB[e] >= 0) {
+                    a3.push_back((int)t);
+                    b3.push_back(posB[e]);
+                    J3.push_back(A[t]);
+                    in3[e] = 1;
+                } else {
+                    a1.push_back((int)t);
+                }
+            }
+            for (size_t t = 0; t < B.size(); ++t)
+                if (!in3[B[t] - op->n_int]) b2.push_back((int)t);
+            auto &nb = nxt[k];
+            nb.reserve(a1.size() + b2.size());
+            for (int t : a1) nb.push_back(A[t]);
+            for (int t : b2) nb.push_back(B[t]);
+            if (k == 0) {
+                H.a1 = a1; H.a3 = a3; H.b2 = b2; H.b3 = b3;
+                H.n1 = (int)a1.size(); H.n2 = (int)b2.size(); H.n3 = (int)a3.size();
+                H.nbc = (int)A.size();
+                H.j3i.assign((size_t)nodes * H.n3, 0);
+            } else if (a1 != H.a1 || a3 != H.a3 || b2 != H.b2 || b3 != H.b3) {
+                hps_set_error("internal: nodes of level %d differ in shape", l);
+                return HPS_EINVAL;
+            }
+            for (int t = 0; t < H.n3; ++t) {
+                const int ii = iface[J3[t] - op->n_int];
+                if (ii < 0) {
+                    hps_set_error("internal: merge interface node on the outer boundary");
+                    return HPS_EINVAL;
+                }
+                H.j3i[(size_t)k * H.n3 + t] = ii;
+            }
+            for (size_t t = 0; t < B.size(); ++t) posB[B[t] - op->n_int] = -1;
+            for (int64_t e : J3) in3[e - op->n_int] = 0;
+        }
+        cur.swap(nxt);
+    }
+    // root boundary -> boundary index
+    root_map.resize(cur[0].size());
+    if ((int64_t)cur[0].size() != op->n_bdry) {
+        hps_set_error("internal: root boundary size mismatch");
+        return HPS_EINVAL;
+    }
+    for (size_t t = 0; t < cur[0].size(); ++t) {
+        const int b = bpos[cur[0][t] - op->n_int];
+        if (b < 0) {
+            hps_set_error("internal: root boundary node is not on the outer boundary");
+            return HPS_EINVAL;
+        }
+        root_map[t] = b;
+    }
+    return HPS_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// build
+// ---------------------------------------------------------------------------------------
+static int build_impl(hps_op *op, const hps_coeffs *co, hipStream_t st) {
+    const hps_grid &g = op->grid;
+    const int q = op->q, q2 = op->q2, nb4 = 4 * q;
+    const bool ir = (op->flags & HPS_FP32_IR) != 0;
+    // constants and plan
+    std::vector<double> D, D2;
+    leaf_derivative(op->p, op->h, D, D2);
+    TRY(upload(op, &op->D, D, st));
+    TRY(upload(op, &op->D2, D2, st));
+    std::vector<int> leaf_ij, root_map, bnd_glob;
+    std::vector<HostLevel> hl;
+    TRY(plan_tree(op, leaf_ij, hl, root_map, bnd_glob));
+    TRY(upload(op, &op->leaf_ij, leaf_ij, st));
+    TRY(upload(op, &op->root_map, root_map, st));
+    TRY(upload(op, &op->bnd_glob, bnd_glob, st));
+    {   // Thomas factors of the interface-line systems (constant coefficients)
+        const int nmax = std::max(g.n1, g.n2);
+        const double lower = D[(size_t)(op->p - 1) * op->p + 0];
+        const double diag = D[(size_t)(op->p - 1) * op->p + (op->p - 1)] - D[0];
+        const double upper = -D[op->p - 1];
+        op->tri_stride = nmax + 1;
+        std::vector<double> tri(2 * (size_t)(nmax + 1), 0.0);
+        double cprev = 0.0;
+        for (int k = 1; k < nmax; ++k) {
+            const double den = diag - (k > 1 ? lower * cprev : 0.0);
+            tri[nmax + 1 + k] = 1.0 / den;
+            tri[k] = upper / den;
+            cprev = tri[k];
+        }
+        TRY(upload(op, &op->tri_cp, tri, st));
+    }
+    // coefficients of L (NULL members are zero)
+    TRY(dev_alloc(op, &op->coef, 5 * op->n_int));
+    const double *src[5] = {co->cxx, co->cyy, co->cx, co->cy, co->c0};
+    for (int k = 0; k < 5; ++k) {
+        if (src[k])
+            HPS_HIP(hipMemcpyAsync(op->coef + k * op->n_int, src[k], sizeof(double) * op->n_int,
+                                   hipMemcpyDeviceToDevice, st));
+        else
+            TRY(launch_zero(op->coef + k * op->n_int, op->n_int, st));
+    }
+    int *sing;
+    TRY(dev_alloc(op, &sing, 1));
+    HPS_HIP(hipMemsetAsync(sing, 0, sizeof(int), st));
+
+    TempBuf tmp;
+    auto gj_scratch = [&](int n, int nb, unsigned char **used, int **order, double **cb, double **rb) -> int {
+        TRY(tmp.get(used, (int64_t)n * nb));
+        TRY(tmp.get(order, (int64_t)n * nb));
+        TRY(tmp.get(cb, (int64_t)n * nb));
+        TRY(tmp.get(rb, (int64_t)n * nb));
+        return HPS_OK;
+    };
+    // ---- leaves (Sec. 2.1, eqs. 5-6) ----
+    const int nl = op->nleaves;
+    double *W, *Ainv, *S, *T;
+    TRY(tmp.get(&W, (int64_t)nl * q2 * q2));
+    TRY(tmp.get(&Ainv, (int64_t)nl * q2 * q2));
+    TRY(launch_leaf_assemble(op, W, st));
+    {
+        unsigned char *used; int *order; double *cb, *rb;
+        TRY(gj_scratch(q2, nl, &used, &order, &cb, &rb));
+        TRY(gj_invert(W, Ainv, q2, nl, used, order, cb, rb, sing, st));
+        tmp.release(used); tmp.release(order); tmp.release(cb); tmp.release(rb);
+    }
+    tmp.release(W);
+    TRY(tmp.get(&S, (int64_t)nl * q2 * nb4));
+    TRY(tmp.get(&T, (int64_t)nl * nb4 * nb4));
+    TRY(launch_leaf_S(op, Ainv, S, st));
+    TRY(launch_leaf_T(op, S, T, st));
+    op->ainv64 = plan_panel(q2, q2, 2, nl, 256, 0);
+    op->sleaf64 = plan_panel(q2, nb4, 2, nl, 256, 0);
+    for (const Panel *pn : {&op->ainv64, &op->sleaf64})
+        if (pn->ntile != 1 || pn->kch != 1) {
+            hps_set_error("internal: leaf operator does not fit one workgroup tile");
+            return HPS_EINVAL;
+        }
+    TRY(alloc_panel(op, op->ainv64));
+    TRY(alloc_panel(op, op->sleaf64));
+    TRY(launch_pack(op->ainv64, Ainv, q2, (int64_t)q2 * q2, q2, nullptr, 0, 0, st));
+    TRY(launch_pack(op->sleaf64, S, q2, (int64_t)q2 * nb4, q2, nullptr, 0, 0, st));
+    if (ir) {
+        op->ainv32 = plan_panel(q2, q2, 4, nl, 256, 0);
+        op->sleaf32 = plan_panel(q2, nb4, 4, nl, 256, 0);
+        TRY(alloc_panel(op, op->ainv32));
+        TRY(alloc_panel(op, op->sleaf32));
+        TRY(launch_pack(op->ainv32, Ainv, q2, (int64_t)q2 * q2, q2, nullptr, 0, 0, st));
+        TRY(launch_pack(op->sleaf32, S, q2, (int64_t)q2 * nb4, q2, nullptr, 0, 0, st));
+    }
+    tmp.release(Ainv);
+    tmp.release(S);
+    TRY(dev_alloc(op, &op->h_leaf, (int64_t)nl * nb4));
+    TRY(dev_alloc(op, &op->ub_leaf, (int64_t)nl * nb4));
+    TRY(dev_alloc(op, &op->w_leaf, (int64_t)nl * q2));
+
+    // ---- merges, bottom-up (merge formulas after eqs. 7-8) ----
+    op->lv.assign(op->L, Level{});
+    double *Tc = T;
+    for (int l = op->L - 1; l >= 0; --l) {
+        const HostLevel &H = hl[l];
+        Level &Lv = op->lv[l];
+        const bool root = (l == 0);
+        Lv.nodes = 1 << l;
+        Lv.n1 = H.n1; Lv.n2 = H.n2; Lv.n3 = H.n3; Lv.n12 = H.n1 + H.n2; Lv.nbc = H.nbc;
+        TRY(upload(op, &Lv.a1, H.a1, st));
+        TRY(upload(op, &Lv.a3, H.a3, st));
+        TRY(upload(op, &Lv.b2, H.b2, st));
+        TRY(upload(op, &Lv.b3, H.b3, st));
+        TRY(upload(op, &Lv.j3i, H.j3i, st));
+        const int n3 = Lv.n3, n12 = Lv.n12, nodes = Lv.nodes;
+        const int64_t s33 = (int64_t)n3 * n3, s3x = (int64_t)n3 * n12, sxx = (int64_t)n12 * n12;
+        double *M, *X, *B, *Cm, *Sx, *U, *Tn = nullptr;
+        TRY(tmp.get(&M, nodes * s33));
+        TRY(tmp.get(&X, nodes * s33));
+        TRY(tmp.get(&B, nodes * s3x));
+        TRY(tmp.get(&Cm, nodes * s3x));
+        TRY(tmp.get(&Sx, nodes * s3x));
+        TRY(tmp.get(&U, nodes * s3x));
+        if (!root) TRY(tmp.get(&Tn, nodes * sxx));
+        TRY(launch_merge_gather(Lv, root, Tc, M, B, Cm, Tn, st));
+        tmp.release(Tc);
+        {
+            unsigned char *used; int *order; double *cb, *rb;
+            TRY(gj_scratch(n3, nodes, &used, &order, &cb, &rb));
+            TRY(gj_invert(M, X, n3, nodes, used, order, cb, rb, sing, st));
+            tmp.release(used); tmp.release(order); tmp.release(cb); tmp.release(rb);
+        }
+        tmp.release(M);
+        // S = X [-T^a_31 | T^b_32];  U = [T^a_13; T^b_23] X;  T = diag(T^a_11, T^b_22) + U [...]
+        TRY(launch_dgemm(n3, n12, n3, X, n3, s33, B, n3, s3x, Sx, n3, s3x, nodes, 1.0, 0.0, st));
+        if (!root) {
+            TRY(launch_dgemm(n12, n3, n3, Cm, n12, s3x, X, n3, s33, U, n12, s3x, nodes, 1.0, 0.0, st));
+            TRY(launch_dgemm(n12, n12, n3, U, n12, s3x, B, n3, s3x, Tn, n12, sxx, nodes, 1.0, 1.0, st));
+        }
+        const int rows = root ? n3 : n3 + n12;
+        Lv.xu64 = plan_panel(rows, n3, 2, nodes, 64, 512);
+        Lv.s64 = plan_panel(n3, n12, 2, nodes, 64, 512);
+        TRY(alloc_panel(op, Lv.xu64));
+        TRY(alloc_panel(op, Lv.s64));
+        TRY(launch_pack(Lv.xu64, X, n3, s33, n3, U, n12, s3x, st));
+        TRY(launch_pack(Lv.s64, Sx, n3, s3x, n3, nullptr, 0, 0, st));
+        if (ir) {
+            Lv.xu32 = plan_panel(rows, n3, 4, nodes, 64, 512);
+            Lv.s32 = plan_panel(n3, n12, 4, nodes, 64, 512);
+            TRY(alloc_panel(op, Lv.xu32));
+            TRY(alloc_panel(op, Lv.s32));
+            TRY(launch_pack(Lv.xu32, X, n3, s33, n3, U, n12, s3x, st));
+            TRY(launch_pack(Lv.s32, Sx, n3, s3x, n3, nullptr, 0, 0, st));
+        }
+        tmp.release(X); tmp.release(B); tmp.release(Cm); tmp.release(Sx); tmp.release(U);
+        Tc = Tn;
+        TRY(dev_alloc(op, &Lv.h, (int64_t)nodes * n12));
+        TRY(dev_alloc(op, &Lv.ub, (int64_t)nodes * n12));
+        TRY(dev_alloc(op, &Lv.w3, (int64_t)nodes * n3));
+        int64_t part = 0;
+        for (const Panel *pn : {&Lv.xu64, &Lv.s64, &Lv.xu32, &Lv.s32})
+            if (pn->kch > 1) part = std::max<int64_t>(part, (int64_t)nodes * pn->ntile * pn->kch * pn->rp * pn->vw);
+        if (part) TRY(dev_alloc(op, &Lv.part, part));
+    }
+    if (ir) {
+        TRY(dev_alloc(op, &op->ir_r, op->n_int));
+        TRY(dev_alloc(op, &op->ir_r3, std::max<int64_t>(op->n_iface, 1)));
+        TRY(dev_alloc(op, &op->ir_flux, (int64_t)nl * nb4));
+        TRY(dev_alloc(op, &op->ir_norms, 2));
+    }
+    HPS_HIP(hipStreamSynchronize(st));
+    int hsing = 0;
+    HPS_HIP(hipMemcpy(&hsing, sing, sizeof(int), hipMemcpyDeviceToHost));
+    if (hsing) {
+        hps_set_error("a zero pivot occurred while inverting a leaf or merge matrix");
+        return HPS_ESINGULAR;
+    }
+    return HPS_OK;
+}
+
+extern "C" void hps_free(hps_op *op) {
+    if (!op) return;
+    for (void *p : op->allocs) (void)hipFree(p);
+    delete op;
+}
+
+extern "C" int hps_build(const hps_grid *grid, const hps_coeffs *coeffs, double gamma_dt, int flags,
+                         void *stream, hps_op **out) {
+    CHECK_ARG(out != nullptr, "out is NULL");
+    *out = nullptr;
+    TRY(check_grid(grid));
+    CHECK_ARG(coeffs != nullptr, "coeffs is NULL");
+    CHECK_ARG(std::isfinite(gamma_dt) && gamma_dt > 0.0, "gamma_dt must be positive and finite");
+    CHECK_ARG(flags == HPS_FP64 || flags == HPS_FP32_IR, "unknown flags %d", flags);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        hps_set_error("no HIP device is available");
+        return HPS_EDEVICE;
+    }
+    const double *cs[5] = {coeffs->cxx, coeffs->cyy, coeffs->cx, coeffs->cy, coeffs->c0};
+    const char *names[5] = {"coeffs.cxx", "coeffs.cyy", "coeffs.cx", "coeffs.cy", "coeffs.c0"};
+    for (int k = 0; k < 5; ++k) TRY(check_device_ptr(cs[k], names[k]));
+    hps_op *op = new hps_op();
+    op->grid = *grid;
+    op->p = grid->p;
+    op->q = grid->p - 2;
+    op->q2 = op->q * op->q;
+    op->nleaves = grid->n1 * grid->n2;
+    int L = 0;
+    while ((1 << L) < op->nleaves) ++L;
+    op->L = L;
+    const Counts c = counts(grid);
+    op->N = c.N; op->n_int = c.n_int; op->n_edge = c.n_edge; op->n_vert = c.n_vert;
+    op->n_iface = c.n_iface; op->n_bdry = c.n_bdry;
+    op->gamma_dt = gamma_dt;
+    op->h = (grid->x1 - grid->x0) / grid->n1;
+    op->flags = flags;
+    int rc = build_impl(op, coeffs, (hipStream_t)stream);
+    if (rc) {
+        (void)hipDeviceSynchronize();
+        hps_free(op);
+        return rc;
+    }
+    *out = op;
+    return HPS_OK;
+}
+
+extern "C" int64_t hps_op_bytes(const hps_op *op, int64_t *operator_bytes) {
+    if (!op) {
+        hps_set_error("op is NULL");
+        return HPS_EINVAL;
+    }
+    if (operator_bytes) {
+        int64_t b = 0;
+        const bool f32 = (op->flags & HPS_FP32_IR) != 0;
+        b += (f32 ? op->ainv32 : op->ainv64).bytes() + (f32 ? op->sleaf32 : op->sleaf64).bytes();
+        for (const Level &L : op->lv) b += (f32 ? L.xu32 : L.xu64).bytes() + (f32 ? L.s32 : L.s64).bytes();
+        *operator_bytes = b;   // bytes streamed by one solve in the op's working precision
+    }
+    return op->total_bytes;
+}
+
+// ---------------------------------------------------------------------------------------
+// solve
+// ---------------------------------------------------------------------------------------
+static int sweep(hps_op *op, bool fp32, const double *body, const double *un, const double *Lu,
+                 const double *F, const StageCoefs *sc, double *rhs_copy, const double *jump,
+                 const double *dir, hipStream_t st) {
+    TRY(launch_leaf_up(op, fp32, body, un, Lu, F, sc, rhs_copy, st));
+    TRY(launch_levels_up(op, fp32, jump, st));
+    TRY(launch_levels_down(op, fp32, dir, st));
+    return HPS_OK;
+}
+
+static double ordered_bits_to_double(unsigned long long v) {
+    double d;
+    std::memcpy(&d, &v, sizeof(d));
+    return d;
+}
+
+// FP32 operators inside FP64 iterative refinement: u = HPS32(rhs); repeat
+// { r = FP64 residual of the global system; u += HPS32(r) } until max|delta| <= tol max|u|.
+static int ir_refine(hps_op *op, const double *rhs, const double *dir, const double *jump, double *u,
+                     hipStream_t st, hps_info *info) {
+    const double tol = 1e-11;
+    const int maxit = 10;
+    GPoly none{0, 0, 0, 0, 0};
+    int it = 0;
+    double rel = 0.0;
+    for (it = 1; it <= maxit; ++it) {
+        TRY(launch_residual(op, u, rhs, jump, op->ir_r, op->ir_r3, st));
+        HPS_HIP(hipMemsetAsync(op->ir_norms, 0, 2 * sizeof(double), st));
+        TRY(sweep(op, true, op->ir_r, nullptr, nullptr, nullptr, nullptr, nullptr,
+                  op->n_iface ? op->ir_r3 : nullptr, nullptr, st));
+        TRY(launch_leaf_down(op, true, 2, u, nullptr, nullptr, nullptr, 0.0, none, st));
+        unsigned long long nb[2];
+        HPS_HIP(hipMemcpyAsync(nb, op->ir_norms, sizeof(nb), hipMemcpyDeviceToHost, st));
+        HPS_HIP(hipStreamSynchronize(st));
+        const double dmax = ordered_bits_to_double(nb[0]), umax = ordered_bits_to_double(nb[1]);
+        rel = umax > 0 ? dmax / umax : dmax;
+        if (dmax <= tol * umax) break;
+    }
+    if (info) {
+        info->ir_iterations = std::min(it, maxit);
+        info->last_correction = rel;
+    }
+    if (it > maxit) {
+        hps_set_error("iterative refinement did not converge: last correction %.3e", rel);
+        return HPS_ENOTCONVERGED;
+    }
+    return HPS_OK;
+}
+
+extern "C" int hps_solve(hps_op *op, int nrhs, const double *body, const double *dirichlet,
+                         const double *jump, double *u, void *stream, hps_info *info) {
+    CHECK_ARG(op != nullptr, "op is NULL");
+    CHECK_ARG(nrhs >= 0, "nrhs must be >= 0");
+    if (nrhs == 0) return HPS_OK;
+    CHECK_ARG(body != nullptr && u != nullptr, "body and u are required");
+    TRY(check_device_ptr(body, "body"));
+    TRY(check_device_ptr(dirichlet, "dirichlet"));
+    TRY(check_device_ptr(jump, "jump"));
+    TRY(check_device_ptr(u, "u"));
+    hipStream_t st = (hipStream_t)stream;
+    const bool ir = (op->flags & HPS_FP32_IR) != 0;
+    GPoly none{0, 0, 0, 0, 0};
+    if (info) {
+        info->ir_iterations = 0;
+        info->last_correction = 0.0;
+    }
+    int worst_it = 0;
+    double worst_rel = 0.0;
+    for (int r = 0; r < nrhs; ++r) {
+        const double *b = body + (int64_t)r * op->n_int;
+        const double *d = dirichlet ? dirichlet + (int64_t)r * op->n_bdry : nullptr;
+        const double *j = (jump && op->n_iface) ? jump + (int64_t)r * op->n_iface : nullptr;
+        double *ur = u + (int64_t)r * op->N;
+        TRY(sweep(op, ir, b, nullptr, nullptr, nullptr, nullptr, nullptr, j, d, st));
+        TRY(launch_leaf_down(op, ir, 0, ur, nullptr, nullptr, nullptr, 0.0, none, st));
+        if (ir) {
+            hps_info inf{};
+            TRY(ir_refine(op, b, d, j, ur, st, &inf));
+            worst_it = std::max(worst_it, inf.ir_iterations);
+            worst_rel = std::max(worst_rel, inf.last_correction);
+        }
+    }
+    if (info) {
+        HPS_HIP(hipStreamSynchronize(st));
+        info->ir_iterations = worst_it;
+        info->last_correction = worst_rel;
+    }
+    return HPS_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// time stepping
+// ---------------------------------------------------------------------------------------
+extern "C" int ark_create(hps_op *op, const ark_tableau *tab, double dt, const ark_g *g, ark_ctx **out) {
+    CHECK_ARG(out != nullptr, "out is NULL");
+    *out = nullptr;
+    CHECK_ARG(op != nullptr && tab != nullptr, "op and tab are required");
+    CHECK_ARG(tab->s >= 2 && tab->s <= 8, "tableau size s must be in [2, 8]");
+    CHECK_ARG(tab->A && tab->b && tab->c && tab->Ahat && tab->bhat, "tableau arrays are required");
+    CHECK_ARG(std::isfinite(dt) && dt > 0, "dt must be positive");
+    const int s = tab->s;
+    CHECK_ARG(tab->A[0] == 0.0, "the ESDIRK tableau must have an explicit first stage");
+    const double gam = tab->A[1 * s + 1];
+    for (int i = 1; i < s; ++i)
+        CHECK_ARG(tab->A[i * s + i] == gam, "the ESDIRK diagonal must be constant (a_ii = gamma)");
+    for (int i = 0; i < s; ++i)
+        for (int j = i + 1; j < s; ++j)
+            CHECK_ARG(tab->A[i * s + j] == 0.0, "the ESDIRK tableau must be lower triangular");
+    for (int i = 0; i < s; ++i)
+        for (int j = i; j < s; ++j)
+            CHECK_ARG(tab->Ahat[i * s + j] == 0.0, "the ERK tableau must be strictly lower triangular");
+    CHECK_ARG(std::fabs(gam * dt - op->gamma_dt) <= 1e-14 * op->gamma_dt,
+              "operator was built for gamma*dt = %.17g, tableau gives %.17g", op->gamma_dt, gam * dt);
+    if (g) CHECK_ARG(g->kind == 0 || g->kind == 1, "ark_g.kind must be 0 or 1");
+    ark_ctx *c = new ark_ctx();
+    c->op = op;
+    c->s = s;
+    c->dt = dt;
+    c->A.assign(tab->A, tab->A + s * s);
+    c->Ah.assign(tab->Ahat, tab->Ahat + s * s);
+    c->b.assign(tab->b, tab->b + s);
+    c->bh.assign(tab->bhat, tab->bhat + s);
+    c->c.assign(tab->c, tab->c + s);
+    if (g) c->g = *g;
+    auto fail = [&](int rc) {
+        ark_free(c);
+        return rc;
+    };
+    if (int rc = dev_alloc<double>(nullptr, &c->Lu, (int64_t)s * op->n_int, false)) return fail(rc);
+    if (int rc = dev_alloc<double>(nullptr, &c->F, (int64_t)s * op->n_int, false)) return fail(rc);
+    if (op->flags & HPS_FP32_IR) {
+        if (int rc = dev_alloc<double>(nullptr, &c->rhs, op->n_int, false)) return fail(rc);
+        if (int rc = dev_alloc<double>(nullptr, &c->stage_u, op->N, false)) return fail(rc);
+    }
+    *out = c;
+    return HPS_OK;
+}
+
+extern "C" void ark_free(ark_ctx *c) {
+    if (!c) return;
+    for (double *p : {c->Lu, c->F, c->rhs, c->stage_u})
+        if (p) (void)hipFree(p);
+    delete c;
+}
+
+extern "C" int ark_stage_solves_per_step(const ark_ctx *c) { return c ? c->s - 1 : HPS_EINVAL; }
+
+extern "C" int ark_step(ark_ctx *c, double t, double *u, const double *q_stages, const double *q_space,
+                        const double *q_time, const double *f_stages, void *stream) {
+    CHECK_ARG(c != nullptr && u != nullptr, "ctx and u are required");
+    CHECK_ARG(std::isfinite(t), "t must be finite");
+    CHECK_ARG(!(q_stages && q_space), "give q_stages or q_space/q_time, not both");
+    CHECK_ARG(!q_space || q_time, "q_space needs q_time (host array of s values)");
+    TRY(check_device_ptr(u, "u"));
+    TRY(check_device_ptr(q_stages, "q_stages"));
+    TRY(check_device_ptr(q_space, "q_space"));
+    TRY(check_device_ptr(f_stages, "f_stages"));
+    hps_op *op = c->op;
+    hipStream_t st = (hipStream_t)stream;
+    const int s = c->s;
+    const int64_t n = op->n_int;
+    const bool ir = (op->flags & HPS_FP32_IR) != 0;
+    GPoly gp{c->g.kind, c->g.g0, c->g.g1, c->g.g2, c->g.g3};
+    auto qsrc = [&](int i, double &scale) -> const double * {
+        scale = 1.0;
+        if (q_stages) return q_stages + (int64_t)i * n;
+        if (q_space) {
+            scale = q_time[i];
+            return q_space;
+        }
+        return nullptr;
+    };
+    double qs;
+    const double *qp = qsrc(0, qs);
+    TRY(launch_eval(op, u, c->Lu, c->F, qp, qs, gp, st));
+    for (int i = 1; i < s; ++i) {
+        StageCoefs sc{};
+        sc.nprev = i;
+        for (int j = 0; j < i; ++j) {
+            sc.ca[j] = c->dt * c->A[i * s + j];
+            sc.cf[j] = c->dt * c->Ah[i * s + j];
+        }
+        const double *fi = f_stages ? f_stages + (int64_t)i * op->n_bdry : nullptr;
+        qp = qsrc(i, qs);
+        double *Lui = c->Lu + (int64_t)i * n, *Fi = c->F + (int64_t)i * n;
+        if (!ir) {
+            TRY(sweep(op, false, nullptr, u, c->Lu, c->F, &sc, nullptr, nullptr, fi, st));
+            TRY(launch_leaf_down(op, false, 1, nullptr, Lui, Fi, qp, qs, gp, st));
+        } else {
+            TRY(sweep(op, true, nullptr, u, c->Lu, c->F, &sc, c->rhs, nullptr, fi, st));
+            TRY(launch_leaf_down(op, true, 0, c->stage_u, nullptr, nullptr, nullptr, 0.0, gp, st));
+            TRY(ir_refine(op, c->rhs, fi, nullptr, c->stage_u, st, nullptr));
+            TRY(launch_eval(op, c->stage_u, Lui, Fi, qp, qs, gp, st));
+        }
+    }
+    std::vector<double> cb(s), cbh(s);
+    for (int j = 0; j < s; ++j) {
+        cb[j] = c->dt * c->b[j];
+        cbh[j] = c->dt * c->bh[j];
+    }
+    const double *fend = f_stages ? f_stages + (int64_t)s * op->n_bdry : nullptr;
+    TRY(launch_update(op, u, u, c->Lu, c->F, cb.data(), cbh.data(), s, fend, st));
+    return HPS_OK;
+}

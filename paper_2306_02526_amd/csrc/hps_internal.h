@@ -1,0 +1,162 @@
+// Internal declarations shared by the HIP kernels and the host side of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "hps.h"
+
+namespace hps {
+
+constexpr int NT = 256;   // threads per workgroup for every kernel of the library
+constexpr int PMAX = 24;  // largest supported Chebyshev order p
+
+// ---------------------------------------------------------------------------------------
+// Packed operator for a streaming matrix-vector product.
+//
+// A logical R x C matrix (per tree node) is cut into `ntile` row tiles of rp*vw rows and
+// `kch` column chunks of S*G columns.  Inside one (tile, chunk) block, thread t = g*rp + r
+// of a workgroup owns the vw consecutive rows r*vw .. r*vw+vw-1 of the tile and the
+// columns chunk_base + s*G + g, s = 0..S-1.  The block is stored in exactly the order the
+// threads read it, [s][t][vw], so every loop iteration of the workgroup reads one
+// contiguous run of G*rp 16-byte vectors.  Padding rows/columns hold zeros.
+// ---------------------------------------------------------------------------------------
+struct Panel {
+    int R = 0, C = 0;      // logical shape
+    int vw = 2;            // elements per 16-byte vector (2 for FP64, 4 for FP32)
+    int rp = 0, G = 0;     // row vectors per tile, column groups
+    int ntile = 0, kch = 0, S = 0;
+    int64_t tile_elems = 0;   // S*G*rp*vw
+    int64_t node_elems = 0;   // ntile*kch*tile_elems
+    int nodes = 0;
+    void *data = nullptr;     // double* (vw = 2) or float* (vw = 4)
+    int64_t bytes() const { return node_elems * nodes * (vw == 2 ? 8 : 4); }
+};
+
+// Choose the packing of an R x C operator for `nodes` nodes.  rp_max bounds the row
+// vectors per tile (the leaf kernels need the whole matrix in one tile); min_wg asks
+// for at least that many workgroups per sweep (column chunks are added to reach it).
+Panel plan_panel(int R, int C, int vw, int nodes, int rp_max, int min_wg);
+
+// One internal level of the tree (level 0 = root), all nodes of the same shape.
+struct Level {
+    int nodes = 0;
+    int n1 = 0, n2 = 0, n3 = 0, n12 = 0;   // |J1|, |J2|, |J3|, |J1|+|J2|
+    int nbc = 0;                            // boundary length of each child (= n1+n3 = n2+n3)
+    int *a1 = nullptr, *a3 = nullptr, *b2 = nullptr, *b3 = nullptr;   // device local maps
+    int *j3i = nullptr;        // device [nodes][n3]: interface index of each J3 node
+    Panel xu64, s64, xu32, s32;
+    double *h = nullptr;       // [nodes][n12] particular fluxes (upward sweep)
+    double *ub = nullptr;      // [nodes][n12] boundary values (downward sweep)
+    double *w3 = nullptr;      // [nodes][n3]
+    double *part = nullptr;    // split-K partial sums
+};
+
+}  // namespace hps
+
+struct hps_op {
+    hps_grid grid{};
+    int p = 0, q = 0, q2 = 0, L = 0, nleaves = 0;
+    int64_t N = 0, n_int = 0, n_edge = 0, n_vert = 0, n_iface = 0, n_bdry = 0;
+    double gamma_dt = 0, h = 0;
+    int flags = 0;
+    double *D = nullptr, *D2 = nullptr;    // device p*p, row-major: D[a*p + m] = d/dx weight
+    double *coef = nullptr;                // device 5*n_int: cxx, cyy, cx, cy, c0 of L
+    int *leaf_ij = nullptr;                // device [nleaves][2] heap order -> (i, j)
+    int *root_map = nullptr;               // device [n_bdry] root boundary -> boundary index
+    int *bnd_glob = nullptr;               // device [n_bdry] boundary index -> canonical index
+    double *tri_cp = nullptr;              // device: Thomas factors cp[k], then 1/den[k]
+    int tri_stride = 0;                    // offset of the 1/den table in tri_cp
+    hps::Panel ainv64, sleaf64, ainv32, sleaf32;
+    std::vector<hps::Level> lv;            // lv[l], l = 0..L-1
+    double *h_leaf = nullptr, *ub_leaf = nullptr, *w_leaf = nullptr;
+    // iterative refinement workspace (FP32_IR)
+    double *ir_rhs = nullptr, *ir_r = nullptr, *ir_r3 = nullptr, *ir_du = nullptr, *ir_flux = nullptr;
+    double *ir_norms = nullptr;            // [2] max|delta|, max|u| (as ordered bit patterns)
+    int64_t operator_bytes = 0, total_bytes = 0;
+    std::vector<void *> allocs;
+};
+
+struct ark_ctx {
+    hps_op *op = nullptr;
+    int s = 0;
+    double dt = 0;
+    std::vector<double> A, b, c, Ah, bh;
+    ark_g g{};
+    double *Lu = nullptr, *F = nullptr;   // device [s][n_int] each
+    double *rhs = nullptr;                // device [n_int] (FP32_IR stage right-hand side)
+    double *stage_u = nullptr;            // device [N] (FP32_IR stage solution)
+};
+
+// ---------------------------------------------------------------------------------------
+// error reporting
+// ---------------------------------------------------------------------------------------
+void hps_set_error(const char *fmt, ...);
+
+#define HPS_HIP(x)                                                                              \
+    do {                                                                                        \
+        hipError_t e_ = (x);                                                                    \
+        if (e_ != hipSuccess) {                                                                 \
+            hps_set_error("%s failed: %s (%s:%d)", #x, hipGetErrorString(e_), __FILE__, __LINE__); \
+            return HPS_EDEVICE;                                                                 \
+        }                                                                                       \
+    } while (0)
+
+#define HPS_LAUNCHED()  HPS_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------------------------------
+// launchers (hps_kernels.hip)
+// ---------------------------------------------------------------------------------------
+namespace hps {
+
+struct StageCoefs {
+    double ca[8];    // dt * a_ij for j < i (ESDIRK)
+    double cf[8];    // dt * ahat_ij for j < i (ERK)
+    int nprev;       // i (number of previous stages)
+};
+
+struct GPoly {
+    int kind;
+    double g0, g1, g2, g3;
+};
+
+// solve sweeps ---------------------------------------------------------------------------
+int launch_leaf_up(const hps_op *op, bool fp32, const double *body, const double *un,
+                   const double *Lu, const double *F, const StageCoefs *sc, double *rhs_copy,
+                   hipStream_t st);
+int launch_levels_up(const hps_op *op, bool fp32, const double *jump, hipStream_t st);
+int launch_levels_down(const hps_op *op, bool fp32, const double *dirichlet, hipStream_t st);
+// mode 0: write u (canonical, interior + edges); mode 1: write L u and F at interior nodes;
+// mode 2: add the solution to u (FP32_IR correction) and record max|delta|, max|u|.
+int launch_leaf_down(const hps_op *op, bool fp32, int mode, double *u, double *Lu, double *F,
+                     const double *q_src, double q_scale, GPoly g, hipStream_t st);
+int launch_eval(const hps_op *op, const double *u, double *Lu, double *F, const double *q_src,
+                double q_scale, GPoly g, hipStream_t st);
+int launch_update(const hps_op *op, const double *un, double *unew, const double *Lu,
+                  const double *F, const double *cb, const double *cbh, int s,
+                  const double *f_end, hipStream_t st);
+int launch_residual(const hps_op *op, const double *u, const double *rhs, const double *jump,
+                    double *r_int, double *r3, hipStream_t st);
+int launch_scatter_boundary(const hps_op *op, const double *f, double *u, hipStream_t st);
+int launch_zero(double *p, int64_t n, hipStream_t st);
+
+// build --------------------------------------------------------------------------------
+int launch_leaf_assemble(const hps_op *op, double *W, hipStream_t st);
+int gj_invert(double *W, double *out, int n, int nb, unsigned char *used, int *order,
+              double *colbuf, double *rowbuf, int *sing, hipStream_t st);
+int launch_leaf_S(const hps_op *op, const double *ainv, double *S, hipStream_t st);
+int launch_leaf_T(const hps_op *op, const double *S, double *T, hipStream_t st);
+int launch_merge_gather(const Level &L, bool root, const double *Tc, double *M, double *B,
+                        double *Cm, double *Tn, hipStream_t st);
+int launch_dgemm(int M, int N, int K, const double *A, int lda, int64_t sA, const double *B,
+                 int ldb, int64_t sB, double *C, int ldc, int64_t sC, int batch, double alpha,
+                 double beta, hipStream_t st);
+// Pack a column-major operator (rows [0,rows0) from src0, rows [rows0,R) from src1) into a
+// Panel, as FP64 or FP32 according to pn.vw.
+int launch_pack(const Panel &pn, const double *src0, int ld0, int64_t stride0, int rows0,
+                const double *src1, int ld1, int64_t stride1, hipStream_t st);
+
+}  // namespace hps

@@ -1,0 +1,248 @@
+"""Thin ctypes binding of libhps.so (argument marshalling only).
+
+Every function here has the name of the C entry point it calls (include/hps.h).
+Device arrays are PyTorch CUDA float64 tensors; the library runs every step of the
+build and of the solves in its own HIP kernels.  There is no fallback: if the
+library is missing or no GPU is present the calls raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhps.so")
+
+HPS_FP64 = 0
+HPS_FP32_IR = 1
+ERRORS = {-1: "HPS_EINVAL", -2: "HPS_ENOMEM", -3: "HPS_EDEVICE", -4: "HPS_ESINGULAR",
+          -5: "HPS_ENOTCONVERGED"}
+
+# every entry point declared in include/hps.h
+EXPORTED = ["hps_last_error", "hps_num_nodes", "hps_nodes", "hps_build", "hps_op_bytes",
+            "hps_solve", "hps_free", "ark_create", "ark_step", "ark_stage_solves_per_step",
+            "ark_free"]
+
+
+class HPSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class HpsGrid(ctypes.Structure):
+    _fields_ = [("x0", ctypes.c_double), ("x1", ctypes.c_double), ("y0", ctypes.c_double),
+                ("y1", ctypes.c_double), ("n1", ctypes.c_int32), ("n2", ctypes.c_int32),
+                ("p", ctypes.c_int32)]
+
+
+class HpsCoeffs(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("cxx", "cyy", "cx", "cy", "c0")]
+
+
+class HpsInfo(ctypes.Structure):
+    _fields_ = [("ir_iterations", ctypes.c_int32), ("last_correction", ctypes.c_double)]
+
+
+class ArkTableau(ctypes.Structure):
+    _fields_ = [("s", ctypes.c_int32)] + [(n, ctypes.POINTER(ctypes.c_double))
+                                          for n in ("A", "b", "c", "Ahat", "bhat")]
+
+
+class ArkG(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("g0", ctypes.c_double), ("g1", ctypes.c_double),
+                ("g2", ctypes.c_double), ("g3", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libhps.so (built by paper_2306_02526_amd.build_lib)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2306_02526_amd.build_lib`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    P = ctypes.POINTER
+    L.hps_last_error.restype = ctypes.c_char_p
+    L.hps_last_error.argtypes = []
+    L.hps_num_nodes.restype = i64
+    L.hps_num_nodes.argtypes = [P(HpsGrid), P(i64), P(i64), P(i64)]
+    L.hps_nodes.restype = i32
+    L.hps_nodes.argtypes = [P(HpsGrid), P(dbl), P(dbl)]
+    L.hps_build.restype = i32
+    L.hps_build.argtypes = [P(HpsGrid), P(HpsCoeffs), dbl, i32, vp, P(vp)]
+    L.hps_op_bytes.restype = i64
+    L.hps_op_bytes.argtypes = [vp, P(i64)]
+    L.hps_solve.restype = i32
+    L.hps_solve.argtypes = [vp, i32, vp, vp, vp, vp, vp, P(HpsInfo)]
+    L.hps_free.restype = None
+    L.hps_free.argtypes = [vp]
+    L.ark_create.restype = i32
+    L.ark_create.argtypes = [vp, P(ArkTableau), dbl, P(ArkG), P(vp)]
+    L.ark_step.restype = i32
+    L.ark_step.argtypes = [vp, dbl, vp, vp, vp, P(dbl), vp, vp]
+    L.ark_stage_solves_per_step.restype = i32
+    L.ark_stage_solves_per_step.argtypes = [vp]
+    L.ark_free.restype = None
+    L.ark_free.argtypes = [vp]
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc < 0:
+        raise HPSError(rc, lib().hps_last_error().decode())
+    return rc
+
+
+def hps_last_error():
+    return lib().hps_last_error().decode()
+
+
+def make_grid(x0, x1, y0, y1, n1, n2, p):
+    return HpsGrid(float(x0), float(x1), float(y0), float(y1), int(n1), int(n2), int(p))
+
+
+def hps_num_nodes(grid):
+    """(N, n_int, n_iface, n_bdry)"""
+    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    N = _check(lib().hps_num_nodes(ctypes.byref(grid), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return int(N), a.value, b.value, c.value
+
+
+def hps_nodes(grid):
+    N = hps_num_nodes(grid)[0]
+    x = np.empty(N)
+    y = np.empty(N)
+    P = ctypes.POINTER(ctypes.c_double)
+    _check(lib().hps_nodes(ctypes.byref(grid), x.ctypes.data_as(P), y.ctypes.data_as(P)))
+    return x, y
+
+
+def _dptr(t, n=None, name="array"):
+    """Device pointer of a contiguous float64 CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+class HpsOp:
+    """Owns an hps_op handle (freed with hps_free)."""
+
+    def __init__(self, handle, grid, gamma_dt, flags, sizes, keep):
+        self.handle = handle
+        self.grid = grid
+        self.gamma_dt = gamma_dt
+        self.flags = flags
+        self.N, self.n_int, self.n_iface, self.n_bdry = sizes
+        self._keep = keep
+
+    def bytes(self):
+        ob = ctypes.c_int64()
+        tot = _check(lib().hps_op_bytes(self.handle, ctypes.byref(ob)))
+        return int(tot), ob.value
+
+    def free(self):
+        if self.handle:
+            lib().hps_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def hps_build(grid, coeffs, gamma_dt, flags=HPS_FP64, stream=None):
+    """coeffs: dict with any of cxx, cyy, cx, cy, c0 -> float64 CUDA tensors of n_int."""
+    sizes = hps_num_nodes(grid)
+    n_int = sizes[1]
+    keep = {k: v for k, v in coeffs.items() if v is not None}
+    c = HpsCoeffs(*[_dptr(coeffs.get(k), n_int, k) for k in ("cxx", "cyy", "cx", "cy", "c0")])
+    h = ctypes.c_void_p()
+    _check(lib().hps_build(ctypes.byref(grid), ctypes.byref(c), float(gamma_dt), int(flags),
+                           _stream(stream), ctypes.byref(h)))
+    return HpsOp(h, grid, float(gamma_dt), flags, sizes, keep)
+
+
+def hps_solve(op, body, dirichlet=None, jump=None, u=None, stream=None, info=False):
+    """Solve (I - gamma_dt L) u = body; body [nrhs, n_int] or [n_int]. Returns u."""
+    import torch
+    squeeze = body.dim() == 1
+    nrhs = 1 if squeeze else body.shape[0]
+    if u is None:
+        u = torch.empty((op.N,) if squeeze else (nrhs, op.N), dtype=torch.float64, device=body.device)
+    inf = HpsInfo()
+    _check(lib().hps_solve(op.handle, nrhs, _dptr(body, nrhs * op.n_int, "body"),
+                           _dptr(dirichlet, nrhs * op.n_bdry, "dirichlet"),
+                           _dptr(jump, nrhs * op.n_iface, "jump"), _dptr(u, nrhs * op.N, "u"),
+                           _stream(stream), ctypes.byref(inf) if info else None))
+    if info:
+        return u, {"ir_iterations": inf.ir_iterations, "last_correction": inf.last_correction}
+    return u
+
+
+class ArkCtx:
+    def __init__(self, handle, op, s):
+        self.handle = handle
+        self.op = op
+        self.s = s
+
+    def free(self):
+        if self.handle:
+            lib().ark_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def ark_create(op, tableau, dt, g=None):
+    """tableau: dict with s, A (s x s), b, c, Ahat, bhat.  g: None or (g0, g1, g2, g3)."""
+    s = int(tableau["s"])
+    arrs = {k: np.ascontiguousarray(np.asarray(tableau[k], dtype=np.float64).ravel())
+            for k in ("A", "b", "c", "Ahat", "bhat")}
+    P = ctypes.POINTER(ctypes.c_double)
+    tab = ArkTableau(s, *[arrs[k].ctypes.data_as(P) for k in ("A", "b", "c", "Ahat", "bhat")])
+    gg = ArkG(0, 0.0, 0.0, 0.0, 0.0) if g is None else ArkG(1, *[float(v) for v in g])
+    h = ctypes.c_void_p()
+    _check(lib().ark_create(op.handle, ctypes.byref(tab), float(dt), ctypes.byref(gg), ctypes.byref(h)))
+    return ArkCtx(h, op, s)
+
+
+def ark_step(ctx, t, u, q_stages=None, q_space=None, q_time=None, f_stages=None, stream=None):
+    op, s = ctx.op, ctx.s
+    qt = None
+    if q_time is not None:
+        qt_arr = np.ascontiguousarray(np.asarray(q_time, dtype=np.float64))
+        if qt_arr.size != s:
+            raise ValueError("q_time needs one value per stage")
+        qt = qt_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(lib().ark_step(ctx.handle, float(t), _dptr(u, op.N, "u"),
+                          _dptr(q_stages, s * op.n_int, "q_stages"), _dptr(q_space, op.n_int, "q_space"),
+                          qt, _dptr(f_stages, (s + 1) * op.n_bdry, "f_stages"), _stream(stream)))
+    return u
+
+
+def ark_stage_solves_per_step(ctx):
+    return _check(lib().ark_stage_solves_per_step(ctx.handle))

@@ -1,0 +1,285 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle on the same seeded inputs.
+
+FP64 path: relative max-norm difference <= 1e-11 (the accuracy target stated for the
+FP64 path).  FP32 operators with FP64 iterative refinement: <= 1e-10.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.ark import ARK, apply_L, ark436l2sa, tableau_float
+from oracle.dense import flux_jump_matrix
+from oracle.grid import Grid
+from oracle.hps import HPS
+from paper_2306_02526_amd import hps, workloads
+from paper_2306_02526_amd.tableau import ark436l2sa as product_tableau
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+TOL32IR = 1e-10
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    return _t
+
+
+def var_coefs(x, y):
+    """Smooth variable coefficients with convection and reaction (any fixed closed form)."""
+    return dict(cxx=1.0 + 0.3 * np.sin(x + 2 * y), cyy=1.2 + 0.2 * np.cos(3 * x),
+                cx=0.5 * np.sin(y), cy=-0.4 * np.cos(x), c0=0.3 * np.sin(x * y))
+
+
+def setup(torch, n1, n2, p, gdt, flags=hps.HPS_FP64, x0=0.0, y0=0.0, h=None, coef_fn=var_coefs):
+    h = h or 1.0 / max(n1, n2)
+    g = hps.make_grid(x0, x0 + n1 * h, y0, y0 + n2 * h, n1, n2, p)
+    og = Grid(x0, x0 + n1 * h, y0, y0 + n2 * h, n1, n2, p)
+    x, y = hps.hps_nodes(g)
+    co = coef_fn(x[: og.n_int], y[: og.n_int])
+    dev = {k: torch.tensor(v, dtype=torch.float64, device="cuda") for k, v in co.items()}
+    op = hps.hps_build(g, dev, gdt, flags)
+    return g, og, x, y, co, op
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+SHAPES = [(1, 1, 5), (2, 1, 6), (1, 2, 3), (2, 2, 8), (4, 4, 8), (8, 4, 10), (4, 8, 12),
+          (16, 16, 16), (2, 2, 24), (32, 8, 7)]
+
+
+@pytest.mark.parametrize("n1,n2,p", SHAPES)
+def test_solve_matches_oracle_fp64(torch, n1, n2, p):
+    say(f"[solve fp64] n1={n1} n2={n2} p={p}")
+    rng = np.random.default_rng(1000 + 100 * n1 + 10 * n2 + p)
+    gdt = 0.01
+    g, og, x, y, co, op = setup(torch, n1, n2, p, gdt)
+    H = HPS(og, co, gdt)
+    nrhs = 2
+    body = rng.standard_normal((nrhs, og.n_int))
+    dirv = rng.standard_normal((nrhs, op.n_bdry))
+    jump = rng.standard_normal((nrhs, op.n_iface)) if op.n_iface else None
+    T = lambda a: None if a is None else torch.tensor(a, device="cuda")
+    u = hps.hps_solve(op, T(body), T(dirv), T(jump)).cpu().numpy()
+    for r in range(nrhs):
+        ref = H.solve(body[r], dirv[r], None if jump is None else jump[r])
+        e = rel(u[r], ref)
+        say(f"   rhs {r}: rel err {e:.2e}")
+        assert e <= TOL64
+
+
+@pytest.mark.parametrize("n1,n2,p", [(2, 2, 8), (8, 8, 12), (16, 8, 16)])
+def test_solve_matches_oracle_fp32_ir(torch, n1, n2, p):
+    say(f"[solve fp32+ir] n1={n1} n2={n2} p={p}")
+    rng = np.random.default_rng(7 + n1 + p)
+    gdt = 2.5e-4
+    g, og, x, y, co, op = setup(torch, n1, n2, p, gdt, flags=hps.HPS_FP32_IR)
+    H = HPS(og, co, gdt)
+    body = rng.standard_normal(og.n_int)
+    dirv = rng.standard_normal(op.n_bdry)
+    u, info = hps.hps_solve(op, torch.tensor(body, device="cuda"), torch.tensor(dirv, device="cuda"),
+                            info=True)
+    e = rel(u.cpu().numpy(), H.solve(body, dirv))
+    say(f"   rel err {e:.2e}, IR iterations {info['ir_iterations']}")
+    assert e <= TOL32IR and 1 <= info["ir_iterations"] <= 10
+
+
+def test_solve_zero_and_homogeneous(torch):
+    say("[solve] zero data gives zero")
+    g, og, x, y, co, op = setup(torch, 4, 4, 6, 0.1)
+    u = hps.hps_solve(op, torch.zeros(og.n_int, dtype=torch.float64, device="cuda"))
+    assert float(u.abs().max()) == 0.0
+
+
+def test_solve_exact_for_polynomials(torch):
+    """Collocation is exact for x^a y^b (a, b <= p-1): the GPU solve returns it to rounding."""
+    say("[solve] polynomial exactness")
+    p, gdt = 7, 0.05
+    g, og, x, y, co, op = setup(torch, 4, 2, p, gdt, x0=-0.3, y0=0.2, h=0.35)
+    xi, yi = x[: og.n_int], y[: og.n_int]
+    ea, eb = p - 1, p - 2
+    u = x ** ea * y ** eb
+    Lu = (co["cxx"] * ea * (ea - 1) * xi ** (ea - 2) * yi ** eb + co["cyy"] * eb * (eb - 1) * xi ** ea * yi ** (eb - 2)
+          + co["cx"] * ea * xi ** (ea - 1) * yi ** eb + co["cy"] * eb * xi ** ea * yi ** (eb - 1) + co["c0"] * u[: og.n_int])
+    body = u[: og.n_int] - gdt * Lu
+    bi = og.boundary_indices()
+    sol = hps.hps_solve(op, torch.tensor(body, device="cuda"), torch.tensor(u[bi], device="cuda")).cpu().numpy()
+    assert rel(sol, u) <= 1e-11
+
+
+def test_build_rejects_mismatched_step(torch):
+    g, og, x, y, co, op = setup(torch, 2, 2, 6, 0.01)
+    tab = product_tableau()
+    with pytest.raises(hps.HPSError) as e:
+        hps.ark_create(op, tab, 0.05)
+    assert e.value.code == -1
+
+
+def test_host_pointer_is_rejected(torch):
+    g, og, x, y, co, op = setup(torch, 2, 2, 6, 0.01)
+    import ctypes
+    host = np.zeros(og.n_int)
+    out = torch.empty(og.N, dtype=torch.float64, device="cuda")
+    rc = hps.lib().hps_solve(op.handle, 1, ctypes.c_void_p(host.ctypes.data), None, None,
+                             ctypes.c_void_p(out.data_ptr()), None, None)
+    assert rc == -1 and "device pointer" in hps.hps_last_error()
+
+
+# ---------------------------------------------------------------------------------------
+# time stepping
+# ---------------------------------------------------------------------------------------
+def _heat_problem(torch, n, p, dt, flags=hps.HPS_FP64, seed_cfg=1):
+    wl = workloads.HeatManufactured(workloads.rng_for(seed_cfg))
+    tab = product_tableau()
+    gdt = tab["gamma"] * dt
+    g = hps.make_grid(0, 1, 0, 1, n, n, p)
+    og = Grid(0, 1, 0, 1, n, n, p)
+    x, y = hps.hps_nodes(g)
+    xi, yi = x[: og.n_int], y[: og.n_int]
+    cxx, cyy, cx, cy, c0 = wl.L_coeffs(xi, yi)
+    co = dict(cxx=cxx, cyy=cyy, cx=cx, cy=cy, c0=c0)
+    op = hps.hps_build(g, {k: torch.tensor(v, device="cuda") for k, v in co.items()}, gdt, flags)
+    ctx = hps.ark_create(op, tab, dt)
+    ark = ARK(HPS(og, co, gdt), co, tableau_float(ark436l2sa()), dt)
+    return wl, tab, g, og, x, y, co, op, ctx, ark
+
+
+def test_ark_heat_manufactured_matches_oracle(torch):
+    """Heat equation with the manufactured solution (4x4 leaves, p = 8, dt = 0.01):
+    separable source q = e^{-t} q_space, homogeneous Dirichlet data."""
+    say("[ark] heat 4x4 p=8")
+    dt = 0.01
+    wl, tab, g, og, x, y, co, op, ctx, ark = _heat_problem(torch, 4, 8, dt)
+    qsp = wl.q_space(x[: og.n_int], y[: og.n_int])
+    u_gpu = torch.tensor(wl.exact(0.0, x, y), device="cuda")
+    u_ref = wl.exact(0.0, x, y)
+    t = 0.0
+    for n in range(20):
+        qt = [wl.q_time(t + c * dt) for c in tab["c"]]
+        hps.ark_step(ctx, t, u_gpu, q_space=torch.tensor(qsp, device="cuda"), q_time=qt)
+        u_ref = ark.step(u_ref, q_stages=np.array([q * qsp for q in qt]))
+        t += dt
+        e = rel(u_gpu.cpu().numpy(), u_ref)
+        assert e <= TOL64, (n, e)
+    err_exact = np.abs(u_ref - wl.exact(t, x, y)).max()
+    say(f"   parity {e:.2e}; oracle error vs exact solution {err_exact:.2e}")
+    assert err_exact < 1e-5
+
+
+def test_ark_allen_cahn_matches_oracle(torch):
+    say("[ark] Allen-Cahn 8x8 p=10 with g = u - u^3")
+    dt = 1e-3
+    tab = product_tableau()
+    gdt = tab["gamma"] * dt
+    g = hps.make_grid(0, 1, 0, 1, 8, 8, 10)
+    og = Grid(0, 1, 0, 1, 8, 8, 10)
+    x, y = hps.hps_nodes(g)
+    xi, yi = x[: og.n_int], y[: og.n_int]
+    wl = workloads.AllenCahn(workloads.rng_for(2))
+    cxx, cyy, cx, cy, c0 = wl.L_coeffs(xi, yi)
+    co = dict(cxx=cxx, cyy=cyy, cx=cx, cy=cy, c0=c0)
+    op = hps.hps_build(g, {k: torch.tensor(v, device="cuda") for k, v in co.items()}, gdt)
+    ctx = hps.ark_create(op, tab, dt, g=workloads.AllenCahn.gpoly)
+    ark = ARK(HPS(og, co, gdt), co, tableau_float(ark436l2sa()), dt, workloads.AllenCahn.gpoly)
+    u0 = wl.u0(x, y)
+    ug = torch.tensor(u0, device="cuda")
+    ur = u0.copy()
+    for n in range(5):
+        hps.ark_step(ctx, n * dt, ug)
+        ur = ark.step(ur)
+        e = rel(ug.cpu().numpy(), ur)
+        say(f"   step {n}: rel err {e:.2e}")
+        assert e <= TOL64
+
+
+def test_ark_inhomogeneous_boundary_and_stage_source(torch):
+    say("[ark] inhomogeneous Dirichlet data, q given per stage")
+    rng = np.random.default_rng(77)
+    dt = 0.02
+    tab = product_tableau()
+    gdt = tab["gamma"] * dt
+    g = hps.make_grid(0, 2, 0, 1, 4, 2, 9)
+    og = Grid(0, 2, 0, 1, 4, 2, 9)
+    x, y = hps.hps_nodes(g)
+    co = var_coefs(x[: og.n_int], y[: og.n_int])
+    op = hps.hps_build(g, {k: torch.tensor(v, device="cuda") for k, v in co.items()}, gdt)
+    gp = (0.1, -0.3, 0.2, -0.5)
+    ctx = hps.ark_create(op, tab, dt, g=gp)
+    ark = ARK(HPS(og, co, gdt), co, tableau_float(ark436l2sa()), dt, gp)
+    bi = og.boundary_indices()
+    u0 = np.sin(x + y) * np.cos(2 * y)
+    ug, ur = torch.tensor(u0, device="cuda"), u0.copy()
+    for n in range(4):
+        t = n * dt
+        qs = np.array([np.cos(x[: og.n_int] * (1 + c)) * math.exp(-(t + c * dt)) for c in tab["c"]])
+        fs = np.array([np.sin(x[bi] + y[bi]) * np.cos(2 * y[bi]) * (1 + t + c * dt)
+                       for c in list(tab["c"]) + [1.0]])
+        hps.ark_step(ctx, t, ug, q_stages=torch.tensor(qs, device="cuda"), f_stages=torch.tensor(fs, device="cuda"))
+        ur = ark.step(ur, qs, fs)
+        e = rel(ug.cpu().numpy(), ur)
+        say(f"   step {n}: rel err {e:.2e}")
+        assert e <= TOL64
+
+
+def test_ark_fp32_ir_matches_oracle(torch):
+    say("[ark fp32+ir] Allen-Cahn 16x16 p=12")
+    dt = 1e-3
+    tab = product_tableau()
+    gdt = tab["gamma"] * dt
+    g = hps.make_grid(0, 1, 0, 1, 16, 16, 12)
+    og = Grid(0, 1, 0, 1, 16, 16, 12)
+    x, y = hps.hps_nodes(g)
+    xi, yi = x[: og.n_int], y[: og.n_int]
+    wl = workloads.AllenCahn(workloads.rng_for(3))
+    cxx, cyy, cx, cy, c0 = wl.L_coeffs(xi, yi)
+    co = dict(cxx=cxx, cyy=cyy, cx=cx, cy=cy, c0=c0)
+    op = hps.hps_build(g, {k: torch.tensor(v, device="cuda") for k, v in co.items()}, gdt, hps.HPS_FP32_IR)
+    ctx = hps.ark_create(op, tab, dt, g=workloads.AllenCahn.gpoly)
+    ark = ARK(HPS(og, co, gdt), co, tableau_float(ark436l2sa()), dt, workloads.AllenCahn.gpoly)
+    ug = torch.tensor(wl.u0(x, y), device="cuda")
+    ur = wl.u0(x, y)
+    for n in range(3):
+        hps.ark_step(ctx, n * dt, ug)
+        ur = ark.step(ur)
+        e = rel(ug.cpu().numpy(), ur)
+        say(f"   step {n}: rel err {e:.2e}")
+        assert e <= TOL32IR
+
+
+def test_full_size_allen_cahn_step_matches_oracle(torch):
+    """The benchmark configuration itself (64x64 leaves, p = 16, FP64): one full step
+    compared element by element with the oracle."""
+    say("[full size] Allen-Cahn 64x64 p=16: oracle build (about a minute on one core)")
+    dt = 1e-3
+    tab = product_tableau()
+    gdt = tab["gamma"] * dt
+    g = hps.make_grid(0, 1, 0, 1, 64, 64, 16)
+    og = Grid(0, 1, 0, 1, 64, 64, 16)
+    x, y = hps.hps_nodes(g)
+    xi, yi = x[: og.n_int], y[: og.n_int]
+    wl = workloads.AllenCahn(workloads.rng_for(2))
+    cxx, cyy, cx, cy, c0 = wl.L_coeffs(xi, yi)
+    co = dict(cxx=cxx, cyy=cyy, cx=cx, cy=cy, c0=c0)
+    op = hps.hps_build(g, {k: torch.tensor(v, device="cuda") for k, v in co.items()}, gdt)
+    ctx = hps.ark_create(op, tab, dt, g=workloads.AllenCahn.gpoly)
+    u0 = wl.u0(x, y)
+    ug = torch.tensor(u0, device="cuda")
+    hps.ark_step(ctx, 0.0, ug)
+    say("   GPU step done; building the oracle")
+    ark = ARK(HPS(og, co, gdt), co, tableau_float(ark436l2sa()), dt, workloads.AllenCahn.gpoly)
+    say("   oracle built; stepping")
+    ur = ark.step(u0)
+    e = rel(ug.cpu().numpy(), ur)
+    say(f"   rel err {e:.2e}")
+    assert e <= TOL64
