@@ -1,0 +1,287 @@
+"""Benchmark of the RKHPS per-stage HPS solve on one MI355X.
+
+Workload (default): variable-coefficient Allen-Cahn u_t = div(a grad u) + u - u^3 on
+[0,1]^2, a = 1 + 0.5 sin(2 pi x) cos(2 pi y), 64 x 64 leaves, p = 16 (N = 919,296
+corner-free nodes, 1,048,576 = p^2 n1 n2 with corners), dt = 1e-3, ARK4(3)6L[2]SA,
+seeded sine-mode initial data, homogeneous Dirichlet data.  One bench step is one ARK
+step = 5 implicit stage solves (each with its fused stage right-hand side, L u_i and
+F_i) plus the step completion.  `value` = stage-solves/s in FP64 with everything
+resident in HBM; the operator build is timed separately.
+
+Also reported: the same steps with FP32 operators + FP64 iterative refinement, single
+stage-solve latency percentiles, the roofline of the dominant kernel (the leaf
+particular solve, measured with HIP events on its launch stream) and the CPU oracle
+timed on a bounded sample on this host.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=64, help="leaves per side")
+    ap.add_argument("--p", type=int, default=16)
+    ap.add_argument("--dt", type=float, default=1e-3)
+    ap.add_argument("--fp32-steps", type=int, default=10)
+    ap.add_argument("--latency-samples", type=int, default=100)
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-stage-solves", type=int, default=3)
+    return ap.parse_args()
+
+
+def leaf_up_algorithmic_bytes(n_leaves, q, stages, elem_bytes):
+    """Algorithmic HBM bytes of the leaf particular-solve kernel per launch, averaged over
+    the implicit stages of one step: the q^2 x q^2 operator of every leaf (elem_bytes
+    each), the stage vectors the fused right-hand side reads (u^n and L u_j, F_j for the
+    previous stages, FP64), and the w (q^2) and h (4q) outputs (FP64)."""
+    q2 = q * q
+    nprev = [i for i in range(1, stages)]          # stage i reads 2 i previous vectors
+    vec_reads = sum(1 + 2 * k for k in nprev) / len(nprev)
+    per_leaf = q2 * q2 * elem_bytes + vec_reads * q2 * 8 + q2 * 8 + 4 * q * 8
+    return n_leaves * per_leaf
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2306_02526_amd import hps, workloads
+    from paper_2306_02526_amd.tableau import ark436l2sa
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    n, p, dt = args.n, args.p, args.dt
+    q = p - 2
+    tab = ark436l2sa()
+    gdt = tab["gamma"] * dt
+    g = hps.make_grid(0.0, 1.0, 0.0, 1.0, n, n, p)
+    N, n_int, n_iface, n_bdry = hps.hps_num_nodes(g)
+    x, y = hps.hps_nodes(g)
+    wl = workloads.AllenCahn(workloads.rng_for(2))
+    cxx, cyy, cx, cy, c0 = wl.L_coeffs(x[:n_int], y[:n_int])
+    coefs = {k: torch.tensor(v, device=dev) for k, v in dict(cxx=cxx, cyy=cyy, cx=cx, cy=cy).items()}
+    u0 = torch.tensor(wl.u0(x, y), device=dev)
+    stages = tab["s"] - 1
+
+    # ---- build (FP64) ----
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = hps.hps_build(g, coefs, gdt, hps.HPS_FP64)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    total_bytes, op_bytes = op.bytes()
+    log(f"build FP64: {build_s:.3f} s, operators {op_bytes / 1e9:.3f} GB")
+    ctx = hps.ark_create(op, tab, dt, g=workloads.AllenCahn.gpoly)
+
+    u = u0.clone()
+    for k in range(args.warmup):
+        hps.ark_step(ctx, k * dt, u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        hps.ark_step(ctx, (args.warmup + k) * dt, u)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = stages * args.steps / elapsed
+    log(f"FP64: {ms_per_step:.3f} ms/step, {value:.1f} stage-solves/s")
+    assert torch.isfinite(u).all()
+
+    # ---- per-kernel timing (HIP events on the launch stream), outside the timed region ----
+    hps.hps_profile_enable(op, True)
+    prof_steps = 4
+    for k in range(prof_steps):
+        hps.ark_step(ctx, k * dt, u)
+    torch.cuda.synchronize()
+    prof = hps.hps_profile_read(op)
+    hps.hps_profile_enable(op, False)
+    launches, tot_ms = prof["leaf_up_fp64"]
+    leaf_up_us = 1e3 * tot_ms / launches
+    alg = leaf_up_algorithmic_bytes(n * n, q, tab["s"], 8)
+    achieved = alg / (leaf_up_us * 1e-6) / 1e9
+    breakdown = {k: round(1e3 * v[1] / (prof_steps * (stages if k.startswith(("leaf", "level")) else 1)), 2)
+                 for k, v in prof.items()}
+    log(f"leaf_up_fp64: {leaf_up_us:.1f} us/launch, {achieved:.0f} GB/s; per-stage breakdown (us): {breakdown}")
+    traffic = None
+    tr_path = os.path.join(ROOT, "profiles", "leaf_up_fp64_traffic.json")
+    if os.path.exists(tr_path):
+        try:
+            tr = json.load(open(tr_path))
+            if tr.get("workload") == f"allen_cahn_n{n}_p{p}" and tr.get("kernel_hash") is not None:
+                traffic = tr.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    stage_solve_bytes = op_bytes   # operator bytes streamed by one stage solve
+
+    # ---- single stage-solve latency (hps_solve: one full up/down sweep) ----
+    body = torch.randn(n_int, dtype=torch.float64, device=dev)
+    uo = torch.empty(N, dtype=torch.float64, device=dev)
+    for _ in range(5):
+        hps.hps_solve(op, body, u=uo)
+    lat = []
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.latency_samples)]
+    for a, b in ev:
+        a.record(stream)
+        hps.hps_solve(op, body, u=uo)
+        b.record(stream)
+    torch.cuda.synchronize()
+    lat = np.array([a.elapsed_time(b) for a, b in ev])
+    p50, p99 = float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+    log(f"hps_solve latency: p50 {p50:.3f} ms, p99 {p99:.3f} ms")
+
+    # ---- FP32 operators + FP64 iterative refinement, same steps ----
+    fp32 = None
+    if not args.no_fp32:
+        del ctx
+        op.free()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op32 = hps.hps_build(g, coefs, gdt, hps.HPS_FP32_IR)
+        torch.cuda.synchronize()
+        b32 = time.perf_counter() - t0
+        ctx32 = hps.ark_create(op32, tab, dt, g=workloads.AllenCahn.gpoly)
+        op64 = hps.hps_build(g, coefs, gdt, hps.HPS_FP64)
+        ctx64 = hps.ark_create(op64, tab, dt, g=workloads.AllenCahn.gpoly)
+        u32 = u0.clone()
+        u64 = u0.clone()
+        hps.ark_step(ctx32, 0.0, u32)
+        hps.ark_step(ctx64, 0.0, u64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        errs = []
+        for k in range(1, args.fp32_steps + 1):
+            hps.ark_step(ctx32, k * dt, u32)
+        torch.cuda.synchronize()
+        el32 = time.perf_counter() - t0
+        for k in range(1, args.fp32_steps + 1):
+            hps.ark_step(ctx64, k * dt, u64)
+        torch.cuda.synchronize()
+        rel32 = float((u32 - u64).abs().max() / u64.abs().max())
+        fp32 = {"stage_solves_per_s": round(stages * args.fp32_steps / el32, 1),
+                "ms_per_step": round(1e3 * el32 / args.fp32_steps, 3),
+                "rel_err_vs_fp64_after_steps": rel32, "steps": args.fp32_steps + 1,
+                "build_s": round(b32, 3)}
+        log(f"FP32+IR: {fp32}")
+        op32.free()
+        op64.free()
+
+    # ---- CPU oracle on a bounded sample of the same workload ----
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(n, p, dt, args.cpu_stage_solves)
+        log(f"cpu oracle: {cpu}")
+
+    out = {
+        "metric": "stage-solves/s at N~1M (FP64; FP32+IR reported alongside); p50/p99 solve latency",
+        "value": round(value, 2),
+        "unit": "stage-solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"allen_cahn_variable_coef_{n}x{n}_leaves_p{p}", "n_leaves": n * n, "p": p,
+                   "N_corner_free": N, "N_with_corners": p * p * n * n, "dt": dt,
+                   "tableau": "ARK4(3)6L[2]SA", "stage_solves_per_step": stages,
+                   "parallelism": "single GPU"},
+        "unknowns_per_s": round(value * N, 1),
+        "build_s": round(build_s, 4),
+        "operator_bytes_per_stage_solve": int(stage_solve_bytes),
+        "latency_ms": {"hps_solve_p50": round(p50, 4), "hps_solve_p99": round(p99, 4)},
+        "kernel_us_per_stage": breakdown,
+        "roofline": {"bound": "hbm", "kernel": "k_leaf_up<double>", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "algorithmic_bytes_per_launch": int(alg),
+                     "avg_launch_us": round(leaf_up_us, 2)},
+        "fp32_ir": fp32,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(n, p, dt, n_solves):
+    """The oracle (plain NumPy FP64, one BLAS thread) on this host: its build on the full
+    grid (timed, not counted), then n_solves implicit stages of the same step timed; value
+    = stage-solves/s on those stages."""
+    import subprocess
+    code = f"""
+import os, sys, time, json
+os.environ['OPENBLAS_NUM_THREADS'] = '1'; os.environ['OMP_NUM_THREADS'] = '1'
+sys.path.insert(0, {ROOT!r})
+import numpy as np
+from oracle.grid import Grid
+from oracle.hps import HPS
+from oracle.ark import ARK, apply_L, ark436l2sa, tableau_float, poly_g
+from paper_2306_02526_amd import workloads
+g = Grid(0, 1, 0, 1, {n}, {n}, {p})
+x, y = g.coordinates()
+wl = workloads.AllenCahn(workloads.rng_for(2))
+cxx, cyy, cx, cy, c0 = wl.L_coeffs(x[:g.n_int], y[:g.n_int])
+co = dict(cxx=cxx, cyy=cyy, cx=cx, cy=cy, c0=c0)
+tab = tableau_float(ark436l2sa()); dt = {dt}
+t0 = time.perf_counter(); H = HPS(g, co, tab['gamma'] * dt); tb = time.perf_counter() - t0
+u = wl.u0(x, y); n_int = g.n_int
+A, Ah = tab['A'], tab['Ahat']
+Lu = [apply_L(g, co, u)]; F = [poly_g(workloads.AllenCahn.gpoly, u[:n_int])]
+times = []
+for i in range(1, 1 + {n_solves}):
+    t0 = time.perf_counter()
+    rhs = u[:n_int].copy()
+    for j in range(i):
+        rhs += dt * A[i, j] * Lu[j] + dt * Ah[i, j] * F[j]
+    ui = H.solve(rhs)
+    Lu.append(apply_L(g, co, ui)); F.append(poly_g(workloads.AllenCahn.gpoly, ui[:n_int]))
+    times.append(time.perf_counter() - t0)
+print(json.dumps(dict(build_s=tb, times=times)))
+"""
+    t0 = time.perf_counter()
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                       env=dict(os.environ, OPENBLAS_NUM_THREADS="1", OMP_NUM_THREADS="1"))
+    if r.returncode != 0:
+        return {"error": r.stderr[-400:]}
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    ts = d["times"]
+    try:
+        model = [ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")][0]
+    except Exception:
+        model = "unknown"
+    return {"value": round(len(ts) / sum(ts), 4), "unit": "stage-solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle build on the full {n}x{n} p={p} grid ({d['build_s']:.1f} s, not counted), then "
+                      f"{len(ts)} implicit stages of one step (rhs assembly, HPS solve, L u_i, F_i) timed",
+            "build_s": round(d["build_s"], 2), "host_cpu": model, "host_nproc": os.cpu_count(),
+            "wall_s": round(time.perf_counter() - t0, 1)}
+
+
+if __name__ == "__main__":
+    main()

@@ -117,6 +117,17 @@ HPS_API int hps_solve(hps_op *op, int nrhs, const double *body, const double *di
 
 HPS_API void hps_free(hps_op *op);
 
+/* Kernel timing for measurement tools: while enabled, every kernel family launched
+ * for this operator (leaf_up, level_up, level_down, leaf_down, eval, residual,
+ * update; per precision) is bracketed by HIP events on its launch stream. */
+HPS_API int hps_profile_enable(hps_op *op, int enable);
+
+/* Aggregate the recorded events per kernel family and clear them.  Writes up to
+ * max entries (static name, number of launches, total milliseconds) into the
+ * host arrays names / launches / total_ms (each may be NULL) and returns the
+ * number of families seen.  Waits for the recorded events to complete. */
+HPS_API int hps_profile_read(hps_op *op, int max, const char **names, int64_t *launches, double *total_ms);
+
 /* Additive Runge-Kutta tableau (Sec. 3.1, Table 1): ESDIRK (A, b, c) with
  * A[0][0] = 0 and A[i][i] = gamma for i >= 1, ERK (Ahat, bhat, c), row-major
  * s x s host arrays, 2 <= s <= 8. */

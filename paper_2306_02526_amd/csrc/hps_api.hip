@@ -874,3 +874,40 @@ extern "C" int ark_step(ark_ctx *c, double t, double *u, const double *q_stages,
     TRY(launch_update(op, u, u, c->Lu, c->F, cb.data(), cbh.data(), s, fend, st));
     return HPS_OK;
 }
+
+// ---------------------------------------------------------------------------------------
+// kernel timing
+// ---------------------------------------------------------------------------------------
+extern "C" int hps_profile_enable(hps_op *op, int enable) {
+    CHECK_ARG(op != nullptr, "op is NULL");
+    op->prof.on = enable != 0;
+    return HPS_OK;
+}
+
+extern "C" int hps_profile_read(hps_op *op, int max, const char **names, int64_t *launches, double *total_ms) {
+    CHECK_ARG(op != nullptr, "op is NULL");
+    CHECK_ARG(max >= 0, "max must be >= 0");
+    int64_t cnt[KF_COUNT] = {0};
+    double ms[KF_COUNT] = {0};
+    for (auto &r : op->prof.recs) {
+        HPS_HIP(hipEventSynchronize(r.b));
+        float t = 0.f;
+        HPS_HIP(hipEventElapsedTime(&t, r.a, r.b));
+        cnt[r.fam] += 1;
+        ms[r.fam] += t;
+        op->prof.pool.push_back(r.a);
+        op->prof.pool.push_back(r.b);
+    }
+    op->prof.recs.clear();
+    int n = 0;
+    for (int f = 0; f < KF_COUNT; ++f) {
+        if (!cnt[f]) continue;
+        if (n < max) {
+            if (names) names[n] = kKernelFamilyNames[f];
+            if (launches) launches[n] = cnt[f];
+            if (total_ms) total_ms[n] = ms[f];
+        }
+        ++n;
+    }
+    return n;
+}

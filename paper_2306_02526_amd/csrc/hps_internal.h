@@ -55,6 +55,34 @@ struct Level {
     double *part = nullptr;    // split-K partial sums
 };
 
+// Optional per-kernel timing with HIP events recorded on the launch stream.
+enum KernelFamily {
+    KF_LEAF_UP64, KF_LEAF_UP32, KF_LEVEL_UP64, KF_LEVEL_UP32, KF_LEVEL_DOWN64, KF_LEVEL_DOWN32,
+    KF_LEAF_DOWN64, KF_LEAF_DOWN32, KF_EVAL, KF_RESIDUAL, KF_UPDATE, KF_COUNT
+};
+extern const char *const kKernelFamilyNames[KF_COUNT];
+
+struct Profiler {
+    bool on = false;
+    struct Rec {
+        int fam;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    hipEvent_t get();
+    ~Profiler();
+};
+
+struct ProfScope {
+    Profiler *p;
+    int fam;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    ProfScope(Profiler *p_, int fam_, hipStream_t st_);
+    ~ProfScope();
+};
+
 }  // namespace hps
 
 struct hps_op {
@@ -78,6 +106,7 @@ struct hps_op {
     double *ir_norms = nullptr;            // [2] max|delta|, max|u| (as ordered bit patterns)
     int64_t operator_bytes = 0, total_bytes = 0;
     std::vector<void *> allocs;
+    mutable hps::Profiler prof;
 };
 
 struct ark_ctx {

@@ -906,14 +906,15 @@ __global__ __launch_bounds__(NT) void k_dgemm(GemmArgs g) {
         }
         __syncthreads();
     }
-    const int cj = lane & 15, ci4 = (lane >> 4) * 4;
+    // v_mfma_f64_16x16x4: lane l, register r holds D[l/16 + 4r][l%16]
+    const int cj = lane & 15, ci = lane >> 4;
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = m0 + wm * 32 + x * 16 + ci4 + r;
+                const int row = m0 + wm * 32 + x * 16 + ci + 4 * r;
                 const int col = n0 + wn * 32 + y * 16 + cj;
                 if (row < g.M && col < g.N) {
                     double *c = C + (int64_t)col * g.ldc + row;
@@ -965,9 +966,51 @@ static LeafGeo geo_of(const hps_op *op) {
 
 static inline unsigned nblk(int64_t n, int t = NT) { return (unsigned)((n + t - 1) / t); }
 
+// ---- profiling ---------------------------------------------------------------------------
+const char *const kKernelFamilyNames[KF_COUNT] = {
+    "leaf_up_fp64", "leaf_up_fp32", "level_up_fp64", "level_up_fp32", "level_down_fp64",
+    "level_down_fp32", "leaf_down_fp64", "leaf_down_fp32", "eval", "residual", "update"};
+
+hipEvent_t Profiler::get() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+Profiler::~Profiler() {
+    for (auto &r : recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+ProfScope::ProfScope(Profiler *p_, int fam_, hipStream_t st_) : p(p_), fam(fam_), st(st_) {
+    if (p && p->on) {
+        a = p->get();
+        if (a) (void)hipEventRecord(a, st);
+    }
+}
+
+ProfScope::~ProfScope() {
+    if (p && p->on && a) {
+        hipEvent_t b = p->get();
+        if (b) {
+            (void)hipEventRecord(b, st);
+            p->recs.push_back(Profiler::Rec{fam, a, b});
+        }
+    }
+}
+
 int launch_leaf_up(const hps_op *op, bool fp32, const double *body, const double *un,
                    const double *Lu, const double *F, const StageCoefs *sc, double *rhs_copy,
                    hipStream_t st) {
+    ProfScope ps_(&op->prof, fp32 ? KF_LEAF_UP32 : KF_LEAF_UP64, st);
     LeafUpArgs a{};
     a.ainv = view(fp32 ? op->ainv32 : op->ainv64);
     a.leaf_ij = op->leaf_ij;
@@ -1007,6 +1050,7 @@ static LevelArgs level_args(const hps_op *op, int l, bool fp32, bool up) {
 }
 
 int launch_levels_up(const hps_op *op, bool fp32, const double *jump, hipStream_t st) {
+    ProfScope ps_(&op->prof, fp32 ? KF_LEVEL_UP32 : KF_LEVEL_UP64, st);
     for (int l = op->L - 1; l >= 0; --l) {
         LevelArgs a = level_args(op, l, fp32, true);
         a.r3 = jump;
@@ -1030,6 +1074,7 @@ __global__ void k_root_leaf_ub(const double *dir, const int *root_map, double *u
 }
 
 int launch_levels_down(const hps_op *op, bool fp32, const double *dirichlet, hipStream_t st) {
+    ProfScope ps_(&op->prof, fp32 ? KF_LEVEL_DOWN32 : KF_LEVEL_DOWN64, st);
     if (op->L == 0) {
         hipLaunchKernelGGL(k_root_leaf_ub, dim3(1), dim3(NT), 0, st, dirichlet, (const int *)op->root_map,
                            op->ub_leaf, 4 * op->q);
@@ -1054,6 +1099,7 @@ int launch_levels_down(const hps_op *op, bool fp32, const double *dirichlet, hip
 
 int launch_leaf_down(const hps_op *op, bool fp32, int mode, double *u, double *Lu, double *F,
                      const double *q_src, double q_scale, GPoly g, hipStream_t st) {
+    ProfScope ps_(&op->prof, fp32 ? KF_LEAF_DOWN32 : KF_LEAF_DOWN64, st);
     LeafDownArgs a{};
     a.sl = view(fp32 ? op->sleaf32 : op->sleaf64);
     a.leaf_ij = op->leaf_ij;
@@ -1079,6 +1125,7 @@ int launch_leaf_down(const hps_op *op, bool fp32, int mode, double *u, double *L
 
 int launch_eval(const hps_op *op, const double *u, double *Lu, double *F, const double *q_src,
                 double q_scale, GPoly g, hipStream_t st) {
+    ProfScope ps_(&op->prof, KF_EVAL, st);
     EvalArgs a{};
     a.geo = geo_of(op);
     a.u = u;
@@ -1097,6 +1144,7 @@ int launch_eval(const hps_op *op, const double *u, double *Lu, double *F, const 
 
 int launch_residual(const hps_op *op, const double *u, const double *rhs, const double *jump,
                     double *r_int, double *r3, hipStream_t st) {
+    ProfScope ps_(&op->prof, KF_RESIDUAL, st);
     EvalArgs a{};
     a.geo = geo_of(op);
     a.u = u;
@@ -1120,6 +1168,7 @@ int launch_residual(const hps_op *op, const double *u, const double *rhs, const 
 int launch_update(const hps_op *op, const double *un, double *unew, const double *Lu,
                   const double *F, const double *cb, const double *cbh, int s,
                   const double *f_end, hipStream_t st) {
+    ProfScope ps_(&op->prof, KF_UPDATE, st);
     UpdateArgs a{};
     a.n_int = op->n_int;
     a.un = un;

@@ -20,7 +20,7 @@ ERRORS = {-1: "HPS_EINVAL", -2: "HPS_ENOMEM", -3: "HPS_EDEVICE", -4: "HPS_ESINGU
 
 # every entry point declared in include/hps.h
 EXPORTED = ["hps_last_error", "hps_num_nodes", "hps_nodes", "hps_build", "hps_op_bytes",
-            "hps_solve", "hps_free", "ark_create", "ark_step", "ark_stage_solves_per_step",
+            "hps_solve", "hps_free", "hps_profile_enable", "hps_profile_read", "ark_create", "ark_step", "ark_stage_solves_per_step",
             "ark_free"]
 
 
@@ -81,6 +81,10 @@ def lib():
     L.hps_solve.argtypes = [vp, i32, vp, vp, vp, vp, vp, P(HpsInfo)]
     L.hps_free.restype = None
     L.hps_free.argtypes = [vp]
+    L.hps_profile_enable.restype = i32
+    L.hps_profile_enable.argtypes = [vp, i32]
+    L.hps_profile_read.restype = i32
+    L.hps_profile_read.argtypes = [vp, i32, P(ctypes.c_char_p), P(i64), P(dbl)]
     L.ark_create.restype = i32
     L.ark_create.argtypes = [vp, P(ArkTableau), dbl, P(ArkG), P(vp)]
     L.ark_step.restype = i32
@@ -168,6 +172,20 @@ class HpsOp:
             self.free()
         except Exception:
             pass
+
+
+def hps_profile_enable(op, enable=True):
+    _check(lib().hps_profile_enable(op.handle, 1 if enable else 0))
+
+
+def hps_profile_read(op):
+    """{kernel family: (launches, total_ms)} recorded since the last read."""
+    m = 32
+    names = (ctypes.c_char_p * m)()
+    cnt = (ctypes.c_int64 * m)()
+    ms = (ctypes.c_double * m)()
+    n = _check(lib().hps_profile_read(op.handle, m, names, cnt, ms))
+    return {names[i].decode(): (int(cnt[i]), float(ms[i])) for i in range(min(n, m))}
 
 
 def hps_build(grid, coeffs, gamma_dt, flags=HPS_FP64, stream=None):
