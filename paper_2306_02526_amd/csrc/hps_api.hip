@@ -160,12 +160,16 @@ static void leaf_derivative(int p, double h, std::vector<double> &D, std::vector
 // ---------------------------------------------------------------------------------------
 namespace hps {
 Panel plan_panel(int R, int C, int vw, int nodes, int rp_max, int min_wg) {
-    constexpr int XS_MAX = 1024;
     Panel p;
     p.R = R; p.C = C; p.vw = vw; p.nodes = nodes;
     const int RV = (R + vw - 1) / vw;
     p.ntile = (RV + rp_max - 1) / rp_max;
+    // more, thinner row tiles until the sweep has min_wg workgroups: the column groups of
+    // a workgroup are reduced in LDS, so no cross-workgroup reduction is needed
+    if (min_wg > 0 && (int64_t)nodes * p.ntile < min_wg)
+        p.ntile = (int)std::min<int64_t>(RV, (min_wg + nodes - 1) / nodes);
     p.rp = (RV + p.ntile - 1) / p.ntile;
+    p.ntile = (RV + p.rp - 1) / p.rp;
     const int Gmax = std::max(1, NT / p.rp);
     // column groups: fewest padded columns, then most groups
     int bestG = Gmax;
@@ -178,14 +182,9 @@ Panel plan_panel(int R, int C, int vw, int nodes, int rp_max, int min_wg) {
         }
     }
     p.G = bestG;
+    // column chunks only when one workgroup's input vector would not fit in LDS
     p.kch = 1;
-    const int64_t wgs = (int64_t)nodes * p.ntile;
-    if (min_wg > 0 && wgs < min_wg) {
-        const int want = (int)((min_wg + wgs - 1) / wgs);
-        const int maxk = std::max(1, C / (p.G * 16));
-        p.kch = std::min(want, maxk);
-    }
-    while ((int64_t)((C + p.G * p.kch - 1) / (p.G * p.kch)) * p.G > XS_MAX) ++p.kch;
+    while ((int64_t)((C + p.G * p.kch - 1) / (p.G * p.kch)) * p.G * (vw == 2 ? 8 : 4) > XS_BYTES) ++p.kch;
     p.S = (C + p.G * p.kch - 1) / (p.G * p.kch);
     p.tile_elems = (int64_t)p.S * p.G * p.rp * vw;
     p.node_elems = (int64_t)p.ntile * p.kch * p.tile_elems;
@@ -524,6 +523,7 @@ static int build_impl(hps_op *op, const hps_coeffs *co, hipStream_t st) {
     TRY(dev_alloc(op, &op->h_leaf, (int64_t)nl * nb4));
     TRY(dev_alloc(op, &op->ub_leaf, (int64_t)nl * nb4));
     TRY(dev_alloc(op, &op->w_leaf, (int64_t)nl * q2));
+    TRY(dev_alloc(op, &op->ir_flux, (int64_t)nl * nb4));   // edge flux parts (update, residual)
 
     // ---- merges, bottom-up (merge formulas after eqs. 7-8) ----
     op->lv.assign(op->L, Level{});
@@ -565,15 +565,15 @@ static int build_impl(hps_op *op, const hps_coeffs *co, hipStream_t st) {
             TRY(launch_dgemm(n12, n12, n3, U, n12, s3x, B, n3, s3x, Tn, n12, sxx, nodes, 1.0, 1.0, st));
         }
         const int rows = root ? n3 : n3 + n12;
-        Lv.xu64 = plan_panel(rows, n3, 2, nodes, 64, 512);
-        Lv.s64 = plan_panel(n3, n12, 2, nodes, 64, 512);
+        Lv.xu64 = plan_panel(rows, n3, 2, nodes, 64, 1024);
+        Lv.s64 = plan_panel(n3, n12, 2, nodes, 64, 1024);
         TRY(alloc_panel(op, Lv.xu64));
         TRY(alloc_panel(op, Lv.s64));
         TRY(launch_pack(Lv.xu64, X, n3, s33, n3, U, n12, s3x, st));
         TRY(launch_pack(Lv.s64, Sx, n3, s3x, n3, nullptr, 0, 0, st));
         if (ir) {
-            Lv.xu32 = plan_panel(rows, n3, 4, nodes, 64, 512);
-            Lv.s32 = plan_panel(n3, n12, 4, nodes, 64, 512);
+            Lv.xu32 = plan_panel(rows, n3, 4, nodes, 64, 1024);
+            Lv.s32 = plan_panel(n3, n12, 4, nodes, 64, 1024);
             TRY(alloc_panel(op, Lv.xu32));
             TRY(alloc_panel(op, Lv.s32));
             TRY(launch_pack(Lv.xu32, X, n3, s33, n3, U, n12, s3x, st));
@@ -588,11 +588,19 @@ static int build_impl(hps_op *op, const hps_coeffs *co, hipStream_t st) {
         for (const Panel *pn : {&Lv.xu64, &Lv.s64, &Lv.xu32, &Lv.s32})
             if (pn->kch > 1) part = std::max<int64_t>(part, (int64_t)nodes * pn->ntile * pn->kch * pn->rp * pn->vw);
         if (part) TRY(dev_alloc(op, &Lv.part, part));
+        // split-K arrival counters start at zero; the last arriving workgroup resets them
+        int **cnts[4] = {&Lv.cnt_up64, &Lv.cnt_dn64, &Lv.cnt_up32, &Lv.cnt_dn32};
+        const Panel *pns[4] = {&Lv.xu64, &Lv.s64, &Lv.xu32, &Lv.s32};
+        for (int k = 0; k < 4; ++k) {
+            if (pns[k]->kch <= 1) continue;
+            const int64_t nc = (int64_t)nodes * pns[k]->ntile;
+            TRY(dev_alloc(op, cnts[k], nc));
+            HPS_HIP(hipMemsetAsync(*cnts[k], 0, sizeof(int) * nc, st));
+        }
     }
     if (ir) {
         TRY(dev_alloc(op, &op->ir_r, op->n_int));
         TRY(dev_alloc(op, &op->ir_r3, std::max<int64_t>(op->n_iface, 1)));
-        TRY(dev_alloc(op, &op->ir_flux, (int64_t)nl * nb4));
         TRY(dev_alloc(op, &op->ir_norms, 2));
     }
     HPS_HIP(hipStreamSynchronize(st));

@@ -1,0 +1,428 @@
+// HIP kernels of the HPS build on gfx950: leaf operators (Sec. 2.1, eqs. 5-6), batched
+// Gauss-Jordan inversion, the merge gather and the FP64 MFMA GEMM for the merge formulas
+// after eqs. (7)-(8), and the packing of the stored operators into streaming order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "hps_device.h"
+
+namespace hps {
+
+struct BuildLeafArgs {
+    LeafGeo geo;
+    const int *leaf_ij;
+    const double *coef, *D, *D2;
+    double gamma_dt;
+};
+
+// A_ii of A = I - gdt L on every leaf (heap order), column-major q2 x q2 (Sec. 2.1, eq. 5)
+__global__ __launch_bounds__(NT) void k_leaf_assemble(BuildLeafArgs a, double *W) {
+    __shared__ double D[PMAX * PMAX], D2[PMAX * PMAX];
+    const int leaf = blockIdx.y;
+    const int q = a.geo.q, p = a.geo.p, q2 = q * q;
+    load_dmat(a.D, D, p * p);
+    load_dmat(a.D2, D2, p * p);
+    __syncthreads();
+    const int li = a.leaf_ij[2 * leaf], lj = a.leaf_ij[2 * leaf + 1];
+    const int64_t base = ((int64_t)lj * a.geo.n1 + li) * q2;
+    const int64_t n_int = a.geo.n_int;
+    const int64_t tot = (int64_t)q2 * q2;
+    for (int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * NT) {
+        const int r = (int)(idx % q2), c = (int)(idx / q2);
+        const int a1 = r % q + 1, b1 = r / q + 1, a2 = c % q + 1, b2 = c / q + 1;
+        const int64_t gi = base + r;
+        const double gdt = a.gamma_dt;
+        double v = 0.0;
+        if (b1 == b2) v += -gdt * a.coef[gi] * D2[a1 * p + a2] - gdt * a.coef[2 * n_int + gi] * D[a1 * p + a2];
+        if (a1 == a2) v += -gdt * a.coef[n_int + gi] * D2[b1 * p + b2] - gdt * a.coef[3 * n_int + gi] * D[b1 * p + b2];
+        if (r == c) v += 1.0 - gdt * a.coef[4 * n_int + gi];
+        W[(int64_t)leaf * tot + idx] = v;
+    }
+}
+
+// S_leaf = -A_ii^{-1} A_ib (eq. 6); A_ib has q nonzeros per boundary column.
+__global__ __launch_bounds__(NT) void k_leaf_S(BuildLeafArgs a, const double *ainv, double *S) {
+    __shared__ double D[PMAX * PMAX], D2[PMAX * PMAX];
+    const int leaf = blockIdx.y;
+    const int q = a.geo.q, p = a.geo.p, q2 = q * q, nb = 4 * q;
+    load_dmat(a.D, D, p * p);
+    load_dmat(a.D2, D2, p * p);
+    __syncthreads();
+    const int li = a.leaf_ij[2 * leaf], lj = a.leaf_ij[2 * leaf + 1];
+    const int64_t base = ((int64_t)lj * a.geo.n1 + li) * q2;
+    const int64_t n_int = a.geo.n_int;
+    const double gdt = a.gamma_dt;
+    const double *Ai = ainv + (int64_t)leaf * q2 * q2;
+    const int64_t tot = (int64_t)q2 * nb;
+    for (int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * NT) {
+        const int r = (int)(idx % q2), col = (int)(idx / q2);
+        const int e = col / q, m = col % q;
+        double s = 0.0;
+        for (int c = 1; c <= q; ++c) {
+            int rho;           // interior row of A_ib touching this boundary node
+            double coefv;
+            if (e < 2) {       // left / right edge node (a' = 0 or p-1, b = m+1): rows (c, m+1)
+                rho = m * q + (c - 1);
+                const int ap = (e == 0) ? 0 : p - 1;
+                const int64_t gi = base + rho;
+                coefv = -gdt * a.coef[gi] * D2[c * p + ap] - gdt * a.coef[2 * n_int + gi] * D[c * p + ap];
+            } else {           // bottom / top edge node (a = m+1, b' = 0 or p-1): rows (m+1, c)
+                rho = (c - 1) * q + m;
+                const int bp = (e == 2) ? 0 : p - 1;
+                const int64_t gi = base + rho;
+                coefv = -gdt * a.coef[n_int + gi] * D2[c * p + bp] - gdt * a.coef[3 * n_int + gi] * D[c * p + bp];
+            }
+            s = fma(Ai[(int64_t)rho * q2 + r], coefv, s);
+        }
+        S[(int64_t)leaf * tot + idx] = -s;
+    }
+}
+
+// T_leaf = flux rows applied to [S u_b; u_b]: coordinate-direction derivative on each edge
+__global__ __launch_bounds__(NT) void k_leaf_T(BuildLeafArgs a, const double *S, double *T) {
+    __shared__ double D[PMAX * PMAX];
+    const int leaf = blockIdx.y;
+    const int q = a.geo.q, p = a.geo.p, q2 = q * q, nb = 4 * q;
+    load_dmat(a.D, D, p * p);
+    __syncthreads();
+    const double *Sl = S + (int64_t)leaf * q2 * nb;
+    const int64_t tot = (int64_t)nb * nb;
+    for (int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * NT) {
+        const int row = (int)(idx % nb), col = (int)(idx / nb);
+        const int e = row / q, m = row % q;
+        const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * p);
+        double v = 0.0;
+        for (int c = 1; c <= q; ++c) {
+            const int rho = (e < 2) ? m * q + (c - 1) : (c - 1) * q + m;
+            v = fma(dr[c], Sl[(int64_t)col * q2 + rho], v);
+        }
+        // direct boundary terms: the two edge nodes on the same tile line
+        const int lo = (e < 2) ? 0 * q + m : 2 * q + m;    // left or bottom node of the line
+        const int hi = (e < 2) ? 1 * q + m : 3 * q + m;    // right or top node of the line
+        if (col == lo) v += dr[0];
+        if (col == hi) v += dr[p - 1];
+        T[(int64_t)leaf * tot + idx] = v;
+    }
+}
+
+// Gather the merge blocks of level-l nodes from their children's DtN maps (column-major):
+// M = T^a_33 - T^b_33, B = [-T^a_31 | T^b_32], Cm = [T^a_13; T^b_23], Tn = diag(T^a_11, T^b_22).
+struct MergeArgs {
+    int n1, n2, n3, n12, nbc;
+    const int *a1, *a3, *b2, *b3;
+    const double *Tc;
+    double *M, *B, *Cm, *Tn;
+};
+
+__global__ __launch_bounds__(NT) void k_merge_gather(MergeArgs a) {
+    const int node = blockIdx.y;
+    const int64_t nbc2 = (int64_t)a.nbc * a.nbc;
+    const double *Ta = a.Tc + (int64_t)(2 * node) * nbc2;
+    const double *Tb = a.Tc + (int64_t)(2 * node + 1) * nbc2;
+    auto ta = [&](int r, int c) { return Ta[(int64_t)c * a.nbc + r]; };
+    auto tb = [&](int r, int c) { return Tb[(int64_t)c * a.nbc + r]; };
+    const int n3 = a.n3, n12 = a.n12, n1 = a.n1;
+    const int64_t sM = (int64_t)n3 * n3, sB = (int64_t)n3 * n12, sT = (int64_t)n12 * n12;
+    const int64_t tot = sM + 2 * sB + (a.Tn ? sT : 0);
+    for (int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * NT) {
+        if (idx < sM) {
+            const int r = (int)(idx % n3), c = (int)(idx / n3);
+            a.M[node * sM + idx] = ta(a.a3[r], a.a3[c]) - tb(a.b3[r], a.b3[c]);
+        } else if (idx < sM + sB) {
+            const int64_t k = idx - sM;
+            const int r = (int)(k % n3), c = (int)(k / n3);
+            a.B[node * sB + k] = (c < n1) ? -ta(a.a3[r], a.a1[c]) : tb(a.b3[r], a.b2[c - n1]);
+        } else if (idx < sM + 2 * sB) {
+            const int64_t k = idx - sM - sB;
+            const int r = (int)(k % n12), c = (int)(k / n12);
+            a.Cm[node * sB + k] = (r < n1) ? ta(a.a1[r], a.a3[c]) : tb(a.b2[r - n1], a.b3[c]);
+        } else {
+            const int64_t k = idx - sM - 2 * sB;
+            const int r = (int)(k % n12), c = (int)(k / n12);
+            double v = 0.0;
+            if (r < n1 && c < n1) v = ta(a.a1[r], a.a1[c]);
+            else if (r >= n1 && c >= n1) v = tb(a.b2[r - n1], a.b2[c - n1]);
+            a.Tn[node * sT + k] = v;
+        }
+    }
+}
+
+// ---- Gauss-Jordan inversion with partial pivoting, batched, column-major --------------
+// Step k picks the unused row with the largest |W[i][k]|, scales it and eliminates column
+// k from every other row in place; rows are never swapped.  After n steps with pivot rows
+// r_0..r_{n-1}, inv(A)[k][r_j] = W[r_k][j].
+__global__ __launch_bounds__(NT) void k_gj_pivot(double *W, int n, int k, unsigned char *used,
+                                                 int *order, double *colbuf, double *rowbuf,
+                                                 int *sing) {
+    __shared__ double bv[NT];
+    __shared__ int bi[NT];
+    const int b = blockIdx.x;
+    double *Wb = W + (int64_t)b * n * n;
+    unsigned char *ub = used + (int64_t)b * n;
+    double best = -1.0;
+    int besti = n;
+    for (int i = threadIdx.x; i < n; i += NT) {
+        if (!ub[i]) {
+            const double v = fabs(Wb[(int64_t)k * n + i]);
+            if (v > best || (v == best && i < besti)) {
+                best = v;
+                besti = i;
+            }
+        }
+    }
+    bv[threadIdx.x] = best;
+    bi[threadIdx.x] = besti;
+    __syncthreads();
+    for (int off = NT / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) {
+            const double v2 = bv[threadIdx.x + off];
+            const int i2 = bi[threadIdx.x + off];
+            if (v2 > bv[threadIdx.x] || (v2 == bv[threadIdx.x] && i2 < bi[threadIdx.x])) {
+                bv[threadIdx.x] = v2;
+                bi[threadIdx.x] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    int pr = bi[0];
+    double piv = 0.0;
+    if (pr < n) piv = Wb[(int64_t)k * n + pr];
+    if (pr >= n || piv == 0.0 || !isfinite(piv)) {
+        if (threadIdx.x == 0) atomicExch(sing, 1);
+        if (pr >= n) pr = 0;
+        piv = 1.0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ub[pr] = 1;
+        order[(int64_t)b * n + k] = pr;
+    }
+    const double ip = 1.0 / piv;
+    for (int i = threadIdx.x; i < n; i += NT) {
+        colbuf[(int64_t)b * n + i] = Wb[(int64_t)k * n + i];
+        rowbuf[(int64_t)b * n + i] = (i == k) ? ip : Wb[(int64_t)i * n + pr] * ip;
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_gj_update(double *W, int n, int nb, int k, const int *order,
+                                                  const double *colbuf, const double *rowbuf) {
+    const int64_t nn = (int64_t)n * n;
+    const int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x;
+    if (idx >= nn * nb) return;
+    const int b = (int)(idx / nn);
+    const int64_t rem = idx - b * nn;
+    const int j = (int)(rem / n), i = (int)(rem % n);
+    const int pr = order[(int64_t)b * n + k];
+    const double *cb = colbuf + (int64_t)b * n;
+    const double *rb = rowbuf + (int64_t)b * n;
+    if (i == pr) W[idx] = rb[j];
+    else if (j == k) W[idx] = -cb[i] * rb[k];
+    else W[idx] = fma(-cb[i], rb[j], W[idx]);
+}
+
+__global__ void k_gj_unpermute(const double *W, double *out, int n, int nb, const int *order) {
+    const int64_t nn = (int64_t)n * n;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= nn * nb) return;
+    const int b = (int)(idx / nn);
+    const int64_t rem = idx - b * nn;
+    const int j = (int)(rem / n), k = (int)(rem % n);
+    const int *o = order + (int64_t)b * n;
+    // out[k][o[j]] = W[o[k]][j]  (column-major)
+    out[b * nn + (int64_t)o[j] * n + k] = W[b * nn + (int64_t)j * n + o[k]];
+}
+
+// ---- batched FP64 GEMM on the matrix cores ----------------------------------------------
+// C = alpha A B + beta C, column-major, 64x64 tile per workgroup, each wave a 32x32
+// sub-tile of 2x2 v_mfma_f64_16x16x4 blocks; K staged through LDS 16 at a time.
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
+struct GemmArgs {
+    int M, N, K;
+    const double *A; int lda; int64_t sA;
+    const double *B; int ldb; int64_t sB;
+    double *C; int ldc; int64_t sC;
+    double alpha, beta;
+};
+
+__global__ __launch_bounds__(NT) void k_dgemm(GemmArgs g) {
+    constexpr int TM = 64, TN = 64, TK = 16;
+    __shared__ double As[TK][TM + 1];
+    __shared__ double Bs[TK][TN + 1];
+    const int bz = blockIdx.z;
+    const double *A = g.A + bz * g.sA;
+    const double *B = g.B + bz * g.sB;
+    double *C = g.C + bz * g.sC;
+    const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int wm = wave & 1, wn = wave >> 1;
+    dvec4 acc[2][2];
+    for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y) acc[x][y] = dvec4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < g.K; k0 += TK) {
+        for (int e = t; e < TM * TK; e += NT) {
+            const int i = e % TM, kk = e / TM;
+            const int gm = m0 + i, gk = k0 + kk;
+            As[kk][i] = (gm < g.M && gk < g.K) ? A[(int64_t)gk * g.lda + gm] : 0.0;
+        }
+        for (int e = t; e < TN * TK; e += NT) {
+            const int kk = e % TK, j = e / TK;
+            const int gn = n0 + j, gk = k0 + kk;
+            Bs[kk][j] = (gn < g.N && gk < g.K) ? B[(int64_t)gn * g.ldb + gk] : 0.0;
+        }
+        __syncthreads();
+        const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+        for (int kk = 0; kk < TK; kk += 4) {
+            double av[2], bv[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) av[x] = As[kk + lk][wm * 32 + x * 16 + li];
+#pragma unroll
+            for (int y = 0; y < 2; ++y) bv[y] = Bs[kk + lk][wn * 32 + y * 16 + li];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // v_mfma_f64_16x16x4: lane l, register r holds D[l/16 + 4r][l%16]
+    const int cj = lane & 15, ci = lane >> 4;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm * 32 + x * 16 + ci + 4 * r;
+                const int col = n0 + wn * 32 + y * 16 + cj;
+                if (row < g.M && col < g.N) {
+                    double *c = C + (int64_t)col * g.ldc + row;
+                    const double v = g.alpha * acc[x][y][r];
+                    *c = (g.beta == 0.0) ? v : fma(g.beta, *c, v);
+                }
+            }
+}
+
+// ---- pack a column-major operator into the streaming layout ------------------------------
+struct PackArgs {
+    int R, C, vw, rp, G, S, ntile, kch;
+    int64_t tile_elems, node_elems, total;
+    const double *src0; int ld0; int64_t stride0; int rows0;
+    const double *src1; int ld1; int64_t stride1;
+    void *dst;
+};
+
+template <typename T>
+__global__ void k_pack(PackArgs a) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.total) return;
+    const int64_t node = idx / a.node_elems;
+    int64_t rem = idx - node * a.node_elems;
+    const int64_t blk = rem / a.tile_elems;
+    rem -= blk * a.tile_elems;
+    const int tile = (int)(blk / a.kch), chunk = (int)(blk % a.kch);
+    const int act = a.rp * a.G;
+    const int s = (int)(rem / ((int64_t)act * a.vw));
+    const int tv = (int)(rem % ((int64_t)act * a.vw));
+    const int t = tv / a.vw, v = tv % a.vw;
+    const int g = t / a.rp, r = t % a.rp;
+    const int row = tile * a.rp * a.vw + r * a.vw + v;
+    const int col = chunk * a.S * a.G + s * a.G + g;
+    double val = 0.0;
+    if (row < a.R && col < a.C) {
+        if (row < a.rows0) val = a.src0[node * a.stride0 + (int64_t)col * a.ld0 + row];
+        else val = a.src1[node * a.stride1 + (int64_t)col * a.ld1 + (row - a.rows0)];
+    }
+    reinterpret_cast<T *>(a.dst)[idx] = (T)val;
+}
+
+// =======================================================================================
+// launchers
+// =======================================================================================
+static BuildLeafArgs build_leaf_args(const hps_op *op) {
+    return BuildLeafArgs{geo_of(op), op->leaf_ij, op->coef, op->D, op->D2, op->gamma_dt};
+}
+
+int launch_leaf_assemble(const hps_op *op, double *W, hipStream_t st) {
+    const int64_t tot = (int64_t)op->q2 * op->q2;
+    const unsigned bx = (unsigned)std::min<int64_t>(nblk(tot), 64);
+    hipLaunchKernelGGL(k_leaf_assemble, dim3(bx, op->nleaves), dim3(NT), 0, st, build_leaf_args(op), W);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+int launch_leaf_S(const hps_op *op, const double *ainv, double *S, hipStream_t st) {
+    const int64_t tot = (int64_t)op->q2 * 4 * op->q;
+    const unsigned bx = (unsigned)std::min<int64_t>(nblk(tot), 64);
+    hipLaunchKernelGGL(k_leaf_S, dim3(bx, op->nleaves), dim3(NT), 0, st, build_leaf_args(op), ainv, S);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+int launch_leaf_T(const hps_op *op, const double *S, double *T, hipStream_t st) {
+    const int64_t tot = (int64_t)16 * op->q * op->q;
+    const unsigned bx = (unsigned)std::min<int64_t>(nblk(tot), 64);
+    hipLaunchKernelGGL(k_leaf_T, dim3(bx, op->nleaves), dim3(NT), 0, st, build_leaf_args(op), S, T);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+int launch_merge_gather(const Level &L, bool root, const double *Tc, double *M, double *B,
+                        double *Cm, double *Tn, hipStream_t st) {
+    MergeArgs a{L.n1, L.n2, L.n3, L.n12, L.nbc, L.a1, L.a3, L.b2, L.b3, Tc, M, B, Cm, root ? nullptr : Tn};
+    const int64_t tot = (int64_t)L.n3 * L.n3 + 2 * (int64_t)L.n3 * L.n12 +
+                        (root ? 0 : (int64_t)L.n12 * L.n12);
+    const unsigned bx = (unsigned)std::min<int64_t>(nblk(tot), 4096);
+    hipLaunchKernelGGL(k_merge_gather, dim3(bx, L.nodes), dim3(NT), 0, st, a);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+int gj_invert(double *W, double *out, int n, int nb, unsigned char *used, int *order,
+              double *colbuf, double *rowbuf, int *sing, hipStream_t st) {
+    HPS_HIP(hipMemsetAsync(used, 0, (size_t)n * nb, st));
+    const int64_t tot = (int64_t)n * n * nb;
+    for (int k = 0; k < n; ++k) {
+        hipLaunchKernelGGL(k_gj_pivot, dim3(nb), dim3(NT), 0, st, W, n, k, used, order, colbuf, rowbuf, sing);
+        HPS_LAUNCHED();
+        hipLaunchKernelGGL(k_gj_update, dim3(nblk(tot)), dim3(NT), 0, st, W, n, nb, k,
+                           (const int *)order, (const double *)colbuf, (const double *)rowbuf);
+        HPS_LAUNCHED();
+    }
+    hipLaunchKernelGGL(k_gj_unpermute, dim3(nblk(tot)), dim3(NT), 0, st, (const double *)W, out, n, nb,
+                       (const int *)order);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+int launch_dgemm(int M, int N, int K, const double *A, int lda, int64_t sA, const double *B,
+                 int ldb, int64_t sB, double *C, int ldc, int64_t sC, int batch, double alpha,
+                 double beta, hipStream_t st) {
+    if (M <= 0 || N <= 0 || batch <= 0) return HPS_OK;
+    GemmArgs g{M, N, K, A, lda, sA, B, ldb, sB, C, ldc, sC, alpha, beta};
+    hipLaunchKernelGGL(k_dgemm, dim3(nblk(M, 64), nblk(N, 64), batch), dim3(NT), 0, st, g);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+int launch_pack(const Panel &pn, const double *src0, int ld0, int64_t stride0, int rows0,
+                const double *src1, int ld1, int64_t stride1, hipStream_t st) {
+    PackArgs a{};
+    a.R = pn.R; a.C = pn.C; a.vw = pn.vw; a.rp = pn.rp; a.G = pn.G; a.S = pn.S;
+    a.ntile = pn.ntile; a.kch = pn.kch;
+    a.tile_elems = pn.tile_elems; a.node_elems = pn.node_elems;
+    a.total = pn.node_elems * pn.nodes;
+    a.src0 = src0; a.ld0 = ld0; a.stride0 = stride0; a.rows0 = rows0;
+    a.src1 = src1; a.ld1 = ld1; a.stride1 = stride1;
+    a.dst = pn.data;
+    if (pn.vw == 2) hipLaunchKernelGGL(k_pack<double>, dim3(nblk(a.total)), dim3(NT), 0, st, a);
+    else hipLaunchKernelGGL(k_pack<float>, dim3(nblk(a.total)), dim3(NT), 0, st, a);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+}  // namespace hps

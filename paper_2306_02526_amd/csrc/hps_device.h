@@ -1,0 +1,154 @@
+// Device-side helpers shared by the solve and build kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "hps_internal.h"
+
+namespace hps {
+
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct V16;
+template <> struct V16<double> { using type = dvec2; };
+template <> struct V16<float> { using type = fvec4; };
+
+__device__ __forceinline__ void vfma(double *acc, const dvec2 &v, double x) {
+    acc[0] = fma(v.x, x, acc[0]);
+    acc[1] = fma(v.y, x, acc[1]);
+}
+__device__ __forceinline__ void vfma(float *acc, const fvec4 &v, float x) {
+    acc[0] = fmaf(v.x, x, acc[0]);
+    acc[1] = fmaf(v.y, x, acc[1]);
+    acc[2] = fmaf(v.z, x, acc[2]);
+    acc[3] = fmaf(v.w, x, acc[3]);
+}
+
+struct PanelView {
+    const void *data;
+    int rp, G, S, ntile, kch;
+    int64_t tile_elems, node_elems;
+};
+
+inline PanelView view(const Panel &p) {
+    return PanelView{p.data, p.rp, p.G, p.S, p.ntile, p.kch, p.tile_elems, p.node_elems};
+}
+
+// Streaming product of one (tile, chunk) block of a Panel with an LDS vector.
+// start(): issue the first PF 16-byte loads of this lane (they do not depend on the
+// input vector, so callers start them before gathering it); finish(): consume them and
+// stream the rest with UNR loads in flight, then store the lane's partial sums.
+template <typename T, int PF, int UNR>
+struct PanelStream {
+    using V = typename V16<T>::type;
+    static constexpr int VW = 16 / sizeof(T);
+    const V *p;
+    int act, S, G, g, r;
+    bool on;
+    V pre[PF];
+
+    __device__ __forceinline__ void start(const T *blk, int rp, int G_, int S_) {
+        const int t = threadIdx.x;
+        act = rp * G_;
+        S = S_;
+        G = G_;
+        on = t < act;
+        g = on ? t / rp : 0;
+        r = on ? t - g * rp : 0;
+        p = reinterpret_cast<const V *>(blk) + t;
+        if (on) {
+#pragma unroll
+            for (int u = 0; u < PF; ++u)
+                if (u < S) pre[u] = __builtin_nontemporal_load(p + (size_t)u * act);
+        }
+    }
+
+    __device__ __forceinline__ void finish(const T *__restrict__ xs, T *__restrict__ part) {
+        if (!on) return;
+        T acc[VW];
+#pragma unroll
+        for (int v = 0; v < VW; ++v) acc[v] = T(0);
+#pragma unroll
+        for (int u = 0; u < PF; ++u)
+            if (u < S) vfma(acc, pre[u], xs[u * G + g]);
+        int s = PF;
+        for (; s + UNR <= S; s += UNR) {
+            V vv[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) vv[u] = __builtin_nontemporal_load(p + (size_t)(s + u) * act);
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) vfma(acc, vv[u], xs[(s + u) * G + g]);
+        }
+        for (; s < S; ++s) vfma(acc, __builtin_nontemporal_load(p + (size_t)s * act), xs[s * G + g]);
+        T *dst = part + g * (act / G * VW) + r * VW;
+#pragma unroll
+        for (int v = 0; v < VW; ++v) dst[v] = acc[v];
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ double panel_sum(const T *__restrict__ part, int rp, int G, int idx) {
+    constexpr int VW = 16 / sizeof(T);
+    T s = T(0);
+    for (int g = 0; g < G; ++g) s += part[g * (rp * VW) + idx];
+    return (double)s;
+}
+
+// LDS carve-up helper for dynamic shared memory
+struct Carve {
+    unsigned char *base;
+    size_t off = 0;
+    template <typename T>
+    __device__ __forceinline__ T *take(size_t n) {
+        off = (off + 15) & ~size_t(15);
+        T *ptr = reinterpret_cast<T *>(base + off);
+        off += n * sizeof(T);
+        return ptr;
+    }
+};
+
+inline size_t carve_bytes(std::initializer_list<size_t> sizes) {
+    size_t off = 0;
+    for (size_t s : sizes) off = ((off + 15) & ~size_t(15)) + s;
+    return off;
+}
+
+struct LeafGeo {
+    int n1, n2, q, p;
+    int64_t n_int, n_vert;
+};
+
+inline LeafGeo geo_of(const hps_op *op) {
+    return LeafGeo{op->grid.n1, op->grid.n2, op->q, op->p, op->n_int, op->n_vert};
+}
+
+// canonical index of a leaf-edge node: e = 0 left, 1 right, 2 bottom, 3 top; m in 0..q-1
+__device__ __forceinline__ int64_t edge_index(const LeafGeo &g, int i, int j, int e, int m) {
+    switch (e) {
+        case 0: return g.n_int + ((int64_t)i * g.n2 + j) * g.q + m;
+        case 1: return g.n_int + ((int64_t)(i + 1) * g.n2 + j) * g.q + m;
+        case 2: return g.n_int + g.n_vert + ((int64_t)j * g.n1 + i) * g.q + m;
+        default: return g.n_int + g.n_vert + ((int64_t)(j + 1) * g.n1 + i) * g.q + m;
+    }
+}
+
+// position in the p x p tile (tile[b*p + a]) of leaf-boundary entry e*q + m
+__device__ __forceinline__ int edge_tile_pos(int p, int q, int e, int m) {
+    switch (e) {
+        case 0: return (m + 1) * p;
+        case 1: return (m + 1) * p + (p - 1);
+        case 2: return m + 1;
+        default: return (p - 1) * p + m + 1;
+    }
+}
+
+__device__ __forceinline__ void load_dmat(const double *src, double *dst, int n) {
+    for (int k = threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
+}
+
+static inline unsigned nblk(int64_t n, int t = NT) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace hps

@@ -13,6 +13,7 @@ namespace hps {
 
 constexpr int NT = 256;   // threads per workgroup for every kernel of the library
 constexpr int PMAX = 24;  // largest supported Chebyshev order p
+constexpr int XS_BYTES = 32768;  // LDS bytes for one workgroup's input vector
 
 // ---------------------------------------------------------------------------------------
 // Packed operator for a streaming matrix-vector product.
@@ -53,6 +54,7 @@ struct Level {
     double *ub = nullptr;      // [nodes][n12] boundary values (downward sweep)
     double *w3 = nullptr;      // [nodes][n3]
     double *part = nullptr;    // split-K partial sums
+    int *cnt_up64 = nullptr, *cnt_dn64 = nullptr, *cnt_up32 = nullptr, *cnt_dn32 = nullptr;  // split-K arrivals
 };
 
 // Optional per-kernel timing with HIP events recorded on the launch stream.

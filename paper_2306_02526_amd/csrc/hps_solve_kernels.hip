@@ -1,0 +1,870 @@
+// HIP kernels of the RKHPS per-stage solve on gfx950.
+//
+// Method: Chen, Appelo, Babb & Martinsson, arXiv 2306.02526.
+//   Sec. 2.1 eqs. (5)-(6): leaf solution operator S = -A_ii^{-1} A_ib and DtN map T;
+//   the merge formulas after eqs. (7)-(8); Algorithm 1 (solve stage) extended by the
+//   particular-solution (body load) and interface-jump terms; Sec. 3.1 eqs. (9)-(11):
+//   stage right-hand sides, stage boundary data and the step update.
+//
+// Every solve kernel streams a packed operator (struct Panel) from HBM exactly once: the
+// storage order equals the order in which the workgroup's lanes read it, so each loop
+// iteration of a workgroup is one contiguous run of 16-byte loads.  The first loads are
+// issued before the workgroup gathers its input vector, which hides the gather latency.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "hps_device.h"
+
+namespace hps {
+
+constexpr int PF = 8;    // operator loads issued before the input gather
+constexpr int UNR = 8;   // operator loads in flight in the streaming loop
+
+// L u at interior node k of the tile: cxx u_xx + cyy u_yy + cx u_x + cy u_y + c0 u (eq. 3
+// written for L, c12 = 0), derivatives along the tile row / column through the node.
+__device__ __forceinline__ double tile_L(const double *tile, const double *D, const double *D2,
+                                         int p, int q, const double *coef, int64_t n_int,
+                                         int64_t gidx, int k) {
+    const int a = k % q + 1;
+    const int b = k / q + 1;
+    double ux = 0, uxx = 0, uy = 0, uyy = 0;
+    for (int m = 0; m < p; ++m) {
+        const double xr = tile[b * p + m];
+        const double yc = tile[m * p + a];
+        ux = fma(D[a * p + m], xr, ux);
+        uxx = fma(D2[a * p + m], xr, uxx);
+        uy = fma(D[b * p + m], yc, uy);
+        uyy = fma(D2[b * p + m], yc, uyy);
+    }
+    const double u = tile[b * p + a];
+    return coef[gidx] * uxx + coef[n_int + gidx] * uyy + coef[2 * n_int + gidx] * ux +
+           coef[3 * n_int + gidx] * uy + coef[4 * n_int + gidx] * u;
+}
+
+__device__ __forceinline__ double gpoly(const GPoly &g, double u) {
+    if (g.kind == 0) return 0.0;
+    return g.g0 + u * (g.g1 + u * (g.g2 + u * g.g3));
+}
+
+template <typename T>
+static size_t panel_lds(const Panel &pn) {
+    return (size_t)pn.S * pn.G * sizeof(T) + (size_t)pn.G * pn.rp * pn.vw * sizeof(T) + 32;
+}
+
+// =======================================================================================
+// leaf upward kernel: stage right-hand side, w = A_ii^{-1} rhs, particular fluxes h
+// =======================================================================================
+struct LeafUpArgs {
+    PanelView ainv;
+    const int *leaf_ij;
+    LeafGeo geo;
+    const double *body;   // mode body: canonical interior rhs
+    const double *un;     // mode stage: u^n (canonical, interior part used)
+    const double *Lu, *F; // stage vectors, j-th at + j*n_int
+    StageCoefs sc;
+    double *rhs_copy;     // optional copy of the assembled rhs (canonical interior)
+    const double *D;
+    double *w_out, *h_out;
+};
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_leaf_up(LeafUpArgs a) {
+    constexpr int VW = 16 / sizeof(T);
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int leaf = blockIdx.x;
+    const int q = a.geo.q, p = a.geo.p, q2 = q * q;
+    const int SG = a.ainv.S * a.ainv.G;
+    Carve cv{smem};
+    T *xs = cv.take<T>(SG);
+    T *part = cv.take<T>((size_t)a.ainv.G * a.ainv.rp * VW);
+    double *wv = cv.take<double>(q2);
+    double *d0 = cv.take<double>(p);
+    double *dl = cv.take<double>(p);
+    PanelStream<T, PF, UNR> ps;
+    ps.start(reinterpret_cast<const T *>(a.ainv.data) + (int64_t)leaf * a.ainv.node_elems,
+             a.ainv.rp, a.ainv.G, a.ainv.S);
+    const int li = a.leaf_ij[2 * leaf], lj = a.leaf_ij[2 * leaf + 1];
+    const int64_t base = ((int64_t)lj * a.geo.n1 + li) * q2;
+    for (int k = threadIdx.x; k < SG; k += NT) {
+        double r = 0.0;
+        if (k < q2) {
+            if (a.body) {
+                r = a.body[base + k];
+            } else {
+                r = a.un[base + k];
+                for (int j = 0; j < a.sc.nprev; ++j) {
+                    r += a.sc.ca[j] * a.Lu[j * a.geo.n_int + base + k];
+                    r += a.sc.cf[j] * a.F[j * a.geo.n_int + base + k];
+                }
+                if (a.rhs_copy) a.rhs_copy[base + k] = r;
+            }
+        }
+        xs[k] = (T)r;
+    }
+    for (int k = threadIdx.x; k < p; k += NT) {
+        d0[k] = a.D[k];
+        dl[k] = a.D[(p - 1) * p + k];
+    }
+    __syncthreads();
+    ps.finish(xs, part);
+    __syncthreads();
+    for (int k = threadIdx.x; k < q2; k += NT) {
+        const double w = panel_sum<T>(part, a.ainv.rp, a.ainv.G, k);
+        wv[k] = w;
+        a.w_out[(int64_t)leaf * q2 + k] = w;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < 4 * q; k += NT) {
+        const int e = k / q, m = k - (k / q) * q;
+        const double *dr = (e == 0 || e == 2) ? d0 : dl;
+        double h = 0.0;
+        if (e < 2) {
+            for (int c = 1; c <= q; ++c) h = fma(dr[c], wv[m * q + c - 1], h);
+        } else {
+            for (int c = 1; c <= q; ++c) h = fma(dr[c], wv[(c - 1) * q + m], h);
+        }
+        a.h_out[(int64_t)leaf * 4 * q + k] = h;
+    }
+}
+
+// =======================================================================================
+// level kernels (upward: w3 = X d, h = [h1; h2] + U d; downward: u3 = S u12 + w3)
+// =======================================================================================
+struct LevelArgs {
+    PanelView pn;
+    int n1, n2, n3, n12, nbc;
+    const int *a1, *a3, *b2, *b3;
+    // upward
+    const double *hc;      // children fluxes [2*nodes][nbc]
+    const double *r3;      // interface jump data (interface-indexed) or null
+    const int *j3i;
+    double *w3, *h;
+    // downward
+    const double *ub;      // this level's boundary values [nodes][n12] (null at root)
+    const double *dir;     // root: Dirichlet data (boundary-indexed) or null
+    const int *root_map;
+    double *ubc;           // children boundary values [2*nodes][nbc]
+    double *part;          // split-K partials [nodes][ntile][kch][rp*vw]
+    int *cnt;              // split-K arrival counters [nodes][ntile], zero between launches
+    int root;
+};
+
+__device__ __forceinline__ void up_finalize(const LevelArgs &a, int node, int row, double y) {
+    if (row < a.n3) {
+        a.w3[(int64_t)node * a.n3 + row] = y;
+    } else if (row < a.n3 + a.n12 && !a.root) {
+        const int m = row - a.n3;
+        const double *ha = a.hc + (int64_t)(2 * node) * a.nbc;
+        const double *hb = a.hc + (int64_t)(2 * node + 1) * a.nbc;
+        const double base = (m < a.n1) ? ha[a.a1[m]] : hb[a.b2[m - a.n1]];
+        a.h[(int64_t)node * a.n12 + m] = base + y;
+    }
+}
+
+__device__ __forceinline__ void down_finalize(const LevelArgs &a, int node, int row, double y) {
+    if (row < a.n3) {
+        const double u3 = y + a.w3[(int64_t)node * a.n3 + row];
+        a.ubc[(int64_t)(2 * node) * a.nbc + a.a3[row]] = u3;
+        a.ubc[(int64_t)(2 * node + 1) * a.nbc + a.b3[row]] = u3;
+    }
+}
+
+__device__ __forceinline__ double down_input(const LevelArgs &a, int node, int k) {
+    if (a.root) return a.dir ? a.dir[a.root_map[k]] : 0.0;
+    return a.ub[(int64_t)node * a.n12 + k];
+}
+
+template <typename T, bool UP>
+__global__ __launch_bounds__(NT) void k_level(LevelArgs a) {
+    constexpr int VW = 16 / sizeof(T);
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT];
+    __shared__ int s_last;
+    const int kch = a.pn.kch, ntile = a.pn.ntile;
+    const int chunk = blockIdx.x % kch;
+    const int tile = (blockIdx.x / kch) % ntile;
+    const int node = blockIdx.x / (kch * ntile);
+    const int SG = a.pn.S * a.pn.G;
+    Carve cv{smem};
+    T *xs = cv.take<T>(SG);
+    T *part = cv.take<T>((size_t)a.pn.G * a.pn.rp * VW);
+    PanelStream<T, PF, UNR> ps;
+    ps.start(reinterpret_cast<const T *>(a.pn.data) + (int64_t)node * a.pn.node_elems +
+                 (int64_t)(tile * kch + chunk) * a.pn.tile_elems,
+             a.pn.rp, a.pn.G, a.pn.S);
+    const int cols = UP ? a.n3 : a.n12;
+    for (int k = threadIdx.x; k < SG; k += NT) {
+        const int kg = chunk * SG + k;
+        double x = 0.0;
+        if (kg < cols) {
+            if (UP) {
+                const double *ha = a.hc + (int64_t)(2 * node) * a.nbc;
+                const double *hb = a.hc + (int64_t)(2 * node + 1) * a.nbc;
+                x = hb[a.b3[kg]] - ha[a.a3[kg]];
+                if (a.r3) x += a.r3[a.j3i[(int64_t)node * a.n3 + kg]];
+            } else {
+                x = down_input(a, node, kg);
+            }
+        }
+        xs[k] = (T)x;
+    }
+    if (!UP && tile == 0 && chunk == 0) {
+        // the J1 / J2 parts of the children's boundary data are the parent's own
+        for (int m = threadIdx.x; m < a.n12; m += NT) {
+            const double v = down_input(a, node, m);
+            if (m < a.n1) a.ubc[(int64_t)(2 * node) * a.nbc + a.a1[m]] = v;
+            else a.ubc[(int64_t)(2 * node + 1) * a.nbc + a.b2[m - a.n1]] = v;
+        }
+    }
+    __syncthreads();
+    ps.finish(xs, part);
+    __syncthreads();
+    const int rows = a.pn.rp * VW;
+    if (kch == 1) {
+        // rows x G partial sums: each row is summed over the column groups by several
+        // threads, then the slices are added in a fixed order
+        const int G = a.pn.G;
+        for (int r0 = 0; r0 < rows; r0 += NT) {
+            const int nr = min(NT, rows - r0);
+            const int nsl = min(G, NT / nr);
+            const int t = threadIdx.x;
+            const int row = t % nr, sl = t / nr;
+            if (sl < nsl) {
+                T y = T(0);
+                for (int gg = sl; gg < G; gg += nsl) y += part[gg * rows + r0 + row];
+                red[sl * nr + row] = (double)y;
+            }
+            __syncthreads();
+            if (t < nr) {
+                double y = 0.0;
+                for (int s2 = 0; s2 < nsl; ++s2) y += red[s2 * nr + t];
+                if (UP) up_finalize(a, node, tile * rows + r0 + t, y);
+                else down_finalize(a, node, tile * rows + r0 + t, y);
+            }
+            __syncthreads();
+        }
+        return;
+    }
+    // split-K: publish this chunk's partial sums; the last workgroup of the (node, tile)
+    // to arrive adds all chunks in a fixed order and finalises (deterministic).
+    double *pp = a.part + ((int64_t)node * ntile + tile) * kch * rows;
+    for (int idx = threadIdx.x; idx < rows; idx += NT)
+        pp[(int64_t)chunk * rows + idx] = panel_sum<T>(part, a.pn.rp, a.pn.G, idx);
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = (atomicAdd(&a.cnt[node * ntile + tile], 1) == kch - 1);
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    for (int r0 = 0; r0 < rows; r0 += NT) {
+        const int nr = min(NT, rows - r0);
+        const int nsl = NT / nr;
+        const int t = threadIdx.x;
+        const int row = t % nr, sl = t / nr;
+        if (sl < nsl) {
+            double y = 0.0;
+            for (int c = sl; c < kch; c += nsl) y += pp[(int64_t)c * rows + r0 + row];
+            red[sl * nr + row] = y;
+        }
+        __syncthreads();
+        if (t < nr) {
+            double y = 0.0;
+            for (int s2 = 0; s2 < nsl; ++s2) y += red[s2 * nr + t];
+            if (UP) up_finalize(a, node, tile * rows + r0 + t, y);
+            else down_finalize(a, node, tile * rows + r0 + t, y);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.cnt[node * ntile + tile] = 0;
+}
+
+// single-leaf tree: the leaf boundary is the domain boundary
+__global__ void k_root_leaf_ub(const double *dir, const int *root_map, double *ub, int nb) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nb) ub[t] = dir ? dir[root_map[t]] : 0.0;
+}
+
+// =======================================================================================
+// leaf downward kernel: u_i = S_leaf u_b + w, then (mode) write u, or L u and F, or add a
+// refinement correction
+// =======================================================================================
+struct LeafDownArgs {
+    PanelView sl;
+    const int *leaf_ij;
+    LeafGeo geo;
+    const double *ub, *w;
+    const double *D, *D2, *coef;
+    int mode;
+    double *u;
+    double *Lu, *F;
+    const double *q_src;
+    double q_scale;
+    GPoly g;
+    unsigned long long *norms;  // mode 2: [0] max|delta|, [1] max|u| as ordered bit patterns
+};
+
+__device__ __forceinline__ void atomic_max_abs(unsigned long long *dst, double v) {
+    // non-negative doubles order like their bit patterns
+    atomicMax(dst, (unsigned long long)__double_as_longlong(fabs(v)));
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_leaf_down(LeafDownArgs a) {
+    constexpr int VW = 16 / sizeof(T);
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[2][NT / 64];
+    const int leaf = blockIdx.x;
+    const int q = a.geo.q, p = a.geo.p, q2 = q * q, nb = 4 * q;
+    const int SG = a.sl.S * a.sl.G;
+    Carve cv{smem};
+    T *xs = cv.take<T>(SG);
+    T *part = cv.take<T>((size_t)a.sl.G * a.sl.rp * VW);
+    double *tile = cv.take<double>(p * p);
+    double *D = cv.take<double>(a.mode == 1 ? p * p : 0);
+    double *D2 = cv.take<double>(a.mode == 1 ? p * p : 0);
+    PanelStream<T, PF, UNR> ps;
+    ps.start(reinterpret_cast<const T *>(a.sl.data) + (int64_t)leaf * a.sl.node_elems, a.sl.rp, a.sl.G,
+             a.sl.S);
+    const int li = a.leaf_ij[2 * leaf], lj = a.leaf_ij[2 * leaf + 1];
+    const int64_t base = ((int64_t)lj * a.geo.n1 + li) * q2;
+    const double *ubl = a.ub + (int64_t)leaf * nb;
+    for (int k = threadIdx.x; k < SG; k += NT) xs[k] = (T)(k < nb ? ubl[k] : 0.0);
+    for (int k = threadIdx.x; k < p * p; k += NT) tile[k] = 0.0;
+    if (a.mode == 1) {
+        load_dmat(a.D, D, p * p);
+        load_dmat(a.D2, D2, p * p);
+    }
+    __syncthreads();
+    ps.finish(xs, part);
+    __syncthreads();
+    for (int k = threadIdx.x; k < q2; k += NT) {
+        const double v = panel_sum<T>(part, a.sl.rp, a.sl.G, k) + a.w[(int64_t)leaf * q2 + k];
+        tile[(k / q + 1) * p + (k % q) + 1] = v;
+    }
+    for (int k = threadIdx.x; k < nb; k += NT) tile[edge_tile_pos(p, q, k / q, k % q)] = ubl[k];
+    __syncthreads();
+    if (a.mode == 0 || a.mode == 2) {
+        double dmax = 0.0, umax = 0.0;
+        for (int k = threadIdx.x; k < q2 + nb; k += NT) {
+            int64_t gi;
+            double v;
+            bool own = true;
+            if (k < q2) {
+                gi = base + k;
+                v = tile[(k / q + 1) * p + (k % q) + 1];
+            } else {
+                const int e = (k - q2) / q, m = (k - q2) % q;
+                // each edge node is written by exactly one leaf: left/bottom edges always,
+                // right/top edges only on the last column/row of leaves
+                own = (e == 0 || e == 2) || (e == 1 && li == a.geo.n1 - 1) ||
+                      (e == 3 && lj == a.geo.n2 - 1);
+                gi = edge_index(a.geo, li, lj, e, m);
+                v = ubl[k - q2];
+            }
+            if (!own) continue;
+            if (a.mode == 0) {
+                a.u[gi] = v;
+            } else {
+                const double nu = a.u[gi] + v;
+                a.u[gi] = nu;
+                dmax = fmax(dmax, fabs(v));
+                umax = fmax(umax, fabs(nu));
+            }
+        }
+        if (a.mode == 2) {
+            for (int off = 32; off > 0; off >>= 1) {
+                dmax = fmax(dmax, __shfl_xor(dmax, off));
+                umax = fmax(umax, __shfl_xor(umax, off));
+            }
+            if ((threadIdx.x & 63) == 0) {
+                red[0][threadIdx.x >> 6] = dmax;
+                red[1][threadIdx.x >> 6] = umax;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double d = 0, uu = 0;
+                for (int w = 0; w < NT / 64; ++w) {
+                    d = fmax(d, red[0][w]);
+                    uu = fmax(uu, red[1][w]);
+                }
+                atomic_max_abs(&a.norms[0], d);
+                atomic_max_abs(&a.norms[1], uu);
+            }
+        }
+        return;
+    }
+    // mode 1: L u_i and F_i = q + g(u_i) at the interior nodes
+    for (int k = threadIdx.x; k < q2; k += NT) {
+        const int64_t gi = base + k;
+        a.Lu[gi] = tile_L(tile, D, D2, p, q, a.coef, a.geo.n_int, gi, k);
+        const double u = tile[(k / q + 1) * p + (k % q) + 1];
+        const double qv = a.q_src ? a.q_scale * a.q_src[gi] : 0.0;
+        a.F[gi] = qv + gpoly(a.g, u);
+    }
+}
+
+// =======================================================================================
+// stage-1 evaluation (L u^n, F_1) and the refinement residual, from a canonical vector
+// =======================================================================================
+__device__ void tile_from_canonical(const LeafGeo &g, int li, int lj, const double *u,
+                                    double *tile) {
+    const int q = g.q, p = g.p, q2 = q * q;
+    const int64_t base = ((int64_t)lj * g.n1 + li) * q2;
+    for (int k = threadIdx.x; k < p * p; k += NT) tile[k] = 0.0;
+    __syncthreads();
+    for (int k = threadIdx.x; k < q2; k += NT) tile[(k / q + 1) * p + (k % q) + 1] = u[base + k];
+    for (int k = threadIdx.x; k < 4 * q; k += NT) {
+        const int e = k / q, m = k % q;
+        tile[edge_tile_pos(p, q, e, m)] = u[edge_index(g, li, lj, e, m)];
+    }
+    __syncthreads();
+}
+
+struct EvalArgs {
+    LeafGeo geo;
+    const double *u;
+    const double *D, *D2, *coef;
+    double *Lu, *F;
+    const double *q_src;
+    double q_scale;
+    GPoly g;
+    // residual mode
+    const double *rhs;
+    double gamma_dt;
+    double *r_int, *flux;
+};
+
+// one workgroup per leaf in canonical order (blockIdx.x = j*n1 + i)
+__global__ __launch_bounds__(NT) void k_eval(EvalArgs a) {
+    __shared__ double tile[PMAX * PMAX];
+    __shared__ double D[PMAX * PMAX], D2[PMAX * PMAX];
+    const int cl = blockIdx.x;
+    const int li = cl % a.geo.n1, lj = cl / a.geo.n1;
+    const int q = a.geo.q, p = a.geo.p, q2 = q * q;
+    load_dmat(a.D, D, p * p);
+    load_dmat(a.D2, D2, p * p);
+    tile_from_canonical(a.geo, li, lj, a.u, tile);
+    const int64_t base = (int64_t)cl * q2;
+    for (int k = threadIdx.x; k < q2; k += NT) {
+        const int64_t gi = base + k;
+        const double Lu = tile_L(tile, D, D2, p, q, a.coef, a.geo.n_int, gi, k);
+        const double u = tile[(k / q + 1) * p + (k % q) + 1];
+        if (a.rhs) {
+            // refinement residual of (I - gamma_dt L) u = rhs at interior nodes
+            a.r_int[gi] = a.rhs[gi] - (u - a.gamma_dt * Lu);
+        } else {
+            a.Lu[gi] = Lu;
+            const double qv = a.q_src ? a.q_scale * a.q_src[gi] : 0.0;
+            a.F[gi] = qv + gpoly(a.g, u);
+        }
+    }
+    if (a.rhs) {
+        // coordinate-direction fluxes on the four leaf edges, [leaf][e][m]
+        for (int k = threadIdx.x; k < 4 * q; k += NT) {
+            const int e = k / q, m = k % q;
+            const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * p);
+            double f = 0.0;
+            if (e < 2) {
+                for (int c = 0; c < p; ++c) f = fma(dr[c], tile[(m + 1) * p + c], f);
+            } else {
+                for (int c = 0; c < p; ++c) f = fma(dr[c], tile[c * p + m + 1], f);
+            }
+            a.flux[(int64_t)cl * 4 * q + k] = f;
+        }
+    }
+}
+
+// interface residual r3 = jump - (flux_alpha - flux_beta), interface-indexed
+__global__ void k_jump(LeafGeo g, const double *flux, const double *jump, double *r3, int64_t n_iface) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_iface) return;
+    const int q = g.q;
+    const int64_t nv = (int64_t)(g.n1 - 1) * g.n2 * q;
+    int ia, ja, ib, jb, ea, eb, m;
+    if (t < nv) {
+        const int k = (int)(t / ((int64_t)g.n2 * q)) + 1;
+        const int rem = (int)(t % ((int64_t)g.n2 * q));
+        const int j = rem / q;
+        m = rem % q;
+        ia = k - 1; ja = j; ea = 1;
+        ib = k; jb = j; eb = 0;
+    } else {
+        const int64_t u = t - nv;
+        const int k = (int)(u / ((int64_t)g.n1 * q)) + 1;
+        const int rem = (int)(u % ((int64_t)g.n1 * q));
+        const int i = rem / q;
+        m = rem % q;
+        ia = i; ja = k - 1; ea = 3;
+        ib = i; jb = k; eb = 2;
+    }
+    const double fa = flux[((int64_t)ja * g.n1 + ia) * 4 * q + ea * q + m];
+    const double fb = flux[((int64_t)jb * g.n1 + ib) * 4 * q + eb * q + m];
+    r3[t] = (jump ? jump[t] : 0.0) - (fa - fb);
+}
+
+// =======================================================================================
+// step completion (interior ARK update, boundary data, interface lines)
+// =======================================================================================
+struct UpdateArgs {
+    int64_t n_int;
+    const double *un;
+    double *unew;
+    const double *Lu, *F;
+    double cb[8], cbh[8];
+    int s;
+};
+
+// One workgroup per leaf (canonical order): interior u^{n+1} = u^n + sum_j (cb_j L u_j +
+// cbh_j F_j), and the interior part of the coordinate-direction flux on the four leaf edges,
+// [leaf][e][m] (e = left, right, bottom, top), for the interface-line solves.
+__global__ __launch_bounds__(NT) void k_update(UpdateArgs a, LeafGeo g, const double *D, double *fpart) {
+    __shared__ double ui[PMAX * PMAX];
+    __shared__ double d0[PMAX], dl[PMAX];
+    const int cl = blockIdx.x;
+    const int q = g.q, p = g.p, q2 = q * q;
+    const int64_t base = (int64_t)cl * q2;
+    for (int k = threadIdx.x; k < p; k += NT) {
+        d0[k] = D[k];
+        dl[k] = D[(p - 1) * p + k];
+    }
+    for (int k = threadIdx.x; k < q2; k += NT) {
+        double v = a.un[base + k];
+        for (int j = 0; j < a.s; ++j) {
+            v += a.cb[j] * a.Lu[j * a.n_int + base + k];
+            v += a.cbh[j] * a.F[j * a.n_int + base + k];
+        }
+        a.unew[base + k] = v;
+        ui[k] = v;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < 4 * q; k += NT) {
+        const int e = k / q, m = k % q;
+        const double *dr = (e == 0 || e == 2) ? d0 : dl;
+        double f = 0.0;
+        if (e < 2) {
+            for (int c = 1; c <= q; ++c) f = fma(dr[c], ui[m * q + c - 1], f);
+        } else {
+            for (int c = 1; c <= q; ++c) f = fma(dr[c], ui[(c - 1) * q + m], f);
+        }
+        fpart[(int64_t)cl * 4 * q + k] = f;
+    }
+}
+
+__global__ void k_scatter_boundary(const double *f, const int *bnd_glob, double *u, int64_t nb) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < nb) u[bnd_glob[k]] = f ? f[k] : 0.0;
+}
+
+// Flux continuity along one grid line of leaves: lower e_{k-1} + diag e_k + upper e_{k+1}
+// = sum_m D[0][m] u^beta(m) - sum_m D[p-1][m] u^alpha(m), k = 1..n-1, with e_0, e_n the
+// boundary values; solved by the Thomas algorithm (diagonally dominant: |diag| >> |lower|+|upper|).
+struct LineArgs {
+    LeafGeo geo;
+    double *u;
+    const double *fpart;      // interior flux parts [leaf][4][q] (canonical leaf order)
+    const double *D;          // p*p
+    const double *cp;         // Thomas factors: cp[k], k = 1..nmax-1
+    const double *inv_den;    // 1 / (diag - lower cp[k-1])
+};
+
+// One thread per grid line; the recursion carries d_{k-1} and e_{k+1} in registers, so the
+// only memory traffic is independent loads of the right-hand sides and of d_k.
+__global__ void k_interface_lines(LineArgs a) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const LeafGeo &g = a.geo;
+    const int q = g.q, p = g.p;
+    const int nvs = g.n2 * q;   // systems along horizontal rows (vertical-edge unknowns)
+    const int nhs = g.n1 * q;
+    if (t >= nvs + nhs) return;
+    const bool vert = t < nvs;
+    const int n = vert ? g.n1 : g.n2;
+    if (n < 2) return;
+    const int line = vert ? t / q : (t - nvs) / q;   // leaf row j (vert) or column i (horz)
+    const int m0 = (vert ? t : t - nvs) % q;          // local node index along the edge
+    auto unk = [&](int k) -> int64_t {
+        return vert ? g.n_int + ((int64_t)k * g.n2 + line) * q + m0
+                    : g.n_int + g.n_vert + ((int64_t)k * g.n1 + line) * q + m0;
+    };
+    // flux part of leaf number k along the line on side e
+    auto fp = [&](int k, int e) -> double {
+        const int64_t leaf = vert ? (int64_t)line * g.n1 + k : (int64_t)k * g.n1 + line;
+        return a.fpart[leaf * 4 * q + e * q + m0];
+    };
+    const int elo = vert ? 0 : 2, ehi = vert ? 1 : 3;   // left/right or bottom/top sides
+    const double lower = a.D[(p - 1) * p + 0];
+    const double upper = -a.D[0 * p + (p - 1)];
+    const double e0 = a.u[unk(0)], en = a.u[unk(n)];
+    double dprev = 0.0;
+    for (int k = 1; k < n; ++k) {
+        double r = fp(k, elo) - fp(k - 1, ehi);
+        if (k == 1) r -= lower * e0;
+        if (k == n - 1) r -= upper * en;
+        const double d = (r - (k > 1 ? lower * dprev : 0.0)) * a.inv_den[k];
+        a.u[unk(k)] = d;
+        dprev = d;
+    }
+    double enext = dprev;   // e_{n-1} = d_{n-1}
+    for (int k = n - 2; k >= 1; --k) {
+        enext = a.u[unk(k)] - a.cp[k] * enext;
+        a.u[unk(k)] = enext;
+    }
+}
+
+__global__ void k_zero(double *p, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = 0.0;
+}
+
+// ---- profiling ---------------------------------------------------------------------------
+const char *const kKernelFamilyNames[KF_COUNT] = {
+    "leaf_up_fp64", "leaf_up_fp32", "level_up_fp64", "level_up_fp32", "level_down_fp64",
+    "level_down_fp32", "leaf_down_fp64", "leaf_down_fp32", "eval", "residual", "update"};
+
+hipEvent_t Profiler::get() {
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+Profiler::~Profiler() {
+    for (auto &r : recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+}
+
+ProfScope::ProfScope(Profiler *p_, int fam_, hipStream_t st_) : p(p_), fam(fam_), st(st_) {
+    if (p && p->on) {
+        a = p->get();
+        if (a) (void)hipEventRecord(a, st);
+    }
+}
+
+ProfScope::~ProfScope() {
+    if (p && p->on && a) {
+        hipEvent_t b = p->get();
+        if (b) {
+            (void)hipEventRecord(b, st);
+            p->recs.push_back(Profiler::Rec{fam, a, b});
+        }
+    }
+}
+
+
+// =======================================================================================
+// launchers
+// =======================================================================================
+int launch_leaf_up(const hps_op *op, bool fp32, const double *body, const double *un,
+                   const double *Lu, const double *F, const StageCoefs *sc, double *rhs_copy,
+                   hipStream_t st) {
+    ProfScope ps_(&op->prof, fp32 ? KF_LEAF_UP32 : KF_LEAF_UP64, st);
+    const Panel &pn = fp32 ? op->ainv32 : op->ainv64;
+    LeafUpArgs a{};
+    a.ainv = view(pn);
+    a.leaf_ij = op->leaf_ij;
+    a.geo = geo_of(op);
+    a.body = body;
+    a.un = un;
+    a.Lu = Lu;
+    a.F = F;
+    if (sc) a.sc = *sc;
+    a.rhs_copy = rhs_copy;
+    a.D = op->D;
+    a.w_out = op->w_leaf;
+    a.h_out = op->h_leaf;
+    const size_t es = fp32 ? 4 : 8;
+    const size_t lds = carve_bytes({pn.S * pn.G * es, (size_t)pn.G * pn.rp * pn.vw * es,
+                                    (size_t)op->q2 * 8, (size_t)op->p * 8, (size_t)op->p * 8});
+    if (fp32) hipLaunchKernelGGL(k_leaf_up<float>, dim3(op->nleaves), dim3(NT), lds, st, a);
+    else hipLaunchKernelGGL(k_leaf_up<double>, dim3(op->nleaves), dim3(NT), lds, st, a);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+static LevelArgs level_args(const hps_op *op, int l, bool fp32, bool up) {
+    const Level &L = op->lv[l];
+    LevelArgs a{};
+    a.pn = view(up ? (fp32 ? L.xu32 : L.xu64) : (fp32 ? L.s32 : L.s64));
+    a.n1 = L.n1; a.n2 = L.n2; a.n3 = L.n3; a.n12 = L.n12; a.nbc = L.nbc;
+    a.a1 = L.a1; a.a3 = L.a3; a.b2 = L.b2; a.b3 = L.b3;
+    a.j3i = L.j3i;
+    const bool child_leaf = (l == op->L - 1);
+    a.hc = child_leaf ? op->h_leaf : op->lv[l + 1].h;
+    a.w3 = L.w3;
+    a.h = L.h;
+    a.ub = L.ub;
+    a.ubc = child_leaf ? op->ub_leaf : op->lv[l + 1].ub;
+    a.root_map = op->root_map;
+    a.root = (l == 0);
+    a.part = L.part;
+    a.cnt = up ? (fp32 ? L.cnt_up32 : L.cnt_up64) : (fp32 ? L.cnt_dn32 : L.cnt_dn64);
+    return a;
+}
+
+static size_t level_lds(const Panel &pn) {
+    const size_t es = pn.vw == 2 ? 8 : 4;
+    return carve_bytes({(size_t)pn.S * pn.G * es, (size_t)pn.G * pn.rp * pn.vw * es});
+}
+
+int launch_levels_up(const hps_op *op, bool fp32, const double *jump, hipStream_t st) {
+    ProfScope ps_(&op->prof, fp32 ? KF_LEVEL_UP32 : KF_LEVEL_UP64, st);
+    for (int l = op->L - 1; l >= 0; --l) {
+        LevelArgs a = level_args(op, l, fp32, true);
+        a.r3 = jump;
+        const Panel &pn = fp32 ? op->lv[l].xu32 : op->lv[l].xu64;
+        const unsigned nb = (unsigned)(op->lv[l].nodes * a.pn.ntile * a.pn.kch);
+        if (fp32) hipLaunchKernelGGL((k_level<float, true>), dim3(nb), dim3(NT), level_lds(pn), st, a);
+        else hipLaunchKernelGGL((k_level<double, true>), dim3(nb), dim3(NT), level_lds(pn), st, a);
+        HPS_LAUNCHED();
+    }
+    return HPS_OK;
+}
+
+int launch_levels_down(const hps_op *op, bool fp32, const double *dirichlet, hipStream_t st) {
+    ProfScope ps_(&op->prof, fp32 ? KF_LEVEL_DOWN32 : KF_LEVEL_DOWN64, st);
+    if (op->L == 0) {
+        hipLaunchKernelGGL(k_root_leaf_ub, dim3(1), dim3(NT), 0, st, dirichlet, (const int *)op->root_map,
+                           op->ub_leaf, 4 * op->q);
+        HPS_LAUNCHED();
+        return HPS_OK;
+    }
+    for (int l = 0; l < op->L; ++l) {
+        LevelArgs a = level_args(op, l, fp32, false);
+        a.dir = dirichlet;
+        const Panel &pn = fp32 ? op->lv[l].s32 : op->lv[l].s64;
+        const unsigned nb = (unsigned)(op->lv[l].nodes * a.pn.ntile * a.pn.kch);
+        if (fp32) hipLaunchKernelGGL((k_level<float, false>), dim3(nb), dim3(NT), level_lds(pn), st, a);
+        else hipLaunchKernelGGL((k_level<double, false>), dim3(nb), dim3(NT), level_lds(pn), st, a);
+        HPS_LAUNCHED();
+    }
+    return HPS_OK;
+}
+
+int launch_leaf_down(const hps_op *op, bool fp32, int mode, double *u, double *Lu, double *F,
+                     const double *q_src, double q_scale, GPoly g, hipStream_t st) {
+    ProfScope ps_(&op->prof, fp32 ? KF_LEAF_DOWN32 : KF_LEAF_DOWN64, st);
+    const Panel &pn = fp32 ? op->sleaf32 : op->sleaf64;
+    LeafDownArgs a{};
+    a.sl = view(pn);
+    a.leaf_ij = op->leaf_ij;
+    a.geo = geo_of(op);
+    a.ub = op->ub_leaf;
+    a.w = op->w_leaf;
+    a.D = op->D;
+    a.D2 = op->D2;
+    a.coef = op->coef;
+    a.mode = mode;
+    a.u = u;
+    a.Lu = Lu;
+    a.F = F;
+    a.q_src = q_src;
+    a.q_scale = q_scale;
+    a.g = g;
+    a.norms = reinterpret_cast<unsigned long long *>(op->ir_norms);
+    const size_t es = fp32 ? 4 : 8;
+    const size_t pp = (size_t)op->p * op->p * 8;
+    const size_t lds = carve_bytes({pn.S * pn.G * es, (size_t)pn.G * pn.rp * pn.vw * es, pp,
+                                    mode == 1 ? pp : 0, mode == 1 ? pp : 0});
+    if (fp32) hipLaunchKernelGGL(k_leaf_down<float>, dim3(op->nleaves), dim3(NT), lds, st, a);
+    else hipLaunchKernelGGL(k_leaf_down<double>, dim3(op->nleaves), dim3(NT), lds, st, a);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+int launch_eval(const hps_op *op, const double *u, double *Lu, double *F, const double *q_src,
+                double q_scale, GPoly g, hipStream_t st) {
+    ProfScope ps_(&op->prof, KF_EVAL, st);
+    EvalArgs a{};
+    a.geo = geo_of(op);
+    a.u = u;
+    a.D = op->D;
+    a.D2 = op->D2;
+    a.coef = op->coef;
+    a.Lu = Lu;
+    a.F = F;
+    a.q_src = q_src;
+    a.q_scale = q_scale;
+    a.g = g;
+    hipLaunchKernelGGL(k_eval, dim3(op->nleaves), dim3(NT), 0, st, a);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+int launch_residual(const hps_op *op, const double *u, const double *rhs, const double *jump,
+                    double *r_int, double *r3, hipStream_t st) {
+    ProfScope ps_(&op->prof, KF_RESIDUAL, st);
+    EvalArgs a{};
+    a.geo = geo_of(op);
+    a.u = u;
+    a.D = op->D;
+    a.D2 = op->D2;
+    a.coef = op->coef;
+    a.rhs = rhs;
+    a.gamma_dt = op->gamma_dt;
+    a.r_int = r_int;
+    a.flux = op->ir_flux;
+    hipLaunchKernelGGL(k_eval, dim3(op->nleaves), dim3(NT), 0, st, a);
+    HPS_LAUNCHED();
+    if (op->n_iface > 0) {
+        hipLaunchKernelGGL(k_jump, dim3(nblk(op->n_iface)), dim3(NT), 0, st, geo_of(op),
+                           (const double *)op->ir_flux, jump, r3, op->n_iface);
+        HPS_LAUNCHED();
+    }
+    return HPS_OK;
+}
+
+int launch_update(const hps_op *op, const double *un, double *unew, const double *Lu,
+                  const double *F, const double *cb, const double *cbh, int s,
+                  const double *f_end, hipStream_t st) {
+    ProfScope ps_(&op->prof, KF_UPDATE, st);
+    UpdateArgs a{};
+    a.n_int = op->n_int;
+    a.un = un;
+    a.unew = unew;
+    a.Lu = Lu;
+    a.F = F;
+    a.s = s;
+    for (int j = 0; j < s; ++j) {
+        a.cb[j] = cb[j];
+        a.cbh[j] = cbh[j];
+    }
+    hipLaunchKernelGGL(k_update, dim3(op->nleaves), dim3(NT), 0, st, a, geo_of(op), (const double *)op->D,
+                       op->ir_flux);
+    HPS_LAUNCHED();
+    int rc = launch_scatter_boundary(op, f_end, unew, st);
+    if (rc) return rc;
+    LineArgs la{};
+    la.geo = geo_of(op);
+    la.u = unew;
+    la.fpart = op->ir_flux;
+    la.D = op->D;
+    la.cp = op->tri_cp;
+    la.inv_den = op->tri_cp + op->tri_stride;
+    const int nsys = op->grid.n2 * op->q + op->grid.n1 * op->q;
+    hipLaunchKernelGGL(k_interface_lines, dim3(nblk(nsys, 64)), dim3(64), 0, st, la);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+int launch_scatter_boundary(const hps_op *op, const double *f, double *u, hipStream_t st) {
+    hipLaunchKernelGGL(k_scatter_boundary, dim3(nblk(op->n_bdry)), dim3(NT), 0, st, f,
+                       (const int *)op->bnd_glob, u, op->n_bdry);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+int launch_zero(double *p, int64_t n, hipStream_t st) {
+    if (n <= 0) return HPS_OK;
+    hipLaunchKernelGGL(k_zero, dim3(nblk(n)), dim3(NT), 0, st, p, n);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+}  // namespace hps
