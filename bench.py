@@ -48,15 +48,18 @@ def parse():
     return ap.parse_args()
 
 
-def leaf_up_algorithmic_bytes(n_leaves, q, stages, elem_bytes):
-    """Algorithmic HBM bytes of the leaf particular-solve kernel per launch, averaged over
-    the implicit stages of one step: the q^2 x q^2 operator of every leaf (elem_bytes
-    each), the stage vectors the fused right-hand side reads (u^n and L u_j, F_j for the
-    previous stages, FP64), and the w (q^2) and h (4q) outputs (FP64)."""
+def leaf_down_up_algorithmic_bytes(n_leaves, q, stages, elem_bytes):
+    """Algorithmic HBM bytes per launch of the fused per-leaf kernel that closes stage i
+    and opens stage i+1 (i = 2..s-1), averaged over those launches:
+      operators  S_leaf (q^2 x 4q) and A_ii^{-1} (q^2 x q^2), elem_bytes each;
+      reads      u_b (4q), w (q^2), the 5 coefficients of L (5 q^2), u^n (q^2) and the
+                 2 (i-1) stage vectors L u_j, F_j, j < i, read from HBM (q^2 each);
+      writes     L u_i, F_i (2 q^2), w (q^2), h (4q);  all field data FP64."""
     q2 = q * q
-    nprev = [i for i in range(1, stages)]          # stage i reads 2 i previous vectors
-    vec_reads = sum(1 + 2 * k for k in nprev) / len(nprev)
-    per_leaf = q2 * q2 * elem_bytes + vec_reads * q2 * 8 + q2 * 8 + 4 * q * 8
+    launches = list(range(2, stages))            # closes stage i, opens i + 1
+    field_reads = [4 * q + q2 + 5 * q2 + q2 + 2 * (i - 1) * q2 for i in launches]
+    field = sum(field_reads) / len(field_reads) + 2 * q2 + q2 + 4 * q
+    per_leaf = (q2 * 4 * q + q2 * q2) * elem_bytes + field * 8
     return n_leaves * per_leaf
 
 
@@ -121,15 +124,15 @@ def main():
     torch.cuda.synchronize()
     prof = hps.hps_profile_read(op)
     hps.hps_profile_enable(op, False)
-    launches, tot_ms = prof["leaf_up_fp64"]
-    leaf_up_us = 1e3 * tot_ms / launches
-    alg = leaf_up_algorithmic_bytes(n * n, q, tab["s"], 8)
-    achieved = alg / (leaf_up_us * 1e-6) / 1e9
-    breakdown = {k: round(1e3 * v[1] / (prof_steps * (stages if k.startswith(("leaf", "level")) else 1)), 2)
+    launches, tot_ms = prof["leaf_down_up_fp64"]
+    leaf_us = 1e3 * tot_ms / launches
+    alg = leaf_down_up_algorithmic_bytes(n * n, q, tab["s"], 8)
+    achieved = alg / (leaf_us * 1e-6) / 1e9
+    breakdown = {k: {"launches_per_step": v[0] // prof_steps, "us_per_launch": round(1e3 * v[1] / v[0], 2)}
                  for k, v in prof.items()}
-    log(f"leaf_up_fp64: {leaf_up_us:.1f} us/launch, {achieved:.0f} GB/s; per-stage breakdown (us): {breakdown}")
+    log(f"leaf_down_up_fp64: {leaf_us:.1f} us/launch, {achieved:.0f} GB/s; kernels: {breakdown}")
     traffic = None
-    tr_path = os.path.join(ROOT, "profiles", "leaf_up_fp64_traffic.json")
+    tr_path = os.path.join(ROOT, "profiles", "leaf_down_up_fp64_traffic.json")
     if os.path.exists(tr_path):
         try:
             tr = json.load(open(tr_path))
@@ -219,11 +222,12 @@ def main():
         "build_s": round(build_s, 4),
         "operator_bytes_per_stage_solve": int(stage_solve_bytes),
         "latency_ms": {"hps_solve_p50": round(p50, 4), "hps_solve_p99": round(p99, 4)},
-        "kernel_us_per_stage": breakdown,
-        "roofline": {"bound": "hbm", "kernel": "k_leaf_up<double>", "achieved": round(achieved, 1),
+        "kernels": breakdown,
+        "roofline": {"bound": "hbm", "kernel": "k_leaf<double> (down stage i + up stage i+1)",
+                     "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes_per_launch": int(alg),
-                     "avg_launch_us": round(leaf_up_us, 2)},
+                     "avg_launch_us": round(leaf_us, 2)},
         "fp32_ir": fp32,
         "cpu_baseline": cpu,
     }

@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhps.so")
-SOURCES = ["hps_solve_kernels.hip", "hps_build_kernels.hip", "hps_api.hip"]
+SOURCES = ["hps_solve_kernels.hip", "hps_leaf_kernels.hip", "hps_build_kernels.hip", "hps_api.hip",
+           "hps_drivers.hip"]
 
 
 def hipcc():

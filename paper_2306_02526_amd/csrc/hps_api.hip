@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -28,19 +29,6 @@ void hps_set_error(const char *fmt, ...) {
 
 extern "C" const char *hps_last_error(void) { return g_err; }
 
-#define CHECK_ARG(cond, ...)          \
-    do {                              \
-        if (!(cond)) {                \
-            hps_set_error(__VA_ARGS__); \
-            return HPS_EINVAL;        \
-        }                             \
-    } while (0)
-
-#define TRY(x)                 \
-    do {                       \
-        int rc_ = (x);         \
-        if (rc_) return rc_;   \
-    } while (0)
 
 // ---------------------------------------------------------------------------------------
 // grid
@@ -240,7 +228,7 @@ struct TempBuf {   // device scratch freed at scope exit
     }
 };
 
-static int check_device_ptr(const void *p, const char *name) {
+int check_device_ptr(const void *p, const char *name) {
     if (!p) return HPS_OK;
     hipPointerAttribute_t attr;
     hipError_t e = hipPointerGetAttributes(&attr, p);
@@ -565,15 +553,16 @@ static int build_impl(hps_op *op, const hps_coeffs *co, hipStream_t st) {
             TRY(launch_dgemm(n12, n12, n3, U, n12, s3x, B, n3, s3x, Tn, n12, sxx, nodes, 1.0, 1.0, st));
         }
         const int rows = root ? n3 : n3 + n12;
-        Lv.xu64 = plan_panel(rows, n3, 2, nodes, 64, 1024);
-        Lv.s64 = plan_panel(n3, n12, 2, nodes, 64, 1024);
+        const int rpm = 64, mwg = 1024;
+        Lv.xu64 = plan_panel(rows, n3, 2, nodes, rpm, mwg);
+        Lv.s64 = plan_panel(n3, n12, 2, nodes, rpm, mwg);
         TRY(alloc_panel(op, Lv.xu64));
         TRY(alloc_panel(op, Lv.s64));
         TRY(launch_pack(Lv.xu64, X, n3, s33, n3, U, n12, s3x, st));
         TRY(launch_pack(Lv.s64, Sx, n3, s3x, n3, nullptr, 0, 0, st));
         if (ir) {
-            Lv.xu32 = plan_panel(rows, n3, 4, nodes, 64, 1024);
-            Lv.s32 = plan_panel(n3, n12, 4, nodes, 64, 1024);
+            Lv.xu32 = plan_panel(rows, n3, 4, nodes, rpm, mwg);
+            Lv.s32 = plan_panel(n3, n12, 4, nodes, rpm, mwg);
             TRY(alloc_panel(op, Lv.xu32));
             TRY(alloc_panel(op, Lv.s32));
             TRY(launch_pack(Lv.xu32, X, n3, s33, n3, U, n12, s3x, st));
@@ -677,98 +666,6 @@ extern "C" int64_t hps_op_bytes(const hps_op *op, int64_t *operator_bytes) {
 }
 
 // ---------------------------------------------------------------------------------------
-// solve
-// ---------------------------------------------------------------------------------------
-static int sweep(hps_op *op, bool fp32, const double *body, const double *un, const double *Lu,
-                 const double *F, const StageCoefs *sc, double *rhs_copy, const double *jump,
-                 const double *dir, hipStream_t st) {
-    TRY(launch_leaf_up(op, fp32, body, un, Lu, F, sc, rhs_copy, st));
-    TRY(launch_levels_up(op, fp32, jump, st));
-    TRY(launch_levels_down(op, fp32, dir, st));
-    return HPS_OK;
-}
-
-static double ordered_bits_to_double(unsigned long long v) {
-    double d;
-    std::memcpy(&d, &v, sizeof(d));
-    return d;
-}
-
-// FP32 operators inside FP64 iterative refinement: u = HPS32(rhs); repeat
-// { r = FP64 residual of the global system; u += HPS32(r) } until max|delta| <= tol max|u|.
-static int ir_refine(hps_op *op, const double *rhs, const double *dir, const double *jump, double *u,
-                     hipStream_t st, hps_info *info) {
-    const double tol = 1e-11;
-    const int maxit = 10;
-    GPoly none{0, 0, 0, 0, 0};
-    int it = 0;
-    double rel = 0.0;
-    for (it = 1; it <= maxit; ++it) {
-        TRY(launch_residual(op, u, rhs, jump, op->ir_r, op->ir_r3, st));
-        HPS_HIP(hipMemsetAsync(op->ir_norms, 0, 2 * sizeof(double), st));
-        TRY(sweep(op, true, op->ir_r, nullptr, nullptr, nullptr, nullptr, nullptr,
-                  op->n_iface ? op->ir_r3 : nullptr, nullptr, st));
-        TRY(launch_leaf_down(op, true, 2, u, nullptr, nullptr, nullptr, 0.0, none, st));
-        unsigned long long nb[2];
-        HPS_HIP(hipMemcpyAsync(nb, op->ir_norms, sizeof(nb), hipMemcpyDeviceToHost, st));
-        HPS_HIP(hipStreamSynchronize(st));
-        const double dmax = ordered_bits_to_double(nb[0]), umax = ordered_bits_to_double(nb[1]);
-        rel = umax > 0 ? dmax / umax : dmax;
-        if (dmax <= tol * umax) break;
-    }
-    if (info) {
-        info->ir_iterations = std::min(it, maxit);
-        info->last_correction = rel;
-    }
-    if (it > maxit) {
-        hps_set_error("iterative refinement did not converge: last correction %.3e", rel);
-        return HPS_ENOTCONVERGED;
-    }
-    return HPS_OK;
-}
-
-extern "C" int hps_solve(hps_op *op, int nrhs, const double *body, const double *dirichlet,
-                         const double *jump, double *u, void *stream, hps_info *info) {
-    CHECK_ARG(op != nullptr, "op is NULL");
-    CHECK_ARG(nrhs >= 0, "nrhs must be >= 0");
-    if (nrhs == 0) return HPS_OK;
-    CHECK_ARG(body != nullptr && u != nullptr, "body and u are required");
-    TRY(check_device_ptr(body, "body"));
-    TRY(check_device_ptr(dirichlet, "dirichlet"));
-    TRY(check_device_ptr(jump, "jump"));
-    TRY(check_device_ptr(u, "u"));
-    hipStream_t st = (hipStream_t)stream;
-    const bool ir = (op->flags & HPS_FP32_IR) != 0;
-    GPoly none{0, 0, 0, 0, 0};
-    if (info) {
-        info->ir_iterations = 0;
-        info->last_correction = 0.0;
-    }
-    int worst_it = 0;
-    double worst_rel = 0.0;
-    for (int r = 0; r < nrhs; ++r) {
-        const double *b = body + (int64_t)r * op->n_int;
-        const double *d = dirichlet ? dirichlet + (int64_t)r * op->n_bdry : nullptr;
-        const double *j = (jump && op->n_iface) ? jump + (int64_t)r * op->n_iface : nullptr;
-        double *ur = u + (int64_t)r * op->N;
-        TRY(sweep(op, ir, b, nullptr, nullptr, nullptr, nullptr, nullptr, j, d, st));
-        TRY(launch_leaf_down(op, ir, 0, ur, nullptr, nullptr, nullptr, 0.0, none, st));
-        if (ir) {
-            hps_info inf{};
-            TRY(ir_refine(op, b, d, j, ur, st, &inf));
-            worst_it = std::max(worst_it, inf.ir_iterations);
-            worst_rel = std::max(worst_rel, inf.last_correction);
-        }
-    }
-    if (info) {
-        HPS_HIP(hipStreamSynchronize(st));
-        info->ir_iterations = worst_it;
-        info->last_correction = worst_rel;
-    }
-    return HPS_OK;
-}
-
-// ---------------------------------------------------------------------------------------
 // time stepping
 // ---------------------------------------------------------------------------------------
 extern "C" int ark_create(hps_op *op, const ark_tableau *tab, double dt, const ark_g *g, ark_ctx **out) {
@@ -818,70 +715,15 @@ extern "C" int ark_create(hps_op *op, const ark_tableau *tab, double dt, const a
 
 extern "C" void ark_free(ark_ctx *c) {
     if (!c) return;
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (double *p : {c->Lu, c->F, c->rhs, c->stage_u})
         if (p) (void)hipFree(p);
     delete c;
 }
 
 extern "C" int ark_stage_solves_per_step(const ark_ctx *c) { return c ? c->s - 1 : HPS_EINVAL; }
-
-extern "C" int ark_step(ark_ctx *c, double t, double *u, const double *q_stages, const double *q_space,
-                        const double *q_time, const double *f_stages, void *stream) {
-    CHECK_ARG(c != nullptr && u != nullptr, "ctx and u are required");
-    CHECK_ARG(std::isfinite(t), "t must be finite");
-    CHECK_ARG(!(q_stages && q_space), "give q_stages or q_space/q_time, not both");
-    CHECK_ARG(!q_space || q_time, "q_space needs q_time (host array of s values)");
-    TRY(check_device_ptr(u, "u"));
-    TRY(check_device_ptr(q_stages, "q_stages"));
-    TRY(check_device_ptr(q_space, "q_space"));
-    TRY(check_device_ptr(f_stages, "f_stages"));
-    hps_op *op = c->op;
-    hipStream_t st = (hipStream_t)stream;
-    const int s = c->s;
-    const int64_t n = op->n_int;
-    const bool ir = (op->flags & HPS_FP32_IR) != 0;
-    GPoly gp{c->g.kind, c->g.g0, c->g.g1, c->g.g2, c->g.g3};
-    auto qsrc = [&](int i, double &scale) -> const double * {
-        scale = 1.0;
-        if (q_stages) return q_stages + (int64_t)i * n;
-        if (q_space) {
-            scale = q_time[i];
-            return q_space;
-        }
-        return nullptr;
-    };
-    double qs;
-    const double *qp = qsrc(0, qs);
-    TRY(launch_eval(op, u, c->Lu, c->F, qp, qs, gp, st));
-    for (int i = 1; i < s; ++i) {
-        StageCoefs sc{};
-        sc.nprev = i;
-        for (int j = 0; j < i; ++j) {
-            sc.ca[j] = c->dt * c->A[i * s + j];
-            sc.cf[j] = c->dt * c->Ah[i * s + j];
-        }
-        const double *fi = f_stages ? f_stages + (int64_t)i * op->n_bdry : nullptr;
-        qp = qsrc(i, qs);
-        double *Lui = c->Lu + (int64_t)i * n, *Fi = c->F + (int64_t)i * n;
-        if (!ir) {
-            TRY(sweep(op, false, nullptr, u, c->Lu, c->F, &sc, nullptr, nullptr, fi, st));
-            TRY(launch_leaf_down(op, false, 1, nullptr, Lui, Fi, qp, qs, gp, st));
-        } else {
-            TRY(sweep(op, true, nullptr, u, c->Lu, c->F, &sc, c->rhs, nullptr, fi, st));
-            TRY(launch_leaf_down(op, true, 0, c->stage_u, nullptr, nullptr, nullptr, 0.0, gp, st));
-            TRY(ir_refine(op, c->rhs, fi, nullptr, c->stage_u, st, nullptr));
-            TRY(launch_eval(op, c->stage_u, Lui, Fi, qp, qs, gp, st));
-        }
-    }
-    std::vector<double> cb(s), cbh(s);
-    for (int j = 0; j < s; ++j) {
-        cb[j] = c->dt * c->b[j];
-        cbh[j] = c->dt * c->bh[j];
-    }
-    const double *fend = f_stages ? f_stages + (int64_t)s * op->n_bdry : nullptr;
-    TRY(launch_update(op, u, u, c->Lu, c->F, cb.data(), cbh.data(), s, fend, st));
-    return HPS_OK;
-}
 
 // ---------------------------------------------------------------------------------------
 // kernel timing

@@ -59,8 +59,9 @@ struct Level {
 
 // Optional per-kernel timing with HIP events recorded on the launch stream.
 enum KernelFamily {
-    KF_LEAF_UP64, KF_LEAF_UP32, KF_LEVEL_UP64, KF_LEVEL_UP32, KF_LEVEL_DOWN64, KF_LEVEL_DOWN32,
-    KF_LEAF_DOWN64, KF_LEAF_DOWN32, KF_EVAL, KF_RESIDUAL, KF_UPDATE, KF_COUNT
+    KF_LEAF_UP64, KF_LEAF_UP32, KF_LEAF_DOWN64, KF_LEAF_DOWN32, KF_LEAF_EVAL_UP64, KF_LEAF_EVAL_UP32,
+    KF_LEAF_DOWN_UP64, KF_LEAF_DOWN_UP32, KF_LEAF_DOWN_UPDATE64, KF_LEAF_EVAL_UPDATE64,
+    KF_LEVEL_UP64, KF_LEVEL_UP32, KF_LEVEL_DOWN64, KF_LEVEL_DOWN32, KF_RESIDUAL, KF_LINES, KF_COUNT
 };
 extern const char *const kKernelFamilyNames[KF_COUNT];
 
@@ -120,6 +121,11 @@ struct ark_ctx {
     double *Lu = nullptr, *F = nullptr;   // device [s][n_int] each
     double *rhs = nullptr;                // device [n_int] (FP32_IR stage right-hand side)
     double *stage_u = nullptr;            // device [N] (FP32_IR stage solution)
+    // the FP64 step is replayed from a captured HIP graph while its arguments repeat
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipStream_t cap_stream = nullptr;     // private stream used only for the capture
+    std::vector<uintptr_t> gkey;          // pointers, stream and source scales of the capture
 };
 
 // ---------------------------------------------------------------------------------------
@@ -138,8 +144,25 @@ void hps_set_error(const char *fmt, ...);
 
 #define HPS_LAUNCHED()  HPS_HIP(hipGetLastError())
 
+#define CHECK_ARG(cond, ...)            \
+    do {                                \
+        if (!(cond)) {                  \
+            hps_set_error(__VA_ARGS__); \
+            return HPS_EINVAL;          \
+        }                               \
+    } while (0)
+
+#define TRY(x)               \
+    do {                     \
+        int rc_ = (x);       \
+        if (rc_) return rc_; \
+    } while (0)
+
+// HPS_EINVAL unless p is NULL or a device (or managed) allocation
+int check_device_ptr(const void *p, const char *name);
+
 // ---------------------------------------------------------------------------------------
-// launchers (hps_kernels.hip)
+// launchers (hps_solve_kernels.hip, hps_leaf_kernels.hip, hps_build_kernels.hip)
 // ---------------------------------------------------------------------------------------
 namespace hps {
 
@@ -155,20 +178,33 @@ struct GPoly {
 };
 
 // solve sweeps ---------------------------------------------------------------------------
-int launch_leaf_up(const hps_op *op, bool fp32, const double *body, const double *un,
-                   const double *Lu, const double *F, const StageCoefs *sc, double *rhs_copy,
-                   hipStream_t st);
+// One per-leaf kernel = a down phase followed by an up phase (hps_leaf_kernels.hip).
+enum { LD_NONE = 0, LD_WRITE_U = 1, LD_STAGE = 2, LD_IR_ADD = 3, LD_EVAL = 4 };
+enum { LU_NONE = 0, LU_BODY = 1, LU_STAGE = 2, LU_UPDATE = 3 };
+struct LeafPhase {
+    int down = LD_NONE, up = LU_NONE;
+    // down
+    const double *u_eval = nullptr;            // LD_EVAL: canonical vector to evaluate
+    double *u_out = nullptr;                   // LD_WRITE_U / LD_IR_ADD
+    double *Lu_out = nullptr, *F_out = nullptr;  // LD_STAGE / LD_EVAL
+    const double *q_src = nullptr;
+    double q_scale = 0.0;
+    GPoly g{0, 0, 0, 0, 0};
+    // up
+    const double *body = nullptr;              // LU_BODY
+    const double *un = nullptr;                // LU_STAGE / LU_UPDATE
+    const double *Lu_in = nullptr, *F_in = nullptr;
+    int nprev = 0;                             // stages before the assembled one (newest in LDS)
+    double ca[8] = {0}, cf[8] = {0};
+    double *rhs_copy = nullptr;
+    double *unew = nullptr;                    // LU_UPDATE
+};
+int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st);
 int launch_levels_up(const hps_op *op, bool fp32, const double *jump, hipStream_t st);
 int launch_levels_down(const hps_op *op, bool fp32, const double *dirichlet, hipStream_t st);
-// mode 0: write u (canonical, interior + edges); mode 1: write L u and F at interior nodes;
-// mode 2: add the solution to u (FP32_IR correction) and record max|delta|, max|u|.
-int launch_leaf_down(const hps_op *op, bool fp32, int mode, double *u, double *Lu, double *F,
-                     const double *q_src, double q_scale, GPoly g, hipStream_t st);
-int launch_eval(const hps_op *op, const double *u, double *Lu, double *F, const double *q_src,
-                double q_scale, GPoly g, hipStream_t st);
-int launch_update(const hps_op *op, const double *un, double *unew, const double *Lu,
-                  const double *F, const double *cb, const double *cbh, int s,
-                  const double *f_end, hipStream_t st);
+// step completion after the interior update: boundary data f(t + dt), then the interface
+// values from flux continuity along every grid line (reads the leaf edge-flux parts)
+int launch_interface_lines(const hps_op *op, double *u, const double *f_end, hipStream_t st);
 int launch_residual(const hps_op *op, const double *u, const double *rhs, const double *jump,
                     double *r_int, double *r3, hipStream_t st);
 int launch_scatter_boundary(const hps_op *op, const double *f, double *u, hipStream_t st);

@@ -1,0 +1,354 @@
+// Per-leaf kernels of the stage solve, fused across stage boundaries.
+//
+// One workgroup per leaf runs a "down" phase and then an "up" phase:
+//   down: u_i = S_leaf u_b + w (Algorithm 1 with the particular part, Sec. 2.1) followed by
+//         writing u, adding a refinement correction, or evaluating L u_i and
+//         F_i = q + g(u_i) (eq. 9); or, instead of the solve, evaluating L u and F of a
+//         given canonical vector (stage 1 uses u^n);
+//   up:   the next stage right-hand side rhs = u^n + dt sum_j (a_ij L u_j + ahat_ij F_j)
+//         (eq. 10) -- the newest L u_j, F_j come straight from LDS -- then
+//         w = A_ii^{-1} rhs and the particular fluxes h = flux rows . w (eqs. 5-6); or the
+//         interior step update u^{n+1} = u^n + dt sum_j (b_j L u_j + bhat_j F_j) and the
+//         interior part of the edge fluxes for the interface-line solves.
+// Everything the two phases exchange is leaf-local, so fusing them saves a launch per
+// stage and overlaps the tail of one stream with the start of the next.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "hps_device.h"
+
+namespace hps {
+
+constexpr int LPF = 8;    // operator loads issued ahead of each stream
+constexpr int LUNR = 8;   // operator loads in flight in the streaming loop
+
+// Sum the G column-group partials of `rows` rows (LDS, [g][rows]) and call fin(row, y).
+// Several threads share a row; the slices are added in a fixed order (deterministic).
+template <typename T, typename Fin>
+__device__ __forceinline__ void reduce_rows(const T *part, int rows, int G, double *red, Fin fin) {
+    for (int r0 = 0; r0 < rows; r0 += NT) {
+        const int nr = min(NT, rows - r0);
+        const int nsl = min(G, NT / nr);
+        const int t = threadIdx.x;
+        const int row = t % nr, sl = t / nr;
+        if (sl < nsl) {
+            T y = T(0);
+            for (int gg = sl; gg < G; gg += nsl) y += part[gg * rows + r0 + row];
+            red[sl * nr + row] = (double)y;
+        }
+        __syncthreads();
+        if (t < nr) {
+            double y = 0.0;
+            for (int s2 = 0; s2 < nsl; ++s2) y += red[s2 * nr + t];
+            fin(r0 + t, y);
+        }
+        __syncthreads();
+    }
+}
+
+enum { DOWN_NONE = 0, DOWN_WRITE_U = 1, DOWN_STAGE = 2, DOWN_IR_ADD = 3, DOWN_EVAL = 4 };
+enum { UP_NONE = 0, UP_BODY = 1, UP_STAGE = 2, UP_UPDATE = 3 };
+
+struct LeafArgs {
+    LeafGeo geo;
+    const int *leaf_ij;
+    const double *D, *D2, *coef;
+    int down, up;
+    int xs_cap, part_cap;
+    // down phase
+    PanelView sl;
+    const double *ub, *w_in;     // leaf boundary values [leaf][4q], particular solutions [leaf][q2]
+    const double *u_eval;        // DOWN_EVAL: canonical vector evaluated
+    double *u_out;               // DOWN_WRITE_U / DOWN_IR_ADD
+    double *Lu_out, *F_out;      // DOWN_STAGE / DOWN_EVAL: L u_i, F_i (interior, canonical)
+    const double *q_src;
+    double q_scale;
+    GPoly g;
+    unsigned long long *norms;   // DOWN_IR_ADD: max|delta|, max|u|
+    // up phase
+    PanelView ainv;
+    const double *body;          // UP_BODY
+    const double *un;            // UP_STAGE / UP_UPDATE: u^n (canonical)
+    const double *Lu_in, *F_in;  // stage vectors [stage][n_int]
+    int nprev;                   // stages before the one being assembled (the last is in LDS)
+    double ca[8], cf[8];         // dt a_ij, dt ahat_ij (UP_STAGE) or dt b_j, dt bhat_j (UP_UPDATE)
+    double *rhs_copy;
+    double *w_out, *h_out;
+    double *unew, *fpart;        // UP_UPDATE
+};
+
+__device__ __forceinline__ double poly_g(const GPoly &g, double u) {
+    if (g.kind == 0) return 0.0;
+    return g.g0 + u * (g.g1 + u * (g.g2 + u * g.g3));
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_leaf(LeafArgs a) {
+    constexpr int VW = 16 / sizeof(T);
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT];
+    __shared__ double nred[2][NT / 64];
+    const int leaf = blockIdx.x;
+    const int q = a.geo.q, p = a.geo.p, q2 = q * q, nb = 4 * q;
+    const int li = a.leaf_ij[2 * leaf], lj = a.leaf_ij[2 * leaf + 1];
+    const int64_t base = ((int64_t)lj * a.geo.n1 + li) * q2;
+    const int64_t n_int = a.geo.n_int;
+    Carve cv{smem};
+    T *xs = cv.take<T>(a.xs_cap);
+    T *part = cv.take<T>(a.part_cap);
+    double *tile = cv.take<double>(p * p);
+    double *D = cv.take<double>(p * p);
+    double *D2 = cv.take<double>(p * p);
+    double *luv = cv.take<double>(q2);
+    double *fv = cv.take<double>(q2);
+    const bool stream_down = a.down == DOWN_WRITE_U || a.down == DOWN_STAGE || a.down == DOWN_IR_ADD;
+    const bool stream_up = a.up == UP_BODY || a.up == UP_STAGE;
+    const bool need_L = a.down == DOWN_STAGE || a.down == DOWN_EVAL;
+    PanelStream<T, LPF, LUNR> ps;
+    if (stream_down) ps.start(reinterpret_cast<const T *>(a.sl.data) + (int64_t)leaf * a.sl.node_elems, a.sl.rp, a.sl.G, a.sl.S);
+    else if (stream_up) ps.start(reinterpret_cast<const T *>(a.ainv.data) + (int64_t)leaf * a.ainv.node_elems, a.ainv.rp, a.ainv.G, a.ainv.S);
+    load_dmat(a.D, D, p * p);
+    if (need_L) load_dmat(a.D2, D2, p * p);
+
+    // ---------------- down phase ----------------
+    if (a.down != DOWN_NONE) {
+        // particular solution w of this leaf, staged in LDS before the stream is consumed
+        if (stream_down)
+            for (int k = threadIdx.x; k < q2; k += NT) fv[k] = a.w_in[(int64_t)leaf * q2 + k];
+        for (int k = threadIdx.x; k < p * p; k += NT) tile[k] = 0.0;
+        if (stream_down) {
+            const double *ubl = a.ub + (int64_t)leaf * nb;
+            const int SG = a.sl.S * a.sl.G;
+            for (int k = threadIdx.x; k < SG; k += NT) xs[k] = (T)(k < nb ? ubl[k] : 0.0);
+            __syncthreads();
+            for (int k = threadIdx.x; k < nb; k += NT) tile[edge_tile_pos(p, q, k / q, k % q)] = ubl[k];
+            ps.finish(xs, part);
+            if (stream_up)
+                ps.start(reinterpret_cast<const T *>(a.ainv.data) + (int64_t)leaf * a.ainv.node_elems, a.ainv.rp,
+                         a.ainv.G, a.ainv.S);
+            __syncthreads();
+            // u_i interior = S_leaf u_b + w (this thread's rows are its own interior nodes)
+            reduce_rows<T>(part, a.sl.rp * VW, a.sl.G, red, [&](int row, double y) {
+                if (row < q2) tile[(row / q + 1) * p + (row % q) + 1] = y + fv[row];
+            });
+        } else {
+            // DOWN_EVAL: the tile of a given canonical vector
+            __syncthreads();
+            for (int k = threadIdx.x; k < q2; k += NT) tile[(k / q + 1) * p + (k % q) + 1] = a.u_eval[base + k];
+            for (int k = threadIdx.x; k < nb; k += NT)
+                tile[edge_tile_pos(p, q, k / q, k % q)] = a.u_eval[edge_index(a.geo, li, lj, k / q, k % q)];
+            __syncthreads();
+        }
+        if (need_L) {
+            for (int k = threadIdx.x; k < q2; k += NT) {
+                {
+                    const int aa = k % q + 1, bb = k / q + 1;
+                    double ux = 0, uxx = 0, uy = 0, uyy = 0;
+                    for (int m = 0; m < p; ++m) {
+                        const double xr = tile[bb * p + m];
+                        const double yc = tile[m * p + aa];
+                        ux = fma(D[aa * p + m], xr, ux);
+                        uxx = fma(D2[aa * p + m], xr, uxx);
+                        uy = fma(D[bb * p + m], yc, uy);
+                        uyy = fma(D2[bb * p + m], yc, uyy);
+                    }
+                    const double u = tile[bb * p + aa];
+                    // L u = cxx u_xx + cyy u_yy + cx u_x + cy u_y + c0 u (eq. 3 for L, c12 = 0)
+                    const double *cf = a.coef + base + k;
+                    const double Lu = cf[0] * uxx + cf[n_int] * uyy + cf[2 * n_int] * ux + cf[3 * n_int] * uy +
+                                      cf[4 * n_int] * u;
+                    const double F = (a.q_src ? a.q_scale * a.q_src[base + k] : 0.0) + poly_g(a.g, u);
+                    luv[k] = Lu;
+                    fv[k] = F;
+                    a.Lu_out[base + k] = Lu;
+                    a.F_out[base + k] = F;
+                }
+            }
+        } else if (a.down == DOWN_WRITE_U || a.down == DOWN_IR_ADD) {
+            double dmax = 0.0, umax = 0.0;
+            const double *ubl = a.ub + (int64_t)leaf * nb;
+            for (int k = threadIdx.x; k < q2 + nb; k += NT) {
+                int64_t gi;
+                double v;
+                bool own = true;
+                if (k < q2) {
+                    gi = base + k;
+                    v = tile[(k / q + 1) * p + (k % q) + 1];
+                } else {
+                    const int e = (k - q2) / q, m = (k - q2) % q;
+                    // each edge node is written by exactly one leaf: left/bottom edges always,
+                    // right/top edges only on the last column/row of leaves
+                    own = (e == 0 || e == 2) || (e == 1 && li == a.geo.n1 - 1) || (e == 3 && lj == a.geo.n2 - 1);
+                    gi = edge_index(a.geo, li, lj, e, m);
+                    v = ubl[k - q2];
+                }
+                if (!own) continue;
+                if (a.down == DOWN_WRITE_U) {
+                    a.u_out[gi] = v;
+                } else {
+                    const double nu = a.u_out[gi] + v;
+                    a.u_out[gi] = nu;
+                    dmax = fmax(dmax, fabs(v));
+                    umax = fmax(umax, fabs(nu));
+                }
+            }
+            if (a.down == DOWN_IR_ADD) {
+                for (int off = 32; off > 0; off >>= 1) {
+                    dmax = fmax(dmax, __shfl_xor(dmax, off));
+                    umax = fmax(umax, __shfl_xor(umax, off));
+                }
+                if ((threadIdx.x & 63) == 0) {
+                    nred[0][threadIdx.x >> 6] = dmax;
+                    nred[1][threadIdx.x >> 6] = umax;
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    double dd = 0, uu = 0;
+                    for (int w = 0; w < NT / 64; ++w) {
+                        dd = fmax(dd, nred[0][w]);
+                        uu = fmax(uu, nred[1][w]);
+                    }
+                    // non-negative doubles order like their bit patterns
+                    atomicMax(&a.norms[0], (unsigned long long)__double_as_longlong(dd));
+                    atomicMax(&a.norms[1], (unsigned long long)__double_as_longlong(uu));
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---------------- up phase ----------------
+    if (a.up == UP_NONE) return;
+    if (a.up == UP_UPDATE) {
+        // interior u^{n+1}; the newest stage's L u, F are in LDS
+        const int last = a.nprev;
+        for (int k = threadIdx.x; k < q2; k += NT) {
+            double v = a.un[base + k];
+            for (int j = 0; j < last; ++j) {
+                v += a.ca[j] * a.Lu_in[j * n_int + base + k];
+                v += a.cf[j] * a.F_in[j * n_int + base + k];
+            }
+            v += a.ca[last] * luv[k] + a.cf[last] * fv[k];
+            a.unew[base + k] = v;
+            tile[k] = v;   // reuse as the interior values, row-major
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nb; k += NT) {
+            const int e = k / q, m = k % q;
+            const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * p);
+            double f = 0.0;
+            if (e < 2) {
+                for (int c = 1; c <= q; ++c) f = fma(dr[c], tile[m * q + c - 1], f);
+            } else {
+                for (int c = 1; c <= q; ++c) f = fma(dr[c], tile[(c - 1) * q + m], f);
+            }
+            a.fpart[((int64_t)lj * a.geo.n1 + li) * nb + k] = f;
+        }
+        return;
+    }
+    const int SG = a.ainv.S * a.ainv.G;
+    for (int k = threadIdx.x; k < SG; k += NT) {
+        double r = 0.0;
+        if (k < q2) {
+            if (a.up == UP_BODY) {
+                r = a.body[base + k];
+            } else {
+                r = a.un[base + k];
+                const int last = a.nprev - 1;   // newest stage, held in LDS
+                for (int j = 0; j < last; ++j) {
+                    r += a.ca[j] * a.Lu_in[j * n_int + base + k];
+                    r += a.cf[j] * a.F_in[j * n_int + base + k];
+                }
+                r += a.ca[last] * luv[k] + a.cf[last] * fv[k];
+                if (a.rhs_copy) a.rhs_copy[base + k] = r;
+            }
+        }
+        xs[k] = (T)r;
+    }
+    __syncthreads();
+    ps.finish(xs, part);
+    __syncthreads();
+    double *wv = luv;   // w = A_ii^{-1} rhs; luv is free again
+    reduce_rows<T>(part, a.ainv.rp * VW, a.ainv.G, red, [&](int row, double y) {
+        if (row < q2) {
+            wv[row] = y;
+            a.w_out[(int64_t)leaf * q2 + row] = y;
+        }
+    });
+    for (int k = threadIdx.x; k < nb; k += NT) {
+        const int e = k / q, m = k % q;
+        const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * p);
+        double h = 0.0;
+        if (e < 2) {
+            for (int c = 1; c <= q; ++c) h = fma(dr[c], wv[m * q + c - 1], h);
+        } else {
+            for (int c = 1; c <= q; ++c) h = fma(dr[c], wv[(c - 1) * q + m], h);
+        }
+        a.h_out[(int64_t)leaf * nb + k] = h;
+    }
+}
+
+// =======================================================================================
+// launcher
+// =======================================================================================
+static int leaf_family(const LeafPhase &ph, bool fp32) {
+    const bool stage_down = ph.down == LD_STAGE;
+    if (ph.down == LD_EVAL) return ph.up == LU_UPDATE ? KF_LEAF_EVAL_UPDATE64 : (fp32 ? KF_LEAF_EVAL_UP32 : KF_LEAF_EVAL_UP64);
+    if (stage_down && ph.up == LU_UPDATE) return KF_LEAF_DOWN_UPDATE64;
+    if (stage_down) return fp32 ? KF_LEAF_DOWN_UP32 : KF_LEAF_DOWN_UP64;
+    if (ph.down != LD_NONE) return fp32 ? KF_LEAF_DOWN32 : KF_LEAF_DOWN64;
+    return fp32 ? KF_LEAF_UP32 : KF_LEAF_UP64;
+}
+
+int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st) {
+    ProfScope ps_(&op->prof, leaf_family(ph, fp32), st);
+    LeafArgs a{};
+    a.geo = geo_of(op);
+    a.leaf_ij = op->leaf_ij;
+    a.D = op->D;
+    a.D2 = op->D2;
+    a.coef = op->coef;
+    a.down = ph.down;
+    a.up = ph.up;
+    const Panel &sl = fp32 ? op->sleaf32 : op->sleaf64;
+    const Panel &ai = fp32 ? op->ainv32 : op->ainv64;
+    a.sl = view(sl);
+    a.ainv = view(ai);
+    const int vw = fp32 ? 4 : 2;
+    a.xs_cap = std::max(sl.S * sl.G, ai.S * ai.G);
+    a.part_cap = std::max(sl.G * sl.rp, ai.G * ai.rp) * vw;
+    a.ub = op->ub_leaf;
+    a.w_in = op->w_leaf;
+    a.u_eval = ph.u_eval;
+    a.u_out = ph.u_out;
+    a.Lu_out = ph.Lu_out;
+    a.F_out = ph.F_out;
+    a.q_src = ph.q_src;
+    a.q_scale = ph.q_scale;
+    a.g = ph.g;
+    a.norms = reinterpret_cast<unsigned long long *>(op->ir_norms);
+    a.body = ph.body;
+    a.un = ph.un;
+    a.Lu_in = ph.Lu_in;
+    a.F_in = ph.F_in;
+    a.nprev = ph.nprev;
+    for (int j = 0; j < 8; ++j) {
+        a.ca[j] = ph.ca[j];
+        a.cf[j] = ph.cf[j];
+    }
+    a.rhs_copy = ph.rhs_copy;
+    a.w_out = op->w_leaf;
+    a.h_out = op->h_leaf;
+    a.unew = ph.unew;
+    a.fpart = op->ir_flux;
+    const size_t es = fp32 ? 4 : 8;
+    const size_t pp = (size_t)op->p * op->p * 8, q2b = (size_t)op->q2 * 8;
+    const size_t lds = carve_bytes({(size_t)a.xs_cap * es, (size_t)a.part_cap * es, pp, pp, pp, q2b, q2b});
+    if (fp32) hipLaunchKernelGGL(k_leaf<float>, dim3(op->nleaves), dim3(NT), lds, st, a);
+    else hipLaunchKernelGGL(k_leaf<double>, dim3(op->nleaves), dim3(NT), lds, st, a);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+}  // namespace hps

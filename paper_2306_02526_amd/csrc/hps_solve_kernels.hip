@@ -47,87 +47,6 @@ __device__ __forceinline__ double gpoly(const GPoly &g, double u) {
     return g.g0 + u * (g.g1 + u * (g.g2 + u * g.g3));
 }
 
-template <typename T>
-static size_t panel_lds(const Panel &pn) {
-    return (size_t)pn.S * pn.G * sizeof(T) + (size_t)pn.G * pn.rp * pn.vw * sizeof(T) + 32;
-}
-
-// =======================================================================================
-// leaf upward kernel: stage right-hand side, w = A_ii^{-1} rhs, particular fluxes h
-// =======================================================================================
-struct LeafUpArgs {
-    PanelView ainv;
-    const int *leaf_ij;
-    LeafGeo geo;
-    const double *body;   // mode body: canonical interior rhs
-    const double *un;     // mode stage: u^n (canonical, interior part used)
-    const double *Lu, *F; // stage vectors, j-th at + j*n_int
-    StageCoefs sc;
-    double *rhs_copy;     // optional copy of the assembled rhs (canonical interior)
-    const double *D;
-    double *w_out, *h_out;
-};
-
-template <typename T>
-__global__ __launch_bounds__(NT) void k_leaf_up(LeafUpArgs a) {
-    constexpr int VW = 16 / sizeof(T);
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int leaf = blockIdx.x;
-    const int q = a.geo.q, p = a.geo.p, q2 = q * q;
-    const int SG = a.ainv.S * a.ainv.G;
-    Carve cv{smem};
-    T *xs = cv.take<T>(SG);
-    T *part = cv.take<T>((size_t)a.ainv.G * a.ainv.rp * VW);
-    double *wv = cv.take<double>(q2);
-    double *d0 = cv.take<double>(p);
-    double *dl = cv.take<double>(p);
-    PanelStream<T, PF, UNR> ps;
-    ps.start(reinterpret_cast<const T *>(a.ainv.data) + (int64_t)leaf * a.ainv.node_elems,
-             a.ainv.rp, a.ainv.G, a.ainv.S);
-    const int li = a.leaf_ij[2 * leaf], lj = a.leaf_ij[2 * leaf + 1];
-    const int64_t base = ((int64_t)lj * a.geo.n1 + li) * q2;
-    for (int k = threadIdx.x; k < SG; k += NT) {
-        double r = 0.0;
-        if (k < q2) {
-            if (a.body) {
-                r = a.body[base + k];
-            } else {
-                r = a.un[base + k];
-                for (int j = 0; j < a.sc.nprev; ++j) {
-                    r += a.sc.ca[j] * a.Lu[j * a.geo.n_int + base + k];
-                    r += a.sc.cf[j] * a.F[j * a.geo.n_int + base + k];
-                }
-                if (a.rhs_copy) a.rhs_copy[base + k] = r;
-            }
-        }
-        xs[k] = (T)r;
-    }
-    for (int k = threadIdx.x; k < p; k += NT) {
-        d0[k] = a.D[k];
-        dl[k] = a.D[(p - 1) * p + k];
-    }
-    __syncthreads();
-    ps.finish(xs, part);
-    __syncthreads();
-    for (int k = threadIdx.x; k < q2; k += NT) {
-        const double w = panel_sum<T>(part, a.ainv.rp, a.ainv.G, k);
-        wv[k] = w;
-        a.w_out[(int64_t)leaf * q2 + k] = w;
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < 4 * q; k += NT) {
-        const int e = k / q, m = k - (k / q) * q;
-        const double *dr = (e == 0 || e == 2) ? d0 : dl;
-        double h = 0.0;
-        if (e < 2) {
-            for (int c = 1; c <= q; ++c) h = fma(dr[c], wv[m * q + c - 1], h);
-        } else {
-            for (int c = 1; c <= q; ++c) h = fma(dr[c], wv[(c - 1) * q + m], h);
-        }
-        a.h_out[(int64_t)leaf * 4 * q + k] = h;
-    }
-}
-
 // =======================================================================================
 // level kernels (upward: w3 = X d, h = [h1; h2] + U d; downward: u3 = S u12 + w3)
 // =======================================================================================
@@ -193,6 +112,25 @@ __global__ __launch_bounds__(NT) void k_level(LevelArgs a) {
     ps.start(reinterpret_cast<const T *>(a.pn.data) + (int64_t)node * a.pn.node_elems +
                  (int64_t)(tile * kch + chunk) * a.pn.tile_elems,
              a.pn.rp, a.pn.G, a.pn.S);
+    // operands of the finalisation, loaded now so the tail has no dependent global loads
+    // (level tiles have at most NT rows, one per thread)
+    const int rows = a.pn.rp * VW;
+    const int myrow = tile * rows + threadIdx.x;
+    double fin = 0.0;
+    int64_t ia = -1, ib = -1;
+    if (kch == 1 && (int)threadIdx.x < rows) {
+        if (UP) {
+            if (!a.root && myrow >= a.n3 && myrow < a.n3 + a.n12) {
+                const int m = myrow - a.n3;
+                fin = (m < a.n1) ? a.hc[(int64_t)(2 * node) * a.nbc + a.a1[m]]
+                                 : a.hc[(int64_t)(2 * node + 1) * a.nbc + a.b2[m - a.n1]];
+            }
+        } else if (myrow < a.n3) {
+            fin = a.w3[(int64_t)node * a.n3 + myrow];
+            ia = (int64_t)(2 * node) * a.nbc + a.a3[myrow];
+            ib = (int64_t)(2 * node + 1) * a.nbc + a.b3[myrow];
+        }
+    }
     const int cols = UP ? a.n3 : a.n12;
     for (int k = threadIdx.x; k < SG; k += NT) {
         const int kg = chunk * SG + k;
@@ -220,29 +158,30 @@ __global__ __launch_bounds__(NT) void k_level(LevelArgs a) {
     __syncthreads();
     ps.finish(xs, part);
     __syncthreads();
-    const int rows = a.pn.rp * VW;
     if (kch == 1) {
         // rows x G partial sums: each row is summed over the column groups by several
         // threads, then the slices are added in a fixed order
         const int G = a.pn.G;
-        for (int r0 = 0; r0 < rows; r0 += NT) {
-            const int nr = min(NT, rows - r0);
-            const int nsl = min(G, NT / nr);
-            const int t = threadIdx.x;
-            const int row = t % nr, sl = t / nr;
-            if (sl < nsl) {
-                T y = T(0);
-                for (int gg = sl; gg < G; gg += nsl) y += part[gg * rows + r0 + row];
-                red[sl * nr + row] = (double)y;
+        const int nsl = min(G, NT / rows);
+        const int t = threadIdx.x;
+        const int row = t % rows, sl = t / rows;
+        if (sl < nsl) {
+            T y = T(0);
+            for (int gg = sl; gg < G; gg += nsl) y += part[gg * rows + row];
+            red[sl * rows + row] = (double)y;
+        }
+        __syncthreads();
+        if (t < rows) {
+            double y = 0.0;
+            for (int s2 = 0; s2 < nsl; ++s2) y += red[s2 * rows + t];
+            if (UP) {
+                if (myrow < a.n3) a.w3[(int64_t)node * a.n3 + myrow] = y;
+                else if (!a.root && myrow < a.n3 + a.n12) a.h[(int64_t)node * a.n12 + myrow - a.n3] = fin + y;
+            } else if (myrow < a.n3) {
+                const double u3 = y + fin;
+                a.ubc[ia] = u3;
+                a.ubc[ib] = u3;
             }
-            __syncthreads();
-            if (t < nr) {
-                double y = 0.0;
-                for (int s2 = 0; s2 < nsl; ++s2) y += red[s2 * nr + t];
-                if (UP) up_finalize(a, node, tile * rows + r0 + t, y);
-                else down_finalize(a, node, tile * rows + r0 + t, y);
-            }
-            __syncthreads();
         }
         return;
     }
@@ -277,131 +216,6 @@ __global__ __launch_bounds__(NT) void k_level(LevelArgs a) {
         __syncthreads();
     }
     if (threadIdx.x == 0) a.cnt[node * ntile + tile] = 0;
-}
-
-// single-leaf tree: the leaf boundary is the domain boundary
-__global__ void k_root_leaf_ub(const double *dir, const int *root_map, double *ub, int nb) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < nb) ub[t] = dir ? dir[root_map[t]] : 0.0;
-}
-
-// =======================================================================================
-// leaf downward kernel: u_i = S_leaf u_b + w, then (mode) write u, or L u and F, or add a
-// refinement correction
-// =======================================================================================
-struct LeafDownArgs {
-    PanelView sl;
-    const int *leaf_ij;
-    LeafGeo geo;
-    const double *ub, *w;
-    const double *D, *D2, *coef;
-    int mode;
-    double *u;
-    double *Lu, *F;
-    const double *q_src;
-    double q_scale;
-    GPoly g;
-    unsigned long long *norms;  // mode 2: [0] max|delta|, [1] max|u| as ordered bit patterns
-};
-
-__device__ __forceinline__ void atomic_max_abs(unsigned long long *dst, double v) {
-    // non-negative doubles order like their bit patterns
-    atomicMax(dst, (unsigned long long)__double_as_longlong(fabs(v)));
-}
-
-template <typename T>
-__global__ __launch_bounds__(NT) void k_leaf_down(LeafDownArgs a) {
-    constexpr int VW = 16 / sizeof(T);
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[2][NT / 64];
-    const int leaf = blockIdx.x;
-    const int q = a.geo.q, p = a.geo.p, q2 = q * q, nb = 4 * q;
-    const int SG = a.sl.S * a.sl.G;
-    Carve cv{smem};
-    T *xs = cv.take<T>(SG);
-    T *part = cv.take<T>((size_t)a.sl.G * a.sl.rp * VW);
-    double *tile = cv.take<double>(p * p);
-    double *D = cv.take<double>(a.mode == 1 ? p * p : 0);
-    double *D2 = cv.take<double>(a.mode == 1 ? p * p : 0);
-    PanelStream<T, PF, UNR> ps;
-    ps.start(reinterpret_cast<const T *>(a.sl.data) + (int64_t)leaf * a.sl.node_elems, a.sl.rp, a.sl.G,
-             a.sl.S);
-    const int li = a.leaf_ij[2 * leaf], lj = a.leaf_ij[2 * leaf + 1];
-    const int64_t base = ((int64_t)lj * a.geo.n1 + li) * q2;
-    const double *ubl = a.ub + (int64_t)leaf * nb;
-    for (int k = threadIdx.x; k < SG; k += NT) xs[k] = (T)(k < nb ? ubl[k] : 0.0);
-    for (int k = threadIdx.x; k < p * p; k += NT) tile[k] = 0.0;
-    if (a.mode == 1) {
-        load_dmat(a.D, D, p * p);
-        load_dmat(a.D2, D2, p * p);
-    }
-    __syncthreads();
-    ps.finish(xs, part);
-    __syncthreads();
-    for (int k = threadIdx.x; k < q2; k += NT) {
-        const double v = panel_sum<T>(part, a.sl.rp, a.sl.G, k) + a.w[(int64_t)leaf * q2 + k];
-        tile[(k / q + 1) * p + (k % q) + 1] = v;
-    }
-    for (int k = threadIdx.x; k < nb; k += NT) tile[edge_tile_pos(p, q, k / q, k % q)] = ubl[k];
-    __syncthreads();
-    if (a.mode == 0 || a.mode == 2) {
-        double dmax = 0.0, umax = 0.0;
-        for (int k = threadIdx.x; k < q2 + nb; k += NT) {
-            int64_t gi;
-            double v;
-            bool own = true;
-            if (k < q2) {
-                gi = base + k;
-                v = tile[(k / q + 1) * p + (k % q) + 1];
-            } else {
-                const int e = (k - q2) / q, m = (k - q2) % q;
-                // each edge node is written by exactly one leaf: left/bottom edges always,
-                // right/top edges only on the last column/row of leaves
-                own = (e == 0 || e == 2) || (e == 1 && li == a.geo.n1 - 1) ||
-                      (e == 3 && lj == a.geo.n2 - 1);
-                gi = edge_index(a.geo, li, lj, e, m);
-                v = ubl[k - q2];
-            }
-            if (!own) continue;
-            if (a.mode == 0) {
-                a.u[gi] = v;
-            } else {
-                const double nu = a.u[gi] + v;
-                a.u[gi] = nu;
-                dmax = fmax(dmax, fabs(v));
-                umax = fmax(umax, fabs(nu));
-            }
-        }
-        if (a.mode == 2) {
-            for (int off = 32; off > 0; off >>= 1) {
-                dmax = fmax(dmax, __shfl_xor(dmax, off));
-                umax = fmax(umax, __shfl_xor(umax, off));
-            }
-            if ((threadIdx.x & 63) == 0) {
-                red[0][threadIdx.x >> 6] = dmax;
-                red[1][threadIdx.x >> 6] = umax;
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                double d = 0, uu = 0;
-                for (int w = 0; w < NT / 64; ++w) {
-                    d = fmax(d, red[0][w]);
-                    uu = fmax(uu, red[1][w]);
-                }
-                atomic_max_abs(&a.norms[0], d);
-                atomic_max_abs(&a.norms[1], uu);
-            }
-        }
-        return;
-    }
-    // mode 1: L u_i and F_i = q + g(u_i) at the interior nodes
-    for (int k = threadIdx.x; k < q2; k += NT) {
-        const int64_t gi = base + k;
-        a.Lu[gi] = tile_L(tile, D, D2, p, q, a.coef, a.geo.n_int, gi, k);
-        const double u = tile[(k / q + 1) * p + (k % q) + 1];
-        const double qv = a.q_src ? a.q_scale * a.q_src[gi] : 0.0;
-        a.F[gi] = qv + gpoly(a.g, u);
-    }
 }
 
 // =======================================================================================
@@ -515,42 +329,6 @@ struct UpdateArgs {
     int s;
 };
 
-// One workgroup per leaf (canonical order): interior u^{n+1} = u^n + sum_j (cb_j L u_j +
-// cbh_j F_j), and the interior part of the coordinate-direction flux on the four leaf edges,
-// [leaf][e][m] (e = left, right, bottom, top), for the interface-line solves.
-__global__ __launch_bounds__(NT) void k_update(UpdateArgs a, LeafGeo g, const double *D, double *fpart) {
-    __shared__ double ui[PMAX * PMAX];
-    __shared__ double d0[PMAX], dl[PMAX];
-    const int cl = blockIdx.x;
-    const int q = g.q, p = g.p, q2 = q * q;
-    const int64_t base = (int64_t)cl * q2;
-    for (int k = threadIdx.x; k < p; k += NT) {
-        d0[k] = D[k];
-        dl[k] = D[(p - 1) * p + k];
-    }
-    for (int k = threadIdx.x; k < q2; k += NT) {
-        double v = a.un[base + k];
-        for (int j = 0; j < a.s; ++j) {
-            v += a.cb[j] * a.Lu[j * a.n_int + base + k];
-            v += a.cbh[j] * a.F[j * a.n_int + base + k];
-        }
-        a.unew[base + k] = v;
-        ui[k] = v;
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < 4 * q; k += NT) {
-        const int e = k / q, m = k % q;
-        const double *dr = (e == 0 || e == 2) ? d0 : dl;
-        double f = 0.0;
-        if (e < 2) {
-            for (int c = 1; c <= q; ++c) f = fma(dr[c], ui[m * q + c - 1], f);
-        } else {
-            for (int c = 1; c <= q; ++c) f = fma(dr[c], ui[(c - 1) * q + m], f);
-        }
-        fpart[(int64_t)cl * 4 * q + k] = f;
-    }
-}
-
 __global__ void k_scatter_boundary(const double *f, const int *bnd_glob, double *u, int64_t nb) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < nb) u[bnd_glob[k]] = f ? f[k] : 0.0;
@@ -568,9 +346,10 @@ struct LineArgs {
     const double *inv_den;    // 1 / (diag - lower cp[k-1])
 };
 
-// One thread per grid line; the recursion carries d_{k-1} and e_{k+1} in registers, so the
-// only memory traffic is independent loads of the right-hand sides and of d_k.
+// One thread per grid line; the recursion carries d_{k-1} and e_{k+1} in registers and
+// its inputs are loaded CH at a time ahead of use, so no load waits on a store.
 __global__ void k_interface_lines(LineArgs a) {
+    constexpr int CH = 8;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const LeafGeo &g = a.geo;
     const int q = g.q, p = g.p;
@@ -582,32 +361,63 @@ __global__ void k_interface_lines(LineArgs a) {
     if (n < 2) return;
     const int line = vert ? t / q : (t - nvs) / q;   // leaf row j (vert) or column i (horz)
     const int m0 = (vert ? t : t - nvs) % q;          // local node index along the edge
-    auto unk = [&](int k) -> int64_t {
-        return vert ? g.n_int + ((int64_t)k * g.n2 + line) * q + m0
-                    : g.n_int + g.n_vert + ((int64_t)k * g.n1 + line) * q + m0;
-    };
-    // flux part of leaf number k along the line on side e
-    auto fp = [&](int k, int e) -> double {
-        const int64_t leaf = vert ? (int64_t)line * g.n1 + k : (int64_t)k * g.n1 + line;
-        return a.fpart[leaf * 4 * q + e * q + m0];
-    };
+    const double *__restrict__ fpart = a.fpart;
+    const double *__restrict__ cp = a.cp;
+    const double *__restrict__ inv_den = a.inv_den;
+    double *__restrict__ u = a.u;
+    const int64_t ustride = vert ? (int64_t)g.n2 * q : (int64_t)g.n1 * q;
+    const int64_t u0 = vert ? g.n_int + (int64_t)line * q + m0 : g.n_int + g.n_vert + (int64_t)line * q + m0;
+    // leaf number k along the line, flux part on side e
+    const int64_t lstride = vert ? 4 * q : (int64_t)g.n1 * 4 * q;
+    const int64_t l0 = (vert ? (int64_t)line * g.n1 * 4 * q : (int64_t)line * 4 * q) + m0;
     const int elo = vert ? 0 : 2, ehi = vert ? 1 : 3;   // left/right or bottom/top sides
     const double lower = a.D[(p - 1) * p + 0];
     const double upper = -a.D[0 * p + (p - 1)];
-    const double e0 = a.u[unk(0)], en = a.u[unk(n)];
+    const double e0 = u[u0], en = u[u0 + (int64_t)n * ustride];
     double dprev = 0.0;
-    for (int k = 1; k < n; ++k) {
-        double r = fp(k, elo) - fp(k - 1, ehi);
-        if (k == 1) r -= lower * e0;
-        if (k == n - 1) r -= upper * en;
-        const double d = (r - (k > 1 ? lower * dprev : 0.0)) * a.inv_den[k];
-        a.u[unk(k)] = d;
-        dprev = d;
+    for (int k0 = 1; k0 < n; k0 += CH) {
+        double fl[CH], fh[CH], id[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int k = k0 + c;
+            if (k < n) {
+                fl[c] = fpart[l0 + k * lstride + elo * q];
+                fh[c] = fpart[l0 + (k - 1) * lstride + ehi * q];
+                id[c] = inv_den[k];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int k = k0 + c;
+            if (k < n) {
+                double r = fl[c] - fh[c];
+                if (k == 1) r -= lower * e0;
+                if (k == n - 1) r -= upper * en;
+                const double d = (r - (k > 1 ? lower * dprev : 0.0)) * id[c];
+                u[u0 + k * ustride] = d;
+                dprev = d;
+            }
+        }
     }
     double enext = dprev;   // e_{n-1} = d_{n-1}
-    for (int k = n - 2; k >= 1; --k) {
-        enext = a.u[unk(k)] - a.cp[k] * enext;
-        a.u[unk(k)] = enext;
+    for (int k0 = n - 2; k0 >= 1; k0 -= CH) {
+        double dv[CH], cv[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int k = k0 - c;
+            if (k >= 1) {
+                dv[c] = u[u0 + k * ustride];
+                cv[c] = cp[k];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int k = k0 - c;
+            if (k >= 1) {
+                enext = dv[c] - cv[c] * enext;
+                u[u0 + k * ustride] = enext;
+            }
+        }
     }
 }
 
@@ -618,8 +428,10 @@ __global__ void k_zero(double *p, int64_t n) {
 
 // ---- profiling ---------------------------------------------------------------------------
 const char *const kKernelFamilyNames[KF_COUNT] = {
-    "leaf_up_fp64", "leaf_up_fp32", "level_up_fp64", "level_up_fp32", "level_down_fp64",
-    "level_down_fp32", "leaf_down_fp64", "leaf_down_fp32", "eval", "residual", "update"};
+    "leaf_up_fp64", "leaf_up_fp32", "leaf_down_fp64", "leaf_down_fp32", "leaf_eval_up_fp64",
+    "leaf_eval_up_fp32", "leaf_down_up_fp64", "leaf_down_up_fp32", "leaf_down_update_fp64",
+    "leaf_eval_update", "level_up_fp64", "level_up_fp32", "level_down_fp64", "level_down_fp32",
+    "residual", "lines"};
 
 hipEvent_t Profiler::get() {
     if (!pool.empty()) {
@@ -661,33 +473,6 @@ ProfScope::~ProfScope() {
 // =======================================================================================
 // launchers
 // =======================================================================================
-int launch_leaf_up(const hps_op *op, bool fp32, const double *body, const double *un,
-                   const double *Lu, const double *F, const StageCoefs *sc, double *rhs_copy,
-                   hipStream_t st) {
-    ProfScope ps_(&op->prof, fp32 ? KF_LEAF_UP32 : KF_LEAF_UP64, st);
-    const Panel &pn = fp32 ? op->ainv32 : op->ainv64;
-    LeafUpArgs a{};
-    a.ainv = view(pn);
-    a.leaf_ij = op->leaf_ij;
-    a.geo = geo_of(op);
-    a.body = body;
-    a.un = un;
-    a.Lu = Lu;
-    a.F = F;
-    if (sc) a.sc = *sc;
-    a.rhs_copy = rhs_copy;
-    a.D = op->D;
-    a.w_out = op->w_leaf;
-    a.h_out = op->h_leaf;
-    const size_t es = fp32 ? 4 : 8;
-    const size_t lds = carve_bytes({pn.S * pn.G * es, (size_t)pn.G * pn.rp * pn.vw * es,
-                                    (size_t)op->q2 * 8, (size_t)op->p * 8, (size_t)op->p * 8});
-    if (fp32) hipLaunchKernelGGL(k_leaf_up<float>, dim3(op->nleaves), dim3(NT), lds, st, a);
-    else hipLaunchKernelGGL(k_leaf_up<double>, dim3(op->nleaves), dim3(NT), lds, st, a);
-    HPS_LAUNCHED();
-    return HPS_OK;
-}
-
 static LevelArgs level_args(const hps_op *op, int l, bool fp32, bool up) {
     const Level &L = op->lv[l];
     LevelArgs a{};
@@ -727,6 +512,12 @@ int launch_levels_up(const hps_op *op, bool fp32, const double *jump, hipStream_
     return HPS_OK;
 }
 
+// single-leaf tree: the leaf boundary is the domain boundary
+__global__ void k_root_leaf_ub(const double *dir, const int *root_map, double *ub, int nb) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nb) ub[t] = dir ? dir[root_map[t]] : 0.0;
+}
+
 int launch_levels_down(const hps_op *op, bool fp32, const double *dirichlet, hipStream_t st) {
     ProfScope ps_(&op->prof, fp32 ? KF_LEVEL_DOWN32 : KF_LEVEL_DOWN64, st);
     if (op->L == 0) {
@@ -744,56 +535,6 @@ int launch_levels_down(const hps_op *op, bool fp32, const double *dirichlet, hip
         else hipLaunchKernelGGL((k_level<double, false>), dim3(nb), dim3(NT), level_lds(pn), st, a);
         HPS_LAUNCHED();
     }
-    return HPS_OK;
-}
-
-int launch_leaf_down(const hps_op *op, bool fp32, int mode, double *u, double *Lu, double *F,
-                     const double *q_src, double q_scale, GPoly g, hipStream_t st) {
-    ProfScope ps_(&op->prof, fp32 ? KF_LEAF_DOWN32 : KF_LEAF_DOWN64, st);
-    const Panel &pn = fp32 ? op->sleaf32 : op->sleaf64;
-    LeafDownArgs a{};
-    a.sl = view(pn);
-    a.leaf_ij = op->leaf_ij;
-    a.geo = geo_of(op);
-    a.ub = op->ub_leaf;
-    a.w = op->w_leaf;
-    a.D = op->D;
-    a.D2 = op->D2;
-    a.coef = op->coef;
-    a.mode = mode;
-    a.u = u;
-    a.Lu = Lu;
-    a.F = F;
-    a.q_src = q_src;
-    a.q_scale = q_scale;
-    a.g = g;
-    a.norms = reinterpret_cast<unsigned long long *>(op->ir_norms);
-    const size_t es = fp32 ? 4 : 8;
-    const size_t pp = (size_t)op->p * op->p * 8;
-    const size_t lds = carve_bytes({pn.S * pn.G * es, (size_t)pn.G * pn.rp * pn.vw * es, pp,
-                                    mode == 1 ? pp : 0, mode == 1 ? pp : 0});
-    if (fp32) hipLaunchKernelGGL(k_leaf_down<float>, dim3(op->nleaves), dim3(NT), lds, st, a);
-    else hipLaunchKernelGGL(k_leaf_down<double>, dim3(op->nleaves), dim3(NT), lds, st, a);
-    HPS_LAUNCHED();
-    return HPS_OK;
-}
-
-int launch_eval(const hps_op *op, const double *u, double *Lu, double *F, const double *q_src,
-                double q_scale, GPoly g, hipStream_t st) {
-    ProfScope ps_(&op->prof, KF_EVAL, st);
-    EvalArgs a{};
-    a.geo = geo_of(op);
-    a.u = u;
-    a.D = op->D;
-    a.D2 = op->D2;
-    a.coef = op->coef;
-    a.Lu = Lu;
-    a.F = F;
-    a.q_src = q_src;
-    a.q_scale = q_scale;
-    a.g = g;
-    hipLaunchKernelGGL(k_eval, dim3(op->nleaves), dim3(NT), 0, st, a);
-    HPS_LAUNCHED();
     return HPS_OK;
 }
 
@@ -820,29 +561,13 @@ int launch_residual(const hps_op *op, const double *u, const double *rhs, const 
     return HPS_OK;
 }
 
-int launch_update(const hps_op *op, const double *un, double *unew, const double *Lu,
-                  const double *F, const double *cb, const double *cbh, int s,
-                  const double *f_end, hipStream_t st) {
-    ProfScope ps_(&op->prof, KF_UPDATE, st);
-    UpdateArgs a{};
-    a.n_int = op->n_int;
-    a.un = un;
-    a.unew = unew;
-    a.Lu = Lu;
-    a.F = F;
-    a.s = s;
-    for (int j = 0; j < s; ++j) {
-        a.cb[j] = cb[j];
-        a.cbh[j] = cbh[j];
-    }
-    hipLaunchKernelGGL(k_update, dim3(op->nleaves), dim3(NT), 0, st, a, geo_of(op), (const double *)op->D,
-                       op->ir_flux);
-    HPS_LAUNCHED();
-    int rc = launch_scatter_boundary(op, f_end, unew, st);
+int launch_interface_lines(const hps_op *op, double *u, const double *f_end, hipStream_t st) {
+    ProfScope ps_(&op->prof, KF_LINES, st);
+    int rc = launch_scatter_boundary(op, f_end, u, st);
     if (rc) return rc;
     LineArgs la{};
     la.geo = geo_of(op);
-    la.u = unew;
+    la.u = u;
     la.fpart = op->ir_flux;
     la.D = op->D;
     la.cp = op->tri_cp;

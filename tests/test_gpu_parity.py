@@ -283,3 +283,33 @@ def test_full_size_allen_cahn_step_matches_oracle(torch):
     e = rel(ug.cpu().numpy(), ur)
     say(f"   rel err {e:.2e}")
     assert e <= TOL64
+
+
+def test_graph_replay_equals_eager_steps(torch, monkeypatch):
+    """The FP64 step is captured into a HIP graph on its first call and replayed after
+    that; every replay, with eager torch work and synchronisation between replays, must
+    equal the eagerly enqueued step bit for bit (the kernels are deterministic)."""
+    say("[ark] graph replay vs eager, 8x8 p=10")
+    dt = 1e-3
+    tab = product_tableau()
+    g = hps.make_grid(0, 1, 0, 1, 8, 8, 10)
+    x, y = hps.hps_nodes(g)
+    n_int = hps.hps_num_nodes(g)[1]
+    wl = workloads.AllenCahn(workloads.rng_for(2))
+    cxx, cyy, cx, cy, c0 = wl.L_coeffs(x[:n_int], y[:n_int])
+    op = hps.hps_build(g, {k: torch.tensor(v, device="cuda") for k, v in dict(cxx=cxx, cyy=cyy, cx=cx, cy=cy).items()},
+                       tab["gamma"] * dt)
+    ctx_g = hps.ark_create(op, tab, dt, g=workloads.AllenCahn.gpoly)
+    ctx_e = hps.ark_create(op, tab, dt, g=workloads.AllenCahn.gpoly)
+    ug = torch.tensor(wl.u0(x, y), device="cuda")
+    ue = ug.clone()
+    scratch = torch.zeros(1 << 16, dtype=torch.float64, device="cuda")
+    for n in range(6):
+        monkeypatch.setenv("HPS_GRAPHS", "1")
+        hps.ark_step(ctx_g, n * dt, ug)
+        scratch.add_(1.0).mul_(0.5)            # eager work between replays
+        torch.cuda.synchronize()
+        monkeypatch.setenv("HPS_GRAPHS", "0")
+        hps.ark_step(ctx_e, n * dt, ue)
+        torch.cuda.synchronize()
+        assert torch.equal(ug, ue), n
