@@ -18,9 +18,7 @@
 using namespace hps;
 
 static int levels(hps_op *op, bool fp32, const double *jump, const double *dir, hipStream_t st) {
-    TRY(launch_levels_up(op, fp32, jump, st));
-    TRY(launch_levels_down(op, fp32, dir, st));
-    return HPS_OK;
+    return launch_levels(op, fp32, jump, dir, st);
 }
 
 static double ordered_bits_to_double(unsigned long long v) {

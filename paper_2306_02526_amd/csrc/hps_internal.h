@@ -200,8 +200,9 @@ struct LeafPhase {
     double *unew = nullptr;                    // LU_UPDATE
 };
 int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st);
-int launch_levels_up(const hps_op *op, bool fp32, const double *jump, hipStream_t st);
-int launch_levels_down(const hps_op *op, bool fp32, const double *dirichlet, hipStream_t st);
+// upward sweep over the levels, the root, then the downward sweep (jump and dirichlet
+// may be NULL)
+int launch_levels(const hps_op *op, bool fp32, const double *jump, const double *dirichlet, hipStream_t st);
 // step completion after the interior update: boundary data f(t + dt), then the interface
 // values from flux continuity along every grid line (reads the leaf edge-flux parts)
 int launch_interface_lines(const hps_op *op, double *u, const double *f_end, hipStream_t st);

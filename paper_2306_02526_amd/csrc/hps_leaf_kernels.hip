@@ -20,7 +20,7 @@
 
 namespace hps {
 
-constexpr int LPF = 8;    // operator loads issued ahead of each stream
+constexpr int LPF = 2;    // operator loads issued ahead of each stream
 constexpr int LUNR = 8;   // operator loads in flight in the streaming loop
 
 // Sum the G column-group partials of `rows` rows (LDS, [g][rows]) and call fin(row, y).
@@ -83,8 +83,8 @@ __device__ __forceinline__ double poly_g(const GPoly &g, double u) {
     return g.g0 + u * (g.g1 + u * (g.g2 + u * g.g3));
 }
 
-template <typename T>
-__global__ __launch_bounds__(NT) void k_leaf(LeafArgs a) {
+template <typename T, int DN, int UPM>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_leaf(LeafArgs a) {
     constexpr int VW = 16 / sizeof(T);
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[NT];
@@ -102,29 +102,29 @@ __global__ __launch_bounds__(NT) void k_leaf(LeafArgs a) {
     double *D2 = cv.take<double>(p * p);
     double *luv = cv.take<double>(q2);
     double *fv = cv.take<double>(q2);
-    const bool stream_down = a.down == DOWN_WRITE_U || a.down == DOWN_STAGE || a.down == DOWN_IR_ADD;
-    const bool stream_up = a.up == UP_BODY || a.up == UP_STAGE;
-    const bool need_L = a.down == DOWN_STAGE || a.down == DOWN_EVAL;
+    constexpr bool stream_down = DN == DOWN_WRITE_U || DN == DOWN_STAGE || DN == DOWN_IR_ADD;
+    constexpr bool stream_up = UPM == UP_BODY || UPM == UP_STAGE;
+    constexpr bool need_L = DN == DOWN_STAGE || DN == DOWN_EVAL;
     PanelStream<T, LPF, LUNR> ps;
-    if (stream_down) ps.start(reinterpret_cast<const T *>(a.sl.data) + (int64_t)leaf * a.sl.node_elems, a.sl.rp, a.sl.G, a.sl.S);
-    else if (stream_up) ps.start(reinterpret_cast<const T *>(a.ainv.data) + (int64_t)leaf * a.ainv.node_elems, a.ainv.rp, a.ainv.G, a.ainv.S);
+    if constexpr (stream_down) ps.start(reinterpret_cast<const T *>(a.sl.data) + (int64_t)leaf * a.sl.node_elems, a.sl.rp, a.sl.G, a.sl.S);
+    else if constexpr (stream_up) ps.start(reinterpret_cast<const T *>(a.ainv.data) + (int64_t)leaf * a.ainv.node_elems, a.ainv.rp, a.ainv.G, a.ainv.S);
     load_dmat(a.D, D, p * p);
     if (need_L) load_dmat(a.D2, D2, p * p);
 
     // ---------------- down phase ----------------
-    if (a.down != DOWN_NONE) {
+    if constexpr (DN != DOWN_NONE) {
         // particular solution w of this leaf, staged in LDS before the stream is consumed
         if (stream_down)
             for (int k = threadIdx.x; k < q2; k += NT) fv[k] = a.w_in[(int64_t)leaf * q2 + k];
         for (int k = threadIdx.x; k < p * p; k += NT) tile[k] = 0.0;
-        if (stream_down) {
+        if constexpr (stream_down) {
             const double *ubl = a.ub + (int64_t)leaf * nb;
             const int SG = a.sl.S * a.sl.G;
             for (int k = threadIdx.x; k < SG; k += NT) xs[k] = (T)(k < nb ? ubl[k] : 0.0);
             __syncthreads();
             for (int k = threadIdx.x; k < nb; k += NT) tile[edge_tile_pos(p, q, k / q, k % q)] = ubl[k];
             ps.finish(xs, part);
-            if (stream_up)
+            if constexpr (stream_up)
                 ps.start(reinterpret_cast<const T *>(a.ainv.data) + (int64_t)leaf * a.ainv.node_elems, a.ainv.rp,
                          a.ainv.G, a.ainv.S);
             __syncthreads();
@@ -140,7 +140,7 @@ __global__ __launch_bounds__(NT) void k_leaf(LeafArgs a) {
                 tile[edge_tile_pos(p, q, k / q, k % q)] = a.u_eval[edge_index(a.geo, li, lj, k / q, k % q)];
             __syncthreads();
         }
-        if (need_L) {
+        if constexpr (need_L) {
             for (int k = threadIdx.x; k < q2; k += NT) {
                 {
                     const int aa = k % q + 1, bb = k / q + 1;
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(NT) void k_leaf(LeafArgs a) {
                     a.F_out[base + k] = F;
                 }
             }
-        } else if (a.down == DOWN_WRITE_U || a.down == DOWN_IR_ADD) {
+        } else if constexpr (DN == DOWN_WRITE_U || DN == DOWN_IR_ADD) {
             double dmax = 0.0, umax = 0.0;
             const double *ubl = a.ub + (int64_t)leaf * nb;
             for (int k = threadIdx.x; k < q2 + nb; k += NT) {
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(NT) void k_leaf(LeafArgs a) {
                     v = ubl[k - q2];
                 }
                 if (!own) continue;
-                if (a.down == DOWN_WRITE_U) {
+                if (DN == DOWN_WRITE_U) {
                     a.u_out[gi] = v;
                 } else {
                     const double nu = a.u_out[gi] + v;
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(NT) void k_leaf(LeafArgs a) {
                     umax = fmax(umax, fabs(nu));
                 }
             }
-            if (a.down == DOWN_IR_ADD) {
+            if (DN == DOWN_IR_ADD) {
                 for (int off = 32; off > 0; off >>= 1) {
                     dmax = fmax(dmax, __shfl_xor(dmax, off));
                     umax = fmax(umax, __shfl_xor(umax, off));
@@ -219,8 +219,8 @@ __global__ __launch_bounds__(NT) void k_leaf(LeafArgs a) {
     }
 
     // ---------------- up phase ----------------
-    if (a.up == UP_NONE) return;
-    if (a.up == UP_UPDATE) {
+    if constexpr (UPM == UP_NONE) return;
+    if constexpr (UPM == UP_UPDATE) {
         // interior u^{n+1}; the newest stage's L u, F are in LDS
         const int last = a.nprev;
         for (int k = threadIdx.x; k < q2; k += NT) {
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(NT) void k_leaf(LeafArgs a) {
     for (int k = threadIdx.x; k < SG; k += NT) {
         double r = 0.0;
         if (k < q2) {
-            if (a.up == UP_BODY) {
+            if (UPM == UP_BODY) {
                 r = a.body[base + k];
             } else {
                 r = a.un[base + k];
@@ -345,10 +345,24 @@ int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st
     const size_t es = fp32 ? 4 : 8;
     const size_t pp = (size_t)op->p * op->p * 8, q2b = (size_t)op->q2 * 8;
     const size_t lds = carve_bytes({(size_t)a.xs_cap * es, (size_t)a.part_cap * es, pp, pp, pp, q2b, q2b});
-    if (fp32) hipLaunchKernelGGL(k_leaf<float>, dim3(op->nleaves), dim3(NT), lds, st, a);
-    else hipLaunchKernelGGL(k_leaf<double>, dim3(op->nleaves), dim3(NT), lds, st, a);
-    HPS_LAUNCHED();
-    return HPS_OK;
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(op->nleaves), dim3(NT), lds, st, a); };
+#define HPS_LEAF_CASE(DNV, UPV)                                                   \
+    if (ph.down == DNV && ph.up == UPV) {                                         \
+        if (fp32) go(k_leaf<float, DNV, UPV>);                                    \
+        else go(k_leaf<double, DNV, UPV>);                                        \
+        HPS_LAUNCHED();                                                           \
+        return HPS_OK;                                                            \
+    }
+    HPS_LEAF_CASE(DOWN_EVAL, UP_STAGE)
+    HPS_LEAF_CASE(DOWN_STAGE, UP_STAGE)
+    HPS_LEAF_CASE(DOWN_STAGE, UP_UPDATE)
+    HPS_LEAF_CASE(DOWN_EVAL, UP_UPDATE)
+    HPS_LEAF_CASE(DOWN_NONE, UP_BODY)
+    HPS_LEAF_CASE(DOWN_WRITE_U, UP_NONE)
+    HPS_LEAF_CASE(DOWN_IR_ADD, UP_NONE)
+#undef HPS_LEAF_CASE
+    hps_set_error("internal: unsupported leaf phase combination (%d, %d)", ph.down, ph.up);
+    return HPS_EINVAL;
 }
 
 }  // namespace hps

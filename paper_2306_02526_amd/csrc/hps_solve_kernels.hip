@@ -147,9 +147,13 @@ __global__ __launch_bounds__(NT) void k_level(LevelArgs a) {
         }
         xs[k] = (T)x;
     }
-    if (!UP && tile == 0 && chunk == 0) {
-        // the J1 / J2 parts of the children's boundary data are the parent's own
-        for (int m = threadIdx.x; m < a.n12; m += NT) {
+    if (!UP) {
+        // the J1 / J2 parts of the children's boundary data are the parent's own; the
+        // workgroups of the node copy one slice each
+        const int nblk_node = ntile * kch, me = tile * kch + chunk;
+        const int per = (a.n12 + nblk_node - 1) / nblk_node;
+        const int m1 = min(a.n12, (me + 1) * per);
+        for (int m = me * per + threadIdx.x; m < m1; m += NT) {
             const double v = down_input(a, node, m);
             if (m < a.n1) a.ubc[(int64_t)(2 * node) * a.nbc + a.a1[m]] = v;
             else a.ubc[(int64_t)(2 * node + 1) * a.nbc + a.b2[m - a.n1]] = v;
@@ -493,23 +497,95 @@ static LevelArgs level_args(const hps_op *op, int l, bool fp32, bool up) {
     return a;
 }
 
+// The root's upward and downward products in one kernel: with u_12 the Dirichlet data,
+// u_3 = S u_12 + X d needs, for each row tile, only that tile's rows of X and of S.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_root(LevelArgs up, LevelArgs dn) {
+    constexpr int VW = 16 / sizeof(T);
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT];
+    const int tile = blockIdx.x;
+    const int SG1 = up.pn.S * up.pn.G, SG2 = dn.pn.S * dn.pn.G;
+    Carve cv{smem};
+    T *xs1 = cv.take<T>(SG1);
+    T *xs2 = cv.take<T>(SG2);
+    T *part1 = cv.take<T>((size_t)up.pn.G * up.pn.rp * VW);
+    T *part2 = cv.take<T>((size_t)dn.pn.G * dn.pn.rp * VW);
+    PanelStream<T, PF, UNR> ps;
+    ps.start(reinterpret_cast<const T *>(up.pn.data) + (int64_t)tile * up.pn.tile_elems, up.pn.rp, up.pn.G, up.pn.S);
+    const int rows = up.pn.rp * VW;   // the same row tiling for X and S
+    const int myrow = tile * rows + threadIdx.x;
+    int64_t ia = -1, ib = -1;
+    if ((int)threadIdx.x < rows && myrow < dn.n3) {
+        ia = dn.a3[myrow];
+        ib = (int64_t)dn.nbc + dn.b3[myrow];
+    }
+    for (int k = threadIdx.x; k < SG1; k += NT) {
+        double x = 0.0;
+        if (k < up.n3) {
+            x = up.hc[(int64_t)up.nbc + up.b3[k]] - up.hc[up.a3[k]];
+            if (up.r3) x += up.r3[up.j3i[k]];
+        }
+        xs1[k] = (T)x;
+    }
+    for (int k = threadIdx.x; k < SG2; k += NT)
+        xs2[k] = (T)((k < dn.n12 && dn.dir) ? dn.dir[dn.root_map[k]] : 0.0);
+    {   // the children's J1 / J2 boundary data: one slice per workgroup
+        const int per = (dn.n12 + (int)gridDim.x - 1) / (int)gridDim.x;
+        const int m1 = min(dn.n12, (tile + 1) * per);
+        for (int m = tile * per + threadIdx.x; m < m1; m += NT) {
+            const double v = dn.dir ? dn.dir[dn.root_map[m]] : 0.0;
+            if (m < dn.n1) dn.ubc[dn.a1[m]] = v;
+            else dn.ubc[(int64_t)dn.nbc + dn.b2[m - dn.n1]] = v;
+        }
+    }
+    __syncthreads();
+    ps.finish(xs1, part1);
+    ps.start(reinterpret_cast<const T *>(dn.pn.data) + (int64_t)tile * dn.pn.tile_elems, dn.pn.rp, dn.pn.G, dn.pn.S);
+    ps.finish(xs2, part2);
+    __syncthreads();
+    // deterministic sums over the column groups of both products, then u_3 = S u_12 + X d
+    const int nsl1 = min(up.pn.G, NT / rows), nsl2 = min(dn.pn.G, NT / rows);
+    const int t = threadIdx.x, row = t % rows, sl = t / rows;
+    double y1 = 0.0, y2 = 0.0;
+    if (sl < nsl1) {
+        T y = T(0);
+        for (int gg = sl; gg < up.pn.G; gg += nsl1) y += part1[gg * rows + row];
+        y1 = (double)y;
+    }
+    if (sl < nsl2) {
+        T y = T(0);
+        for (int gg = sl; gg < dn.pn.G; gg += nsl2) y += part2[gg * rows + row];
+        y2 = (double)y;
+    }
+    red[t] = y1;
+    __syncthreads();
+    double w3 = 0.0;
+    if (t < rows)
+        for (int s2 = 0; s2 < nsl1; ++s2) w3 += red[s2 * rows + t];
+    __syncthreads();
+    red[t] = y2;
+    __syncthreads();
+    if (t < rows && myrow < dn.n3) {
+        double su = 0.0;
+        for (int s2 = 0; s2 < nsl2; ++s2) su += red[s2 * rows + t];
+        const double u3 = su + w3;
+        dn.ubc[ia] = u3;
+        dn.ubc[ib] = u3;
+    }
+}
+
 static size_t level_lds(const Panel &pn) {
     const size_t es = pn.vw == 2 ? 8 : 4;
     return carve_bytes({(size_t)pn.S * pn.G * es, (size_t)pn.G * pn.rp * pn.vw * es});
 }
 
-int launch_levels_up(const hps_op *op, bool fp32, const double *jump, hipStream_t st) {
-    ProfScope ps_(&op->prof, fp32 ? KF_LEVEL_UP32 : KF_LEVEL_UP64, st);
-    for (int l = op->L - 1; l >= 0; --l) {
-        LevelArgs a = level_args(op, l, fp32, true);
-        a.r3 = jump;
-        const Panel &pn = fp32 ? op->lv[l].xu32 : op->lv[l].xu64;
-        const unsigned nb = (unsigned)(op->lv[l].nodes * a.pn.ntile * a.pn.kch);
-        if (fp32) hipLaunchKernelGGL((k_level<float, true>), dim3(nb), dim3(NT), level_lds(pn), st, a);
-        else hipLaunchKernelGGL((k_level<double, true>), dim3(nb), dim3(NT), level_lds(pn), st, a);
-        HPS_LAUNCHED();
-    }
-    return HPS_OK;
+static bool root_fusable(const hps_op *op, bool fp32) {
+    if (op->L < 1) return false;
+    const Panel &x = fp32 ? op->lv[0].xu32 : op->lv[0].xu64;
+    const Panel &sp = fp32 ? op->lv[0].s32 : op->lv[0].s64;
+    return x.kch == 1 && sp.kch == 1 && x.ntile == sp.ntile && x.rp == sp.rp &&
+           level_lds(x) + level_lds(sp) <= 65536;
 }
 
 // single-leaf tree: the leaf boundary is the domain boundary
@@ -518,7 +594,20 @@ __global__ void k_root_leaf_ub(const double *dir, const int *root_map, double *u
     if (t < nb) ub[t] = dir ? dir[root_map[t]] : 0.0;
 }
 
-int launch_levels_down(const hps_op *op, bool fp32, const double *dirichlet, hipStream_t st) {
+int launch_levels(const hps_op *op, bool fp32, const double *jump, const double *dirichlet, hipStream_t st) {
+    const bool rootf = root_fusable(op, fp32);
+    {
+        ProfScope ps_(&op->prof, fp32 ? KF_LEVEL_UP32 : KF_LEVEL_UP64, st);
+        for (int l = op->L - 1; l >= (rootf ? 1 : 0); --l) {
+            LevelArgs a = level_args(op, l, fp32, true);
+            a.r3 = jump;
+            const Panel &pn = fp32 ? op->lv[l].xu32 : op->lv[l].xu64;
+            const unsigned nb = (unsigned)(op->lv[l].nodes * a.pn.ntile * a.pn.kch);
+            if (fp32) hipLaunchKernelGGL((k_level<float, true>), dim3(nb), dim3(NT), level_lds(pn), st, a);
+            else hipLaunchKernelGGL((k_level<double, true>), dim3(nb), dim3(NT), level_lds(pn), st, a);
+            HPS_LAUNCHED();
+        }
+    }
     ProfScope ps_(&op->prof, fp32 ? KF_LEVEL_DOWN32 : KF_LEVEL_DOWN64, st);
     if (op->L == 0) {
         hipLaunchKernelGGL(k_root_leaf_ub, dim3(1), dim3(NT), 0, st, dirichlet, (const int *)op->root_map,
@@ -526,7 +615,18 @@ int launch_levels_down(const hps_op *op, bool fp32, const double *dirichlet, hip
         HPS_LAUNCHED();
         return HPS_OK;
     }
-    for (int l = 0; l < op->L; ++l) {
+    if (rootf) {
+        LevelArgs up = level_args(op, 0, fp32, true), dn = level_args(op, 0, fp32, false);
+        up.r3 = jump;
+        dn.dir = dirichlet;
+        const Panel &x = fp32 ? op->lv[0].xu32 : op->lv[0].xu64;
+        const Panel &sp = fp32 ? op->lv[0].s32 : op->lv[0].s64;
+        const size_t lds = level_lds(x) + level_lds(sp) + 32;
+        if (fp32) hipLaunchKernelGGL(k_root<float>, dim3(x.ntile), dim3(NT), lds, st, up, dn);
+        else hipLaunchKernelGGL(k_root<double>, dim3(x.ntile), dim3(NT), lds, st, up, dn);
+        HPS_LAUNCHED();
+    }
+    for (int l = rootf ? 1 : 0; l < op->L; ++l) {
         LevelArgs a = level_args(op, l, fp32, false);
         a.dir = dirichlet;
         const Panel &pn = fp32 ? op->lv[l].s32 : op->lv[l].s64;

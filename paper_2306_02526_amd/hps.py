@@ -11,7 +11,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libhps.so")
+LIB_PATH = os.environ.get("HPS_LIB", os.path.join(HERE, "libhps.so"))
 
 HPS_FP64 = 0
 HPS_FP32_IR = 1
