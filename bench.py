@@ -28,6 +28,17 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 
 
+def leaf_kernel_hash():
+    """sha256 of the sources the fused per-leaf kernel is compiled from; stored counter
+    traffic is only reported while it matches."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("hps_leaf_kernels.hip", "hps_device.h", "hps_internal.h"):
+        with open(os.path.join(ROOT, "paper_2306_02526_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -45,7 +56,39 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stage-solves", type=int, default=3)
+    ap.add_argument("--counter-run", action="store_true",
+                    help="short run for hardware-counter passes: build, 2 steps, then a plain "
+                         "1 GiB device copy whose counters calibrate the byte counts")
     return ap.parse_args()
+
+
+def counter_run(args):
+    """Build, two FP64 steps and a plain 1 GiB device-to-device copy (the copy's
+    FETCH_SIZE / WRITE_SIZE per byte moved calibrates the counters)."""
+    import torch
+
+    from paper_2306_02526_amd import hps, workloads
+    from paper_2306_02526_amd.tableau import ark436l2sa
+
+    dev = torch.device("cuda:0")
+    n, p, dt = args.n, args.p, args.dt
+    tab = ark436l2sa()
+    g = hps.make_grid(0.0, 1.0, 0.0, 1.0, n, n, p)
+    N, n_int, _, _ = hps.hps_num_nodes(g)
+    x, y = hps.hps_nodes(g)
+    wl = workloads.AllenCahn(workloads.rng_for(2))
+    cxx, cyy, cx, cy, _ = wl.L_coeffs(x[:n_int], y[:n_int])
+    coefs = {k: torch.tensor(v, device=dev) for k, v in dict(cxx=cxx, cyy=cyy, cx=cx, cy=cy).items()}
+    op = hps.hps_build(g, coefs, tab["gamma"] * dt, hps.HPS_FP64)
+    ctx = hps.ark_create(op, tab, dt, g=workloads.AllenCahn.gpoly)
+    u = torch.tensor(wl.u0(x, y), device=dev)
+    for k in range(2):
+        hps.ark_step(ctx, k * dt, u)
+    src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log("counter run done: 2 steps, 1 GiB copy")
 
 
 def leaf_down_up_algorithmic_bytes(n_leaves, q, stages, elem_bytes):
@@ -69,6 +112,9 @@ def main():
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
+    if args.counter_run:
+        counter_run(args)
+        return
     import numpy as np
     import torch
 
@@ -136,7 +182,7 @@ def main():
     if os.path.exists(tr_path):
         try:
             tr = json.load(open(tr_path))
-            if tr.get("workload") == f"allen_cahn_n{n}_p{p}" and tr.get("kernel_hash") is not None:
+            if tr.get("workload") == f"allen_cahn_n{n}_p{p}" and tr.get("kernel_hash") == leaf_kernel_hash():
                 traffic = tr.get("bytes_per_launch")
         except Exception:
             traffic = None

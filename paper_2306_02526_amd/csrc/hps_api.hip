@@ -157,6 +157,9 @@ Panel plan_panel(int R, int C, int vw, int nodes, int rp_max, int min_wg) {
     if (min_wg > 0 && (int64_t)nodes * p.ntile < min_wg)
         p.ntile = (int)std::min<int64_t>(RV, (min_wg + nodes - 1) / nodes);
     p.rp = (RV + p.ntile - 1) / p.ntile;
+    // level panels: at most 16 loads per lane, so a workgroup issues its whole block up front
+    if (min_wg > 0)
+        while (p.rp > 1 && (int64_t)(C + NT / p.rp - 1) / (NT / p.rp) > 16) p.rp = (p.rp + 1) / 2;
     p.ntile = (RV + p.rp - 1) / p.rp;
     const int Gmax = std::max(1, NT / p.rp);
     // column groups: fewest padded columns, then most groups

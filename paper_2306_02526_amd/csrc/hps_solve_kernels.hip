@@ -18,7 +18,8 @@
 
 namespace hps {
 
-constexpr int PF = 8;    // operator loads issued before the input gather
+constexpr int PF = 16;   // operator loads issued before the input gather (level panels keep S <= 16,
+                         // so a workgroup's whole operator block is in flight during the gather)
 constexpr int UNR = 8;   // operator loads in flight in the streaming loop
 
 // L u at interior node k of the tile: cxx u_xx + cyy u_yy + cx u_x + cy u_y + c0 u (eq. 3
