@@ -16,6 +16,7 @@ timed on a bounded sample on this host.
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
 import argparse
+import math
 import json
 import os
 import sys
@@ -56,6 +57,12 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stage-solves", type=int, default=3)
+    ap.add_argument("--workload", default="allen_cahn", choices=["allen_cahn", "batched", "serving"],
+                    help="allen_cahn: the single-problem benchmark (default); batched: 256 seeded "
+                         "problems stepped together; serving: Poisson job arrivals on the server")
+    ap.add_argument("--problems", type=int, default=256, help="batched: number of problems")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
+    ap.add_argument("--window", type=float, default=2.0, help="serving: seconds of arrivals")
     ap.add_argument("--counter-run", action="store_true",
                     help="short run for hardware-counter passes: build, 2 steps, then a plain "
                          "1 GiB device copy whose counters calibrate the byte counts")
@@ -114,6 +121,12 @@ def main():
         sys.exit(2)
     if args.counter_run:
         counter_run(args)
+        return
+    if args.workload == "batched":
+        batched_run(args)
+        return
+    if args.workload == "serving":
+        serving_run(args)
         return
     import numpy as np
     import torch
@@ -277,6 +290,165 @@ def main():
         "fp32_ir": fp32,
         "cpu_baseline": cpu,
     }
+    print(json.dumps(out), flush=True)
+
+
+def _mix_problem(torch, m, dev):
+    """Device data of one problem of the batched recipe."""
+    from paper_2306_02526_amd import hps, workloads
+    from paper_2306_02526_amd.tableau import ark436l2sa
+    tab = ark436l2sa()
+    g = hps.make_grid(*m["domain"], m["n1"], m["n2"], m["p"])
+    N, n_int, _, _ = hps.hps_num_nodes(g)
+    x, y = hps.hps_nodes(g)
+    pr = m["problem"]
+    cxx, cyy, cx, cy, c0 = pr.L_coeffs(x[:n_int], y[:n_int])
+    coefs = {k: torch.tensor(v, device=dev) for k, v in dict(cxx=cxx, cyy=cyy, cx=cx, cy=cy).items()}
+    heat = m["kind"] == "heat"
+    u0 = torch.tensor(pr.exact(0.0, x, y) if heat else pr.u0(x, y), device=dev)
+    qsp = torch.tensor(pr.q_space(x[:n_int], y[:n_int]), device=dev) if heat else None
+    return dict(grid=g, coefs=coefs, u0=u0, q_space=qsp, heat=heat, tab=tab,
+                dt=m["gamma_dt"] / tab["gamma"], gpoly=None if heat else workloads.AllenCahn.gpoly)
+
+
+def batched_run(args):
+    """The batched workload: args.problems seeded problems (leaves per side 8..64, p 8/12/16,
+    gamma*dt 1e-3/1e-2, heat or Allen-Cahn), built once, then args.steps steps of every
+    problem per ark_step_batched call.  Prints one JSON line."""
+    import torch
+
+    from paper_2306_02526_amd import hps, workloads
+    dev = torch.device("cuda:0")
+    mix = workloads.batched_mix(n_problems=args.problems)
+    probs, ctxs, us = [], [], []
+    op_bytes = 0
+    t0 = time.perf_counter()
+    for m in mix:
+        d = _mix_problem(torch, m, dev)
+        op = hps.hps_build(d["grid"], d["coefs"], m["gamma_dt"], hps.HPS_FP64)
+        op_bytes += op.bytes()[1]
+        ctxs.append(hps.ark_create(op, d["tab"], d["dt"], g=d["gpoly"]))
+        us.append(d["u0"].clone())
+        probs.append(d)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    log(f"batched: {len(mix)} problems built in {setup_s:.1f} s, operators {op_bytes / 1e9:.1f} GB")
+    qsp = [d["q_space"] for d in probs]
+    s = probs[0]["tab"]["s"]
+    c = probs[0]["tab"]["c"]
+
+    def step(k):
+        ts = [k * d["dt"] for d in probs]
+        qt = [[math.exp(-(t + ci * d["dt"])) for ci in c] if d["heat"] else None for d, t in zip(probs, ts)]
+        hps.ark_step_batched(ctxs, ts, us, q_space=qsp, q_time=qt)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(args.warmup + k)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    # the same steps one problem at a time on one stream, for comparison
+    t1 = time.perf_counter()
+    for k in range(args.steps):
+        for b, d in enumerate(probs):
+            t = (args.warmup + args.steps + k) * d["dt"]
+            qt = [math.exp(-(t + ci * d["dt"])) for ci in c] if d["heat"] else None
+            hps.ark_step(ctxs[b], t, us[b], q_space=qsp[b], q_time=qt)
+    torch.cuda.synchronize()
+    el_seq = time.perf_counter() - t1
+    finite = all(bool(torch.isfinite(u).all()) for u in us)
+    ss = (s - 1) * len(probs) * args.steps
+    out = {"metric": "stage-solves/s, batched mix", "value": round(ss / el, 1), "unit": "stage-solves/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * el / args.steps, 3),
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"batched_mix_{len(probs)}", "problems": len(probs),
+                      "streams": hps.hps_batch_streams()},
+           "problem_steps_per_s": round(len(probs) * args.steps / el, 1),
+           "operator_GBps": round(op_bytes * (s - 1) * args.steps / el / 1e9, 1),
+           "operator_bytes": op_bytes, "setup_s": round(setup_s, 1),
+           "one_stream_sequential_stage_solves_per_s": round(ss / el_seq, 1), "finite": finite}
+    print(json.dumps(out), flush=True)
+
+
+def serving_run(args):
+    """Serving: 16 seeded keys from the batched recipe; jobs arrive as a Poisson process at
+    args.rate per second for args.window seconds, each with a key drawn uniformly and
+    steps ~ U{50..500}.  First a burst of jobs measures the saturation rate.  Prints one
+    JSON line with throughput and latency percentiles."""
+    import numpy as np
+    import torch
+
+    from paper_2306_02526_amd import hps, workloads
+    dev = torch.device("cuda:0")
+    keys = [_mix_problem(torch, m, dev) for m in workloads.batched_mix(n_problems=16)]
+    rng = workloads.rng_for(5, 1000)
+    stream = torch.cuda.current_stream()
+    srv = hps.Server(max_active=128)
+
+    def submit(kidx, steps):
+        d = keys[kidx]
+        u = d["u0"].clone()
+        extra = dict(q_space=d["q_space"], q_amp=1.0, q_rate=-1.0) if d["heat"] else {}
+        return srv.submit(d["grid"], kidx, d["coefs"], d["tab"], d["dt"], u, steps, g=d["gpoly"],
+                          stream=stream, **extra)
+
+    def drain(ids):
+        lat, fin = [], []
+        for j in ids:
+            st = srv.wait(j)
+            assert st["state"] == hps.SRV_DONE, st
+            lat.append(st["finish_s"] - st["submit_s"])
+            fin.append(st["finish_s"])
+            srv.release(j)
+        return np.array(lat), np.array(fin)
+
+    # warm the operator cache with one short job per key
+    drain([submit(k, 1) for k in range(len(keys))])
+    # saturation: a burst of jobs submitted at once
+    nb = 48
+    t0 = time.perf_counter()
+    ids = [submit(int(rng.integers(0, len(keys))), int(rng.integers(50, 501))) for _ in range(nb)]
+    lat_b, fin_b = drain(ids)
+    sat = nb / (time.perf_counter() - t0)
+    log(f"serving: saturation {sat:.2f} jobs/s from a burst of {nb}")
+
+    def poisson(rate, window):
+        arr, t = [], 0.0
+        while True:
+            t += float(rng.exponential(1.0 / rate))
+            if t > window:
+                return arr
+            arr.append((t, int(rng.integers(0, len(keys))), int(rng.integers(50, 501))))
+
+    def run(rate, window):
+        arr = poisson(rate, window)
+        t0 = time.perf_counter()
+        ids = []
+        for t, k, n in arr:
+            dly = t - (time.perf_counter() - t0)
+            if dly > 0:
+                time.sleep(dly)
+            ids.append(submit(k, n))
+        backlog = sum(1 for j in ids if srv.poll(j)["state"] == hps.SRV_QUEUED)
+        lat, fin = drain(ids)
+        span = time.perf_counter() - t0
+        return {"rate": rate, "window_s": window, "jobs": len(ids), "p50_s": round(float(np.percentile(lat, 50)), 3),
+                "p99_s": round(float(np.percentile(lat, 99)), 3), "completed_per_s": round(len(ids) / span, 2),
+                "queued_at_window_end": backlog, "stable": bool(backlog <= 2)}
+
+    r_low = run(0.8 * sat, max(args.window, 5.0))
+    log(f"serving at 0.8x saturation: {r_low}")
+    r_hi = run(args.rate, args.window)
+    log(f"serving at {args.rate}/s: {r_hi}")
+    st = srv.stats()
+    srv.close()
+    out = {"metric": "jobs/s at saturation (served ARK integrations); p50/p99 latency", "value": round(sat, 2),
+           "unit": "jobs/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "serving_16_keys_steps_50_500", "keys": len(keys), "burst": nb},
+           "at_0.8x_saturation": r_low, "at_rate": r_hi, "server_stats": st}
     print(json.dumps(out), flush=True)
 
 

@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhps.so")
 SOURCES = ["hps_solve_kernels.hip", "hps_leaf_kernels.hip", "hps_build_kernels.hip", "hps_api.hip",
-           "hps_drivers.hip"]
+           "hps_drivers.hip", "hps_batch.hip", "hps_serve.hip"]
+OBJDIR = os.path.join(HERE, "_build")
 
 
 def hipcc():
@@ -22,23 +23,38 @@ def hipcc():
     return "hipcc"
 
 
-def build(verbose=False, out=LIB):
-    tmp = out + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-fvisibility=hidden",
-           # packed FP32 instructions stay off (see the design notes)
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-command-line-argument",
-           "-I", INCLUDE, "-I", CSRC]
-    cmd += [os.path.join(CSRC, s) for s in SOURCES]
-    cmd += ["-o", tmp]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
+         # hipcc forms packed FP32 instructions from plain float code; keep them off
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wno-unused-command-line-argument", "-I", INCLUDE, "-I", CSRC]
+
+
+def _run(cmd, what):
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libhps.so")
-    if verbose and r.stderr.strip():
-        sys.stderr.write(r.stderr)
+        raise RuntimeError(f"hipcc failed: {what}")
+    return r.stderr
+
+
+def build(verbose=False, out=LIB):
+    """Compile every source to an object (in parallel), then link libhps.so."""
+    from concurrent.futures import ThreadPoolExecutor
+    os.makedirs(OBJDIR, exist_ok=True)
+    objs = [os.path.join(OBJDIR, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+    cmds = [[hipcc()] + FLAGS + ["-c", os.path.join(CSRC, s), "-o", o] for s, o in zip(SOURCES, objs)]
+    if verbose:
+        for c in cmds:
+            print(" ".join(c), flush=True)
+    workers = max(1, min(len(cmds), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(workers) as ex:
+        errs = list(ex.map(lambda c: _run(c, c[-3]), cmds))
+    tmp = out + ".tmp"
+    _run([hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", tmp], "link")
+    if verbose:
+        for e in errs:
+            if e.strip():
+                sys.stderr.write(e)
     os.replace(tmp, out)
     return out
 

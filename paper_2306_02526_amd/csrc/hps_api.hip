@@ -162,10 +162,11 @@ Panel plan_panel(int R, int C, int vw, int nodes, int rp_max, int min_wg) {
         while (p.rp > 1 && (int64_t)(C + NT / p.rp - 1) / (NT / p.rp) > 16) p.rp = (p.rp + 1) / 2;
     p.ntile = (RV + p.rp - 1) / p.rp;
     const int Gmax = std::max(1, NT / p.rp);
-    // column groups: fewest padded columns, then most groups
+    // column groups: fewest padded columns, then most groups (narrow panels may leave
+    // lanes idle rather than stream padding)
     int bestG = Gmax;
     int64_t bestPad = -1;
-    for (int G = Gmax; G >= std::max(1, Gmax / 2); --G) {
+    for (int G = Gmax; G >= std::max(1, std::min(Gmax / 2, C)); --G) {
         const int64_t pad = (int64_t)((C + G - 1) / G) * G - C;
         if (bestPad < 0 || pad < bestPad) {
             bestPad = pad;
@@ -180,6 +181,30 @@ Panel plan_panel(int R, int C, int vw, int nodes, int rp_max, int min_wg) {
     p.tile_elems = (int64_t)p.S * p.G * p.rp * vw;
     p.node_elems = (int64_t)p.ntile * p.kch * p.tile_elems;
     return p;
+}
+
+// Bytes of the packed operators hps_build stores for a grid, from the same panel plans
+// (the tree splits the longer side of each box, ties with a vertical cut).
+int64_t plan_operator_bytes(const hps_grid &g, int flags) {
+    const int q = g.p - 2, q2 = q * q, nl = g.n1 * g.n2;
+    const bool ir = (flags & HPS_FP32_IR) != 0;
+    int64_t bytes = plan_panel(q2, q2, 2, nl, 256, 0).bytes() + plan_panel(q2, 4 * q, 2, nl, 256, 0).bytes();
+    if (ir) bytes += plan_panel(q2, q2, 4, nl, 256, 0).bytes() + plan_panel(q2, 4 * q, 4, nl, 256, 0).bytes();
+    int w = g.n1, h = g.n2, nodes = 1;
+    bool root = true;
+    while (w * h > 1) {
+        const bool vert = w >= h;
+        const int n3 = q * (vert ? h : w), n12 = 2 * q * (w + h);
+        const int rows = root ? n3 : n3 + n12;
+        bytes += plan_panel(rows, n3, 2, nodes, 64, 1024).bytes() + plan_panel(n3, n12, 2, nodes, 64, 1024).bytes();
+        if (ir)
+            bytes += plan_panel(rows, n3, 4, nodes, 64, 1024).bytes() + plan_panel(n3, n12, 4, nodes, 64, 1024).bytes();
+        if (vert) w /= 2;
+        else h /= 2;
+        nodes *= 2;
+        root = false;
+    }
+    return bytes;
 }
 }  // namespace hps
 
@@ -602,6 +627,12 @@ static int build_impl(hps_op *op, const hps_coeffs *co, hipStream_t st) {
         hps_set_error("a zero pivot occurred while inverting a leaf or merge matrix");
         return HPS_ESINGULAR;
     }
+    // the host-side size plan (used to admit operators into a server's cache) must match
+    if (op->operator_bytes != plan_operator_bytes(op->grid, op->flags)) {
+        hps_set_error("internal: operator size plan %lld != allocated %lld",
+                      (long long)plan_operator_bytes(op->grid, op->flags), (long long)op->operator_bytes);
+        return HPS_EDEVICE;
+    }
     return HPS_OK;
 }
 
@@ -708,6 +739,7 @@ extern "C" int ark_create(hps_op *op, const ark_tableau *tab, double dt, const a
     };
     if (int rc = dev_alloc<double>(nullptr, &c->Lu, (int64_t)s * op->n_int, false)) return fail(rc);
     if (int rc = dev_alloc<double>(nullptr, &c->F, (int64_t)s * op->n_int, false)) return fail(rc);
+    if (int rc = dev_alloc<double>(nullptr, &c->qt_dev, s, false)) return fail(rc);
     if (op->flags & HPS_FP32_IR) {
         if (int rc = dev_alloc<double>(nullptr, &c->rhs, op->n_int, false)) return fail(rc);
         if (int rc = dev_alloc<double>(nullptr, &c->stage_u, op->N, false)) return fail(rc);
@@ -721,7 +753,7 @@ extern "C" void ark_free(ark_ctx *c) {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    for (double *p : {c->Lu, c->F, c->rhs, c->stage_u})
+    for (double *p : {c->Lu, c->F, c->rhs, c->stage_u, c->qt_dev})
         if (p) (void)hipFree(p);
     delete c;
 }

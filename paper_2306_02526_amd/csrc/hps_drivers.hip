@@ -123,8 +123,10 @@ static int enqueue_step(ark_ctx *c, double *u, const double *q_stages, const dou
         ph.q_src = nullptr;
         if (q_stages) ph.q_src = q_stages + (int64_t)i * n;
         else if (q_space) {
+            // the time factors are written to c->qt_dev before the step (outside any
+            // captured graph), so a replayed step picks up new values
             ph.q_src = q_space;
-            ph.q_scale = q_time[i];
+            ph.q_scale_ptr = c->qt_dev + i;
         }
     };
     auto set_rhs = [&](LeafPhase &ph, int i) {   // up phase: right-hand side of stage i
@@ -206,19 +208,14 @@ extern "C" int ark_step(ark_ctx *c, double t, double *u, const double *q_stages,
     TRY(check_device_ptr(f_stages, "f_stages"));
     hipStream_t st = (hipStream_t)stream;
     hps_op *op = c->op;
+    if (q_space) TRY(launch_set_values(c->qt_dev, q_time, c->s, st));
     // The FP64 step has no host synchronisation, so it is captured once into a HIP graph
-    // and replayed while its arguments (pointers, stream, source scales) repeat.  The
+    // and replayed while its array arguments repeat.  The
     // refinement loop of FP32_IR waits on the host and runs eagerly; so does a profiled step.
     const char *env = getenv("HPS_GRAPHS");
     const bool graphs = !(env && env[0] == '0') && !(op->flags & HPS_FP32_IR) && !op->prof.on;
     if (!graphs) return enqueue_step(c, u, q_stages, q_space, q_time, f_stages, st);
-    std::vector<uintptr_t> key = {(uintptr_t)u, (uintptr_t)q_stages, (uintptr_t)q_space, (uintptr_t)f_stages};
-    if (q_space)
-        for (int i = 0; i < c->s; ++i) {
-            uint64_t bits;
-            std::memcpy(&bits, &q_time[i], sizeof(bits));
-            key.push_back((uintptr_t)bits);
-        }
+    const std::vector<uintptr_t> key = {(uintptr_t)u, (uintptr_t)q_stages, (uintptr_t)q_space, (uintptr_t)f_stages};
     if (!c->gexec || key != c->gkey) {
         if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
         if (c->graph) (void)hipGraphDestroy(c->graph);

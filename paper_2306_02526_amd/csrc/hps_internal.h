@@ -41,6 +41,7 @@ struct Panel {
 // vectors per tile (the leaf kernels need the whole matrix in one tile); min_wg asks
 // for at least that many workgroups per sweep (column chunks are added to reach it).
 Panel plan_panel(int R, int C, int vw, int nodes, int rp_max, int min_wg);
+int64_t plan_operator_bytes(const hps_grid &g, int flags);   // what hps_build's panels take
 
 // One internal level of the tree (level 0 = root), all nodes of the same shape.
 struct Level {
@@ -121,11 +122,12 @@ struct ark_ctx {
     double *Lu = nullptr, *F = nullptr;   // device [s][n_int] each
     double *rhs = nullptr;                // device [n_int] (FP32_IR stage right-hand side)
     double *stage_u = nullptr;            // device [N] (FP32_IR stage solution)
+    double *qt_dev = nullptr;             // device [s]: time factors of a separable source
     // the FP64 step is replayed from a captured HIP graph while its arguments repeat
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     hipStream_t cap_stream = nullptr;     // private stream used only for the capture
-    std::vector<uintptr_t> gkey;          // pointers, stream and source scales of the capture
+    std::vector<uintptr_t> gkey;          // array arguments of the captured step
 };
 
 // ---------------------------------------------------------------------------------------
@@ -189,6 +191,7 @@ struct LeafPhase {
     double *Lu_out = nullptr, *F_out = nullptr;  // LD_STAGE / LD_EVAL
     const double *q_src = nullptr;
     double q_scale = 0.0;
+    const double *q_scale_ptr = nullptr;   // device scalar; when set it replaces q_scale
     GPoly g{0, 0, 0, 0, 0};
     // up
     const double *body = nullptr;              // LU_BODY
@@ -210,6 +213,7 @@ int launch_residual(const hps_op *op, const double *u, const double *rhs, const 
                     double *r_int, double *r3, hipStream_t st);
 int launch_scatter_boundary(const hps_op *op, const double *f, double *u, hipStream_t st);
 int launch_zero(double *p, int64_t n, hipStream_t st);
+int launch_set_values(double *dst, const double *vals, int n, hipStream_t st);   // n <= 8, vals on the host
 
 // build --------------------------------------------------------------------------------
 int launch_leaf_assemble(const hps_op *op, double *W, hipStream_t st);

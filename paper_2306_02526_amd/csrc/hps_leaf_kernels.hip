@@ -64,6 +64,7 @@ struct LeafArgs {
     double *Lu_out, *F_out;      // DOWN_STAGE / DOWN_EVAL: L u_i, F_i (interior, canonical)
     const double *q_src;
     double q_scale;
+    const double *q_scale_ptr;   // device scalar replacing q_scale when set
     GPoly g;
     unsigned long long *norms;   // DOWN_IR_ADD: max|delta|, max|u|
     // up phase
@@ -141,6 +142,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
             __syncthreads();
         }
         if constexpr (need_L) {
+            const double qs = a.q_scale_ptr ? *a.q_scale_ptr : a.q_scale;
             for (int k = threadIdx.x; k < q2; k += NT) {
                 {
                     const int aa = k % q + 1, bb = k / q + 1;
@@ -158,7 +160,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
                     const double *cf = a.coef + base + k;
                     const double Lu = cf[0] * uxx + cf[n_int] * uyy + cf[2 * n_int] * ux + cf[3 * n_int] * uy +
                                       cf[4 * n_int] * u;
-                    const double F = (a.q_src ? a.q_scale * a.q_src[base + k] : 0.0) + poly_g(a.g, u);
+                    const double F = (a.q_src ? qs * a.q_src[base + k] : 0.0) + poly_g(a.g, u);
                     luv[k] = Lu;
                     fv[k] = F;
                     a.Lu_out[base + k] = Lu;
@@ -326,6 +328,7 @@ int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st
     a.F_out = ph.F_out;
     a.q_src = ph.q_src;
     a.q_scale = ph.q_scale;
+    a.q_scale_ptr = ph.q_scale_ptr;
     a.g = ph.g;
     a.norms = reinterpret_cast<unsigned long long *>(op->ir_norms);
     a.body = ph.body;

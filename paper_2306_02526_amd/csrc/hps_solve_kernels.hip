@@ -426,6 +426,15 @@ __global__ void k_interface_lines(LineArgs a) {
     }
 }
 
+// up to 8 host values handed over as a kernel argument (no host buffer stays in use)
+struct Values8 {
+    double v[8];
+};
+
+__global__ void k_set_values(double *dst, Values8 v, int n) {
+    if ((int)threadIdx.x < n) dst[threadIdx.x] = v.v[threadIdx.x];
+}
+
 __global__ void k_zero(double *p, int64_t n) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n) p[k] = 0.0;
@@ -682,6 +691,19 @@ int launch_interface_lines(const hps_op *op, double *u, const double *f_end, hip
 int launch_scatter_boundary(const hps_op *op, const double *f, double *u, hipStream_t st) {
     hipLaunchKernelGGL(k_scatter_boundary, dim3(nblk(op->n_bdry)), dim3(NT), 0, st, f,
                        (const int *)op->bnd_glob, u, op->n_bdry);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+int launch_set_values(double *dst, const double *vals, int n, hipStream_t st) {
+    if (n <= 0) return HPS_OK;
+    if (n > 8) {
+        hps_set_error("internal: at most 8 values per launch_set_values");
+        return HPS_EINVAL;
+    }
+    Values8 v{};
+    for (int i = 0; i < n; ++i) v.v[i] = vals[i];
+    hipLaunchKernelGGL(k_set_values, dim3(1), dim3(64), 0, st, dst, v, n);
     HPS_LAUNCHED();
     return HPS_OK;
 }

@@ -18,10 +18,11 @@ HPS_FP32_IR = 1
 ERRORS = {-1: "HPS_EINVAL", -2: "HPS_ENOMEM", -3: "HPS_EDEVICE", -4: "HPS_ESINGULAR",
           -5: "HPS_ENOTCONVERGED"}
 
-# every entry point declared in include/hps.h
+# every entry point declared in include/hps.h, include/hps_batch.h and include/hps_serve.h
 EXPORTED = ["hps_last_error", "hps_num_nodes", "hps_nodes", "hps_build", "hps_op_bytes",
             "hps_solve", "hps_free", "hps_profile_enable", "hps_profile_read", "ark_create", "ark_step", "ark_stage_solves_per_step",
-            "ark_free"]
+            "ark_free", "hps_solve_batched", "ark_step_batched", "hps_batch_streams",
+            "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_release", "srv_get_stats", "srv_destroy"]
 
 
 class HPSError(RuntimeError):
@@ -53,6 +54,31 @@ class ArkG(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("g0", ctypes.c_double), ("g1", ctypes.c_double),
                 ("g2", ctypes.c_double), ("g3", ctypes.c_double)]
 
+
+class SrvConfig(ctypes.Structure):
+    _fields_ = [("cache_bytes", ctypes.c_int64), ("max_active", ctypes.c_int32)]
+
+
+class SrvJob(ctypes.Structure):
+    _fields_ = [("grid", HpsGrid), ("coef_key", ctypes.c_uint64), ("coeffs", HpsCoeffs),
+                ("flags", ctypes.c_int32), ("tab", ArkTableau), ("dt", ctypes.c_double), ("g", ArkG),
+                ("t0", ctypes.c_double), ("steps", ctypes.c_int32), ("u", ctypes.c_void_p),
+                ("q_space", ctypes.c_void_p), ("q_amp", ctypes.c_double), ("q_rate", ctypes.c_double)]
+
+
+class SrvStatus(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("error", ctypes.c_int32), ("steps_done", ctypes.c_int32),
+                ("cache_hit", ctypes.c_int32), ("submit_s", ctypes.c_double), ("start_s", ctypes.c_double),
+                ("finish_s", ctypes.c_double)]
+
+
+class SrvStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "failed", "builds", "cache_hits",
+                                              "evictions", "cached_ops", "cached_bytes", "iterations",
+                                              "job_steps")]
+
+
+SRV_QUEUED, SRV_ACTIVE, SRV_DONE, SRV_FAILED = 0, 1, 2, 3
 
 _lib = None
 
@@ -93,6 +119,26 @@ def lib():
     L.ark_stage_solves_per_step.argtypes = [vp]
     L.ark_free.restype = None
     L.ark_free.argtypes = [vp]
+    L.hps_solve_batched.restype = i32
+    L.hps_solve_batched.argtypes = [P(vp), i32, P(vp), P(vp), P(vp), P(vp), vp, P(HpsInfo)]
+    L.ark_step_batched.restype = i32
+    L.ark_step_batched.argtypes = [P(vp), i32, P(dbl), P(vp), P(vp), P(vp), P(vp), P(vp), vp]
+    L.hps_batch_streams.restype = i32
+    L.hps_batch_streams.argtypes = []
+    L.srv_create.restype = i32
+    L.srv_create.argtypes = [P(SrvConfig), P(vp)]
+    L.srv_submit.restype = i32
+    L.srv_submit.argtypes = [vp, P(SrvJob), vp, P(i64)]
+    L.srv_poll.restype = i32
+    L.srv_poll.argtypes = [vp, i64, P(SrvStatus)]
+    L.srv_wait.restype = i32
+    L.srv_wait.argtypes = [vp, i64, P(SrvStatus)]
+    L.srv_release.restype = i32
+    L.srv_release.argtypes = [vp, i64]
+    L.srv_get_stats.restype = i32
+    L.srv_get_stats.argtypes = [vp, P(SrvStats)]
+    L.srv_destroy.restype = None
+    L.srv_destroy.argtypes = [vp]
     _lib = L
     return L
 
@@ -264,3 +310,141 @@ def ark_step(ctx, t, u, q_stages=None, q_space=None, q_time=None, f_stages=None,
 
 def ark_stage_solves_per_step(ctx):
     return _check(lib().ark_stage_solves_per_step(ctx.handle))
+
+
+# ---------------------------------------------------------------------------------------
+# batched entry points (include/hps_batch.h)
+# ---------------------------------------------------------------------------------------
+def _ptr_array(items, sizes, name, required=False):
+    """Host array of device pointers (None for an absent list or entry)."""
+    if items is None:
+        if required:
+            raise ValueError(f"{name} is required")
+        return None
+    if len(items) != len(sizes):
+        raise ValueError(f"{name} needs one entry per problem")
+    arr = (ctypes.c_void_p * len(items))()
+    for b, (t, n) in enumerate(zip(items, sizes)):
+        if t is None and required:
+            raise ValueError(f"{name}[{b}] is required")
+        arr[b] = None if t is None else _dptr(t, n, f"{name}[{b}]").value
+    return arr
+
+
+def hps_batch_streams():
+    return lib().hps_batch_streams()
+
+
+def hps_solve_batched(ops, body, dirichlet=None, jump=None, u=None, stream=None, info=False):
+    """One right-hand side per problem: body[b] [n_int(b)] -> u[b] [N(b)] (list of tensors)."""
+    import torch
+    nb = len(ops)
+    if len(body) != nb or any(t is None for t in body):
+        raise ValueError("body needs one tensor per problem")
+    if u is None:
+        u = [torch.empty(op.N, dtype=torch.float64, device=body[b].device) for b, op in enumerate(ops)]
+    opa = (ctypes.c_void_p * nb)(*[op.handle for op in ops])
+    inf = (HpsInfo * nb)() if info else None
+    _check(lib().hps_solve_batched(opa, nb, _ptr_array(body, [o.n_int for o in ops], "body", True),
+                                   _ptr_array(dirichlet, [o.n_bdry for o in ops], "dirichlet"),
+                                   _ptr_array(jump, [o.n_iface for o in ops], "jump"),
+                                   _ptr_array(u, [o.N for o in ops], "u", True), _stream(stream), inf))
+    if info:
+        return u, [{"ir_iterations": i.ir_iterations, "last_correction": i.last_correction} for i in inf]
+    return u
+
+
+def ark_step_batched(ctxs, t, u, q_stages=None, q_space=None, q_time=None, f_stages=None, stream=None):
+    """One step of every problem: t list of floats, u list of [N(b)] tensors (in place)."""
+    nb = len(ctxs)
+    ca = (ctypes.c_void_p * nb)(*[c.handle for c in ctxs])
+    ta = (ctypes.c_double * nb)(*[float(v) for v in t])
+    ops = [c.op for c in ctxs]
+    qt = None
+    keep = []
+    if q_time is not None:
+        qt = (ctypes.c_void_p * nb)()
+        for b, v in enumerate(q_time):
+            if v is None:
+                continue
+            arr = np.ascontiguousarray(np.asarray(v, dtype=np.float64))
+            if arr.size != ctxs[b].s:
+                raise ValueError(f"q_time[{b}] needs one value per stage")
+            keep.append(arr)
+            qt[b] = arr.ctypes.data
+    _check(lib().ark_step_batched(ca, nb, ta, _ptr_array(u, [o.N for o in ops], "u", True),
+                                  _ptr_array(q_stages, [c.s * c.op.n_int for c in ctxs], "q_stages"),
+                                  _ptr_array(q_space, [o.n_int for o in ops], "q_space"), qt,
+                                  _ptr_array(f_stages, [(c.s + 1) * c.op.n_bdry for c in ctxs], "f_stages"),
+                                  _stream(stream)))
+    return u
+
+
+# ---------------------------------------------------------------------------------------
+# time-stepping server (include/hps_serve.h)
+# ---------------------------------------------------------------------------------------
+def _status_dict(st):
+    return {"state": st.state, "error": st.error, "steps_done": st.steps_done, "cache_hit": st.cache_hit,
+            "submit_s": st.submit_s, "start_s": st.start_s, "finish_s": st.finish_s}
+
+
+class Server:
+    """Owns an srv_server handle (srv_destroy drains it).  Keeps every array of a job
+    alive until the job is released."""
+
+    def __init__(self, cache_bytes=0, max_active=0):
+        h = ctypes.c_void_p()
+        cfg = SrvConfig(int(cache_bytes), int(max_active))
+        _check(lib().srv_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, grid, coef_key, coeffs, tableau, dt, u, steps, t0=0.0, flags=HPS_FP64, g=None,
+               q_space=None, q_amp=0.0, q_rate=0.0, stream=None):
+        """coeffs: dict of float64 CUDA tensors [n_int]; u: float64 CUDA tensor [N] (in/out)."""
+        N, n_int, _, _ = hps_num_nodes(grid)
+        s = int(tableau["s"])
+        arrs = {k: np.ascontiguousarray(np.asarray(tableau[k], dtype=np.float64).ravel())
+                for k in ("A", "b", "c", "Ahat", "bhat")}
+        P = ctypes.POINTER(ctypes.c_double)
+        tab = ArkTableau(s, *[arrs[k].ctypes.data_as(P) for k in ("A", "b", "c", "Ahat", "bhat")])
+        gg = ArkG(0, 0.0, 0.0, 0.0, 0.0) if g is None else ArkG(1, *[float(v) for v in g])
+        co = HpsCoeffs(*[_dptr(coeffs.get(k), n_int, k) for k in ("cxx", "cyy", "cx", "cy", "c0")])
+        job = SrvJob(grid, ctypes.c_uint64(coef_key), co, int(flags), tab, float(dt), gg, float(t0),
+                     int(steps), _dptr(u, N, "u"), _dptr(q_space, n_int, "q_space"), float(q_amp),
+                     float(q_rate))
+        jid = ctypes.c_int64()
+        _check(lib().srv_submit(self.handle, ctypes.byref(job), _stream(stream), ctypes.byref(jid)))
+        self._keep[jid.value] = (coeffs, u, q_space)
+        return jid.value
+
+    def poll(self, jid):
+        st = SrvStatus()
+        _check(lib().srv_poll(self.handle, int(jid), ctypes.byref(st)))
+        return _status_dict(st)
+
+    def wait(self, jid):
+        st = SrvStatus()
+        _check(lib().srv_wait(self.handle, int(jid), ctypes.byref(st)))
+        return _status_dict(st)
+
+    def release(self, jid):
+        _check(lib().srv_release(self.handle, int(jid)))
+        self._keep.pop(jid, None)
+
+    def stats(self):
+        st = SrvStats()
+        _check(lib().srv_get_stats(self.handle, ctypes.byref(st)))
+        return {n: getattr(st, n) for n, _ in SrvStats._fields_}
+
+    def close(self):
+        if self.handle:
+            lib().srv_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

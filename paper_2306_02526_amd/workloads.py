@@ -32,7 +32,9 @@ class HeatManufactured:
     """u(t,x,y) = e^{-t} phi(x,y), phi = sin(pi x) sin(pi y) (1 + 0.1 F),
     F = sum_m alpha_m sin(pi (k_m x + l_m y) + ph_m); L = Laplacian, g = 0."""
 
-    def __init__(self, rng, n_modes=8, amp=0.1, kmax=4, coef=None):
+    def __init__(self, rng, n_modes=8, amp=0.1, kmax=4, coef=None, Lx=1.0, Ly=1.0):
+        # on [0, Lx] x [0, Ly] the envelope is sin(pi x / Lx) sin(pi y / Ly)
+        self.Lx, self.Ly = float(Lx), float(Ly)
         self.k = rng.integers(1, kmax + 1, size=n_modes).astype(np.float64)
         self.l = rng.integers(1, kmax + 1, size=n_modes).astype(np.float64)
         self.ph = rng.uniform(0.0, 2.0 * math.pi, size=n_modes)
@@ -53,11 +55,11 @@ class HeatManufactured:
     def phi_parts(self, x, y):
         x = np.asarray(x, dtype=np.float64)
         y = np.asarray(y, dtype=np.float64)
-        pi = math.pi
-        s = np.sin(pi * x) * np.sin(pi * y)
-        sx = pi * np.cos(pi * x) * np.sin(pi * y)
-        sy = pi * np.sin(pi * x) * np.cos(pi * y)
-        lap_s = -2.0 * pi * pi * s
+        wx, wy = math.pi / self.Lx, math.pi / self.Ly
+        s = np.sin(wx * x) * np.sin(wy * y)
+        sx = wx * np.cos(wx * x) * np.sin(wy * y)
+        sy = wy * np.sin(wx * x) * np.cos(wy * y)
+        lap_s = -(wx * wx + wy * wy) * s
         F, Fx, Fy, lapF = self._F(x, y)
         m = 1.0 + self.amp * F
         phi = s * m
@@ -117,17 +119,20 @@ class AllenCahn:
 
     gpoly = (0.0, 1.0, 0.0, -1.0)
 
-    def __init__(self, rng, kmax=8):
+    def __init__(self, rng, kmax=8, coef=None, Lx=1.0, Ly=1.0):
+        # on [0, Lx] x [0, Ly] the modes are sin(k pi x / Lx) sin(l pi y / Ly); coef (None:
+        # allen_cahn_a) gives a and its gradient
         self.c = rng.standard_normal((kmax, kmax))
         self.kmax = kmax
-        xs = np.linspace(0.0, 1.0, 257)
-        X, Y = np.meshgrid(xs, xs, indexing="ij")
+        self.coef = coef
+        self.Lx, self.Ly = float(Lx), float(Ly)
+        X, Y = np.meshgrid(np.linspace(0.0, self.Lx, 257), np.linspace(0.0, self.Ly, 257), indexing="ij")
         self.scale = 1.0 / np.max(np.abs(self._raw(X.ravel(), Y.ravel())))
 
     def _raw(self, x, y):
         k = np.arange(1, self.kmax + 1, dtype=np.float64)
-        sx = np.sin(math.pi * np.multiply.outer(x, k))
-        sy = np.sin(math.pi * np.multiply.outer(y, k))
+        sx = np.sin(math.pi / self.Lx * np.multiply.outer(x, k))
+        sy = np.sin(math.pi / self.Ly * np.multiply.outer(y, k))
         return np.einsum("nk,kl,nl->n", sx, self.c, sy)
 
     def u0(self, x, y):
@@ -135,9 +140,8 @@ class AllenCahn:
         y = np.asarray(y, dtype=np.float64)
         return self.scale * self._raw(x.ravel(), y.ravel()).reshape(x.shape)
 
-    @staticmethod
-    def L_coeffs(x, y):
-        a, ax, ay = allen_cahn_a(x, y)
+    def L_coeffs(self, x, y):
+        a, ax, ay = (allen_cahn_a if self.coef is None else self.coef)(x, y)
         return a, a.copy(), ax, ay, np.zeros_like(a)
 
 
@@ -170,18 +174,26 @@ class SmoothDiffusivity:
         return a, ax, ay
 
 
-def batched_mix(n_problems=256, config_index=4):
-    """Per-problem sizes and data for the batched workload: n in {8,16,32,64} per side,
-    p in {8,12,16}, gamma*dt in {1e-3,1e-2}, heat or Allen-Cahn type 50/50."""
+def batched_mix(n_problems=256, config_index=4, sides=(8, 16, 32, 64), orders=(8, 12, 16)):
+    """Per-problem data of the batched workload: n1, n2 drawn from `sides`, p from `orders`,
+    gamma*dt in {1e-3, 1e-2}, smooth diffusivity a in [0.5, 1.5], heat (manufactured
+    solution) or Allen-Cahn type 50/50.  Leaves are squares of side 1 / max(n1, n2), so the
+    domain is [0, n1 h] x [0, n2 h] (the unit square when n1 == n2)."""
     out = []
     for b in range(n_problems):
         rng = rng_for(config_index, b)
-        n1 = int(rng.choice([8, 16, 32, 64]))
-        n2 = int(rng.choice([8, 16, 32, 64]))
-        p = int(rng.choice([8, 12, 16]))
+        n1 = int(rng.choice(list(sides)))
+        n2 = int(rng.choice(list(sides)))
+        p = int(rng.choice(list(orders)))
         gdt = float(rng.choice([1e-3, 1e-2]))
         kind = "heat" if rng.uniform() < 0.5 else "allen_cahn"
         coef = SmoothDiffusivity(rng)
+        h = 1.0 / max(n1, n2)
+        Lx, Ly = n1 * h, n2 * h
+        if kind == "heat":
+            prob = HeatManufactured(rng, coef=coef, Lx=Lx, Ly=Ly)
+        else:
+            prob = AllenCahn(rng, coef=coef, Lx=Lx, Ly=Ly)
         out.append({"n1": n1, "n2": n2, "p": p, "gamma_dt": gdt, "kind": kind,
-                    "coef": coef, "rng": rng})
+                    "domain": (0.0, Lx, 0.0, Ly), "problem": prob})
     return out

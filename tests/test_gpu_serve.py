@@ -1,0 +1,151 @@
+"""Time-stepping server (include/hps_serve.h) through the C ABI: a served job gives the
+oracle's result, is bitwise the same alone and among other jobs, and the operator cache
+shares, evicts and rebuilds operators without changing results."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.ark import ARK, ark436l2sa, tableau_float
+from oracle.grid import Grid
+from oracle.hps import HPS
+from paper_2306_02526_amd import hps, workloads
+from paper_2306_02526_amd.tableau import ark436l2sa as product_tableau
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    return _t
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+class Problem:
+    """One seeded problem of the batched recipe with its device data."""
+
+    def __init__(self, torch, kind, n1, n2, p, gdt, seed):
+        rng = workloads.rng_for(5, seed)
+        coef = workloads.SmoothDiffusivity(rng)
+        h = 1.0 / max(n1, n2)
+        self.domain = (0.0, n1 * h, 0.0, n2 * h)
+        self.kind = kind
+        self.pr = (workloads.HeatManufactured(rng, coef=coef, Lx=n1 * h, Ly=n2 * h) if kind == "heat"
+                   else workloads.AllenCahn(rng, coef=coef, Lx=n1 * h, Ly=n2 * h))
+        self.grid = hps.make_grid(*self.domain, n1, n2, p)
+        self.og = Grid(*self.domain, n1, n2, p)
+        self.x, self.y = hps.hps_nodes(self.grid)
+        ni = self.og.n_int
+        cxx, cyy, cx, cy, c0 = self.pr.L_coeffs(self.x[:ni], self.y[:ni])
+        self.co = dict(cxx=cxx, cyy=cyy, cx=cx, cy=cy, c0=c0)
+        self.dco = {k: torch.tensor(v, device="cuda") for k, v in self.co.items()}
+        self.tab = product_tableau()
+        self.gdt = gdt
+        self.dt = gdt / self.tab["gamma"]
+        self.gp = None if kind == "heat" else workloads.AllenCahn.gpoly
+        self.u0 = self.pr.exact(0.0, self.x, self.y) if kind == "heat" else self.pr.u0(self.x, self.y)
+        self.qsp = (torch.tensor(self.pr.q_space(self.x[:ni], self.y[:ni]), device="cuda")
+                    if kind == "heat" else None)
+        self.key = seed
+
+    def submit(self, torch, srv, steps):
+        u = torch.tensor(self.u0, device="cuda")
+        extra = dict(q_space=self.qsp, q_amp=1.0, q_rate=-1.0) if self.kind == "heat" else {}
+        jid = srv.submit(self.grid, self.key, self.dco, self.tab, self.dt, u, steps, g=self.gp, **extra)
+        return jid, u
+
+    def oracle(self, steps):
+        ark = ARK(HPS(self.og, self.co, self.gdt), self.co, tableau_float(ark436l2sa()), self.dt, self.gp)
+        u = self.u0.copy()
+        ni = self.og.n_int
+        for n in range(steps):
+            t = n * self.dt
+            qst = None
+            if self.kind == "heat":
+                qs = self.pr.q_space(self.x[:ni], self.y[:ni])
+                qst = np.array([np.exp(-(t + c * self.dt)) * qs for c in self.tab["c"]])
+            u = ark.step(u, q_stages=qst)
+        return u
+
+
+def test_served_job_matches_oracle_alone_and_in_a_mix(torch):
+    say("[serve] one job alone, then the same job among 7 others")
+    A = Problem(torch, "allen_cahn", 4, 4, 8, 1e-3, 0)
+    H = Problem(torch, "heat", 2, 4, 8, 1e-2, 1)
+    others = [Problem(torch, "heat", 4, 2, 6, 1e-3, 2), Problem(torch, "allen_cahn", 8, 8, 10, 1e-2, 3),
+              Problem(torch, "heat", 1, 1, 12, 1e-2, 4)]
+    steps = 6
+    srv = hps.Server()
+    ja, ua_alone = A.submit(torch, srv, steps)
+    st = srv.wait(ja)
+    assert st["state"] == hps.SRV_DONE and st["steps_done"] == steps
+    srv.close()
+    e = rel(ua_alone.cpu().numpy(), A.oracle(steps))
+    say(f"   Allen-Cahn 4x4 p=8 alone: oracle {e:.2e}")
+    assert e <= TOL64
+
+    srv = hps.Server(max_active=5)
+    counts = [steps + 1, steps, steps, steps + 2, steps + 1, steps, steps + 1, steps + 2]
+    jobs = []
+    for P, n in zip([others[0], H, A, others[1], A, others[2], H, A], counts):
+        jobs.append((P, *P.submit(torch, srv, n)))
+    for P, jid, u in jobs:
+        st = srv.wait(jid)
+        assert st["state"] == hps.SRV_DONE, st
+    stats = srv.stats()
+    srv.close()
+    say(f"   mix: {stats}")
+    assert stats["builds"] == 5 and stats["cache_hits"] == 3 and stats["completed"] == 8
+    # the first copy of job A ran the same number of steps as the job alone
+    assert torch.equal(jobs[2][2], ua_alone)
+    for k, ((P, jid, u), n) in enumerate(zip(jobs, counts)):
+        e = rel(u.cpu().numpy(), P.oracle(n))
+        say(f"   job {k}: {P.kind} {P.og.n1}x{P.og.n2} p={P.og.p} {n} steps: oracle {e:.2e}")
+        assert e <= TOL64, (k, e)
+
+
+def test_cache_eviction_keeps_results(torch):
+    say("[serve] cache budget of one operator: every key change evicts and rebuilds")
+    P1 = Problem(torch, "allen_cahn", 4, 4, 8, 1e-3, 10)
+    P2 = Problem(torch, "heat", 4, 4, 8, 1e-3, 11)
+    op = hps.hps_build(P1.grid, P1.dco, P1.gdt)
+    budget = int(op.bytes()[0] * 1.5)     # room for one operator with its workspace, not two
+    op.free()
+    srv = hps.Server(cache_bytes=budget, max_active=1)
+    res = [(P, *P.submit(torch, srv, 3)) for P in (P1, P2, P1)]
+    for P, jid, u in res:
+        assert srv.wait(jid)["state"] == hps.SRV_DONE
+    stats = srv.stats()
+    srv.close()
+    say(f"   {stats}")
+    assert stats["builds"] == 3 and stats["evictions"] == 2
+    assert torch.equal(res[0][2], res[2][2])
+    for P, jid, u in res:
+        assert rel(u.cpu().numpy(), P.oracle(3)) <= TOL64
+
+
+def test_server_rejects_bad_jobs(torch):
+    P = Problem(torch, "allen_cahn", 2, 2, 6, 1e-3, 20)
+    srv = hps.Server()
+    with pytest.raises(hps.HPSError) as e:
+        P.submit(torch, srv, 0)
+    assert e.value.code == -1
+    u = torch.tensor(P.u0, device="cuda")
+    too_big = hps.Server(cache_bytes=1024)
+    jid = too_big.submit(P.grid, 1, P.dco, P.tab, P.dt, u, 2, g=P.gp)
+    st = too_big.wait(jid)
+    assert st["state"] == hps.SRV_FAILED and st["error"] == -2
+    too_big.close()
+    srv.close()

@@ -1,4 +1,4 @@
-"""Host-side checks of the C-ABI library: it loads, exports what include/hps.h declares,
+"""Host-side checks of the C-ABI library: it loads, exports what include/*.h declare,
 and its host-only entry points (node counts, coordinates, argument errors) agree with
 the oracle's grid.  No GPU compute is called here."""
 import ctypes
@@ -17,8 +17,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    text = open(os.path.join(ROOT, "include", "hps.h")).read()
-    return sorted(set(re.findall(r"^HPS_API[^;(]*?\b(\w+)\s*\(", text, flags=re.M)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            names |= set(re.findall(r"^HPS_API[^;(]*?\b(\w+)\s*\(", text, flags=re.M))
+    return sorted(names)
 
 
 def test_header_declarations_match_binding():
@@ -78,3 +82,39 @@ def test_product_tableau_equals_oracle_tableau():
     for k in ("A", "Ahat", "b", "bhat", "c"):
         assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
     assert a["s"] == b["s"] and a["gamma"] == b["gamma"]
+
+
+def test_binding_structs_match_header_layout(tmp_path):
+    """Sizes and field offsets of every struct in include/*.h, as gcc lays them out, equal
+    the ctypes structures of the binding."""
+    import subprocess
+    structs = {"hps_grid": hps.HpsGrid, "hps_coeffs": hps.HpsCoeffs, "hps_info": hps.HpsInfo,
+               "ark_tableau": hps.ArkTableau, "ark_g": hps.ArkG, "srv_config": hps.SrvConfig,
+               "srv_job": hps.SrvJob, "srv_status": hps.SrvStatus, "srv_stats": hps.SrvStats}
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "hps_batch.h"', '#include "hps_serve.h"',
+             "int main(void) {"]
+    expect = []
+    for cname, py in structs.items():
+        lines.append(f'printf("%zu\\n", sizeof({cname}));')
+        expect.append(ctypes.sizeof(py))
+        for fname, _ in py._fields_:
+            lines.append(f'printf("%zu\\n", offsetof({cname}, {fname}));')
+            expect.append(getattr(py, fname).offset)
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert got == expect
+
+
+def test_batched_and_server_argument_errors():
+    """Argument checks that return before any device call."""
+    L = hps.lib()
+    assert L.hps_solve_batched(None, 1, None, None, None, None, None, None) == -1
+    assert L.hps_solve_batched(None, -1, None, None, None, None, None, None) == -1
+    assert L.hps_solve_batched(None, 0, None, None, None, None, None, None) == 0
+    assert L.ark_step_batched(None, 2, None, None, None, None, None, None, None) == -1
+    assert L.srv_submit(None, None, None, None) == -1
+    assert L.srv_poll(None, 0, None) == -1
