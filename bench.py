@@ -62,7 +62,7 @@ def parse():
                          "problems stepped together; serving: Poisson job arrivals on the server")
     ap.add_argument("--problems", type=int, default=256, help="batched: number of problems")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
-    ap.add_argument("--window", type=float, default=2.0, help="serving: seconds of arrivals")
+    ap.add_argument("--window", type=float, default=1.0, help="serving: seconds of arrivals at --rate")
     ap.add_argument("--counter-run", action="store_true",
                     help="short run for hardware-counter passes: build, 2 steps, then a plain "
                          "1 GiB device copy whose counters calibrate the byte counts")
@@ -397,7 +397,9 @@ def serving_run(args):
 
     def drain(ids):
         lat, fin = [], []
-        for j in ids:
+        for k, j in enumerate(ids):
+            if k and k % 50 == 0:
+                log(f"   {k}/{len(ids)} jobs finished")
             st = srv.wait(j)
             assert st["state"] == hps.SRV_DONE, st
             lat.append(st["finish_s"] - st["submit_s"])
@@ -441,7 +443,7 @@ def serving_run(args):
 
     r_low = run(0.8 * sat, max(args.window, 5.0))
     log(f"serving at 0.8x saturation: {r_low}")
-    r_hi = run(args.rate, args.window)
+    r_hi = run(args.rate, args.window) if args.window > 0 else None
     log(f"serving at {args.rate}/s: {r_hi}")
     st = srv.stats()
     srv.close()

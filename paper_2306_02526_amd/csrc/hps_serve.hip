@@ -31,6 +31,7 @@ struct CacheEntry {
     int64_t bytes = 0;
     int refs = 0;
     uint64_t last_use = 0;
+    std::vector<ark_ctx *> spare;   // stepping contexts of finished jobs, reused by later ones
 };
 
 struct Job {
@@ -43,8 +44,17 @@ struct Job {
     ark_ctx *ctx = nullptr;
     hps_op *op = nullptr;
     bool waited = false;
+    int enqueued = 0;             // steps enqueued (st.steps_done counts completed ones)
     srv_status st{};
 };
+
+// A context can serve another job of the same operator if the step it takes is the same.
+bool same_step(const ark_ctx *c, const Job *j) {
+    const int s = j->spec.tab.s;
+    return c->s == s && c->dt == j->spec.dt && c->A == j->A && c->b == j->b && c->c == j->c &&
+           c->Ah == j->Ah && c->bh == j->bh && c->g.kind == j->spec.g.kind && c->g.g0 == j->spec.g.g0 &&
+           c->g.g1 == j->spec.g.g1 && c->g.g2 == j->spec.g.g2 && c->g.g3 == j->spec.g.g3;
+}
 
 // Device bytes an operator of this grid will hold: its packed panels plus the solve
 // workspace (about ten doubles per node).
@@ -71,24 +81,41 @@ struct srv_server {
     uint64_t use_clock = 0;
     srv_stats stats{};
     hipStream_t stream = nullptr;
-    hipEvent_t iter_done = nullptr;
+    // iterations enqueued but not yet known complete (at most two)
+    struct Inflight {
+        hipEvent_t ev = nullptr;
+        std::vector<Job *> stepped, last;   // jobs stepped; jobs whose last step this is
+    };
+    std::deque<Inflight> inflight;
+    std::vector<hipEvent_t> ev_pool;
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
     void run();
     int admit(Job *j);
     void finish(Job *j, int state, int err);
     void release_op(Job *j);
+    int retire_oldest();
+    void evict_entry(std::map<Key, CacheEntry>::iterator it);
 };
 
+void srv_server::evict_entry(std::map<Key, CacheEntry>::iterator it) {
+    for (ark_ctx *c : it->second.spare) ark_free(c);
+    hps_free(it->second.op);
+    cache.erase(it);
+}
+
 void srv_server::release_op(Job *j) {
-    if (j->ctx) ark_free(j->ctx);
+    auto it = j->op ? cache.find(j->key) : cache.end();
+    if (j->ctx) {
+        // keep the context for the next job of this operator (freeing device memory would
+        // wait for the whole device)
+        if (it != cache.end()) it->second.spare.push_back(j->ctx);
+        else ark_free(j->ctx);
+    }
     j->ctx = nullptr;
-    if (j->op) {
-        auto it = cache.find(j->key);
-        if (it != cache.end()) {
-            it->second.refs--;
-            it->second.last_use = ++use_clock;
-        }
+    if (it != cache.end()) {
+        it->second.refs--;
+        it->second.last_use = ++use_clock;
     }
     j->op = nullptr;
     if (j->ready) (void)hipEventDestroy(j->ready);
@@ -127,8 +154,7 @@ int srv_server::admit(Job *j) {
                     victim = e;
             if (victim == cache.end()) return 1;
             held -= victim->second.bytes;
-            hps_free(victim->second.op);
-            cache.erase(victim);
+            evict_entry(victim);
             std::lock_guard<std::mutex> g(mu);
             stats.evictions++;
         }
@@ -154,8 +180,16 @@ int srv_server::admit(Job *j) {
     it->second.refs++;
     it->second.last_use = ++use_clock;
     j->op = it->second.op;
-    ark_tableau tab{j->spec.tab.s, j->A.data(), j->b.data(), j->c.data(), j->Ah.data(), j->bh.data()};
-    if (int rc = ark_create(j->op, &tab, j->spec.dt, &j->spec.g, &j->ctx)) return rc;
+    auto &sp = it->second.spare;
+    for (size_t k = 0; k < sp.size() && !j->ctx; ++k)
+        if (same_step(sp[k], j)) {
+            j->ctx = sp[k];
+            sp.erase(sp.begin() + (long)k);
+        }
+    if (!j->ctx) {
+        ark_tableau tab{j->spec.tab.s, j->A.data(), j->b.data(), j->c.data(), j->Ah.data(), j->bh.data()};
+        if (int rc = ark_create(j->op, &tab, j->spec.dt, &j->spec.g, &j->ctx)) return rc;
+    }
     std::lock_guard<std::mutex> g(mu);
     j->st.cache_hit = hit ? 1 : 0;
     j->st.state = SRV_ACTIVE;
@@ -169,14 +203,30 @@ int srv_server::admit(Job *j) {
     return 0;
 }
 
+// Wait for the oldest in-flight iteration; count its steps and finish the jobs whose
+// last step it held.  Returns the iteration's error (HPS_OK or HPS_EDEVICE).
+int srv_server::retire_oldest() {
+    Inflight f = inflight.front();
+    inflight.pop_front();
+    const int rc = hipEventSynchronize(f.ev) == hipSuccess ? HPS_OK : HPS_EDEVICE;
+    ev_pool.push_back(f.ev);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        for (Job *j : f.stepped) j->st.steps_done++;
+        stats.job_steps += (int64_t)f.stepped.size();
+    }
+    for (Job *j : f.last) finish(j, rc == HPS_OK ? SRV_DONE : SRV_FAILED, rc);
+    return rc;
+}
+
 void srv_server::run() {
     (void)hipSetDevice(device);
     for (;;) {
         std::vector<Job *> incoming;
         {
             std::unique_lock<std::mutex> lk(mu);
-            wake.wait(lk, [&] { return stopping || !queue.empty() || !active.empty(); });
-            if (stopping && queue.empty() && active.empty()) break;
+            wake.wait(lk, [&] { return stopping || !queue.empty() || !active.empty() || !inflight.empty(); });
+            if (stopping && queue.empty() && active.empty() && inflight.empty()) break;
             // first come, first served: take jobs from the head while slots are free
             while (!queue.empty() && (int)(active.size() + incoming.size()) < cfg.max_active) {
                 incoming.push_back(queue.front());
@@ -195,61 +245,72 @@ void srv_server::run() {
             if (rc < 0) finish(j, SRV_FAILED, rc);
             else active.push_back(j);
         }
-        if (active.empty()) {
-            // nothing could be admitted: wait for a submission or the end
+        if (!active.empty()) {
+            // one step of every running job, as one batched call; the next iteration is
+            // enqueued before this one is waited for, so the GPU does not idle in between
+            const int n = (int)active.size();
+            std::vector<ark_ctx *> ctxs(n);
+            std::vector<double> ts(n);
+            std::vector<double *> us(n);
+            std::vector<const double *> qsp(n, nullptr), qtp(n, nullptr);
+            std::vector<std::vector<double>> qt(n);
+            bool any_q = false;
+            int rc = HPS_OK;
+            for (int b = 0; b < n; ++b) {
+                Job *j = active[b];
+                if (!j->waited) {
+                    if (hipStreamWaitEvent(stream, j->ready, 0) != hipSuccess) rc = HPS_EDEVICE;
+                    j->waited = true;
+                }
+                ctxs[b] = j->ctx;
+                ts[b] = j->spec.t0 + j->enqueued * j->spec.dt;
+                us[b] = j->spec.u;
+                if (j->spec.q_space) {
+                    any_q = true;
+                    qsp[b] = j->spec.q_space;
+                    qt[b].resize(j->spec.tab.s);
+                    for (int i = 0; i < j->spec.tab.s; ++i)
+                        qt[b][i] = j->spec.q_amp * std::exp(j->spec.q_rate * (ts[b] + j->c[i] * j->spec.dt));
+                    qtp[b] = qt[b].data();
+                }
+            }
+            if (rc == HPS_OK)
+                rc = ark_step_batched(ctxs.data(), n, ts.data(), us.data(), nullptr, any_q ? qsp.data() : nullptr,
+                                      any_q ? qtp.data() : nullptr, nullptr, stream);
+            Inflight f;
+            if (ev_pool.empty()) {
+                hipEvent_t e = nullptr;
+                if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) rc = HPS_EDEVICE;
+                ev_pool.push_back(e);
+            }
+            f.ev = ev_pool.back();
+            ev_pool.pop_back();
+            if (rc == HPS_OK && hipEventRecord(f.ev, stream) != hipSuccess) rc = HPS_EDEVICE;
+            if (rc != HPS_OK) {
+                ev_pool.push_back(f.ev);
+                while (!inflight.empty()) retire_oldest();
+                for (Job *j : active) finish(j, SRV_FAILED, rc);
+                active.clear();
+            } else {
+                std::vector<Job *> still;
+                for (Job *j : active) {
+                    f.stepped.push_back(j);
+                    if (++j->enqueued >= j->spec.steps) f.last.push_back(j);
+                    else still.push_back(j);
+                }
+                active.swap(still);
+                inflight.push_back(f);
+                std::lock_guard<std::mutex> g(mu);
+                stats.iterations++;
+            }
+        }
+        // keep one iteration in flight while more work is queued or running
+        const size_t keep = active.empty() ? 0 : 1;
+        while (inflight.size() > keep) retire_oldest();
+        if (active.empty() && inflight.empty()) {
             std::unique_lock<std::mutex> lk(mu);
             if (!stopping && !queue.empty()) wake.wait_for(lk, std::chrono::milliseconds(1));
-            continue;
         }
-        // one step of every running job, as one batched call
-        const int n = (int)active.size();
-        std::vector<ark_ctx *> ctxs(n);
-        std::vector<double> ts(n);
-        std::vector<double *> us(n);
-        std::vector<const double *> qsp(n, nullptr), qtp(n, nullptr);
-        std::vector<std::vector<double>> qt(n);
-        bool any_q = false;
-        int rc = HPS_OK;
-        for (int b = 0; b < n; ++b) {
-            Job *j = active[b];
-            if (!j->waited) {
-                if (hipStreamWaitEvent(stream, j->ready, 0) != hipSuccess) rc = HPS_EDEVICE;
-                j->waited = true;
-            }
-            ctxs[b] = j->ctx;
-            ts[b] = j->spec.t0 + j->st.steps_done * j->spec.dt;
-            us[b] = j->spec.u;
-            if (j->spec.q_space) {
-                any_q = true;
-                qsp[b] = j->spec.q_space;
-                qt[b].resize(j->spec.tab.s);
-                for (int i = 0; i < j->spec.tab.s; ++i)
-                    qt[b][i] = j->spec.q_amp * std::exp(j->spec.q_rate * (ts[b] + j->c[i] * j->spec.dt));
-                qtp[b] = qt[b].data();
-            }
-        }
-        if (rc == HPS_OK)
-            rc = ark_step_batched(ctxs.data(), n, ts.data(), us.data(), nullptr, any_q ? qsp.data() : nullptr,
-                                  any_q ? qtp.data() : nullptr, nullptr, stream);
-        if (rc == HPS_OK && hipEventRecord(iter_done, stream) != hipSuccess) rc = HPS_EDEVICE;
-        if (rc == HPS_OK && hipEventSynchronize(iter_done) != hipSuccess) rc = HPS_EDEVICE;
-        std::vector<Job *> still;
-        for (Job *j : active) {
-            if (rc != HPS_OK) {
-                finish(j, SRV_FAILED, rc);
-                continue;
-            }
-            {
-                std::lock_guard<std::mutex> g(mu);
-                j->st.steps_done++;
-                stats.job_steps++;
-            }
-            if (j->st.steps_done >= j->spec.steps) finish(j, SRV_DONE, HPS_OK);
-            else still.push_back(j);
-        }
-        active.swap(still);
-        std::lock_guard<std::mutex> g(mu);
-        stats.iterations++;
     }
 }
 
@@ -271,9 +332,7 @@ extern "C" int srv_create(const srv_config *cfg, srv_server **out) {
     s->device = dev;
     s->cfg = c;
     s->t0 = Clock::now();
-    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&s->iter_done, hipEventDisableTiming) != hipSuccess) {
-        if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess) {
         delete s;
         hps_set_error("could not create the server's stream");
         return HPS_EDEVICE;
@@ -389,9 +448,9 @@ extern "C" void srv_destroy(srv_server *srv) {
         srv->wake.notify_all();
     }
     if (srv->worker.joinable()) srv->worker.join();
-    for (auto &e : srv->cache) hps_free(e.second.op);
+    while (!srv->cache.empty()) srv->evict_entry(srv->cache.begin());
     for (auto &kv : srv->jobs) delete kv.second;
-    (void)hipEventDestroy(srv->iter_done);
+    for (hipEvent_t e : srv->ev_pool) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(srv->stream);
     delete srv;
 }
