@@ -1,4 +1,5 @@
-"""IMEX additive Runge-Kutta step in the stage formulation (oracle; test infrastructure only).
+"""IMEX additive Runge-Kutta steps, stage formulation (ARK) and slope formulation with
+flux-jump penalisation (SlopeARK) (oracle; test infrastructure only).
 
 Sec. 3.1: the stiff part L u is integrated by an ESDIRK tableau (A, b, c) with
 an explicit first stage and a_ii = gamma, the non-stiff part q + g(u) by an
@@ -127,14 +128,21 @@ class InterfaceSolver:
         rest = np.ones(grid.N, dtype=bool)
         rest[self.iface] = False
         self.rest = np.nonzero(rest)[0]
-        Jr = J[self.iface]
-        self.J_ii = sp.csc_matrix(Jr[:, self.iface])
-        self.J_ir = Jr[:, self.rest]
+        self.Jr = sp.csr_matrix(J[self.iface])
+        self.J_ii = sp.csc_matrix(self.Jr[:, self.iface])
+        self.J_ir = self.Jr[:, self.rest]
 
-    def fill(self, u):
+    def jump(self, u):
+        """flux_alpha - flux_beta of u at every interface node."""
+        return self.Jr @ u
+
+    def fill(self, u, jump=None):
+        """Set the interface values of u so that its flux jump equals `jump` (None: 0)."""
         if len(self.iface) == 0:
             return u
         rhs = -(self.J_ir @ u[self.rest])
+        if jump is not None:
+            rhs = rhs + jump
         u[self.iface] = spla.spsolve(self.J_ii, rhs)
         return u
 
@@ -183,4 +191,82 @@ class ARK:
         self.iface.fill(unew)
         if return_stages:
             return unew, stages
+        return unew
+
+
+class SlopeARK:
+    """One step of the slope formulation (Sec. 3.1, eqs. for k_i and l_i) with the
+    flux-jump penalisation of Sec. 3.1 ("Penalization in the slope formulation").
+
+      k_1 = L u^n + q(t^n),           l_1 = g(u^n),
+      (I - dt gamma L) k_i = L u^n + dt sum_{j<i} a_ij L k_j + dt sum_{j<i} ahat_ij L l_j
+                             + q(t^n + c_i dt),                                  i = 2..s,
+      l_i = g(u^n + dt sum_{j<=i} a_ij k_j + dt sum_{j<i} ahat_ij l_j),           i = 2..s,
+      u^{n+1} = u^n + dt sum_j b_j k_j + dt sum_j bhat_j l_j   (at every node).
+
+    Readings (the paper leaves them open):
+      * k_i on the boundary is u_t there (fdot_stages, the time derivative of the Dirichlet
+        data at t^n + c_i dt); l_i is 0 on the boundary (the paper assigns zero slope data
+        when the boundary data do not depend on time, the only case it allows with g).
+      * k_1 is an explicit equation: interior values L u^n + q, boundary values as above,
+        interface values from the (penalised) flux condition, i.e. the identity equation
+        solved on the tree (Sec. 3.1.1).  l_i is pointwise at interior and interface nodes.
+      * The penalised condition replaces zero flux jump of each slope k_i by the jump
+        -[[u^n]]/dt, [[.]] = flux_alpha - flux_beta of u^n.  Since sum_j b_j = 1 this makes
+        u^{n+1} flux-continuous when g = 0 (the sign that achieves what the paragraph asks).
+    """
+
+    def __init__(self, hps, coefs_int, tab, dt, gpoly=None):
+        self.hps = hps
+        self.grid = hps.grid
+        self.coefs = coefs_int
+        self.tab = tableau_float(tab) if isinstance(tab["gamma"], Fr) else tab
+        self.dt = float(dt)
+        self.gpoly = gpoly
+        if abs(self.tab["gamma"] * self.dt - hps.gamma_dt) > 1e-15 * abs(hps.gamma_dt):
+            raise ValueError("operator was built for a different gamma*dt")
+        self.iface = InterfaceSolver(self.grid)
+        self.bnd = self.grid.boundary_indices()
+
+    def step(self, u, q_stages=None, fdot_stages=None):
+        """u: full N vector at t^n.  q_stages: (s, n_int) source at t^n + c_i dt (or None).
+        fdot_stages: (s, n_bdry) time derivative of the Dirichlet data at t^n + c_i dt
+        (or None = 0)."""
+        g, tab, dt = self.grid, self.tab, self.dt
+        s, n_int = tab["s"], g.n_int
+        A, Ah, b, bh = tab["A"], tab["Ahat"], tab["b"], tab["bhat"]
+        q_at = (lambda i: np.zeros(n_int)) if q_stages is None else (lambda i: q_stages[i])
+        fd_at = (lambda i: np.zeros(len(self.bnd))) if fdot_stages is None else (lambda i: fdot_stages[i])
+        L = lambda v: apply_L(g, self.coefs, v)
+        penalty = -self.iface.jump(u) / dt
+        Lun = L(u)
+
+        def slope_l(v):
+            w = poly_g(self.gpoly, v)
+            w[self.bnd] = 0.0
+            return w
+
+        k1 = np.zeros(g.N)
+        k1[:n_int] = Lun + q_at(0)
+        k1[self.bnd] = fd_at(0)
+        self.iface.fill(k1, penalty)
+        k, l = [k1], [slope_l(u.copy())]
+        Lk, Ll = [L(k1)], [L(l[0])]
+        for i in range(1, s):
+            rhs = Lun + q_at(i)
+            for j in range(i):
+                rhs = rhs + dt * A[i, j] * Lk[j] + dt * Ah[i, j] * Ll[j]
+            ki = self.hps.solve(rhs, fd_at(i), penalty if len(self.iface.iface) else None)
+            k.append(ki)
+            Lk.append(L(ki))
+            ui = u.copy()
+            for j in range(i + 1):
+                ui += dt * A[i, j] * k[j]
+            for j in range(i):
+                ui += dt * Ah[i, j] * l[j]
+            l.append(slope_l(ui))
+            Ll.append(L(l[i]))
+        unew = u.copy()
+        for j in range(s):
+            unew += dt * b[j] * k[j] + dt * bh[j] * l[j]
         return unew

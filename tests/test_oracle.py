@@ -12,7 +12,7 @@ from fractions import Fraction as Fr
 import numpy as np
 import pytest
 
-from oracle.ark import ARK, InterfaceSolver, apply_L, ark436l2sa, tableau_float
+from oracle.ark import ARK, InterfaceSolver, SlopeARK, apply_L, ark436l2sa, tableau_float
 from oracle.cheb import cheb_diff_ref, cheb_points, leaf_diff_1d, leaf_points_1d
 from oracle.dense import dense_solve, flux_jump_matrix
 from oracle.grid import Grid
@@ -365,3 +365,90 @@ def test_backward_euler_step_map_is_stable(h):
     assert np.sum(np.abs(ev) < 1e-12) >= len(g.interface_indices())
     # and the interior-to-interior block contracts in the 2-norm
     assert np.linalg.norm(M[:n, :n], 2) <= 1.0 + 1e-12
+
+
+# ---------------------------------------------------------------------------------------
+# slope formulation with flux-jump penalisation (Sec. 3.1)
+# ---------------------------------------------------------------------------------------
+def _slope_coefs(x, y):
+    return dict(cxx=1.0 + 0.3 * np.sin(x + 2 * y), cyy=1.2 + 0.2 * np.cos(3 * x), cx=0.5 * np.sin(y),
+                cy=-0.4 * np.cos(x), c0=0.3 * np.sin(x * y))
+
+
+def test_slope_equals_stage_for_flux_continuous_data():
+    """Without sources and with fixed zero boundary data the two formulations are the same
+    discrete map when u^n has a continuous flux: k_i = L u_i at interior nodes, and
+    u^n + dt sum_j a_ij k_j solves the stage equation (uniqueness of the HPS solution)."""
+    tab = tableau_float(ark436l2sa())
+    g = Grid(0, 1, 0, 0.5, 4, 2, 8)
+    x, y = g.coordinates()
+    co = _slope_coefs(x[: g.n_int], y[: g.n_int])
+    dt = 0.01
+    H = HPS(g, co, tab["gamma"] * dt)
+    un = H.solve(np.random.default_rng(1).standard_normal(g.n_int))
+    st = ARK(H, co, tab, dt).step(un)
+    sl = SlopeARK(H, co, tab, dt).step(un)
+    assert np.abs(st - sl).max() <= 1e-12 * np.abs(st).max()
+
+
+def test_slope_penalisation_removes_flux_jumps():
+    """With every slope's flux jump set to -[[u^n]]/dt and sum_j b_j = 1, the step leaves no
+    flux jump in u^{n+1} (g = 0), whatever the jumps of u^n."""
+    tab = tableau_float(ark436l2sa())
+    g = Grid(0, 1, 0, 0.5, 4, 2, 8)
+    x, y = g.coordinates()
+    co = _slope_coefs(x[: g.n_int], y[: g.n_int])
+    dt = 0.01
+    H = HPS(g, co, tab["gamma"] * dt)
+    rng = np.random.default_rng(2)
+    un = rng.standard_normal(g.N)
+    un[g.boundary_indices()] = 0.0
+    I = InterfaceSolver(g)
+    before = np.abs(I.jump(un)).max()
+    q = rng.standard_normal((tab["s"], g.n_int))
+    un1 = SlopeARK(H, co, tab, dt).step(un, q_stages=q)
+    assert before > 10.0
+    assert np.abs(I.jump(un1)).max() <= 1e-13 * before
+
+
+def test_slope_equals_stage_on_one_leaf_with_nonlinearity():
+    """On one leaf (no interfaces) and fixed zero boundary data the formulations are the
+    stage and slope forms of one IMEX method for the ODE u' = K u + g(u): equal maps."""
+    tab = tableau_float(ark436l2sa())
+    g = Grid(0, 1, 0, 1, 1, 1, 10)
+    x, y = g.coordinates()
+    co = _slope_coefs(x[: g.n_int], y[: g.n_int])
+    dt = 0.01
+    H = HPS(g, co, tab["gamma"] * dt)
+    u = np.sin(math.pi * x) * np.sin(math.pi * y)
+    gp = (0.2, 1.0, 0.3, -1.0)
+    st = ARK(H, co, tab, dt, gp).step(u)
+    sl = SlopeARK(H, co, tab, dt, gp).step(u)
+    assert np.abs(st - sl).max() <= 1e-13 * np.abs(st).max()
+
+
+def test_slope_fourth_order_with_time_dependent_boundary_data():
+    """Heat equation with u = e^{-t} (sin(x + 2y) + x^2), whose boundary data depend on time:
+    the penalised slope formulation (boundary slopes = u_t) converges at fourth order, the
+    order of the tableau (error ratio 16 per halving of dt; checked >= 12)."""
+    tab = tableau_float(ark436l2sa())
+    g = Grid(0, 1, 0, 1, 2, 2, 16)
+    x, y = g.coordinates()
+    xi, yi = x[: g.n_int], y[: g.n_int]
+    one, zero = np.ones(g.n_int), np.zeros(g.n_int)
+    co = dict(cxx=one, cyy=one, cx=zero, cy=zero, c0=zero)
+    psi = lambda X, Y: np.sin(X + 2 * Y) + X ** 2
+    lap = lambda X, Y: -5.0 * np.sin(X + 2 * Y) + 2.0
+    bnd = g.boundary_indices()
+    T = 0.4
+    errs = []
+    for dt in (0.1, 0.05, 0.025):
+        sl = SlopeARK(HPS(g, co, tab["gamma"] * dt), co, tab, dt)
+        u = psi(x, y)
+        for m in range(int(round(T / dt))):
+            t = m * dt
+            q = np.array([math.exp(-(t + c * dt)) * (-psi(xi, yi) - lap(xi, yi)) for c in tab["c"]])
+            fd = np.array([-math.exp(-(t + c * dt)) * psi(x[bnd], y[bnd]) for c in tab["c"]])
+            u = sl.step(u, q_stages=q, fdot_stages=fd)
+        errs.append(np.abs(u - math.exp(-T) * psi(x, y)).max())
+    assert errs[0] / errs[1] >= 12.0 and errs[1] / errs[2] >= 12.0, errs
