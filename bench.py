@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--fp32-steps", type=int, default=10)
     ap.add_argument("--latency-samples", type=int, default=100)
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-slope", action="store_true")
+    ap.add_argument("--slope-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stage-solves", type=int, default=3)
     ap.add_argument("--workload", default="allen_cahn", choices=["allen_cahn", "batched", "serving"],
@@ -218,6 +220,28 @@ def main():
     p50, p99 = float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
     log(f"hps_solve latency: p50 {p50:.3f} ms, p99 {p99:.3f} ms")
 
+    # ---- slope formulation with flux-jump penalisation, same operator and start ----
+    slope = None
+    if not args.no_slope:
+        ctxs = hps.ark_create(op, tab, dt, g=workloads.AllenCahn.gpoly)
+        us = u0.clone()
+        hps.ark_step_slope(ctxs, 0.0, us)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(1, args.slope_steps + 1):
+            hps.ark_step_slope(ctxs, k * dt, us)
+        torch.cuda.synchronize()
+        els = time.perf_counter() - t0
+        ust = u0.clone()
+        for k in range(args.slope_steps + 1):
+            hps.ark_step(ctx, k * dt, ust)
+        torch.cuda.synchronize()
+        slope = {"stage_solves_per_s": round(stages * args.slope_steps / els, 1),
+                 "ms_per_step": round(1e3 * els / args.slope_steps, 3), "steps": args.slope_steps + 1,
+                 "rel_diff_vs_stage_formulation": float((us - ust).abs().max() / ust.abs().max())}
+        log(f"slope formulation: {slope}")
+        del ctxs
+
     # ---- FP32 operators + FP64 iterative refinement, same steps ----
     fp32 = None
     if not args.no_fp32:
@@ -257,7 +281,12 @@ def main():
     # ---- CPU oracle on a bounded sample of the same workload ----
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(n, p, dt, args.cpu_stage_solves)
+        # all of this host's share of cores (BLAS threads), and one core
+        share = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16))
+        cpu = cpu_baseline(n, p, dt, args.cpu_stage_solves, threads=share)
+        one = cpu_baseline(n, p, dt, args.cpu_stage_solves, threads=1)
+        if "value" in one:
+            cpu["one_core"] = {"value": one["value"], "build_s": one["build_s"], "cores": 1}
         log(f"cpu oracle: {cpu}")
 
     out = {
@@ -288,6 +317,7 @@ def main():
                      "traffic": traffic, "algorithmic_bytes_per_launch": int(alg),
                      "avg_launch_us": round(leaf_us, 2)},
         "fp32_ir": fp32,
+        "slope_formulation": slope,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -454,14 +484,13 @@ def serving_run(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(n, p, dt, n_solves):
-    """The oracle (plain NumPy FP64, one BLAS thread) on this host: its build on the full
-    grid (timed, not counted), then n_solves implicit stages of the same step timed; value
-    = stage-solves/s on those stages."""
+def cpu_baseline(n, p, dt, n_solves, threads=1):
+    """The oracle (plain NumPy FP64) on this host with `threads` BLAS threads: its build on
+    the full grid (timed, not counted), then n_solves implicit stages of the same step
+    timed; value = stage-solves/s on those stages."""
     import subprocess
     code = f"""
 import os, sys, time, json
-os.environ['OPENBLAS_NUM_THREADS'] = '1'; os.environ['OMP_NUM_THREADS'] = '1'
 sys.path.insert(0, {ROOT!r})
 import numpy as np
 from oracle.grid import Grid
@@ -490,8 +519,9 @@ for i in range(1, 1 + {n_solves}):
 print(json.dumps(dict(build_s=tb, times=times)))
 """
     t0 = time.perf_counter()
+    th = str(threads)
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
-                       env=dict(os.environ, OPENBLAS_NUM_THREADS="1", OMP_NUM_THREADS="1"))
+                       env=dict(os.environ, OPENBLAS_NUM_THREADS=th, OMP_NUM_THREADS=th, MKL_NUM_THREADS=th))
     if r.returncode != 0:
         return {"error": r.stderr[-400:]}
     d = json.loads(r.stdout.strip().splitlines()[-1])
@@ -500,7 +530,7 @@ print(json.dumps(dict(build_s=tb, times=times)))
         model = [ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")][0]
     except Exception:
         model = "unknown"
-    return {"value": round(len(ts) / sum(ts), 4), "unit": "stage-solves/s", "cores": 1, "kind": "oracle",
+    return {"value": round(len(ts) / sum(ts), 4), "unit": "stage-solves/s", "cores": threads, "kind": "oracle",
             "sample": f"oracle build on the full {n}x{n} p={p} grid ({d['build_s']:.1f} s, not counted), then "
                       f"{len(ts)} implicit stages of one step (rhs assembly, HPS solve, L u_i, F_i) timed",
             "build_s": round(d["build_s"], 2), "host_cpu": model, "host_nproc": os.cpu_count(),

@@ -160,6 +160,23 @@ HPS_API int ark_create(hps_op *op, const ark_tableau *tab, double dt, const ark_
 HPS_API int ark_step(ark_ctx *ctx, double t, double *u, const double *q_stages,
              const double *q_space, const double *q_time, const double *f_stages, void *stream);
 
+/* One step t -> t + dt of the slope formulation (Sec. 3.1) with the flux-jump
+ * penalisation of Sec. 3.1, in place on u (device [N]):
+ *   k_1 = L u^n + q(t),  l_1 = g(u^n);
+ *   (I - gamma dt L) k_i = L u^n + dt sum_{j<i} (a_ij L k_j + ahat_ij L l_j) + q(t + c_i dt),
+ *   l_i = g(u^n + dt sum_{j<=i} a_ij k_j + dt sum_{j<i} ahat_ij l_j),        i = 2..s;
+ *   u^{n+1} = u^n + dt sum_j (b_j k_j + bhat_j l_j) at every node.
+ * k_i on the outer boundary = fdot_stages[i] (device [s][n_bdry]: the time derivative of
+ * the Dirichlet data at t + c_i dt; NULL = 0); l_i = 0 there, so with g the Dirichlet data
+ * must not depend on time.  Every k_i takes the flux jump -(flux_alpha - flux_beta)(u^n)/dt
+ * across the interfaces (the penalised condition), so u^{n+1} is flux-continuous when
+ * g = 0.  k_1 and l_i are explicit: interface values of k_1 come from that condition,
+ * l_i is pointwise.  q as in ark_step.  The first call allocates the slopes' workspace
+ * (about 2 s (N + n_int) doubles with g, half without). */
+HPS_API int ark_step_slope(ark_ctx *ctx, double t, double *u, const double *q_stages,
+                           const double *q_space, const double *q_time, const double *fdot_stages,
+                           void *stream);
+
 /* Number of implicit stage solves performed per ark_step (s - 1). */
 HPS_API int ark_stage_solves_per_step(const ark_ctx *ctx);
 

@@ -748,12 +748,29 @@ extern "C" int ark_create(hps_op *op, const ark_tableau *tab, double dt, const a
     return HPS_OK;
 }
 
+int hps::ark_slope_workspace(ark_ctx *c) {
+    if (c->K) return HPS_OK;
+    const hps_op *op = c->op;
+    const int64_t s = c->s;
+    TRY(dev_alloc<double>(nullptr, &c->K, s * op->N, false));
+    TRY(dev_alloc<double>(nullptr, &c->Lk, s * op->n_int, false));
+    if (c->g.kind) {
+        TRY(dev_alloc<double>(nullptr, &c->Ls, s * op->N, false));
+        TRY(dev_alloc<double>(nullptr, &c->Ll, s * op->n_int, false));
+    }
+    TRY(dev_alloc<double>(nullptr, &c->Lun, op->n_int, false));
+    TRY(dev_alloc<double>(nullptr, &c->srhs, op->n_int, false));
+    TRY(dev_alloc<double>(nullptr, &c->pen, std::max<int64_t>(op->n_iface, 1), false));
+    return HPS_OK;
+}
+
 extern "C" void ark_free(ark_ctx *c) {
     if (!c) return;
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    for (double *p : {c->Lu, c->F, c->rhs, c->stage_u, c->qt_dev})
+    for (double *p : {c->Lu, c->F, c->rhs, c->stage_u, c->qt_dev, c->K, c->Ls, c->Lk, c->Ll, c->Lun, c->srhs,
+                      c->pen})
         if (p) (void)hipFree(p);
     delete c;
 }

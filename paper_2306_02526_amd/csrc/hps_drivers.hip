@@ -66,6 +66,24 @@ static int ir_refine(hps_op *op, const double *rhs, const double *jump, double *
     return HPS_OK;
 }
 
+// One right-hand side: leaf particular solutions, the level sweeps, reconstruction of u
+// (full canonical vector), and for FP32_IR the refinement loop.
+static int solve_one(hps_op *op, const double *body, const double *dir, const double *jump, double *u,
+                     hipStream_t st, hps_info *inf) {
+    const bool ir = (op->flags & HPS_FP32_IR) != 0;
+    LeafPhase up;
+    up.up = LU_BODY;
+    up.body = body;
+    TRY(launch_leaf(op, ir, up, st));
+    TRY(levels(op, ir, jump, dir, st));
+    LeafPhase dn;
+    dn.down = LD_WRITE_U;
+    dn.u_out = u;
+    TRY(launch_leaf(op, ir, dn, st));
+    if (ir) TRY(ir_refine(op, body, jump, u, st, inf));
+    return HPS_OK;
+}
+
 extern "C" int hps_solve(hps_op *op, int nrhs, const double *body, const double *dirichlet,
                          const double *jump, double *u, void *stream, hps_info *info) {
     CHECK_ARG(op != nullptr, "op is NULL");
@@ -77,7 +95,6 @@ extern "C" int hps_solve(hps_op *op, int nrhs, const double *body, const double 
     TRY(check_device_ptr(jump, "jump"));
     TRY(check_device_ptr(u, "u"));
     hipStream_t st = (hipStream_t)stream;
-    const bool ir = (op->flags & HPS_FP32_IR) != 0;
     int worst_it = 0;
     double worst_rel = 0.0;
     for (int r = 0; r < nrhs; ++r) {
@@ -85,21 +102,10 @@ extern "C" int hps_solve(hps_op *op, int nrhs, const double *body, const double 
         const double *d = dirichlet ? dirichlet + (int64_t)r * op->n_bdry : nullptr;
         const double *j = (jump && op->n_iface) ? jump + (int64_t)r * op->n_iface : nullptr;
         double *ur = u + (int64_t)r * op->N;
-        LeafPhase up;
-        up.up = LU_BODY;
-        up.body = b;
-        TRY(launch_leaf(op, ir, up, st));
-        TRY(levels(op, ir, j, d, st));
-        LeafPhase dn;
-        dn.down = LD_WRITE_U;
-        dn.u_out = ur;
-        TRY(launch_leaf(op, ir, dn, st));
-        if (ir) {
-            hps_info inf{};
-            TRY(ir_refine(op, b, j, ur, st, &inf));
-            worst_it = std::max(worst_it, inf.ir_iterations);
-            worst_rel = std::max(worst_rel, inf.last_correction);
-        }
+        hps_info inf{};
+        TRY(solve_one(op, b, d, j, ur, st, &inf));
+        worst_it = std::max(worst_it, inf.ir_iterations);
+        worst_rel = std::max(worst_rel, inf.last_correction);
     }
     if (info) {
         HPS_HIP(hipStreamSynchronize(st));
@@ -196,26 +202,119 @@ static int enqueue_step(ark_ctx *c, double *u, const double *q_stages, const dou
     return HPS_OK;
 }
 
-extern "C" int ark_step(ark_ctx *c, double t, double *u, const double *q_stages, const double *q_space,
-                        const double *q_time, const double *f_stages, void *stream) {
-    CHECK_ARG(c != nullptr && u != nullptr, "ctx and u are required");
-    CHECK_ARG(std::isfinite(t), "t must be finite");
-    CHECK_ARG(!(q_stages && q_space), "give q_stages or q_space/q_time, not both");
-    CHECK_ARG(!q_space || q_time, "q_space needs q_time (host array of s values)");
-    TRY(check_device_ptr(u, "u"));
-    TRY(check_device_ptr(q_stages, "q_stages"));
-    TRY(check_device_ptr(q_space, "q_space"));
-    TRY(check_device_ptr(f_stages, "f_stages"));
-    hipStream_t st = (hipStream_t)stream;
+// One step of the slope formulation with flux-jump penalisation (Sec. 3.1):
+//   pen = -[[u^n]]/dt (flux_alpha - flux_beta of u^n), the flux jump every slope gets;
+//   k_1: interior L u^n + q_1, boundary fdot_1, interface values from the penalised
+//        flux condition (identity equation on the tree: the line solves);
+//   l_i = g(u^n + dt sum_{j<=i} a_ij k_j + dt sum_{j<i} ahat_ij l_j), zero on the boundary;
+//   (I - gamma dt L) k_i = L u^n + dt sum_{j<i} (a_ij L k_j + ahat_ij L l_j) + q_i with
+//        k_i = fdot_i on the boundary and flux jump pen;
+//   u^{n+1} = u^n + dt sum_j (b_j k_j + bhat_j l_j) at every node.
+static int enqueue_slope_step(ark_ctx *c, double *u, const double *q_stages, const double *q_space,
+                              const double *f_dot, hipStream_t st) {
     hps_op *op = c->op;
+    const int s = c->s;
+    const int64_t n = op->n_int, N = op->N;
+    const bool ir = (op->flags & HPS_FP32_IR) != 0;
+    const bool nl = c->g.kind != 0;
+    const GPoly gp{c->g.kind, c->g.g0, c->g.g1, c->g.g2, c->g.g3};
+    const GPoly none{0, 0, 0, 0, 0};
+    const double dt = c->dt;
+    double *K = c->K, *Ls = c->Ls;
+    auto kv = [&](int j) { return K + (int64_t)j * N; };
+    auto lv = [&](int j) { return Ls + (int64_t)j * N; };
+    auto Lk = [&](int j) { return c->Lk + (int64_t)j * n; };
+    auto Ll = [&](int j) { return c->Ll + (int64_t)j * n; };
+    auto fd = [&](int i) { return f_dot ? f_dot + (int64_t)i * op->n_bdry : nullptr; };
+    auto q_of = [&](int i) -> const double * { return q_stages ? q_stages + (int64_t)i * n : q_space; };
+    auto qs_of = [&](int i) -> const double * { return q_space ? c->qt_dev + i : nullptr; };
+    const double *pen = op->n_iface ? c->pen : nullptr;
+    // L u^n and the penalised jump
+    TRY(launch_eval(op, u, c->Lun, true, st));
+    if (pen) TRY(launch_flux_jump(op, 1.0 / dt, c->pen, st));
+    // k_1: interior values, interior flux parts (edges zero), boundary and interface values
+    {
+        const double *v[1] = {c->Lun};
+        const double cf[1] = {1.0};
+        TRY(launch_lincomb(v, cf, 1, q_of(0), qs_of(0), &none, kv(0), n, st));
+        TRY(launch_zero(kv(0) + n, N - n, st));
+        TRY(launch_eval(op, kv(0), nullptr, true, st));
+        TRY(launch_interface_lines(op, kv(0), fd(0), st, pen));
+        TRY(launch_eval(op, kv(0), Lk(0), false, st));
+    }
+    auto make_l = [&](int i) -> int {   // l_i and L l_i
+        const double *v[kMaxLinComb];
+        double cf[kMaxLinComb];
+        int m = 0;
+        v[m] = u;
+        cf[m++] = 1.0;
+        for (int j = 0; j <= i; ++j) {
+            v[m] = kv(j);
+            cf[m++] = i == 0 ? 0.0 : dt * c->A[i * s + j];
+        }
+        for (int j = 0; j < i; ++j) {
+            v[m] = lv(j);
+            cf[m++] = dt * c->Ah[i * s + j];
+        }
+        TRY(launch_lincomb(v, cf, m, nullptr, nullptr, &gp, lv(i), N, st));
+        TRY(launch_scatter_boundary(op, nullptr, lv(i), st));
+        TRY(launch_eval(op, lv(i), Ll(i), false, st));
+        return HPS_OK;
+    };
+    if (nl) TRY(make_l(0));
+    for (int i = 1; i < s; ++i) {
+        const double *v[kMaxLinComb];
+        double cf[kMaxLinComb];
+        int m = 0;
+        v[m] = c->Lun;
+        cf[m++] = 1.0;
+        for (int j = 0; j < i; ++j) {
+            v[m] = Lk(j);
+            cf[m++] = dt * c->A[i * s + j];
+            if (nl) {
+                v[m] = Ll(j);
+                cf[m++] = dt * c->Ah[i * s + j];
+            }
+        }
+        TRY(launch_lincomb(v, cf, m, q_of(i), qs_of(i), &none, c->srhs, n, st));
+        TRY(solve_one(op, c->srhs, fd(i), pen, kv(i), st, nullptr));
+        TRY(launch_eval(op, kv(i), Lk(i), false, st));
+        if (nl) TRY(make_l(i));
+    }
+    const double *v[kMaxLinComb];
+    double cf[kMaxLinComb];
+    int m = 0;
+    v[m] = u;
+    cf[m++] = 1.0;
+    for (int j = 0; j < s; ++j) {
+        v[m] = kv(j);
+        cf[m++] = dt * c->b[j];
+        if (nl) {
+            v[m] = lv(j);
+            cf[m++] = dt * c->bh[j];
+        }
+    }
+    (void)ir;
+    return launch_lincomb(v, cf, m, nullptr, nullptr, &none, u, N, st);
+}
+
+// Enqueue one step of either formulation.  The FP64 step has no host synchronisation, so
+// it is captured once into a HIP graph and replayed while the formulation and the array
+// arguments repeat.  The refinement loop of FP32_IR waits on the host and runs eagerly; so
+// does a profiled step.
+static int run_step(ark_ctx *c, int mode, double *u, const double *q_stages, const double *q_space,
+                    const double *q_time, const double *f, hipStream_t st) {
+    hps_op *op = c->op;
+    auto enqueue = [&](hipStream_t s2) {
+        return mode == 0 ? enqueue_step(c, u, q_stages, q_space, q_time, f, s2)
+                         : enqueue_slope_step(c, u, q_stages, q_space, f, s2);
+    };
     if (q_space) TRY(launch_set_values(c->qt_dev, q_time, c->s, st));
-    // The FP64 step has no host synchronisation, so it is captured once into a HIP graph
-    // and replayed while its array arguments repeat.  The
-    // refinement loop of FP32_IR waits on the host and runs eagerly; so does a profiled step.
     const char *env = getenv("HPS_GRAPHS");
     const bool graphs = !(env && env[0] == '0') && !(op->flags & HPS_FP32_IR) && !op->prof.on;
-    if (!graphs) return enqueue_step(c, u, q_stages, q_space, q_time, f_stages, st);
-    const std::vector<uintptr_t> key = {(uintptr_t)u, (uintptr_t)q_stages, (uintptr_t)q_space, (uintptr_t)f_stages};
+    if (!graphs) return enqueue(st);
+    const std::vector<uintptr_t> key = {(uintptr_t)mode, (uintptr_t)u, (uintptr_t)q_stages, (uintptr_t)q_space,
+                                        (uintptr_t)f};
     if (!c->gexec || key != c->gkey) {
         if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
         if (c->graph) (void)hipGraphDestroy(c->graph);
@@ -226,7 +325,7 @@ extern "C" int ark_step(ark_ctx *c, double t, double *u, const double *q_stages,
         // instantiated graph is then launched on the caller's stream
         if (!c->cap_stream) HPS_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
         HPS_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
-        int rc = enqueue_step(c, u, q_stages, q_space, q_time, f_stages, c->cap_stream);
+        int rc = enqueue(c->cap_stream);
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
         if (rc) {
@@ -240,4 +339,31 @@ extern "C" int ark_step(ark_ctx *c, double t, double *u, const double *q_stages,
     }
     HPS_HIP(hipGraphLaunch(c->gexec, st));
     return HPS_OK;
+}
+
+static int check_step_args(ark_ctx *c, double t, double *u, const double *q_stages, const double *q_space,
+                           const double *q_time, const double *f) {
+    CHECK_ARG(c != nullptr && u != nullptr, "ctx and u are required");
+    CHECK_ARG(std::isfinite(t), "t must be finite");
+    CHECK_ARG(!(q_stages && q_space), "give q_stages or q_space/q_time, not both");
+    CHECK_ARG(!q_space || q_time, "q_space needs q_time (host array of s values)");
+    TRY(check_device_ptr(u, "u"));
+    TRY(check_device_ptr(q_stages, "q_stages"));
+    TRY(check_device_ptr(q_space, "q_space"));
+    TRY(check_device_ptr(f, "boundary data"));
+    return HPS_OK;
+}
+
+extern "C" int ark_step(ark_ctx *c, double t, double *u, const double *q_stages, const double *q_space,
+                        const double *q_time, const double *f_stages, void *stream) {
+    TRY(check_step_args(c, t, u, q_stages, q_space, q_time, f_stages));
+    return run_step(c, 0, u, q_stages, q_space, q_time, f_stages, (hipStream_t)stream);
+}
+
+extern "C" int ark_step_slope(ark_ctx *c, double t, double *u, const double *q_stages, const double *q_space,
+                              const double *q_time, const double *fdot_stages, void *stream) {
+    TRY(check_step_args(c, t, u, q_stages, q_space, q_time, fdot_stages));
+    CHECK_ARG(c->s <= 8, "the slope step takes at most 8 stages");
+    TRY(ark_slope_workspace(c));
+    return run_step(c, 1, u, q_stages, q_space, q_time, fdot_stages, (hipStream_t)stream);
 }

@@ -123,6 +123,12 @@ struct ark_ctx {
     double *rhs = nullptr;                // device [n_int] (FP32_IR stage right-hand side)
     double *stage_u = nullptr;            // device [N] (FP32_IR stage solution)
     double *qt_dev = nullptr;             // device [s]: time factors of a separable source
+    // slope formulation (allocated on its first step): slopes k_j [s][N] and l_j [s][N]
+    // (l only with g), L k_j and L l_j [s][n_int], L u^n [n_int], the stage right-hand
+    // side [n_int] and the penalised flux jumps [n_iface]
+    double *K = nullptr, *Ls = nullptr, *Lk = nullptr, *Ll = nullptr, *Lun = nullptr, *srhs = nullptr,
+           *pen = nullptr;
+    int graph_mode = 0;                   // formulation of the captured step (0 stage, 1 slope)
     // the FP64 step is replayed from a captured HIP graph while its arguments repeat
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -208,11 +214,18 @@ int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st
 int launch_levels(const hps_op *op, bool fp32, const double *jump, const double *dirichlet, hipStream_t st);
 // step completion after the interior update: boundary data f(t + dt), then the interface
 // values from flux continuity along every grid line (reads the leaf edge-flux parts)
-int launch_interface_lines(const hps_op *op, double *u, const double *f_end, hipStream_t st);
+int launch_interface_lines(const hps_op *op, double *u, const double *f_end, hipStream_t st,
+                           const double *jump = nullptr);
 int launch_residual(const hps_op *op, const double *u, const double *rhs, const double *jump,
                     double *r_int, double *r3, hipStream_t st);
 int launch_scatter_boundary(const hps_op *op, const double *f, double *u, hipStream_t st);
 int launch_zero(double *p, int64_t n, hipStream_t st);
+constexpr int kMaxLinComb = 24;
+int launch_lincomb(const double *const *v, const double *c, int nv, const double *q, const double *q_scale_ptr,
+                   const GPoly *g, double *out, int64_t n, hipStream_t st);
+int launch_eval(const hps_op *op, const double *v, double *Lu, bool flux, hipStream_t st);
+int launch_flux_jump(const hps_op *op, double scale, double *r3, hipStream_t st);
+int ark_slope_workspace(ark_ctx *c);
 int launch_set_values(double *dst, const double *vals, int n, hipStream_t st);   // n <= 8, vals on the host
 
 // build --------------------------------------------------------------------------------

@@ -84,13 +84,12 @@ __device__ __forceinline__ double poly_g(const GPoly &g, double u) {
     return g.g0 + u * (g.g1 + u * (g.g2 + u * g.g3));
 }
 
+// One leaf (heap index `leaf`) of one operator: the down phase of the stage that ends here
+// and the up phase of the stage that starts here, as selected by DN and UPM.
 template <typename T, int DN, int UPM>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_leaf(LeafArgs a) {
+__device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned char *smem, double *red,
+                                          double (*nred)[NT / 64]) {
     constexpr int VW = 16 / sizeof(T);
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[NT];
-    __shared__ double nred[2][NT / 64];
-    const int leaf = blockIdx.x;
     const int q = a.geo.q, p = a.geo.p, q2 = q * q, nb = 4 * q;
     const int li = a.leaf_ij[2 * leaf], lj = a.leaf_ij[2 * leaf + 1];
     const int64_t base = ((int64_t)lj * a.geo.n1 + li) * q2;
@@ -289,6 +288,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
         }
         a.h_out[(int64_t)leaf * nb + k] = h;
     }
+}
+
+template <typename T, int DN, int UPM>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_leaf(LeafArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT];
+    __shared__ double nred[2][NT / 64];
+    leaf_body<T, DN, UPM>(a, blockIdx.x, smem, red, nred);
 }
 
 // =======================================================================================

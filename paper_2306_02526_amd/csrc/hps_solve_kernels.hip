@@ -244,10 +244,7 @@ struct EvalArgs {
     LeafGeo geo;
     const double *u;
     const double *D, *D2, *coef;
-    double *Lu, *F;
-    const double *q_src;
-    double q_scale;
-    GPoly g;
+    double *Lu;                 // L u at interior nodes, or null
     // residual mode
     const double *rhs;
     double gamma_dt;
@@ -272,13 +269,11 @@ __global__ __launch_bounds__(NT) void k_eval(EvalArgs a) {
         if (a.rhs) {
             // refinement residual of (I - gamma_dt L) u = rhs at interior nodes
             a.r_int[gi] = a.rhs[gi] - (u - a.gamma_dt * Lu);
-        } else {
+        } else if (a.Lu) {
             a.Lu[gi] = Lu;
-            const double qv = a.q_src ? a.q_scale * a.q_src[gi] : 0.0;
-            a.F[gi] = qv + gpoly(a.g, u);
         }
     }
-    if (a.rhs) {
+    if (a.flux) {
         // coordinate-direction fluxes on the four leaf edges, [leaf][e][m]
         for (int k = threadIdx.x; k < 4 * q; k += NT) {
             const int e = k / q, m = k % q;
@@ -295,7 +290,8 @@ __global__ __launch_bounds__(NT) void k_eval(EvalArgs a) {
 }
 
 // interface residual r3 = jump - (flux_alpha - flux_beta), interface-indexed
-__global__ void k_jump(LeafGeo g, const double *flux, const double *jump, double *r3, int64_t n_iface) {
+__global__ void k_jump(LeafGeo g, const double *flux, const double *jump, double scale, double *r3,
+                       int64_t n_iface) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_iface) return;
     const int q = g.q;
@@ -319,7 +315,7 @@ __global__ void k_jump(LeafGeo g, const double *flux, const double *jump, double
     }
     const double fa = flux[((int64_t)ja * g.n1 + ia) * 4 * q + ea * q + m];
     const double fb = flux[((int64_t)jb * g.n1 + ib) * 4 * q + eb * q + m];
-    r3[t] = (jump ? jump[t] : 0.0) - (fa - fb);
+    r3[t] = scale * ((jump ? jump[t] : 0.0) - (fa - fb));
 }
 
 // =======================================================================================
@@ -349,6 +345,7 @@ struct LineArgs {
     const double *D;          // p*p
     const double *cp;         // Thomas factors: cp[k], k = 1..nmax-1
     const double *inv_den;    // 1 / (diag - lower cp[k-1])
+    const double *jump;       // flux_alpha - flux_beta per interface node (interface order) or null
 };
 
 // One thread per grid line; the recursion carries d_{k-1} and e_{k+1} in registers and
@@ -376,6 +373,10 @@ __global__ void k_interface_lines(LineArgs a) {
     const int64_t lstride = vert ? 4 * q : (int64_t)g.n1 * 4 * q;
     const int64_t l0 = (vert ? (int64_t)line * g.n1 * 4 * q : (int64_t)line * 4 * q) + m0;
     const int elo = vert ? 0 : 2, ehi = vert ? 1 : 3;   // left/right or bottom/top sides
+    // interface index of the node on grid line k: vertical edges first, by line k-1
+    const int64_t j0 = vert ? (int64_t)line * q + m0 : (int64_t)(g.n1 - 1) * g.n2 * q + (int64_t)line * q + m0;
+    const int64_t jstride = vert ? (int64_t)g.n2 * q : (int64_t)g.n1 * q;
+    const double *__restrict__ jump = a.jump;
     const double lower = a.D[(p - 1) * p + 0];
     const double upper = -a.D[0 * p + (p - 1)];
     const double e0 = u[u0], en = u[u0 + (int64_t)n * ustride];
@@ -396,6 +397,7 @@ __global__ void k_interface_lines(LineArgs a) {
             const int k = k0 + c;
             if (k < n) {
                 double r = fl[c] - fh[c];
+                if (jump) r += jump[j0 + (int64_t)(k - 1) * jstride];
                 if (k == 1) r -= lower * e0;
                 if (k == n - 1) r -= upper * en;
                 const double d = (r - (k > 1 ? lower * dprev : 0.0)) * id[c];
@@ -521,8 +523,10 @@ __global__ __launch_bounds__(NT) void k_root(LevelArgs up, LevelArgs dn) {
     T *xs2 = cv.take<T>(SG2);
     T *part1 = cv.take<T>((size_t)up.pn.G * up.pn.rp * VW);
     T *part2 = cv.take<T>((size_t)dn.pn.G * dn.pn.rp * VW);
-    PanelStream<T, PF, UNR> ps;
+    // both operators' first loads are issued before the inputs are gathered
+    PanelStream<T, PF, UNR> ps, ps2;
     ps.start(reinterpret_cast<const T *>(up.pn.data) + (int64_t)tile * up.pn.tile_elems, up.pn.rp, up.pn.G, up.pn.S);
+    ps2.start(reinterpret_cast<const T *>(dn.pn.data) + (int64_t)tile * dn.pn.tile_elems, dn.pn.rp, dn.pn.G, dn.pn.S);
     const int rows = up.pn.rp * VW;   // the same row tiling for X and S
     const int myrow = tile * rows + threadIdx.x;
     int64_t ia = -1, ib = -1;
@@ -551,8 +555,7 @@ __global__ __launch_bounds__(NT) void k_root(LevelArgs up, LevelArgs dn) {
     }
     __syncthreads();
     ps.finish(xs1, part1);
-    ps.start(reinterpret_cast<const T *>(dn.pn.data) + (int64_t)tile * dn.pn.tile_elems, dn.pn.rp, dn.pn.G, dn.pn.S);
-    ps.finish(xs2, part2);
+    ps2.finish(xs2, part2);
     __syncthreads();
     // deterministic sums over the column groups of both products, then u_3 = S u_12 + X d
     const int nsl1 = min(up.pn.G, NT / rows), nsl2 = min(dn.pn.G, NT / rows);
@@ -665,13 +668,14 @@ int launch_residual(const hps_op *op, const double *u, const double *rhs, const 
     HPS_LAUNCHED();
     if (op->n_iface > 0) {
         hipLaunchKernelGGL(k_jump, dim3(nblk(op->n_iface)), dim3(NT), 0, st, geo_of(op),
-                           (const double *)op->ir_flux, jump, r3, op->n_iface);
+                           (const double *)op->ir_flux, jump, 1.0, r3, op->n_iface);
         HPS_LAUNCHED();
     }
     return HPS_OK;
 }
 
-int launch_interface_lines(const hps_op *op, double *u, const double *f_end, hipStream_t st) {
+int launch_interface_lines(const hps_op *op, double *u, const double *f_end, hipStream_t st,
+                           const double *jump) {
     ProfScope ps_(&op->prof, KF_LINES, st);
     int rc = launch_scatter_boundary(op, f_end, u, st);
     if (rc) return rc;
@@ -682,6 +686,7 @@ int launch_interface_lines(const hps_op *op, double *u, const double *f_end, hip
     la.D = op->D;
     la.cp = op->tri_cp;
     la.inv_den = op->tri_cp + op->tri_stride;
+    la.jump = jump;
     const int nsys = op->grid.n2 * op->q + op->grid.n1 * op->q;
     hipLaunchKernelGGL(k_interface_lines, dim3(nblk(nsys, 64)), dim3(64), 0, st, la);
     HPS_LAUNCHED();
@@ -704,6 +709,77 @@ int launch_set_values(double *dst, const double *vals, int n, hipStream_t st) {
     Values8 v{};
     for (int i = 0; i < n; ++i) v.v[i] = vals[i];
     hipLaunchKernelGGL(k_set_values, dim3(1), dim3(64), 0, st, dst, v, n);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+// out = g(sum_k c_k v_k + qs q) over n entries (g applied when g.kind != 0); qs is the
+// device scalar *q_scale_ptr when given, else 1.  out may alias one of the inputs.
+struct LinComb {
+    const double *v[kMaxLinComb];
+    double c[kMaxLinComb];
+    int nv;
+    const double *q;
+    const double *q_scale_ptr;
+    GPoly g;
+    double *out;
+    int64_t n;
+};
+
+__global__ void k_lincomb(LinComb a) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    double s = 0.0;
+    for (int k = 0; k < a.nv; ++k) s = fma(a.c[k], a.v[k][i], s);
+    if (a.q) s = fma(a.q_scale_ptr ? *a.q_scale_ptr : 1.0, a.q[i], s);
+    if (a.g.kind) s = gpoly(a.g, s);
+    a.out[i] = s;
+}
+
+int launch_lincomb(const double *const *v, const double *c, int nv, const double *q, const double *q_scale_ptr,
+                   const GPoly *g, double *out, int64_t n, hipStream_t st) {
+    if (n <= 0) return HPS_OK;
+    if (nv > kMaxLinComb) {
+        hps_set_error("internal: %d terms exceed the %d a combination takes", nv, kMaxLinComb);
+        return HPS_EINVAL;
+    }
+    LinComb a{};
+    for (int k = 0; k < nv; ++k) {
+        a.v[k] = v[k];
+        a.c[k] = c[k];
+    }
+    a.nv = nv;
+    a.q = q;
+    a.q_scale_ptr = q_scale_ptr;
+    if (g) a.g = *g;
+    a.out = out;
+    a.n = n;
+    hipLaunchKernelGGL(k_lincomb, dim3(nblk(n)), dim3(NT), 0, st, a);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+// L v at interior nodes (into Lu, if given) and, when `flux` is set, the coordinate-
+// direction fluxes of v on every leaf edge into op->ir_flux, from a canonical vector v.
+int launch_eval(const hps_op *op, const double *v, double *Lu, bool flux, hipStream_t st) {
+    EvalArgs a{};
+    a.geo = geo_of(op);
+    a.u = v;
+    a.D = op->D;
+    a.D2 = op->D2;
+    a.coef = op->coef;
+    a.Lu = Lu;
+    a.flux = flux ? op->ir_flux : nullptr;
+    hipLaunchKernelGGL(k_eval, dim3(op->nleaves), dim3(NT), 0, st, a);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+// r3 = -scale (flux_alpha - flux_beta) per interface node, from the fluxes in op->ir_flux
+int launch_flux_jump(const hps_op *op, double scale, double *r3, hipStream_t st) {
+    if (op->n_iface <= 0) return HPS_OK;
+    hipLaunchKernelGGL(k_jump, dim3(nblk(op->n_iface)), dim3(NT), 0, st, geo_of(op), (const double *)op->ir_flux,
+                       (const double *)nullptr, scale, r3, op->n_iface);
     HPS_LAUNCHED();
     return HPS_OK;
 }

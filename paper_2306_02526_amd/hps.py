@@ -21,7 +21,7 @@ ERRORS = {-1: "HPS_EINVAL", -2: "HPS_ENOMEM", -3: "HPS_EDEVICE", -4: "HPS_ESINGU
 # every entry point declared in include/hps.h, include/hps_batch.h and include/hps_serve.h
 EXPORTED = ["hps_last_error", "hps_num_nodes", "hps_nodes", "hps_build", "hps_op_bytes",
             "hps_solve", "hps_free", "hps_profile_enable", "hps_profile_read", "ark_create", "ark_step", "ark_stage_solves_per_step",
-            "ark_free", "hps_solve_batched", "ark_step_batched", "hps_batch_streams",
+            "ark_free", "ark_step_slope", "hps_solve_batched", "ark_step_batched", "hps_batch_streams",
             "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_release", "srv_get_stats", "srv_destroy"]
 
 
@@ -115,6 +115,8 @@ def lib():
     L.ark_create.argtypes = [vp, P(ArkTableau), dbl, P(ArkG), P(vp)]
     L.ark_step.restype = i32
     L.ark_step.argtypes = [vp, dbl, vp, vp, vp, P(dbl), vp, vp]
+    L.ark_step_slope.restype = i32
+    L.ark_step_slope.argtypes = [vp, dbl, vp, vp, vp, P(dbl), vp, vp]
     L.ark_stage_solves_per_step.restype = i32
     L.ark_stage_solves_per_step.argtypes = [vp]
     L.ark_free.restype = None
@@ -305,6 +307,21 @@ def ark_step(ctx, t, u, q_stages=None, q_space=None, q_time=None, f_stages=None,
     _check(lib().ark_step(ctx.handle, float(t), _dptr(u, op.N, "u"),
                           _dptr(q_stages, s * op.n_int, "q_stages"), _dptr(q_space, op.n_int, "q_space"),
                           qt, _dptr(f_stages, (s + 1) * op.n_bdry, "f_stages"), _stream(stream)))
+    return u
+
+
+def ark_step_slope(ctx, t, u, q_stages=None, q_space=None, q_time=None, fdot_stages=None, stream=None):
+    """One slope-formulation step (flux-jump penalised); fdot_stages [s][n_bdry] or None."""
+    op, s = ctx.op, ctx.s
+    qt = None
+    if q_time is not None:
+        qt_arr = np.ascontiguousarray(np.asarray(q_time, dtype=np.float64))
+        if qt_arr.size != s:
+            raise ValueError("q_time needs one value per stage")
+        qt = qt_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    _check(lib().ark_step_slope(ctx.handle, float(t), _dptr(u, op.N, "u"),
+                                _dptr(q_stages, s * op.n_int, "q_stages"), _dptr(q_space, op.n_int, "q_space"),
+                                qt, _dptr(fdot_stages, s * op.n_bdry, "fdot_stages"), _stream(stream)))
     return u
 
 

@@ -7,6 +7,13 @@ for _v in ("OPENBLAS_NUM_THREADS", "OMP_NUM_THREADS", "MKL_NUM_THREADS"):
 
 import pytest  # noqa: E402
 
+try:   # also when a BLAS library was loaded before the variables above were set
+    import threadpoolctl  # noqa: E402
+
+    _BLAS_LIMIT = threadpoolctl.threadpool_limits(limits=1, user_api="blas")
+except ImportError:
+    _BLAS_LIMIT = None
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

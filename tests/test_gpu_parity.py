@@ -5,6 +5,7 @@ FP64 path).  FP32 operators with FP64 iterative refinement: <= 1e-10.
 """
 import math
 import sys
+import time
 
 import numpy as np
 import pytest
@@ -116,6 +117,50 @@ def test_solve_exact_for_polynomials(torch):
     bi = og.boundary_indices()
     sol = hps.hps_solve(op, torch.tensor(body, device="cuda"), torch.tensor(u[bi], device="cuda")).cpu().numpy()
     assert rel(sol, u) <= 1e-11
+
+
+@pytest.mark.parametrize("n1,n2,p,flags", [(64, 64, 16, hps.HPS_FP64), (64, 64, 16, hps.HPS_FP32_IR),
+                                          (128, 32, 12, hps.HPS_FP64), (128, 128, 24, hps.HPS_FP64)])
+def test_polynomial_exact_at_large_sizes(torch, n1, n2, p, flags):
+    """Collocation reproduces a polynomial of degree <= p-1 in each variable exactly, so the
+    solve must return it to rounding at any size: the benchmark grid (both precisions) and
+    the largest grids the library accepts (n1 n2 = 2^14; at p = 24 the top levels split
+    their input vectors into column chunks)."""
+    say(f"[solve] polynomial at {n1}x{n2} p={p} flags={flags}")
+    gdt = 2.5e-4
+    h = 1.0 / max(n1, n2)
+    g = hps.make_grid(0, n1 * h, 0, n2 * h, n1, n2, p)
+    N, n_int, n_iface, n_bdry = hps.hps_num_nodes(g)
+    x, y = hps.hps_nodes(g)
+    xi, yi = x[:n_int], y[:n_int]
+    co = var_coefs(xi, yi)
+    terms = [(1.0, 0, 0), (0.7, 3, 2), (-1.3, p - 1, 1), (0.4, 2, p - 2), (0.9, p - 1, p - 1)]
+
+    def mono(c, a, b, dx, dy, X, Y):
+        ca = 1.0
+        for k in range(dx):
+            ca *= a - k
+        cb = 1.0
+        for k in range(dy):
+            cb *= b - k
+        if ca == 0.0 or cb == 0.0:
+            return np.zeros_like(X)
+        return c * ca * cb * X ** (a - dx) * Y ** (b - dy)
+
+    u = sum(mono(c, a, b, 0, 0, x, y) for c, a, b in terms)
+    D = lambda dx, dy: sum(mono(c, a, b, dx, dy, xi, yi) for c, a, b in terms)
+    Lu = co["cxx"] * D(2, 0) + co["cyy"] * D(0, 2) + co["cx"] * D(1, 0) + co["cy"] * D(0, 1) + co["c0"] * u[:n_int]
+    body = u[:n_int] - gdt * Lu
+    bidx = Grid(0, n1 * h, 0, n2 * h, n1, n2, p).boundary_indices()
+    dev = {k: torch.tensor(v, device="cuda") for k, v in co.items()}
+    t0 = time.perf_counter()
+    op = hps.hps_build(g, dev, gdt, flags)
+    tb = time.perf_counter() - t0
+    sol = hps.hps_solve(op, torch.tensor(body, device="cuda"), torch.tensor(u[bidx], device="cuda"))
+    e = rel(sol.cpu().numpy(), u)
+    say(f"   build {tb:.1f} s, operators {op.bytes()[1] / 1e9:.1f} GB, rel err {e:.2e}")
+    op.free()
+    assert e <= 1e-10
 
 
 def test_build_rejects_mismatched_step(torch):
@@ -277,9 +322,12 @@ def test_full_size_allen_cahn_step_matches_oracle(torch):
     ug = torch.tensor(u0, device="cuda")
     hps.ark_step(ctx, 0.0, ug)
     say("   GPU step done; building the oracle")
+    t0 = time.perf_counter()
     ark = ARK(HPS(og, co, gdt), co, tableau_float(ark436l2sa()), dt, workloads.AllenCahn.gpoly)
-    say("   oracle built; stepping")
+    say(f"   oracle built in {time.perf_counter() - t0:.1f} s; stepping")
+    t0 = time.perf_counter()
     ur = ark.step(u0)
+    say(f"   oracle step {time.perf_counter() - t0:.1f} s")
     e = rel(ug.cpu().numpy(), ur)
     say(f"   rel err {e:.2e}")
     assert e <= TOL64
