@@ -4,12 +4,21 @@
  * A batch holds problems of different grids, orders p, gamma*dt and precision
  * (each with its own hps_op / ark_ctx built by hps.h).  Each problem is one
  * instance of the per-stage HPS solve of Sec. 2.1 (Algorithm 1) or of one step
- * of the stage formulation of Sec. 3.1 (eqs. 9-11); the batch entry points only
- * schedule them: the problems are spread over a small pool of library-owned HIP
- * streams of the current device (default priority), largest operator first onto
- * the least-loaded stream, so that small latency-bound problems overlap on the
- * GPU.  Problems whose handles share one hps_op are kept on one stream, in batch
- * order, because an operator's workspace serves one solve at a time.
+ * of the stage formulation of Sec. 3.1 (eqs. 9-11).
+ *
+ * ark_step_batched runs a batch of FP64 problems with distinct operators, equal
+ * stage counts, no boundary data and at least two leaves each as grouped launches:
+ * one launch per leaf phase and per tree level covers every problem (levels are
+ * aligned at the roots), so a step of the batch costs as many launches as a step of
+ * its deepest problem; the argument records are built once per set of (context, u,
+ * source) pointers and the step is replayed from a HIP graph while that set repeats.
+ * Every other batch, and hps_solve_batched, runs each problem through the
+ * single-problem entry point on a small pool of library-owned HIP streams of the
+ * current device (default priority), largest operator first onto the least-loaded
+ * stream, so that small latency-bound problems overlap; problems whose handles share
+ * one hps_op stay on one stream, in batch order, because an operator's workspace
+ * serves one solve at a time.  Either way each problem runs the kernels' arithmetic
+ * of its single call, so results are bitwise those of the single calls.
  *
  * Stream semantics: the work starts after everything already enqueued on
  * `stream` and everything enqueued on `stream` afterwards waits for all of it,

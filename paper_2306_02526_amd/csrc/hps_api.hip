@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -723,7 +724,9 @@ extern "C" int ark_create(hps_op *op, const ark_tableau *tab, double dt, const a
     CHECK_ARG(std::fabs(gam * dt - op->gamma_dt) <= 1e-14 * op->gamma_dt,
               "operator was built for gamma*dt = %.17g, tableau gives %.17g", op->gamma_dt, gam * dt);
     if (g) CHECK_ARG(g->kind == 0 || g->kind == 1, "ark_g.kind must be 0 or 1");
+    static std::atomic<uint64_t> next_uid{1};
     ark_ctx *c = new ark_ctx();
+    c->uid = next_uid++;
     c->op = op;
     c->s = s;
     c->dt = dt;

@@ -1,10 +1,12 @@
-// Batched entry points: many independent problems per call, spread over a pool of
-// library-owned HIP streams so that small problems overlap on the GPU.  Every problem
-// runs through the same entry points as a single call (hps_solve, ark_step); this file
-// only forks, assigns and joins streams.
+// Batched entry points: many independent problems per call.  FP64 time steps of problems
+// with distinct operators run as grouped launches (one launch per leaf phase and per tree
+// level for all problems); everything else runs each problem through the single-problem
+// entry points on a pool of library-owned HIP streams, so that small problems overlap.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -113,6 +115,261 @@ int run_batched(const std::vector<const hps_op *> &ops, hipStream_t caller, Fn f
     return rc;
 }
 
+// ---- all problems of a batch in one launch per phase (FP64 stage formulation) ----------
+// One launch runs a leaf phase for the leaves of every problem, one launch a tree level
+// (levels aligned at the roots), one the fused roots, one the line solves: a step of any
+// number of problems takes as many launches as a step of the largest one.  The argument
+// records live in device memory, built once per set of (context, u, source) pointers,
+// and the step is captured into a HIP graph and replayed while that set repeats.
+struct GroupPlan {
+    struct Launch {
+        int kind;            // 0 leaf phase, 1 level up, 2 level down, 3 roots, 4 boundary, 5 lines
+        size_t a, a2, base;  // offsets of the records (a2: downward root records) and bases
+        int cnt, total;
+        size_t lds;
+        int down, up;
+    };
+    std::vector<uintptr_t> key;
+    int s = 0, n = 0;
+    unsigned char *dmem = nullptr;
+    double *qt = nullptr;                // device [n][8] time factors of separable sources
+    std::vector<Launch> leaf, sweep;
+    Launch zb{}, lines{};
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    uint64_t last_use = 0;
+};
+
+std::mutex g_plans_mu;
+std::vector<GroupPlan *> g_plans;   // a few recent plans (each set of problems has one)
+uint64_t g_plan_clock = 0;
+
+void free_plan(GroupPlan *p) {
+    if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap) (void)hipStreamDestroy(p->cap);
+    if (p->dmem) (void)hipFree(p->dmem);
+    if (p->qt) (void)hipFree(p->qt);
+    delete p;
+}
+
+struct HostTables {
+    std::vector<unsigned char> bytes;
+    size_t put(const void *src, size_t n) {
+        const size_t off = (bytes.size() + 255) & ~size_t(255);
+        bytes.resize(off + n);
+        if (src) std::memcpy(bytes.data() + off, src, n);
+        return off;
+    }
+};
+
+bool groupable(ark_ctx *const *ctx, int nprob, const double *const *q_stages, const double *const *f_stages) {
+    const char *env = getenv("HPS_GROUP");
+    if (env && env[0] == '0') return false;
+    if (nprob < 2) return false;
+    std::map<const hps_op *, int> seen;
+    for (int b = 0; b < nprob; ++b) {
+        const hps_op *op = ctx[b]->op;
+        if (op->flags & HPS_FP32_IR) return false;
+        if (op->prof.on || op->L < 1 || ctx[b]->s != ctx[0]->s) return false;
+        if (f_stages && f_stages[b]) return false;
+        if (seen[op]++) return false;   // one operator's workspace serves one problem at a time
+    }
+    (void)q_stages;
+    return true;
+}
+
+int build_plan(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, const double *const *q_stages,
+               const double *const *q_space) {
+    P->n = n;
+    P->s = ctx[0]->s;
+    HPS_HIP(hipMalloc(&P->qt, sizeof(double) * 8 * n));
+    HPS_HIP(hipMemset(P->qt, 0, sizeof(double) * 8 * n));
+    HostTables T;
+    std::vector<int> base(n + 1);
+    // leaf phases
+    for (int k = 0; k < P->s; ++k) {
+        GroupPlan::Launch L{};
+        L.kind = 0;
+        const size_t rs = leaf_args_size();
+        std::vector<unsigned char> recs(rs * n);
+        base[0] = 0;
+        for (int b = 0; b < n; ++b) {
+            LeafPhase ph;
+            step_phase(ctx[b], k, u[b], q_stages ? q_stages[b] : nullptr, q_space ? q_space[b] : nullptr,
+                       P->qt + 8 * b, ph);
+            size_t lds = 0;
+            TRY(fill_leaf_args(ctx[b]->op, ph, recs.data() + rs * b, &lds));
+            L.lds = std::max(L.lds, lds);
+            L.down = ph.down;
+            L.up = ph.up;
+            base[b + 1] = base[b] + ctx[b]->op->nleaves;
+        }
+        L.a = T.put(recs.data(), recs.size());
+        L.base = T.put(base.data(), sizeof(int) * (n + 1));
+        L.cnt = n;
+        L.total = base[n];
+        P->leaf.push_back(L);
+    }
+    // one sweep: upward levels aligned at the roots, the fused roots, downward levels
+    int Lmax = 0;
+    for (int b = 0; b < n; ++b) Lmax = std::max(Lmax, ctx[b]->op->L);
+    const size_t ls = level_record_size();
+    auto level_launch = [&](int l, bool up) -> int {
+        GroupPlan::Launch L{};
+        L.kind = up ? 1 : 2;
+        std::vector<unsigned char> recs;
+        std::vector<int> bs(1, 0);
+        for (int b = 0; b < n; ++b) {
+            const hps_op *op = ctx[b]->op;
+            if (l >= op->L || (l == 0 && root_fused64(op))) continue;
+            recs.resize(recs.size() + ls);
+            int blocks = 0;
+            size_t lds = 0;
+            level_record(op, l, up, nullptr, recs.data() + recs.size() - ls, &blocks, &lds);
+            L.lds = std::max(L.lds, lds);
+            bs.push_back(bs.back() + blocks);
+        }
+        L.cnt = (int)bs.size() - 1;
+        if (L.cnt == 0) return HPS_OK;
+        L.a = T.put(recs.data(), recs.size());
+        L.base = T.put(bs.data(), sizeof(int) * bs.size());
+        L.total = bs.back();
+        P->sweep.push_back(L);
+        return HPS_OK;
+    };
+    for (int l = Lmax - 1; l >= 0; --l) TRY(level_launch(l, true));
+    {
+        GroupPlan::Launch L{};
+        L.kind = 3;
+        std::vector<unsigned char> ups, dns;
+        std::vector<int> bs(1, 0);
+        for (int b = 0; b < n; ++b) {
+            const hps_op *op = ctx[b]->op;
+            if (!root_fused64(op)) continue;
+            ups.resize(ups.size() + ls);
+            dns.resize(dns.size() + ls);
+            int blocks = 0;
+            size_t lds = 0;
+            root_records(op, nullptr, ups.data() + ups.size() - ls, dns.data() + dns.size() - ls, &blocks, &lds);
+            L.lds = std::max(L.lds, lds);
+            bs.push_back(bs.back() + blocks);
+        }
+        L.cnt = (int)bs.size() - 1;
+        if (L.cnt > 0) {
+            L.a = T.put(ups.data(), ups.size());
+            L.a2 = T.put(dns.data(), dns.size());
+            L.base = T.put(bs.data(), sizeof(int) * bs.size());
+            L.total = bs.back();
+            P->sweep.push_back(L);
+        }
+    }
+    for (int l = 0; l < Lmax; ++l) TRY(level_launch(l, false));
+    // boundary values (zero) and interface line solves of the update
+    {
+        const size_t zs = scatter_record_size(), lr = line_record_size();
+        std::vector<unsigned char> zrec(zs * n), lrec(lr * n);
+        std::vector<int> zb(n + 1, 0), lb(n + 1, 0);
+        for (int b = 0; b < n; ++b) {
+            int cnt = 0, sys = 0;
+            scatter_record(ctx[b]->op, u[b], zrec.data() + zs * b, &cnt);
+            line_record(ctx[b]->op, u[b], lrec.data() + lr * b, &sys);
+            zb[b + 1] = zb[b] + cnt;
+            lb[b + 1] = lb[b] + sys;
+        }
+        P->zb = GroupPlan::Launch{4, T.put(zrec.data(), zrec.size()), 0, T.put(zb.data(), sizeof(int) * (n + 1)),
+                                  n, zb[n], 0, 0, 0};
+        P->lines = GroupPlan::Launch{5, T.put(lrec.data(), lrec.size()), 0, T.put(lb.data(), sizeof(int) * (n + 1)),
+                                     n, lb[n], 0, 0, 0};
+    }
+    HPS_HIP(hipMalloc(&P->dmem, std::max<size_t>(T.bytes.size(), 256)));
+    HPS_HIP(hipMemcpy(P->dmem, T.bytes.data(), T.bytes.size(), hipMemcpyHostToDevice));
+    return HPS_OK;
+}
+
+int enqueue_plan(const GroupPlan *P, hipStream_t st) {
+    unsigned char *d = P->dmem;
+    auto basep = [&](const GroupPlan::Launch &L) { return reinterpret_cast<const int *>(d + L.base); };
+    auto run_sweep = [&]() -> int {
+        for (const GroupPlan::Launch &L : P->sweep) {
+            if (L.kind == 3) TRY(launch_root_group(d + L.a, d + L.a2, basep(L), L.cnt, L.total, L.lds, st));
+            else TRY(launch_level_group(d + L.a, basep(L), L.cnt, L.total, L.lds, L.kind == 1, st));
+        }
+        return HPS_OK;
+    };
+    for (int k = 0; k < P->s; ++k) {
+        if (k > 0) TRY(run_sweep());
+        const GroupPlan::Launch &L = P->leaf[k];
+        TRY(launch_leaf_group(d + L.a, basep(L), L.cnt, L.total, L.lds, L.down, L.up, st));
+    }
+    TRY(launch_zero_boundary_group(d + P->zb.a, basep(P->zb), P->zb.cnt, P->zb.total, st));
+    TRY(launch_lines_group(d + P->lines.a, basep(P->lines), P->lines.cnt, P->lines.total, st));
+    return HPS_OK;
+}
+
+int grouped_step(ark_ctx *const *ctx, int n, double *const *u, const double *const *q_stages,
+                 const double *const *q_space, const double *const *q_time, hipStream_t st) {
+    std::vector<uintptr_t> key;
+    for (int b = 0; b < n; ++b) {
+        key.push_back((uintptr_t)ctx[b]);
+        key.push_back((uintptr_t)ctx[b]->uid);
+        key.push_back((uintptr_t)u[b]);
+        key.push_back((uintptr_t)(q_stages ? q_stages[b] : nullptr));
+        key.push_back((uintptr_t)(q_space ? q_space[b] : nullptr));
+    }
+    std::lock_guard<std::mutex> g(g_plans_mu);
+    GroupPlan *P = nullptr;
+    for (GroupPlan *p : g_plans)
+        if (p->key == key) P = p;
+    if (!P) {
+        if (g_plans.size() >= 4) {
+            auto lru = std::min_element(g_plans.begin(), g_plans.end(),
+                                        [](GroupPlan *a, GroupPlan *b) { return a->last_use < b->last_use; });
+            HPS_HIP(hipStreamSynchronize(st));
+            free_plan(*lru);
+            g_plans.erase(lru);
+        }
+        P = new GroupPlan();
+        P->key = key;
+        if (int rc = build_plan(P, ctx, n, u, q_stages, q_space)) {
+            free_plan(P);
+            return rc;
+        }
+        g_plans.push_back(P);
+    }
+    P->last_use = ++g_plan_clock;
+    // separable sources: this step's time factors, copied before the (replayed) step
+    if (q_space && q_time) {
+        std::vector<double> qt(8 * (size_t)n, 0.0);
+        bool any = false;
+        for (int b = 0; b < n; ++b)
+            if (q_space[b] && q_time[b]) {
+                any = true;
+                for (int i = 0; i < P->s; ++i) qt[8 * b + i] = q_time[b][i];
+            }
+        if (any) HPS_HIP(hipMemcpyAsync(P->qt, qt.data(), sizeof(double) * qt.size(), hipMemcpyHostToDevice, st));
+    }
+    const char *env = getenv("HPS_GRAPHS");
+    if (env && env[0] == '0') return enqueue_plan(P, st);
+    if (!P->gexec) {
+        if (!P->cap) HPS_HIP(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
+        HPS_HIP(hipStreamBeginCapture(P->cap, hipStreamCaptureModeRelaxed));
+        const int rc = enqueue_plan(P, P->cap);
+        hipGraph_t gr = nullptr;
+        const hipError_t e = hipStreamEndCapture(P->cap, &gr);
+        if (rc) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return rc;
+        }
+        HPS_HIP(e);
+        P->graph = gr;
+        HPS_HIP(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
+    }
+    HPS_HIP(hipGraphLaunch(P->gexec, st));
+    return HPS_OK;
+}
+
 }  // namespace
 
 extern "C" int hps_batch_streams(void) { return kStreams; }
@@ -155,6 +412,16 @@ extern "C" int ark_step_batched(ark_ctx *const *ctx, int nprob, const double *t,
         }
         v[b] = ctx[b]->op;
     }
+    for (int b = 0; b < nprob; ++b) {
+        CHECK_ARG(std::isfinite(t[b]), "problem %d: t must be finite", b);
+        TRY(check_device_ptr(u[b], "u"));
+        if (q_stages) TRY(check_device_ptr(q_stages[b], "q_stages"));
+        if (q_space) TRY(check_device_ptr(q_space[b], "q_space"));
+        if (q_space && q_space[b]) CHECK_ARG(q_time && q_time[b], "problem %d: q_space needs q_time", b);
+        CHECK_ARG(!(q_stages && q_stages[b] && q_space && q_space[b]), "problem %d: q_stages or q_space, not both", b);
+    }
+    if (groupable(ctx, nprob, q_stages, f_stages)) return grouped_step(ctx, nprob, u, q_stages, q_space, q_time,
+                                                                       (hipStream_t)stream);
     return run_batched(v, (hipStream_t)stream, [&](int b, hipStream_t st) {
         return ark_step(ctx[b], t[b], u[b], q_stages ? q_stages[b] : nullptr,
                         q_space ? q_space[b] : nullptr, q_time ? q_time[b] : nullptr,

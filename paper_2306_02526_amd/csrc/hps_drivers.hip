@@ -115,85 +115,80 @@ extern "C" int hps_solve(hps_op *op, int nrhs, const double *body, const double 
     return HPS_OK;
 }
 
-static int enqueue_step(ark_ctx *c, double *u, const double *q_stages, const double *q_space,
-                        const double *q_time, const double *f_stages, hipStream_t st) {
-    hps_op *op = c->op;
+// The leaf launch that opens step phase k of the stage formulation: k = 0 evaluates stage 1
+// (L u^n, F_1) and assembles stage 2's right-hand side; k = 1..s-1 closes stage k+1
+// (reconstruction, L u, F) and assembles stage k+2's right-hand side, or for the last stage
+// the interior update.  qt: device time factors of a separable source (s values).
+void hps::step_phase(const ark_ctx *c, int k, double *u, const double *q_stages, const double *q_space,
+                     const double *qt, LeafPhase &ph) {
+    const hps_op *op = c->op;
     const int s = c->s;
     const int64_t n = op->n_int;
-    const bool ir = (op->flags & HPS_FP32_IR) != 0;
-    const GPoly gp{c->g.kind, c->g.g0, c->g.g1, c->g.g2, c->g.g3};
-    // source of stage i and the coefficients that assemble stage i's right-hand side
-    auto set_q = [&](LeafPhase &ph, int i) {
-        ph.g = gp;
-        ph.q_scale = 1.0;
-        ph.q_src = nullptr;
-        if (q_stages) ph.q_src = q_stages + (int64_t)i * n;
-        else if (q_space) {
-            // the time factors are written to c->qt_dev before the step (outside any
-            // captured graph), so a replayed step picks up new values
-            ph.q_src = q_space;
-            ph.q_scale_ptr = c->qt_dev + i;
-        }
-    };
-    auto set_rhs = [&](LeafPhase &ph, int i) {   // up phase: right-hand side of stage i
+    ph = LeafPhase{};
+    ph.g = GPoly{c->g.kind, c->g.g0, c->g.g1, c->g.g2, c->g.g3};
+    ph.q_scale = 1.0;
+    if (q_stages) ph.q_src = q_stages + (int64_t)k * n;
+    else if (q_space) {
+        // the time factors are written to device memory before the step (outside any
+        // captured graph), so a replayed step picks up new values
+        ph.q_src = q_space;
+        ph.q_scale_ptr = qt + k;
+    }
+    ph.Lu_out = c->Lu + (int64_t)k * n;
+    ph.F_out = c->F + (int64_t)k * n;
+    if (k == 0) {
+        ph.down = LD_EVAL;
+        ph.u_eval = u;
+    } else {
+        ph.down = LD_STAGE;
+    }
+    ph.un = u;
+    ph.Lu_in = c->Lu;
+    ph.F_in = c->F;
+    if (k + 1 < s) {          // up phase: right-hand side of stage k+2 (index k+1)
+        const int i = k + 1;
         ph.up = LU_STAGE;
-        ph.un = u;
-        ph.Lu_in = c->Lu;
-        ph.F_in = c->F;
         ph.nprev = i;
         for (int j = 0; j < i; ++j) {
             ph.ca[j] = c->dt * c->A[i * s + j];
             ph.cf[j] = c->dt * c->Ah[i * s + j];
         }
-    };
-    auto set_update = [&](LeafPhase &ph) {       // up phase: interior u^{n+1}
+    } else {                  // up phase: interior u^{n+1}
         ph.up = LU_UPDATE;
-        ph.un = u;
         ph.unew = u;
-        ph.Lu_in = c->Lu;
-        ph.F_in = c->F;
         ph.nprev = s - 1;
         for (int j = 0; j < s; ++j) {
             ph.ca[j] = c->dt * c->b[j];
             ph.cf[j] = c->dt * c->bh[j];
         }
-    };
-    // stage 1 is explicit: L u^n and F_1, fused with the right-hand side of stage 2
-    {
-        LeafPhase ph;
-        ph.down = LD_EVAL;
-        ph.u_eval = u;
-        ph.Lu_out = c->Lu;
-        ph.F_out = c->F;
-        set_q(ph, 0);
-        set_rhs(ph, 1);
-        if (ir) ph.rhs_copy = c->rhs;
-        TRY(launch_leaf(op, ir, ph, st));
     }
-    for (int i = 1; i < s; ++i) {
-        const double *fi = f_stages ? f_stages + (int64_t)i * op->n_bdry : nullptr;
-        TRY(levels(op, ir, nullptr, fi, st));
-        LeafPhase ph;
-        set_q(ph, i);
-        ph.Lu_out = c->Lu + (int64_t)i * n;
-        ph.F_out = c->F + (int64_t)i * n;
-        if (!ir) {
-            ph.down = LD_STAGE;
-        } else {
-            // FP32 stage solve, refined in FP64, then L u_i and F_i from the refined u_i
-            LeafPhase w;
-            w.down = LD_WRITE_U;
-            w.u_out = c->stage_u;
-            TRY(launch_leaf(op, true, w, st));
-            TRY(ir_refine(op, c->rhs, nullptr, c->stage_u, st, nullptr));
-            ph.down = LD_EVAL;
-            ph.u_eval = c->stage_u;
+}
+
+static int enqueue_step(ark_ctx *c, double *u, const double *q_stages, const double *q_space,
+                        const double *q_time, const double *f_stages, hipStream_t st) {
+    hps_op *op = c->op;
+    const int s = c->s;
+    const bool ir = (op->flags & HPS_FP32_IR) != 0;
+    (void)q_time;
+    for (int k = 0; k < s; ++k) {
+        if (k > 0) {
+            const double *fk = f_stages ? f_stages + (int64_t)k * op->n_bdry : nullptr;
+            TRY(levels(op, ir, nullptr, fk, st));
         }
-        if (i + 1 < s) {
-            set_rhs(ph, i + 1);
-            if (ir) ph.rhs_copy = c->rhs;
-        } else {
-            set_update(ph);
+        LeafPhase ph;
+        step_phase(c, k, u, q_stages, q_space, c->qt_dev, ph);
+        if (ir) {
+            if (k > 0) {
+                // FP32 stage solve, refined in FP64, then L u_i and F_i from the refined u_i
+                LeafPhase w;
+                w.down = LD_WRITE_U;
+                w.u_out = c->stage_u;
+                TRY(launch_leaf(op, true, w, st));
+                TRY(ir_refine(op, c->rhs, nullptr, c->stage_u, st, nullptr));
+                ph.down = LD_EVAL;
+                ph.u_eval = c->stage_u;
+            }
+            if (k + 1 < s) ph.rhs_copy = c->rhs;
         }
         TRY(launch_leaf(op, ir, ph, st));
     }

@@ -115,6 +115,7 @@ struct hps_op {
 
 struct ark_ctx {
     hps_op *op = nullptr;
+    uint64_t uid = 0;                     // unique per context created in this process
     int s = 0;
     double dt = 0;
     std::vector<double> A, b, c, Ah, bh;
@@ -226,6 +227,26 @@ int launch_lincomb(const double *const *v, const double *c, int nv, const double
 int launch_eval(const hps_op *op, const double *v, double *Lu, bool flux, hipStream_t st);
 int launch_flux_jump(const hps_op *op, double scale, double *r3, hipStream_t st);
 int ark_slope_workspace(ark_ctx *c);
+// several operators per launch (FP64 stage formulation): argument records and launches
+size_t leaf_args_size();
+int fill_leaf_args(const hps_op *op, const LeafPhase &ph, void *dst, size_t *lds);
+int launch_leaf_group(const void *args, const int *base, int nprob, int total, size_t lds, int down, int up,
+                      hipStream_t st);
+size_t level_record_size();
+void level_record(const hps_op *op, int l, bool up, const double *dir, void *dst, int *blocks, size_t *lds);
+bool root_fused64(const hps_op *op);
+void root_records(const hps_op *op, const double *dir, void *up_dst, void *dn_dst, int *blocks, size_t *lds);
+size_t line_record_size();
+void line_record(const hps_op *op, double *u, void *dst, int *systems);
+size_t scatter_record_size();
+void scatter_record(const hps_op *op, double *u, void *dst, int *count);
+int launch_level_group(const void *args, const int *base, int n, int total, size_t lds, bool up, hipStream_t st);
+int launch_root_group(const void *ups, const void *dns, const int *base, int n, int total, size_t lds,
+                      hipStream_t st);
+int launch_lines_group(const void *args, const int *base, int n, int total, hipStream_t st);
+int launch_zero_boundary_group(const void *args, const int *base, int n, int total, hipStream_t st);
+void step_phase(const ark_ctx *c, int k, double *u, const double *q_stages, const double *q_space,
+                const double *qt, LeafPhase &ph);
 int launch_set_values(double *dst, const double *vals, int n, hipStream_t st);   // n <= 8, vals on the host
 
 // build --------------------------------------------------------------------------------

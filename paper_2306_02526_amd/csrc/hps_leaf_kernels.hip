@@ -298,6 +298,24 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
     leaf_body<T, DN, UPM>(a, blockIdx.x, smem, red, nred);
 }
 
+// The leaves of several operators in one launch: workgroup w works on leaf w - base[b] of
+// problem b, base[b] <= w < base[b + 1] (found by bisection; uniform per workgroup).
+template <typename T, int DN, int UPM>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_leaf_group(
+    const LeafArgs *args, const int *base, int nprob) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT];
+    __shared__ double nred[2][NT / 64];
+    const int w = blockIdx.x;
+    int lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    leaf_body<T, DN, UPM>(args[lo], w - base[lo], smem, red, nred);
+}
+
 // =======================================================================================
 // launcher
 // =======================================================================================
@@ -310,9 +328,8 @@ static int leaf_family(const LeafPhase &ph, bool fp32) {
     return fp32 ? KF_LEAF_UP32 : KF_LEAF_UP64;
 }
 
-int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st) {
-    ProfScope ps_(&op->prof, leaf_family(ph, fp32), st);
-    LeafArgs a{};
+static void make_leaf_args(const hps_op *op, bool fp32, const LeafPhase &ph, LeafArgs &a, size_t &lds) {
+    a = LeafArgs{};
     a.geo = geo_of(op);
     a.leaf_ij = op->leaf_ij;
     a.D = op->D;
@@ -354,7 +371,14 @@ int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st
     a.fpart = op->ir_flux;
     const size_t es = fp32 ? 4 : 8;
     const size_t pp = (size_t)op->p * op->p * 8, q2b = (size_t)op->q2 * 8;
-    const size_t lds = carve_bytes({(size_t)a.xs_cap * es, (size_t)a.part_cap * es, pp, pp, pp, q2b, q2b});
+    lds = carve_bytes({(size_t)a.xs_cap * es, (size_t)a.part_cap * es, pp, pp, pp, q2b, q2b});
+}
+
+int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st) {
+    ProfScope ps_(&op->prof, leaf_family(ph, fp32), st);
+    LeafArgs a;
+    size_t lds = 0;
+    make_leaf_args(op, fp32, ph, a, lds);
     auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(op->nleaves), dim3(NT), lds, st, a); };
 #define HPS_LEAF_CASE(DNV, UPV)                                                   \
     if (ph.down == DNV && ph.up == UPV) {                                         \
@@ -372,6 +396,32 @@ int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st
     HPS_LEAF_CASE(DOWN_IR_ADD, UP_NONE)
 #undef HPS_LEAF_CASE
     hps_set_error("internal: unsupported leaf phase combination (%d, %d)", ph.down, ph.up);
+    return HPS_EINVAL;
+}
+
+size_t leaf_args_size() { return sizeof(LeafArgs); }
+
+int fill_leaf_args(const hps_op *op, const LeafPhase &ph, void *dst, size_t *lds) {
+    make_leaf_args(op, false, ph, *reinterpret_cast<LeafArgs *>(dst), *lds);
+    return HPS_OK;
+}
+
+int launch_leaf_group(const void *args, const int *base, int nprob, int total, size_t lds, int down, int up,
+                      hipStream_t st) {
+    if (total <= 0) return HPS_OK;
+    const LeafArgs *a = reinterpret_cast<const LeafArgs *>(args);
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(total), dim3(NT), lds, st, a, base, nprob); };
+#define HPS_LEAF_GROUP_CASE(DNV, UPV)                                               \
+    if (down == DNV && up == UPV) {                                                 \
+        go(k_leaf_group<double, DNV, UPV>);                                         \
+        HPS_LAUNCHED();                                                             \
+        return HPS_OK;                                                              \
+    }
+    HPS_LEAF_GROUP_CASE(DOWN_EVAL, UP_STAGE)
+    HPS_LEAF_GROUP_CASE(DOWN_STAGE, UP_STAGE)
+    HPS_LEAF_GROUP_CASE(DOWN_STAGE, UP_UPDATE)
+#undef HPS_LEAF_GROUP_CASE
+    hps_set_error("internal: unsupported grouped leaf phase (%d, %d)", down, up);
     return HPS_EINVAL;
 }
 

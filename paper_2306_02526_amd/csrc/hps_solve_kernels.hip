@@ -90,21 +90,21 @@ __device__ __forceinline__ void down_finalize(const LevelArgs &a, int node, int 
     }
 }
 
-__device__ __forceinline__ double down_input(const LevelArgs &a, int node, int k) {
-    if (a.root) return a.dir ? a.dir[a.root_map[k]] : 0.0;
+__device__ __forceinline__ double down_input(const LevelArgs &a, const double *dir, int node, int k) {
+    if (a.root) return dir ? dir[a.root_map[k]] : 0.0;
     return a.ub[(int64_t)node * a.n12 + k];
 }
 
+
+// One (node, row tile, column chunk) of a level product: workgroup-local index blk.
 template <typename T, bool UP>
-__global__ __launch_bounds__(NT) void k_level(LevelArgs a) {
+__device__ __forceinline__ void level_body(const LevelArgs &a, int blk, unsigned char *smem, double *red,
+                                           int *s_last) {
     constexpr int VW = 16 / sizeof(T);
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[NT];
-    __shared__ int s_last;
     const int kch = a.pn.kch, ntile = a.pn.ntile;
-    const int chunk = blockIdx.x % kch;
-    const int tile = (blockIdx.x / kch) % ntile;
-    const int node = blockIdx.x / (kch * ntile);
+    const int chunk = blk % kch;
+    const int tile = (blk / kch) % ntile;
+    const int node = blk / (kch * ntile);
     const int SG = a.pn.S * a.pn.G;
     Carve cv{smem};
     T *xs = cv.take<T>(SG);
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(NT) void k_level(LevelArgs a) {
                 x = hb[a.b3[kg]] - ha[a.a3[kg]];
                 if (a.r3) x += a.r3[a.j3i[(int64_t)node * a.n3 + kg]];
             } else {
-                x = down_input(a, node, kg);
+                x = down_input(a, a.dir, node, kg);
             }
         }
         xs[k] = (T)x;
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(NT) void k_level(LevelArgs a) {
         const int per = (a.n12 + nblk_node - 1) / nblk_node;
         const int m1 = min(a.n12, (me + 1) * per);
         for (int m = me * per + threadIdx.x; m < m1; m += NT) {
-            const double v = down_input(a, node, m);
+            const double v = down_input(a, a.dir, node, m);
             if (m < a.n1) a.ubc[(int64_t)(2 * node) * a.nbc + a.a1[m]] = v;
             else a.ubc[(int64_t)(2 * node + 1) * a.nbc + a.b2[m - a.n1]] = v;
         }
@@ -197,9 +197,9 @@ __global__ __launch_bounds__(NT) void k_level(LevelArgs a) {
         pp[(int64_t)chunk * rows + idx] = panel_sum<T>(part, a.pn.rp, a.pn.G, idx);
     __threadfence();
     __syncthreads();
-    if (threadIdx.x == 0) s_last = (atomicAdd(&a.cnt[node * ntile + tile], 1) == kch - 1);
+    if (threadIdx.x == 0) *s_last = (atomicAdd(&a.cnt[node * ntile + tile], 1) == kch - 1);
     __syncthreads();
-    if (!s_last) return;
+    if (!*s_last) return;
     __threadfence();
     for (int r0 = 0; r0 < rows; r0 += NT) {
         const int nr = min(NT, rows - r0);
@@ -221,6 +221,31 @@ __global__ __launch_bounds__(NT) void k_level(LevelArgs a) {
         __syncthreads();
     }
     if (threadIdx.x == 0) a.cnt[node * ntile + tile] = 0;
+}
+
+template <typename T, bool UP>
+__global__ __launch_bounds__(NT) void k_level(LevelArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT];
+    __shared__ int s_last;
+    level_body<T, UP>(a, blockIdx.x, smem, red, &s_last);
+}
+
+// One level product of several operators in one launch: workgroup w belongs to entry e,
+// base[e] <= w < base[e + 1].
+template <typename T, bool UP>
+__global__ __launch_bounds__(NT) void k_level_group(const LevelArgs *args, const int *base, int n) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT];
+    __shared__ int s_last;
+    const int w = blockIdx.x;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    level_body<T, UP>(args[lo], w - base[lo], smem, red, &s_last);
 }
 
 // =======================================================================================
@@ -350,9 +375,8 @@ struct LineArgs {
 
 // One thread per grid line; the recursion carries d_{k-1} and e_{k+1} in registers and
 // its inputs are loaded CH at a time ahead of use, so no load waits on a store.
-__global__ void k_interface_lines(LineArgs a) {
+__device__ __forceinline__ void line_body(const LineArgs &a, int t) {
     constexpr int CH = 8;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const LeafGeo &g = a.geo;
     const int q = g.q, p = g.p;
     const int nvs = g.n2 * q;   // systems along horizontal rows (vertical-edge unknowns)
@@ -426,6 +450,39 @@ __global__ void k_interface_lines(LineArgs a) {
             }
         }
     }
+}
+
+__global__ void k_interface_lines(LineArgs a) { line_body(a, blockIdx.x * blockDim.x + threadIdx.x); }
+
+// Line systems of several operators: thread index t belongs to problem b,
+// base[b] <= t < base[b + 1]; then the outer-boundary data of each problem (zero).
+__global__ void k_lines_group(const LineArgs *args, const int *base, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= base[n]) return;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    line_body(args[lo], t - base[lo]);
+}
+
+struct ScatterTask {
+    const int *bnd_glob;
+    double *u;
+};
+
+__global__ void k_zero_boundary_group(const ScatterTask *tasks, const int *base, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= base[n]) return;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    tasks[lo].u[tasks[lo].bnd_glob[t - base[lo]]] = 0.0;
 }
 
 // up to 8 host values handed over as a kernel argument (no host buffer stays in use)
@@ -512,11 +569,9 @@ static LevelArgs level_args(const hps_op *op, int l, bool fp32, bool up) {
 // The root's upward and downward products in one kernel: with u_12 the Dirichlet data,
 // u_3 = S u_12 + X d needs, for each row tile, only that tile's rows of X and of S.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_root(LevelArgs up, LevelArgs dn) {
+__device__ __forceinline__ void root_body(const LevelArgs &up, const LevelArgs &dn, int tile, unsigned char *smem,
+                                          double *red) {
     constexpr int VW = 16 / sizeof(T);
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[NT];
-    const int tile = blockIdx.x;
     const int SG1 = up.pn.S * up.pn.G, SG2 = dn.pn.S * dn.pn.G;
     Carve cv{smem};
     T *xs1 = cv.take<T>(SG1);
@@ -545,7 +600,7 @@ __global__ __launch_bounds__(NT) void k_root(LevelArgs up, LevelArgs dn) {
     for (int k = threadIdx.x; k < SG2; k += NT)
         xs2[k] = (T)((k < dn.n12 && dn.dir) ? dn.dir[dn.root_map[k]] : 0.0);
     {   // the children's J1 / J2 boundary data: one slice per workgroup
-        const int per = (dn.n12 + (int)gridDim.x - 1) / (int)gridDim.x;
+        const int per = (dn.n12 + dn.pn.ntile - 1) / dn.pn.ntile;
         const int m1 = min(dn.n12, (tile + 1) * per);
         for (int m = tile * per + threadIdx.x; m < m1; m += NT) {
             const double v = dn.dir ? dn.dir[dn.root_map[m]] : 0.0;
@@ -586,6 +641,28 @@ __global__ __launch_bounds__(NT) void k_root(LevelArgs up, LevelArgs dn) {
         dn.ubc[ia] = u3;
         dn.ubc[ib] = u3;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_root(LevelArgs up, LevelArgs dn) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT];
+    root_body<T>(up, dn, blockIdx.x, smem, red);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_root_group(const LevelArgs *ups, const LevelArgs *dns, const int *base,
+                                                   int n) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT];
+    const int w = blockIdx.x;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    root_body<T>(ups[lo], dns[lo], w - base[lo], smem, red);
 }
 
 static size_t level_lds(const Panel &pn) {
@@ -648,6 +725,83 @@ int launch_levels(const hps_op *op, bool fp32, const double *jump, const double 
         else hipLaunchKernelGGL((k_level<double, false>), dim3(nb), dim3(NT), level_lds(pn), st, a);
         HPS_LAUNCHED();
     }
+    return HPS_OK;
+}
+
+// ---- argument records and launches for several operators at once (FP64) ----
+size_t level_record_size() { return sizeof(LevelArgs); }
+
+void level_record(const hps_op *op, int l, bool up, const double *dir, void *dst, int *blocks, size_t *lds) {
+    LevelArgs a = level_args(op, l, false, up);
+    a.dir = dir;
+    *reinterpret_cast<LevelArgs *>(dst) = a;
+    *blocks = op->lv[l].nodes * a.pn.ntile * a.pn.kch;
+    *lds = level_lds(up ? op->lv[l].xu64 : op->lv[l].s64);
+}
+
+bool root_fused64(const hps_op *op) { return root_fusable(op, false); }
+
+void root_records(const hps_op *op, const double *dir, void *up_dst, void *dn_dst, int *blocks, size_t *lds) {
+    LevelArgs up = level_args(op, 0, false, true), dn = level_args(op, 0, false, false);
+    dn.dir = dir;
+    *reinterpret_cast<LevelArgs *>(up_dst) = up;
+    *reinterpret_cast<LevelArgs *>(dn_dst) = dn;
+    *blocks = op->lv[0].xu64.ntile;
+    *lds = level_lds(op->lv[0].xu64) + level_lds(op->lv[0].s64) + 32;
+}
+
+size_t line_record_size() { return sizeof(LineArgs); }
+
+void line_record(const hps_op *op, double *u, void *dst, int *systems) {
+    LineArgs la{};
+    la.geo = geo_of(op);
+    la.u = u;
+    la.fpart = op->ir_flux;
+    la.D = op->D;
+    la.cp = op->tri_cp;
+    la.inv_den = op->tri_cp + op->tri_stride;
+    *reinterpret_cast<LineArgs *>(dst) = la;
+    *systems = op->grid.n2 * op->q + op->grid.n1 * op->q;
+}
+
+size_t scatter_record_size() { return sizeof(ScatterTask); }
+
+void scatter_record(const hps_op *op, double *u, void *dst, int *count) {
+    *reinterpret_cast<ScatterTask *>(dst) = ScatterTask{op->bnd_glob, u};
+    *count = (int)op->n_bdry;
+}
+
+int launch_level_group(const void *args, const int *base, int n, int total, size_t lds, bool up, hipStream_t st) {
+    if (total <= 0) return HPS_OK;
+    const LevelArgs *a = reinterpret_cast<const LevelArgs *>(args);
+    if (up) hipLaunchKernelGGL((k_level_group<double, true>), dim3(total), dim3(NT), lds, st, a, base, n);
+    else hipLaunchKernelGGL((k_level_group<double, false>), dim3(total), dim3(NT), lds, st, a, base, n);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+int launch_root_group(const void *ups, const void *dns, const int *base, int n, int total, size_t lds,
+                      hipStream_t st) {
+    if (total <= 0) return HPS_OK;
+    hipLaunchKernelGGL(k_root_group<double>, dim3(total), dim3(NT), lds, st, reinterpret_cast<const LevelArgs *>(ups),
+                       reinterpret_cast<const LevelArgs *>(dns), base, n);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+int launch_lines_group(const void *args, const int *base, int n, int total, hipStream_t st) {
+    if (total <= 0) return HPS_OK;
+    hipLaunchKernelGGL(k_lines_group, dim3(nblk(total, 64)), dim3(64), 0, st, reinterpret_cast<const LineArgs *>(args),
+                       base, n);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+int launch_zero_boundary_group(const void *args, const int *base, int n, int total, hipStream_t st) {
+    if (total <= 0) return HPS_OK;
+    hipLaunchKernelGGL(k_zero_boundary_group, dim3(nblk(total)), dim3(NT), 0, st,
+                       reinterpret_cast<const ScatterTask *>(args), base, n);
+    HPS_LAUNCHED();
     return HPS_OK;
 }
 

@@ -141,3 +141,58 @@ def test_batched_rejects_missing_entries(torch):
     with pytest.raises(ValueError):
         hps.hps_solve_batched([op, op], [body, None])
     assert hps.hps_solve_batched([], []) == []
+
+
+def test_grouped_batched_steps_match_single_steps_and_oracle(torch, monkeypatch):
+    """FP64 problems with distinct operators and at least two leaves run as grouped launches
+    (one launch per leaf phase and per tree level for all problems): the same bits as single
+    steps, and the oracle's result; the plan and its graph are reused on later steps."""
+    mix = workloads.batched_mix(n_problems=7, config_index=6, sides=(2, 4, 8), orders=(6, 8, 10))
+    tab = product_tableau()
+    otab = tableau_float(ark436l2sa())
+    res = {}
+    for mode in ("grouped", "streams"):
+        monkeypatch.setenv("HPS_GROUP", "1" if mode == "grouped" else "0")
+        ctxs, us, probs, orcs, refs = [], [], [], [], []
+        for m in mix:
+            x0, x1, y0, y1 = m["domain"]
+            g = hps.make_grid(x0, x1, y0, y1, m["n1"], m["n2"], m["p"])
+            og = Grid(x0, x1, y0, y1, m["n1"], m["n2"], m["p"])
+            x, y = hps.hps_nodes(g)
+            pr = m["problem"]
+            cxx, cyy, cx, cy, c0 = pr.L_coeffs(x[: og.n_int], y[: og.n_int])
+            co = dict(cxx=cxx, cyy=cyy, cx=cx, cy=cy, c0=c0)
+            dt = m["gamma_dt"] / tab["gamma"]
+            op = hps.hps_build(g, {c: torch.tensor(v, device="cuda") for c, v in co.items()}, m["gamma_dt"])
+            gp = None if m["kind"] == "heat" else workloads.AllenCahn.gpoly
+            ctxs.append(hps.ark_create(op, tab, dt, g=gp))
+            u0 = pr.exact(0.0, x, y) if m["kind"] == "heat" else pr.u0(x, y)
+            us.append(torch.tensor(u0, device="cuda"))
+            probs.append((m, x, y, og, dt))
+            if mode == "grouped":
+                orcs.append(ARK(HPS(og, co, m["gamma_dt"]), co, otab, dt, gp))
+                refs.append(u0.copy())
+        qsp = [torch.tensor(m["problem"].q_space(x[: og.n_int], y[: og.n_int]), device="cuda")
+               if m["kind"] == "heat" else None for m, x, y, og, dt in probs]
+        out = []
+        for n in range(3):
+            ts = [n * dt for *_, dt in probs]
+            qt = [[workloads.HeatManufactured.q_time(t + c * dt) for c in tab["c"]] if m["kind"] == "heat" else None
+                  for (m, _, _, _, dt), t in zip(probs, ts)]
+            hps.ark_step_batched(ctxs, ts, us, q_space=qsp, q_time=qt)
+            torch.cuda.synchronize()
+            out.append([u.clone() for u in us])
+            if mode == "grouped":
+                for b in range(len(ctxs)):
+                    q_st = None
+                    if qt[b] is not None:
+                        qs = qsp[b].cpu().numpy()
+                        q_st = np.array([v * qs for v in qt[b]])
+                    refs[b] = orcs[b].step(refs[b], q_stages=q_st)
+                    e = rel(us[b].cpu().numpy(), refs[b])
+                    assert e <= TOL64, (n, b, e)
+        res[mode] = out
+        say(f"   {mode}: {len(ctxs)} problems, 3 steps")
+    for a, b in zip(res["grouped"], res["streams"]):
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
