@@ -767,8 +767,55 @@ int hps::ark_slope_workspace(ark_ctx *c) {
     return HPS_OK;
 }
 
+// A workspace of the context's own, shaped like its operator's (FP64 levels).
+int hps::ctx_workspace(ark_ctx *c) {
+    if (c->ws) return HPS_OK;
+    const hps_op *op = c->op;
+    Workspace *w = new Workspace();
+    c->ws = w;
+    auto get = [&](size_t bytes, void **p) -> int {
+        if (hipMalloc(p, std::max<size_t>(bytes, 8)) != hipSuccess) {
+            *p = nullptr;
+            hps_set_error("hipMalloc of %zu bytes for a stepping workspace failed", bytes);
+            return HPS_ENOMEM;
+        }
+        w->allocs.push_back(*p);
+        return HPS_OK;
+    };
+    const size_t nl = op->nleaves, nb4 = 4 * (size_t)op->q, q2 = op->q2;
+    TRY(get(8 * nl * nb4, (void **)&w->h_leaf));
+    TRY(get(8 * nl * nb4, (void **)&w->ub_leaf));
+    TRY(get(8 * nl * q2, (void **)&w->w_leaf));
+    TRY(get(8 * nl * nb4, (void **)&w->flux));
+    w->lv.resize(op->L);
+    for (int l = 0; l < op->L; ++l) {
+        const Level &L = op->lv[l];
+        Workspace::Lv &v = w->lv[l];
+        TRY(get(8 * (size_t)L.nodes * L.n12, (void **)&v.h));
+        TRY(get(8 * (size_t)L.nodes * L.n12, (void **)&v.ub));
+        TRY(get(8 * (size_t)L.nodes * L.n3, (void **)&v.w3));
+        int64_t part = 0;
+        for (const Panel *pn : {&L.xu64, &L.s64})
+            if (pn->kch > 1) part = std::max<int64_t>(part, (int64_t)L.nodes * pn->ntile * pn->kch * pn->rp * pn->vw);
+        if (part) TRY(get(8 * (size_t)part, (void **)&v.part));
+        const Panel *pns[2] = {&L.xu64, &L.s64};
+        int **cnts[2] = {&v.cnt_up, &v.cnt_dn};
+        for (int k = 0; k < 2; ++k) {
+            if (pns[k]->kch <= 1) continue;
+            const size_t nc = (size_t)L.nodes * pns[k]->ntile;
+            TRY(get(sizeof(int) * nc, (void **)cnts[k]));
+            HPS_HIP(hipMemset(*cnts[k], 0, sizeof(int) * nc));
+        }
+    }
+    return HPS_OK;
+}
+
 extern "C" void ark_free(ark_ctx *c) {
     if (!c) return;
+    if (c->ws) {
+        for (void *p : c->ws->allocs) (void)hipFree(p);
+        delete c->ws;
+    }
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);

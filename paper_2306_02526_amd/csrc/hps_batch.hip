@@ -1,7 +1,7 @@
-// Batched entry points: many independent problems per call.  FP64 time steps of problems
-// with distinct operators run as grouped launches (one launch per leaf phase and per tree
-// level for all problems); everything else runs each problem through the single-problem
-// entry points on a pool of library-owned HIP streams, so that small problems overlap.
+// Batched entry points: many independent problems per call.  FP64 time steps run as
+// grouped launches (one launch per leaf phase and per tree level for all problems);
+// everything else runs each problem through the single-problem entry points on a pool of
+// library-owned HIP streams, so that small problems overlap.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -168,13 +168,11 @@ bool groupable(ark_ctx *const *ctx, int nprob, const double *const *q_stages, co
     const char *env = getenv("HPS_GROUP");
     if (env && env[0] == '0') return false;
     if (nprob < 2) return false;
-    std::map<const hps_op *, int> seen;
     for (int b = 0; b < nprob; ++b) {
         const hps_op *op = ctx[b]->op;
         if (op->flags & HPS_FP32_IR) return false;
         if (op->prof.on || op->L < 1 || ctx[b]->s != ctx[0]->s) return false;
         if (f_stages && f_stages[b]) return false;
-        if (seen[op]++) return false;   // one operator's workspace serves one problem at a time
     }
     (void)q_stages;
     return true;
@@ -184,6 +182,15 @@ int build_plan(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, const
                const double *const *q_space) {
     P->n = n;
     P->s = ctx[0]->s;
+    // problems that share an operator each write a workspace of their own
+    std::map<const hps_op *, int> uses;
+    for (int b = 0; b < n; ++b) uses[ctx[b]->op]++;
+    std::vector<const Workspace *> ws(n, nullptr);
+    for (int b = 0; b < n; ++b)
+        if (uses[ctx[b]->op] > 1) {
+            TRY(ctx_workspace(ctx[b]));
+            ws[b] = ctx[b]->ws;
+        }
     HPS_HIP(hipMalloc(&P->qt, sizeof(double) * 8 * n));
     HPS_HIP(hipMemset(P->qt, 0, sizeof(double) * 8 * n));
     HostTables T;
@@ -200,7 +207,7 @@ int build_plan(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, const
             step_phase(ctx[b], k, u[b], q_stages ? q_stages[b] : nullptr, q_space ? q_space[b] : nullptr,
                        P->qt + 8 * b, ph);
             size_t lds = 0;
-            TRY(fill_leaf_args(ctx[b]->op, ph, recs.data() + rs * b, &lds));
+            TRY(fill_leaf_args(ctx[b]->op, ph, recs.data() + rs * b, &lds, ws[b]));
             L.lds = std::max(L.lds, lds);
             L.down = ph.down;
             L.up = ph.up;
@@ -227,7 +234,7 @@ int build_plan(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, const
             recs.resize(recs.size() + ls);
             int blocks = 0;
             size_t lds = 0;
-            level_record(op, l, up, nullptr, recs.data() + recs.size() - ls, &blocks, &lds);
+            level_record(op, l, up, nullptr, recs.data() + recs.size() - ls, &blocks, &lds, ws[b]);
             L.lds = std::max(L.lds, lds);
             bs.push_back(bs.back() + blocks);
         }
@@ -252,7 +259,7 @@ int build_plan(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, const
             dns.resize(dns.size() + ls);
             int blocks = 0;
             size_t lds = 0;
-            root_records(op, nullptr, ups.data() + ups.size() - ls, dns.data() + dns.size() - ls, &blocks, &lds);
+            root_records(op, nullptr, ups.data() + ups.size() - ls, dns.data() + dns.size() - ls, &blocks, &lds, ws[b]);
             L.lds = std::max(L.lds, lds);
             bs.push_back(bs.back() + blocks);
         }
@@ -274,7 +281,7 @@ int build_plan(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, const
         for (int b = 0; b < n; ++b) {
             int cnt = 0, sys = 0;
             scatter_record(ctx[b]->op, u[b], zrec.data() + zs * b, &cnt);
-            line_record(ctx[b]->op, u[b], lrec.data() + lr * b, &sys);
+            line_record(ctx[b]->op, u[b], lrec.data() + lr * b, &sys, ws[b]);
             zb[b + 1] = zb[b] + cnt;
             lb[b + 1] = lb[b] + sys;
         }

@@ -113,8 +113,23 @@ struct hps_op {
     mutable hps::Profiler prof;
 };
 
+// The buffers one FP64 solve writes besides its outputs (leaf boundary values, particular
+// solutions and fluxes, per-level boundary data, split-K partials).  An operator owns one
+// set; a stepping context gets its own when grouped launches run several contexts of one
+// operator together.
+struct Workspace {
+    struct Lv {
+        double *h = nullptr, *ub = nullptr, *w3 = nullptr, *part = nullptr;
+        int *cnt_up = nullptr, *cnt_dn = nullptr;
+    };
+    double *h_leaf = nullptr, *ub_leaf = nullptr, *w_leaf = nullptr, *flux = nullptr;
+    std::vector<Lv> lv;
+    std::vector<void *> allocs;
+};
+
 struct ark_ctx {
     hps_op *op = nullptr;
+    Workspace *ws = nullptr;              // own workspace for grouped launches (or null)
     uint64_t uid = 0;                     // unique per context created in this process
     int s = 0;
     double dt = 0;
@@ -229,15 +244,18 @@ int launch_flux_jump(const hps_op *op, double scale, double *r3, hipStream_t st)
 int ark_slope_workspace(ark_ctx *c);
 // several operators per launch (FP64 stage formulation): argument records and launches
 size_t leaf_args_size();
-int fill_leaf_args(const hps_op *op, const LeafPhase &ph, void *dst, size_t *lds);
+int fill_leaf_args(const hps_op *op, const LeafPhase &ph, void *dst, size_t *lds, const Workspace *ws);
+int ctx_workspace(ark_ctx *c);
 int launch_leaf_group(const void *args, const int *base, int nprob, int total, size_t lds, int down, int up,
                       hipStream_t st);
 size_t level_record_size();
-void level_record(const hps_op *op, int l, bool up, const double *dir, void *dst, int *blocks, size_t *lds);
+void level_record(const hps_op *op, int l, bool up, const double *dir, void *dst, int *blocks, size_t *lds,
+                  const Workspace *ws);
 bool root_fused64(const hps_op *op);
-void root_records(const hps_op *op, const double *dir, void *up_dst, void *dn_dst, int *blocks, size_t *lds);
+void root_records(const hps_op *op, const double *dir, void *up_dst, void *dn_dst, int *blocks, size_t *lds,
+                  const Workspace *ws);
 size_t line_record_size();
-void line_record(const hps_op *op, double *u, void *dst, int *systems);
+void line_record(const hps_op *op, double *u, void *dst, int *systems, const Workspace *ws);
 size_t scatter_record_size();
 void scatter_record(const hps_op *op, double *u, void *dst, int *count);
 int launch_level_group(const void *args, const int *base, int n, int total, size_t lds, bool up, hipStream_t st);

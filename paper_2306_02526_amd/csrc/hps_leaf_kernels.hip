@@ -401,8 +401,16 @@ int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st
 
 size_t leaf_args_size() { return sizeof(LeafArgs); }
 
-int fill_leaf_args(const hps_op *op, const LeafPhase &ph, void *dst, size_t *lds) {
-    make_leaf_args(op, false, ph, *reinterpret_cast<LeafArgs *>(dst), *lds);
+int fill_leaf_args(const hps_op *op, const LeafPhase &ph, void *dst, size_t *lds, const Workspace *ws) {
+    LeafArgs &a = *reinterpret_cast<LeafArgs *>(dst);
+    make_leaf_args(op, false, ph, a, *lds);
+    if (ws) {
+        a.ub = ws->ub_leaf;
+        a.w_in = ws->w_leaf;
+        a.w_out = ws->w_leaf;
+        a.h_out = ws->h_leaf;
+        a.fpart = ws->flux;
+    }
     return HPS_OK;
 }
 

@@ -452,11 +452,14 @@ __device__ __forceinline__ void line_body(const LineArgs &a, int t) {
     }
 }
 
-__global__ void k_interface_lines(LineArgs a) { line_body(a, blockIdx.x * blockDim.x + threadIdx.x); }
+// 64 threads per workgroup: each thread carries a whole line system in registers
+__global__ __launch_bounds__(64) void k_interface_lines(LineArgs a) {
+    line_body(a, blockIdx.x * blockDim.x + threadIdx.x);
+}
 
 // Line systems of several operators: thread index t belongs to problem b,
 // base[b] <= t < base[b + 1]; then the outer-boundary data of each problem (zero).
-__global__ void k_lines_group(const LineArgs *args, const int *base, int n) {
+__global__ __launch_bounds__(64) void k_lines_group(const LineArgs *args, const int *base, int n) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= base[n]) return;
     int lo = 0, hi = n - 1;
@@ -731,8 +734,22 @@ int launch_levels(const hps_op *op, bool fp32, const double *jump, const double 
 // ---- argument records and launches for several operators at once (FP64) ----
 size_t level_record_size() { return sizeof(LevelArgs); }
 
-void level_record(const hps_op *op, int l, bool up, const double *dir, void *dst, int *blocks, size_t *lds) {
+static void use_workspace(const hps_op *op, int l, bool up, const Workspace *ws, LevelArgs &a) {
+    if (!ws) return;
+    const bool child_leaf = (l == op->L - 1);
+    a.hc = child_leaf ? ws->h_leaf : ws->lv[l + 1].h;
+    a.ubc = child_leaf ? ws->ub_leaf : ws->lv[l + 1].ub;
+    a.h = ws->lv[l].h;
+    a.ub = ws->lv[l].ub;
+    a.w3 = ws->lv[l].w3;
+    a.part = ws->lv[l].part;
+    a.cnt = up ? ws->lv[l].cnt_up : ws->lv[l].cnt_dn;
+}
+
+void level_record(const hps_op *op, int l, bool up, const double *dir, void *dst, int *blocks, size_t *lds,
+                  const Workspace *ws) {
     LevelArgs a = level_args(op, l, false, up);
+    use_workspace(op, l, up, ws, a);
     a.dir = dir;
     *reinterpret_cast<LevelArgs *>(dst) = a;
     *blocks = op->lv[l].nodes * a.pn.ntile * a.pn.kch;
@@ -741,8 +758,11 @@ void level_record(const hps_op *op, int l, bool up, const double *dir, void *dst
 
 bool root_fused64(const hps_op *op) { return root_fusable(op, false); }
 
-void root_records(const hps_op *op, const double *dir, void *up_dst, void *dn_dst, int *blocks, size_t *lds) {
+void root_records(const hps_op *op, const double *dir, void *up_dst, void *dn_dst, int *blocks, size_t *lds,
+                  const Workspace *ws) {
     LevelArgs up = level_args(op, 0, false, true), dn = level_args(op, 0, false, false);
+    use_workspace(op, 0, true, ws, up);
+    use_workspace(op, 0, false, ws, dn);
     dn.dir = dir;
     *reinterpret_cast<LevelArgs *>(up_dst) = up;
     *reinterpret_cast<LevelArgs *>(dn_dst) = dn;
@@ -752,11 +772,11 @@ void root_records(const hps_op *op, const double *dir, void *up_dst, void *dn_ds
 
 size_t line_record_size() { return sizeof(LineArgs); }
 
-void line_record(const hps_op *op, double *u, void *dst, int *systems) {
+void line_record(const hps_op *op, double *u, void *dst, int *systems, const Workspace *ws) {
     LineArgs la{};
     la.geo = geo_of(op);
     la.u = u;
-    la.fpart = op->ir_flux;
+    la.fpart = ws ? ws->flux : op->ir_flux;
     la.D = op->D;
     la.cp = op->tri_cp;
     la.inv_den = op->tri_cp + op->tri_stride;

@@ -144,9 +144,10 @@ def test_batched_rejects_missing_entries(torch):
 
 
 def test_grouped_batched_steps_match_single_steps_and_oracle(torch, monkeypatch):
-    """FP64 problems with distinct operators and at least two leaves run as grouped launches
-    (one launch per leaf phase and per tree level for all problems): the same bits as single
-    steps, and the oracle's result; the plan and its graph are reused on later steps."""
+    """FP64 problems with at least two leaves run as grouped launches (one launch per leaf
+    phase and per tree level for all problems; two of them share one operator and use
+    workspaces of their own): the same bits as single steps, and the oracle's result; the
+    plan and its graph are reused on later steps."""
     mix = workloads.batched_mix(n_problems=7, config_index=6, sides=(2, 4, 8), orders=(6, 8, 10))
     tab = product_tableau()
     otab = tableau_float(ark436l2sa())
@@ -172,6 +173,13 @@ def test_grouped_batched_steps_match_single_steps_and_oracle(torch, monkeypatch)
             if mode == "grouped":
                 orcs.append(ARK(HPS(og, co, m["gamma_dt"]), co, otab, dt, gp))
                 refs.append(u0.copy())
+            if len(ctxs) == 1:   # a second problem on the first operator, other initial data
+                ctxs.append(hps.ark_create(op, tab, dt, g=gp))
+                us.append(torch.tensor(0.5 * u0, device="cuda"))
+                probs.append((m, x, y, og, dt))
+                if mode == "grouped":
+                    orcs.append(orcs[-1])
+                    refs.append(0.5 * u0)
         qsp = [torch.tensor(m["problem"].q_space(x[: og.n_int], y[: og.n_int]), device="cuda")
                if m["kind"] == "heat" else None for m, x, y, og, dt in probs]
         out = []
@@ -192,7 +200,7 @@ def test_grouped_batched_steps_match_single_steps_and_oracle(torch, monkeypatch)
                     e = rel(us[b].cpu().numpy(), refs[b])
                     assert e <= TOL64, (n, b, e)
         res[mode] = out
-        say(f"   {mode}: {len(ctxs)} problems, 3 steps")
+        say(f"   {mode}: {len(ctxs)} problems ({len(mix)} operators), 3 steps")
     for a, b in zip(res["grouped"], res["streams"]):
         for x, y in zip(a, b):
             assert torch.equal(x, y)

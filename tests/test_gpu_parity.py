@@ -322,10 +322,18 @@ print(f"   oracle step done after {time.perf_counter() - t0:.1f} s", file=sys.st
 """
 
 
+# At 64x64 leaves, p = 16, gamma dt = 2.5e-4 the stage operator I - gamma dt L has
+# condition number ~1e5 (the collocation second derivative has row sums ~3e8), so two
+# equally valid FP64 evaluations of one step differ by ~1e-11 relative: the oracle with
+# explicit inverses instead of LU solves differs from itself by 2.0e-11 after one step
+# (8.7e-13 at 16x16).  The full-size comparison therefore uses 1e-10.
+TOL_FULL = 1e-10
+
+
 def test_full_size_allen_cahn_step_matches_oracle(torch, tmp_path):
     """The benchmark configuration itself (64x64 leaves, p = 16, FP64): one full step
     compared element by element with the oracle (run in a child process on one BLAS
-    thread, as the CPU baseline is)."""
+    thread, as the CPU baseline is), to the FP64 conditioning floor of this size."""
     import os
     import subprocess
     say("[full size] Allen-Cahn 64x64 p=16")
@@ -354,7 +362,7 @@ def test_full_size_allen_cahn_step_matches_oracle(torch, tmp_path):
                    timeout=600)
     e = rel(u_gpu, np.load(outp))
     say(f"   rel err {e:.2e}")
-    assert e <= TOL64
+    assert e <= TOL_FULL
 
 
 def test_graph_replay_equals_eager_steps(torch, monkeypatch):
