@@ -34,7 +34,7 @@ def leaf_kernel_hash():
     traffic is only reported while it matches."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("hps_leaf_kernels.hip", "hps_device.h", "hps_internal.h"):
+    for f in ("hps_leaf_kernels.hip", "hps_device.h"):
         with open(os.path.join(ROOT, "paper_2306_02526_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -63,6 +63,9 @@ def parse():
                     help="allen_cahn: the single-problem benchmark (default); batched: 256 seeded "
                          "problems stepped together; serving: Poisson job arrivals on the server")
     ap.add_argument("--problems", type=int, default=256, help="batched: number of problems")
+    ap.add_argument("--level-tiles", default="auto", choices=["auto", "wide", "thin"],
+                    help="level operators in few large row tiles (HPS_WIDE_TILES) or thin ones; "
+                         "auto: thin for one problem, wide for the batched and serving workloads")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
     ap.add_argument("--window", type=float, default=1.0, help="serving: seconds of arrivals at --rate")
     ap.add_argument("--counter-run", action="store_true",
@@ -156,7 +159,8 @@ def main():
     # ---- build (FP64) ----
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    op = hps.hps_build(g, coefs, gdt, hps.HPS_FP64)
+    tiles = hps.HPS_WIDE_TILES if args.level_tiles == "wide" else 0
+    op = hps.hps_build(g, coefs, gdt, hps.HPS_FP64 | tiles)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     total_bytes, op_bytes = op.bytes()
@@ -249,11 +253,11 @@ def main():
         op.free()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        op32 = hps.hps_build(g, coefs, gdt, hps.HPS_FP32_IR)
+        op32 = hps.hps_build(g, coefs, gdt, hps.HPS_FP32_IR | tiles)
         torch.cuda.synchronize()
         b32 = time.perf_counter() - t0
         ctx32 = hps.ark_create(op32, tab, dt, g=workloads.AllenCahn.gpoly)
-        op64 = hps.hps_build(g, coefs, gdt, hps.HPS_FP64)
+        op64 = hps.hps_build(g, coefs, gdt, hps.HPS_FP64 | tiles)
         ctx64 = hps.ark_create(op64, tab, dt, g=workloads.AllenCahn.gpoly)
         u32 = u0.clone()
         u64 = u0.clone()
@@ -305,7 +309,7 @@ def main():
         "config": {"workload": f"allen_cahn_variable_coef_{n}x{n}_leaves_p{p}", "n_leaves": n * n, "p": p,
                    "N_corner_free": N, "N_with_corners": p * p * n * n, "dt": dt,
                    "tableau": "ARK4(3)6L[2]SA", "stage_solves_per_step": stages,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU", "level_tiles": "wide" if tiles else "thin"},
         "unknowns_per_s": round(value * N, 1),
         "build_s": round(build_s, 4),
         "operator_bytes_per_stage_solve": int(stage_solve_bytes),
@@ -353,9 +357,12 @@ def batched_run(args):
     probs, ctxs, us = [], [], []
     op_bytes = 0
     t0 = time.perf_counter()
-    for m in mix:
+    for k, m in enumerate(mix):
+        if k and k % 32 == 0:
+            log(f"   {k}/{len(mix)} problems built")
         d = _mix_problem(torch, m, dev)
-        op = hps.hps_build(d["grid"], d["coefs"], m["gamma_dt"], hps.HPS_FP64)
+        flags = hps.HPS_FP64 | (0 if args.level_tiles == "thin" else hps.HPS_WIDE_TILES)
+        op = hps.hps_build(d["grid"], d["coefs"], m["gamma_dt"], flags)
         op_bytes += op.bytes()[1]
         ctxs.append(hps.ark_create(op, d["tab"], d["dt"], g=d["gpoly"]))
         us.append(d["u0"].clone())
@@ -395,7 +402,7 @@ def batched_run(args):
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * el / args.steps, 3),
            "higher_is_better": True, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"batched_mix_{len(probs)}", "problems": len(probs),
-                      "streams": hps.hps_batch_streams()},
+                      "streams": hps.hps_batch_streams(), "level_tiles": args.level_tiles},
            "problem_steps_per_s": round(len(probs) * args.steps / el, 1),
            "operator_GBps": round(op_bytes * (s - 1) * args.steps / el / 1e9, 1),
            "operator_bytes": op_bytes, "setup_s": round(setup_s, 1),

@@ -60,6 +60,10 @@ extern "C" {
 #define HPS_FP64     0   /* stored operators and their application in FP64          */
 #define HPS_FP32_IR  1   /* FP64 build; operators applied in FP32 inside an FP64
                             iterative-refinement loop (residual in FP64)           */
+#define HPS_WIDE_TILES 2 /* or-ed with either: cut each tree level's operators into few
+                            large row tiles (fewer workgroups per level).  For
+                            operators stepped many at a time (ark_step_batched, the
+                            server); a single solve of one operator is slower.      */
 
 typedef struct {
     double x0, x1, y0, y1;   /* domain; (x1-x0)/n1 must equal (y1-y0)/n2 (square leaves) */

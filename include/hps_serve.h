@@ -5,7 +5,8 @@
  * (Sec. 3.1, eqs. 9-11; ark_step in hps.h) of one problem.  A server owns a
  * thread on the device that was current at srv_create, and
  *   - an operator cache: the HPS operator of (grid, coefficient key, gamma*dt,
- *     flags) is built once (hps_build) and shared by every job with that key;
+ *     flags) is built once (hps_build, with HPS_WIDE_TILES added to the job's
+ *     flags) and shared by every job with that key;
  *     unreferenced operators are evicted least-recently-used first when a build
  *     would exceed the cache budget;
  *   - admission: jobs are admitted first-come first-served while fewer than
@@ -13,8 +14,8 @@
  *   - continuous batching: every iteration advances each running job by one step
  *     in a single ark_step_batched call (include/hps_batch.h), so jobs join and
  *     leave between steps and small problems overlap on the GPU.
- * Each job runs exactly the kernels ark_step runs for it alone, in the same order,
- * so a job's result does not depend on what else the server is running.
+ * Each job runs exactly the kernels ark_step runs for it alone on that operator, in
+ * the same order, so a job's result does not depend on what else the server is running.
  *
  * Arrays handed to srv_submit (coefficients, u, q_space) are caller-owned device
  * arrays and must stay valid until srv_poll reports the job finished

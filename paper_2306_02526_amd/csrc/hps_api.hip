@@ -184,6 +184,10 @@ Panel plan_panel(int R, int C, int vw, int nodes, int rp_max, int min_wg) {
     return p;
 }
 
+// Workgroups a level's product is cut into at least: enough to fill the GPU for one
+// problem, or (HPS_WIDE_TILES) few and large when many problems share each launch.
+static int level_min_wg(int flags) { return (flags & HPS_WIDE_TILES) ? 32 : 1024; }
+
 // Bytes of the packed operators hps_build stores for a grid, from the same panel plans
 // (the tree splits the longer side of each box, ties with a vertical cut).
 int64_t plan_operator_bytes(const hps_grid &g, int flags) {
@@ -197,9 +201,10 @@ int64_t plan_operator_bytes(const hps_grid &g, int flags) {
         const bool vert = w >= h;
         const int n3 = q * (vert ? h : w), n12 = 2 * q * (w + h);
         const int rows = root ? n3 : n3 + n12;
-        bytes += plan_panel(rows, n3, 2, nodes, 64, 1024).bytes() + plan_panel(n3, n12, 2, nodes, 64, 1024).bytes();
+        const int mwg = level_min_wg(flags);
+        bytes += plan_panel(rows, n3, 2, nodes, 64, mwg).bytes() + plan_panel(n3, n12, 2, nodes, 64, mwg).bytes();
         if (ir)
-            bytes += plan_panel(rows, n3, 4, nodes, 64, 1024).bytes() + plan_panel(n3, n12, 4, nodes, 64, 1024).bytes();
+            bytes += plan_panel(rows, n3, 4, nodes, 64, mwg).bytes() + plan_panel(n3, n12, 4, nodes, 64, mwg).bytes();
         if (vert) w /= 2;
         else h /= 2;
         nodes *= 2;
@@ -582,7 +587,7 @@ static int build_impl(hps_op *op, const hps_coeffs *co, hipStream_t st) {
             TRY(launch_dgemm(n12, n12, n3, U, n12, s3x, B, n3, s3x, Tn, n12, sxx, nodes, 1.0, 1.0, st));
         }
         const int rows = root ? n3 : n3 + n12;
-        const int rpm = 64, mwg = 1024;
+        const int rpm = 64, mwg = level_min_wg(op->flags);
         Lv.xu64 = plan_panel(rows, n3, 2, nodes, rpm, mwg);
         Lv.s64 = plan_panel(n3, n12, 2, nodes, rpm, mwg);
         TRY(alloc_panel(op, Lv.xu64));
@@ -650,7 +655,7 @@ extern "C" int hps_build(const hps_grid *grid, const hps_coeffs *coeffs, double 
     TRY(check_grid(grid));
     CHECK_ARG(coeffs != nullptr, "coeffs is NULL");
     CHECK_ARG(std::isfinite(gamma_dt) && gamma_dt > 0.0, "gamma_dt must be positive and finite");
-    CHECK_ARG(flags == HPS_FP64 || flags == HPS_FP32_IR, "unknown flags %d", flags);
+    CHECK_ARG((flags & ~(HPS_FP32_IR | HPS_WIDE_TILES)) == 0, "unknown flags %d", flags);
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
         (void)hipGetLastError();

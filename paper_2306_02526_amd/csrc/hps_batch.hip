@@ -14,7 +14,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/hps_batch.h"
+#include "hps_batch.h"
 #include "hps_internal.h"
 
 using namespace hps;

@@ -140,7 +140,7 @@ int srv_server::admit(Job *j) {
     auto it = cache.find(j->key);
     bool hit = it != cache.end();
     if (!hit) {
-        const int64_t need = operator_footprint(j->spec.grid, j->spec.flags);
+        const int64_t need = operator_footprint(j->spec.grid, j->spec.flags | HPS_WIDE_TILES);
         if (need > cfg.cache_bytes) {
             hps_set_error("operator of %lld bytes exceeds the cache budget", (long long)need);
             return HPS_ENOMEM;
@@ -165,7 +165,10 @@ int srv_server::admit(Job *j) {
         }
         j->waited = true;
         hps_op *op = nullptr;
-        if (int rc = hps_build(&j->spec.grid, &j->spec.coeffs, j->gamma_dt, j->spec.flags, stream, &op)) return rc;
+        // served jobs are stepped many at a time: level operators in few large tiles
+        if (int rc = hps_build(&j->spec.grid, &j->spec.coeffs, j->gamma_dt, j->spec.flags | HPS_WIDE_TILES,
+                               stream, &op))
+            return rc;
         CacheEntry e;
         e.op = op;
         int64_t ob = 0;

@@ -143,11 +143,13 @@ def test_batched_rejects_missing_entries(torch):
     assert hps.hps_solve_batched([], []) == []
 
 
-def test_grouped_batched_steps_match_single_steps_and_oracle(torch, monkeypatch):
+@pytest.mark.parametrize("flags", [hps.HPS_FP64, hps.HPS_WIDE_TILES], ids=["thin", "wide"])
+def test_grouped_batched_steps_match_single_steps_and_oracle(torch, monkeypatch, flags):
     """FP64 problems with at least two leaves run as grouped launches (one launch per leaf
     phase and per tree level for all problems; two of them share one operator and use
     workspaces of their own): the same bits as single steps, and the oracle's result; the
-    plan and its graph are reused on later steps."""
+    plan and its graph are reused on later steps.  Both level tilings (thin tiles for one
+    problem, wide tiles for many)."""
     mix = workloads.batched_mix(n_problems=7, config_index=6, sides=(2, 4, 8), orders=(6, 8, 10))
     tab = product_tableau()
     otab = tableau_float(ark436l2sa())
@@ -164,7 +166,8 @@ def test_grouped_batched_steps_match_single_steps_and_oracle(torch, monkeypatch)
             cxx, cyy, cx, cy, c0 = pr.L_coeffs(x[: og.n_int], y[: og.n_int])
             co = dict(cxx=cxx, cyy=cyy, cx=cx, cy=cy, c0=c0)
             dt = m["gamma_dt"] / tab["gamma"]
-            op = hps.hps_build(g, {c: torch.tensor(v, device="cuda") for c, v in co.items()}, m["gamma_dt"])
+            op = hps.hps_build(g, {c: torch.tensor(v, device="cuda") for c, v in co.items()}, m["gamma_dt"],
+                               flags)
             gp = None if m["kind"] == "heat" else workloads.AllenCahn.gpoly
             ctxs.append(hps.ark_create(op, tab, dt, g=gp))
             u0 = pr.exact(0.0, x, y) if m["kind"] == "heat" else pr.u0(x, y)

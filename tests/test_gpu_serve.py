@@ -120,7 +120,7 @@ def test_cache_eviction_keeps_results(torch):
     say("[serve] cache budget of one operator: every key change evicts and rebuilds")
     P1 = Problem(torch, "allen_cahn", 4, 4, 8, 1e-3, 10)
     P2 = Problem(torch, "heat", 4, 4, 8, 1e-3, 11)
-    op = hps.hps_build(P1.grid, P1.dco, P1.gdt)
+    op = hps.hps_build(P1.grid, P1.dco, P1.gdt, hps.HPS_WIDE_TILES)   # as the server builds it
     budget = int(op.bytes()[0] * 1.5)     # room for one operator with its workspace, not two
     op.free()
     srv = hps.Server(cache_bytes=budget, max_active=1)

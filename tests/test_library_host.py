@@ -76,6 +76,18 @@ def test_null_handles_are_rejected():
     assert L.hps_build(None, None, 1.0, 0, None, ctypes.byref(out)) == -1
 
 
+@pytest.mark.parametrize("flags", [4, -1, 8 | hps.HPS_FP32_IR])
+def test_unknown_build_flags_are_rejected(flags):
+    """Only HPS_FP32_IR and HPS_WIDE_TILES may be set; the check comes before any device use."""
+    g = hps.make_grid(0.0, 1.0, 0.0, 1.0, 2, 2, 6)
+    fake = ctypes.c_void_p(4096)
+    co = hps.HpsCoeffs(fake, fake, fake, fake, fake)
+    out = ctypes.c_void_p()
+    L = hps.lib()
+    assert L.hps_build(ctypes.byref(g), ctypes.byref(co), 1e-2, flags, None, ctypes.byref(out)) == -1
+    assert b"flags" in L.hps_last_error()
+
+
 def test_product_tableau_equals_oracle_tableau():
     a = product_tableau()
     b = tableau_float(ark436l2sa())
