@@ -22,7 +22,11 @@ implicit Runge-Kutta methods" (arXiv 2306.02526):
               the same discrete solution.
 * ``ark``   - the ARK4(3)6L[2]SA tableau (Sec. 3.1, Table 1 structure), the
               collocation apply of L, and one step of the stage formulation
-              (eqs. 9-11) with the interface update reading documented there.
+              (eqs. 9-11) with the interface update reading documented there,
+              and the slope formulation with flux-jump penalisation (Sec. 3.1).
+* ``burgers`` - the 2-D viscous Burgers system of Sec. 5.4 in the stage
+              formulation: two components on one implicit operator, coupled
+              through the collocation advection term.
 
 Every function is written from the paper's definitions with no blocking,
 fusion or reordering beyond what those definitions state.  The oracle shares

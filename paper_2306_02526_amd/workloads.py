@@ -13,6 +13,11 @@ Workloads (all on the unit square, Dirichlet data):
   allen_cahn  u_t = div(a grad u) + u - u^3, a = 1 + 0.5 sin(2 pi x) cos(2 pi y),
               u0 = seeded sine modes k, l <= 8 normalised to max |u0| = 1, f = 0.
   batched     a seeded mix of heat / reaction problems with smooth a in [0.5, 1.5].
+  burgers     the 2-D viscous Burgers system u_t = eps Lap u - (u u_x + v u_y),
+              v_t = eps Lap v - (u v_x + v v_y) with the closed-form traveling-wave and
+              diffusive solutions of the paper's analytic tests (eps = 0.1) and the
+              rotating-flow initial data (eps = 0.005); boundary data from the exact
+              solutions, zero for the rotating flow.
 """
 import math
 
@@ -197,3 +202,63 @@ def batched_mix(n_problems=256, config_index=4, sides=(8, 16, 32, 64), orders=(8
         out.append({"n1": n1, "n2": n2, "p": p, "gamma_dt": gdt, "kind": kind,
                     "domain": (0.0, Lx, 0.0, Ly), "problem": prob})
     return out
+
+
+# ---------------------------------------------------------------------------------------
+# 2-D Burgers system
+# ---------------------------------------------------------------------------------------
+class BurgersTravelingWave:
+    """u = 3/4 - 1/(4 (1 + e^{(4y - 4x - t)/(32 eps)})), v = 3/4 + 1/(4 (1 + e^{...})).
+    (The printed formula places 32 eps outside the exponential; only the exponent reading
+    solves the equations.)"""
+
+    def __init__(self, eps=0.1):
+        self.eps = float(eps)
+
+    def exact(self, t, x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        w = 1.0 / (4.0 * (1.0 + np.exp((4.0 * y - 4.0 * x - t) / (32.0 * self.eps))))
+        return 0.75 - w, 0.75 + w
+
+
+class BurgersDiffusive:
+    """u = -4 pi eps E cos(2 pi x) sin(pi y) / (2 + E sin(2 pi x) sin(pi y)),
+    v = -2 pi eps E sin(2 pi x) cos(pi y) / (2 + E sin(2 pi x) sin(pi y)),
+    E = e^{-5 pi^2 eps t}."""
+
+    def __init__(self, eps=0.1):
+        self.eps = float(eps)
+
+    def exact(self, t, x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        e = math.exp(-5.0 * math.pi ** 2 * self.eps * t)
+        den = 2.0 + e * np.sin(2 * math.pi * x) * np.sin(math.pi * y)
+        u = -4.0 * math.pi * self.eps * e * np.cos(2 * math.pi * x) * np.sin(math.pi * y) / den
+        v = -2.0 * math.pi * self.eps * e * np.sin(2 * math.pi * x) * np.cos(math.pi * y) / den
+        return u, v
+
+
+class BurgersRotating:
+    """Rotating flow on [-pi, pi]^2: u0 = -5 y e^{-3 (x^2 + y^2)}, v0 = 5 x e^{-3 (x^2 + y^2)},
+    no-slip walls (u = v = 0 on the boundary), eps = 0.005."""
+
+    domain = (-math.pi, math.pi, -math.pi, math.pi)
+
+    def __init__(self, eps=0.005):
+        self.eps = float(eps)
+
+    def u0(self, x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        e = np.exp(-3.0 * (x * x + y * y))
+        return -5.0 * y * e, 5.0 * x * e
+
+
+def burgers_coeffs(eps, n):
+    """Coefficients of L = eps Lap at n nodes: cxx, cyy, cx, cy, c0."""
+    e = np.full(n, float(eps))
+    z = np.zeros(n)
+    return e, e.copy(), z, z.copy(), z.copy()
+
