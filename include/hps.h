@@ -181,6 +181,24 @@ HPS_API int ark_step_slope(ark_ctx *ctx, double t, double *u, const double *q_st
                            const double *q_space, const double *q_time, const double *fdot_stages,
                            void *stream);
 
+/* One step t -> t + dt of the two-dimensional viscous Burgers system of Sec. 5.4,
+ *   u_t = L u - (u u_x + v u_y),   v_t = L v - (u v_x + v v_y),
+ * (L = eps Lap there; any operator built by hps_build is accepted), in the stage
+ * formulation (eqs. 9-11) for both components, in place on u and v (device [N] each,
+ * different arrays).  cu and cv are the contexts of the two components: created by
+ * ark_create on the same FP64 operator (HPS_FP32_IR is rejected) with the same tableau
+ * and dt and with g = NULL (the advection terms are the explicit part; they couple the
+ * components at every stage and are evaluated by collocation on the leaves, like L).
+ * Each stage solves both components' systems together: every operator block is read
+ * once for the two right-hand sides.
+ * fu_stages, fv_stages: device [s+1][n_bdry], the Dirichlet data of u and v at
+ * t + c_i dt (i < s) and at t + dt; NULL = 0.  The first call allocates solve buffers
+ * for cv (about the operator's workspace, O(N) doubles).
+ * Errors: HPS_EINVAL for NULL or mismatched handles, equal u and v, or an FP32_IR
+ * operator; HPS_EDEVICE for a failed launch. */
+HPS_API int ark_step_burgers(ark_ctx *cu, ark_ctx *cv, double t, double *u, double *v,
+                             const double *fu_stages, const double *fv_stages, void *stream);
+
 /* Number of implicit stage solves performed per ark_step (s - 1). */
 HPS_API int ark_stage_solves_per_step(const ark_ctx *ctx);
 

@@ -87,6 +87,45 @@ struct PanelStream {
 #pragma unroll
         for (int v = 0; v < VW; ++v) dst[v] = acc[v];
     }
+
+    // finish() for NC input vectors at once (vector c at xs + c*xstride, its partial sums
+    // to part + c*pstride): every operator load feeds NC products.
+    template <int NC>
+    __device__ __forceinline__ void finish_n(const T *__restrict__ xs, int xstride, T *__restrict__ part,
+                                             int pstride) {
+        if (!on) return;
+        T acc[NC][VW];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int v = 0; v < VW; ++v) acc[c][v] = T(0);
+#pragma unroll
+        for (int u = 0; u < PF; ++u)
+            if (u < S)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) vfma(acc[c], pre[u], xs[c * xstride + u * G + g]);
+        int s = PF;
+        for (; s + UNR <= S; s += UNR) {
+            V vv[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) vv[u] = __builtin_nontemporal_load(p + (size_t)(s + u) * act);
+#pragma unroll
+            for (int u = 0; u < UNR; ++u)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) vfma(acc[c], vv[u], xs[c * xstride + (s + u) * G + g]);
+        }
+        for (; s < S; ++s) {
+            const V w = __builtin_nontemporal_load(p + (size_t)s * act);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) vfma(acc[c], w, xs[c * xstride + s * G + g]);
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            T *dst = part + c * pstride + g * (act / G * VW) + r * VW;
+#pragma unroll
+            for (int v = 0; v < VW; ++v) dst[v] = acc[c][v];
+        }
+    }
 };
 
 template <typename T>

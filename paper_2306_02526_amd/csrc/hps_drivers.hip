@@ -293,23 +293,42 @@ static int enqueue_slope_step(ark_ctx *c, double *u, const double *q_stages, con
     return launch_lincomb(v, cf, m, nullptr, nullptr, &none, u, N, st);
 }
 
-// Enqueue one step of either formulation.  The FP64 step has no host synchronisation, so
-// it is captured once into a HIP graph and replayed while the formulation and the array
-// arguments repeat.  The refinement loop of FP32_IR waits on the host and runs eagerly; so
-// does a profiled step.
-static int run_step(ark_ctx *c, int mode, double *u, const double *q_stages, const double *q_space,
-                    const double *q_time, const double *f, hipStream_t st) {
+// One step of the two-component Burgers system (Sec. 5.4) in the stage formulation: both
+// components share the operator and the tableau; every leaf launch and level sweep runs
+// both (each operator block is read once for the two right-hand sides), and the advection
+// terms that couple them are evaluated in the leaf kernels.  Component 0 uses the
+// operator's solve buffers, component 1 those of its context.
+static int enqueue_burgers_step(ark_ctx *cu, ark_ctx *cv, double *u, double *v, const double *fu,
+                                const double *fv, hipStream_t st) {
+    hps_op *op = cu->op;
+    const int s = cu->s;
+    const int64_t nb = op->n_bdry;
+    const Workspace *ws[2] = {nullptr, cv->ws};
+    for (int k = 0; k < s; ++k) {
+        if (k > 0) {
+            const double *dir[2] = {fu ? fu + (int64_t)k * nb : nullptr, fv ? fv + (int64_t)k * nb : nullptr};
+            TRY(launch_levels_sys(op, ws, dir, st));
+        }
+        LeafPhase p0, p1;
+        step_phase(cu, k, u, nullptr, nullptr, cu->qt_dev, p0);
+        step_phase(cv, k, v, nullptr, nullptr, cv->qt_dev, p1);
+        TRY(launch_leaf_sys(op, p0, p1, ws[0], ws[1], st));
+    }
+    TRY(launch_interface_lines(op, u, fu ? fu + (int64_t)s * nb : nullptr, st));
+    TRY(launch_interface_lines(op, v, fv ? fv + (int64_t)s * nb : nullptr, st, nullptr, cv->ws->flux));
+    return HPS_OK;
+}
+
+// Enqueue one step.  The FP64 step has no host synchronisation, so it is captured once
+// into a HIP graph (kept in c) and replayed while `key` (the formulation and the array
+// arguments) repeats.  The refinement loop of FP32_IR waits on the host and runs eagerly;
+// so does a profiled step.
+template <typename Enqueue>
+static int run_captured(ark_ctx *c, const std::vector<uintptr_t> &key, Enqueue enqueue, hipStream_t st) {
     hps_op *op = c->op;
-    auto enqueue = [&](hipStream_t s2) {
-        return mode == 0 ? enqueue_step(c, u, q_stages, q_space, q_time, f, s2)
-                         : enqueue_slope_step(c, u, q_stages, q_space, f, s2);
-    };
-    if (q_space) TRY(launch_set_values(c->qt_dev, q_time, c->s, st));
     const char *env = getenv("HPS_GRAPHS");
     const bool graphs = !(env && env[0] == '0') && !(op->flags & HPS_FP32_IR) && !op->prof.on;
     if (!graphs) return enqueue(st);
-    const std::vector<uintptr_t> key = {(uintptr_t)mode, (uintptr_t)u, (uintptr_t)q_stages, (uintptr_t)q_space,
-                                        (uintptr_t)f};
     if (!c->gexec || key != c->gkey) {
         if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
         if (c->graph) (void)hipGraphDestroy(c->graph);
@@ -334,6 +353,18 @@ static int run_step(ark_ctx *c, int mode, double *u, const double *q_stages, con
     }
     HPS_HIP(hipGraphLaunch(c->gexec, st));
     return HPS_OK;
+}
+
+static int run_step(ark_ctx *c, int mode, double *u, const double *q_stages, const double *q_space,
+                    const double *q_time, const double *f, hipStream_t st) {
+    auto enqueue = [&](hipStream_t s2) {
+        return mode == 0 ? enqueue_step(c, u, q_stages, q_space, q_time, f, s2)
+                         : enqueue_slope_step(c, u, q_stages, q_space, f, s2);
+    };
+    if (q_space) TRY(launch_set_values(c->qt_dev, q_time, c->s, st));
+    const std::vector<uintptr_t> key = {(uintptr_t)mode, (uintptr_t)u, (uintptr_t)q_stages, (uintptr_t)q_space,
+                                        (uintptr_t)f};
+    return run_captured(c, key, enqueue, st);
 }
 
 static int check_step_args(ark_ctx *c, double t, double *u, const double *q_stages, const double *q_space,
@@ -361,4 +392,28 @@ extern "C" int ark_step_slope(ark_ctx *c, double t, double *u, const double *q_s
     CHECK_ARG(c->s <= 8, "the slope step takes at most 8 stages");
     TRY(ark_slope_workspace(c));
     return run_step(c, 1, u, q_stages, q_space, q_time, fdot_stages, (hipStream_t)stream);
+}
+
+extern "C" int ark_step_burgers(ark_ctx *cu, ark_ctx *cv, double t, double *u, double *v,
+                                const double *fu_stages, const double *fv_stages, void *stream) {
+    CHECK_ARG(cu != nullptr && cv != nullptr && u != nullptr && v != nullptr, "cu, cv, u and v are required");
+    CHECK_ARG(cu != cv, "the two components need a context each");
+    CHECK_ARG(u != v, "u and v must be different arrays");
+    CHECK_ARG(cu->op == cv->op, "both contexts must be created on the same operator");
+    CHECK_ARG(!(cu->op->flags & HPS_FP32_IR), "two-component steps need an operator built with HPS_FP64");
+    CHECK_ARG(cu->s == cv->s && cu->dt == cv->dt && cu->A == cv->A && cu->b == cv->b && cu->c == cv->c &&
+                  cu->Ah == cv->Ah && cu->bh == cv->bh,
+              "both contexts must have the same tableau and dt");
+    CHECK_ARG(cu->g.kind == 0 && cv->g.kind == 0, "the advection terms replace g: create both contexts with g = NULL");
+    CHECK_ARG(std::isfinite(t), "t must be finite");
+    TRY(check_device_ptr(u, "u"));
+    TRY(check_device_ptr(v, "v"));
+    TRY(check_device_ptr(fu_stages, "fu_stages"));
+    TRY(check_device_ptr(fv_stages, "fv_stages"));
+    TRY(ctx_workspace(cv));
+    const std::vector<uintptr_t> key = {(uintptr_t)2,         (uintptr_t)u,         (uintptr_t)v,
+                                        (uintptr_t)fu_stages, (uintptr_t)fv_stages, (uintptr_t)cv,
+                                        (uintptr_t)cv->uid};
+    return run_captured(cu, key, [&](hipStream_t s2) { return enqueue_burgers_step(cu, cv, u, v, fu_stages, fv_stages, s2); },
+                        (hipStream_t)stream);
 }

@@ -144,7 +144,6 @@ struct ark_ctx {
     // side [n_int] and the penalised flux jumps [n_iface]
     double *K = nullptr, *Ls = nullptr, *Lk = nullptr, *Ll = nullptr, *Lun = nullptr, *srhs = nullptr,
            *pen = nullptr;
-    int graph_mode = 0;                   // formulation of the captured step (0 stage, 1 slope)
     // the FP64 step is replayed from a captured HIP graph while its arguments repeat
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -231,7 +230,7 @@ int launch_levels(const hps_op *op, bool fp32, const double *jump, const double 
 // step completion after the interior update: boundary data f(t + dt), then the interface
 // values from flux continuity along every grid line (reads the leaf edge-flux parts)
 int launch_interface_lines(const hps_op *op, double *u, const double *f_end, hipStream_t st,
-                           const double *jump = nullptr);
+                           const double *jump = nullptr, const double *fpart = nullptr);
 int launch_residual(const hps_op *op, const double *u, const double *rhs, const double *jump,
                     double *r_int, double *r3, hipStream_t st);
 int launch_scatter_boundary(const hps_op *op, const double *f, double *u, hipStream_t st);
@@ -265,6 +264,11 @@ int launch_lines_group(const void *args, const int *base, int n, int total, hipS
 int launch_zero_boundary_group(const void *args, const int *base, int n, int total, hipStream_t st);
 void step_phase(const ark_ctx *c, int k, double *u, const double *q_stages, const double *q_space,
                 const double *qt, LeafPhase &ph);
+// two components on one operator (FP64): both components' leaf phase in one launch, and
+// the level sweeps of both (ws[c]: component c's solve buffers, null for the operator's)
+int launch_leaf_sys(const hps_op *op, const LeafPhase &ph0, const LeafPhase &ph1, const Workspace *ws0,
+                    const Workspace *ws1, hipStream_t st);
+int launch_levels_sys(const hps_op *op, const Workspace *const ws[2], const double *const dir[2], hipStream_t st);
 int launch_set_values(double *dst, const double *vals, int n, hipStream_t st);   // n <= 8, vals on the host
 
 // build --------------------------------------------------------------------------------

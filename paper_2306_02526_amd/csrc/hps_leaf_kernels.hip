@@ -317,6 +317,214 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
 }
 
 // =======================================================================================
+// Two-component systems on one operator (the Burgers system of Sec. 5.4): one workgroup
+// per leaf runs the down and up phases of both components.  Each operator block is
+// streamed once and applied to both components' vectors; the explicit term couples them
+// at the interior nodes:
+//   F^u = q^u - (u u_x + v u_y),   F^v = q^v - (u v_x + v v_y),
+// with the derivatives taken on the leaf tiles exactly as in L (eq. 3).
+// =======================================================================================
+struct LeafSysArgs {
+    LeafArgs c[2];   // per component; the operator fields of c[0] and c[1] are the same
+};
+
+template <int DN, int UPM>
+__device__ __forceinline__ void leaf_sys_body(const LeafSysArgs &A, int leaf, unsigned char *smem, double *red) {
+    constexpr int NC = 2, VW = 2;
+    const LeafArgs &a = A.c[0];
+    const int q = a.geo.q, p = a.geo.p, q2 = q * q, nb = 4 * q, pp = p * p;
+    const int li = a.leaf_ij[2 * leaf], lj = a.leaf_ij[2 * leaf + 1];
+    const int64_t base = ((int64_t)lj * a.geo.n1 + li) * q2;
+    const int64_t n_int = a.geo.n_int;
+    const int xcap = a.xs_cap, pcap = a.part_cap;
+    Carve cv{smem};
+    double *xs = cv.take<double>((size_t)NC * xcap);
+    double *part = cv.take<double>((size_t)NC * pcap);
+    double *tile = cv.take<double>((size_t)NC * pp);
+    double *D = cv.take<double>(pp);
+    double *D2 = cv.take<double>(pp);
+    double *luv = cv.take<double>((size_t)NC * q2);
+    double *fv = cv.take<double>((size_t)NC * q2);
+    constexpr bool stream_down = DN == DOWN_STAGE;
+    PanelStream<double, LPF, LUNR> ps;
+    if constexpr (stream_down)
+        ps.start(reinterpret_cast<const double *>(a.sl.data) + (int64_t)leaf * a.sl.node_elems, a.sl.rp, a.sl.G, a.sl.S);
+    else if constexpr (UPM == UP_STAGE)
+        ps.start(reinterpret_cast<const double *>(a.ainv.data) + (int64_t)leaf * a.ainv.node_elems, a.ainv.rp,
+                 a.ainv.G, a.ainv.S);
+    load_dmat(a.D, D, pp);
+    load_dmat(a.D2, D2, pp);
+
+    // ---------------- down phase: the tiles of u_i and v_i ----------------
+    for (int k = threadIdx.x; k < NC * pp; k += NT) tile[k] = 0.0;
+    if constexpr (stream_down) {
+        const int SG = a.sl.S * a.sl.G;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double *ubl = A.c[c].ub + (int64_t)leaf * nb;
+            for (int k = threadIdx.x; k < q2; k += NT) fv[c * q2 + k] = A.c[c].w_in[(int64_t)leaf * q2 + k];
+            for (int k = threadIdx.x; k < SG; k += NT) xs[c * xcap + k] = k < nb ? ubl[k] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double *ubl = A.c[c].ub + (int64_t)leaf * nb;
+            for (int k = threadIdx.x; k < nb; k += NT) tile[c * pp + edge_tile_pos(p, q, k / q, k % q)] = ubl[k];
+        }
+        ps.finish_n<NC>(xs, xcap, part, pcap);
+        if constexpr (UPM == UP_STAGE)
+            ps.start(reinterpret_cast<const double *>(a.ainv.data) + (int64_t)leaf * a.ainv.node_elems, a.ainv.rp,
+                     a.ainv.G, a.ainv.S);
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            reduce_rows<double>(part + c * pcap, a.sl.rp * VW, a.sl.G, red, [&](int row, double y) {
+                if (row < q2) tile[c * pp + (row / q + 1) * p + (row % q) + 1] = y + fv[c * q2 + row];
+            });
+    } else {
+        // DOWN_EVAL: the tiles of given canonical vectors
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double *ue = A.c[c].u_eval;
+            for (int k = threadIdx.x; k < q2; k += NT) tile[c * pp + (k / q + 1) * p + (k % q) + 1] = ue[base + k];
+            for (int k = threadIdx.x; k < nb; k += NT)
+                tile[c * pp + edge_tile_pos(p, q, k / q, k % q)] = ue[edge_index(a.geo, li, lj, k / q, k % q)];
+        }
+        __syncthreads();
+    }
+    // L u_i, L v_i and the coupled advection terms
+    {
+        double qs[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) qs[c] = A.c[c].q_scale_ptr ? *A.c[c].q_scale_ptr : A.c[c].q_scale;
+        for (int k = threadIdx.x; k < q2; k += NT) {
+            const int aa = k % q + 1, bb = k / q + 1;
+            const double *cf = a.coef + base + k;
+            double val[NC], dx[NC], dy[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double *tc = tile + c * pp;
+                double ux = 0, uxx = 0, uy = 0, uyy = 0;
+                for (int m = 0; m < p; ++m) {
+                    const double xr = tc[bb * p + m];
+                    const double yc = tc[m * p + aa];
+                    ux = fma(D[aa * p + m], xr, ux);
+                    uxx = fma(D2[aa * p + m], xr, uxx);
+                    uy = fma(D[bb * p + m], yc, uy);
+                    uyy = fma(D2[bb * p + m], yc, uyy);
+                }
+                val[c] = tc[bb * p + aa];
+                dx[c] = ux;
+                dy[c] = uy;
+                const double Lu = cf[0] * uxx + cf[n_int] * uyy + cf[2 * n_int] * ux + cf[3 * n_int] * uy +
+                                  cf[4 * n_int] * val[c];
+                luv[c * q2 + k] = Lu;
+                A.c[c].Lu_out[base + k] = Lu;
+            }
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double src = A.c[c].q_src ? qs[c] * A.c[c].q_src[base + k] : 0.0;
+                const double F = src - (val[0] * dx[c] + val[1] * dy[c]);
+                fv[c * q2 + k] = F;
+                A.c[c].F_out[base + k] = F;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---------------- up phase ----------------
+    if constexpr (UPM == UP_UPDATE) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const LeafArgs &ac = A.c[c];
+            const int last = ac.nprev;
+            double *vals = tile + c * pp;   // interior values of u^{n+1}, row-major q x q
+            for (int k = threadIdx.x; k < q2; k += NT) {
+                double v = ac.un[base + k];
+                for (int j = 0; j < last; ++j) {
+                    v += ac.ca[j] * ac.Lu_in[j * n_int + base + k];
+                    v += ac.cf[j] * ac.F_in[j * n_int + base + k];
+                }
+                v += ac.ca[last] * luv[c * q2 + k] + ac.cf[last] * fv[c * q2 + k];
+                ac.unew[base + k] = v;
+                vals[k] = v;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double *vals = tile + c * pp;
+            for (int k = threadIdx.x; k < nb; k += NT) {
+                const int e = k / q, m = k % q;
+                const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * p);
+                double f = 0.0;
+                if (e < 2) {
+                    for (int cc = 1; cc <= q; ++cc) f = fma(dr[cc], vals[m * q + cc - 1], f);
+                } else {
+                    for (int cc = 1; cc <= q; ++cc) f = fma(dr[cc], vals[(cc - 1) * q + m], f);
+                }
+                A.c[c].fpart[((int64_t)lj * a.geo.n1 + li) * nb + k] = f;
+            }
+        }
+        return;
+    }
+    const int SG = a.ainv.S * a.ainv.G;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const LeafArgs &ac = A.c[c];
+        for (int k = threadIdx.x; k < SG; k += NT) {
+            double r = 0.0;
+            if (k < q2) {
+                r = ac.un[base + k];
+                const int last = ac.nprev - 1;   // newest stage, held in LDS
+                for (int j = 0; j < last; ++j) {
+                    r += ac.ca[j] * ac.Lu_in[j * n_int + base + k];
+                    r += ac.cf[j] * ac.F_in[j * n_int + base + k];
+                }
+                r += ac.ca[last] * luv[c * q2 + k] + ac.cf[last] * fv[c * q2 + k];
+            }
+            xs[c * xcap + k] = r;
+        }
+    }
+    __syncthreads();
+    ps.finish_n<NC>(xs, xcap, part, pcap);
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double *wv = luv + c * q2;   // w = A_ii^{-1} rhs; luv is free again
+        reduce_rows<double>(part + c * pcap, a.ainv.rp * VW, a.ainv.G, red, [&](int row, double y) {
+            if (row < q2) {
+                wv[row] = y;
+                A.c[c].w_out[(int64_t)leaf * q2 + row] = y;
+            }
+        });
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const double *wv = luv + c * q2;
+        for (int k = threadIdx.x; k < nb; k += NT) {
+            const int e = k / q, m = k % q;
+            const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * p);
+            double h = 0.0;
+            if (e < 2) {
+                for (int cc = 1; cc <= q; ++cc) h = fma(dr[cc], wv[m * q + cc - 1], h);
+            } else {
+                for (int cc = 1; cc <= q; ++cc) h = fma(dr[cc], wv[(cc - 1) * q + m], h);
+            }
+            A.c[c].h_out[(int64_t)leaf * nb + k] = h;
+        }
+    }
+}
+
+template <int DN, int UPM>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_leaf_sys(LeafSysArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT];
+    leaf_sys_body<DN, UPM>(a, blockIdx.x, smem, red);
+}
+
+// =======================================================================================
 // launcher
 // =======================================================================================
 static int leaf_family(const LeafPhase &ph, bool fp32) {
@@ -430,6 +638,37 @@ int launch_leaf_group(const void *args, const int *base, int nprob, int total, s
     HPS_LEAF_GROUP_CASE(DOWN_STAGE, UP_UPDATE)
 #undef HPS_LEAF_GROUP_CASE
     hps_set_error("internal: unsupported grouped leaf phase (%d, %d)", down, up);
+    return HPS_EINVAL;
+}
+
+// Both components of a two-component step phase in one launch (FP64; the phase pairs of
+// the stage formulation).  ws[c] redirects component c's solve buffers (null: the
+// operator's own).
+int launch_leaf_sys(const hps_op *op, const LeafPhase &ph0, const LeafPhase &ph1, const Workspace *ws0,
+                    const Workspace *ws1, hipStream_t st) {
+    LeafSysArgs A;
+    size_t l0 = 0, l1 = 0;
+    TRY(fill_leaf_args(op, ph0, &A.c[0], &l0, ws0));
+    TRY(fill_leaf_args(op, ph1, &A.c[1], &l1, ws1));
+    const size_t pp = (size_t)op->p * op->p * 8, q2b = (size_t)op->q2 * 8;
+    const size_t lds = carve_bytes({2 * (size_t)A.c[0].xs_cap * 8, 2 * (size_t)A.c[0].part_cap * 8, 2 * pp, pp, pp,
+                                    2 * q2b, 2 * q2b});
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(op->nleaves), dim3(NT), lds, st, A); };
+    if (ph0.down != ph1.down || ph0.up != ph1.up) {
+        hps_set_error("internal: the two components must run the same phase");
+        return HPS_EINVAL;
+    }
+#define HPS_LEAF_SYS_CASE(DNV, UPV)     \
+    if (ph0.down == DNV && ph0.up == UPV) { \
+        go(k_leaf_sys<DNV, UPV>);       \
+        HPS_LAUNCHED();                 \
+        return HPS_OK;                  \
+    }
+    HPS_LEAF_SYS_CASE(DOWN_EVAL, UP_STAGE)
+    HPS_LEAF_SYS_CASE(DOWN_STAGE, UP_STAGE)
+    HPS_LEAF_SYS_CASE(DOWN_STAGE, UP_UPDATE)
+#undef HPS_LEAF_SYS_CASE
+    hps_set_error("internal: unsupported two-component leaf phase (%d, %d)", ph0.down, ph0.up);
     return HPS_EINVAL;
 }
 

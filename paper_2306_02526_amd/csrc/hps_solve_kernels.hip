@@ -249,6 +249,164 @@ __global__ __launch_bounds__(NT) void k_level_group(const LevelArgs *args, const
 }
 
 // =======================================================================================
+// two-component level products (FP64): both components of one (node, row tile, column
+// chunk) in one workgroup, the operator block streamed once for both
+// =======================================================================================
+struct LevelSysArgs {
+    LevelArgs c[2];   // per component; the operator fields of c[0] and c[1] are the same
+};
+
+template <bool UP>
+__device__ __forceinline__ void level_sys_body(const LevelSysArgs &A, int blk, unsigned char *smem, double *red,
+                                               int *s_last) {
+    constexpr int NC = 2, VW = 2;
+    const LevelArgs &a = A.c[0];
+    const int kch = a.pn.kch, ntile = a.pn.ntile;
+    const int chunk = blk % kch;
+    const int tile = (blk / kch) % ntile;
+    const int node = blk / (kch * ntile);
+    const int SG = a.pn.S * a.pn.G;
+    const int pst = a.pn.G * a.pn.rp * VW;
+    Carve cv{smem};
+    double *xs = cv.take<double>((size_t)NC * SG);
+    double *part = cv.take<double>((size_t)NC * pst);
+    PanelStream<double, PF, UNR> ps;
+    ps.start(reinterpret_cast<const double *>(a.pn.data) + (int64_t)node * a.pn.node_elems +
+                 (int64_t)(tile * kch + chunk) * a.pn.tile_elems,
+             a.pn.rp, a.pn.G, a.pn.S);
+    const int rows = a.pn.rp * VW;
+    const int myrow = tile * rows + threadIdx.x;
+    double fin[NC] = {0.0, 0.0};
+    int64_t ia = -1, ib = -1;
+    if (kch == 1 && (int)threadIdx.x < rows) {
+        if (UP) {
+            if (!a.root && myrow >= a.n3 && myrow < a.n3 + a.n12) {
+                const int m = myrow - a.n3;
+                const int64_t at = (m < a.n1) ? (int64_t)(2 * node) * a.nbc + a.a1[m]
+                                              : (int64_t)(2 * node + 1) * a.nbc + a.b2[m - a.n1];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) fin[c] = A.c[c].hc[at];
+            }
+        } else if (myrow < a.n3) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) fin[c] = A.c[c].w3[(int64_t)node * a.n3 + myrow];
+            ia = (int64_t)(2 * node) * a.nbc + a.a3[myrow];
+            ib = (int64_t)(2 * node + 1) * a.nbc + a.b3[myrow];
+        }
+    }
+    const int cols = UP ? a.n3 : a.n12;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const LevelArgs &ac = A.c[c];
+        for (int k = threadIdx.x; k < SG; k += NT) {
+            const int kg = chunk * SG + k;
+            double x = 0.0;
+            if (kg < cols) {
+                if (UP) {
+                    const double *ha = ac.hc + (int64_t)(2 * node) * a.nbc;
+                    const double *hb = ac.hc + (int64_t)(2 * node + 1) * a.nbc;
+                    x = hb[a.b3[kg]] - ha[a.a3[kg]];
+                    if (ac.r3) x += ac.r3[a.j3i[(int64_t)node * a.n3 + kg]];
+                } else {
+                    x = down_input(ac, ac.dir, node, kg);
+                }
+            }
+            xs[c * SG + k] = x;
+        }
+        if (!UP) {
+            const int nblk_node = ntile * kch, me = tile * kch + chunk;
+            const int per = (a.n12 + nblk_node - 1) / nblk_node;
+            const int m1 = min(a.n12, (me + 1) * per);
+            for (int m = me * per + threadIdx.x; m < m1; m += NT) {
+                const double v = down_input(ac, ac.dir, node, m);
+                if (m < a.n1) ac.ubc[(int64_t)(2 * node) * a.nbc + a.a1[m]] = v;
+                else ac.ubc[(int64_t)(2 * node + 1) * a.nbc + a.b2[m - a.n1]] = v;
+            }
+        }
+    }
+    __syncthreads();
+    ps.finish_n<NC>(xs, SG, part, pst);
+    __syncthreads();
+    if (kch == 1) {
+        const int G = a.pn.G;
+        const int nsl = min(G, NT / rows);
+        const int t = threadIdx.x;
+        const int row = t % rows, sl = t / rows;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const LevelArgs &ac = A.c[c];
+            if (sl < nsl) {
+                double y = 0.0;
+                for (int gg = sl; gg < G; gg += nsl) y += part[c * pst + gg * rows + row];
+                red[sl * rows + row] = y;
+            }
+            __syncthreads();
+            if (t < rows) {
+                double y = 0.0;
+                for (int s2 = 0; s2 < nsl; ++s2) y += red[s2 * rows + t];
+                if (UP) {
+                    if (myrow < a.n3) ac.w3[(int64_t)node * a.n3 + myrow] = y;
+                    else if (!a.root && myrow < a.n3 + a.n12) ac.h[(int64_t)node * a.n12 + myrow - a.n3] = fin[c] + y;
+                } else if (myrow < a.n3) {
+                    const double u3 = y + fin[c];
+                    ac.ubc[ia] = u3;
+                    ac.ubc[ib] = u3;
+                }
+            }
+            __syncthreads();
+        }
+        return;
+    }
+    // split-K: publish both components' partial sums; the last workgroup of the (node,
+    // tile) to arrive (counted on component 0's counters) adds the chunks in a fixed order
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double *pp = A.c[c].part + ((int64_t)node * ntile + tile) * kch * rows;
+        for (int idx = threadIdx.x; idx < rows; idx += NT)
+            pp[(int64_t)chunk * rows + idx] = panel_sum<double>(part + c * pst, a.pn.rp, a.pn.G, idx);
+    }
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) *s_last = (atomicAdd(&a.cnt[node * ntile + tile], 1) == kch - 1);
+    __syncthreads();
+    if (!*s_last) return;
+    __threadfence();
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const LevelArgs &ac = A.c[c];
+        const double *pp = ac.part + ((int64_t)node * ntile + tile) * kch * rows;
+        for (int r0 = 0; r0 < rows; r0 += NT) {
+            const int nr = min(NT, rows - r0);
+            const int nsl = NT / nr;
+            const int t = threadIdx.x;
+            const int row = t % nr, sl = t / nr;
+            if (sl < nsl) {
+                double y = 0.0;
+                for (int cc = sl; cc < kch; cc += nsl) y += pp[(int64_t)cc * rows + r0 + row];
+                red[sl * nr + row] = y;
+            }
+            __syncthreads();
+            if (t < nr) {
+                double y = 0.0;
+                for (int s2 = 0; s2 < nsl; ++s2) y += red[s2 * nr + t];
+                if (UP) up_finalize(ac, node, tile * rows + r0 + t, y);
+                else down_finalize(ac, node, tile * rows + r0 + t, y);
+            }
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) a.cnt[node * ntile + tile] = 0;
+}
+
+template <bool UP>
+__global__ __launch_bounds__(NT) void k_level_sys(LevelSysArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT];
+    __shared__ int s_last;
+    level_sys_body<UP>(a, blockIdx.x, smem, red, &s_last);
+}
+
+// =======================================================================================
 // stage-1 evaluation (L u^n, F_1) and the refinement residual, from a canonical vector
 // =======================================================================================
 __device__ void tile_from_canonical(const LeafGeo &g, int li, int lj, const double *u,
@@ -668,6 +826,89 @@ __global__ __launch_bounds__(NT) void k_root_group(const LevelArgs *ups, const L
     root_body<T>(ups[lo], dns[lo], w - base[lo], smem, red);
 }
 
+// The fused root for two components: u_3 = S u_12 + X d for each.
+__device__ __forceinline__ void root_sys_body(const LevelSysArgs &U, const LevelSysArgs &Dn, int tile,
+                                              unsigned char *smem, double *red) {
+    constexpr int NC = 2, VW = 2;
+    const LevelArgs &up = U.c[0], &dn = Dn.c[0];
+    const int SG1 = up.pn.S * up.pn.G, SG2 = dn.pn.S * dn.pn.G;
+    const int pst1 = up.pn.G * up.pn.rp * VW, pst2 = dn.pn.G * dn.pn.rp * VW;
+    Carve cv{smem};
+    double *xs1 = cv.take<double>((size_t)NC * SG1);
+    double *xs2 = cv.take<double>((size_t)NC * SG2);
+    double *part1 = cv.take<double>((size_t)NC * pst1);
+    double *part2 = cv.take<double>((size_t)NC * pst2);
+    PanelStream<double, PF, UNR> ps, ps2;
+    ps.start(reinterpret_cast<const double *>(up.pn.data) + (int64_t)tile * up.pn.tile_elems, up.pn.rp, up.pn.G,
+             up.pn.S);
+    ps2.start(reinterpret_cast<const double *>(dn.pn.data) + (int64_t)tile * dn.pn.tile_elems, dn.pn.rp, dn.pn.G,
+              dn.pn.S);
+    const int rows = up.pn.rp * VW;
+    const int myrow = tile * rows + threadIdx.x;
+    int64_t ia = -1, ib = -1;
+    if ((int)threadIdx.x < rows && myrow < dn.n3) {
+        ia = dn.a3[myrow];
+        ib = (int64_t)dn.nbc + dn.b3[myrow];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const LevelArgs &uc = U.c[c], &dc = Dn.c[c];
+        for (int k = threadIdx.x; k < SG1; k += NT) {
+            double x = 0.0;
+            if (k < up.n3) {
+                x = uc.hc[(int64_t)up.nbc + up.b3[k]] - uc.hc[up.a3[k]];
+                if (uc.r3) x += uc.r3[up.j3i[k]];
+            }
+            xs1[c * SG1 + k] = x;
+        }
+        for (int k = threadIdx.x; k < SG2; k += NT)
+            xs2[c * SG2 + k] = (k < dn.n12 && dc.dir) ? dc.dir[dn.root_map[k]] : 0.0;
+        const int per = (dn.n12 + dn.pn.ntile - 1) / dn.pn.ntile;
+        const int m1 = min(dn.n12, (tile + 1) * per);
+        for (int m = tile * per + threadIdx.x; m < m1; m += NT) {
+            const double v = dc.dir ? dc.dir[dn.root_map[m]] : 0.0;
+            if (m < dn.n1) dc.ubc[dn.a1[m]] = v;
+            else dc.ubc[(int64_t)dn.nbc + dn.b2[m - dn.n1]] = v;
+        }
+    }
+    __syncthreads();
+    ps.finish_n<NC>(xs1, SG1, part1, pst1);
+    ps2.finish_n<NC>(xs2, SG2, part2, pst2);
+    __syncthreads();
+    const int nsl1 = min(up.pn.G, NT / rows), nsl2 = min(dn.pn.G, NT / rows);
+    const int t = threadIdx.x, row = t % rows, sl = t / rows;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double y1 = 0.0, y2 = 0.0;
+        if (sl < nsl1)
+            for (int gg = sl; gg < up.pn.G; gg += nsl1) y1 += part1[c * pst1 + gg * rows + row];
+        if (sl < nsl2)
+            for (int gg = sl; gg < dn.pn.G; gg += nsl2) y2 += part2[c * pst2 + gg * rows + row];
+        red[t] = y1;
+        __syncthreads();
+        double w3 = 0.0;
+        if (t < rows)
+            for (int s2 = 0; s2 < nsl1; ++s2) w3 += red[s2 * rows + t];
+        __syncthreads();
+        red[t] = y2;
+        __syncthreads();
+        if (t < rows && myrow < dn.n3) {
+            double su = 0.0;
+            for (int s2 = 0; s2 < nsl2; ++s2) su += red[s2 * rows + t];
+            const double u3 = su + w3;
+            Dn.c[c].ubc[ia] = u3;
+            Dn.c[c].ubc[ib] = u3;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_root_sys(LevelSysArgs up, LevelSysArgs dn) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT];
+    root_sys_body(up, dn, blockIdx.x, smem, red);
+}
+
 static size_t level_lds(const Panel &pn) {
     const size_t es = pn.vw == 2 ? 8 : 4;
     return carve_bytes({(size_t)pn.S * pn.G * es, (size_t)pn.G * pn.rp * pn.vw * es});
@@ -728,6 +969,84 @@ int launch_levels(const hps_op *op, bool fp32, const double *jump, const double 
         else hipLaunchKernelGGL((k_level<double, false>), dim3(nb), dim3(NT), level_lds(pn), st, a);
         HPS_LAUNCHED();
     }
+    return HPS_OK;
+}
+
+// ---- two components on one operator (FP64) ----
+static void use_workspace(const hps_op *op, int l, bool up, const Workspace *ws, LevelArgs &a);
+
+static size_t sys_level_lds(const Panel &pn) {
+    return carve_bytes({(size_t)2 * pn.S * pn.G * 8, (size_t)2 * pn.G * pn.rp * pn.vw * 8});
+}
+
+static size_t sys_root_lds(const hps_op *op) {
+    const Panel &x = op->lv[0].xu64, &sp = op->lv[0].s64;
+    return carve_bytes({(size_t)2 * x.S * x.G * 8, (size_t)2 * sp.S * sp.G * 8, (size_t)2 * x.G * x.rp * x.vw * 8,
+                        (size_t)2 * sp.G * sp.rp * sp.vw * 8}) + 32;
+}
+
+// Dynamic LDS a two-component level kernel may take on the current device (the kernels'
+// static arrays take the rest).
+static size_t sys_lds_limit() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) {
+        (void)hipGetLastError();
+        return 65536 - 4096;
+    }
+    return (size_t)v - 4096;
+}
+
+int launch_levels_sys(const hps_op *op, const Workspace *const ws[2], const double *const dir[2], hipStream_t st) {
+    const size_t lim = sys_lds_limit();
+    auto comp_args = [&](int l, bool up, int c) {
+        LevelArgs a = level_args(op, l, false, up);
+        use_workspace(op, l, up, ws[c], a);
+        a.dir = dir[c];
+        return a;
+    };
+    auto run_level = [&](int l, bool up) -> int {
+        const Panel &pn = up ? op->lv[l].xu64 : op->lv[l].s64;
+        const unsigned nb = (unsigned)(op->lv[l].nodes * pn.ntile * pn.kch);
+        const size_t lds2 = sys_level_lds(pn);
+        if (lds2 <= lim) {
+            LevelSysArgs A;
+            A.c[0] = comp_args(l, up, 0);
+            A.c[1] = comp_args(l, up, 1);
+            if (up) hipLaunchKernelGGL(k_level_sys<true>, dim3(nb), dim3(NT), lds2, st, A);
+            else hipLaunchKernelGGL(k_level_sys<false>, dim3(nb), dim3(NT), lds2, st, A);
+            HPS_LAUNCHED();
+            return HPS_OK;
+        }
+        // both input vectors would not fit in LDS: one launch per component
+        for (int c = 0; c < 2; ++c) {
+            const LevelArgs a = comp_args(l, up, c);
+            if (up) hipLaunchKernelGGL((k_level<double, true>), dim3(nb), dim3(NT), level_lds(pn), st, a);
+            else hipLaunchKernelGGL((k_level<double, false>), dim3(nb), dim3(NT), level_lds(pn), st, a);
+            HPS_LAUNCHED();
+        }
+        return HPS_OK;
+    };
+    const bool rootf = root_fusable(op, false) && sys_root_lds(op) <= lim;
+    for (int l = op->L - 1; l >= (rootf ? 1 : 0); --l) TRY(run_level(l, true));
+    if (op->L == 0) {
+        for (int c = 0; c < 2; ++c) {
+            hipLaunchKernelGGL(k_root_leaf_ub, dim3(1), dim3(NT), 0, st, dir[c], (const int *)op->root_map,
+                               ws[c] ? ws[c]->ub_leaf : op->ub_leaf, 4 * op->q);
+            HPS_LAUNCHED();
+        }
+        return HPS_OK;
+    }
+    if (rootf) {
+        LevelSysArgs U, Dn;
+        for (int c = 0; c < 2; ++c) {
+            U.c[c] = comp_args(0, true, c);
+            Dn.c[c] = comp_args(0, false, c);
+        }
+        hipLaunchKernelGGL(k_root_sys, dim3(op->lv[0].xu64.ntile), dim3(NT), sys_root_lds(op), st, U, Dn);
+        HPS_LAUNCHED();
+    }
+    for (int l = rootf ? 1 : 0; l < op->L; ++l) TRY(run_level(l, false));
     return HPS_OK;
 }
 
@@ -849,14 +1168,14 @@ int launch_residual(const hps_op *op, const double *u, const double *rhs, const 
 }
 
 int launch_interface_lines(const hps_op *op, double *u, const double *f_end, hipStream_t st,
-                           const double *jump) {
+                           const double *jump, const double *fpart) {
     ProfScope ps_(&op->prof, KF_LINES, st);
     int rc = launch_scatter_boundary(op, f_end, u, st);
     if (rc) return rc;
     LineArgs la{};
     la.geo = geo_of(op);
     la.u = u;
-    la.fpart = op->ir_flux;
+    la.fpart = fpart ? fpart : op->ir_flux;
     la.D = op->D;
     la.cp = op->tri_cp;
     la.inv_den = op->tri_cp + op->tri_stride;

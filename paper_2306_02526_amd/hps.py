@@ -22,7 +22,7 @@ ERRORS = {-1: "HPS_EINVAL", -2: "HPS_ENOMEM", -3: "HPS_EDEVICE", -4: "HPS_ESINGU
 # every entry point declared in include/hps.h, include/hps_batch.h and include/hps_serve.h
 EXPORTED = ["hps_last_error", "hps_num_nodes", "hps_nodes", "hps_build", "hps_op_bytes",
             "hps_solve", "hps_free", "hps_profile_enable", "hps_profile_read", "ark_create", "ark_step", "ark_stage_solves_per_step",
-            "ark_free", "ark_step_slope", "hps_solve_batched", "ark_step_batched", "hps_batch_streams",
+            "ark_free", "ark_step_slope", "ark_step_burgers", "hps_solve_batched", "ark_step_batched", "hps_batch_streams",
             "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_release", "srv_get_stats", "srv_destroy"]
 
 
@@ -118,6 +118,8 @@ def lib():
     L.ark_step.argtypes = [vp, dbl, vp, vp, vp, P(dbl), vp, vp]
     L.ark_step_slope.restype = i32
     L.ark_step_slope.argtypes = [vp, dbl, vp, vp, vp, P(dbl), vp, vp]
+    L.ark_step_burgers.restype = i32
+    L.ark_step_burgers.argtypes = [vp, vp, dbl, vp, vp, vp, vp, vp]
     L.ark_stage_solves_per_step.restype = i32
     L.ark_stage_solves_per_step.argtypes = [vp]
     L.ark_free.restype = None
@@ -324,6 +326,16 @@ def ark_step_slope(ctx, t, u, q_stages=None, q_space=None, q_time=None, fdot_sta
                                 _dptr(q_stages, s * op.n_int, "q_stages"), _dptr(q_space, op.n_int, "q_space"),
                                 qt, _dptr(fdot_stages, s * op.n_bdry, "fdot_stages"), _stream(stream)))
     return u
+
+
+def ark_step_burgers(cu, cv, t, u, v, fu_stages=None, fv_stages=None, stream=None):
+    """One step of the 2-D Burgers system on the contexts cu, cv of one operator, in place on
+    u and v; fu_stages, fv_stages: Dirichlet data [s+1][n_bdry] of each component or None."""
+    op, s = cu.op, cu.s
+    _check(lib().ark_step_burgers(cu.handle, cv.handle, float(t), _dptr(u, op.N, "u"), _dptr(v, op.N, "v"),
+                                  _dptr(fu_stages, (s + 1) * op.n_bdry, "fu_stages"),
+                                  _dptr(fv_stages, (s + 1) * op.n_bdry, "fv_stages"), _stream(stream)))
+    return u, v
 
 
 def ark_stage_solves_per_step(ctx):

@@ -74,6 +74,7 @@ def test_null_handles_are_rejected():
     L.ark_free(None)
     out = ctypes.c_void_p()
     assert L.hps_build(None, None, 1.0, 0, None, ctypes.byref(out)) == -1
+    assert L.ark_step_burgers(None, None, 0.0, None, None, None, None, None) == -1
 
 
 @pytest.mark.parametrize("flags", [4, -1, 8 | hps.HPS_FP32_IR])
