@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-slope", action="store_true")
     ap.add_argument("--slope-steps", type=int, default=10)
+    ap.add_argument("--no-burgers", action="store_true")
+    ap.add_argument("--burgers-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stage-solves", type=int, default=3)
     ap.add_argument("--workload", default="allen_cahn", choices=["allen_cahn", "batched", "serving"],
@@ -116,6 +118,82 @@ def leaf_down_up_algorithmic_bytes(n_leaves, q, stages, elem_bytes):
     field = sum(field_reads) / len(field_reads) + 2 * q2 + q2 + 4 * q
     per_leaf = (q2 * 4 * q + q2 * q2) * elem_bytes + field * 8
     return n_leaves * per_leaf
+
+
+def leaf2_down_up_algorithmic_bytes(n_leaves, q, stages, elem_bytes):
+    """The same for the two-component leaf kernel: the operators and the 5 coefficients of
+    L are read once, every field vector of the list above once per component."""
+    q2 = q * q
+    launches = list(range(2, stages))
+    comp = [4 * q + q2 + q2 + 2 * (i - 1) * q2 + 2 * q2 + q2 + 4 * q for i in launches]
+    field = 5 * q2 + 2 * sum(comp) / len(comp)
+    return n_leaves * ((q2 * 4 * q + q2 * q2) * elem_bytes + field * 8)
+
+
+def burgers_leg(args, torch, hps, workloads, g, x, y, n_int, tab, tiles, dev):
+    """Two-dimensional Burgers system (traveling-wave closed form, eps = 0.1, dt = 1e-3,
+    boundary data from the closed form) on the bench grid: ark_step_burgers, which solves
+    both components in every stage, 2 (s - 1) stage solves per step."""
+    import numpy as np
+    sol = workloads.BurgersTravelingWave(0.1)
+    dt = 1e-3
+    co = dict(zip(("cxx", "cyy", "cx", "cy", "c0"), workloads.burgers_coeffs(sol.eps, n_int)))
+    op = hps.hps_build(g, {k: torch.tensor(v, device=dev) for k, v in co.items()}, tab["gamma"] * dt,
+                       hps.HPS_FP64 | tiles)
+    _, op_bytes = op.bytes()
+    cu, cv = hps.ark_create(op, tab, dt), hps.ark_create(op, tab, dt)
+    N = len(x)
+    x0, x1, y0, y1 = g.x0, g.x1, g.y0, g.y1
+    on = lambda a, b: np.abs(a - b) < 1e-13
+    bd = np.nonzero((np.arange(N) >= n_int) & (on(x, x0) | on(x, x1) | on(y, y0) | on(y, y1)))[0]
+    assert len(bd) == op.n_bdry
+    nsteps = args.warmup + args.burgers_steps + 4
+    # boundary data of every step, resident on the GPU; copied into fixed arrays per step
+    ts = [[k * dt + c * dt for c in tab["c"]] + [(k + 1) * dt] for k in range(nsteps)]
+    ex = [[sol.exact(t, x[bd], y[bd]) for t in row] for row in ts]
+    all_fu = torch.tensor(np.array([[e[0] for e in row] for row in ex]), device=dev)
+    all_fv = torch.tensor(np.array([[e[1] for e in row] for row in ex]), device=dev)
+    fu, fv = all_fu[0].clone(), all_fv[0].clone()
+    u0, v0 = sol.exact(0.0, x, y)
+    u, v = torch.tensor(u0, device=dev), torch.tensor(v0, device=dev)
+
+    def step(k):
+        fu.copy_(all_fu[k])
+        fv.copy_(all_fv[k])
+        hps.ark_step_burgers(cu, cv, k * dt, u, v, fu, fv)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.burgers_steps):
+        step(k)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    k_end = args.warmup + args.burgers_steps
+    ue, ve = sol.exact(k_end * dt, x, y)
+    err = max(float(np.abs(u.cpu().numpy() - ue).max()), float(np.abs(v.cpu().numpy() - ve).max()))
+    # per-kernel durations (eager steps, HIP events on the launch stream)
+    hps.hps_profile_enable(op, True)
+    for k in range(k_end, k_end + 4):
+        step(k)
+    torch.cuda.synchronize()
+    prof = hps.hps_profile_read(op)
+    hps.hps_profile_enable(op, False)
+    stages = tab["s"] - 1
+    kern = {k: {"launches_per_step": v[0] // 4, "us_per_launch": round(1e3 * v[1] / v[0], 2)} for k, v in prof.items()}
+    q = g.p - 2
+    leaf_us = 1e3 * prof["leaf2_down_up_fp64"][1] / prof["leaf2_down_up_fp64"][0]
+    alg = leaf2_down_up_algorithmic_bytes(g.n1 * g.n2, q, tab["s"], 8)
+    out = {"stage_solves_per_s": round(2 * stages * args.burgers_steps / el, 1),
+           "ms_per_step": round(1e3 * el / args.burgers_steps, 3), "steps": args.burgers_steps,
+           "components": 2, "eps": sol.eps, "dt": dt,
+           "operator_GBps": round(op_bytes * stages * args.burgers_steps / el / 1e9, 1),
+           "max_err_vs_closed_form": err, "kernels": kern,
+           "leaf2_down_up": {"us_per_launch": round(leaf_us, 2), "algorithmic_bytes_per_launch": int(alg),
+                             "achieved_GBps": round(alg / (leaf_us * 1e-6) / 1e9, 1)}}
+    op.free()
+    return out
 
 
 def main():
@@ -246,6 +324,12 @@ def main():
         log(f"slope formulation: {slope}")
         del ctxs
 
+    # ---- two-component Burgers system on the same grid ----
+    burgers = None
+    if not args.no_burgers:
+        burgers = burgers_leg(args, torch, hps, workloads, g, x, y, n_int, tab, tiles, dev)
+        log(f"burgers: {burgers}")
+
     # ---- FP32 operators + FP64 iterative refinement, same steps ----
     fp32 = None
     if not args.no_fp32:
@@ -322,6 +406,7 @@ def main():
                      "avg_launch_us": round(leaf_us, 2)},
         "fp32_ir": fp32,
         "slope_formulation": slope,
+        "burgers_system": burgers,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -646,6 +646,9 @@ int launch_leaf_group(const void *args, const int *base, int nprob, int total, s
 // operator's own).
 int launch_leaf_sys(const hps_op *op, const LeafPhase &ph0, const LeafPhase &ph1, const Workspace *ws0,
                     const Workspace *ws1, hipStream_t st) {
+    ProfScope ps_(&op->prof,
+                  ph0.down == LD_EVAL ? KF_LEAF2_EVAL_UP64 : (ph0.up == LU_UPDATE ? KF_LEAF2_DOWN_UPDATE64 : KF_LEAF2_DOWN_UP64),
+                  st);
     LeafSysArgs A;
     size_t l0 = 0, l1 = 0;
     TRY(fill_leaf_args(op, ph0, &A.c[0], &l0, ws0));

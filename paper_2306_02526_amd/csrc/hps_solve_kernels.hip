@@ -665,7 +665,8 @@ const char *const kKernelFamilyNames[KF_COUNT] = {
     "leaf_up_fp64", "leaf_up_fp32", "leaf_down_fp64", "leaf_down_fp32", "leaf_eval_up_fp64",
     "leaf_eval_up_fp32", "leaf_down_up_fp64", "leaf_down_up_fp32", "leaf_down_update_fp64",
     "leaf_eval_update", "level_up_fp64", "level_up_fp32", "level_down_fp64", "level_down_fp32",
-    "residual", "lines"};
+    "residual", "lines", "leaf2_eval_up_fp64", "leaf2_down_up_fp64", "leaf2_down_update_fp64",
+    "level2_up_fp64", "level2_down_fp64"};
 
 hipEvent_t Profiler::get() {
     if (!pool.empty()) {
@@ -1028,7 +1029,11 @@ int launch_levels_sys(const hps_op *op, const Workspace *const ws[2], const doub
         return HPS_OK;
     };
     const bool rootf = root_fusable(op, false) && sys_root_lds(op) <= lim;
-    for (int l = op->L - 1; l >= (rootf ? 1 : 0); --l) TRY(run_level(l, true));
+    {
+        ProfScope ps_(&op->prof, KF_LEVEL2_UP64, st);
+        for (int l = op->L - 1; l >= (rootf ? 1 : 0); --l) TRY(run_level(l, true));
+    }
+    ProfScope ps_(&op->prof, KF_LEVEL2_DOWN64, st);
     if (op->L == 0) {
         for (int c = 0; c < 2; ++c) {
             hipLaunchKernelGGL(k_root_leaf_ub, dim3(1), dim3(NT), 0, st, dir[c], (const int *)op->root_map,
