@@ -140,6 +140,7 @@ def burgers_leg(args, torch, hps, workloads, g, x, y, n_int, tab, tiles, dev):
     co = dict(zip(("cxx", "cyy", "cx", "cy", "c0"), workloads.burgers_coeffs(sol.eps, n_int)))
     op = hps.hps_build(g, {k: torch.tensor(v, device=dev) for k, v in co.items()}, tab["gamma"] * dt,
                        hps.HPS_FP64 | tiles)
+    wide = bool(tiles & hps.HPS_WIDE_TILES)
     _, op_bytes = op.bytes()
     cu, cv = hps.ark_create(op, tab, dt), hps.ark_create(op, tab, dt)
     N = len(x)
@@ -187,7 +188,7 @@ def burgers_leg(args, torch, hps, workloads, g, x, y, n_int, tab, tiles, dev):
     alg = leaf2_down_up_algorithmic_bytes(g.n1 * g.n2, q, tab["s"], 8)
     out = {"stage_solves_per_s": round(2 * stages * args.burgers_steps / el, 1),
            "ms_per_step": round(1e3 * el / args.burgers_steps, 3), "steps": args.burgers_steps,
-           "components": 2, "eps": sol.eps, "dt": dt,
+           "components": 2, "eps": sol.eps, "dt": dt, "level_tiles": "wide" if wide else "thin",
            "operator_GBps": round(op_bytes * stages * args.burgers_steps / el / 1e9, 1),
            "max_err_vs_closed_form": err, "kernels": kern,
            "leaf2_down_up": {"us_per_launch": round(leaf_us, 2), "algorithmic_bytes_per_launch": int(alg),
@@ -327,7 +328,9 @@ def main():
     # ---- two-component Burgers system on the same grid ----
     burgers = None
     if not args.no_burgers:
-        burgers = burgers_leg(args, torch, hps, workloads, g, x, y, n_int, tab, tiles, dev)
+        # two right-hand sides per level product: wide level tiles unless thin ones are asked for
+        btiles = 0 if args.level_tiles == "thin" else hps.HPS_WIDE_TILES
+        burgers = burgers_leg(args, torch, hps, workloads, g, x, y, n_int, tab, btiles, dev)
         log(f"burgers: {burgers}")
 
     # ---- FP32 operators + FP64 iterative refinement, same steps ----

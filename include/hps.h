@@ -63,7 +63,8 @@ extern "C" {
 #define HPS_WIDE_TILES 2 /* or-ed with either: cut each tree level's operators into few
                             large row tiles (fewer workgroups per level).  For
                             operators stepped many at a time (ark_step_batched, the
-                            server); a single solve of one operator is slower.      */
+                            server) and for two-component steps (ark_step_burgers);
+                            one scalar problem runs at the same speed either way.   */
 
 typedef struct {
     double x0, x1, y0, y1;   /* domain; (x1-x0)/n1 must equal (y1-y0)/n2 (square leaves) */

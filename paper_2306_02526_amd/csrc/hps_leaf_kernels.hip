@@ -518,7 +518,7 @@ __device__ __forceinline__ void leaf_sys_body(const LeafSysArgs &A, int leaf, un
 }
 
 template <int DN, int UPM>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_leaf_sys(LeafSysArgs a) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_leaf_sys(LeafSysArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[NT];
     leaf_sys_body<DN, UPM>(a, blockIdx.x, smem, red);

@@ -12,6 +12,7 @@
 // issued before the workgroup gathers its input vector, which hides the gather latency.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "hps_device.h"
@@ -1009,26 +1010,24 @@ int launch_levels_sys(const hps_op *op, const Workspace *const ws[2], const doub
     auto run_level = [&](int l, bool up) -> int {
         const Panel &pn = up ? op->lv[l].xu64 : op->lv[l].s64;
         const unsigned nb = (unsigned)(op->lv[l].nodes * pn.ntile * pn.kch);
+        // at most 2 * XS_BYTES of input vectors plus the partial sums: within the LDS of a
+        // gfx950 workgroup (160 KiB)
         const size_t lds2 = sys_level_lds(pn);
-        if (lds2 <= lim) {
-            LevelSysArgs A;
-            A.c[0] = comp_args(l, up, 0);
-            A.c[1] = comp_args(l, up, 1);
-            if (up) hipLaunchKernelGGL(k_level_sys<true>, dim3(nb), dim3(NT), lds2, st, A);
-            else hipLaunchKernelGGL(k_level_sys<false>, dim3(nb), dim3(NT), lds2, st, A);
-            HPS_LAUNCHED();
-            return HPS_OK;
+        if (lds2 > lim) {
+            hps_set_error("two-component level product needs %zu bytes of LDS, the device allows %zu", lds2, lim);
+            return HPS_EDEVICE;
         }
-        // both input vectors would not fit in LDS: one launch per component
-        for (int c = 0; c < 2; ++c) {
-            const LevelArgs a = comp_args(l, up, c);
-            if (up) hipLaunchKernelGGL((k_level<double, true>), dim3(nb), dim3(NT), level_lds(pn), st, a);
-            else hipLaunchKernelGGL((k_level<double, false>), dim3(nb), dim3(NT), level_lds(pn), st, a);
-            HPS_LAUNCHED();
-        }
+        LevelSysArgs A;
+        A.c[0] = comp_args(l, up, 0);
+        A.c[1] = comp_args(l, up, 1);
+        if (up) hipLaunchKernelGGL(k_level_sys<true>, dim3(nb), dim3(NT), lds2, st, A);
+        else hipLaunchKernelGGL(k_level_sys<false>, dim3(nb), dim3(NT), lds2, st, A);
+        HPS_LAUNCHED();
         return HPS_OK;
     };
-    const bool rootf = root_fusable(op, false) && sys_root_lds(op) <= lim;
+    // the fused root only while two workgroups fit on a compute unit: above that the
+    // separate up and down root launches are faster (measured at 64x64 leaves, p = 16)
+    const bool rootf = root_fusable(op, false) && sys_root_lds(op) <= std::min<size_t>(lim, 65536);
     {
         ProfScope ps_(&op->prof, KF_LEVEL2_UP64, st);
         for (int l = op->L - 1; l >= (rootf ? 1 : 0); --l) TRY(run_level(l, true));

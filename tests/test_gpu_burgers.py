@@ -115,6 +115,15 @@ def test_rotating_flow_matches_oracle(torch):
     run_against_oracle(torch, S, u, v, 2)
 
 
+def test_wide_level_tiles_match_oracle(torch):
+    """An operator built with HPS_WIDE_TILES (few large level tiles, separate root launches)."""
+    say("[burgers] wide level tiles, 8x8 p=12, diffusive closed form, 2 steps")
+    sol = workloads.BurgersDiffusive(0.1)
+    S = Setup(torch, (0, 1, 0, 1), 8, 8, 12, sol.eps, 0.01, flags=hps.HPS_WIDE_TILES)
+    u, v = sol.exact(0.0, S.x, S.y)
+    run_against_oracle(torch, S, u, v, 2, sol)
+
+
 def test_single_leaf_and_random_data(torch):
     """One leaf (no merge levels) and a 2x1 grid, random fields and boundary data."""
     rng = np.random.default_rng(17)
