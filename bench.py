@@ -130,16 +130,18 @@ def leaf2_down_up_algorithmic_bytes(n_leaves, q, stages, elem_bytes):
     return n_leaves * ((q2 * 4 * q + q2 * q2) * elem_bytes + field * 8)
 
 
-def burgers_leg(args, torch, hps, workloads, g, x, y, n_int, tab, tiles, dev):
+def burgers_leg(args, torch, hps, workloads, g, x, y, n_int, tab, tiles, dev, uniform=True, profile=True):
     """Two-dimensional Burgers system (traveling-wave closed form, eps = 0.1, dt = 1e-3,
     boundary data from the closed form) on the bench grid: ark_step_burgers, which solves
-    both components in every stage, 2 (s - 1) stage solves per step."""
+    both components in every stage, 2 (s - 1) stage solves per step.  uniform: build with
+    HPS_UNIFORM_COEFFS (L = eps Lap has constant coefficients: one stored copy of every
+    leaf and level operator)."""
     import numpy as np
     sol = workloads.BurgersTravelingWave(0.1)
     dt = 1e-3
     co = dict(zip(("cxx", "cyy", "cx", "cy", "c0"), workloads.burgers_coeffs(sol.eps, n_int)))
     op = hps.hps_build(g, {k: torch.tensor(v, device=dev) for k, v in co.items()}, tab["gamma"] * dt,
-                       hps.HPS_FP64 | tiles)
+                       hps.HPS_FP64 | tiles | (hps.HPS_UNIFORM_COEFFS if uniform else 0))
     wide = bool(tiles & hps.HPS_WIDE_TILES)
     _, op_bytes = op.bytes()
     cu, cv = hps.ark_create(op, tab, dt), hps.ark_create(op, tab, dt)
@@ -174,6 +176,15 @@ def burgers_leg(args, torch, hps, workloads, g, x, y, n_int, tab, tiles, dev):
     k_end = args.warmup + args.burgers_steps
     ue, ve = sol.exact(k_end * dt, x, y)
     err = max(float(np.abs(u.cpu().numpy() - ue).max()), float(np.abs(v.cpu().numpy() - ve).max()))
+    stages = tab["s"] - 1
+    out = {"stage_solves_per_s": round(2 * stages * args.burgers_steps / el, 1),
+           "ms_per_step": round(1e3 * el / args.burgers_steps, 3), "steps": args.burgers_steps,
+           "components": 2, "eps": sol.eps, "dt": dt, "level_tiles": "wide" if wide else "thin",
+           "operators": "one shared copy (uniform coefficients)" if uniform else "per node",
+           "operator_bytes": op_bytes, "max_err_vs_closed_form": err}
+    if not profile:
+        op.free()
+        return out
     # per-kernel durations (eager steps, HIP events on the launch stream)
     hps.hps_profile_enable(op, True)
     for k in range(k_end, k_end + 4):
@@ -181,18 +192,15 @@ def burgers_leg(args, torch, hps, workloads, g, x, y, n_int, tab, tiles, dev):
     torch.cuda.synchronize()
     prof = hps.hps_profile_read(op)
     hps.hps_profile_enable(op, False)
-    stages = tab["s"] - 1
     kern = {k: {"launches_per_step": v[0] // 4, "us_per_launch": round(1e3 * v[1] / v[0], 2)} for k, v in prof.items()}
-    q = g.p - 2
     leaf_us = 1e3 * prof["leaf2_down_up_fp64"][1] / prof["leaf2_down_up_fp64"][0]
-    alg = leaf2_down_up_algorithmic_bytes(g.n1 * g.n2, q, tab["s"], 8)
-    out = {"stage_solves_per_s": round(2 * stages * args.burgers_steps / el, 1),
-           "ms_per_step": round(1e3 * el / args.burgers_steps, 3), "steps": args.burgers_steps,
-           "components": 2, "eps": sol.eps, "dt": dt, "level_tiles": "wide" if wide else "thin",
-           "operator_GBps": round(op_bytes * stages * args.burgers_steps / el / 1e9, 1),
-           "max_err_vs_closed_form": err, "kernels": kern,
-           "leaf2_down_up": {"us_per_launch": round(leaf_us, 2), "algorithmic_bytes_per_launch": int(alg),
-                             "achieved_GBps": round(alg / (leaf_us * 1e-6) / 1e9, 1)}}
+    out["kernels"] = kern
+    out["leaf2_down_up_us_per_launch"] = round(leaf_us, 2)
+    if not uniform:
+        # every leaf's operators streamed from HBM: bytes as for the scalar kernel
+        alg = leaf2_down_up_algorithmic_bytes(g.n1 * g.n2, g.p - 2, tab["s"], 8)
+        out["leaf2_down_up"] = {"algorithmic_bytes_per_launch": int(alg),
+                                "achieved_GBps": round(alg / (leaf_us * 1e-6) / 1e9, 1)}
     op.free()
     return out
 
@@ -331,6 +339,8 @@ def main():
         # two right-hand sides per level product: wide level tiles unless thin ones are asked for
         btiles = 0 if args.level_tiles == "thin" else hps.HPS_WIDE_TILES
         burgers = burgers_leg(args, torch, hps, workloads, g, x, y, n_int, tab, btiles, dev)
+        burgers["per_node_operators"] = burgers_leg(args, torch, hps, workloads, g, x, y, n_int, tab, btiles, dev,
+                                                    uniform=False)
         log(f"burgers: {burgers}")
 
     # ---- FP32 operators + FP64 iterative refinement, same steps ----

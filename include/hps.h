@@ -65,6 +65,15 @@ extern "C" {
                             operators stepped many at a time (ark_step_batched, the
                             server) and for two-component steps (ark_step_burgers);
                             one scalar problem runs at the same speed either way.   */
+#define HPS_UNIFORM_COEFFS 4 /* or-ed with the above: the caller states that every
+                            coefficient of L is the same at every node (e.g. L = eps
+                            Lap).  Then every leaf, and every node of one tree level,
+                            has the same operators: they are stored once and all
+                            workgroups read that copy, which stays in the on-chip
+                            caches (operator memory / number of leaves, and far less
+                            HBM traffic).  hps_build checks the claim (HPS_EINVAL if
+                            any coefficient varies); results are bitwise those of
+                            the build without the flag.                             */
 
 typedef struct {
     double x0, x1, y0, y1;   /* domain; (x1-x0)/n1 must equal (y1-y0)/n2 (square leaves) */

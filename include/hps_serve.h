@@ -45,7 +45,7 @@ typedef struct {
                               (grid, coef_key, gamma_dt, flags) share one operator        */
     hps_coeffs coeffs;     /* device arrays of L's coefficients (read when the operator
                               of this key is not cached)                                  */
-    int32_t flags;         /* HPS_FP64 or HPS_FP32_IR                                     */
+    int32_t flags;         /* HPS_FP64 or HPS_FP32_IR, optionally | HPS_UNIFORM_COEFFS     */
     ark_tableau tab;       /* copied at submission; host arrays                           */
     double dt;             /* gamma_dt of the operator = tab.A[1][1] * dt                 */
     ark_g g;               /* nonlinearity (kind 0 = none)                                */

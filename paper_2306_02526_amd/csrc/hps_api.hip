@@ -184,6 +184,12 @@ Panel plan_panel(int R, int C, int vw, int nodes, int rp_max, int min_wg) {
     return p;
 }
 
+Panel shared_panel(Panel p) {
+    p.nodes = 1;
+    p.shared = true;
+    return p;
+}
+
 // Workgroups a level's product is cut into at least: enough to fill the GPU for one
 // problem, or (HPS_WIDE_TILES) few and large when many problems share each launch.
 static int level_min_wg(int flags) { return (flags & HPS_WIDE_TILES) ? 32 : 1024; }
@@ -193,8 +199,11 @@ static int level_min_wg(int flags) { return (flags & HPS_WIDE_TILES) ? 32 : 1024
 int64_t plan_operator_bytes(const hps_grid &g, int flags) {
     const int q = g.p - 2, q2 = q * q, nl = g.n1 * g.n2;
     const bool ir = (flags & HPS_FP32_IR) != 0;
-    int64_t bytes = plan_panel(q2, q2, 2, nl, 256, 0).bytes() + plan_panel(q2, 4 * q, 2, nl, 256, 0).bytes();
-    if (ir) bytes += plan_panel(q2, q2, 4, nl, 256, 0).bytes() + plan_panel(q2, 4 * q, 4, nl, 256, 0).bytes();
+    const bool uni = (flags & HPS_UNIFORM_COEFFS) != 0;
+    auto sh = [&](const Panel &p) { return uni ? shared_panel(p) : p; };
+    int64_t bytes = sh(plan_panel(q2, q2, 2, nl, 256, 0)).bytes() + sh(plan_panel(q2, 4 * q, 2, nl, 256, 0)).bytes();
+    if (ir)
+        bytes += sh(plan_panel(q2, q2, 4, nl, 256, 0)).bytes() + sh(plan_panel(q2, 4 * q, 4, nl, 256, 0)).bytes();
     int w = g.n1, h = g.n2, nodes = 1;
     bool root = true;
     while (w * h > 1) {
@@ -202,9 +211,10 @@ int64_t plan_operator_bytes(const hps_grid &g, int flags) {
         const int n3 = q * (vert ? h : w), n12 = 2 * q * (w + h);
         const int rows = root ? n3 : n3 + n12;
         const int mwg = level_min_wg(flags);
-        bytes += plan_panel(rows, n3, 2, nodes, 64, mwg).bytes() + plan_panel(n3, n12, 2, nodes, 64, mwg).bytes();
+        bytes += sh(plan_panel(rows, n3, 2, nodes, 64, mwg)).bytes() + sh(plan_panel(n3, n12, 2, nodes, 64, mwg)).bytes();
         if (ir)
-            bytes += plan_panel(rows, n3, 4, nodes, 64, mwg).bytes() + plan_panel(n3, n12, 4, nodes, 64, mwg).bytes();
+            bytes += sh(plan_panel(rows, n3, 4, nodes, 64, mwg)).bytes() +
+                     sh(plan_panel(n3, n12, 4, nodes, 64, mwg)).bytes();
         if (vert) w /= 2;
         else h /= 2;
         nodes *= 2;
@@ -455,6 +465,9 @@ static int build_impl(hps_op *op, const hps_coeffs *co, hipStream_t st) {
     const hps_grid &g = op->grid;
     const int q = op->q, q2 = op->q2, nb4 = 4 * q;
     const bool ir = (op->flags & HPS_FP32_IR) != 0;
+    const bool uni = (op->flags & HPS_UNIFORM_COEFFS) != 0;
+    // operators equal at every node of a sweep are packed once (node 0's)
+    auto sh = [&](const Panel &p) { return uni ? shared_panel(p) : p; };
     // constants and plan
     std::vector<double> D, D2;
     leaf_derivative(op->p, op->h, D, D2);
@@ -495,6 +508,16 @@ static int build_impl(hps_op *op, const hps_coeffs *co, hipStream_t st) {
     int *sing;
     TRY(dev_alloc(op, &sing, 1));
     HPS_HIP(hipMemsetAsync(sing, 0, sizeof(int), st));
+    if (uni) {   // the caller's claim that the coefficients are constant is checked
+        int *diff;
+        TRY(dev_alloc(op, &diff, 1));
+        HPS_HIP(hipMemsetAsync(diff, 0, sizeof(int), st));
+        TRY(launch_coef_uniform(op->coef, op->n_int, diff, st));
+        int hdiff = 0;
+        HPS_HIP(hipMemcpyAsync(&hdiff, diff, sizeof(int), hipMemcpyDeviceToHost, st));
+        HPS_HIP(hipStreamSynchronize(st));
+        CHECK_ARG(hdiff == 0, "HPS_UNIFORM_COEFFS: the coefficients of L vary over the nodes");
+    }
 
     TempBuf tmp;
     auto gj_scratch = [&](int n, int nb, unsigned char **used, int **order, double **cb, double **rb) -> int {
@@ -521,8 +544,8 @@ static int build_impl(hps_op *op, const hps_coeffs *co, hipStream_t st) {
     TRY(tmp.get(&T, (int64_t)nl * nb4 * nb4));
     TRY(launch_leaf_S(op, Ainv, S, st));
     TRY(launch_leaf_T(op, S, T, st));
-    op->ainv64 = plan_panel(q2, q2, 2, nl, 256, 0);
-    op->sleaf64 = plan_panel(q2, nb4, 2, nl, 256, 0);
+    op->ainv64 = sh(plan_panel(q2, q2, 2, nl, 256, 0));
+    op->sleaf64 = sh(plan_panel(q2, nb4, 2, nl, 256, 0));
     for (const Panel *pn : {&op->ainv64, &op->sleaf64})
         if (pn->ntile != 1 || pn->kch != 1) {
             hps_set_error("internal: leaf operator does not fit one workgroup tile");
@@ -533,8 +556,8 @@ static int build_impl(hps_op *op, const hps_coeffs *co, hipStream_t st) {
     TRY(launch_pack(op->ainv64, Ainv, q2, (int64_t)q2 * q2, q2, nullptr, 0, 0, st));
     TRY(launch_pack(op->sleaf64, S, q2, (int64_t)q2 * nb4, q2, nullptr, 0, 0, st));
     if (ir) {
-        op->ainv32 = plan_panel(q2, q2, 4, nl, 256, 0);
-        op->sleaf32 = plan_panel(q2, nb4, 4, nl, 256, 0);
+        op->ainv32 = sh(plan_panel(q2, q2, 4, nl, 256, 0));
+        op->sleaf32 = sh(plan_panel(q2, nb4, 4, nl, 256, 0));
         TRY(alloc_panel(op, op->ainv32));
         TRY(alloc_panel(op, op->sleaf32));
         TRY(launch_pack(op->ainv32, Ainv, q2, (int64_t)q2 * q2, q2, nullptr, 0, 0, st));
@@ -588,15 +611,15 @@ static int build_impl(hps_op *op, const hps_coeffs *co, hipStream_t st) {
         }
         const int rows = root ? n3 : n3 + n12;
         const int rpm = 64, mwg = level_min_wg(op->flags);
-        Lv.xu64 = plan_panel(rows, n3, 2, nodes, rpm, mwg);
-        Lv.s64 = plan_panel(n3, n12, 2, nodes, rpm, mwg);
+        Lv.xu64 = sh(plan_panel(rows, n3, 2, nodes, rpm, mwg));
+        Lv.s64 = sh(plan_panel(n3, n12, 2, nodes, rpm, mwg));
         TRY(alloc_panel(op, Lv.xu64));
         TRY(alloc_panel(op, Lv.s64));
         TRY(launch_pack(Lv.xu64, X, n3, s33, n3, U, n12, s3x, st));
         TRY(launch_pack(Lv.s64, Sx, n3, s3x, n3, nullptr, 0, 0, st));
         if (ir) {
-            Lv.xu32 = plan_panel(rows, n3, 4, nodes, rpm, mwg);
-            Lv.s32 = plan_panel(n3, n12, 4, nodes, rpm, mwg);
+            Lv.xu32 = sh(plan_panel(rows, n3, 4, nodes, rpm, mwg));
+            Lv.s32 = sh(plan_panel(n3, n12, 4, nodes, rpm, mwg));
             TRY(alloc_panel(op, Lv.xu32));
             TRY(alloc_panel(op, Lv.s32));
             TRY(launch_pack(Lv.xu32, X, n3, s33, n3, U, n12, s3x, st));
@@ -655,7 +678,7 @@ extern "C" int hps_build(const hps_grid *grid, const hps_coeffs *coeffs, double 
     TRY(check_grid(grid));
     CHECK_ARG(coeffs != nullptr, "coeffs is NULL");
     CHECK_ARG(std::isfinite(gamma_dt) && gamma_dt > 0.0, "gamma_dt must be positive and finite");
-    CHECK_ARG((flags & ~(HPS_FP32_IR | HPS_WIDE_TILES)) == 0, "unknown flags %d", flags);
+    CHECK_ARG((flags & ~(HPS_FP32_IR | HPS_WIDE_TILES | HPS_UNIFORM_COEFFS)) == 0, "unknown flags %d", flags);
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
         (void)hipGetLastError();

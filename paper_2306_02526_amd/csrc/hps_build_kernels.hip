@@ -425,4 +425,19 @@ int launch_pack(const Panel &pn, const double *src0, int ld0, int64_t stride0, i
     return HPS_OK;
 }
 
+// every coefficient compared bitwise with its value at node 0
+__global__ void k_coef_uniform(const double *coef, int64_t n, int *flag) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 5 * n) return;
+    const int64_t c = t / n;
+    if (__double_as_longlong(coef[t]) != __double_as_longlong(coef[c * n])) atomicOr(flag, 1);
+}
+
+int launch_coef_uniform(const double *coef, int64_t n, int *flag, hipStream_t st) {
+    if (n <= 0) return HPS_OK;
+    hipLaunchKernelGGL(k_coef_uniform, dim3(nblk(5 * n)), dim3(NT), 0, st, coef, n, flag);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
 }  // namespace hps

@@ -34,66 +34,58 @@ struct PanelView {
 };
 
 inline PanelView view(const Panel &p) {
-    return PanelView{p.data, p.rp, p.G, p.S, p.ntile, p.kch, p.tile_elems, p.node_elems};
+    // a shared panel has one block that every node reads
+    return PanelView{p.data, p.rp, p.G, p.S, p.ntile, p.kch, p.tile_elems, p.shared ? 0 : p.node_elems};
 }
 
 // Streaming product of one (tile, chunk) block of a Panel with an LDS vector.
 // start(): issue the first PF 16-byte loads of this lane (they do not depend on the
 // input vector, so callers start them before gathering it); finish(): consume them and
 // stream the rest with UNR loads in flight, then store the lane's partial sums.
+// Operators read once per sweep use nontemporal loads; a shared panel (one copy read by
+// every node, `cached`) uses ordinary loads so that the copy stays in the caches.
 template <typename T, int PF, int UNR>
 struct PanelStream {
     using V = typename V16<T>::type;
     static constexpr int VW = 16 / sizeof(T);
     const V *p;
     int act, S, G, g, r;
-    bool on;
+    bool on, nt;
     V pre[PF];
 
-    __device__ __forceinline__ void start(const T *blk, int rp, int G_, int S_) {
+    template <bool NTL>
+    static __device__ __forceinline__ V ld(const V *q) {
+        if constexpr (NTL) return __builtin_nontemporal_load(q);
+        else return *q;
+    }
+
+    __device__ __forceinline__ void start(const T *blk, int rp, int G_, int S_, bool cached = false) {
         const int t = threadIdx.x;
         act = rp * G_;
         S = S_;
         G = G_;
         on = t < act;
+        nt = !cached;
         g = on ? t / rp : 0;
         r = on ? t - g * rp : 0;
         p = reinterpret_cast<const V *>(blk) + t;
         if (on) {
+            if (nt) {
 #pragma unroll
-            for (int u = 0; u < PF; ++u)
-                if (u < S) pre[u] = __builtin_nontemporal_load(p + (size_t)u * act);
+                for (int u = 0; u < PF; ++u)
+                    if (u < S) pre[u] = ld<true>(p + (size_t)u * act);
+            } else {
+#pragma unroll
+                for (int u = 0; u < PF; ++u)
+                    if (u < S) pre[u] = ld<false>(p + (size_t)u * act);
+            }
         }
     }
 
-    __device__ __forceinline__ void finish(const T *__restrict__ xs, T *__restrict__ part) {
-        if (!on) return;
-        T acc[VW];
-#pragma unroll
-        for (int v = 0; v < VW; ++v) acc[v] = T(0);
-#pragma unroll
-        for (int u = 0; u < PF; ++u)
-            if (u < S) vfma(acc, pre[u], xs[u * G + g]);
-        int s = PF;
-        for (; s + UNR <= S; s += UNR) {
-            V vv[UNR];
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) vv[u] = __builtin_nontemporal_load(p + (size_t)(s + u) * act);
-#pragma unroll
-            for (int u = 0; u < UNR; ++u) vfma(acc, vv[u], xs[(s + u) * G + g]);
-        }
-        for (; s < S; ++s) vfma(acc, __builtin_nontemporal_load(p + (size_t)s * act), xs[s * G + g]);
-        T *dst = part + g * (act / G * VW) + r * VW;
-#pragma unroll
-        for (int v = 0; v < VW; ++v) dst[v] = acc[v];
-    }
-
-    // finish() for NC input vectors at once (vector c at xs + c*xstride, its partial sums
-    // to part + c*pstride): every operator load feeds NC products.
-    template <int NC>
-    __device__ __forceinline__ void finish_n(const T *__restrict__ xs, int xstride, T *__restrict__ part,
-                                             int pstride) {
-        if (!on) return;
+    // NC input vectors at once (vector c at xs + c*xstride, its partial sums to
+    // part + c*pstride): every operator load feeds NC products.
+    template <bool NTL, int NC>
+    __device__ __forceinline__ void run(const T *__restrict__ xs, int xstride, T *__restrict__ part, int pstride) {
         T acc[NC][VW];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
@@ -108,14 +100,14 @@ struct PanelStream {
         for (; s + UNR <= S; s += UNR) {
             V vv[UNR];
 #pragma unroll
-            for (int u = 0; u < UNR; ++u) vv[u] = __builtin_nontemporal_load(p + (size_t)(s + u) * act);
+            for (int u = 0; u < UNR; ++u) vv[u] = ld<NTL>(p + (size_t)(s + u) * act);
 #pragma unroll
             for (int u = 0; u < UNR; ++u)
 #pragma unroll
                 for (int c = 0; c < NC; ++c) vfma(acc[c], vv[u], xs[c * xstride + (s + u) * G + g]);
         }
         for (; s < S; ++s) {
-            const V w = __builtin_nontemporal_load(p + (size_t)s * act);
+            const V w = ld<NTL>(p + (size_t)s * act);
 #pragma unroll
             for (int c = 0; c < NC; ++c) vfma(acc[c], w, xs[c * xstride + s * G + g]);
         }
@@ -125,6 +117,20 @@ struct PanelStream {
 #pragma unroll
             for (int v = 0; v < VW; ++v) dst[v] = acc[c][v];
         }
+    }
+
+    __device__ __forceinline__ void finish(const T *__restrict__ xs, T *__restrict__ part) {
+        if (!on) return;
+        if (nt) run<true, 1>(xs, 0, part, 0);
+        else run<false, 1>(xs, 0, part, 0);
+    }
+
+    template <int NC>
+    __device__ __forceinline__ void finish_n(const T *__restrict__ xs, int xstride, T *__restrict__ part,
+                                             int pstride) {
+        if (!on) return;
+        if (nt) run<true, NC>(xs, xstride, part, pstride);
+        else run<false, NC>(xs, xstride, part, pstride);
     }
 };
 

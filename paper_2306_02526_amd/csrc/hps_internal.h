@@ -32,7 +32,8 @@ struct Panel {
     int ntile = 0, kch = 0, S = 0;
     int64_t tile_elems = 0;   // S*G*rp*vw
     int64_t node_elems = 0;   // ntile*kch*tile_elems
-    int nodes = 0;
+    int nodes = 0;            // nodes stored (1 when shared)
+    bool shared = false;      // one copy read by every node of the sweep
     void *data = nullptr;     // double* (vw = 2) or float* (vw = 4)
     int64_t bytes() const { return node_elems * nodes * (vw == 2 ? 8 : 4); }
 };
@@ -41,6 +42,8 @@ struct Panel {
 // vectors per tile (the leaf kernels need the whole matrix in one tile); min_wg asks
 // for at least that many workgroups per sweep (column chunks are added to reach it).
 Panel plan_panel(int R, int C, int vw, int nodes, int rp_max, int min_wg);
+// The same plan stored once for all `nodes` (operators that are equal at every node).
+Panel shared_panel(Panel p);
 int64_t plan_operator_bytes(const hps_grid &g, int flags);   // what hps_build's panels take
 
 // One internal level of the tree (level 0 = root), all nodes of the same shape.
@@ -274,6 +277,9 @@ int launch_set_values(double *dst, const double *vals, int n, hipStream_t st);  
 
 // build --------------------------------------------------------------------------------
 int launch_leaf_assemble(const hps_op *op, double *W, hipStream_t st);
+// sets *flag (device int, zero beforehand) when some coefficient differs from its value at
+// node 0
+int launch_coef_uniform(const double *coef, int64_t n, int *flag, hipStream_t st);
 int gj_invert(double *W, double *out, int n, int nb, unsigned char *used, int *order,
               double *colbuf, double *rowbuf, int *sing, hipStream_t st);
 int launch_leaf_S(const hps_op *op, const double *ainv, double *S, hipStream_t st);

@@ -106,8 +106,12 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
     constexpr bool stream_up = UPM == UP_BODY || UPM == UP_STAGE;
     constexpr bool need_L = DN == DOWN_STAGE || DN == DOWN_EVAL;
     PanelStream<T, LPF, LUNR> ps;
-    if constexpr (stream_down) ps.start(reinterpret_cast<const T *>(a.sl.data) + (int64_t)leaf * a.sl.node_elems, a.sl.rp, a.sl.G, a.sl.S);
-    else if constexpr (stream_up) ps.start(reinterpret_cast<const T *>(a.ainv.data) + (int64_t)leaf * a.ainv.node_elems, a.ainv.rp, a.ainv.G, a.ainv.S);
+    if constexpr (stream_down)
+        ps.start(reinterpret_cast<const T *>(a.sl.data) + (int64_t)leaf * a.sl.node_elems, a.sl.rp, a.sl.G, a.sl.S,
+                 a.sl.node_elems == 0);
+    else if constexpr (stream_up)
+        ps.start(reinterpret_cast<const T *>(a.ainv.data) + (int64_t)leaf * a.ainv.node_elems, a.ainv.rp, a.ainv.G,
+                 a.ainv.S, a.ainv.node_elems == 0);
     load_dmat(a.D, D, p * p);
     if (need_L) load_dmat(a.D2, D2, p * p);
 
@@ -126,7 +130,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
             ps.finish(xs, part);
             if constexpr (stream_up)
                 ps.start(reinterpret_cast<const T *>(a.ainv.data) + (int64_t)leaf * a.ainv.node_elems, a.ainv.rp,
-                         a.ainv.G, a.ainv.S);
+                         a.ainv.G, a.ainv.S, a.ainv.node_elems == 0);
             __syncthreads();
             // u_i interior = S_leaf u_b + w (this thread's rows are its own interior nodes)
             reduce_rows<T>(part, a.sl.rp * VW, a.sl.G, red, [&](int row, double y) {
@@ -348,10 +352,11 @@ __device__ __forceinline__ void leaf_sys_body(const LeafSysArgs &A, int leaf, un
     constexpr bool stream_down = DN == DOWN_STAGE;
     PanelStream<double, LPF, LUNR> ps;
     if constexpr (stream_down)
-        ps.start(reinterpret_cast<const double *>(a.sl.data) + (int64_t)leaf * a.sl.node_elems, a.sl.rp, a.sl.G, a.sl.S);
+        ps.start(reinterpret_cast<const double *>(a.sl.data) + (int64_t)leaf * a.sl.node_elems, a.sl.rp, a.sl.G, a.sl.S,
+                 a.sl.node_elems == 0);
     else if constexpr (UPM == UP_STAGE)
         ps.start(reinterpret_cast<const double *>(a.ainv.data) + (int64_t)leaf * a.ainv.node_elems, a.ainv.rp,
-                 a.ainv.G, a.ainv.S);
+                 a.ainv.G, a.ainv.S, a.ainv.node_elems == 0);
     load_dmat(a.D, D, pp);
     load_dmat(a.D2, D2, pp);
 
@@ -374,7 +379,7 @@ __device__ __forceinline__ void leaf_sys_body(const LeafSysArgs &A, int leaf, un
         ps.finish_n<NC>(xs, xcap, part, pcap);
         if constexpr (UPM == UP_STAGE)
             ps.start(reinterpret_cast<const double *>(a.ainv.data) + (int64_t)leaf * a.ainv.node_elems, a.ainv.rp,
-                     a.ainv.G, a.ainv.S);
+                     a.ainv.G, a.ainv.S, a.ainv.node_elems == 0);
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < NC; ++c)

@@ -354,7 +354,8 @@ extern "C" int srv_submit(srv_server *srv, const srv_job *job, void *stream, int
     CHECK_ARG(t.s >= 2 && t.s <= 8 && t.A && t.b && t.c && t.Ahat && t.bhat, "tableau needs 2 <= s <= 8 and all arrays");
     CHECK_ARG(job->dt > 0 && std::isfinite(job->dt), "dt must be positive");
     CHECK_ARG(job->steps >= 1, "steps must be >= 1");
-    CHECK_ARG(job->flags == HPS_FP64 || job->flags == HPS_FP32_IR, "flags must be HPS_FP64 or HPS_FP32_IR");
+    CHECK_ARG((job->flags & ~(HPS_FP32_IR | HPS_UNIFORM_COEFFS)) == 0,
+              "flags must be HPS_FP64 or HPS_FP32_IR, optionally with HPS_UNIFORM_COEFFS");
     CHECK_ARG(job->g.kind == 0 || job->g.kind == 1, "ark_g.kind must be 0 or 1");
     CHECK_ARG(job->u != nullptr, "u is required");
     CHECK_ARG(std::isfinite(job->t0) && std::isfinite(job->q_amp) && std::isfinite(job->q_rate),

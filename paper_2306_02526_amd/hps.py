@@ -16,6 +16,7 @@ LIB_PATH = os.environ.get("HPS_LIB", os.path.join(HERE, "libhps.so"))
 HPS_FP64 = 0
 HPS_FP32_IR = 1
 HPS_WIDE_TILES = 2
+HPS_UNIFORM_COEFFS = 4
 ERRORS = {-1: "HPS_EINVAL", -2: "HPS_ENOMEM", -3: "HPS_EDEVICE", -4: "HPS_ESINGULAR",
           -5: "HPS_ENOTCONVERGED"}
 

@@ -77,9 +77,10 @@ def test_null_handles_are_rejected():
     assert L.ark_step_burgers(None, None, 0.0, None, None, None, None, None) == -1
 
 
-@pytest.mark.parametrize("flags", [4, -1, 8 | hps.HPS_FP32_IR])
+@pytest.mark.parametrize("flags", [8, -1, 16 | hps.HPS_FP32_IR])
 def test_unknown_build_flags_are_rejected(flags):
-    """Only HPS_FP32_IR and HPS_WIDE_TILES may be set; the check comes before any device use."""
+    """Only HPS_FP32_IR, HPS_WIDE_TILES and HPS_UNIFORM_COEFFS may be set; the check comes
+    before any device use."""
     g = hps.make_grid(0.0, 1.0, 0.0, 1.0, 2, 2, 6)
     fake = ctypes.c_void_p(4096)
     co = hps.HpsCoeffs(fake, fake, fake, fake, fake)
