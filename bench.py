@@ -382,12 +382,11 @@ def main():
     # ---- CPU oracle on a bounded sample of the same workload ----
     cpu = None
     if not args.no_cpu_baseline:
-        # all of this host's share of cores (BLAS threads), and one core
-        share = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16))
-        cpu = cpu_baseline(n, p, dt, args.cpu_stage_solves, threads=share)
-        one = cpu_baseline(n, p, dt, args.cpu_stage_solves, threads=1)
-        if "value" in one:
-            cpu["one_core"] = {"value": one["value"], "build_s": one["build_s"], "cores": 1}
+        # one BLAS thread: the oracle is a sequence of small dense operations per leaf and
+        # node, which threaded BLAS slows down (a run with 8 threads did not finish its
+        # build in 150 s where one thread takes 27 s)
+        log("cpu oracle: one BLAS thread")
+        cpu = cpu_baseline(n, p, dt, args.cpu_stage_solves, threads=1, limit_s=240)
         log(f"cpu oracle: {cpu}")
 
     out = {
@@ -589,7 +588,7 @@ def serving_run(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(n, p, dt, n_solves, threads=1):
+def cpu_baseline(n, p, dt, n_solves, threads=1, limit_s=150):
     """The oracle (plain NumPy FP64) on this host with `threads` BLAS threads: its build on
     the full grid (timed, not counted), then n_solves implicit stages of the same step
     timed; value = stage-solves/s on those stages."""
@@ -609,6 +608,7 @@ cxx, cyy, cx, cy, c0 = wl.L_coeffs(x[:g.n_int], y[:g.n_int])
 co = dict(cxx=cxx, cyy=cyy, cx=cx, cy=cy, c0=c0)
 tab = tableau_float(ark436l2sa()); dt = {dt}
 t0 = time.perf_counter(); H = HPS(g, co, tab['gamma'] * dt); tb = time.perf_counter() - t0
+print(f"   oracle build {{tb:.1f}} s", file=sys.stderr, flush=True)
 u = wl.u0(x, y); n_int = g.n_int
 A, Ah = tab['A'], tab['Ahat']
 Lu = [apply_L(g, co, u)]; F = [poly_g(workloads.AllenCahn.gpoly, u[:n_int])]
@@ -621,14 +621,19 @@ for i in range(1, 1 + {n_solves}):
     ui = H.solve(rhs)
     Lu.append(apply_L(g, co, ui)); F.append(poly_g(workloads.AllenCahn.gpoly, ui[:n_int]))
     times.append(time.perf_counter() - t0)
+    print(f"   oracle stage {{i}}: {{times[-1]:.1f}} s", file=sys.stderr, flush=True)
 print(json.dumps(dict(build_s=tb, times=times)))
 """
     t0 = time.perf_counter()
     th = str(threads)
-    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
-                       env=dict(os.environ, OPENBLAS_NUM_THREADS=th, OMP_NUM_THREADS=th, MKL_NUM_THREADS=th))
+    try:
+        # progress lines go straight to stderr; the result is the last stdout line
+        r = subprocess.run([sys.executable, "-c", code], stdout=subprocess.PIPE, text=True, timeout=limit_s,
+                           env=dict(os.environ, OPENBLAS_NUM_THREADS=th, OMP_NUM_THREADS=th, MKL_NUM_THREADS=th))
+    except subprocess.TimeoutExpired:
+        return {"error": f"not finished within {limit_s} s with {threads} BLAS threads"}
     if r.returncode != 0:
-        return {"error": r.stderr[-400:]}
+        return {"error": f"exit status {r.returncode}"}
     d = json.loads(r.stdout.strip().splitlines()[-1])
     ts = d["times"]
     try:
