@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--slope-steps", type=int, default=10)
     ap.add_argument("--no-burgers", action="store_true")
     ap.add_argument("--burgers-steps", type=int, default=10)
+    ap.add_argument("--no-heat", action="store_true")
+    ap.add_argument("--heat-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stage-solves", type=int, default=3)
     ap.add_argument("--workload", default="allen_cahn", choices=["allen_cahn", "batched", "serving"],
@@ -205,6 +207,50 @@ def burgers_leg(args, torch, hps, workloads, g, x, y, n_int, tab, tiles, dev, un
     return out
 
 
+def heat_leg(args, torch, hps, workloads, g, x, y, n_int, tab, dev, uniform):
+    """The 2-D heat test (u_t = Lap u + q, manufactured solution, f = 0) on the bench grid:
+    the scalar stage formulation with a separable source; uniform: one shared operator copy
+    (L = Lap has constant coefficients)."""
+    import numpy as np
+    wl = workloads.HeatManufactured(workloads.rng_for(1))
+    dt = 1e-3
+    one = torch.ones(n_int, dtype=torch.float64, device=dev)
+    op = hps.hps_build(g, {"cxx": one, "cyy": one}, tab["gamma"] * dt,
+                       hps.HPS_FP64 | (hps.HPS_UNIFORM_COEFFS if uniform else 0))
+    _, op_bytes = op.bytes()
+    ctx = hps.ark_create(op, tab, dt)
+    u = torch.tensor(wl.exact(0.0, x, y), device=dev)
+    qs = torch.tensor(wl.q_space(x[:n_int], y[:n_int]), device=dev)
+
+    def step(k):
+        t = k * dt
+        hps.ark_step(ctx, t, u, q_space=qs, q_time=[wl.q_time(t + c * dt) for c in tab["c"]])
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.heat_steps):
+        step(k)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    k_end = args.warmup + args.heat_steps
+    err = float(np.abs(u.cpu().numpy() - wl.exact(k_end * dt, x, y)).max())
+    hps.hps_profile_enable(op, True)
+    for k in range(k_end, k_end + 2):
+        step(k)
+    torch.cuda.synchronize()
+    prof = hps.hps_profile_read(op)
+    hps.hps_profile_enable(op, False)
+    op.free()
+    stages = tab["s"] - 1
+    return {"stage_solves_per_s": round(stages * args.heat_steps / el, 1),
+            "ms_per_step": round(1e3 * el / args.heat_steps, 3), "steps": args.heat_steps, "dt": dt,
+            "operators": "one shared copy (uniform coefficients)" if uniform else "per node",
+            "operator_bytes": op_bytes, "max_err_vs_exact": err,
+            "leaf_down_up_us_per_launch": round(1e3 * prof["leaf_down_up_fp64"][1] / prof["leaf_down_up_fp64"][0], 2)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -343,6 +389,13 @@ def main():
                                                     uniform=False)
         log(f"burgers: {burgers}")
 
+    # ---- the heat test (constant coefficients) on the same grid ----
+    heat = None
+    if not args.no_heat:
+        heat = heat_leg(args, torch, hps, workloads, g, x, y, n_int, tab, dev, uniform=True)
+        heat["per_node_operators"] = heat_leg(args, torch, hps, workloads, g, x, y, n_int, tab, dev, uniform=False)
+        log(f"heat: {heat}")
+
     # ---- FP32 operators + FP64 iterative refinement, same steps ----
     fp32 = None
     if not args.no_fp32:
@@ -419,6 +472,7 @@ def main():
         "fp32_ir": fp32,
         "slope_formulation": slope,
         "burgers_system": burgers,
+        "heat_constant_coefficients": heat,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -181,6 +181,57 @@ def test_linear_fields_stay_linear_at_full_size(torch, n, p):
         a, b = an, bn
 
 
+ORACLE_BURGERS_STEP = """
+import sys, time
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from oracle.ark import ark436l2sa, tableau_float
+from oracle.burgers import BurgersARK
+from oracle.grid import Grid
+from oracle.hps import HPS
+d = np.load(sys.argv[2])
+og = Grid(0, 1, 0, 1, 64, 64, 16)
+co = {k: d[k] for k in ("cxx", "cyy", "cx", "cy", "c0")}
+t0 = time.perf_counter()
+orc = BurgersARK(HPS(og, co, float(d["gdt"])), co, tableau_float(ark436l2sa()), float(d["dt"]))
+print(f"   oracle built in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+u, v = orc.step(d["u0"], d["v0"], d["fu"], d["fv"])
+np.savez(sys.argv[3], u=u, v=v)
+print(f"   oracle step done after {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+"""
+
+
+def test_full_size_step_matches_oracle(torch, tmp_path):
+    """The bench leg's configuration (64x64 leaves, p = 16, traveling wave, eps = 0.1,
+    dt = 1e-3, time-dependent boundary data): one step element by element against the
+    oracle, run in a child process on one BLAS thread."""
+    import os
+    import subprocess
+    say("[burgers] full size 64x64 p=16, traveling wave")
+    sol = workloads.BurgersTravelingWave(0.1)
+    S = Setup(torch, (0, 1, 0, 1), 64, 64, 16, sol.eps, 1e-3, oracle=False)
+    og = Grid(0, 1, 0, 1, 64, 64, 16)
+    S.bnd = og.boundary_indices()
+    u0, v0 = sol.exact(0.0, S.x, S.y)
+    fu, fv = S.boundary(sol, 0.0)
+    ug, vg = torch.tensor(u0, device="cuda"), torch.tensor(v0, device="cuda")
+    hps.ark_step_burgers(S.cu, S.cv, 0.0, ug, vg, torch.tensor(fu, device="cuda"), torch.tensor(fv, device="cuda"))
+    ugh, vgh = ug.cpu().numpy(), vg.cpu().numpy()
+    say("   GPU step done; oracle in a child process")
+    n_int = og.n_int
+    co = dict(zip(("cxx", "cyy", "cx", "cy", "c0"), workloads.burgers_coeffs(sol.eps, n_int)))
+    inp, outp = tmp_path / "in.npz", tmp_path / "out.npz"
+    np.savez(inp, u0=u0, v0=v0, fu=fu, fv=fv, gdt=S.tab["gamma"] * S.dt, dt=S.dt, **co)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, OPENBLAS_NUM_THREADS="1", OMP_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    subprocess.run([sys.executable, "-c", ORACLE_BURGERS_STEP, root, str(inp), str(outp)], env=env, check=True,
+                   timeout=600)
+    ref = np.load(outp)
+    eu, ev = rel(ugh, ref["u"]), rel(vgh, ref["v"])
+    say(f"   rel err u {eu:.2e}, v {ev:.2e}")
+    assert eu <= TOL64 and ev <= TOL64
+
+
 def test_graph_replay_equals_eager(torch, monkeypatch):
     say("[burgers] graph replay vs eager, 8x4 p=8, 4 steps")
     res = []
