@@ -114,6 +114,18 @@ HPS_API int hps_nodes(const hps_grid *grid, double *x, double *y);
 HPS_API int hps_build(const hps_grid *grid, const hps_coeffs *coeffs, double gamma_dt, int flags,
               void *stream, hps_op **out);
 
+/* The same for complex coefficients (the regularised NLS of Sec. 5.5 has L = (a eps + i)
+ * Lap): re and im hold the real and imaginary parts of each coefficient (device arrays,
+ * NULL members zero).  The operator is the real embedding [[Re, -Im], [Im, Re]] of the
+ * complex one, built and applied in FP64; every complex vector the operator takes or
+ * returns (hps_solve, ark_step) is two planes of the real layout, real part then
+ * imaginary part (body [2][n_int], u [2][N], dirichlet [2][n_bdry], jump [2][n_iface],
+ * per right-hand side).  flags: HPS_FP64, optionally HPS_WIDE_TILES and
+ * HPS_UNIFORM_COEFFS (not HPS_FP32_IR); p <= 18 (one leaf's embedded operator fills a
+ * workgroup tile).  Stored operators take about 4x the real ones. */
+HPS_API int hps_build_complex(const hps_grid *grid, const hps_coeffs *re, const hps_coeffs *im, double gamma_dt,
+                              int flags, void *stream, hps_op **out);
+
 /* Bytes of device memory held by the operator (stored operators + workspace). */
 HPS_API int64_t hps_op_bytes(const hps_op *op, int64_t *operator_bytes);
 
@@ -150,7 +162,9 @@ typedef struct {
     const double *A, *b, *c, *Ahat, *bhat;
 } ark_tableau;
 
-/* Explicit nonlinearity g(u) = g0 + g1 u + g2 u^2 + g3 u^3 (kind = 1), or none (kind = 0). */
+/* Explicit nonlinearity g(u) = g0 + g1 u + g2 u^2 + g3 u^3 (kind = 1), or none (kind = 0).
+ * For a complex operator: kind = 2, g(u) = (g0 + i g1) u + (g2 + i g3) |u|^2 u (the NLS of
+ * Sec. 5.5 has g0 = b eps, g1 = 0, g2 = -c eps, g3 = 1), or kind = 0. */
 typedef struct {
     int32_t kind;
     double g0, g1, g2, g3;
@@ -170,7 +184,9 @@ HPS_API int ark_create(hps_op *op, const ark_tableau *tab, double dt, const ark_
  * Source q, by one of (or none: q = 0):
  *   q_stages  device [s][n_int]: q at t + c_i dt;
  *   q_space   device [n_int] with q_time host [s]: q = q_time[i] * q_space.
- * f_stages: device [s+1][n_bdry], f at t + c_i dt (i < s) and at t + dt; NULL = 0. */
+ * f_stages: device [s+1][n_bdry], f at t + c_i dt (i < s) and at t + dt; NULL = 0.
+ * Complex operator (hps_build_complex): u device [2][N], f_stages [s+1][2][n_bdry], no
+ * source (q_stages and q_space must be NULL; HPS_EINVAL otherwise). */
 HPS_API int ark_step(ark_ctx *ctx, double t, double *u, const double *q_stages,
              const double *q_space, const double *q_time, const double *f_stages, void *stream);
 

@@ -87,11 +87,12 @@ def apply_L(grid, coefs_int, u):
     p, q = grid.p, grid.q
     D = leaf_diff_1d(grid.h, p)
     D2 = D @ D
-    out = np.empty(grid.n_int)
+    dt = np.result_type(np.asarray(u), *[np.asarray(v) for v in coefs_int.values()])
+    out = np.empty(grid.n_int, dtype=dt)
     q2 = q * q
     for j in range(grid.n2):
         for i in range(grid.n1):
-            U = np.full((p, p), np.nan)   # U[b, a]; corners stay NaN and must never be read
+            U = np.full((p, p), np.nan, dtype=dt)   # U[b, a]; corners stay NaN and must never be read
             for b in range(p):
                 for a in range(p):
                     g = grid.local_to_global(i, j, a, b)
@@ -162,6 +163,10 @@ class ARK:
         self.iface = InterfaceSolver(self.grid)
         self.bnd = self.grid.boundary_indices()
 
+    def g_of(self, u):
+        """The explicit nonlinearity g at interior values u."""
+        return poly_g(self.gpoly, u)
+
     def step(self, u, q_stages=None, f_stages=None, return_stages=False):
         """u: full N vector at t^n.  q_stages: (s, n_int) source at t^n + c_i dt (or None).
         f_stages: (s+1, n_bdry) Dirichlet data at t^n + c_i dt and at t^n + dt (or None = 0)."""
@@ -173,7 +178,7 @@ class ARK:
         f_at = (lambda i: np.zeros(len(self.bnd))) if f_stages is None else (lambda i: f_stages[i])
         un_int = u[:n_int].copy()
         Lu = [apply_L(g, self.coefs, u)]
-        F = [q_at(0) + poly_g(self.gpoly, un_int)]
+        F = [q_at(0) + self.g_of(un_int)]
         stages = [u.copy()]
         for i in range(1, s):
             rhs = un_int.copy()
@@ -182,8 +187,8 @@ class ARK:
             ui = self.hps.solve(rhs, f_at(i), None)
             stages.append(ui)
             Lu.append(apply_L(g, self.coefs, ui))
-            F.append(q_at(i) + poly_g(self.gpoly, ui[:n_int]))
-        unew = np.zeros(g.N)
+            F.append(q_at(i) + self.g_of(ui[:n_int]))
+        unew = np.zeros(g.N, dtype=np.result_type(u, *Lu))
         unew[:n_int] = un_int
         for j in range(s):
             unew[:n_int] += dt * b[j] * Lu[j] + dt * bh[j] * F[j]

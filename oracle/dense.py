@@ -90,7 +90,7 @@ def dense_solve(grid, coefs_int, gamma_dt, body, dirichlet=None, jump=None):
     if grid.N > 6000:
         raise ValueError("dense reference is for tiny grids")
     A = global_matrix(grid, coefs_int, gamma_dt)
-    rhs = np.zeros(grid.N)
+    rhs = np.zeros(grid.N, dtype=np.result_type(A, np.asarray(body)))
     rhs[: grid.n_int] = body
     if dirichlet is not None:
         rhs[grid.boundary_indices()] = dirichlet

@@ -148,7 +148,7 @@ class Node:
             self.T = None
         else:
             n1, n2 = len(self.J1), len(self.J2)
-            Td = np.zeros((n1 + n2, n1 + n2))
+            Td = np.zeros((n1 + n2, n1 + n2), dtype=np.result_type(Ta11, Tb22))
             Td[:n1, :n1] = Ta11
             Td[n1:, n1:] = Tb22
             self.T = Td + np.vstack([Ta13, Tb23]) @ self.S
@@ -180,6 +180,8 @@ class HPS:
             raise ValueError("n1 and n2 must be powers of two")
         self.grid = grid
         self.gamma_dt = float(gamma_dt)
+        # complex coefficients (Sec. 5.5) give complex operators; real ones stay FP64
+        self.dtype = np.result_type(np.float64, *[np.asarray(v) for v in coefs_int.values()])
         q2 = grid.q * grid.q
         self.leaves = {}
 
@@ -187,7 +189,7 @@ class HPS:
             i0, i1, j0, j1 = box
             if i1 - i0 == 1 and j1 - j0 == 1:
                 k = j0 * n1 + i0
-                c = {name: np.asarray(v, dtype=np.float64)[k * q2:(k + 1) * q2]
+                c = {name: np.asarray(v, dtype=np.result_type(v, np.float64))[k * q2:(k + 1) * q2]
                      for name, v in coefs_int.items()}
                 leaf = Leaf(grid, i0, j0, c, gamma_dt)
                 self.leaves[(i0, j0)] = leaf
@@ -206,11 +208,12 @@ class HPS:
         flux_alpha - flux_beta = jump on interface edge nodes.  Returns u over all N
         nodes in canonical order."""
         g = self.grid
-        body = np.asarray(body, dtype=np.float64)
-        r3 = np.zeros(g.N)
+        dt = np.result_type(self.dtype, *[np.asarray(v) for v in (body, dirichlet, jump) if v is not None])
+        body = np.asarray(body, dtype=dt)
+        r3 = np.zeros(g.N, dtype=dt)
         if jump is not None:
             r3[self.iface_idx] = jump
-        u = np.zeros(g.N)
+        u = np.zeros(g.N, dtype=dt)
         if dirichlet is not None:
             u[self.bnd_idx] = dirichlet
         if isinstance(self.root, Leaf):

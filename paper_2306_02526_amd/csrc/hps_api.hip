@@ -196,19 +196,20 @@ static int level_min_wg(int flags) { return (flags & HPS_WIDE_TILES) ? 32 : 1024
 
 // Bytes of the packed operators hps_build stores for a grid, from the same panel plans
 // (the tree splits the longer side of each box, ties with a vertical cut).
-int64_t plan_operator_bytes(const hps_grid &g, int flags) {
-    const int q = g.p - 2, q2 = q * q, nl = g.n1 * g.n2;
+int64_t plan_operator_bytes(const hps_grid &g, int flags, int ncomp) {
+    const int q = g.p - 2, q2 = q * q * ncomp, nl = g.n1 * g.n2;
     const bool ir = (flags & HPS_FP32_IR) != 0;
     const bool uni = (flags & HPS_UNIFORM_COEFFS) != 0;
     auto sh = [&](const Panel &p) { return uni ? shared_panel(p) : p; };
-    int64_t bytes = sh(plan_panel(q2, q2, 2, nl, 256, 0)).bytes() + sh(plan_panel(q2, 4 * q, 2, nl, 256, 0)).bytes();
+    const int nbl = 4 * q * ncomp;
+    int64_t bytes = sh(plan_panel(q2, q2, 2, nl, 256, 0)).bytes() + sh(plan_panel(q2, nbl, 2, nl, 256, 0)).bytes();
     if (ir)
-        bytes += sh(plan_panel(q2, q2, 4, nl, 256, 0)).bytes() + sh(plan_panel(q2, 4 * q, 4, nl, 256, 0)).bytes();
+        bytes += sh(plan_panel(q2, q2, 4, nl, 256, 0)).bytes() + sh(plan_panel(q2, nbl, 4, nl, 256, 0)).bytes();
     int w = g.n1, h = g.n2, nodes = 1;
     bool root = true;
     while (w * h > 1) {
         const bool vert = w >= h;
-        const int n3 = q * (vert ? h : w), n12 = 2 * q * (w + h);
+        const int n3 = q * (vert ? h : w) * ncomp, n12 = 2 * q * (w + h) * ncomp;
         const int rows = root ? n3 : n3 + n12;
         const int mwg = level_min_wg(flags);
         bytes += sh(plan_panel(rows, n3, 2, nodes, 64, mwg)).bytes() + sh(plan_panel(n3, n12, 2, nodes, 64, mwg)).bytes();
@@ -458,12 +459,72 @@ static int plan_tree(const hps_op *op, std::vector<int> &leaf_ij, std::vector<Ho
     return HPS_OK;
 }
 
+// A complex operator is built as the real two-component system of its real embedding.
+// Every index set of the scalar tree appears twice (component 0: real part, 1: imaginary
+// part).  Leaves order their boundary [component 0 edges | component 1 edges]; an internal
+// node orders its boundary [alpha side: component 0, component 1 | beta side: component 0,
+// component 1], so that the level kernels' split of a node boundary into its alpha part
+// (the first n1 entries) and beta part still holds.  J3 is ordered [component 0 |
+// component 1]; interface and boundary data are two planes of the scalar index space.
+static void complexify(std::vector<HostLevel> &hl, std::vector<int> &root_map, int q, int64_t n_iface,
+                       int64_t n_bdry) {
+    const int L = (int)hl.size();
+    std::vector<int> sn1(L), sn2(L);
+    for (int l = 0; l < L; ++l) {
+        sn1[l] = hl[l].n1;
+        sn2[l] = hl[l].n2;
+    }
+    // position of (component c, scalar position t) in a child's two-component boundary
+    auto child = [&](int l, int c, int t) -> int {
+        if (l == L - 1) return c * 4 * q + t;
+        const int n1c = sn1[l + 1], n2c = sn2[l + 1];
+        return t < n1c ? c * n1c + t : 2 * n1c + c * n2c + (t - n1c);
+    };
+    for (int l = 0; l < L; ++l) {
+        HostLevel &H = hl[l];
+        auto twice = [&](const std::vector<int> &v) {
+            std::vector<int> out(2 * v.size());
+            for (int c = 0; c < 2; ++c)
+                for (size_t k = 0; k < v.size(); ++k) out[c * v.size() + k] = child(l, c, v[k]);
+            return out;
+        };
+        H.a1 = twice(H.a1);
+        H.a3 = twice(H.a3);
+        H.b2 = twice(H.b2);
+        H.b3 = twice(H.b3);
+        const size_t nodes = H.n3 ? H.j3i.size() / H.n3 : 0;
+        std::vector<int> j3(2 * H.j3i.size());
+        for (size_t nd = 0; nd < nodes; ++nd)
+            for (int c = 0; c < 2; ++c)
+                for (int k = 0; k < H.n3; ++k)
+                    j3[nd * 2 * H.n3 + c * H.n3 + k] = (int)(c * n_iface) + H.j3i[nd * H.n3 + k];
+        H.j3i.swap(j3);
+        H.n1 *= 2;
+        H.n2 *= 2;
+        H.n3 *= 2;
+        H.nbc *= 2;
+    }
+    std::vector<int> rm(2 * root_map.size());
+    if (L == 0) {   // the single leaf's boundary is the root's
+        for (int c = 0; c < 2; ++c)
+            for (size_t t = 0; t < root_map.size(); ++t) rm[c * root_map.size() + t] = (int)(c * n_bdry) + root_map[t];
+    } else {
+        const int n1 = sn1[0], n2 = sn2[0];
+        for (int c = 0; c < 2; ++c) {
+            for (int k = 0; k < n1; ++k) rm[c * n1 + k] = (int)(c * n_bdry) + root_map[k];
+            for (int k = 0; k < n2; ++k) rm[2 * n1 + c * n2 + k] = (int)(c * n_bdry) + root_map[n1 + k];
+        }
+    }
+    root_map.swap(rm);
+}
+
 // ---------------------------------------------------------------------------------------
 // build
 // ---------------------------------------------------------------------------------------
-static int build_impl(hps_op *op, const hps_coeffs *co, hipStream_t st) {
+static int build_impl(hps_op *op, const hps_coeffs *co, const hps_coeffs *co_im, hipStream_t st) {
     const hps_grid &g = op->grid;
-    const int q = op->q, q2 = op->q2, nb4 = 4 * q;
+    const int m = op->ncomp;
+    const int q = op->q, q2 = op->q2 * m, nb4 = 4 * q * m;   // leaf interior / boundary lengths
     const bool ir = (op->flags & HPS_FP32_IR) != 0;
     const bool uni = (op->flags & HPS_UNIFORM_COEFFS) != 0;
     // operators equal at every node of a sweep are packed once (node 0's)
@@ -476,6 +537,7 @@ static int build_impl(hps_op *op, const hps_coeffs *co, hipStream_t st) {
     std::vector<int> leaf_ij, root_map, bnd_glob;
     std::vector<HostLevel> hl;
     TRY(plan_tree(op, leaf_ij, hl, root_map, bnd_glob));
+    if (m == 2) complexify(hl, root_map, q, op->n_iface, op->n_bdry);
     TRY(upload(op, &op->leaf_ij, leaf_ij, st));
     TRY(upload(op, &op->root_map, root_map, st));
     TRY(upload(op, &op->bnd_glob, bnd_glob, st));
@@ -495,10 +557,13 @@ static int build_impl(hps_op *op, const hps_coeffs *co, hipStream_t st) {
         }
         TRY(upload(op, &op->tri_cp, tri, st));
     }
-    // coefficients of L (NULL members are zero)
-    TRY(dev_alloc(op, &op->coef, 5 * op->n_int));
-    const double *src[5] = {co->cxx, co->cyy, co->cx, co->cy, co->c0};
-    for (int k = 0; k < 5; ++k) {
+    // coefficients of L (NULL members are zero); complex: real parts, then imaginary parts
+    TRY(dev_alloc(op, &op->coef, 5 * m * op->n_int));
+    const double *src[10] = {co->cxx, co->cyy, co->cx, co->cy, co->c0, nullptr, nullptr, nullptr, nullptr, nullptr};
+    if (co_im) {
+        src[5] = co_im->cxx; src[6] = co_im->cyy; src[7] = co_im->cx; src[8] = co_im->cy; src[9] = co_im->c0;
+    }
+    for (int k = 0; k < 5 * m; ++k) {
         if (src[k])
             HPS_HIP(hipMemcpyAsync(op->coef + k * op->n_int, src[k], sizeof(double) * op->n_int,
                                    hipMemcpyDeviceToDevice, st));
@@ -512,7 +577,7 @@ static int build_impl(hps_op *op, const hps_coeffs *co, hipStream_t st) {
         int *diff;
         TRY(dev_alloc(op, &diff, 1));
         HPS_HIP(hipMemsetAsync(diff, 0, sizeof(int), st));
-        TRY(launch_coef_uniform(op->coef, op->n_int, diff, st));
+        for (int c = 0; c < m; ++c) TRY(launch_coef_uniform(op->coef + (int64_t)c * 5 * op->n_int, op->n_int, diff, st));
         int hdiff = 0;
         HPS_HIP(hipMemcpyAsync(&hdiff, diff, sizeof(int), hipMemcpyDeviceToHost, st));
         HPS_HIP(hipStreamSynchronize(st));
@@ -532,7 +597,8 @@ static int build_impl(hps_op *op, const hps_coeffs *co, hipStream_t st) {
     double *W, *Ainv, *S, *T;
     TRY(tmp.get(&W, (int64_t)nl * q2 * q2));
     TRY(tmp.get(&Ainv, (int64_t)nl * q2 * q2));
-    TRY(launch_leaf_assemble(op, W, st));
+    if (m == 2) TRY(launch_leaf_assemble_cx(op, W, st));
+    else TRY(launch_leaf_assemble(op, W, st));
     {
         unsigned char *used; int *order; double *cb, *rb;
         TRY(gj_scratch(q2, nl, &used, &order, &cb, &rb));
@@ -542,8 +608,13 @@ static int build_impl(hps_op *op, const hps_coeffs *co, hipStream_t st) {
     tmp.release(W);
     TRY(tmp.get(&S, (int64_t)nl * q2 * nb4));
     TRY(tmp.get(&T, (int64_t)nl * nb4 * nb4));
-    TRY(launch_leaf_S(op, Ainv, S, st));
-    TRY(launch_leaf_T(op, S, T, st));
+    if (m == 2) {
+        TRY(launch_leaf_S_cx(op, Ainv, S, st));
+        TRY(launch_leaf_T_cx(op, S, T, st));
+    } else {
+        TRY(launch_leaf_S(op, Ainv, S, st));
+        TRY(launch_leaf_T(op, S, T, st));
+    }
     op->ainv64 = sh(plan_panel(q2, q2, 2, nl, 256, 0));
     op->sleaf64 = sh(plan_panel(q2, nb4, 2, nl, 256, 0));
     for (const Panel *pn : {&op->ainv64, &op->sleaf64})
@@ -657,9 +728,9 @@ static int build_impl(hps_op *op, const hps_coeffs *co, hipStream_t st) {
         return HPS_ESINGULAR;
     }
     // the host-side size plan (used to admit operators into a server's cache) must match
-    if (op->operator_bytes != plan_operator_bytes(op->grid, op->flags)) {
+    if (op->operator_bytes != plan_operator_bytes(op->grid, op->flags, m)) {
         hps_set_error("internal: operator size plan %lld != allocated %lld",
-                      (long long)plan_operator_bytes(op->grid, op->flags), (long long)op->operator_bytes);
+                      (long long)plan_operator_bytes(op->grid, op->flags, m), (long long)op->operator_bytes);
         return HPS_EDEVICE;
     }
     return HPS_OK;
@@ -671,14 +742,20 @@ extern "C" void hps_free(hps_op *op) {
     delete op;
 }
 
-extern "C" int hps_build(const hps_grid *grid, const hps_coeffs *coeffs, double gamma_dt, int flags,
-                         void *stream, hps_op **out) {
+static int build_op(const hps_grid *grid, const hps_coeffs *coeffs, const hps_coeffs *coeffs_im, double gamma_dt,
+                    int flags, void *stream, hps_op **out) {
     CHECK_ARG(out != nullptr, "out is NULL");
     *out = nullptr;
     TRY(check_grid(grid));
     CHECK_ARG(coeffs != nullptr, "coeffs is NULL");
     CHECK_ARG(std::isfinite(gamma_dt) && gamma_dt > 0.0, "gamma_dt must be positive and finite");
     CHECK_ARG((flags & ~(HPS_FP32_IR | HPS_WIDE_TILES | HPS_UNIFORM_COEFFS)) == 0, "unknown flags %d", flags);
+    const int ncomp = coeffs_im ? 2 : 1;
+    if (ncomp == 2) {
+        CHECK_ARG(!(flags & HPS_FP32_IR), "complex operators are FP64 only");
+        // a leaf's embedded operator (2 (p-2)^2 rows) must fit one workgroup tile
+        CHECK_ARG(grid->p <= 18, "complex operators need p <= 18 (got %d)", grid->p);
+    }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
         (void)hipGetLastError();
@@ -688,6 +765,10 @@ extern "C" int hps_build(const hps_grid *grid, const hps_coeffs *coeffs, double 
     const double *cs[5] = {coeffs->cxx, coeffs->cyy, coeffs->cx, coeffs->cy, coeffs->c0};
     const char *names[5] = {"coeffs.cxx", "coeffs.cyy", "coeffs.cx", "coeffs.cy", "coeffs.c0"};
     for (int k = 0; k < 5; ++k) TRY(check_device_ptr(cs[k], names[k]));
+    if (coeffs_im) {
+        const double *ci[5] = {coeffs_im->cxx, coeffs_im->cyy, coeffs_im->cx, coeffs_im->cy, coeffs_im->c0};
+        for (int k = 0; k < 5; ++k) TRY(check_device_ptr(ci[k], names[k]));
+    }
     hps_op *op = new hps_op();
     op->grid = *grid;
     op->p = grid->p;
@@ -703,7 +784,8 @@ extern "C" int hps_build(const hps_grid *grid, const hps_coeffs *coeffs, double 
     op->gamma_dt = gamma_dt;
     op->h = (grid->x1 - grid->x0) / grid->n1;
     op->flags = flags;
-    int rc = build_impl(op, coeffs, (hipStream_t)stream);
+    op->ncomp = ncomp;
+    int rc = build_impl(op, coeffs, coeffs_im, (hipStream_t)stream);
     if (rc) {
         (void)hipDeviceSynchronize();
         hps_free(op);
@@ -711,6 +793,17 @@ extern "C" int hps_build(const hps_grid *grid, const hps_coeffs *coeffs, double 
     }
     *out = op;
     return HPS_OK;
+}
+
+extern "C" int hps_build(const hps_grid *grid, const hps_coeffs *coeffs, double gamma_dt, int flags,
+                         void *stream, hps_op **out) {
+    return build_op(grid, coeffs, nullptr, gamma_dt, flags, stream, out);
+}
+
+extern "C" int hps_build_complex(const hps_grid *grid, const hps_coeffs *re, const hps_coeffs *im, double gamma_dt,
+                                 int flags, void *stream, hps_op **out) {
+    CHECK_ARG(im != nullptr, "im is NULL");
+    return build_op(grid, re, im, gamma_dt, flags, stream, out);
 }
 
 extern "C" int64_t hps_op_bytes(const hps_op *op, int64_t *operator_bytes) {
@@ -751,7 +844,8 @@ extern "C" int ark_create(hps_op *op, const ark_tableau *tab, double dt, const a
             CHECK_ARG(tab->Ahat[i * s + j] == 0.0, "the ERK tableau must be strictly lower triangular");
     CHECK_ARG(std::fabs(gam * dt - op->gamma_dt) <= 1e-14 * op->gamma_dt,
               "operator was built for gamma*dt = %.17g, tableau gives %.17g", op->gamma_dt, gam * dt);
-    if (g) CHECK_ARG(g->kind == 0 || g->kind == 1, "ark_g.kind must be 0 or 1");
+    if (g && op->ncomp == 1) CHECK_ARG(g->kind == 0 || g->kind == 1, "ark_g.kind must be 0 or 1");
+    if (g && op->ncomp == 2) CHECK_ARG(g->kind == 0 || g->kind == 2, "a complex operator takes ark_g.kind 0 or 2");
     static std::atomic<uint64_t> next_uid{1};
     ark_ctx *c = new ark_ctx();
     c->uid = next_uid++;
@@ -768,8 +862,8 @@ extern "C" int ark_create(hps_op *op, const ark_tableau *tab, double dt, const a
         ark_free(c);
         return rc;
     };
-    if (int rc = dev_alloc<double>(nullptr, &c->Lu, (int64_t)s * op->n_int, false)) return fail(rc);
-    if (int rc = dev_alloc<double>(nullptr, &c->F, (int64_t)s * op->n_int, false)) return fail(rc);
+    if (int rc = dev_alloc<double>(nullptr, &c->Lu, (int64_t)s * op->ncomp * op->n_int, false)) return fail(rc);
+    if (int rc = dev_alloc<double>(nullptr, &c->F, (int64_t)s * op->ncomp * op->n_int, false)) return fail(rc);
     if (int rc = dev_alloc<double>(nullptr, &c->qt_dev, s, false)) return fail(rc);
     if (op->flags & HPS_FP32_IR) {
         if (int rc = dev_alloc<double>(nullptr, &c->rhs, op->n_int, false)) return fail(rc);

@@ -170,7 +170,7 @@ bool groupable(ark_ctx *const *ctx, int nprob, const double *const *q_stages, co
     if (nprob < 2) return false;
     for (int b = 0; b < nprob; ++b) {
         const hps_op *op = ctx[b]->op;
-        if (op->flags & HPS_FP32_IR) return false;
+        if ((op->flags & HPS_FP32_IR) || op->ncomp != 1) return false;
         if (op->prof.on || op->L < 1 || ctx[b]->s != ctx[0]->s) return false;
         if (f_stages && f_stages[b]) return false;
     }

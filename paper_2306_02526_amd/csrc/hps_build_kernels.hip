@@ -107,6 +107,121 @@ __global__ __launch_bounds__(NT) void k_leaf_T(BuildLeafArgs a, const double *S,
     }
 }
 
+// ---- complex operators (Sec. 5.5): real embeddings --------------------------------------
+// A complex matrix M = Mr + i Mi acts on (Re z, Im z) as [[Mr, -Mi], [Mi, Mr]].  The
+// coefficient planes of a complex operator hold the 5 real parts, then the 5 imaginary
+// parts; A = I - gdt L has real part I - gdt L_re and imaginary part -gdt L_im.
+
+// entry (r, c) of the interior block of L's coefficient plane set `co` (identity excluded)
+__device__ __forceinline__ double leaf_L_entry(const double *co, int64_t n_int, int64_t gi, const double *D,
+                                               const double *D2, int p, int a1, int b1, int a2, int b2) {
+    double v = 0.0;
+    if (b1 == b2) v += co[gi] * D2[a1 * p + a2] + co[2 * n_int + gi] * D[a1 * p + a2];
+    if (a1 == a2) v += co[n_int + gi] * D2[b1 * p + b2] + co[3 * n_int + gi] * D[b1 * p + b2];
+    if (a1 == a2 && b1 == b2) v += co[4 * n_int + gi];
+    return v;
+}
+
+// embedded A_ii (2 q2 x 2 q2, column-major) on every leaf
+__global__ __launch_bounds__(NT) void k_leaf_assemble_cx(BuildLeafArgs a, double *W) {
+    __shared__ double D[PMAX * PMAX], D2[PMAX * PMAX];
+    const int leaf = blockIdx.y;
+    const int q = a.geo.q, p = a.geo.p, q2 = q * q, n = 2 * q2;
+    load_dmat(a.D, D, p * p);
+    load_dmat(a.D2, D2, p * p);
+    __syncthreads();
+    const int li = a.leaf_ij[2 * leaf], lj = a.leaf_ij[2 * leaf + 1];
+    const int64_t base = ((int64_t)lj * a.geo.n1 + li) * q2;
+    const int64_t n_int = a.geo.n_int;
+    const int64_t tot = (int64_t)n * n;
+    for (int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * NT) {
+        const int R = (int)(idx % n), Cc = (int)(idx / n);
+        const int cr = R / q2, r = R % q2, cc = Cc / q2, c = Cc % q2;
+        const int a1 = r % q + 1, b1 = r / q + 1, a2 = c % q + 1, b2 = c / q + 1;
+        const int64_t gi = base + r;
+        double v;
+        if (cr == cc) {   // real part: I - gdt L_re
+            v = -a.gamma_dt * leaf_L_entry(a.coef, n_int, gi, D, D2, p, a1, b1, a2, b2) + (r == c ? 1.0 : 0.0);
+        } else {          // imaginary part -gdt L_im, with the sign of its block
+            const double im = -a.gamma_dt * leaf_L_entry(a.coef + 5 * n_int, n_int, gi, D, D2, p, a1, b1, a2, b2);
+            v = (cr == 1) ? im : -im;
+        }
+        W[(int64_t)leaf * tot + idx] = v;
+    }
+}
+
+// embedded S_leaf = -A_ii^{-1} A_ib (2 q2 x 8 q): boundary column (cc, e, m)
+__global__ __launch_bounds__(NT) void k_leaf_S_cx(BuildLeafArgs a, const double *ainv, double *S) {
+    __shared__ double D[PMAX * PMAX], D2[PMAX * PMAX];
+    const int leaf = blockIdx.y;
+    const int q = a.geo.q, p = a.geo.p, q2 = q * q, nb = 4 * q, n = 2 * q2;
+    load_dmat(a.D, D, p * p);
+    load_dmat(a.D2, D2, p * p);
+    __syncthreads();
+    const int li = a.leaf_ij[2 * leaf], lj = a.leaf_ij[2 * leaf + 1];
+    const int64_t base = ((int64_t)lj * a.geo.n1 + li) * q2;
+    const int64_t n_int = a.geo.n_int;
+    const double gdt = a.gamma_dt;
+    const double *Ai = ainv + (int64_t)leaf * n * n;
+    const int64_t tot = (int64_t)n * 2 * nb;
+    for (int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * NT) {
+        const int R = (int)(idx % n), col2 = (int)(idx / n);
+        const int cc = col2 / nb, col = col2 % nb;
+        const int e = col / q, m = col % q;
+        double s = 0.0;
+        for (int c = 1; c <= q; ++c) {
+            int rho;
+            double vre, vim;   // real and imaginary part of the A_ib entry (row rho, this node)
+            if (e < 2) {
+                rho = m * q + (c - 1);
+                const int ap = (e == 0) ? 0 : p - 1;
+                const int64_t gi = base + rho;
+                vre = -gdt * (a.coef[gi] * D2[c * p + ap] + a.coef[2 * n_int + gi] * D[c * p + ap]);
+                vim = -gdt * (a.coef[5 * n_int + gi] * D2[c * p + ap] + a.coef[7 * n_int + gi] * D[c * p + ap]);
+            } else {
+                rho = (c - 1) * q + m;
+                const int bp = (e == 2) ? 0 : p - 1;
+                const int64_t gi = base + rho;
+                vre = -gdt * (a.coef[n_int + gi] * D2[c * p + bp] + a.coef[3 * n_int + gi] * D[c * p + bp]);
+                vim = -gdt * (a.coef[6 * n_int + gi] * D2[c * p + bp] + a.coef[8 * n_int + gi] * D[c * p + bp]);
+            }
+            // column cc of the embedded A_ib: rows of component 0 and 1
+            const double top = (cc == 0) ? vre : -vim;   // block (0, cc)
+            const double bot = (cc == 0) ? vim : vre;    // block (1, cc)
+            s = fma(Ai[(int64_t)rho * n + R], top, s);
+            s = fma(Ai[(int64_t)(q2 + rho) * n + R], bot, s);
+        }
+        S[(int64_t)leaf * tot + idx] = -s;
+    }
+}
+
+// embedded DtN map (8 q x 8 q): the flux rows act on each component separately
+__global__ __launch_bounds__(NT) void k_leaf_T_cx(BuildLeafArgs a, const double *S, double *T) {
+    __shared__ double D[PMAX * PMAX];
+    const int leaf = blockIdx.y;
+    const int q = a.geo.q, p = a.geo.p, q2 = q * q, nb = 4 * q, n = 2 * q2, nbl = 2 * nb;
+    load_dmat(a.D, D, p * p);
+    __syncthreads();
+    const double *Sl = S + (int64_t)leaf * n * nbl;
+    const int64_t tot = (int64_t)nbl * nbl;
+    for (int64_t idx = (int64_t)blockIdx.x * NT + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * NT) {
+        const int row2 = (int)(idx % nbl), col = (int)(idx / nbl);
+        const int cr = row2 / nb, row = row2 % nb;
+        const int e = row / q, m = row % q;
+        const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * p);
+        double v = 0.0;
+        for (int c = 1; c <= q; ++c) {
+            const int rho = (e < 2) ? m * q + (c - 1) : (c - 1) * q + m;
+            v = fma(dr[c], Sl[(int64_t)col * n + cr * q2 + rho], v);
+        }
+        const int lo = cr * nb + ((e < 2) ? 0 * q + m : 2 * q + m);
+        const int hi = cr * nb + ((e < 2) ? 1 * q + m : 3 * q + m);
+        if (col == lo) v += dr[0];
+        if (col == hi) v += dr[p - 1];
+        T[(int64_t)leaf * tot + idx] = v;
+    }
+}
+
 // Gather the merge blocks of level-l nodes from their children's DtN maps (column-major):
 // M = T^a_33 - T^b_33, B = [-T^a_31 | T^b_32], Cm = [T^a_13; T^b_23], Tn = diag(T^a_11, T^b_22).
 struct MergeArgs {
@@ -367,6 +482,30 @@ int launch_leaf_T(const hps_op *op, const double *S, double *T, hipStream_t st) 
     const int64_t tot = (int64_t)16 * op->q * op->q;
     const unsigned bx = (unsigned)std::min<int64_t>(nblk(tot), 64);
     hipLaunchKernelGGL(k_leaf_T, dim3(bx, op->nleaves), dim3(NT), 0, st, build_leaf_args(op), S, T);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+int launch_leaf_assemble_cx(const hps_op *op, double *W, hipStream_t st) {
+    const int64_t n = 2 * (int64_t)op->q2, tot = n * n;
+    const unsigned bx = (unsigned)std::min<int64_t>(nblk(tot), 128);
+    hipLaunchKernelGGL(k_leaf_assemble_cx, dim3(bx, op->nleaves), dim3(NT), 0, st, build_leaf_args(op), W);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+int launch_leaf_S_cx(const hps_op *op, const double *ainv, double *S, hipStream_t st) {
+    const int64_t tot = 2 * (int64_t)op->q2 * 8 * op->q;
+    const unsigned bx = (unsigned)std::min<int64_t>(nblk(tot), 128);
+    hipLaunchKernelGGL(k_leaf_S_cx, dim3(bx, op->nleaves), dim3(NT), 0, st, build_leaf_args(op), ainv, S);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+int launch_leaf_T_cx(const hps_op *op, const double *S, double *T, hipStream_t st) {
+    const int64_t tot = (int64_t)64 * op->q * op->q;
+    const unsigned bx = (unsigned)std::min<int64_t>(nblk(tot), 128);
+    hipLaunchKernelGGL(k_leaf_T_cx, dim3(bx, op->nleaves), dim3(NT), 0, st, build_leaf_args(op), S, T);
     HPS_LAUNCHED();
     return HPS_OK;
 }

@@ -70,6 +70,17 @@ static int ir_refine(hps_op *op, const double *rhs, const double *jump, double *
 // (full canonical vector), and for FP32_IR the refinement loop.
 static int solve_one(hps_op *op, const double *body, const double *dir, const double *jump, double *u,
                      hipStream_t st, hps_info *inf) {
+    if (op->ncomp == 2) {   // complex operator: the same sweeps on the real embedding
+        LeafPhase up;
+        up.up = LU_BODY;
+        up.body = body;
+        TRY(launch_leaf_cx(op, up, st));
+        TRY(levels(op, false, jump, dir, st));
+        LeafPhase dn;
+        dn.down = LD_WRITE_U;
+        dn.u_out = u;
+        return launch_leaf_cx(op, dn, st);
+    }
     const bool ir = (op->flags & HPS_FP32_IR) != 0;
     LeafPhase up;
     up.up = LU_BODY;
@@ -97,11 +108,12 @@ extern "C" int hps_solve(hps_op *op, int nrhs, const double *body, const double 
     hipStream_t st = (hipStream_t)stream;
     int worst_it = 0;
     double worst_rel = 0.0;
+    const int m = op->ncomp;
     for (int r = 0; r < nrhs; ++r) {
-        const double *b = body + (int64_t)r * op->n_int;
-        const double *d = dirichlet ? dirichlet + (int64_t)r * op->n_bdry : nullptr;
-        const double *j = (jump && op->n_iface) ? jump + (int64_t)r * op->n_iface : nullptr;
-        double *ur = u + (int64_t)r * op->N;
+        const double *b = body + (int64_t)r * m * op->n_int;
+        const double *d = dirichlet ? dirichlet + (int64_t)r * m * op->n_bdry : nullptr;
+        const double *j = (jump && op->n_iface) ? jump + (int64_t)r * m * op->n_iface : nullptr;
+        double *ur = u + (int64_t)r * m * op->N;
         hps_info inf{};
         TRY(solve_one(op, b, d, j, ur, st, &inf));
         worst_it = std::max(worst_it, inf.ir_iterations);
@@ -123,7 +135,7 @@ void hps::step_phase(const ark_ctx *c, int k, double *u, const double *q_stages,
                      const double *qt, LeafPhase &ph) {
     const hps_op *op = c->op;
     const int s = c->s;
-    const int64_t n = op->n_int;
+    const int64_t n = op->n_int * op->ncomp;   // one stage vector (both planes when complex)
     ph = LeafPhase{};
     ph.g = GPoly{c->g.kind, c->g.g0, c->g.g1, c->g.g2, c->g.g3};
     ph.q_scale = 1.0;
@@ -170,6 +182,21 @@ static int enqueue_step(ark_ctx *c, double *u, const double *q_stages, const dou
     const int s = c->s;
     const bool ir = (op->flags & HPS_FP32_IR) != 0;
     (void)q_time;
+    if (op->ncomp == 2) {
+        // complex operator: u, the boundary data and every stage vector in two planes
+        const int64_t nb = op->n_bdry, N = op->N, plane = (int64_t)op->nleaves * 4 * op->q;
+        for (int k = 0; k < s; ++k) {
+            if (k > 0) TRY(levels(op, false, nullptr, f_stages ? f_stages + (int64_t)k * 2 * nb : nullptr, st));
+            LeafPhase ph;
+            step_phase(c, k, u, nullptr, nullptr, c->qt_dev, ph);
+            TRY(launch_leaf_cx(op, ph, st));
+        }
+        const double *fend = f_stages ? f_stages + (int64_t)s * 2 * nb : nullptr;
+        for (int cc = 0; cc < 2; ++cc)
+            TRY(launch_interface_lines(op, u + cc * N, fend ? fend + cc * nb : nullptr, st, nullptr,
+                                       op->ir_flux + cc * plane));
+        return HPS_OK;
+    }
     for (int k = 0; k < s; ++k) {
         if (k > 0) {
             const double *fk = f_stages ? f_stages + (int64_t)k * op->n_bdry : nullptr;
@@ -383,6 +410,7 @@ static int check_step_args(ark_ctx *c, double t, double *u, const double *q_stag
 extern "C" int ark_step(ark_ctx *c, double t, double *u, const double *q_stages, const double *q_space,
                         const double *q_time, const double *f_stages, void *stream) {
     TRY(check_step_args(c, t, u, q_stages, q_space, q_time, f_stages));
+    CHECK_ARG(c->op->ncomp == 1 || (!q_stages && !q_space), "steps of a complex operator take no source");
     return run_step(c, 0, u, q_stages, q_space, q_time, f_stages, (hipStream_t)stream);
 }
 
@@ -390,6 +418,7 @@ extern "C" int ark_step_slope(ark_ctx *c, double t, double *u, const double *q_s
                               const double *q_time, const double *fdot_stages, void *stream) {
     TRY(check_step_args(c, t, u, q_stages, q_space, q_time, fdot_stages));
     CHECK_ARG(c->s <= 8, "the slope step takes at most 8 stages");
+    CHECK_ARG(c->op->ncomp == 1, "the slope step takes a real operator");
     TRY(ark_slope_workspace(c));
     return run_step(c, 1, u, q_stages, q_space, q_time, fdot_stages, (hipStream_t)stream);
 }
@@ -400,7 +429,8 @@ extern "C" int ark_step_burgers(ark_ctx *cu, ark_ctx *cv, double t, double *u, d
     CHECK_ARG(cu != cv, "the two components need a context each");
     CHECK_ARG(u != v, "u and v must be different arrays");
     CHECK_ARG(cu->op == cv->op, "both contexts must be created on the same operator");
-    CHECK_ARG(!(cu->op->flags & HPS_FP32_IR), "two-component steps need an operator built with HPS_FP64");
+    CHECK_ARG(!(cu->op->flags & HPS_FP32_IR) && cu->op->ncomp == 1,
+              "two-component steps need a real operator built with HPS_FP64");
     CHECK_ARG(cu->s == cv->s && cu->dt == cv->dt && cu->A == cv->A && cu->b == cv->b && cu->c == cv->c &&
                   cu->Ah == cv->Ah && cu->bh == cv->bh,
               "both contexts must have the same tableau and dt");

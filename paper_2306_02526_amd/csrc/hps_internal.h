@@ -44,7 +44,7 @@ struct Panel {
 Panel plan_panel(int R, int C, int vw, int nodes, int rp_max, int min_wg);
 // The same plan stored once for all `nodes` (operators that are equal at every node).
 Panel shared_panel(Panel p);
-int64_t plan_operator_bytes(const hps_grid &g, int flags);   // what hps_build's panels take
+int64_t plan_operator_bytes(const hps_grid &g, int flags, int ncomp = 1);   // what hps_build's panels take
 
 // One internal level of the tree (level 0 = root), all nodes of the same shape.
 struct Level {
@@ -99,8 +99,12 @@ struct hps_op {
     int64_t N = 0, n_int = 0, n_edge = 0, n_vert = 0, n_iface = 0, n_bdry = 0;
     double gamma_dt = 0, h = 0;
     int flags = 0;
+    // 1: real operator; 2: complex operator stored as its real embedding (every vector in
+    // two planes, real part then imaginary part, of the real layout's length)
+    int ncomp = 1;
     double *D = nullptr, *D2 = nullptr;    // device p*p, row-major: D[a*p + m] = d/dx weight
     double *coef = nullptr;                // device 5*n_int: cxx, cyy, cx, cy, c0 of L
+                                           // (complex: the 5 real parts, then the 5 imaginary)
     int *leaf_ij = nullptr;                // device [nleaves][2] heap order -> (i, j)
     int *root_map = nullptr;               // device [n_bdry] root boundary -> boundary index
     int *bnd_glob = nullptr;               // device [n_bdry] boundary index -> canonical index
@@ -228,6 +232,8 @@ struct LeafPhase {
     double *unew = nullptr;                    // LU_UPDATE
 };
 int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st);
+// the same phases for a complex operator (FP64; vectors in real / imaginary planes)
+int launch_leaf_cx(const hps_op *op, const LeafPhase &ph, hipStream_t st);
 // upward sweep over the levels, the root, then the downward sweep (jump and dirichlet
 // may be NULL)
 int launch_levels(const hps_op *op, bool fp32, const double *jump, const double *dirichlet, hipStream_t st);
@@ -277,6 +283,10 @@ int launch_set_values(double *dst, const double *vals, int n, hipStream_t st);  
 
 // build --------------------------------------------------------------------------------
 int launch_leaf_assemble(const hps_op *op, double *W, hipStream_t st);
+// complex operators: the real embeddings [[Re, -Im], [Im, Re]] of A_ii, S_leaf and the DtN map
+int launch_leaf_assemble_cx(const hps_op *op, double *W, hipStream_t st);
+int launch_leaf_S_cx(const hps_op *op, const double *ainv, double *S, hipStream_t st);
+int launch_leaf_T_cx(const hps_op *op, const double *S, double *T, hipStream_t st);
 // sets *flag (device int, zero beforehand) when some coefficient differs from its value at
 // node 0
 int launch_coef_uniform(const double *coef, int64_t n, int *flag, hipStream_t st);

@@ -947,7 +947,7 @@ int launch_levels(const hps_op *op, bool fp32, const double *jump, const double 
     ProfScope ps_(&op->prof, fp32 ? KF_LEVEL_DOWN32 : KF_LEVEL_DOWN64, st);
     if (op->L == 0) {
         hipLaunchKernelGGL(k_root_leaf_ub, dim3(1), dim3(NT), 0, st, dirichlet, (const int *)op->root_map,
-                           op->ub_leaf, 4 * op->q);
+                           op->ub_leaf, 4 * op->q * op->ncomp);
         HPS_LAUNCHED();
         return HPS_OK;
     }

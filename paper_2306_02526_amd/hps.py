@@ -22,7 +22,7 @@ ERRORS = {-1: "HPS_EINVAL", -2: "HPS_ENOMEM", -3: "HPS_EDEVICE", -4: "HPS_ESINGU
 
 # every entry point declared in include/hps.h, include/hps_batch.h and include/hps_serve.h
 EXPORTED = ["hps_last_error", "hps_num_nodes", "hps_nodes", "hps_build", "hps_op_bytes",
-            "hps_solve", "hps_free", "hps_profile_enable", "hps_profile_read", "ark_create", "ark_step", "ark_stage_solves_per_step",
+            "hps_solve", "hps_free", "hps_build_complex", "hps_profile_enable", "hps_profile_read", "ark_create", "ark_step", "ark_stage_solves_per_step",
             "ark_free", "ark_step_slope", "ark_step_burgers", "hps_solve_batched", "ark_step_batched", "hps_batch_streams",
             "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_release", "srv_get_stats", "srv_destroy"]
 
@@ -103,6 +103,8 @@ def lib():
     L.hps_nodes.argtypes = [P(HpsGrid), P(dbl), P(dbl)]
     L.hps_build.restype = i32
     L.hps_build.argtypes = [P(HpsGrid), P(HpsCoeffs), dbl, i32, vp, P(vp)]
+    L.hps_build_complex.restype = i32
+    L.hps_build_complex.argtypes = [P(HpsGrid), P(HpsCoeffs), P(HpsCoeffs), dbl, i32, vp, P(vp)]
     L.hps_op_bytes.restype = i64
     L.hps_op_bytes.argtypes = [vp, P(i64)]
     L.hps_solve.restype = i32
@@ -201,11 +203,12 @@ def _stream(stream):
 class HpsOp:
     """Owns an hps_op handle (freed with hps_free)."""
 
-    def __init__(self, handle, grid, gamma_dt, flags, sizes, keep):
+    def __init__(self, handle, grid, gamma_dt, flags, sizes, keep, ncomp=1):
         self.handle = handle
         self.grid = grid
         self.gamma_dt = gamma_dt
         self.flags = flags
+        self.ncomp = ncomp        # 2: complex operator, vectors as [real plane, imaginary plane]
         self.N, self.n_int, self.n_iface, self.n_bdry = sizes
         self._keep = keep
 
@@ -252,6 +255,33 @@ def hps_build(grid, coeffs, gamma_dt, flags=HPS_FP64, stream=None):
     return HpsOp(h, grid, float(gamma_dt), flags, sizes, keep)
 
 
+def hps_build_complex(grid, coeffs_re, coeffs_im, gamma_dt, flags=HPS_FP64, stream=None):
+    """Complex coefficients: coeffs_re / coeffs_im dicts of float64 CUDA tensors (real and
+    imaginary parts, any of cxx, cyy, cx, cy, c0)."""
+    sizes = hps_num_nodes(grid)
+    n_int = sizes[1]
+    keep = [v for d in (coeffs_re, coeffs_im) for v in d.values() if v is not None]
+    cr = HpsCoeffs(*[_dptr(coeffs_re.get(k), n_int, k) for k in ("cxx", "cyy", "cx", "cy", "c0")])
+    ci = HpsCoeffs(*[_dptr(coeffs_im.get(k), n_int, k) for k in ("cxx", "cyy", "cx", "cy", "c0")])
+    h = ctypes.c_void_p()
+    _check(lib().hps_build_complex(ctypes.byref(grid), ctypes.byref(cr), ctypes.byref(ci), float(gamma_dt),
+                                   int(flags), _stream(stream), ctypes.byref(h)))
+    return HpsOp(h, grid, float(gamma_dt), flags, sizes, keep, ncomp=2)
+
+
+def hps_solve_complex(op, body, dirichlet=None, jump=None, u=None, stream=None):
+    """Complex operator, one right-hand side: body [2, n_int] (real, imaginary plane),
+    dirichlet [2, n_bdry], jump [2, n_iface]; returns u [2, N]."""
+    import torch
+    if op.ncomp != 2:
+        raise ValueError("hps_solve_complex needs an operator from hps_build_complex")
+    if u is None:
+        u = torch.empty((2, op.N), dtype=torch.float64, device=body.device)
+    _check(lib().hps_solve(op.handle, 1, _dptr(body, 2 * op.n_int, "body"), _dptr(dirichlet, 2 * op.n_bdry, "dirichlet"),
+                           _dptr(jump, 2 * op.n_iface, "jump"), _dptr(u, 2 * op.N, "u"), _stream(stream), None))
+    return u
+
+
 def hps_solve(op, body, dirichlet=None, jump=None, u=None, stream=None, info=False):
     """Solve (I - gamma_dt L) u = body; body [nrhs, n_int] or [n_int]. Returns u."""
     import torch
@@ -288,13 +318,16 @@ class ArkCtx:
 
 
 def ark_create(op, tableau, dt, g=None):
-    """tableau: dict with s, A (s x s), b, c, Ahat, bhat.  g: None or (g0, g1, g2, g3)."""
+    """tableau: dict with s, A (s x s), b, c, Ahat, bhat.  g: None or (g0, g1, g2, g3): the
+    polynomial g0 + g1 u + g2 u^2 + g3 u^3, or for a complex operator the NLS form
+    (g0 + i g1) u + (g2 + i g3) |u|^2 u."""
     s = int(tableau["s"])
     arrs = {k: np.ascontiguousarray(np.asarray(tableau[k], dtype=np.float64).ravel())
             for k in ("A", "b", "c", "Ahat", "bhat")}
     P = ctypes.POINTER(ctypes.c_double)
     tab = ArkTableau(s, *[arrs[k].ctypes.data_as(P) for k in ("A", "b", "c", "Ahat", "bhat")])
-    gg = ArkG(0, 0.0, 0.0, 0.0, 0.0) if g is None else ArkG(1, *[float(v) for v in g])
+    kind = 2 if getattr(op, "ncomp", 1) == 2 else 1
+    gg = ArkG(0, 0.0, 0.0, 0.0, 0.0) if g is None else ArkG(kind, *[float(v) for v in g])
     h = ctypes.c_void_p()
     _check(lib().ark_create(op.handle, ctypes.byref(tab), float(dt), ctypes.byref(gg), ctypes.byref(h)))
     return ArkCtx(h, op, s)
@@ -308,9 +341,10 @@ def ark_step(ctx, t, u, q_stages=None, q_space=None, q_time=None, f_stages=None,
         if qt_arr.size != s:
             raise ValueError("q_time needs one value per stage")
         qt = qt_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-    _check(lib().ark_step(ctx.handle, float(t), _dptr(u, op.N, "u"),
+    m = getattr(op, "ncomp", 1)   # complex: u [2, N], f_stages [s + 1, 2, n_bdry]
+    _check(lib().ark_step(ctx.handle, float(t), _dptr(u, m * op.N, "u"),
                           _dptr(q_stages, s * op.n_int, "q_stages"), _dptr(q_space, op.n_int, "q_space"),
-                          qt, _dptr(f_stages, (s + 1) * op.n_bdry, "f_stages"), _stream(stream)))
+                          qt, _dptr(f_stages, (s + 1) * m * op.n_bdry, "f_stages"), _stream(stream)))
     return u
 
 

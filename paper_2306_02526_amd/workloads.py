@@ -18,6 +18,10 @@ Workloads (all on the unit square, Dirichlet data):
               diffusive solutions of the paper's analytic tests (eps = 0.1) and the
               rotating-flow initial data (eps = 0.005); boundary data from the exact
               solutions, zero for the rotating flow.
+  nls         the regularised NLS filamentation test, i u_t + (1 - i a eps) Lap u
+              + (1 + i c eps)|u|^2 u = i b eps u on [0, 25.6]^2, u0 = 5 exp(-r^2) about the
+              centre, zero boundary data; a, b, c, eps are not printed and are chosen here
+              (a = b = c = 1, eps = 0.05).
 """
 import math
 
@@ -261,4 +265,33 @@ def burgers_coeffs(eps, n):
     e = np.full(n, float(eps))
     z = np.zeros(n)
     return e, e.copy(), z, z.copy(), z.copy()
+
+
+# ---------------------------------------------------------------------------------------
+# regularised nonlinear Schroedinger equation (multiple filamentation)
+# ---------------------------------------------------------------------------------------
+class NLSFilamentation:
+    """u_t = (a eps + i) Lap u + (i - c eps)|u|^2 u + b eps u on [0, 25.6]^2, u = 0 on the
+    boundary, u0 = 5 exp(-(x - 12.8)^2 - (y - 12.8)^2)."""
+
+    domain = (0.0, 25.6, 0.0, 25.6)
+
+    def __init__(self, a=1.0, b=1.0, c=1.0, eps=0.05):
+        self.a, self.b, self.c, self.eps = float(a), float(b), float(c), float(eps)
+
+    def u0(self, x, y):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        return (5.0 * np.exp(-(x - 12.8) ** 2 - (y - 12.8) ** 2)).astype(np.complex128)
+
+    def coeffs(self, n):
+        """Real and imaginary parts of the coefficients of L = (a eps + i) Lap."""
+        z = np.zeros(n)
+        re = dict(cxx=np.full(n, self.a * self.eps), cyy=np.full(n, self.a * self.eps), cx=z, cy=z.copy(), c0=z.copy())
+        im = dict(cxx=np.ones(n), cyy=np.ones(n), cx=z.copy(), cy=z.copy(), c0=z.copy())
+        return re, im
+
+    def g(self):
+        """(g0, g1, g2, g3) of g(u) = (g0 + i g1) u + (g2 + i g3)|u|^2 u."""
+        return (self.b * self.eps, 0.0, -self.c * self.eps, 1.0)
 
