@@ -60,6 +60,8 @@ def parse():
     ap.add_argument("--no-burgers", action="store_true")
     ap.add_argument("--burgers-steps", type=int, default=10)
     ap.add_argument("--no-heat", action="store_true")
+    ap.add_argument("--no-nls", action="store_true")
+    ap.add_argument("--nls-steps", type=int, default=10)
     ap.add_argument("--heat-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stage-solves", type=int, default=3)
@@ -251,6 +253,55 @@ def heat_leg(args, torch, hps, workloads, g, x, y, n_int, tab, dev, uniform):
             "leaf_down_up_us_per_launch": round(1e3 * prof["leaf_down_up_fp64"][1] / prof["leaf_down_up_fp64"][0], 2)}
 
 
+def nls_leg(args, torch, hps, workloads, n, p, tab, dev, uniform, steps, tiles=0):
+    """The regularised NLS filamentation problem (Sec. 5.5: [0, 25.6]^2, u0 = 5 exp(-r^2),
+    zero boundary data, dt = 0.005) on n x n leaves of order p: complex operators (real
+    embedding), ark_step with the NLS nonlinearity; 5 complex stage solves per step."""
+    import numpy as np
+    nls = workloads.NLSFilamentation()
+    dt = 0.005
+    g = hps.make_grid(*nls.domain, n, n, p)
+    N, n_int, _, _ = hps.hps_num_nodes(g)
+    x, y = hps.hps_nodes(g)
+    re, im = nls.coeffs(n_int)
+    t0 = time.perf_counter()
+    op = hps.hps_build_complex(g, {k: torch.tensor(v, device=dev) for k, v in re.items()},
+                               {k: torch.tensor(v, device=dev) for k, v in im.items()}, tab["gamma"] * dt,
+                               hps.HPS_FP64 | tiles | (hps.HPS_UNIFORM_COEFFS if uniform else 0))
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    _, op_bytes = op.bytes()
+    ctx = hps.ark_create(op, tab, dt, g=nls.g())
+    u0 = nls.u0(x, y)
+    u = torch.tensor(np.stack([u0.real, u0.imag]), device=dev).contiguous()
+    for k in range(args.warmup):
+        hps.ark_step(ctx, k * dt, u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + steps):
+        hps.ark_step(ctx, k * dt, u)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    hps.hps_profile_enable(op, True)
+    for k in range(2):
+        hps.ark_step(ctx, (args.warmup + steps + k) * dt, u)
+    torch.cuda.synchronize()
+    prof = hps.hps_profile_read(op)
+    hps.hps_profile_enable(op, False)
+    finite = bool(torch.isfinite(u).all())
+    mass = float((u[0] ** 2 + u[1] ** 2).max().sqrt())
+    op.free()
+    stages = tab["s"] - 1
+    out = {"grid": f"{n}x{n}_p{p}", "level_tiles": "wide" if tiles else "thin",
+           "stage_solves_per_s": round(stages * steps / el, 1),
+           "ms_per_step": round(1e3 * el / steps, 3), "steps": steps, "dt": dt, "build_s": round(build_s, 2),
+           "operators": "one shared copy (uniform coefficients)" if uniform else "per node",
+           "operator_bytes": op_bytes, "max_abs_u": mass, "finite": finite,
+           "kernels": {k: {"launches_per_step": v[0] // 2, "us_per_launch": round(1e3 * v[1] / v[0], 2)}
+                       for k, v in prof.items()}}
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -396,6 +447,16 @@ def main():
         heat["per_node_operators"] = heat_leg(args, torch, hps, workloads, g, x, y, n_int, tab, dev, uniform=False)
         log(f"heat: {heat}")
 
+    # ---- the regularised NLS (complex operators): bench grid and the paper's grid ----
+    nls = None
+    if not args.no_nls:
+        nls = nls_leg(args, torch, hps, workloads, n, p, tab, dev, uniform=True, steps=args.nls_steps)
+        nls["per_node_operators"] = nls_leg(args, torch, hps, workloads, n, p, tab, dev, uniform=False,
+                                            steps=args.nls_steps)
+        nls["filamentation_8x8_p13"] = nls_leg(args, torch, hps, workloads, 8, 13, tab, dev, uniform=True,
+                                               steps=args.nls_steps)
+        log(f"nls: {nls}")
+
     # ---- FP32 operators + FP64 iterative refinement, same steps ----
     fp32 = None
     if not args.no_fp32:
@@ -473,6 +534,7 @@ def main():
         "slope_formulation": slope,
         "burgers_system": burgers,
         "heat_constant_coefficients": heat,
+        "nls_complex": nls,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -288,6 +288,10 @@ __global__ __launch_bounds__(NT) void k_leaf_cx(LeafCxArgs a) {
 }  // namespace
 
 int launch_leaf_cx(const hps_op *op, const LeafPhase &ph, hipStream_t st) {
+    const int fam = ph.down == LD_EVAL ? KF_LEAFC_EVAL_UP64
+                    : ph.down == LD_STAGE ? (ph.up == LU_UPDATE ? KF_LEAFC_DOWN_UPDATE64 : KF_LEAFC_DOWN_UP64)
+                                          : KF_LEAFC_SOLVE64;
+    ProfScope ps_(&op->prof, fam, st);
     LeafCxArgs a{};
     a.geo = geo_of(op);
     a.N = op->N;

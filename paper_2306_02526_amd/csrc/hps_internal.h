@@ -66,7 +66,8 @@ enum KernelFamily {
     KF_LEAF_UP64, KF_LEAF_UP32, KF_LEAF_DOWN64, KF_LEAF_DOWN32, KF_LEAF_EVAL_UP64, KF_LEAF_EVAL_UP32,
     KF_LEAF_DOWN_UP64, KF_LEAF_DOWN_UP32, KF_LEAF_DOWN_UPDATE64, KF_LEAF_EVAL_UPDATE64,
     KF_LEVEL_UP64, KF_LEVEL_UP32, KF_LEVEL_DOWN64, KF_LEVEL_DOWN32, KF_RESIDUAL, KF_LINES,
-    KF_LEAF2_EVAL_UP64, KF_LEAF2_DOWN_UP64, KF_LEAF2_DOWN_UPDATE64, KF_LEVEL2_UP64, KF_LEVEL2_DOWN64, KF_COUNT
+    KF_LEAF2_EVAL_UP64, KF_LEAF2_DOWN_UP64, KF_LEAF2_DOWN_UPDATE64, KF_LEVEL2_UP64, KF_LEVEL2_DOWN64,
+    KF_LEAFC_EVAL_UP64, KF_LEAFC_DOWN_UP64, KF_LEAFC_DOWN_UPDATE64, KF_LEAFC_SOLVE64, KF_COUNT
 };
 extern const char *const kKernelFamilyNames[KF_COUNT];
 

@@ -667,7 +667,8 @@ const char *const kKernelFamilyNames[KF_COUNT] = {
     "leaf_eval_up_fp32", "leaf_down_up_fp64", "leaf_down_up_fp32", "leaf_down_update_fp64",
     "leaf_eval_update", "level_up_fp64", "level_up_fp32", "level_down_fp64", "level_down_fp32",
     "residual", "lines", "leaf2_eval_up_fp64", "leaf2_down_up_fp64", "leaf2_down_update_fp64",
-    "level2_up_fp64", "level2_down_fp64"};
+    "level2_up_fp64", "level2_down_fp64", "leafc_eval_up_fp64", "leafc_down_up_fp64", "leafc_down_update_fp64",
+    "leafc_solve_fp64"};
 
 hipEvent_t Profiler::get() {
     if (!pool.empty()) {
