@@ -13,7 +13,7 @@ namespace hps {
 
 constexpr int NT = 256;   // threads per workgroup for every kernel of the library
 constexpr int PMAX = 24;  // largest supported Chebyshev order p
-constexpr int XS_BYTES = 32768;  // LDS bytes for one workgroup's input vector
+constexpr int XS_BYTES = 65536;  // LDS bytes for one workgroup's input vector (larger ones are split)
 
 // ---------------------------------------------------------------------------------------
 // Packed operator for a streaming matrix-vector product.
