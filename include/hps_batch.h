@@ -6,7 +6,7 @@
  * instance of the per-stage HPS solve of Sec. 2.1 (Algorithm 1) or of one step
  * of the stage formulation of Sec. 3.1 (eqs. 9-11).
  *
- * ark_step_batched runs a batch of FP64 problems with equal stage counts, no boundary
+ * ark_step_batched runs a batch of real FP64 problems with equal stage counts, no boundary
  * data and at least two leaves each as grouped launches (problems that share an
  * operator get stepping workspaces of their own, allocated on first use):
  * one launch per leaf phase and per tree level covers every problem (levels are
