@@ -178,6 +178,61 @@ def test_damped_schroedinger_mode_on_the_gpu(torch):
     assert np.abs(unplanes(ug) - exact).max() < 1e-5   # the time-discretisation error after 4 steps
 
 
+ORACLE_NLS_STEP = """
+import sys, time
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+from oracle.ark import ark436l2sa, tableau_float
+from oracle.grid import Grid
+from oracle.hps import HPS
+from oracle.nls import NLSARK
+d = np.load(sys.argv[2])
+og = Grid(0, 25.6, 0, 25.6, 64, 64, 16)
+co = {k: d[k + "_re"] + 1j * d[k + "_im"] for k in ("cxx", "cyy", "cx", "cy", "c0")}
+t0 = time.perf_counter()
+orc = NLSARK(HPS(og, co, float(d["gdt"])), co, tableau_float(ark436l2sa()), float(d["dt"]),
+             float(d["b"]), float(d["c"]), float(d["eps"]))
+print(f"   oracle built in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+np.save(sys.argv[3], orc.step(d["u0"]))
+print(f"   oracle step done after {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+"""
+
+
+def test_full_size_nls_step_matches_oracle(torch, tmp_path):
+    """The bench leg's NLS configuration (64x64 leaves, p = 16, [0, 25.6]^2, dt = 0.005, shared
+    operator copy): one step element by element against the oracle in a child process."""
+    import os
+    import subprocess
+    say("[nls] full size 64x64 p=16")
+    nls = workloads.NLSFilamentation()
+    og = Grid(*nls.domain, 64, 64, 16)
+    x, y = og.coordinates()
+    tab = product_tableau()
+    dt = 0.005
+    re, im = nls.coeffs(og.n_int)
+    g = hps.make_grid(*nls.domain, 64, 64, 16)
+    op = hps.hps_build_complex(g, {k: torch.tensor(v, device="cuda") for k, v in re.items()},
+                               {k: torch.tensor(v, device="cuda") for k, v in im.items()}, tab["gamma"] * dt,
+                               hps.HPS_UNIFORM_COEFFS)
+    ctx = hps.ark_create(op, tab, dt, g=nls.g())
+    u0 = nls.u0(x, y)
+    ug = planes(torch, u0)
+    hps.ark_step(ctx, 0.0, ug)
+    u_gpu = unplanes(ug)
+    say("   GPU step done; oracle in a child process")
+    inp, outp = tmp_path / "in.npz", tmp_path / "out.npy"
+    arrs = {f"{k}_re": v for k, v in re.items()}
+    arrs.update({f"{k}_im": v for k, v in im.items()})
+    np.savez(inp, u0=u0, gdt=tab["gamma"] * dt, dt=dt, b=nls.b, c=nls.c, eps=nls.eps, **arrs)
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, OPENBLAS_NUM_THREADS="1", OMP_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    subprocess.run([sys.executable, "-c", ORACLE_NLS_STEP, root, str(inp), str(outp)], env=env, check=True,
+                   timeout=900)
+    e = rel(u_gpu, np.load(outp))
+    say(f"   rel err {e:.2e}")
+    assert e <= TOL64
+
+
 def test_graph_replay_equals_eager(torch, monkeypatch):
     say("[nls] graph replay vs eager, 4x4 p=9")
     nls = workloads.NLSFilamentation()
