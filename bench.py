@@ -305,7 +305,7 @@ def nls_leg(args, torch, hps, workloads, n, p, tab, dev, uniform, steps, tiles=0
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+        print(f"bench.py measures one GPU only (the library has no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
     if args.counter_run:

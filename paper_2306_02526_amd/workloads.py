@@ -30,8 +30,8 @@ import numpy as np
 SEED_BASE = 2306025260
 
 
-def rng_for(config_index, offset=0):
-    return np.random.default_rng(SEED_BASE + int(config_index) + int(offset))
+def rng_for(stream, offset=0):
+    return np.random.default_rng(SEED_BASE + int(stream) + int(offset))
 
 
 # ---------------------------------------------------------------------------------------
@@ -183,14 +183,14 @@ class SmoothDiffusivity:
         return a, ax, ay
 
 
-def batched_mix(n_problems=256, config_index=4, sides=(8, 16, 32, 64), orders=(8, 12, 16)):
+def batched_mix(n_problems=256, stream=4, sides=(8, 16, 32, 64), orders=(8, 12, 16)):
     """Per-problem data of the batched workload: n1, n2 drawn from `sides`, p from `orders`,
     gamma*dt in {1e-3, 1e-2}, smooth diffusivity a in [0.5, 1.5], heat (manufactured
     solution) or Allen-Cahn type 50/50.  Leaves are squares of side 1 / max(n1, n2), so the
     domain is [0, n1 h] x [0, n2 h] (the unit square when n1 == n2)."""
     out = []
     for b in range(n_problems):
-        rng = rng_for(config_index, b)
+        rng = rng_for(stream, b)
         n1 = int(rng.choice(list(sides)))
         n2 = int(rng.choice(list(sides)))
         p = int(rng.choice(list(orders)))

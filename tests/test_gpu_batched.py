@@ -150,7 +150,7 @@ def test_grouped_batched_steps_match_single_steps_and_oracle(torch, monkeypatch,
     workspaces of their own): the same bits as single steps, and the oracle's result; the
     plan and its graph are reused on later steps.  Both level tilings (thin tiles for one
     problem, wide tiles for many)."""
-    mix = workloads.batched_mix(n_problems=7, config_index=6, sides=(2, 4, 8), orders=(6, 8, 10))
+    mix = workloads.batched_mix(n_problems=7, stream=6, sides=(2, 4, 8), orders=(6, 8, 10))
     tab = product_tableau()
     otab = tableau_float(ark436l2sa())
     res = {}
