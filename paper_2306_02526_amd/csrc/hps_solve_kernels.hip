@@ -49,6 +49,31 @@ __device__ __forceinline__ double gpoly(const GPoly &g, double u) {
     return g.g0 + u * (g.g1 + u * (g.g2 + u * g.g3));
 }
 
+// Sum of the nsl slice partials red[s * rows + r] for row r = threadIdx.x < rows, in a fixed
+// order.  Many slices (thin row tiles) are first added in groups of 8 in parallel (into
+// red2), so no thread runs a long dependent chain of LDS reads.  Every thread calls it.
+__device__ __forceinline__ double slice_sum(const double *red, double *red2, int nsl, int rows) {
+    const int t = threadIdx.x;
+    double y = 0.0;
+    if (nsl <= 16) {
+        if (t < rows)
+            for (int s2 = 0; s2 < nsl; ++s2) y += red[s2 * rows + t];
+        return y;
+    }
+    const int ng = (nsl + 7) / 8;   // ng * rows <= NT / 8 + rows
+    if (t < ng * rows) {
+        const int g = t / rows, r = t % rows;
+        const int s1 = min(nsl, g * 8 + 8);
+        double z = 0.0;
+        for (int s2 = g * 8; s2 < s1; ++s2) z += red[s2 * rows + r];
+        red2[g * rows + r] = z;
+    }
+    __syncthreads();
+    if (t < rows)
+        for (int g = 0; g < ng; ++g) y += red2[g * rows + t];
+    return y;
+}
+
 // =======================================================================================
 // level kernels (upward: w3 = X d, h = [h1; h2] + U d; downward: u3 = S u12 + w3)
 // =======================================================================================
@@ -177,9 +202,8 @@ __device__ __forceinline__ void level_body(const LevelArgs &a, int blk, unsigned
             red[sl * rows + row] = (double)y;
         }
         __syncthreads();
+        const double y = slice_sum(red, red + NT, nsl, rows);
         if (t < rows) {
-            double y = 0.0;
-            for (int s2 = 0; s2 < nsl; ++s2) y += red[s2 * rows + t];
             if (UP) {
                 if (myrow < a.n3) a.w3[(int64_t)node * a.n3 + myrow] = y;
                 else if (!a.root && myrow < a.n3 + a.n12) a.h[(int64_t)node * a.n12 + myrow - a.n3] = fin + y;
@@ -227,7 +251,7 @@ __device__ __forceinline__ void level_body(const LevelArgs &a, int blk, unsigned
 template <typename T, bool UP>
 __global__ __launch_bounds__(NT) void k_level(LevelArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[NT];
+    __shared__ double red[NT + 64];
     __shared__ int s_last;
     level_body<T, UP>(a, blockIdx.x, smem, red, &s_last);
 }
@@ -237,7 +261,7 @@ __global__ __launch_bounds__(NT) void k_level(LevelArgs a) {
 template <typename T, bool UP>
 __global__ __launch_bounds__(NT) void k_level_group(const LevelArgs *args, const int *base, int n) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[NT];
+    __shared__ double red[NT + 64];
     __shared__ int s_last;
     const int w = blockIdx.x;
     int lo = 0, hi = n - 1;
@@ -342,9 +366,8 @@ __device__ __forceinline__ void level_sys_body(const LevelSysArgs &A, int blk, u
                 red[sl * rows + row] = y;
             }
             __syncthreads();
+            const double y = slice_sum(red, red + NT, nsl, rows);
             if (t < rows) {
-                double y = 0.0;
-                for (int s2 = 0; s2 < nsl; ++s2) y += red[s2 * rows + t];
                 if (UP) {
                     if (myrow < a.n3) ac.w3[(int64_t)node * a.n3 + myrow] = y;
                     else if (!a.root && myrow < a.n3 + a.n12) ac.h[(int64_t)node * a.n12 + myrow - a.n3] = fin[c] + y;
@@ -402,7 +425,7 @@ __device__ __forceinline__ void level_sys_body(const LevelSysArgs &A, int blk, u
 template <bool UP>
 __global__ __launch_bounds__(NT) void k_level_sys(LevelSysArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[NT];
+    __shared__ double red[NT + 64];
     __shared__ int s_last;
     level_sys_body<UP>(a, blockIdx.x, smem, red, &s_last);
 }
@@ -792,15 +815,12 @@ __device__ __forceinline__ void root_body(const LevelArgs &up, const LevelArgs &
     }
     red[t] = y1;
     __syncthreads();
-    double w3 = 0.0;
-    if (t < rows)
-        for (int s2 = 0; s2 < nsl1; ++s2) w3 += red[s2 * rows + t];
+    const double w3 = slice_sum(red, red + NT, nsl1, rows);
     __syncthreads();
     red[t] = y2;
     __syncthreads();
+    const double su = slice_sum(red, red + NT, nsl2, rows);
     if (t < rows && myrow < dn.n3) {
-        double su = 0.0;
-        for (int s2 = 0; s2 < nsl2; ++s2) su += red[s2 * rows + t];
         const double u3 = su + w3;
         dn.ubc[ia] = u3;
         dn.ubc[ib] = u3;
@@ -810,7 +830,7 @@ __device__ __forceinline__ void root_body(const LevelArgs &up, const LevelArgs &
 template <typename T>
 __global__ __launch_bounds__(NT) void k_root(LevelArgs up, LevelArgs dn) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[NT];
+    __shared__ double red[NT + 64];
     root_body<T>(up, dn, blockIdx.x, smem, red);
 }
 
@@ -818,7 +838,7 @@ template <typename T>
 __global__ __launch_bounds__(NT) void k_root_group(const LevelArgs *ups, const LevelArgs *dns, const int *base,
                                                    int n) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[NT];
+    __shared__ double red[NT + 64];
     const int w = blockIdx.x;
     int lo = 0, hi = n - 1;
     while (lo < hi) {
@@ -889,15 +909,12 @@ __device__ __forceinline__ void root_sys_body(const LevelSysArgs &U, const Level
             for (int gg = sl; gg < dn.pn.G; gg += nsl2) y2 += part2[c * pst2 + gg * rows + row];
         red[t] = y1;
         __syncthreads();
-        double w3 = 0.0;
-        if (t < rows)
-            for (int s2 = 0; s2 < nsl1; ++s2) w3 += red[s2 * rows + t];
+        const double w3 = slice_sum(red, red + NT, nsl1, rows);
         __syncthreads();
         red[t] = y2;
         __syncthreads();
+        const double su = slice_sum(red, red + NT, nsl2, rows);
         if (t < rows && myrow < dn.n3) {
-            double su = 0.0;
-            for (int s2 = 0; s2 < nsl2; ++s2) su += red[s2 * rows + t];
             const double u3 = su + w3;
             Dn.c[c].ubc[ia] = u3;
             Dn.c[c].ubc[ib] = u3;
@@ -908,7 +925,7 @@ __device__ __forceinline__ void root_sys_body(const LevelSysArgs &U, const Level
 
 __global__ __launch_bounds__(NT) void k_root_sys(LevelSysArgs up, LevelSysArgs dn) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[NT];
+    __shared__ double red[NT + 64];
     root_sys_body(up, dn, blockIdx.x, smem, red);
 }
 
