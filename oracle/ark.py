@@ -75,6 +75,48 @@ def ark436l2sa():
     return {"s": s, "gamma": g, "A": A, "b": b, "Ahat": Ah, "bhat": list(b), "c": c}
 
 
+def ark548l2sa():
+    """ARK5(4)8L[2]SA (Kennedy & Carpenter 2003), the fifth-order pair Sec. 3 names next to
+    ARK4(3)6L[2]SA and Sec. 5.4 uses for the rotating flow, as exact rationals: ESDIRK with
+    an explicit first stage, a_ii = 41/200, last row equal to b; the ERK part shares c and b;
+    a_i2 = 0 in both parts for i >= 4."""
+    s = 8
+    A = [[Fr(0)] * s for _ in range(s)]
+    Ah = [[Fr(0)] * s for _ in range(s)]
+    g = Fr(41, 200)
+    A[1][0] = g
+    A[2][:2] = [Fr(41, 400), Fr(-567603406766, 11931857230679)]
+    A[3][:3] = [Fr(683785636431, 9252920307686), Fr(0), Fr(-110385047103, 1367015193373)]
+    A[4][:4] = [Fr(3016520224154, 10081342136671), Fr(0), Fr(30586259806659, 12414158314087),
+                Fr(-22760509404356, 11113319521817)]
+    A[5][:5] = [Fr(218866479029, 1489978393911), Fr(0), Fr(638256894668, 5436446318841),
+                Fr(-1179710474555, 5321154724896), Fr(-60928119172, 8023461067671)]
+    A[6][:6] = [Fr(1020004230633, 5715676835656), Fr(0), Fr(25762820946817, 25263940353407),
+                Fr(-2161375909145, 9755907335909), Fr(-211217309593, 5846859502534),
+                Fr(-4269925059573, 7827059040749)]
+    b = [Fr(-872700587467, 9133579230613), Fr(0), Fr(0), Fr(22348218063261, 9555858737531),
+         Fr(-1143369518992, 8141816002931), Fr(-39379526789629, 19018526304540),
+         Fr(32727382324388, 42900044865799), g]
+    A[7][:7] = b[:7]
+    for i in range(1, s):
+        A[i][i] = g
+    Ah[1][0] = Fr(41, 100)
+    Ah[2][:2] = [Fr(367902744464, 2072280473677), Fr(677623207551, 8224143866563)]
+    Ah[3][:3] = [Fr(1268023523408, 10340822734521), Fr(0), Fr(1029933939417, 13636558850479)]
+    Ah[4][:4] = [Fr(14463281900351, 6315353703477), Fr(0), Fr(66114435211212, 5879490589093),
+                 Fr(-54053170152839, 4284798021562)]
+    Ah[5][:5] = [Fr(14090043504691, 34967701212078), Fr(0), Fr(15191511035443, 11219624916014),
+                 Fr(-18461159152457, 12425892160975), Fr(-281667163811, 9011619295870)]
+    Ah[6][:6] = [Fr(19230459214898, 13134317526959), Fr(0), Fr(21275331358303, 2942455364971),
+                 Fr(-38145345988419, 4862620318723), Fr(-1, 8), Fr(-1, 8)]
+    Ah[7][:7] = [Fr(-19977161125411, 11928030595625), Fr(0), Fr(-40795976796054, 6384907823539),
+                 Fr(177454434618887, 12078138498510), Fr(782672205425, 8267701900261),
+                 Fr(-69563011059811, 9646580694205), Fr(7356628210526, 4942186776405)]
+    c = [Fr(0), Fr(41, 100), Fr(2935347310677, 11292855782101), Fr(1426016391358, 7196633302097),
+         Fr(23, 25), Fr(6, 25), Fr(3, 5), Fr(1)]
+    return {"s": s, "gamma": g, "A": A, "b": b, "Ahat": Ah, "bhat": list(b), "c": c}
+
+
 def tableau_float(tab):
     f = lambda M: np.array([[float(x) for x in row] for row in M])
     return {"s": tab["s"], "gamma": float(tab["gamma"]), "A": f(tab["A"]), "Ahat": f(tab["Ahat"]),
