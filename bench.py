@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--no-nls", action="store_true")
     ap.add_argument("--nls-steps", type=int, default=10)
     ap.add_argument("--heat-steps", type=int, default=20)
+    ap.add_argument("--no-ark5", action="store_true")
+    ap.add_argument("--ark5-steps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-stage-solves", type=int, default=3)
     ap.add_argument("--workload", default="allen_cahn", choices=["allen_cahn", "batched", "serving"],
@@ -302,6 +304,95 @@ def nls_leg(args, torch, hps, workloads, n, p, tab, dev, uniform, steps, tiles=0
     return out
 
 
+def ark5_leg(args, torch, hps, workloads, g, x, y, n_int, coefs, u0, dt, tiles, dev):
+    """The headline Allen-Cahn workload stepped with the fifth-order pair ARK5(4)8L[2]SA
+    (Sec. 3): its own operator (gamma = 41/200), 7 stage solves per step."""
+    from paper_2306_02526_amd.tableau import ark548l2sa
+    tab = ark548l2sa()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = hps.hps_build(g, coefs, tab["gamma"] * dt, hps.HPS_FP64 | tiles)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    ctx = hps.ark_create(op, tab, dt, g=workloads.AllenCahn.gpoly)
+    u = u0.clone()
+    for k in range(args.warmup):
+        hps.ark_step(ctx, k * dt, u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.ark5_steps):
+        hps.ark_step(ctx, (args.warmup + k) * dt, u)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    hps.hps_profile_enable(op, True)
+    for k in range(2):
+        hps.ark_step(ctx, k * dt, u)
+    torch.cuda.synchronize()
+    prof = hps.hps_profile_read(op)
+    hps.hps_profile_enable(op, False)
+    finite = bool(torch.isfinite(u).all())
+    op.free()
+    stages = tab["s"] - 1
+    return {"tableau": "ARK5(4)8L[2]SA", "stage_solves_per_step": stages,
+            "stage_solves_per_s": round(stages * args.ark5_steps / el, 1),
+            "ms_per_step": round(1e3 * el / args.ark5_steps, 3), "steps": args.ark5_steps, "dt": dt,
+            "build_s": round(build_s, 3), "finite": finite,
+            "kernels": {k: {"launches_per_step": v[0] // 2, "us_per_launch": round(1e3 * v[1] / v[0], 2)}
+                        for k, v in prof.items()}}
+
+
+def rotating_flow_leg(args, torch, hps, workloads, dev, n=32, p=18):
+    """The rotating-flow Burgers test of Sec. 5.4 run to its terminal time T = 1.5 with the
+    fifth-order pair ARK5(4)8L[2]SA, as the paper does: [-pi, pi]^2, eps = 0.005, no-slip
+    walls, dt = 0.01 (150 steps, 14 stage solves each).  The paper's 24 x 24 leaves of order
+    24 (528 nodes per direction) are not a power of two: 32 x 32 leaves of order 18 give 512.
+    Shared operators (L = eps Lap has constant coefficients).  Each velocity component obeys
+    a maximum principle (advection-diffusion with the velocity field), so max |u|, max |v|
+    at T must not exceed their initial values beyond the discretisation error."""
+    import numpy as np
+    from paper_2306_02526_amd.tableau import ark548l2sa
+    tab = ark548l2sa()
+    rot = workloads.BurgersRotating()
+    dt, T = 0.01, 1.5
+    steps = int(round(T / dt))
+    g = hps.make_grid(*rot.domain, n, n, p)
+    N, n_int, _, _ = hps.hps_num_nodes(g)
+    x, y = hps.hps_nodes(g)
+    co = dict(zip(("cxx", "cyy", "cx", "cy", "c0"), workloads.burgers_coeffs(rot.eps, n_int)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = hps.hps_build(g, {k: torch.tensor(v, device=dev) for k, v in co.items()}, tab["gamma"] * dt,
+                       hps.HPS_FP64 | hps.HPS_WIDE_TILES | hps.HPS_UNIFORM_COEFFS)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    cu, cv = hps.ark_create(op, tab, dt), hps.ark_create(op, tab, dt)
+    u0, v0 = rot.u0(x, y)
+    on = lambda a, b: np.abs(a - b) < 1e-13
+    x0, x1, y0, y1 = rot.domain
+    bd = (np.arange(N) >= n_int) & (on(x, x0) | on(x, x1) | on(y, y0) | on(y, y1))
+    u0[bd] = 0.0
+    v0[bd] = 0.0
+    u, v = torch.tensor(u0, device=dev), torch.tensor(v0, device=dev)
+    hps.ark_step_burgers(cu, cv, 0.0, u, v)   # step 1, untimed: its first call captures the step's graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(1, steps):
+        hps.ark_step_burgers(cu, cv, k * dt, u, v)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    um, vm = float(u.abs().max()), float(v.abs().max())
+    op.free()
+    stages = tab["s"] - 1
+    timed = steps - 1
+    return {"grid": f"{n}x{n}_p{p}", "tableau": "ARK5(4)8L[2]SA", "eps": rot.eps, "dt": dt, "T": T,
+            "steps": steps, "timed_steps": timed, "stage_solves_per_s": round(2 * stages * timed / el, 1),
+            "ms_per_step": round(1e3 * el / timed, 3), "run_to_T_s": round(el * steps / timed, 3),
+            "build_s": round(build_s, 3),
+            "max_abs_u": {"t0": float(np.abs(u0).max()), "T": um},
+            "max_abs_v": {"t0": float(np.abs(v0).max()), "T": vm},
+            "finite": bool(np.isfinite(um) and np.isfinite(vm))}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -457,6 +548,14 @@ def main():
                                                steps=args.nls_steps)
         log(f"nls: {nls}")
 
+    # ---- the fifth-order pair: the headline workload and the rotating flow to T = 1.5 ----
+    ark5 = None
+    if not args.no_ark5:
+        ark5 = ark5_leg(args, torch, hps, workloads, g, x, y, n_int, coefs, u0, dt, tiles, dev)
+        log(f"ark5: {ark5}")
+        ark5["rotating_flow"] = rotating_flow_leg(args, torch, hps, workloads, dev)
+        log(f"ark5 rotating flow: {ark5['rotating_flow']}")
+
     # ---- FP32 operators + FP64 iterative refinement, same steps ----
     fp32 = None
     if not args.no_fp32:
@@ -535,6 +634,7 @@ def main():
         "burgers_system": burgers,
         "heat_constant_coefficients": heat,
         "nls_complex": nls,
+        "ark5": ark5,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
