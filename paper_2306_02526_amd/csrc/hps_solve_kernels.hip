@@ -22,6 +22,10 @@ namespace hps {
 constexpr int PF = 16;   // operator loads issued before the input gather (level panels keep S <= 16,
                          // so a workgroup's whole operator block is in flight during the gather)
 constexpr int UNR = 8;   // operator loads in flight in the streaming loop
+// Level panels with at most PF_SMALL columns per lane (the bottom levels: many small nodes,
+// more workgroups than stay resident at the full kernel's register use) take a variant with
+// fewer load registers, so that 8 waves per SIMD fit and the grid runs in one round.
+constexpr int PF_SMALL = 4;
 
 // L u at interior node k of the tile: cxx u_xx + cyy u_yy + cx u_x + cy u_y + c0 u (eq. 3
 // written for L, c12 = 0), derivatives along the tile row / column through the node.
@@ -123,7 +127,7 @@ __device__ __forceinline__ double down_input(const LevelArgs &a, const double *d
 
 
 // One (node, row tile, column chunk) of a level product: workgroup-local index blk.
-template <typename T, bool UP>
+template <typename T, bool UP, int PFX = PF, int UNRX = UNR>
 __device__ __forceinline__ void level_body(const LevelArgs &a, int blk, unsigned char *smem, double *red,
                                            int *s_last) {
     constexpr int VW = 16 / sizeof(T);
@@ -135,7 +139,7 @@ __device__ __forceinline__ void level_body(const LevelArgs &a, int blk, unsigned
     Carve cv{smem};
     T *xs = cv.take<T>(SG);
     T *part = cv.take<T>((size_t)a.pn.G * a.pn.rp * VW);
-    PanelStream<T, PF, UNR> ps;
+    PanelStream<T, PFX, UNRX> ps;
     ps.start(reinterpret_cast<const T *>(a.pn.data) + (int64_t)node * a.pn.node_elems +
                  (int64_t)(tile * kch + chunk) * a.pn.tile_elems,
              a.pn.rp, a.pn.G, a.pn.S);
@@ -254,6 +258,21 @@ __global__ __launch_bounds__(NT) void k_level(LevelArgs a) {
     __shared__ double red[NT + 64];
     __shared__ int s_last;
     level_body<T, UP>(a, blockIdx.x, smem, red, &s_last);
+}
+
+// Panels with S <= PF_SMALL: the same product with fewer registers (8 waves per SIMD).
+template <typename T, bool UP>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_level_small(LevelArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT + 64];
+    __shared__ int s_last;
+    level_body<T, UP, PF_SMALL, PF_SMALL>(a, blockIdx.x, smem, red, &s_last);
+}
+
+template <typename T, bool UP>
+static void launch_level(const LevelArgs &a, unsigned nb, size_t lds, hipStream_t st) {
+    if (a.pn.S <= PF_SMALL) hipLaunchKernelGGL((k_level_small<T, UP>), dim3(nb), dim3(NT), lds, st, a);
+    else hipLaunchKernelGGL((k_level<T, UP>), dim3(nb), dim3(NT), lds, st, a);
 }
 
 // One level product of several operators in one launch: workgroup w belongs to entry e,
@@ -957,8 +976,8 @@ int launch_levels(const hps_op *op, bool fp32, const double *jump, const double 
             a.r3 = jump;
             const Panel &pn = fp32 ? op->lv[l].xu32 : op->lv[l].xu64;
             const unsigned nb = (unsigned)(op->lv[l].nodes * a.pn.ntile * a.pn.kch);
-            if (fp32) hipLaunchKernelGGL((k_level<float, true>), dim3(nb), dim3(NT), level_lds(pn), st, a);
-            else hipLaunchKernelGGL((k_level<double, true>), dim3(nb), dim3(NT), level_lds(pn), st, a);
+            if (fp32) launch_level<float, true>(a, nb, level_lds(pn), st);
+            else launch_level<double, true>(a, nb, level_lds(pn), st);
             HPS_LAUNCHED();
         }
     }
@@ -985,8 +1004,8 @@ int launch_levels(const hps_op *op, bool fp32, const double *jump, const double 
         a.dir = dirichlet;
         const Panel &pn = fp32 ? op->lv[l].s32 : op->lv[l].s64;
         const unsigned nb = (unsigned)(op->lv[l].nodes * a.pn.ntile * a.pn.kch);
-        if (fp32) hipLaunchKernelGGL((k_level<float, false>), dim3(nb), dim3(NT), level_lds(pn), st, a);
-        else hipLaunchKernelGGL((k_level<double, false>), dim3(nb), dim3(NT), level_lds(pn), st, a);
+        if (fp32) launch_level<float, false>(a, nb, level_lds(pn), st);
+        else launch_level<double, false>(a, nb, level_lds(pn), st);
         HPS_LAUNCHED();
     }
     return HPS_OK;
