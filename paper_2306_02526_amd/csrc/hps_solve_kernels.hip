@@ -574,37 +574,70 @@ struct LineArgs {
     const double *jump;       // flux_alpha - flux_beta per interface node (interface order) or null
 };
 
+// The arithmetic of one line system, shared by both line kernels so that they give the
+// same bits: right-hand side of equation k, forward elimination, back substitution.
+__device__ __forceinline__ double line_rhs(double fl, double fh, const double *jump, int64_t jidx, int k, int n,
+                                           double lower, double upper, double e0, double en) {
+    double r = fl - fh;
+    if (jump) r += jump[jidx];
+    if (k == 1) r -= lower * e0;
+    if (k == n - 1) r -= upper * en;
+    return r;
+}
+
+__device__ __forceinline__ double line_fwd(double r, int k, double lower, double dprev, double id) {
+    return (r - (k > 1 ? lower * dprev : 0.0)) * id;
+}
+
+__device__ __forceinline__ double line_bwd(double dv, double cv, double enext) { return dv - cv * enext; }
+
+// Geometry of line system t: orientation, length n, strides of u, flux parts and jumps.
+struct LineGeo {
+    int n;
+    int64_t u0, ustride, l0, lstride, j0, jstride;
+    int elo, ehi;
+};
+
+__device__ __forceinline__ bool line_geo(const LeafGeo &g, int t, LineGeo &L) {
+    const int q = g.q;
+    const int nvs = g.n2 * q;   // systems along horizontal rows (vertical-edge unknowns)
+    const int nhs = g.n1 * q;
+    if (t >= nvs + nhs) return false;
+    const bool vert = t < nvs;
+    L.n = vert ? g.n1 : g.n2;
+    if (L.n < 2) return false;
+    const int line = vert ? t / q : (t - nvs) / q;   // leaf row j (vert) or column i (horz)
+    const int m0 = (vert ? t : t - nvs) % q;          // local node index along the edge
+    L.ustride = vert ? (int64_t)g.n2 * q : (int64_t)g.n1 * q;
+    L.u0 = vert ? g.n_int + (int64_t)line * q + m0 : g.n_int + g.n_vert + (int64_t)line * q + m0;
+    // leaf number k along the line, flux part on side e
+    L.lstride = vert ? 4 * q : (int64_t)g.n1 * 4 * q;
+    L.l0 = (vert ? (int64_t)line * g.n1 * 4 * q : (int64_t)line * 4 * q) + m0;
+    L.elo = vert ? 0 : 2;   // left/right or bottom/top sides
+    L.ehi = vert ? 1 : 3;
+    // interface index of the node on grid line k: vertical edges first, by line k-1
+    L.j0 = vert ? (int64_t)line * q + m0 : (int64_t)(g.n1 - 1) * g.n2 * q + (int64_t)line * q + m0;
+    L.jstride = vert ? (int64_t)g.n2 * q : (int64_t)g.n1 * q;
+    return true;
+}
+
 // One thread per grid line; the recursion carries d_{k-1} and e_{k+1} in registers and
 // its inputs are loaded CH at a time ahead of use, so no load waits on a store.
 __device__ __forceinline__ void line_body(const LineArgs &a, int t) {
     constexpr int CH = 8;
     const LeafGeo &g = a.geo;
     const int q = g.q, p = g.p;
-    const int nvs = g.n2 * q;   // systems along horizontal rows (vertical-edge unknowns)
-    const int nhs = g.n1 * q;
-    if (t >= nvs + nhs) return;
-    const bool vert = t < nvs;
-    const int n = vert ? g.n1 : g.n2;
-    if (n < 2) return;
-    const int line = vert ? t / q : (t - nvs) / q;   // leaf row j (vert) or column i (horz)
-    const int m0 = (vert ? t : t - nvs) % q;          // local node index along the edge
+    LineGeo L;
+    if (!line_geo(g, t, L)) return;
+    (void)q;
+    const int n = L.n;
     const double *__restrict__ fpart = a.fpart;
     const double *__restrict__ cp = a.cp;
     const double *__restrict__ inv_den = a.inv_den;
     double *__restrict__ u = a.u;
-    const int64_t ustride = vert ? (int64_t)g.n2 * q : (int64_t)g.n1 * q;
-    const int64_t u0 = vert ? g.n_int + (int64_t)line * q + m0 : g.n_int + g.n_vert + (int64_t)line * q + m0;
-    // leaf number k along the line, flux part on side e
-    const int64_t lstride = vert ? 4 * q : (int64_t)g.n1 * 4 * q;
-    const int64_t l0 = (vert ? (int64_t)line * g.n1 * 4 * q : (int64_t)line * 4 * q) + m0;
-    const int elo = vert ? 0 : 2, ehi = vert ? 1 : 3;   // left/right or bottom/top sides
-    // interface index of the node on grid line k: vertical edges first, by line k-1
-    const int64_t j0 = vert ? (int64_t)line * q + m0 : (int64_t)(g.n1 - 1) * g.n2 * q + (int64_t)line * q + m0;
-    const int64_t jstride = vert ? (int64_t)g.n2 * q : (int64_t)g.n1 * q;
-    const double *__restrict__ jump = a.jump;
     const double lower = a.D[(p - 1) * p + 0];
     const double upper = -a.D[0 * p + (p - 1)];
-    const double e0 = u[u0], en = u[u0 + (int64_t)n * ustride];
+    const double e0 = u[L.u0], en = u[L.u0 + (int64_t)n * L.ustride];
     double dprev = 0.0;
     for (int k0 = 1; k0 < n; k0 += CH) {
         double fl[CH], fh[CH], id[CH];
@@ -612,8 +645,8 @@ __device__ __forceinline__ void line_body(const LineArgs &a, int t) {
         for (int c = 0; c < CH; ++c) {
             const int k = k0 + c;
             if (k < n) {
-                fl[c] = fpart[l0 + k * lstride + elo * q];
-                fh[c] = fpart[l0 + (k - 1) * lstride + ehi * q];
+                fl[c] = fpart[L.l0 + k * L.lstride + L.elo * g.q];
+                fh[c] = fpart[L.l0 + (k - 1) * L.lstride + L.ehi * g.q];
                 id[c] = inv_den[k];
             }
         }
@@ -621,12 +654,10 @@ __device__ __forceinline__ void line_body(const LineArgs &a, int t) {
         for (int c = 0; c < CH; ++c) {
             const int k = k0 + c;
             if (k < n) {
-                double r = fl[c] - fh[c];
-                if (jump) r += jump[j0 + (int64_t)(k - 1) * jstride];
-                if (k == 1) r -= lower * e0;
-                if (k == n - 1) r -= upper * en;
-                const double d = (r - (k > 1 ? lower * dprev : 0.0)) * id[c];
-                u[u0 + k * ustride] = d;
+                const double r = line_rhs(fl[c], fh[c], a.jump, L.j0 + (int64_t)(k - 1) * L.jstride, k, n, lower,
+                                          upper, e0, en);
+                const double d = line_fwd(r, k, lower, dprev, id[c]);
+                u[L.u0 + k * L.ustride] = d;
                 dprev = d;
             }
         }
@@ -638,7 +669,7 @@ __device__ __forceinline__ void line_body(const LineArgs &a, int t) {
         for (int c = 0; c < CH; ++c) {
             const int k = k0 - c;
             if (k >= 1) {
-                dv[c] = u[u0 + k * ustride];
+                dv[c] = u[L.u0 + k * L.ustride];
                 cv[c] = cp[k];
             }
         }
@@ -646,10 +677,60 @@ __device__ __forceinline__ void line_body(const LineArgs &a, int t) {
         for (int c = 0; c < CH; ++c) {
             const int k = k0 - c;
             if (k >= 1) {
-                enext = dv[c] - cv[c] * enext;
-                u[u0 + k * ustride] = enext;
+                enext = line_bwd(dv[c], cv[c], enext);
+                u[L.u0 + k * L.ustride] = enext;
             }
         }
+    }
+}
+
+// LINES lines per workgroup of LINE_NT threads: all waves first load the lines' right-hand
+// sides (every equation of every line at once, no dependent chain) into LDS, then one
+// thread per line runs the recursion out of LDS and writes only the final values.
+constexpr int LINES = 64;
+constexpr int LINE_NT = 256;
+
+__global__ __launch_bounds__(LINE_NT) void k_interface_lines_lds(LineArgs a, int nmax) {
+    extern __shared__ __align__(16) double lsm[];
+    double *rr = lsm;                                  // [nmax][LINES]: r_k, then d_k
+    double *sid = lsm + (size_t)nmax * LINES;          // [nmax]: 1 / den_k
+    double *scp = sid + nmax;                          // [nmax]: cp_k
+    const LeafGeo &g = a.geo;
+    const int p = g.p;
+    const int lane = threadIdx.x % LINES, wv = threadIdx.x / LINES;
+    constexpr int NW = LINE_NT / LINES;
+    const int t = blockIdx.x * LINES + lane;
+    LineGeo L;
+    const bool on = line_geo(g, t, L);
+    const double lower = a.D[(p - 1) * p + 0];
+    const double upper = -a.D[0 * p + (p - 1)];
+    for (int k = threadIdx.x; k < nmax; k += LINE_NT) {
+        sid[k] = a.inv_den[k];
+        scp[k] = a.cp[k];
+    }
+    double e0 = 0.0, en = 0.0;
+    if (on) {
+        e0 = a.u[L.u0];
+        en = a.u[L.u0 + (int64_t)L.n * L.ustride];
+        for (int k = 1 + wv; k < L.n; k += NW)
+            rr[k * LINES + lane] = line_rhs(a.fpart[L.l0 + k * L.lstride + L.elo * g.q],
+                                            a.fpart[L.l0 + (k - 1) * L.lstride + L.ehi * g.q], a.jump,
+                                            L.j0 + (int64_t)(k - 1) * L.jstride, k, L.n, lower, upper, e0, en);
+    }
+    __syncthreads();
+    if (wv != 0 || !on) return;
+    const int n = L.n;
+    double dprev = 0.0;
+    for (int k = 1; k < n; ++k) {
+        const double d = line_fwd(rr[k * LINES + lane], k, lower, dprev, sid[k]);
+        rr[k * LINES + lane] = d;
+        dprev = d;
+    }
+    double enext = dprev;   // e_{n-1} = d_{n-1}
+    a.u[L.u0 + (int64_t)(n - 1) * L.ustride] = enext;
+    for (int k = n - 2; k >= 1; --k) {
+        enext = line_bwd(rr[k * LINES + lane], scp[k], enext);
+        a.u[L.u0 + k * L.ustride] = enext;
     }
 }
 
@@ -1222,7 +1303,12 @@ int launch_interface_lines(const hps_op *op, double *u, const double *f_end, hip
     la.inv_den = op->tri_cp + op->tri_stride;
     la.jump = jump;
     const int nsys = op->grid.n2 * op->q + op->grid.n1 * op->q;
-    hipLaunchKernelGGL(k_interface_lines, dim3(nblk(nsys, 64)), dim3(64), 0, st, la);
+    const int nmax = std::max(op->grid.n1, op->grid.n2);
+    const size_t lds = ((size_t)nmax * LINES + 2 * (size_t)nmax) * sizeof(double);
+    if (lds <= sys_lds_limit())
+        hipLaunchKernelGGL(k_interface_lines_lds, dim3(nblk(nsys, LINES)), dim3(LINE_NT), lds, st, la, nmax);
+    else   // lines too long to stage in LDS: one thread per line, inputs read from memory
+        hipLaunchKernelGGL(k_interface_lines, dim3(nblk(nsys, 64)), dim3(64), 0, st, la);
     HPS_LAUNCHED();
     return HPS_OK;
 }
