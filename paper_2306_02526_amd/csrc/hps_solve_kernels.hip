@@ -626,10 +626,9 @@ __device__ __forceinline__ bool line_geo(const LeafGeo &g, int t, LineGeo &L) {
 __device__ __forceinline__ void line_body(const LineArgs &a, int t) {
     constexpr int CH = 8;
     const LeafGeo &g = a.geo;
-    const int q = g.q, p = g.p;
+    const int p = g.p;
     LineGeo L;
     if (!line_geo(g, t, L)) return;
-    (void)q;
     const int n = L.n;
     const double *__restrict__ fpart = a.fpart;
     const double *__restrict__ cp = a.cp;
