@@ -8,10 +8,9 @@ import re
 import numpy as np
 import pytest
 
-from oracle.ark import ark436l2sa, tableau_float
+from oracle.ark import tableau_float
 from oracle.grid import Grid
 from paper_2306_02526_amd import hps
-from paper_2306_02526_amd.tableau import ark436l2sa as product_tableau
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -90,9 +89,14 @@ def test_unknown_build_flags_are_rejected(flags):
     assert b"flags" in L.hps_last_error()
 
 
-def test_product_tableau_equals_oracle_tableau():
-    a = product_tableau()
-    b = tableau_float(ark436l2sa())
+@pytest.mark.parametrize("name", ["ark436l2sa", "ark548l2sa"])
+def test_product_tableau_equals_oracle_tableau(name):
+    """The product's tableaux (written separately from the oracle's) equal the oracle's
+    pinned ones in every double."""
+    import oracle.ark as oark
+    from paper_2306_02526_amd import tableau as ptab
+    a = getattr(ptab, name)()
+    b = tableau_float(getattr(oark, name)())
     for k in ("A", "Ahat", "b", "bhat", "c"):
         assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
     assert a["s"] == b["s"] and a["gamma"] == b["gamma"]
