@@ -603,7 +603,7 @@ def main():
         log(f"cpu oracle: {cpu}")
 
     out = {
-        "metric": "stage-solves/s at N~1M (FP64; FP32+IR reported alongside); p50/p99 solve latency",
+        "metric": "stage-solves/s at N\u22481M (FP64 vs FP32+IR @1e-10 rel); p50/p99 solve latency",
         "value": round(value, 2),
         "unit": "stage-solves/s",
         "n_gpus": 1,
