@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstdint>
+#include <cstdlib>
 
 #include "hps_device.h"
 
@@ -349,6 +350,148 @@ __global__ void k_gj_unpermute(const double *W, double *out, int n, int nb, cons
     out[b * nn + (int64_t)o[j] * n + k] = W[b * nn + (int64_t)j * n + o[k]];
 }
 
+// ---- the same inversion with one matrix per workgroup, held in registers ---------------
+// A GJ_TR x GJ_TC grid of threads holds the n x n matrix: thread (r, c) owns rows
+// r + GJ_TR a (a < RA) and columns c + GJ_TC b (b < CB), n <= GJ_TR RA and n <= GJ_TC CB, so
+// every step touches the matrix in registers instead of streaming the whole batch through
+// memory twice per step (512 threads: up to 256 registers per lane, 13 x 7 doubles each
+// at n = 196).  Each step performs
+// exactly the operations of k_gj_pivot / k_gj_update (same pivot rule, same products and
+// fused multiply-adds), so the result is bitwise that of the batched kernels; the
+// unpermutation is done on the way out.
+constexpr int GJ_TR = 16, GJ_TC = 32;   // thread grid: rows x columns
+constexpr int GJ_NT = GJ_TR * GJ_TC;
+
+template <int RA, int CB>
+__global__ __launch_bounds__(GJ_NT) void k_gj_reg(const double *W, double *out, int n, int *sing) {
+    extern __shared__ __align__(16) unsigned char gsm[];
+    double *colbuf = reinterpret_cast<double *>(gsm);        // [n]
+    double *rowbuf = colbuf + n;                              // [n]
+    int *order = reinterpret_cast<int *>(rowbuf + n);         // [n] pivot row of step k
+    int *pinv = order + n;                                    // [n] step of pivot row i
+    unsigned char *used = reinterpret_cast<unsigned char *>(pinv + n);   // [n]
+    __shared__ int s_pr;
+    __shared__ double s_ip;
+    const int t = threadIdx.x, b = blockIdx.x;
+    const int r = t % GJ_TR, c = t / GJ_TR;
+    const int64_t nn = (int64_t)n * n;
+    const double *Wb = W + b * nn;
+    double w[RA][CB];   // w[a][bb] = W[r + GJ_TR a][c + GJ_TC bb]
+#pragma unroll
+    for (int a = 0; a < RA; ++a)
+#pragma unroll
+        for (int bb = 0; bb < CB; ++bb) {
+            const int i = r + GJ_TR * a, j = c + GJ_TC * bb;
+            w[a][bb] = (i < n && j < n) ? Wb[(int64_t)j * n + i] : 0.0;
+        }
+    for (int i = t; i < n; i += GJ_NT) {
+        used[i] = 0;
+        order[i] = i;   // complete permutations even if a singular step repeats a row
+        pinv[i] = i;
+    }
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
+        // column k of every row (thread column c == k % GJ_TC holds it)
+        if (c == k % GJ_TC) {
+            const int bk = k / GJ_TC;
+#pragma unroll
+            for (int bb = 0; bb < CB; ++bb)
+                if (bb == bk)
+#pragma unroll
+                    for (int a = 0; a < RA; ++a) {
+                        const int i = r + GJ_TR * a;
+                        if (i < n) colbuf[i] = w[a][bb];
+                    }
+        }
+        __syncthreads();
+        if (t < 64) {
+            // unused row with the largest |W[i][k]|, ties to the smallest i
+            double best = -1.0;
+            int besti = n;
+            for (int i = t; i < n; i += 64) {
+                if (!used[i]) {
+                    const double v = fabs(colbuf[i]);
+                    if (v > best || (v == best && i < besti)) {
+                        best = v;
+                        besti = i;
+                    }
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double v2 = __shfl_xor(best, off);
+                const int i2 = __shfl_xor(besti, off);
+                if (v2 > best || (v2 == best && i2 < besti)) {
+                    best = v2;
+                    besti = i2;
+                }
+            }
+            if (t == 0) {
+                int pr = besti;
+                double piv = pr < n ? colbuf[pr] : 0.0;
+                if (pr >= n || piv == 0.0 || !isfinite(piv)) {
+                    atomicExch(sing, 1);
+                    if (pr >= n) pr = 0;
+                    piv = 1.0;
+                }
+                used[pr] = 1;
+                order[k] = pr;
+                pinv[pr] = k;
+                s_pr = pr;
+                s_ip = 1.0 / piv;
+            }
+        }
+        __syncthreads();
+        const int pr = s_pr;
+        const double ip = s_ip;
+        // the pivot row, scaled (thread row r == pr % GJ_TR holds it)
+        if (r == pr % GJ_TR) {
+            const int ap = pr / GJ_TR;
+#pragma unroll
+            for (int a = 0; a < RA; ++a)
+                if (a == ap)
+#pragma unroll
+                    for (int bb = 0; bb < CB; ++bb) {
+                        const int j = c + GJ_TC * bb;
+                        if (j < n) rowbuf[j] = (j == k) ? ip : w[a][bb] * ip;
+                    }
+        }
+        __syncthreads();
+        double cb[RA], rb[CB];
+#pragma unroll
+        for (int a = 0; a < RA; ++a) {
+            const int i = r + GJ_TR * a;
+            cb[a] = i < n ? colbuf[i] : 0.0;
+        }
+#pragma unroll
+        for (int bb = 0; bb < CB; ++bb) {
+            const int j = c + GJ_TC * bb;
+            rb[bb] = j < n ? rowbuf[j] : 0.0;
+        }
+        const double rbk = rowbuf[k];
+#pragma unroll
+        for (int a = 0; a < RA; ++a)
+#pragma unroll
+            for (int bb = 0; bb < CB; ++bb) {
+                const int i = r + GJ_TR * a, j = c + GJ_TC * bb;
+                if (i < n && j < n) {
+                    if (i == pr) w[a][bb] = rb[bb];
+                    else if (j == k) w[a][bb] = -cb[a] * rbk;
+                    else w[a][bb] = fma(-cb[a], rb[bb], w[a][bb]);
+                }
+            }
+        __syncthreads();
+    }
+    // inv(A)[k][order[j]] = W[order[k]][j]: element (i, j) goes to row pinv[i], column order[j]
+    double *ob = out + b * nn;
+#pragma unroll
+    for (int a = 0; a < RA; ++a)
+#pragma unroll
+        for (int bb = 0; bb < CB; ++bb) {
+            const int i = r + GJ_TR * a, j = c + GJ_TC * bb;
+            if (i < n && j < n) ob[(int64_t)order[j] * n + pinv[i]] = w[a][bb];
+        }
+}
+
 // ---- batched FP64 GEMM on the matrix cores ----------------------------------------------
 // C = alpha A B + beta C, column-major, 64x64 tile per workgroup, each wave a 32x32
 // sub-tile of 2x2 v_mfma_f64_16x16x4 blocks; K staged through LDS 16 at a time.
@@ -523,6 +666,20 @@ int launch_merge_gather(const Level &L, bool root, const double *Tc, double *M, 
 
 int gj_invert(double *W, double *out, int n, int nb, unsigned char *used, int *order,
               double *colbuf, double *rowbuf, int *sing, hipStream_t st) {
+    const size_t lds = (size_t)n * (2 * sizeof(double) + 2 * sizeof(int) + 1);
+    const char *env = getenv("HPS_GJ_REG");   // "0": always the batched kernels
+    const bool reg = !(env && env[0] == '0') && nb > 0 && n >= 1;
+#define HPS_GJ_REG_CASE(RA, CB)                                                           \
+    if (reg && n <= GJ_TR * (RA) && n <= GJ_TC * (CB)) {                                  \
+        hipLaunchKernelGGL((k_gj_reg<RA, CB>), dim3(nb), dim3(GJ_NT), lds, st, (const double *)W, out, n, sing); \
+        HPS_LAUNCHED();                                                                   \
+        return HPS_OK;                                                                    \
+    }
+    HPS_GJ_REG_CASE(2, 1)
+    HPS_GJ_REG_CASE(4, 2)
+    HPS_GJ_REG_CASE(8, 4)
+    HPS_GJ_REG_CASE(13, 7)
+#undef HPS_GJ_REG_CASE
     HPS_HIP(hipMemsetAsync(used, 0, (size_t)n * nb, st));
     const int64_t tot = (int64_t)n * n * nb;
     for (int k = 0; k < n; ++k) {

@@ -393,3 +393,24 @@ def test_graph_replay_equals_eager_steps(torch, monkeypatch):
         hps.ark_step(ctx_e, n * dt, ue)
         torch.cuda.synchronize()
         assert torch.equal(ug, ue), n
+
+
+@pytest.mark.parametrize("n1,n2,p", [(8, 8, 10), (16, 16, 16), (4, 8, 12), (2, 2, 24), (32, 8, 7)],
+                         ids=["8x8_p10", "16x16_p16", "4x8_p12", "2x2_p24", "32x8_p7"])
+def test_register_gauss_jordan_equals_batched(torch, monkeypatch, n1, n2, p):
+    """The build inverts with one matrix per workgroup held in registers when it fits
+    (n <= 208) and with the batched kernels otherwise; both perform the same operations in
+    the same order, so operators built either way give bitwise equal solves."""
+    say(f"[build] register vs batched Gauss-Jordan, {n1}x{n2} p={p}")
+    rng = np.random.default_rng(n1 + 7 * p)
+    outs = []
+    for mode in ("0", "1"):
+        monkeypatch.setenv("HPS_GJ_REG", mode)
+        g, og, x, y, co, op = setup(torch, n1, n2, p, 2e-3)
+        if mode == "0":
+            body = torch.tensor(rng.standard_normal(og.n_int), device="cuda")
+            dirichlet = torch.tensor(rng.standard_normal(op.n_bdry), device="cuda")
+        outs.append(hps.hps_solve(op, body, dirichlet))
+        torch.cuda.synchronize()
+        op.free()
+    assert torch.equal(outs[0], outs[1])
