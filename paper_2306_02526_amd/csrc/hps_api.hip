@@ -594,20 +594,24 @@ static int build_impl(hps_op *op, const hps_coeffs *co, const hps_coeffs *co_im,
     };
     // ---- leaves (Sec. 2.1, eqs. 5-6) ----
     const int nl = op->nleaves;
+    // with uniform coefficients every leaf (and every node of a level) has the same
+    // operators: compute leaf 0 and node 0 of each level only, the ones the panels keep
+    op->build_one = uni;
+    const int nlb = uni ? 1 : nl;
     double *W, *Ainv, *S, *T;
-    TRY(tmp.get(&W, (int64_t)nl * q2 * q2));
-    TRY(tmp.get(&Ainv, (int64_t)nl * q2 * q2));
+    TRY(tmp.get(&W, (int64_t)nlb * q2 * q2));
+    TRY(tmp.get(&Ainv, (int64_t)nlb * q2 * q2));
     if (m == 2) TRY(launch_leaf_assemble_cx(op, W, st));
     else TRY(launch_leaf_assemble(op, W, st));
     {
         unsigned char *used; int *order; double *cb, *rb;
-        TRY(gj_scratch(q2, nl, &used, &order, &cb, &rb));
-        TRY(gj_invert(W, Ainv, q2, nl, used, order, cb, rb, sing, st));
+        TRY(gj_scratch(q2, nlb, &used, &order, &cb, &rb));
+        TRY(gj_invert(W, Ainv, q2, nlb, used, order, cb, rb, sing, st));
         tmp.release(used); tmp.release(order); tmp.release(cb); tmp.release(rb);
     }
     tmp.release(W);
-    TRY(tmp.get(&S, (int64_t)nl * q2 * nb4));
-    TRY(tmp.get(&T, (int64_t)nl * nb4 * nb4));
+    TRY(tmp.get(&S, (int64_t)nlb * q2 * nb4));
+    TRY(tmp.get(&T, (int64_t)nlb * nb4 * nb4));
     if (m == 2) {
         TRY(launch_leaf_S_cx(op, Ainv, S, st));
         TRY(launch_leaf_T_cx(op, S, T, st));
@@ -655,42 +659,44 @@ static int build_impl(hps_op *op, const hps_coeffs *co, const hps_coeffs *co_im,
         TRY(upload(op, &Lv.b2, H.b2, st));
         TRY(upload(op, &Lv.b3, H.b3, st));
         TRY(upload(op, &Lv.j3i, H.j3i, st));
-        const int n3 = Lv.n3, n12 = Lv.n12, nodes = Lv.nodes;
+        const int n3 = Lv.n3, n12 = Lv.n12, nbuilt = uni ? 1 : Lv.nodes;   // nodes whose operators are built
         const int64_t s33 = (int64_t)n3 * n3, s3x = (int64_t)n3 * n12, sxx = (int64_t)n12 * n12;
         double *M, *X, *B, *Cm, *Sx, *U, *Tn = nullptr;
-        TRY(tmp.get(&M, nodes * s33));
-        TRY(tmp.get(&X, nodes * s33));
-        TRY(tmp.get(&B, nodes * s3x));
-        TRY(tmp.get(&Cm, nodes * s3x));
-        TRY(tmp.get(&Sx, nodes * s3x));
-        TRY(tmp.get(&U, nodes * s3x));
-        if (!root) TRY(tmp.get(&Tn, nodes * sxx));
-        TRY(launch_merge_gather(Lv, root, Tc, M, B, Cm, Tn, st));
+        TRY(tmp.get(&M, nbuilt * s33));
+        TRY(tmp.get(&X, nbuilt * s33));
+        TRY(tmp.get(&B, nbuilt * s3x));
+        TRY(tmp.get(&Cm, nbuilt * s3x));
+        TRY(tmp.get(&Sx, nbuilt * s3x));
+        TRY(tmp.get(&U, nbuilt * s3x));
+        if (!root) TRY(tmp.get(&Tn, nbuilt * sxx));
+        // children's DtN maps: 2k, 2k+1 of the level below, or the one shared map
+        const int64_t cstride = uni ? 0 : (int64_t)Lv.nbc * Lv.nbc;
+        TRY(launch_merge_gather(Lv, nbuilt, cstride, root, Tc, M, B, Cm, Tn, st));
         tmp.release(Tc);
         {
             unsigned char *used; int *order; double *cb, *rb;
-            TRY(gj_scratch(n3, nodes, &used, &order, &cb, &rb));
-            TRY(gj_invert(M, X, n3, nodes, used, order, cb, rb, sing, st));
+            TRY(gj_scratch(n3, nbuilt, &used, &order, &cb, &rb));
+            TRY(gj_invert(M, X, n3, nbuilt, used, order, cb, rb, sing, st));
             tmp.release(used); tmp.release(order); tmp.release(cb); tmp.release(rb);
         }
         tmp.release(M);
         // S = X [-T^a_31 | T^b_32];  U = [T^a_13; T^b_23] X;  T = diag(T^a_11, T^b_22) + U [...]
-        TRY(launch_dgemm(n3, n12, n3, X, n3, s33, B, n3, s3x, Sx, n3, s3x, nodes, 1.0, 0.0, st));
+        TRY(launch_dgemm(n3, n12, n3, X, n3, s33, B, n3, s3x, Sx, n3, s3x, nbuilt, 1.0, 0.0, st));
         if (!root) {
-            TRY(launch_dgemm(n12, n3, n3, Cm, n12, s3x, X, n3, s33, U, n12, s3x, nodes, 1.0, 0.0, st));
-            TRY(launch_dgemm(n12, n12, n3, U, n12, s3x, B, n3, s3x, Tn, n12, sxx, nodes, 1.0, 1.0, st));
+            TRY(launch_dgemm(n12, n3, n3, Cm, n12, s3x, X, n3, s33, U, n12, s3x, nbuilt, 1.0, 0.0, st));
+            TRY(launch_dgemm(n12, n12, n3, U, n12, s3x, B, n3, s3x, Tn, n12, sxx, nbuilt, 1.0, 1.0, st));
         }
         const int rows = root ? n3 : n3 + n12;
         const int rpm = 64, mwg = level_min_wg(op->flags);
-        Lv.xu64 = sh(plan_panel(rows, n3, 2, nodes, rpm, mwg));
-        Lv.s64 = sh(plan_panel(n3, n12, 2, nodes, rpm, mwg));
+        Lv.xu64 = sh(plan_panel(rows, n3, 2, Lv.nodes, rpm, mwg));   // tiles planned for every node
+        Lv.s64 = sh(plan_panel(n3, n12, 2, Lv.nodes, rpm, mwg));
         TRY(alloc_panel(op, Lv.xu64));
         TRY(alloc_panel(op, Lv.s64));
         TRY(launch_pack(Lv.xu64, X, n3, s33, n3, U, n12, s3x, st));
         TRY(launch_pack(Lv.s64, Sx, n3, s3x, n3, nullptr, 0, 0, st));
         if (ir) {
-            Lv.xu32 = sh(plan_panel(rows, n3, 4, nodes, rpm, mwg));
-            Lv.s32 = sh(plan_panel(n3, n12, 4, nodes, rpm, mwg));
+            Lv.xu32 = sh(plan_panel(rows, n3, 4, Lv.nodes, rpm, mwg));
+            Lv.s32 = sh(plan_panel(n3, n12, 4, Lv.nodes, rpm, mwg));
             TRY(alloc_panel(op, Lv.xu32));
             TRY(alloc_panel(op, Lv.s32));
             TRY(launch_pack(Lv.xu32, X, n3, s33, n3, U, n12, s3x, st));
@@ -698,19 +704,21 @@ static int build_impl(hps_op *op, const hps_coeffs *co, const hps_coeffs *co_im,
         }
         tmp.release(X); tmp.release(B); tmp.release(Cm); tmp.release(Sx); tmp.release(U);
         Tc = Tn;
-        TRY(dev_alloc(op, &Lv.h, (int64_t)nodes * n12));
-        TRY(dev_alloc(op, &Lv.ub, (int64_t)nodes * n12));
-        TRY(dev_alloc(op, &Lv.w3, (int64_t)nodes * n3));
+        // solve workspaces: every node of the level (not only the nodes whose operators were built)
+        const int64_t lnodes = Lv.nodes;
+        TRY(dev_alloc(op, &Lv.h, lnodes * n12));
+        TRY(dev_alloc(op, &Lv.ub, lnodes * n12));
+        TRY(dev_alloc(op, &Lv.w3, lnodes * n3));
         int64_t part = 0;
         for (const Panel *pn : {&Lv.xu64, &Lv.s64, &Lv.xu32, &Lv.s32})
-            if (pn->kch > 1) part = std::max<int64_t>(part, (int64_t)nodes * pn->ntile * pn->kch * pn->rp * pn->vw);
+            if (pn->kch > 1) part = std::max<int64_t>(part, lnodes * pn->ntile * pn->kch * pn->rp * pn->vw);
         if (part) TRY(dev_alloc(op, &Lv.part, part));
         // split-K arrival counters start at zero; the last arriving workgroup resets them
         int **cnts[4] = {&Lv.cnt_up64, &Lv.cnt_dn64, &Lv.cnt_up32, &Lv.cnt_dn32};
         const Panel *pns[4] = {&Lv.xu64, &Lv.s64, &Lv.xu32, &Lv.s32};
         for (int k = 0; k < 4; ++k) {
             if (pns[k]->kch <= 1) continue;
-            const int64_t nc = (int64_t)nodes * pns[k]->ntile;
+            const int64_t nc = lnodes * pns[k]->ntile;
             TRY(dev_alloc(op, cnts[k], nc));
             HPS_HIP(hipMemsetAsync(*cnts[k], 0, sizeof(int) * nc, st));
         }

@@ -230,13 +230,13 @@ struct MergeArgs {
     const int *a1, *a3, *b2, *b3;
     const double *Tc;
     double *M, *B, *Cm, *Tn;
+    int64_t cstride;   // elements between children's T in Tc (0: every node's children are T[0])
 };
 
 __global__ __launch_bounds__(NT) void k_merge_gather(MergeArgs a) {
     const int node = blockIdx.y;
-    const int64_t nbc2 = (int64_t)a.nbc * a.nbc;
-    const double *Ta = a.Tc + (int64_t)(2 * node) * nbc2;
-    const double *Tb = a.Tc + (int64_t)(2 * node + 1) * nbc2;
+    const double *Ta = a.Tc + (int64_t)(2 * node) * a.cstride;
+    const double *Tb = a.Tc + (int64_t)(2 * node + 1) * a.cstride;
     auto ta = [&](int r, int c) { return Ta[(int64_t)c * a.nbc + r]; };
     auto tb = [&](int r, int c) { return Tb[(int64_t)c * a.nbc + r]; };
     const int n3 = a.n3, n12 = a.n12, n1 = a.n1;
@@ -601,6 +601,9 @@ __global__ void k_pack(PackArgs a) {
 // =======================================================================================
 // launchers
 // =======================================================================================
+// leaves whose operators the build computes (one when all leaves have the same operators)
+static unsigned build_leaves(const hps_op *op) { return op->build_one ? 1u : (unsigned)op->nleaves; }
+
 static BuildLeafArgs build_leaf_args(const hps_op *op) {
     return BuildLeafArgs{geo_of(op), op->leaf_ij, op->coef, op->D, op->D2, op->gamma_dt};
 }
@@ -608,7 +611,7 @@ static BuildLeafArgs build_leaf_args(const hps_op *op) {
 int launch_leaf_assemble(const hps_op *op, double *W, hipStream_t st) {
     const int64_t tot = (int64_t)op->q2 * op->q2;
     const unsigned bx = (unsigned)std::min<int64_t>(nblk(tot), 64);
-    hipLaunchKernelGGL(k_leaf_assemble, dim3(bx, op->nleaves), dim3(NT), 0, st, build_leaf_args(op), W);
+    hipLaunchKernelGGL(k_leaf_assemble, dim3(bx, build_leaves(op)), dim3(NT), 0, st, build_leaf_args(op), W);
     HPS_LAUNCHED();
     return HPS_OK;
 }
@@ -616,7 +619,7 @@ int launch_leaf_assemble(const hps_op *op, double *W, hipStream_t st) {
 int launch_leaf_S(const hps_op *op, const double *ainv, double *S, hipStream_t st) {
     const int64_t tot = (int64_t)op->q2 * 4 * op->q;
     const unsigned bx = (unsigned)std::min<int64_t>(nblk(tot), 64);
-    hipLaunchKernelGGL(k_leaf_S, dim3(bx, op->nleaves), dim3(NT), 0, st, build_leaf_args(op), ainv, S);
+    hipLaunchKernelGGL(k_leaf_S, dim3(bx, build_leaves(op)), dim3(NT), 0, st, build_leaf_args(op), ainv, S);
     HPS_LAUNCHED();
     return HPS_OK;
 }
@@ -624,7 +627,7 @@ int launch_leaf_S(const hps_op *op, const double *ainv, double *S, hipStream_t s
 int launch_leaf_T(const hps_op *op, const double *S, double *T, hipStream_t st) {
     const int64_t tot = (int64_t)16 * op->q * op->q;
     const unsigned bx = (unsigned)std::min<int64_t>(nblk(tot), 64);
-    hipLaunchKernelGGL(k_leaf_T, dim3(bx, op->nleaves), dim3(NT), 0, st, build_leaf_args(op), S, T);
+    hipLaunchKernelGGL(k_leaf_T, dim3(bx, build_leaves(op)), dim3(NT), 0, st, build_leaf_args(op), S, T);
     HPS_LAUNCHED();
     return HPS_OK;
 }
@@ -632,7 +635,7 @@ int launch_leaf_T(const hps_op *op, const double *S, double *T, hipStream_t st) 
 int launch_leaf_assemble_cx(const hps_op *op, double *W, hipStream_t st) {
     const int64_t n = 2 * (int64_t)op->q2, tot = n * n;
     const unsigned bx = (unsigned)std::min<int64_t>(nblk(tot), 128);
-    hipLaunchKernelGGL(k_leaf_assemble_cx, dim3(bx, op->nleaves), dim3(NT), 0, st, build_leaf_args(op), W);
+    hipLaunchKernelGGL(k_leaf_assemble_cx, dim3(bx, build_leaves(op)), dim3(NT), 0, st, build_leaf_args(op), W);
     HPS_LAUNCHED();
     return HPS_OK;
 }
@@ -640,7 +643,7 @@ int launch_leaf_assemble_cx(const hps_op *op, double *W, hipStream_t st) {
 int launch_leaf_S_cx(const hps_op *op, const double *ainv, double *S, hipStream_t st) {
     const int64_t tot = 2 * (int64_t)op->q2 * 8 * op->q;
     const unsigned bx = (unsigned)std::min<int64_t>(nblk(tot), 128);
-    hipLaunchKernelGGL(k_leaf_S_cx, dim3(bx, op->nleaves), dim3(NT), 0, st, build_leaf_args(op), ainv, S);
+    hipLaunchKernelGGL(k_leaf_S_cx, dim3(bx, build_leaves(op)), dim3(NT), 0, st, build_leaf_args(op), ainv, S);
     HPS_LAUNCHED();
     return HPS_OK;
 }
@@ -648,18 +651,18 @@ int launch_leaf_S_cx(const hps_op *op, const double *ainv, double *S, hipStream_
 int launch_leaf_T_cx(const hps_op *op, const double *S, double *T, hipStream_t st) {
     const int64_t tot = (int64_t)64 * op->q * op->q;
     const unsigned bx = (unsigned)std::min<int64_t>(nblk(tot), 128);
-    hipLaunchKernelGGL(k_leaf_T_cx, dim3(bx, op->nleaves), dim3(NT), 0, st, build_leaf_args(op), S, T);
+    hipLaunchKernelGGL(k_leaf_T_cx, dim3(bx, build_leaves(op)), dim3(NT), 0, st, build_leaf_args(op), S, T);
     HPS_LAUNCHED();
     return HPS_OK;
 }
 
-int launch_merge_gather(const Level &L, bool root, const double *Tc, double *M, double *B,
-                        double *Cm, double *Tn, hipStream_t st) {
-    MergeArgs a{L.n1, L.n2, L.n3, L.n12, L.nbc, L.a1, L.a3, L.b2, L.b3, Tc, M, B, Cm, root ? nullptr : Tn};
+int launch_merge_gather(const Level &L, int nodes, int64_t child_stride, bool root, const double *Tc, double *M,
+                        double *B, double *Cm, double *Tn, hipStream_t st) {
+    MergeArgs a{L.n1, L.n2, L.n3, L.n12, L.nbc, L.a1, L.a3, L.b2, L.b3, Tc, M, B, Cm, root ? nullptr : Tn, child_stride};
     const int64_t tot = (int64_t)L.n3 * L.n3 + 2 * (int64_t)L.n3 * L.n12 +
                         (root ? 0 : (int64_t)L.n12 * L.n12);
     const unsigned bx = (unsigned)std::min<int64_t>(nblk(tot), 4096);
-    hipLaunchKernelGGL(k_merge_gather, dim3(bx, L.nodes), dim3(NT), 0, st, a);
+    hipLaunchKernelGGL(k_merge_gather, dim3(bx, nodes), dim3(NT), 0, st, a);
     HPS_LAUNCHED();
     return HPS_OK;
 }

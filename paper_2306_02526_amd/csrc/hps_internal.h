@@ -114,6 +114,9 @@ struct hps_op {
     hps::Panel ainv64, sleaf64, ainv32, sleaf32;
     std::vector<hps::Level> lv;            // lv[l], l = 0..L-1
     double *h_leaf = nullptr, *ub_leaf = nullptr, *w_leaf = nullptr;
+    // HPS_UNIFORM_COEFFS: every leaf, and every node of a level, has the same operators, so
+    // the build computes one leaf and one node per level (the panels keep node 0 only)
+    bool build_one = false;
     // iterative refinement workspace (FP32_IR)
     double *ir_rhs = nullptr, *ir_r = nullptr, *ir_r3 = nullptr, *ir_du = nullptr, *ir_flux = nullptr;
     double *ir_norms = nullptr;            // [2] max|delta|, max|u| (as ordered bit patterns)
@@ -295,7 +298,7 @@ int gj_invert(double *W, double *out, int n, int nb, unsigned char *used, int *o
               double *colbuf, double *rowbuf, int *sing, hipStream_t st);
 int launch_leaf_S(const hps_op *op, const double *ainv, double *S, hipStream_t st);
 int launch_leaf_T(const hps_op *op, const double *S, double *T, hipStream_t st);
-int launch_merge_gather(const Level &L, bool root, const double *Tc, double *M, double *B,
+int launch_merge_gather(const Level &L, int nodes, int64_t child_stride, bool root, const double *Tc, double *M, double *B,
                         double *Cm, double *Tn, hipStream_t st);
 int launch_dgemm(int M, int N, int K, const double *A, int lda, int64_t sA, const double *B,
                  int ldb, int64_t sB, double *C, int ldc, int64_t sC, int batch, double alpha,
