@@ -471,6 +471,15 @@ def main():
     breakdown = {k: {"launches_per_step": v[0] // prof_steps, "us_per_launch": round(1e3 * v[1] / v[0], 2)}
                  for k, v in prof.items()}
     log(f"leaf_down_up_fp64: {leaf_us:.1f} us/launch, {achieved:.0f} GB/s; kernels: {breakdown}")
+    # the level sweeps of one stage solve: the operator bytes outside the leaf panels (A_ii^-1
+    # and S_leaf, q2 x q2 and q2 x 4q per leaf) over the up and down sweep times
+    level_bytes = op.bytes()[1] - n * n * (q * q * q * q + q * q * 4 * q) * 8
+    level_us = sum(1e3 * prof[k][1] / prof[k][0] for k in ("level_up_fp64", "level_down_fp64") if k in prof)
+    levels = {"bytes_per_stage": int(level_bytes), "us_per_stage": round(level_us, 2),
+              "achieved_GBps": round(level_bytes / (level_us * 1e-6) / 1e9, 1),
+              "frac": round(level_bytes / (level_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+              "launches_per_stage": 2 * (int(math.log2(n * n)) - 1) + 1,
+              "note": "latency-bound: one dependent launch per tree level and direction"}
     traffic = None
     tr_path = os.path.join(ROOT, "profiles", "leaf_down_up_fp64_traffic.json")
     if os.path.exists(tr_path):
@@ -629,6 +638,7 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "algorithmic_bytes_per_launch": int(alg),
                      "avg_launch_us": round(leaf_us, 2)},
+        "level_sweeps": levels,
         "fp32_ir": fp32,
         "slope_formulation": slope,
         "burgers_system": burgers,
