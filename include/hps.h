@@ -68,10 +68,11 @@ extern "C" {
 #define HPS_UNIFORM_COEFFS 4 /* or-ed with the above: the caller states that every
                             coefficient of L is the same at every node (e.g. L = eps
                             Lap).  Then every leaf, and every node of one tree level,
-                            has the same operators: they are stored once and all
-                            workgroups read that copy, which stays in the on-chip
-                            caches (operator memory / number of leaves, and far less
-                            HBM traffic).  hps_build checks the claim (HPS_EINVAL if
+                            has the same operators: they are computed and stored
+                            once (one leaf, one node per level) and all workgroups
+                            read that copy, which stays in the on-chip caches
+                            (operator memory / number of leaves, and far less HBM
+                            traffic).  hps_build checks the claim (HPS_EINVAL if
                             any coefficient varies); results are bitwise those of
                             the build without the flag.                             */
 
