@@ -6,11 +6,12 @@ import sys
 import numpy as np
 import pytest
 
-from oracle.ark import ARK, ark436l2sa, tableau_float
+from oracle.ark import ARK, ark436l2sa, ark548l2sa, tableau_float
 from oracle.grid import Grid
 from oracle.hps import HPS
 from paper_2306_02526_amd import hps, workloads
 from paper_2306_02526_amd.tableau import ark436l2sa as product_tableau
+from paper_2306_02526_amd.tableau import ark548l2sa as product_ark5
 
 pytestmark = pytest.mark.gpu
 
@@ -36,7 +37,7 @@ def rel(a, b):
 class Problem:
     """One seeded problem of the batched recipe with its device data."""
 
-    def __init__(self, torch, kind, n1, n2, p, gdt, seed):
+    def __init__(self, torch, kind, n1, n2, p, gdt, seed, fifth=False):
         rng = workloads.rng_for(5, seed)
         coef = workloads.SmoothDiffusivity(rng)
         h = 1.0 / max(n1, n2)
@@ -51,7 +52,8 @@ class Problem:
         cxx, cyy, cx, cy, c0 = self.pr.L_coeffs(self.x[:ni], self.y[:ni])
         self.co = dict(cxx=cxx, cyy=cyy, cx=cx, cy=cy, c0=c0)
         self.dco = {k: torch.tensor(v, device="cuda") for k, v in self.co.items()}
-        self.tab = product_tableau()
+        self.tab = product_ark5() if fifth else product_tableau()
+        self.otab = tableau_float(ark548l2sa() if fifth else ark436l2sa())
         self.gdt = gdt
         self.dt = gdt / self.tab["gamma"]
         self.gp = None if kind == "heat" else workloads.AllenCahn.gpoly
@@ -67,7 +69,7 @@ class Problem:
         return jid, u
 
     def oracle(self, steps):
-        ark = ARK(HPS(self.og, self.co, self.gdt), self.co, tableau_float(ark436l2sa()), self.dt, self.gp)
+        ark = ARK(HPS(self.og, self.co, self.gdt), self.co, self.otab, self.dt, self.gp)
         u = self.u0.copy()
         ni = self.og.n_int
         for n in range(steps):
@@ -149,3 +151,22 @@ def test_server_rejects_bad_jobs(torch):
     assert st["state"] == hps.SRV_FAILED and st["error"] == -2
     too_big.close()
     srv.close()
+
+
+def test_served_jobs_with_both_tableaux(torch):
+    """Jobs stepping with ARK4(3)6L[2]SA and with ARK5(4)8L[2]SA (8 stages) in one server:
+    each equals its oracle run."""
+    say("[serve] ARK4 and ARK5 jobs in one server")
+    P4 = Problem(torch, "heat", 4, 4, 8, 1e-2, 11)
+    P5 = Problem(torch, "heat", 4, 4, 8, 1e-2, 12, fifth=True)
+    A5 = Problem(torch, "allen_cahn", 8, 4, 9, 2e-3, 13, fifth=True)
+    srv = hps.Server(max_active=3)
+    jobs = [(P, *P.submit(torch, srv, n)) for P, n in ((P4, 5), (P5, 4), (A5, 3))]
+    for P, jid, u in jobs:
+        st = srv.wait(jid)
+        assert st["state"] == hps.SRV_DONE, st
+    srv.close()
+    for (P, jid, u), n in zip(jobs, (5, 4, 3)):
+        e = rel(u.cpu().numpy(), P.oracle(n))
+        say(f"   {P.kind} s={P.tab['s']}: oracle {e:.2e}")
+        assert e <= TOL64
