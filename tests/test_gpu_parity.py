@@ -306,6 +306,8 @@ ORACLE_FULL_STEP = """
 import sys, time
 import numpy as np
 sys.path.insert(0, sys.argv[1])
+sys.path.insert(0, sys.argv[1] + "/tests")
+from inverse_oracle import explicit_inverses
 from oracle.ark import ARK, ark436l2sa, tableau_float
 from oracle.grid import Grid
 from oracle.hps import HPS
@@ -313,30 +315,38 @@ from paper_2306_02526_amd import workloads
 d = np.load(sys.argv[2])
 og = Grid(0, 1, 0, 1, 64, 64, 16)
 co = {k: d[k] for k in ("cxx", "cyy", "cx", "cy", "c0")}
-t0 = time.perf_counter()
 tab = tableau_float(ark436l2sa())
+t0 = time.perf_counter()
 ark = ARK(HPS(og, co, float(d["gdt"])), co, tab, float(d["dt"]), workloads.AllenCahn.gpoly)
 print(f"   oracle built in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
 np.save(sys.argv[3], ark.step(d["u0"]))
 print(f"   oracle step done after {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+with explicit_inverses():
+    ark = ARK(HPS(og, co, float(d["gdt"])), co, tab, float(d["dt"]), workloads.AllenCahn.gpoly)
+    np.save(sys.argv[4], ark.step(d["u0"]))
+print(f"   explicit-inverse oracle step done after {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
 """
 
 
 # At 64x64 leaves, p = 16, gamma dt = 2.5e-4 the stage operator I - gamma dt L has
 # condition number ~1e5 (the collocation second derivative has row sums ~3e8), so two
-# equally valid FP64 evaluations of one step differ by ~1e-11 relative: the oracle with
-# explicit inverses instead of LU solves differs from itself by 2.0e-11 after one step
-# (8.7e-13 at 16x16).  The full-size comparison therefore uses 1e-10.
+# equally valid FP64 evaluations of one step differ by more than 1e-11 relative: the
+# oracle with explicit inverses instead of LU solves differs from the LU oracle by
+# 1.8e-11 after one step (6.9e-13 at 16x16; both pinned by tests/test_oracle_floor.py).
+# The full-size comparisons therefore use 1e-10, and the FP64 path is also held to
+# FLOOR_FACTOR times the spread measured in the same run, so that a regression that
+# doubles its error is caught.
 TOL_FULL = 1e-10
+FLOOR_FACTOR = 3.0
 
 
-def test_full_size_allen_cahn_step_matches_oracle(torch, tmp_path):
-    """The benchmark configuration itself (64x64 leaves, p = 16, FP64): one full step
-    compared element by element with the oracle (run in a child process on one BLAS
-    thread, as the CPU baseline is), to the FP64 conditioning floor of this size."""
+@pytest.fixture(scope="module")
+def full_size_case(torch, tmp_path_factory):
+    """The benchmark configuration (Allen-Cahn, 64x64 leaves, p = 16, dt = 1e-3): inputs
+    and one oracle step, computed once in a child process on one BLAS thread (as the CPU
+    baseline is), with LU solves and with explicit inverses."""
     import os
     import subprocess
-    say("[full size] Allen-Cahn 64x64 p=16")
     dt = 1e-3
     tab = product_tableau()
     gdt = tab["gamma"] * dt
@@ -347,22 +357,52 @@ def test_full_size_allen_cahn_step_matches_oracle(torch, tmp_path):
     wl = workloads.AllenCahn(workloads.rng_for(2))
     cxx, cyy, cx, cy, c0 = wl.L_coeffs(xi, yi)
     co = dict(cxx=cxx, cyy=cyy, cx=cx, cy=cy, c0=c0)
-    op = hps.hps_build(g, {k: torch.tensor(v, device="cuda") for k, v in co.items()}, gdt)
-    ctx = hps.ark_create(op, tab, dt, g=workloads.AllenCahn.gpoly)
     u0 = wl.u0(x, y)
-    ug = torch.tensor(u0, device="cuda")
-    hps.ark_step(ctx, 0.0, ug)
-    u_gpu = ug.cpu().numpy()
-    say("   GPU step done; oracle in a child process")
-    inp, outp = tmp_path / "in.npz", tmp_path / "out.npy"
+    tmp = tmp_path_factory.mktemp("full_size")
+    inp, out_lu, out_inv = tmp / "in.npz", tmp / "lu.npy", tmp / "inv.npy"
     np.savez(inp, u0=u0, gdt=gdt, dt=dt, **co)
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     env = dict(os.environ, OPENBLAS_NUM_THREADS="1", OMP_NUM_THREADS="1", MKL_NUM_THREADS="1")
-    subprocess.run([sys.executable, "-c", ORACLE_FULL_STEP, root, str(inp), str(outp)], env=env, check=True,
-                   timeout=600)
-    e = rel(u_gpu, np.load(outp))
-    say(f"   rel err {e:.2e}")
+    say("[full size] oracle step of Allen-Cahn 64x64 p=16 in a child process (LU and explicit inverses)")
+    subprocess.run([sys.executable, "-c", ORACLE_FULL_STEP, root, str(inp), str(out_lu), str(out_inv)], env=env,
+                   check=True, timeout=600)
+    ref = np.load(out_lu)
+    spread = rel(np.load(out_inv), ref)
+    say(f"   oracle spread (explicit inverses vs LU) {spread:.2e}")
+    return dict(grid=g, co=co, u0=u0, dt=dt, gdt=gdt, tab=tab, ref=ref, spread=spread)
+
+
+def _full_size_gpu_step(torch, case, flags):
+    co = case["co"]
+    op = hps.hps_build(case["grid"], {k: torch.tensor(v, device="cuda") for k, v in co.items()}, case["gdt"], flags)
+    ctx = hps.ark_create(op, case["tab"], case["dt"], g=workloads.AllenCahn.gpoly)
+    ug = torch.tensor(case["u0"], device="cuda")
+    hps.ark_step(ctx, 0.0, ug)
+    out = ug.cpu().numpy()
+    del ctx
+    op.free()
+    return out
+
+
+def test_full_size_allen_cahn_step_matches_oracle(torch, full_size_case):
+    """The benchmark configuration itself (64x64 leaves, p = 16, FP64): one full step
+    compared element by element with the oracle, to the FP64 conditioning floor of this
+    size (1e-10, and at most FLOOR_FACTOR times the spread of two oracle evaluations)."""
+    say("[full size] Allen-Cahn 64x64 p=16, FP64")
+    e = rel(_full_size_gpu_step(torch, full_size_case, hps.HPS_FP64), full_size_case["ref"])
+    say(f"   rel err {e:.2e} ({e / full_size_case['spread']:.2f} x the oracle spread)")
     assert e <= TOL_FULL
+    assert e <= FLOOR_FACTOR * full_size_case["spread"]
+
+
+def test_full_size_fp32_ir_step_matches_oracle(torch, full_size_case):
+    """The FP32+IR configuration at its own size (64x64 leaves, p = 16, FP32 operators with
+    FP64 iterative refinement): one full step element by element against the oracle, to
+    the 1e-10 stated for refined results."""
+    say("[full size] Allen-Cahn 64x64 p=16, FP32+IR")
+    e = rel(_full_size_gpu_step(torch, full_size_case, hps.HPS_FP32_IR), full_size_case["ref"])
+    say(f"   rel err {e:.2e} ({e / full_size_case['spread']:.2f} x the oracle spread)")
+    assert e <= TOL32IR
 
 
 def test_graph_replay_equals_eager_steps(torch, monkeypatch):
