@@ -142,6 +142,24 @@ HPS_API int64_t hps_op_bytes(const hps_op *op, int64_t *operator_bytes);
 HPS_API int hps_solve(hps_op *op, int nrhs, const double *body, const double *dirichlet,
               const double *jump, double *u, void *stream, hps_info *info);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): hps_solve without allocation.
+ * Same arguments, layouts and results as hps_solve (bitwise: the same kernels in the
+ * same order), without `info`, for real operators built with HPS_FP64 (HPS_WIDE_TILES
+ * and HPS_UNIFORM_COEFFS allowed); FP32_IR and complex operators give HPS_EINVAL.
+ * The solve's intermediate data (leaf and level boundary values, particular solutions
+ * and fluxes, split-K partials) go to one fixed device array of
+ * HPS_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on until the
+ * process ends (64 x 64 leaves at p = 16 use 19.1 MiB of it); an operator whose solve
+ * needs more is rejected with HPS_EINVAL.  Nothing is allocated: the first call on a
+ * device only looks up the array's address.  The array is shared by every call on that
+ * GPU and keeps the last call's contents (the call clears what must start at zero), so
+ * calls that overlap on one GPU (two streams or two threads at once) race: serialize
+ * them.  Stream-ordered; returns without waiting. */
+#define HPS_NOALLOC_SCRATCH_BYTES (32LL << 20)
+HPS_API int hps_solve_noalloc(hps_op *op, int nrhs, const double *body, const double *dirichlet,
+                              const double *jump, double *u, void *stream);
+
 HPS_API void hps_free(hps_op *op);
 
 /* Kernel timing for measurement tools: while enabled, every kernel family launched

@@ -897,46 +897,62 @@ int hps::ark_slope_workspace(ark_ctx *c) {
     return HPS_OK;
 }
 
-// A workspace of the context's own, shaped like its operator's (FP64 levels).
-int hps::ctx_workspace(ark_ctx *c) {
-    if (c->ws) return HPS_OK;
-    const hps_op *op = c->op;
-    Workspace *w = new Workspace();
-    c->ws = w;
-    auto get = [&](size_t bytes, void **p) -> int {
-        if (hipMalloc(p, std::max<size_t>(bytes, 8)) != hipSuccess) {
-            *p = nullptr;
-            hps_set_error("hipMalloc of %zu bytes for a stepping workspace failed", bytes);
-            return HPS_ENOMEM;
-        }
-        w->allocs.push_back(*p);
-        return HPS_OK;
+int64_t hps::workspace_layout(const hps_op *op, char *base, Workspace *w, int64_t *cnt_off, int64_t *cnt_bytes) {
+    int64_t off = 0;
+    auto take = [&](int64_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += (std::max<int64_t>(bytes, 8) + 255) & ~int64_t(255);
+        return p;
     };
-    const size_t nl = op->nleaves, nb4 = 4 * (size_t)op->q, q2 = op->q2;
-    TRY(get(8 * nl * nb4, (void **)&w->h_leaf));
-    TRY(get(8 * nl * nb4, (void **)&w->ub_leaf));
-    TRY(get(8 * nl * q2, (void **)&w->w_leaf));
-    TRY(get(8 * nl * nb4, (void **)&w->flux));
-    w->lv.resize(op->L);
+    const int64_t nl = op->nleaves, nb4 = 4 * (int64_t)op->q, q2 = op->q2;
+    Workspace tmp;
+    Workspace &ws = w ? *w : tmp;
+    ws.h_leaf = (double *)take(8 * nl * nb4);
+    ws.ub_leaf = (double *)take(8 * nl * nb4);
+    ws.w_leaf = (double *)take(8 * nl * q2);
+    ws.flux = (double *)take(8 * nl * nb4);
+    ws.lv.resize(op->L);
     for (int l = 0; l < op->L; ++l) {
         const Level &L = op->lv[l];
-        Workspace::Lv &v = w->lv[l];
-        TRY(get(8 * (size_t)L.nodes * L.n12, (void **)&v.h));
-        TRY(get(8 * (size_t)L.nodes * L.n12, (void **)&v.ub));
-        TRY(get(8 * (size_t)L.nodes * L.n3, (void **)&v.w3));
+        Workspace::Lv &v = ws.lv[l];
+        v = Workspace::Lv{};
+        v.h = (double *)take(8 * (int64_t)L.nodes * L.n12);
+        v.ub = (double *)take(8 * (int64_t)L.nodes * L.n12);
+        v.w3 = (double *)take(8 * (int64_t)L.nodes * L.n3);
         int64_t part = 0;
         for (const Panel *pn : {&L.xu64, &L.s64})
             if (pn->kch > 1) part = std::max<int64_t>(part, (int64_t)L.nodes * pn->ntile * pn->kch * pn->rp * pn->vw);
-        if (part) TRY(get(8 * (size_t)part, (void **)&v.part));
-        const Panel *pns[2] = {&L.xu64, &L.s64};
-        int **cnts[2] = {&v.cnt_up, &v.cnt_dn};
-        for (int k = 0; k < 2; ++k) {
-            if (pns[k]->kch <= 1) continue;
-            const size_t nc = (size_t)L.nodes * pns[k]->ntile;
-            TRY(get(sizeof(int) * nc, (void **)cnts[k]));
-            HPS_HIP(hipMemset(*cnts[k], 0, sizeof(int) * nc));
-        }
+        if (part) v.part = (double *)take(8 * part);
     }
+    // the arrival counters, contiguous at the end
+    const int64_t c0 = off;
+    for (int l = 0; l < op->L; ++l) {
+        const Level &L = op->lv[l];
+        Workspace::Lv &v = ws.lv[l];
+        if (L.xu64.kch > 1) v.cnt_up = (int *)take(sizeof(int) * (int64_t)L.nodes * L.xu64.ntile);
+        if (L.s64.kch > 1) v.cnt_dn = (int *)take(sizeof(int) * (int64_t)L.nodes * L.s64.ntile);
+    }
+    if (cnt_off) *cnt_off = c0;
+    if (cnt_bytes) *cnt_bytes = off - c0;
+    return off;
+}
+
+// A workspace of the context's own, shaped like its operator's (FP64 levels), in one block.
+int hps::ctx_workspace(ark_ctx *c) {
+    if (c->ws) return HPS_OK;
+    const hps_op *op = c->op;
+    int64_t co = 0, cb = 0;
+    const int64_t bytes = workspace_layout(op, nullptr, nullptr, &co, &cb);
+    void *blk = nullptr;
+    if (hipMalloc(&blk, (size_t)bytes) != hipSuccess) {
+        hps_set_error("hipMalloc of %lld bytes for a stepping workspace failed", (long long)bytes);
+        return HPS_ENOMEM;
+    }
+    Workspace *w = new Workspace();
+    w->allocs.push_back(blk);
+    c->ws = w;
+    workspace_layout(op, (char *)blk, w, &co, &cb);
+    if (cb) HPS_HIP(hipMemset((char *)blk + co, 0, (size_t)cb));
     return HPS_OK;
 }
 

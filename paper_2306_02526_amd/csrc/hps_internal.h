@@ -139,6 +139,13 @@ struct Workspace {
     std::vector<void *> allocs;
 };
 
+namespace hps {
+// Layout of one solve's workspace in a single block (256-byte aligned pieces; the split-K
+// arrival counters last, at [*cnt_off, *cnt_off + *cnt_bytes), which must hold zeros before
+// the first sweep).  Returns the block's size; with base == nullptr only sizes are computed.
+int64_t workspace_layout(const hps_op *op, char *base, Workspace *w, int64_t *cnt_off, int64_t *cnt_bytes);
+}  // namespace hps
+
 struct ark_ctx {
     hps_op *op = nullptr;
     Workspace *ws = nullptr;              // own workspace for grouped launches (or null)
@@ -235,12 +242,15 @@ struct LeafPhase {
     double *rhs_copy = nullptr;
     double *unew = nullptr;                    // LU_UPDATE
 };
-int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st);
+// ws (FP64 only) redirects the solve buffers (leaf boundary values, particular solutions
+// and fluxes) from the operator's own to a workspace
+int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st, const Workspace *ws = nullptr);
 // the same phases for a complex operator (FP64; vectors in real / imaginary planes)
 int launch_leaf_cx(const hps_op *op, const LeafPhase &ph, hipStream_t st);
 // upward sweep over the levels, the root, then the downward sweep (jump and dirichlet
-// may be NULL)
-int launch_levels(const hps_op *op, bool fp32, const double *jump, const double *dirichlet, hipStream_t st);
+// may be NULL); ws (FP64 only) redirects the per-level buffers to a workspace
+int launch_levels(const hps_op *op, bool fp32, const double *jump, const double *dirichlet, hipStream_t st,
+                  const Workspace *ws = nullptr);
 // step completion after the interior update: boundary data f(t + dt), then the interface
 // values from flux continuity along every grid line (reads the leaf edge-flux parts)
 int launch_interface_lines(const hps_op *op, double *u, const double *f_end, hipStream_t st,

@@ -587,11 +587,21 @@ static void make_leaf_args(const hps_op *op, bool fp32, const LeafPhase &ph, Lea
     lds = carve_bytes({(size_t)a.xs_cap * es, (size_t)a.part_cap * es, pp, pp, pp, q2b, q2b});
 }
 
-int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st) {
+static void use_leaf_workspace(LeafArgs &a, const Workspace *ws) {
+    if (!ws) return;
+    a.ub = ws->ub_leaf;
+    a.w_in = ws->w_leaf;
+    a.w_out = ws->w_leaf;
+    a.h_out = ws->h_leaf;
+    a.fpart = ws->flux;
+}
+
+int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st, const Workspace *ws) {
     ProfScope ps_(&op->prof, leaf_family(ph, fp32), st);
     LeafArgs a;
     size_t lds = 0;
     make_leaf_args(op, fp32, ph, a, lds);
+    use_leaf_workspace(a, ws);
     auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(op->nleaves), dim3(NT), lds, st, a); };
 #define HPS_LEAF_CASE(DNV, UPV)                                                   \
     if (ph.down == DNV && ph.up == UPV) {                                         \
@@ -617,13 +627,7 @@ size_t leaf_args_size() { return sizeof(LeafArgs); }
 int fill_leaf_args(const hps_op *op, const LeafPhase &ph, void *dst, size_t *lds, const Workspace *ws) {
     LeafArgs &a = *reinterpret_cast<LeafArgs *>(dst);
     make_leaf_args(op, false, ph, a, *lds);
-    if (ws) {
-        a.ub = ws->ub_leaf;
-        a.w_in = ws->w_leaf;
-        a.w_out = ws->w_leaf;
-        a.h_out = ws->h_leaf;
-        a.fpart = ws->flux;
-    }
+    use_leaf_workspace(a, ws);
     return HPS_OK;
 }
 

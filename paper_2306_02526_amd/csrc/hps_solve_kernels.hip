@@ -1047,12 +1047,16 @@ __global__ void k_root_leaf_ub(const double *dir, const int *root_map, double *u
     if (t < nb) ub[t] = dir ? dir[root_map[t]] : 0.0;
 }
 
-int launch_levels(const hps_op *op, bool fp32, const double *jump, const double *dirichlet, hipStream_t st) {
+static void use_workspace(const hps_op *op, int l, bool up, const Workspace *ws, LevelArgs &a);
+
+int launch_levels(const hps_op *op, bool fp32, const double *jump, const double *dirichlet, hipStream_t st,
+                  const Workspace *ws) {
     const bool rootf = root_fusable(op, fp32);
     {
         ProfScope ps_(&op->prof, fp32 ? KF_LEVEL_UP32 : KF_LEVEL_UP64, st);
         for (int l = op->L - 1; l >= (rootf ? 1 : 0); --l) {
             LevelArgs a = level_args(op, l, fp32, true);
+            use_workspace(op, l, true, ws, a);
             a.r3 = jump;
             const Panel &pn = fp32 ? op->lv[l].xu32 : op->lv[l].xu64;
             const unsigned nb = (unsigned)(op->lv[l].nodes * a.pn.ntile * a.pn.kch);
@@ -1064,12 +1068,14 @@ int launch_levels(const hps_op *op, bool fp32, const double *jump, const double 
     ProfScope ps_(&op->prof, fp32 ? KF_LEVEL_DOWN32 : KF_LEVEL_DOWN64, st);
     if (op->L == 0) {
         hipLaunchKernelGGL(k_root_leaf_ub, dim3(1), dim3(NT), 0, st, dirichlet, (const int *)op->root_map,
-                           op->ub_leaf, 4 * op->q * op->ncomp);
+                           ws ? ws->ub_leaf : op->ub_leaf, 4 * op->q * op->ncomp);
         HPS_LAUNCHED();
         return HPS_OK;
     }
     if (rootf) {
         LevelArgs up = level_args(op, 0, fp32, true), dn = level_args(op, 0, fp32, false);
+        use_workspace(op, 0, true, ws, up);
+        use_workspace(op, 0, false, ws, dn);
         up.r3 = jump;
         dn.dir = dirichlet;
         const Panel &x = fp32 ? op->lv[0].xu32 : op->lv[0].xu64;
@@ -1081,6 +1087,7 @@ int launch_levels(const hps_op *op, bool fp32, const double *jump, const double 
     }
     for (int l = rootf ? 1 : 0; l < op->L; ++l) {
         LevelArgs a = level_args(op, l, fp32, false);
+        use_workspace(op, l, false, ws, a);
         a.dir = dirichlet;
         const Panel &pn = fp32 ? op->lv[l].s32 : op->lv[l].s64;
         const unsigned nb = (unsigned)(op->lv[l].nodes * a.pn.ntile * a.pn.kch);
@@ -1092,7 +1099,6 @@ int launch_levels(const hps_op *op, bool fp32, const double *jump, const double 
 }
 
 // ---- two components on one operator (FP64) ----
-static void use_workspace(const hps_op *op, int l, bool up, const Workspace *ws, LevelArgs &a);
 
 static size_t sys_level_lds(const Panel &pn) {
     return carve_bytes({(size_t)2 * pn.S * pn.G * 8, (size_t)2 * pn.G * pn.rp * pn.vw * 8});

@@ -22,7 +22,7 @@ ERRORS = {-1: "HPS_EINVAL", -2: "HPS_ENOMEM", -3: "HPS_EDEVICE", -4: "HPS_ESINGU
 
 # every entry point declared in include/hps.h, include/hps_batch.h and include/hps_serve.h
 EXPORTED = ["hps_last_error", "hps_num_nodes", "hps_nodes", "hps_build", "hps_op_bytes",
-            "hps_solve", "hps_free", "hps_build_complex", "hps_profile_enable", "hps_profile_read", "ark_create", "ark_step", "ark_stage_solves_per_step",
+            "hps_solve", "hps_solve_noalloc", "hps_free", "hps_build_complex", "hps_profile_enable", "hps_profile_read", "ark_create", "ark_step", "ark_stage_solves_per_step",
             "ark_free", "ark_step_slope", "ark_step_burgers", "hps_solve_batched", "ark_step_batched", "hps_batch_streams",
             "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_release", "srv_get_stats", "srv_destroy"]
 
@@ -109,6 +109,8 @@ def lib():
     L.hps_op_bytes.argtypes = [vp, P(i64)]
     L.hps_solve.restype = i32
     L.hps_solve.argtypes = [vp, i32, vp, vp, vp, vp, vp, P(HpsInfo)]
+    L.hps_solve_noalloc.restype = i32
+    L.hps_solve_noalloc.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     L.hps_free.restype = None
     L.hps_free.argtypes = [vp]
     L.hps_profile_enable.restype = i32
@@ -267,6 +269,25 @@ def hps_build_complex(grid, coeffs_re, coeffs_im, gamma_dt, flags=HPS_FP64, stre
     _check(lib().hps_build_complex(ctypes.byref(grid), ctypes.byref(cr), ctypes.byref(ci), float(gamma_dt),
                                    int(flags), _stream(stream), ctypes.byref(h)))
     return HpsOp(h, grid, float(gamma_dt), flags, sizes, keep, ncomp=2)
+
+
+HPS_NOALLOC_SCRATCH_BYTES = 32 << 20   # the fixed device array of hps_solve_noalloc
+
+
+def hps_solve_noalloc(op, body, dirichlet=None, jump=None, u=None, stream=None):
+    """hps_solve without allocation in the library (FP64 real operators): its intermediate
+    data go to the library's fixed per-GPU scratch array.  body [nrhs, n_int] or [n_int];
+    u (output) is allocated here by torch unless given."""
+    import torch
+    squeeze = body.dim() == 1
+    nrhs = 1 if squeeze else body.shape[0]
+    if u is None:
+        u = torch.empty((op.N,) if squeeze else (nrhs, op.N), dtype=torch.float64, device=body.device)
+    _check(lib().hps_solve_noalloc(op.handle, nrhs, _dptr(body, nrhs * op.n_int, "body"),
+                                   _dptr(dirichlet, nrhs * op.n_bdry, "dirichlet"),
+                                   _dptr(jump, nrhs * op.n_iface, "jump"), _dptr(u, nrhs * op.N, "u"),
+                                   _stream(stream)))
+    return u
 
 
 def hps_solve_complex(op, body, dirichlet=None, jump=None, u=None, stream=None):
