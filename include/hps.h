@@ -59,12 +59,32 @@ extern "C" {
 /* hps_build flags */
 #define HPS_FP64     0   /* stored operators and their application in FP64          */
 #define HPS_FP32_IR  1   /* FP64 build; operators applied in FP32 inside an FP64
-                            iterative-refinement loop (residual in FP64)           */
+                            iterative-refinement loop (residual in FP64): corrections
+                            until ||delta||_inf <= 1e-11 ||u||_inf, at most 10; a solve
+                            that does not get there is redone with the FP64 operators,
+                            which the operator keeps (unless HPS_IR_STRICT)          */
 #define HPS_WIDE_TILES 2 /* or-ed with either: cut each tree level's operators into few
                             large row tiles (fewer workgroups per level).  For
                             operators stepped many at a time (ark_step_batched, the
                             server) and for two-component steps (ark_step_burgers);
                             one scalar problem runs at the same speed either way.   */
+#define HPS_IR_STRICT 8   /* or-ed with HPS_FP32_IR: a refinement that does not reach
+                            its tolerance is an error (HPS_ENOTCONVERGED) instead of
+                            being redone with the FP64 operators                    */
+#define HPS_TEST_FP32_SKEW 16 /* or-ed with HPS_FP32_IR, for tests of the refinement's
+                            failure handling only: the FP32 copy of every leaf inverse
+                            is stored multiplied by 1.5, so each correction removes only
+                            about half of the error and refinement cannot converge   */
+#define HPS_AUTOTUNE 32  /* or-ed with the others (not with HPS_WIDE_TILES): choose how finely
+                            every tree level's products are cut into workgroups by timing
+                            the candidates on the device: the first build of an operator
+                            class (grid shape, p, precision, real/complex, uniform
+                            coefficients) builds it with each candidate tiling and times
+                            hps_solve; the choice is kept for the process and, when the
+                            environment variable HPS_TUNE_FILE names a file, read from and
+                            written to it (JSON: class -> chosen minimum of workgroups per
+                            level and the measured microseconds per solve).  Results differ
+                            from untuned ones by rounding only.                        */
 #define HPS_UNIFORM_COEFFS 4 /* or-ed with the above: the caller states that every
                             coefficient of L is the same at every node (e.g. L = eps
                             Lap).  Then every leaf, and every node of one tree level,
@@ -91,6 +111,8 @@ typedef struct {
 typedef struct {
     int32_t ir_iterations;    /* FP32_IR: correction solves used by the last call       */
     double  last_correction;  /* FP32_IR: ||delta||_inf / ||u||_inf of the last one     */
+    int32_t fp64_fallbacks;   /* FP32_IR: solves of the last call that did not converge
+                                 and were redone with the FP64 operators                */
 } hps_info;
 
 typedef struct hps_op  hps_op;
@@ -243,6 +265,18 @@ HPS_API int ark_step_slope(ark_ctx *ctx, double t, double *u, const double *q_st
  * operator; HPS_EDEVICE for a failed launch. */
 HPS_API int ark_step_burgers(ark_ctx *cu, ark_ctx *cv, double t, double *u, double *v,
                              const double *fu_stages, const double *fv_stages, void *stream);
+
+/* Refinement record of the last ark_step on an FP32_IR operator: ir_iterations = the
+ * corrections per stage solve (the most any stage used), last_correction = the largest
+ * final ||delta||_inf / ||u||_inf over the stages, fp64_fallbacks = stages redone with the
+ * FP64 operators.  Zeros for FP64 operators.
+ * An FP32_IR ark_step of the stage formulation is replayed from a captured HIP graph with
+ * a fixed number of corrections per stage (the most the first, host-checked, step needed);
+ * after the replay the call waits for the stream and reads every stage's last correction
+ * norm: if one missed the tolerance, the step is redone from the saved u^n with
+ * host-checked refinement and FP64 re-solves where needed (HPS_IR_STRICT: HPS_ENOTCONVERGED
+ * instead, u then holds the unconverged step), and later steps use more corrections. */
+HPS_API int ark_info(const ark_ctx *ctx, hps_info *info);
 
 /* Number of implicit stage solves performed per ark_step (s - 1). */
 HPS_API int ark_stage_solves_per_step(const ark_ctx *ctx);

@@ -10,7 +10,14 @@
  *     unreferenced operators are evicted least-recently-used first when a build
  *     would exceed the cache budget;
  *   - admission: jobs are admitted first-come first-served while fewer than
- *     max_active jobs run and their operator fits in the budget;
+ *     max_active jobs run and their device memory fits in the budget: the operator
+ *     (when not cached) and the job's stepping context (its stage vectors L u_j, F_j,
+ *     its solve buffers and, for FP32_IR, its refinement vectors).  Contexts of
+ *     finished jobs are kept for later jobs of the same operator (at most four per
+ *     operator) and stay charged to the budget until they are reused or freed; to make
+ *     room, kept contexts are freed first, then unreferenced operators.  A job that
+ *     does not fit waits (in arrival order) until running jobs release memory; one
+ *     that could never fit fails with HPS_ENOMEM;
  *   - continuous batching: every iteration advances each running job by one step
  *     in a single ark_step_batched call (include/hps_batch.h), so jobs join and
  *     leave between steps and small problems overlap on the GPU.
@@ -72,9 +79,11 @@ typedef struct {
 typedef struct {
     int64_t submitted, completed, failed;
     int64_t builds, cache_hits, evictions;
-    int64_t cached_ops, cached_bytes;
+    int64_t cached_ops, cached_bytes;   /* operators held and their bytes              */
     int64_t iterations;     /* batched step calls made                                  */
     int64_t job_steps;      /* job steps taken                                          */
+    int64_t context_bytes;  /* bytes charged for stepping contexts (running and kept)  */
+    int64_t waits;          /* times the head of the queue waited for memory           */
 } srv_stats;
 
 /* Start a server on the current device.  cfg may be NULL (defaults). */

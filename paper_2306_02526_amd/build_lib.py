@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhps.so")
 SOURCES = ["hps_solve_kernels.hip", "hps_leaf_kernels.hip", "hps_cx_kernels.hip", "hps_build_kernels.hip",
            "hps_api.hip", "hps_drivers.hip", "hps_batch.hip", "hps_serve.hip",
-           "hps_noalloc.hip"]
+           "hps_noalloc.hip", "hps_tune.hip", "hps_compose.hip"]
 OBJDIR = os.path.join(HERE, "_build")
 
 

@@ -192,11 +192,15 @@ Panel shared_panel(Panel p) {
 
 // Workgroups a level's product is cut into at least: enough to fill the GPU for one
 // problem, or (HPS_WIDE_TILES) few and large when many problems share each launch.
-static int level_min_wg(int flags) { return (flags & HPS_WIDE_TILES) ? 32 : 1024; }
+// mwg > 0: the number chosen by the autotuner for this operator class.
+static int level_min_wg(int flags, int mwg = 0) {
+    if (mwg > 0) return mwg;
+    return (flags & HPS_WIDE_TILES) ? 32 : 1024;
+}
 
 // Bytes of the packed operators hps_build stores for a grid, from the same panel plans
 // (the tree splits the longer side of each box, ties with a vertical cut).
-int64_t plan_operator_bytes(const hps_grid &g, int flags, int ncomp) {
+int64_t plan_operator_bytes(const hps_grid &g, int flags, int ncomp, int mwg) {
     const int q = g.p - 2, q2 = q * q * ncomp, nl = g.n1 * g.n2;
     const bool ir = (flags & HPS_FP32_IR) != 0;
     const bool uni = (flags & HPS_UNIFORM_COEFFS) != 0;
@@ -211,11 +215,11 @@ int64_t plan_operator_bytes(const hps_grid &g, int flags, int ncomp) {
         const bool vert = w >= h;
         const int n3 = q * (vert ? h : w) * ncomp, n12 = 2 * q * (w + h) * ncomp;
         const int rows = root ? n3 : n3 + n12;
-        const int mwg = level_min_wg(flags);
-        bytes += sh(plan_panel(rows, n3, 2, nodes, 64, mwg)).bytes() + sh(plan_panel(n3, n12, 2, nodes, 64, mwg)).bytes();
+        const int lmw = level_min_wg(flags, mwg);
+        bytes += sh(plan_panel(rows, n3, 2, nodes, 64, lmw)).bytes() + sh(plan_panel(n3, n12, 2, nodes, 64, lmw)).bytes();
         if (ir)
-            bytes += sh(plan_panel(rows, n3, 4, nodes, 64, mwg)).bytes() +
-                     sh(plan_panel(n3, n12, 4, nodes, 64, mwg)).bytes();
+            bytes += sh(plan_panel(rows, n3, 4, nodes, 64, lmw)).bytes() +
+                     sh(plan_panel(n3, n12, 4, nodes, 64, lmw)).bytes();
         if (vert) w /= 2;
         else h /= 2;
         nodes *= 2;
@@ -306,11 +310,6 @@ struct Box {
     int i0, i1, j0, j1;
 };
 
-struct HostLevel {
-    int n1 = 0, n2 = 0, n3 = 0, nbc = 0;
-    std::vector<int> a1, a3, b2, b3;
-    std::vector<int> j3i;   // [nodes][n3]
-};
 
 static int plan_tree(const hps_op *op, std::vector<int> &leaf_ij, std::vector<HostLevel> &hl,
                      std::vector<int> &root_map, std::vector<int> &bnd_glob) {
@@ -635,7 +634,8 @@ static int build_impl(hps_op *op, const hps_coeffs *co, const hps_coeffs *co_im,
         op->sleaf32 = sh(plan_panel(q2, nb4, 4, nl, 256, 0));
         TRY(alloc_panel(op, op->ainv32));
         TRY(alloc_panel(op, op->sleaf32));
-        TRY(launch_pack(op->ainv32, Ainv, q2, (int64_t)q2 * q2, q2, nullptr, 0, 0, st));
+        TRY(launch_pack(op->ainv32, Ainv, q2, (int64_t)q2 * q2, q2, nullptr, 0, 0, st,
+                        (op->flags & HPS_TEST_FP32_SKEW) ? 1.5 : 1.0));
         TRY(launch_pack(op->sleaf32, S, q2, (int64_t)q2 * nb4, q2, nullptr, 0, 0, st));
     }
     tmp.release(Ainv);
@@ -647,6 +647,11 @@ static int build_impl(hps_op *op, const hps_coeffs *co, const hps_coeffs *co_im,
 
     // ---- merges, bottom-up (merge formulas after eqs. 7-8) ----
     op->lv.assign(op->L, Level{});
+    // level pairs swept through composite operators: the odd level's X, U, S are kept
+    // until its parent level (even) has been built, then both are multiplied out
+    op->composed = op->composed && compose_eligible(op, hl);
+    op->pairs.clear();
+    double *kX = nullptr, *kU = nullptr, *kS = nullptr;   // the kept lower level of a pair
     double *Tc = T;
     for (int l = op->L - 1; l >= 0; --l) {
         const HostLevel &H = hl[l];
@@ -687,7 +692,7 @@ static int build_impl(hps_op *op, const hps_coeffs *co, const hps_coeffs *co_im,
             TRY(launch_dgemm(n12, n12, n3, U, n12, s3x, B, n3, s3x, Tn, n12, sxx, nbuilt, 1.0, 1.0, st));
         }
         const int rows = root ? n3 : n3 + n12;
-        const int rpm = 64, mwg = level_min_wg(op->flags);
+        const int rpm = 64, mwg = level_min_wg(op->flags, op->level_mwg);
         Lv.xu64 = sh(plan_panel(rows, n3, 2, Lv.nodes, rpm, mwg));   // tiles planned for every node
         Lv.s64 = sh(plan_panel(n3, n12, 2, Lv.nodes, rpm, mwg));
         TRY(alloc_panel(op, Lv.xu64));
@@ -702,7 +707,24 @@ static int build_impl(hps_op *op, const hps_coeffs *co, const hps_coeffs *co_im,
             TRY(launch_pack(Lv.xu32, X, n3, s33, n3, U, n12, s3x, st));
             TRY(launch_pack(Lv.s32, Sx, n3, s3x, n3, nullptr, 0, 0, st));
         }
-        tmp.release(X); tmp.release(B); tmp.release(Cm); tmp.release(Sx); tmp.release(U);
+        tmp.release(B);
+        tmp.release(Cm);
+        if (op->composed && (l % 2 == 1)) {
+            kX = X;   // the lower level of pair (l - 1, l)
+            kU = U;
+            kS = Sx;
+        } else {
+            if (op->composed && l + 1 < op->L) {
+                TRY(compose_pair(op, l, hl, kX, kU, kS, X, U, Sx, st));
+                tmp.release(kX);
+                tmp.release(kU);
+                tmp.release(kS);
+                kX = kU = kS = nullptr;
+            }
+            tmp.release(X);
+            tmp.release(Sx);
+            tmp.release(U);
+        }
         Tc = Tn;
         // solve workspaces: every node of the level (not only the nodes whose operators were built)
         const int64_t lnodes = Lv.nodes;
@@ -735,10 +757,21 @@ static int build_impl(hps_op *op, const hps_coeffs *co, const hps_coeffs *co_im,
         hps_set_error("a zero pivot occurred while inverting a leaf or merge matrix");
         return HPS_ESINGULAR;
     }
-    // the host-side size plan (used to admit operators into a server's cache) must match
-    if (op->operator_bytes != plan_operator_bytes(op->grid, op->flags, m)) {
+    // the host-side size plan (used to admit operators into a server's cache) must match;
+    // composite pairs come on top of it
+    std::sort(op->pairs.begin(), op->pairs.end(), [](const PairOps &a, const PairOps &b) { return a.l < b.l; });
+    int64_t pair_bytes = 0;
+    for (size_t k = 0; k < op->pairs.size(); ++k) {
+        if (op->pairs[k].l != 2 * (int)k) {
+            hps_set_error("internal: composite pair %zu is for level %d", k, op->pairs[k].l);
+            return HPS_EDEVICE;
+        }
+        pair_bytes += op->pairs[k].up.bytes() + op->pairs[k].dn.bytes();
+    }
+    if (op->operator_bytes - pair_bytes != plan_operator_bytes(op->grid, op->flags, m, op->level_mwg)) {
         hps_set_error("internal: operator size plan %lld != allocated %lld",
-                      (long long)plan_operator_bytes(op->grid, op->flags, m), (long long)op->operator_bytes);
+                      (long long)plan_operator_bytes(op->grid, op->flags, m, op->level_mwg),
+                      (long long)(op->operator_bytes - pair_bytes));
         return HPS_EDEVICE;
     }
     return HPS_OK;
@@ -747,6 +780,7 @@ static int build_impl(hps_op *op, const hps_coeffs *co, const hps_coeffs *co_im,
 extern "C" void hps_free(hps_op *op) {
     if (!op) return;
     for (void *p : op->allocs) (void)hipFree(p);
+    for (Workspace *w : op->mws) delete w;
     delete op;
 }
 
@@ -757,7 +791,24 @@ static int build_op(const hps_grid *grid, const hps_coeffs *coeffs, const hps_co
     TRY(check_grid(grid));
     CHECK_ARG(coeffs != nullptr, "coeffs is NULL");
     CHECK_ARG(std::isfinite(gamma_dt) && gamma_dt > 0.0, "gamma_dt must be positive and finite");
-    CHECK_ARG((flags & ~(HPS_FP32_IR | HPS_WIDE_TILES | HPS_UNIFORM_COEFFS)) == 0, "unknown flags %d", flags);
+    CHECK_ARG((flags & ~(HPS_FP32_IR | HPS_WIDE_TILES | HPS_UNIFORM_COEFFS | HPS_IR_STRICT | HPS_TEST_FP32_SKEW |
+                         HPS_AUTOTUNE)) == 0,
+              "unknown flags %d", flags);
+    CHECK_ARG((flags & HPS_FP32_IR) || !(flags & (HPS_IR_STRICT | HPS_TEST_FP32_SKEW)),
+              "flags HPS_IR_STRICT and HPS_TEST_FP32_SKEW apply to HPS_FP32_IR operators only");
+    CHECK_ARG(!((flags & HPS_AUTOTUNE) && (flags & HPS_WIDE_TILES)),
+              "flags HPS_AUTOTUNE and HPS_WIDE_TILES exclude each other (the tuner times one problem per launch)");
+    int mwg = 0, compose = 0;
+    if (flags & HPS_AUTOTUNE) {
+        flags &= ~HPS_AUTOTUNE;
+        TRY(tune_level_tiling(grid, coeffs, coeffs_im, gamma_dt, flags, (hipStream_t)stream, &mwg, &compose));
+    }
+    return build_op_tiled(grid, coeffs, coeffs_im, gamma_dt, flags, mwg, compose, stream, out);
+}
+
+int hps::build_op_tiled(const hps_grid *grid, const hps_coeffs *coeffs, const hps_coeffs *coeffs_im,
+                        double gamma_dt, int flags, int mwg, int compose, void *stream, hps_op **out) {
+    *out = nullptr;
     const int ncomp = coeffs_im ? 2 : 1;
     if (ncomp == 2) {
         CHECK_ARG(!(flags & HPS_FP32_IR), "complex operators are FP64 only");
@@ -793,6 +844,10 @@ static int build_op(const hps_grid *grid, const hps_coeffs *coeffs, const hps_co
     op->h = (grid->x1 - grid->x0) / grid->n1;
     op->flags = flags;
     op->ncomp = ncomp;
+    op->level_mwg = mwg;
+    // composite pair sweeps: chosen by the tuner, or forced on with HPS_COMPOSE=1 (off with 0)
+    const char *cenv = getenv("HPS_COMPOSE");
+    op->composed = cenv && cenv[0] ? cenv[0] == '1' : compose != 0;
     int rc = build_impl(op, coeffs, coeffs_im, (hipStream_t)stream);
     if (rc) {
         (void)hipDeviceSynchronize();
@@ -823,7 +878,12 @@ extern "C" int64_t hps_op_bytes(const hps_op *op, int64_t *operator_bytes) {
         int64_t b = 0;
         const bool f32 = (op->flags & HPS_FP32_IR) != 0;
         b += (f32 ? op->ainv32 : op->ainv64).bytes() + (f32 ? op->sleaf32 : op->sleaf64).bytes();
-        for (const Level &L : op->lv) b += (f32 ? L.xu32 : L.xu64).bytes() + (f32 ? L.s32 : L.s64).bytes();
+        if (op->composed) {   // the composites, and the single bottom level of an odd tree
+            for (const PairOps &P : op->pairs) b += P.up.bytes() + P.dn.bytes();
+            if (op->L % 2 == 1) b += op->lv[op->L - 1].xu64.bytes() + op->lv[op->L - 1].s64.bytes();
+        } else {
+            for (const Level &L : op->lv) b += (f32 ? L.xu32 : L.xu64).bytes() + (f32 ? L.s32 : L.s64).bytes();
+        }
         *operator_bytes = b;   // bytes streamed by one solve in the op's working precision
     }
     return op->total_bytes;
@@ -876,9 +936,17 @@ extern "C" int ark_create(hps_op *op, const ark_tableau *tab, double dt, const a
     if (op->flags & HPS_FP32_IR) {
         if (int rc = dev_alloc<double>(nullptr, &c->rhs, op->n_int, false)) return fail(rc);
         if (int rc = dev_alloc<double>(nullptr, &c->stage_u, op->N, false)) return fail(rc);
+        if (int rc = dev_alloc<double>(nullptr, &c->ir_stat, (int64_t)s * IR_MAXIT * 2, false)) return fail(rc);
+        if (int rc = dev_alloc<double>(nullptr, &c->u_save, op->N, false)) return fail(rc);
     }
     *out = c;
     return HPS_OK;
+}
+
+int64_t hps::ark_ctx_footprint(const hps_op *op, int s) {
+    int64_t d = 2LL * s * op->ncomp * op->n_int + s;   // L u_j, F_j, the source's time factors
+    if (op->flags & HPS_FP32_IR) d += op->n_int + 2 * op->N + (int64_t)s * IR_MAXIT * 2;
+    return 8 * d + workspace_layout(op, nullptr, nullptr, nullptr, nullptr);
 }
 
 int hps::ark_slope_workspace(ark_ctx *c) {
@@ -965,7 +1033,7 @@ extern "C" void ark_free(ark_ctx *c) {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    for (double *p : {c->Lu, c->F, c->rhs, c->stage_u, c->qt_dev, c->K, c->Ls, c->Lk, c->Ll, c->Lun, c->srhs,
+    for (double *p : {c->Lu, c->F, c->rhs, c->stage_u, c->ir_stat, c->u_save, c->qt_dev, c->K, c->Ls, c->Lk, c->Ll, c->Lun, c->srhs,
                       c->pen})
         if (p) (void)hipFree(p);
     delete c;

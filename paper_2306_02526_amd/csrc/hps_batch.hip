@@ -121,6 +121,19 @@ int run_batched(const std::vector<const hps_op *> &ops, hipStream_t caller, Fn f
 // number of problems takes as many launches as a step of the largest one.  The argument
 // records live in device memory, built once per set of (context, u, source) pointers,
 // and the step is captured into a HIP graph and replayed while that set repeats.
+// An event shared by a retired plan and its pooled blocks, destroyed with its last holder.
+struct SharedEvent {
+    hipEvent_t e = nullptr;
+    int refs = 0;
+};
+
+void unref(SharedEvent *ev) {
+    if (ev && --ev->refs == 0) {
+        if (ev->e) (void)hipEventDestroy(ev->e);
+        delete ev;
+    }
+}
+
 struct GroupPlan {
     struct Launch {
         int kind;            // 0 leaf phase, 1 level up, 2 level down, 3 roots, 4 boundary, 5 lines
@@ -131,27 +144,104 @@ struct GroupPlan {
     };
     std::vector<uintptr_t> key;
     int s = 0, n = 0;
-    unsigned char *dmem = nullptr;
-    double *qt = nullptr;                // device [n][8] time factors of separable sources
+    unsigned char *dmem = nullptr;       // the records (a block of the pool)
+    size_t dbytes = 0;
+    unsigned char *qblk = nullptr;       // the separable sources' time factors (a pool block)
+    size_t qbytes = 0;
+    double *qt = nullptr;                // = qblk: device [n][8]
+    std::vector<unsigned char> host;     // host copy of the records (read by the upload)
     std::vector<Launch> leaf, sweep;
     Launch zb{}, lines{};
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    SharedEvent *done = nullptr;         // recorded after every launch of the plan
+    int uses = 0;
     uint64_t last_use = 0;
 };
 
+// Plans are cheap to replace: a new set of problems (every arrival or completion in a
+// server) takes its device blocks from a pool instead of hipMalloc (and an evicted plan's
+// blocks go back to it instead of hipFree, which would wait for the whole device); the
+// records are uploaded asynchronously behind the block's previous use; the first step of
+// a set runs without a graph (capture and instantiation pay off only for a set that
+// repeats); an evicted plan's graph is destroyed once its last launch has completed.
 std::mutex g_plans_mu;
 std::vector<GroupPlan *> g_plans;   // a few recent plans (each set of problems has one)
 uint64_t g_plan_clock = 0;
+constexpr size_t kMaxPlans = 4;
 
-void free_plan(GroupPlan *p) {
+struct PoolBlock {
+    unsigned char *p;
+    size_t bytes;
+    SharedEvent *last;   // completion of the block's last use (null if none)
+};
+std::vector<PoolBlock> g_blocks;    // free device blocks
+std::vector<GroupPlan *> g_retired; // evicted plans whose last launch may still run
+
+// A device block of at least `bytes`, usable on stream st (st first waits for its last use).
+int take_block(size_t bytes, hipStream_t st, unsigned char **out, size_t *got) {
+    size_t best = g_blocks.size();
+    for (size_t k = 0; k < g_blocks.size(); ++k)
+        if (g_blocks[k].bytes >= bytes && (best == g_blocks.size() || g_blocks[k].bytes < g_blocks[best].bytes))
+            best = k;
+    if (best < g_blocks.size()) {
+        PoolBlock b = g_blocks[best];
+        g_blocks.erase(g_blocks.begin() + (long)best);
+        hipError_t e = hipSuccess;
+        if (b.last) e = hipStreamWaitEvent(st, b.last->e, 0);
+        unref(b.last);
+        *out = b.p;
+        *got = b.bytes;
+        HPS_HIP(e);
+        return HPS_OK;
+    }
+    const size_t sz = std::max<size_t>((bytes + 65535) & ~size_t(65535), 65536);
+    void *p = nullptr;
+    if (hipMalloc(&p, sz) != hipSuccess) {
+        (void)hipGetLastError();
+        hps_set_error("hipMalloc of %zu bytes for grouped-launch records failed", sz);
+        return HPS_ENOMEM;
+    }
+    *out = (unsigned char *)p;
+    *got = sz;
+    return HPS_OK;
+}
+
+void destroy_plan_objects(GroupPlan *p) {
     if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->cap) (void)hipStreamDestroy(p->cap);
-    if (p->dmem) (void)hipFree(p->dmem);
-    if (p->qt) (void)hipFree(p->qt);
+    unref(p->done);
     delete p;
+}
+
+// Retire an evicted (or failed) plan: its blocks go back to the pool, each holding the
+// plan's completion event; the plan waits in g_retired until its last launch is done.
+void retire_plan(GroupPlan *p) {
+    SharedEvent *ev = p->uses > 0 ? p->done : nullptr;
+    for (auto blk : {std::make_pair(p->dmem, p->dbytes), std::make_pair(p->qblk, p->qbytes)}) {
+        if (!blk.first) continue;
+        if (ev) ev->refs++;
+        g_blocks.push_back(PoolBlock{blk.first, blk.second, ev});
+    }
+    p->dmem = p->qblk = nullptr;
+    g_retired.push_back(p);
+}
+
+// Destroy the retired plans whose last launch has completed (never waits).
+void reap_retired() {
+    for (size_t k = 0; k < g_retired.size();) {
+        GroupPlan *p = g_retired[k];
+        const bool busy = p->uses > 0 && p->done && hipEventQuery(p->done->e) != hipSuccess;
+        if (busy) {
+            (void)hipGetLastError();   // not ready is not an error here
+            ++k;
+            continue;
+        }
+        destroy_plan_objects(p);
+        g_retired.erase(g_retired.begin() + (long)k);
+    }
 }
 
 struct HostTables {
@@ -179,7 +269,7 @@ bool groupable(ark_ctx *const *ctx, int nprob, const double *const *q_stages, co
 }
 
 int build_plan(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, const double *const *q_stages,
-               const double *const *q_space) {
+               const double *const *q_space, hipStream_t st) {
     P->n = n;
     P->s = ctx[0]->s;
     // problems that share an operator each write a workspace of their own
@@ -191,8 +281,9 @@ int build_plan(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, const
             TRY(ctx_workspace(ctx[b]));
             ws[b] = ctx[b]->ws;
         }
-    HPS_HIP(hipMalloc(&P->qt, sizeof(double) * 8 * n));
-    HPS_HIP(hipMemset(P->qt, 0, sizeof(double) * 8 * n));
+    TRY(take_block(sizeof(double) * 8 * n, st, &P->qblk, &P->qbytes));
+    P->qt = reinterpret_cast<double *>(P->qblk);
+    TRY(launch_zero(P->qt, 8 * (int64_t)n, st));
     HostTables T;
     std::vector<int> base(n + 1);
     // leaf phases
@@ -290,8 +381,12 @@ int build_plan(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, const
         P->lines = GroupPlan::Launch{5, T.put(lrec.data(), lrec.size()), 0, T.put(lb.data(), sizeof(int) * (n + 1)),
                                      n, lb[n], 0, 0, 0};
     }
-    HPS_HIP(hipMalloc(&P->dmem, std::max<size_t>(T.bytes.size(), 256)));
-    HPS_HIP(hipMemcpy(P->dmem, T.bytes.data(), T.bytes.size(), hipMemcpyHostToDevice));
+    P->host.swap(T.bytes);
+    TRY(take_block(std::max<size_t>(P->host.size(), 256), st, &P->dmem, &P->dbytes));
+    HPS_HIP(hipMemcpyAsync(P->dmem, P->host.data(), P->host.size(), hipMemcpyHostToDevice, st));
+    P->done = new SharedEvent();
+    P->done->refs = 1;
+    HPS_HIP(hipEventCreateWithFlags(&P->done->e, hipEventDisableTiming));
     return HPS_OK;
 }
 
@@ -326,21 +421,21 @@ int grouped_step(ark_ctx *const *ctx, int n, double *const *u, const double *con
         key.push_back((uintptr_t)(q_space ? q_space[b] : nullptr));
     }
     std::lock_guard<std::mutex> g(g_plans_mu);
+    reap_retired();
     GroupPlan *P = nullptr;
     for (GroupPlan *p : g_plans)
         if (p->key == key) P = p;
     if (!P) {
-        if (g_plans.size() >= 4) {
+        if (g_plans.size() >= kMaxPlans) {
             auto lru = std::min_element(g_plans.begin(), g_plans.end(),
                                         [](GroupPlan *a, GroupPlan *b) { return a->last_use < b->last_use; });
-            HPS_HIP(hipStreamSynchronize(st));
-            free_plan(*lru);
+            retire_plan(*lru);
             g_plans.erase(lru);
         }
         P = new GroupPlan();
         P->key = key;
-        if (int rc = build_plan(P, ctx, n, u, q_stages, q_space)) {
-            free_plan(P);
+        if (int rc = build_plan(P, ctx, n, u, q_stages, q_space, st)) {
+            retire_plan(P);
             return rc;
         }
         g_plans.push_back(P);
@@ -358,22 +453,28 @@ int grouped_step(ark_ctx *const *ctx, int n, double *const *u, const double *con
         if (any) HPS_HIP(hipMemcpyAsync(P->qt, qt.data(), sizeof(double) * qt.size(), hipMemcpyHostToDevice, st));
     }
     const char *env = getenv("HPS_GRAPHS");
-    if (env && env[0] == '0') return enqueue_plan(P, st);
-    if (!P->gexec) {
-        if (!P->cap) HPS_HIP(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
-        HPS_HIP(hipStreamBeginCapture(P->cap, hipStreamCaptureModeRelaxed));
-        const int rc = enqueue_plan(P, P->cap);
-        hipGraph_t gr = nullptr;
-        const hipError_t e = hipStreamEndCapture(P->cap, &gr);
-        if (rc) {
-            if (gr) (void)hipGraphDestroy(gr);
-            return rc;
+    const bool graphs = !(env && env[0] == '0') && P->uses > 0;   // a set's first step runs eagerly
+    P->uses++;
+    if (!graphs) {
+        TRY(enqueue_plan(P, st));
+    } else {
+        if (!P->gexec) {
+            if (!P->cap) HPS_HIP(hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking));
+            HPS_HIP(hipStreamBeginCapture(P->cap, hipStreamCaptureModeRelaxed));
+            const int rc = enqueue_plan(P, P->cap);
+            hipGraph_t gr = nullptr;
+            const hipError_t e = hipStreamEndCapture(P->cap, &gr);
+            if (rc) {
+                if (gr) (void)hipGraphDestroy(gr);
+                return rc;
+            }
+            HPS_HIP(e);
+            P->graph = gr;
+            HPS_HIP(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
         }
-        HPS_HIP(e);
-        P->graph = gr;
-        HPS_HIP(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
+        HPS_HIP(hipGraphLaunch(P->gexec, st));
     }
-    HPS_HIP(hipGraphLaunch(P->gexec, st));
+    HPS_HIP(hipEventRecord(P->done->e, st));
     return HPS_OK;
 }
 

@@ -572,6 +572,7 @@ struct PackArgs {
     const double *src0; int ld0; int64_t stride0; int rows0;
     const double *src1; int ld1; int64_t stride1;
     void *dst;
+    double scale;
 };
 
 template <typename T>
@@ -595,7 +596,7 @@ __global__ void k_pack(PackArgs a) {
         if (row < a.rows0) val = a.src0[node * a.stride0 + (int64_t)col * a.ld0 + row];
         else val = a.src1[node * a.stride1 + (int64_t)col * a.ld1 + (row - a.rows0)];
     }
-    reinterpret_cast<T *>(a.dst)[idx] = (T)val;
+    reinterpret_cast<T *>(a.dst)[idx] = (T)(val * a.scale);
 }
 
 // =======================================================================================
@@ -709,7 +710,7 @@ int launch_dgemm(int M, int N, int K, const double *A, int lda, int64_t sA, cons
 }
 
 int launch_pack(const Panel &pn, const double *src0, int ld0, int64_t stride0, int rows0,
-                const double *src1, int ld1, int64_t stride1, hipStream_t st) {
+                const double *src1, int ld1, int64_t stride1, hipStream_t st, double scale) {
     PackArgs a{};
     a.R = pn.R; a.C = pn.C; a.vw = pn.vw; a.rp = pn.rp; a.G = pn.G; a.S = pn.S;
     a.ntile = pn.ntile; a.kch = pn.kch;
@@ -718,6 +719,7 @@ int launch_pack(const Panel &pn, const double *src0, int ld0, int64_t stride0, i
     a.src0 = src0; a.ld0 = ld0; a.stride0 = stride0; a.rows0 = rows0;
     a.src1 = src1; a.ld1 = ld1; a.stride1 = stride1;
     a.dst = pn.data;
+    a.scale = scale;
     if (pn.vw == 2) hipLaunchKernelGGL(k_pack<double>, dim3(nblk(a.total)), dim3(NT), 0, st, a);
     else hipLaunchKernelGGL(k_pack<float>, dim3(nblk(a.total)), dim3(NT), 0, st, a);
     HPS_LAUNCHED();

@@ -1,0 +1,349 @@
+// Composite operators of level pairs: the products of two adjacent tree levels of the
+// merge formulas after eqs. (7)-(8) and of Algorithm 1 (Sec. 2.1), multiplied out once at
+// build time so that one launch per direction sweeps both levels.
+//
+// Notation for an upper node tau (level l) with children alpha = 2 tau, beta = 2 tau + 1
+// (level l + 1): X, U, S are the stored per-level operators (w3 = X d, h = [h1; h2] + U d,
+// u3 = S u12 + w3); a1, a3, b2, b3 are the upper level's maps (tau's boundary m < n1 is
+// alpha's boundary position a1[m], otherwise beta's b2[m - n1]; tau's J3 index k is alpha's
+// position a3[k] and beta's b3[k]).
+//
+// Upward, with d_a, d_b the children's interface differences and e the node's difference
+// of the fluxes its children pass through unchanged,
+//   d_tau = e + U_b[b3, :] d_b - U_a[a3, :] d_a = V [d_a; d_b; e],  V = [-U_a[a3,:] | U_b[b3,:] | I],
+// so [w3_a; w3_b; w3_tau; h_tau - pass-through] = M_up [d_a; d_b; e] with
+//   M_up = [ X_a 0 0 ; 0 X_b 0 ; X_tau V ; [U_a[a1,:] | U_b[b2,:] | 0] (row blocks J1, J2) + U_tau V ].
+// Downward, with the node's boundary values u12 and w3_tau,
+//   u3_tau = S_tau u12 + w3_tau,
+//   u3_a = S_a[:, a1] u12|J1 + S_a[:, a3] u3_tau + w3_a = ([S_a[:, a1 | 0]] + S_a[:, a3] [S_tau | I]) [u12; w3_tau] + w3_a,
+// so M_dn = [ S_tau 0 ; S_a[:, a1 | 0] + S_a[:, a3] W ; S_b[:, 0 | b2] + S_b[:, b3] W ],  W = [S_tau | I],
+// with the own-level w3 added when the rows are finalised.  The top pair takes the
+// Dirichlet data f (the root's boundary values) and the differences below it:
+//   u3_root = [S_root | X_root V] [f; d_a; d_b; e],  u3_a = [S_a[:, a1 | 0] | X_a | 0 | 0] [...] + S_a[:, a3] u3_root, ...
+// The index tables that go with each composite are built here too (see PairArgs).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <vector>
+
+#include "hps_internal.h"
+
+using namespace hps;
+
+namespace hps {
+
+// dst[b][(c0 + j) * ldd + r0 + i] (+)= scale * src[b * sstr + cc * lds + rr], rr = ri ? ri[i] : i,
+// cc = cj ? cj[j] : j; a negative index reads zero; src == null reads the identity.
+struct PlaceArgs {
+    double *dst;
+    int ldd;
+    int64_t dstr;
+    int r0, c0, rows, cols;
+    const double *src;
+    int lds;
+    int64_t sstr;
+    const int *ri, *cj;
+    double scale;
+    int accumulate;
+};
+
+__global__ void k_place(PlaceArgs a) {
+    const int64_t n = (int64_t)a.rows * a.cols;
+    const int b = blockIdx.y;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(t % a.rows), j = (int)(t / a.rows);
+        const int rr = a.ri ? a.ri[i] : i, cc = a.cj ? a.cj[j] : j;
+        double v = 0.0;
+        if (rr >= 0 && cc >= 0) v = a.src ? a.src[(int64_t)b * a.sstr + (int64_t)cc * a.lds + rr] : (rr == cc ? 1.0 : 0.0);
+        double *d = a.dst + (int64_t)b * a.dstr + (int64_t)(a.c0 + j) * a.ldd + a.r0 + i;
+        *d = a.accumulate ? *d + a.scale * v : a.scale * v;
+    }
+}
+
+int launch_place(double *dst, int ldd, int64_t dstr, int r0, int c0, int rows, int cols, const double *src, int lds,
+                 int64_t sstr, const int *ri, const int *cj, double scale, bool accumulate, int batch, hipStream_t st) {
+    if (rows <= 0 || cols <= 0 || batch <= 0) return HPS_OK;
+    PlaceArgs a{dst, ldd, dstr, r0, c0, rows, cols, src, lds, sstr, ri, cj, scale, accumulate ? 1 : 0};
+    const int64_t n = (int64_t)rows * cols;
+    const unsigned gx = (unsigned)std::min<int64_t>((n + NT - 1) / NT, 1024);
+    hipLaunchKernelGGL(k_place, dim3(gx, batch), dim3(NT), 0, st, a);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+}  // namespace hps
+
+namespace {
+
+// grandchild offsets (relative to the node's four grandchildren, nbcc entries each) of
+// alpha's / beta's boundary position j
+struct Pos {
+    const HostLevel &c;
+    int nbcc;
+    int a(int j) const { return j < c.n1 ? c.a1[j] : nbcc + c.b2[j - c.n1]; }
+    int b(int j) const { return j < c.n1 ? 2 * nbcc + c.a1[j] : 3 * nbcc + c.b2[j - c.n1]; }
+};
+
+struct DevScratch {
+    std::vector<void *> p;
+    ~DevScratch() {
+        for (void *q : p) (void)hipFree(q);
+    }
+    template <typename T>
+    int get(T **out, int64_t n) {
+        void *q = nullptr;
+        if (hipMalloc(&q, sizeof(T) * std::max<int64_t>(n, 1)) != hipSuccess) {
+            (void)hipGetLastError();
+            hps_set_error("hipMalloc of %lld bytes for composite operators failed", (long long)(sizeof(T) * n));
+            return HPS_ENOMEM;
+        }
+        p.push_back(q);
+        *out = (T *)q;
+        return HPS_OK;
+    }
+    template <typename T>
+    int upload(T **out, const std::vector<T> &v, hipStream_t st) {
+        TRY(get(out, (int64_t)v.size()));
+        HPS_HIP(hipMemcpyAsync(*out, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+        return HPS_OK;
+    }
+};
+
+int64_t level_nodes(int l) { return int64_t(1) << l; }
+
+}  // namespace
+
+static int pair_min_wg(const hps_op *op) { return op->level_mwg > 0 ? op->level_mwg : 1024; }
+
+// Composites need one workgroup's input vector in LDS (no split-K), FP64 real per-node
+// operators and at least the root and one level below it.
+bool hps::compose_eligible(const hps_op *op, const std::vector<HostLevel> &hl) {
+    if (op->ncomp != 1 || op->build_one || (op->flags & (HPS_FP32_IR | HPS_WIDE_TILES)) || op->L < 2) return false;
+    // the top pair (0, 1), then (2, 3), (4, 5), ... while the lower level exists
+    for (int l = 0; l + 1 < op->L; l += 2) {
+        const HostLevel &t = hl[l], &c = hl[l + 1];
+        const int n12t = t.n1 + t.n2, nt = (int)level_nodes(l);
+        const int CV = 2 * c.n3 + t.n3;
+        if (l == 0) {
+            if (plan_panel(t.n3 + 2 * c.n3, n12t + CV, 2, 1, 64, pair_min_wg(op)).kch != 1) return false;
+        } else if (plan_panel(CV + n12t, CV, 2, nt, 64, pair_min_wg(op)).kch != 1 ||
+                   plan_panel(t.n3 + 2 * c.n3, n12t + t.n3, 2, nt, 64, pair_min_wg(op)).kch != 1) {
+            return false;
+        }
+    }
+    return true;
+}
+
+int hps::compose_pair(hps_op *op, int l, const std::vector<HostLevel> &hl, const double *Xc, const double *Uc,
+                      const double *Sc, const double *Xt, const double *Ut, const double *St, hipStream_t st) {
+    const HostLevel &T = hl[l], &Cl = hl[l + 1];
+    const int n3t = T.n3, n1t = T.n1, n12t = T.n1 + T.n2;
+    const int n3c = Cl.n3, n12c = Cl.n1 + Cl.n2;   // a child's boundary length = the child level's n12
+    // grandchildren: level l + 2 nodes (or leaves), boundary length = the lower level's nbc
+    const int nbcc = Cl.nbc;
+    const Pos pos{Cl, nbcc};
+    const int nt = (int)level_nodes(l);
+    const bool top = (l == 0);
+    const int mwg = pair_min_wg(op);
+    DevScratch tmp;
+    // index vectors on the device: the upper level's maps, padded to its boundary length
+    std::vector<int> a1pad(n12t, -1), b2pad(n12t, -1);
+    for (int m = 0; m < n1t; ++m) a1pad[m] = T.a1[m];
+    for (int m = n1t; m < n12t; ++m) b2pad[m] = T.b2[m - n1t];
+    int *d_a3, *d_b3, *d_a1pad, *d_b2pad;
+    TRY(tmp.upload(&d_a3, T.a3, st));
+    TRY(tmp.upload(&d_b3, T.b3, st));
+    TRY(tmp.upload(&d_a1pad, a1pad, st));
+    TRY(tmp.upload(&d_b2pad, b2pad, st));
+    const int64_t sX = (int64_t)n3c * n3c, sU = (int64_t)n12c * n3c, sS = (int64_t)n3c * n12c;   // per child
+    const double *Xa = Xc, *Xb = Xc + sX, *Ua = Uc, *Ub = Uc + sU, *Sa = Sc, *Sb = Sc + sS;
+
+    PairOps P;
+    P.l = l;
+    // V = [-U_a[a3,:] | U_b[b3,:] | I]  (n3t x (2 n3c + n3t)) per node
+    const int CV = 2 * n3c + n3t;
+    double *V;
+    TRY(tmp.get(&V, (int64_t)n3t * CV * nt));
+    const int64_t sV = (int64_t)n3t * CV;
+    TRY(launch_place(V, n3t, sV, 0, 0, n3t, n3c, Ua, n12c, 2 * sU, d_a3, nullptr, -1.0, false, nt, st));
+    TRY(launch_place(V, n3t, sV, 0, n3c, n3t, n3c, Ub, n12c, 2 * sU, d_b3, nullptr, 1.0, false, nt, st));
+    TRY(launch_place(V, n3t, sV, 0, 2 * n3c, n3t, n3t, nullptr, 0, 0, nullptr, nullptr, 1.0, false, nt, st));
+    // the children's S restricted to the upper node's J3 columns
+    double *Sa3, *Sb3;
+    TRY(tmp.get(&Sa3, (int64_t)n3c * n3t * nt));
+    TRY(tmp.get(&Sb3, (int64_t)n3c * n3t * nt));
+    const int64_t s3 = (int64_t)n3c * n3t;
+    TRY(launch_place(Sa3, n3c, s3, 0, 0, n3c, n3t, Sa, n3c, 2 * sS, nullptr, d_a3, 1.0, false, nt, st));
+    TRY(launch_place(Sb3, n3c, s3, 0, 0, n3c, n3t, Sb, n3c, 2 * sS, nullptr, d_b3, 1.0, false, nt, st));
+
+    double *Mup = nullptr, *Mdn = nullptr;
+    if (!top) {
+        // ---- upward composite [w3_a; w3_b; w3_tau; h_tau] x [d_a; d_b; e] ----
+        const int R = 2 * n3c + n3t + n12t, C = CV;
+        const int64_t sM = (int64_t)R * C;
+        TRY(tmp.get(&Mup, sM * nt));
+        TRY(launch_zero(Mup, sM * nt, st));
+        TRY(launch_place(Mup, R, sM, 0, 0, n3c, n3c, Xa, n3c, 2 * sX, nullptr, nullptr, 1.0, false, nt, st));
+        TRY(launch_place(Mup, R, sM, n3c, n3c, n3c, n3c, Xb, n3c, 2 * sX, nullptr, nullptr, 1.0, false, nt, st));
+        TRY(launch_dgemm(n3t, C, n3t, Xt, n3t, (int64_t)n3t * n3t, V, n3t, sV, Mup + 2 * n3c, R, sM, nt, 1.0, 0.0, st));
+        const int h0 = 2 * n3c + n3t;
+        TRY(launch_place(Mup, R, sM, h0, 0, n12t, n3c, Ua, n12c, 2 * sU, d_a1pad, nullptr, 1.0, false, nt, st));
+        TRY(launch_place(Mup, R, sM, h0, n3c, n12t, n3c, Ub, n12c, 2 * sU, d_b2pad, nullptr, 1.0, false, nt, st));
+        TRY(launch_dgemm(n12t, C, n3t, Ut, n12t, (int64_t)n12t * n3t, V, n3t, sV, Mup + h0, R, sM, nt, 1.0, 1.0, st));
+        P.R_up = R;
+        P.C_up = C;
+        // ---- downward composite [u3_tau; u3_a; u3_b] x [u12; w3_tau] ----
+        const int Rd = n3t + 2 * n3c, Cd = n12t + n3t;
+        const int64_t sD = (int64_t)Rd * Cd;
+        double *W;
+        TRY(tmp.get(&W, (int64_t)n3t * Cd * nt));
+        const int64_t sW = (int64_t)n3t * Cd;
+        TRY(launch_place(W, n3t, sW, 0, 0, n3t, n12t, St, n3t, (int64_t)n3t * n12t, nullptr, nullptr, 1.0, false, nt, st));
+        TRY(launch_place(W, n3t, sW, 0, n12t, n3t, n3t, nullptr, 0, 0, nullptr, nullptr, 1.0, false, nt, st));
+        TRY(tmp.get(&Mdn, sD * nt));
+        TRY(launch_zero(Mdn, sD * nt, st));
+        TRY(launch_place(Mdn, Rd, sD, 0, 0, n3t, n12t, St, n3t, (int64_t)n3t * n12t, nullptr, nullptr, 1.0, false, nt,
+                         st));
+        TRY(launch_place(Mdn, Rd, sD, n3t, 0, n3c, n12t, Sa, n3c, 2 * sS, nullptr, d_a1pad, 1.0, false, nt, st));
+        TRY(launch_place(Mdn, Rd, sD, n3t + n3c, 0, n3c, n12t, Sb, n3c, 2 * sS, nullptr, d_b2pad, 1.0, false, nt, st));
+        TRY(launch_dgemm(n3c, Cd, n3t, Sa3, n3c, s3, W, n3t, sW, Mdn + n3t, Rd, sD, nt, 1.0, 1.0, st));
+        TRY(launch_dgemm(n3c, Cd, n3t, Sb3, n3c, s3, W, n3t, sW, Mdn + n3t + n3c, Rd, sD, nt, 1.0, 1.0, st));
+        P.R_dn = Rd;
+        P.C_dn = Cd;
+    } else {
+        // ---- the top pair: [u3_root; u3_a; u3_b] x [f; d_a; d_b; e] ----
+        const int R = n3t + 2 * n3c, C = n12t + CV;
+        const int64_t sM = (int64_t)R * C;
+        TRY(tmp.get(&Mdn, sM));
+        TRY(launch_zero(Mdn, sM, st));
+        TRY(launch_place(Mdn, R, sM, 0, 0, n3t, n12t, St, n3t, 0, nullptr, nullptr, 1.0, false, 1, st));
+        TRY(launch_dgemm(n3t, CV, n3t, Xt, n3t, 0, V, n3t, 0, Mdn + (int64_t)n12t * R, R, 0, 1, 1.0, 0.0, st));
+        TRY(launch_place(Mdn, R, sM, n3t, 0, n3c, n12t, Sa, n3c, 0, nullptr, d_a1pad, 1.0, false, 1, st));
+        TRY(launch_place(Mdn, R, sM, n3t, n12t, n3c, n3c, Xa, n3c, 0, nullptr, nullptr, 1.0, false, 1, st));
+        TRY(launch_place(Mdn, R, sM, n3t + n3c, 0, n3c, n12t, Sb, n3c, 0, nullptr, d_b2pad, 1.0, false, 1, st));
+        TRY(launch_place(Mdn, R, sM, n3t + n3c, n12t + n3c, n3c, n3c, Xb, n3c, 0, nullptr, nullptr, 1.0, false, 1, st));
+        // the children's rows: + S_a[:, a3] u3_root (the root rows, already complete)
+        TRY(launch_dgemm(n3c, C, n3t, Sa3, n3c, 0, Mdn, R, 0, Mdn + n3t, R, 0, 1, 1.0, 1.0, st));
+        TRY(launch_dgemm(n3c, C, n3t, Sb3, n3c, 0, Mdn, R, 0, Mdn + n3t + n3c, R, 0, 1, 1.0, 1.0, st));
+        P.R_dn = R;
+        P.C_dn = C;
+    }
+
+    // ---- pack (streaming layout, FP64) ----
+    auto pack = [&](Panel &pn, const double *M, int R, int C) -> int {
+        pn = plan_panel(R, C, 2, nt, 64, mwg);
+        double *d;
+        if (hipMalloc(&d, sizeof(double) * pn.node_elems * pn.nodes) != hipSuccess) {
+            (void)hipGetLastError();
+            hps_set_error("hipMalloc for a composite operator failed");
+            return HPS_ENOMEM;
+        }
+        op->allocs.push_back(d);
+        op->operator_bytes += pn.bytes();
+        op->total_bytes += pn.bytes();
+        pn.data = d;
+        if (pn.kch != 1 || pn.rp * pn.vw > NT) {
+            hps_set_error("internal: a composite operator was planned with column chunks");
+            return HPS_EDEVICE;
+        }
+        return launch_pack(pn, M, R, (int64_t)R * C, R, nullptr, 0, 0, st);
+    };
+    if (!top) TRY(pack(P.up, Mup, P.R_up, P.C_up));
+    TRY(pack(P.dn, Mdn, P.R_dn, P.C_dn));
+
+    // ---- index tables ----
+    std::vector<int> tab;
+    auto put = [&](const std::vector<int> &v) {
+        const int off = (int)tab.size();
+        tab.insert(tab.end(), v.begin(), v.end());
+        return off;
+    };
+    const int Cg = top ? P.C_dn : P.C_up;    // columns of the gather from the grandchildren's fluxes
+    const int g0 = top ? n12t : 0;           // the first such column
+    std::vector<int> plus(Cg, 0), minus(Cg, 0), j3(Cg, 0);
+    for (int k = 0; k < n3c; ++k) {
+        plus[g0 + k] = nbcc + Cl.b3[k];
+        minus[g0 + k] = Cl.a3[k];
+        j3[g0 + k] = k;
+        plus[g0 + n3c + k] = 3 * nbcc + Cl.b3[k];
+        minus[g0 + n3c + k] = 2 * nbcc + Cl.a3[k];
+        j3[g0 + n3c + k] = n3c + k;
+    }
+    for (int k = 0; k < n3t; ++k) {
+        plus[g0 + 2 * n3c + k] = pos.b(T.b3[k]);
+        minus[g0 + 2 * n3c + k] = pos.a(T.a3[k]);
+        j3[g0 + 2 * n3c + k] = -(k + 1);
+    }
+    P.t_plus = put(plus);
+    P.t_minus = put(minus);
+    P.t_j3 = put(j3);
+    if (!top) {
+        std::vector<int> fin(3 * (size_t)P.R_up, 0);
+        for (int r = 0; r < P.R_up; ++r) {
+            int kind, idx, pass = 0;
+            if (r < 2 * n3c) {
+                kind = 0;
+                idx = r;
+            } else if (r < 2 * n3c + n3t) {
+                kind = 1;
+                idx = r - 2 * n3c;
+            } else {
+                kind = 2;
+                idx = r - 2 * n3c - n3t;
+                pass = idx < n1t ? pos.a(T.a1[idx]) : pos.b(T.b2[idx - n1t]);
+            }
+            fin[3 * r] = kind;
+            fin[3 * r + 1] = idx;
+            fin[3 * r + 2] = pass;
+        }
+        P.t_fin_up = put(fin);
+    }
+    {
+        std::vector<int> fin(4 * (size_t)P.R_dn, 0);
+        for (int r = 0; r < P.R_dn; ++r) {
+            int kind, idx, p1, p2;
+            if (r < n3t) {
+                kind = top ? -1 : 1;
+                idx = r;
+                p1 = pos.a(T.a3[r]);
+                p2 = pos.b(T.b3[r]);
+            } else if (r < n3t + n3c) {
+                const int k = r - n3t;
+                kind = top ? -1 : 0;
+                idx = k;
+                p1 = Cl.a3[k];
+                p2 = nbcc + Cl.b3[k];
+            } else {
+                const int k = r - n3t - n3c;
+                kind = top ? -1 : 0;
+                idx = n3c + k;
+                p1 = 2 * nbcc + Cl.a3[k];
+                p2 = 3 * nbcc + Cl.b3[k];
+            }
+            fin[4 * r] = kind;
+            fin[4 * r + 1] = idx;
+            fin[4 * r + 2] = p1;
+            fin[4 * r + 3] = p2;
+        }
+        P.t_fin_dn = put(fin);
+    }
+    {
+        std::vector<int> copy(n12t);
+        for (int m = 0; m < n12t; ++m) copy[m] = m < n1t ? pos.a(T.a1[m]) : pos.b(T.b2[m - n1t]);
+        P.t_copy = put(copy);
+    }
+    int *d_tab;
+    if (hipMalloc(&d_tab, sizeof(int) * tab.size()) != hipSuccess) {
+        (void)hipGetLastError();
+        hps_set_error("hipMalloc for composite tables failed");
+        return HPS_ENOMEM;
+    }
+    op->allocs.push_back(d_tab);
+    HPS_HIP(hipMemcpyAsync(d_tab, tab.data(), sizeof(int) * tab.size(), hipMemcpyHostToDevice, st));
+    P.tab = d_tab;
+    // the scratch above is freed at return: the stream must be done with it
+    HPS_HIP(hipStreamSynchronize(st));
+    op->pairs.push_back(P);
+    return HPS_OK;
+}

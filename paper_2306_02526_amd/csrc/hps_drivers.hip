@@ -27,43 +27,85 @@ static double ordered_bits_to_double(unsigned long long v) {
     return d;
 }
 
-// FP32 operators inside FP64 iterative refinement: u = HPS32(rhs) has been computed;
-// repeat { r = FP64 residual of the global system (interior rows and interface flux
-// jumps); u += HPS32(r) } until max|delta| <= tol max|u|.
-static int ir_refine(hps_op *op, const double *rhs, const double *jump, double *u, hipStream_t st,
-                     hps_info *info) {
-    const double tol = 1e-11;
-    const int maxit = 10;
-    int it = 0;
-    double rel = 0.0;
-    for (it = 1; it <= maxit; ++it) {
-        TRY(launch_residual(op, u, rhs, jump, op->ir_r, op->ir_r3, st));
-        HPS_HIP(hipMemsetAsync(op->ir_norms, 0, 2 * sizeof(double), st));
-        LeafPhase up;
-        up.up = LU_BODY;
-        up.body = op->ir_r;
-        TRY(launch_leaf(op, true, up, st));
-        TRY(levels(op, true, op->n_iface ? op->ir_r3 : nullptr, nullptr, st));
-        LeafPhase dn;
-        dn.down = LD_IR_ADD;
-        dn.u_out = u;
-        TRY(launch_leaf(op, true, dn, st));
+// One correction pass of FP64 iterative refinement around the FP32 operators:
+// r = FP64 residual of the global system (interior rows rhs - (I - gamma dt L) u and the
+// interface flux jumps), delta = HPS32(r) with zero boundary data, u += delta.  The pass's
+// max|delta| and max|u| are accumulated into norms[0..1] (ordered bit patterns of
+// non-negative doubles, zero beforehand).
+static int ir_pass(hps_op *op, const double *rhs, const double *jump, double *u, double *norms, hipStream_t st) {
+    TRY(launch_residual(op, u, rhs, jump, op->ir_r, op->ir_r3, st));
+    LeafPhase up;
+    up.up = LU_BODY;
+    up.body = op->ir_r;
+    TRY(launch_leaf(op, true, up, st));
+    TRY(levels(op, true, op->n_iface ? op->ir_r3 : nullptr, nullptr, st));
+    LeafPhase dn;
+    dn.down = LD_IR_ADD;
+    dn.u_out = u;
+    dn.norms = norms;
+    return launch_leaf(op, true, dn, st);
+}
+
+// max|delta| / max|u| of one pass from its two ordered-bit words; converged when
+// max|delta| <= IR_TOL max|u|
+static bool ir_converged(const unsigned long long nb[2], double *rel) {
+    const double dmax = ordered_bits_to_double(nb[0]), umax = ordered_bits_to_double(nb[1]);
+    *rel = umax > 0 ? dmax / umax : dmax;
+    return dmax <= IR_TOL * umax;
+}
+
+// Corrections until converged (at most IR_MAXIT), the host reading each pass's norms.
+// *passes: corrections run; returns whether the last one met the tolerance.
+static int ir_adaptive(hps_op *op, const double *rhs, const double *jump, double *u, hipStream_t st, int *passes,
+                       double *rel, bool *ok) {
+    *ok = false;
+    for (int it = 1; it <= IR_MAXIT; ++it) {
+        TRY(launch_zero(op->ir_norms, 2, st));
+        TRY(ir_pass(op, rhs, jump, u, op->ir_norms, st));
         unsigned long long nb[2];
         HPS_HIP(hipMemcpyAsync(nb, op->ir_norms, sizeof(nb), hipMemcpyDeviceToHost, st));
         HPS_HIP(hipStreamSynchronize(st));
-        const double dmax = ordered_bits_to_double(nb[0]), umax = ordered_bits_to_double(nb[1]);
-        rel = umax > 0 ? dmax / umax : dmax;
-        if (dmax <= tol * umax) break;
-    }
-    if (info) {
-        info->ir_iterations = std::min(it, maxit);
-        info->last_correction = rel;
-    }
-    if (it > maxit) {
-        hps_set_error("iterative refinement did not converge: last correction %.3e", rel);
-        return HPS_ENOTCONVERGED;
+        *passes = it;
+        if (ir_converged(nb, rel)) {
+            *ok = true;
+            break;
+        }
     }
     return HPS_OK;
+}
+
+// The FP64 solve (leaf particular solutions, level sweeps, reconstruction) of one right-hand side.
+static int solve64(hps_op *op, const double *body, const double *dir, const double *jump, double *u, hipStream_t st) {
+    LeafPhase up;
+    up.up = LU_BODY;
+    up.body = body;
+    TRY(launch_leaf(op, false, up, st));
+    TRY(levels(op, false, jump, dir, st));
+    LeafPhase dn;
+    dn.down = LD_WRITE_U;
+    dn.u_out = u;
+    return launch_leaf(op, false, dn, st);
+}
+
+// FP32_IR: refine the FP32 solution u of (body, dir, jump) on the host-checked loop; if it
+// does not converge, redo the solve with the FP64 operators (HPS_IR_STRICT: error).
+static int ir_finish(hps_op *op, const double *body, const double *dir, const double *jump, double *u,
+                     hipStream_t st, hps_info *info) {
+    int passes = 0;
+    double rel = 0.0;
+    bool ok = false;
+    TRY(ir_adaptive(op, body, jump, u, st, &passes, &rel, &ok));
+    if (info) {
+        info->ir_iterations = std::max(info->ir_iterations, passes);
+        info->last_correction = std::max(info->last_correction, rel);
+    }
+    if (ok) return HPS_OK;
+    if (op->flags & HPS_IR_STRICT) {
+        hps_set_error("iterative refinement did not converge: last correction %.3e after %d passes", rel, passes);
+        return HPS_ENOTCONVERGED;
+    }
+    if (info) info->fp64_fallbacks += 1;
+    return solve64(op, body, dir, jump, u, st);
 }
 
 // One right-hand side: leaf particular solutions, the level sweeps, reconstruction of u
@@ -91,14 +133,49 @@ static int solve_one(hps_op *op, const double *body, const double *dir, const do
     dn.down = LD_WRITE_U;
     dn.u_out = u;
     TRY(launch_leaf(op, ir, dn, st));
-    if (ir) TRY(ir_refine(op, body, jump, u, st, inf));
+    if (ir) TRY(ir_finish(op, body, dir, jump, u, st, inf));
     return HPS_OK;
+}
+
+// Solve buffers for right-hand sides 1..n of a multi-right-hand-side solve (made once per
+// operator, one allocation each).
+static int multi_workspaces(hps_op *op, int n) {
+    for (int k = 0; k < n; ++k) {
+        if (op->mws[k]) continue;
+        int64_t co = 0, cb = 0;
+        const int64_t bytes = workspace_layout(op, nullptr, nullptr, &co, &cb);
+        void *blk = nullptr;
+        if (hipMalloc(&blk, (size_t)bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            hps_set_error("hipMalloc of %lld bytes for multi-right-hand-side solve buffers failed", (long long)bytes);
+            return HPS_ENOMEM;
+        }
+        op->allocs.push_back(blk);
+        op->total_bytes += bytes;
+        Workspace *w = new Workspace();
+        workspace_layout(op, (char *)blk, w, &co, &cb);
+        if (cb) HPS_HIP(hipMemset((char *)blk + co, 0, (size_t)cb));
+        op->mws[k] = w;
+    }
+    return HPS_OK;
+}
+
+// nc right-hand sides (2..4) of an FP64 real operator: one leaf launch up, one level sweep
+// and one leaf launch down for all of them, each operator block read once.
+static int solve_multi(hps_op *op, int nc, const double *const *body, const double *const *dir,
+                       const double *const *jump, double *const *u, hipStream_t st) {
+    TRY(multi_workspaces(op, nc - 1));
+    const Workspace *ws[MAX_MULTI] = {nullptr, op->mws[0], op->mws[1], op->mws[2]};
+    TRY(launch_leaf_multi(op, nc, true, body, nullptr, ws, st));
+    TRY(launch_levels_multi(op, nc, ws, dir, jump, st));
+    return launch_leaf_multi(op, nc, false, nullptr, u, ws, st);
 }
 
 extern "C" int hps_solve(hps_op *op, int nrhs, const double *body, const double *dirichlet,
                          const double *jump, double *u, void *stream, hps_info *info) {
     CHECK_ARG(op != nullptr, "op is NULL");
     CHECK_ARG(nrhs >= 0, "nrhs must be >= 0");
+    if (info) *info = hps_info{};
     if (nrhs == 0) return HPS_OK;
     CHECK_ARG(body != nullptr && u != nullptr, "body and u are required");
     TRY(check_device_ptr(body, "body"));
@@ -106,23 +183,36 @@ extern "C" int hps_solve(hps_op *op, int nrhs, const double *body, const double 
     TRY(check_device_ptr(jump, "jump"));
     TRY(check_device_ptr(u, "u"));
     hipStream_t st = (hipStream_t)stream;
-    int worst_it = 0;
-    double worst_rel = 0.0;
     const int m = op->ncomp;
-    for (int r = 0; r < nrhs; ++r) {
+    hps_info inf{};
+    // FP64 real operators: right-hand sides in groups of up to MAX_MULTI per sweep
+    const bool multi = m == 1 && !(op->flags & HPS_FP32_IR) && op->L > 0;
+    for (int r = 0; r < nrhs;) {
+        int nc = multi ? std::min(MAX_MULTI, nrhs - r) : 1;
+        while (nc > 1 && !levels_multi_fit(op, nc)) --nc;
+        if (nc > 1) {
+            const double *b[MAX_MULTI], *d[MAX_MULTI], *j[MAX_MULTI];
+            double *uu[MAX_MULTI];
+            for (int c = 0; c < nc; ++c) {
+                b[c] = body + (int64_t)(r + c) * op->n_int;
+                d[c] = dirichlet ? dirichlet + (int64_t)(r + c) * op->n_bdry : nullptr;
+                j[c] = (jump && op->n_iface) ? jump + (int64_t)(r + c) * op->n_iface : nullptr;
+                uu[c] = u + (int64_t)(r + c) * op->N;
+            }
+            TRY(solve_multi(op, nc, b, d, j, uu, st));
+            r += nc;
+            continue;
+        }
         const double *b = body + (int64_t)r * m * op->n_int;
         const double *d = dirichlet ? dirichlet + (int64_t)r * m * op->n_bdry : nullptr;
         const double *j = (jump && op->n_iface) ? jump + (int64_t)r * m * op->n_iface : nullptr;
         double *ur = u + (int64_t)r * m * op->N;
-        hps_info inf{};
         TRY(solve_one(op, b, d, j, ur, st, &inf));
-        worst_it = std::max(worst_it, inf.ir_iterations);
-        worst_rel = std::max(worst_rel, inf.last_correction);
+        ++r;
     }
     if (info) {
         HPS_HIP(hipStreamSynchronize(st));
-        info->ir_iterations = worst_it;
-        info->last_correction = worst_rel;
+        *info = inf;
     }
     return HPS_OK;
 }
@@ -176,11 +266,22 @@ void hps::step_phase(const ark_ctx *c, int k, double *u, const double *q_stages,
     }
 }
 
+// FP32_IR stage solves inside the step: `fixed` > 0 runs that many corrections per stage
+// with no host involvement (stage k's pass j accumulates its norms into
+// c->ir_stat[(k * IR_MAXIT + j) * 2]); fixed == 0 refines each stage on the host-checked
+// loop and redoes a stage that does not converge with the FP64 operators (rec: the
+// record of the step).
+struct IrStep {
+    int fixed = 0;
+    hps_info *rec = nullptr;
+    bool fp64 = false;   // every stage with the FP64 operators (refinement failed for this operator)
+};
+
 static int enqueue_step(ark_ctx *c, double *u, const double *q_stages, const double *q_space,
-                        const double *q_time, const double *f_stages, hipStream_t st) {
+                        const double *q_time, const double *f_stages, hipStream_t st, IrStep irs = IrStep{}) {
     hps_op *op = c->op;
     const int s = c->s;
-    const bool ir = (op->flags & HPS_FP32_IR) != 0;
+    const bool ir = (op->flags & HPS_FP32_IR) != 0 && !irs.fp64;
     (void)q_time;
     if (op->ncomp == 2) {
         // complex operator: u, the boundary data and every stage vector in two planes
@@ -197,11 +298,14 @@ static int enqueue_step(ark_ctx *c, double *u, const double *q_stages, const dou
                                        op->ir_flux + cc * plane));
         return HPS_OK;
     }
+    if (ir && irs.fixed > 0) {
+        // a replayed step: keep u^n for a redo, clear the correction norms
+        TRY(launch_copy(c->u_save, u, op->N, st));
+        TRY(launch_zero(c->ir_stat, (int64_t)s * IR_MAXIT * 2, st));
+    }
     for (int k = 0; k < s; ++k) {
-        if (k > 0) {
-            const double *fk = f_stages ? f_stages + (int64_t)k * op->n_bdry : nullptr;
-            TRY(levels(op, ir, nullptr, fk, st));
-        }
+        const double *fk = (k > 0 && f_stages) ? f_stages + (int64_t)k * op->n_bdry : nullptr;
+        if (k > 0) TRY(levels(op, ir, nullptr, fk, st));
         LeafPhase ph;
         step_phase(c, k, u, q_stages, q_space, c->qt_dev, ph);
         if (ir) {
@@ -211,7 +315,12 @@ static int enqueue_step(ark_ctx *c, double *u, const double *q_stages, const dou
                 w.down = LD_WRITE_U;
                 w.u_out = c->stage_u;
                 TRY(launch_leaf(op, true, w, st));
-                TRY(ir_refine(op, c->rhs, nullptr, c->stage_u, st, nullptr));
+                if (irs.fixed > 0) {
+                    for (int j = 0; j < irs.fixed; ++j)
+                        TRY(ir_pass(op, c->rhs, nullptr, c->stage_u, c->ir_stat + ((int64_t)k * IR_MAXIT + j) * 2, st));
+                } else {
+                    TRY(ir_finish(op, c->rhs, fk, nullptr, c->stage_u, st, irs.rec));
+                }
                 ph.down = LD_EVAL;
                 ph.u_eval = c->stage_u;
             }
@@ -346,15 +455,16 @@ static int enqueue_burgers_step(ark_ctx *cu, ark_ctx *cv, double *u, double *v, 
     return HPS_OK;
 }
 
-// Enqueue one step.  The FP64 step has no host synchronisation, so it is captured once
-// into a HIP graph (kept in c) and replayed while `key` (the formulation and the array
-// arguments) repeats.  The refinement loop of FP32_IR waits on the host and runs eagerly;
-// so does a profiled step.
+// Enqueue one step.  A step without host synchronisation (FP64; FP32_IR with a fixed
+// number of corrections) is captured once into a HIP graph (kept in c) and replayed while
+// `key` (the formulation and the array arguments) repeats.  Host-checked refinement and
+// profiled steps run eagerly.
 template <typename Enqueue>
-static int run_captured(ark_ctx *c, const std::vector<uintptr_t> &key, Enqueue enqueue, hipStream_t st) {
+static int run_captured(ark_ctx *c, const std::vector<uintptr_t> &key, Enqueue enqueue, hipStream_t st,
+                        bool capturable = true) {
     hps_op *op = c->op;
     const char *env = getenv("HPS_GRAPHS");
-    const bool graphs = !(env && env[0] == '0') && !(op->flags & HPS_FP32_IR) && !op->prof.on;
+    const bool graphs = capturable && !(env && env[0] == '0') && !op->prof.on;
     if (!graphs) return enqueue(st);
     if (!c->gexec || key != c->gkey) {
         if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
@@ -382,16 +492,94 @@ static int run_captured(ark_ctx *c, const std::vector<uintptr_t> &key, Enqueue e
     return HPS_OK;
 }
 
+// The stage formulation on an FP32_IR operator.  The first step (and a profiled one)
+// refines every stage on the host-checked loop and records the most corrections a stage
+// needed; later steps replay a captured graph with that many corrections per stage, then
+// wait for the stream and read every stage's last correction norm.  A stage that missed
+// the tolerance makes the step be redone from the saved u^n on the host-checked loop,
+// with FP64 re-solves where needed (HPS_IR_STRICT: HPS_ENOTCONVERGED), and the next
+// captured steps run one correction more.  Once a stage had to be re-solved in FP64, the
+// refinement is taken to fail for this operator: later steps use the FP64 operators only
+// (replayed like an FP64 step).
+static int run_step_ir(ark_ctx *c, double *u, const double *q_stages, const double *q_space, const double *q_time,
+                       const double *f, hipStream_t st) {
+    hps_op *op = c->op;
+    const int s = c->s;
+    const char *env = getenv("HPS_GRAPHS");
+    const bool graphs = !(env && env[0] == '0') && !op->prof.on;
+    if (c->ir_passes < 0) {
+        IrStep irs;
+        irs.fp64 = true;
+        const std::vector<uintptr_t> key = {(uintptr_t)4, (uintptr_t)u, (uintptr_t)q_stages, (uintptr_t)q_space,
+                                            (uintptr_t)f};
+        TRY(run_captured(c, key, [&](hipStream_t s2) { return enqueue_step(c, u, q_stages, q_space, q_time, f, s2, irs); },
+                         st));
+        c->last = hps_info{0, 0.0, s - 1};
+        return HPS_OK;
+    }
+    auto eager = [&]() -> int {
+        hps_info rec{};
+        IrStep irs;
+        irs.rec = &rec;
+        const int rc = enqueue_step(c, u, q_stages, q_space, q_time, f, st, irs);
+        c->last = rec;
+        if (rc) return rc;
+        if (rec.fp64_fallbacks > 0) c->ir_passes = -1;
+        else c->ir_passes = std::min(IR_MAXIT, std::max(c->ir_passes, rec.ir_iterations));
+        return HPS_OK;
+    };
+    if (!graphs || c->ir_passes == 0) return eager();
+    const int K = c->ir_passes;
+    const std::vector<uintptr_t> key = {(uintptr_t)3, (uintptr_t)u, (uintptr_t)q_stages, (uintptr_t)q_space,
+                                        (uintptr_t)f, (uintptr_t)K};
+    IrStep irs;
+    irs.fixed = K;
+    TRY(run_captured(c, key, [&](hipStream_t s2) { return enqueue_step(c, u, q_stages, q_space, q_time, f, s2, irs); },
+                     st));
+    std::vector<unsigned long long> nb((size_t)s * IR_MAXIT * 2);
+    HPS_HIP(hipMemcpyAsync(nb.data(), c->ir_stat, nb.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+    HPS_HIP(hipStreamSynchronize(st));
+    hps_info rec{};
+    rec.ir_iterations = K;
+    bool all = true;
+    for (int k = 1; k < s; ++k) {
+        double rel = 0.0;
+        all = ir_converged(&nb[((size_t)k * IR_MAXIT + K - 1) * 2], &rel) && all;
+        rec.last_correction = std::max(rec.last_correction, rel);
+    }
+    c->last = rec;
+    if (all) return HPS_OK;
+    if (op->flags & HPS_IR_STRICT) {
+        hps_set_error("iterative refinement did not converge within %d corrections: last correction %.3e", K,
+                      rec.last_correction);
+        return HPS_ENOTCONVERGED;
+    }
+    // redo the step from u^n with host-checked refinement
+    TRY(launch_copy(u, c->u_save, op->N, st));
+    TRY(eager());
+    if (c->ir_passes >= 0) c->ir_passes = std::min(IR_MAXIT, std::max(c->ir_passes, K + 1));
+    return HPS_OK;
+}
+
 static int run_step(ark_ctx *c, int mode, double *u, const double *q_stages, const double *q_space,
                     const double *q_time, const double *f, hipStream_t st) {
+    if (q_space) TRY(launch_set_values(c->qt_dev, q_time, c->s, st));
+    const bool ir = (c->op->flags & HPS_FP32_IR) != 0;
+    if (ir && mode == 0) return run_step_ir(c, u, q_stages, q_space, q_time, f, st);
     auto enqueue = [&](hipStream_t s2) {
         return mode == 0 ? enqueue_step(c, u, q_stages, q_space, q_time, f, s2)
                          : enqueue_slope_step(c, u, q_stages, q_space, f, s2);
     };
-    if (q_space) TRY(launch_set_values(c->qt_dev, q_time, c->s, st));
     const std::vector<uintptr_t> key = {(uintptr_t)mode, (uintptr_t)u, (uintptr_t)q_stages, (uintptr_t)q_space,
                                         (uintptr_t)f};
-    return run_captured(c, key, enqueue, st);
+    // the slope formulation's FP32_IR solves refine on the host-checked loop
+    return run_captured(c, key, enqueue, st, !ir);
+}
+
+extern "C" int ark_info(const ark_ctx *c, hps_info *info) {
+    CHECK_ARG(c != nullptr && info != nullptr, "ctx and info are required");
+    *info = c->last;
+    return HPS_OK;
 }
 
 static int check_step_args(ark_ctx *c, double t, double *u, const double *q_stages, const double *q_space,

@@ -44,7 +44,23 @@ struct Panel {
 Panel plan_panel(int R, int C, int vw, int nodes, int rp_max, int min_wg);
 // The same plan stored once for all `nodes` (operators that are equal at every node).
 Panel shared_panel(Panel p);
-int64_t plan_operator_bytes(const hps_grid &g, int flags, int ncomp = 1);   // what hps_build's panels take
+
+// what hps_build's panels take (mwg: the tuned minimum of workgroups per level, 0: the rule)
+int64_t plan_operator_bytes(const hps_grid &g, int flags, int ncomp = 1, int mwg = 0);
+// hps_build's body with a given level tiling (mwg as above; flags without HPS_AUTOTUNE)
+int build_op_tiled(const hps_grid *grid, const hps_coeffs *coeffs, const hps_coeffs *coeffs_im, double gamma_dt,
+                   int flags, int mwg, int compose, void *stream, hps_op **out);
+// composite operators of level pairs (hps_compose.hip)
+struct HostLevel;
+bool compose_eligible(const hps_op *op, const std::vector<HostLevel> &hl);
+int compose_pair(hps_op *op, int l, const std::vector<HostLevel> &hl, const double *Xc, const double *Uc,
+                 const double *Sc, const double *Xt, const double *Ut, const double *St, hipStream_t st);
+int launch_place(double *dst, int ldd, int64_t dstr, int r0, int c0, int rows, int cols, const double *src, int lds,
+                 int64_t sstr, const int *ri, const int *cj, double scale, bool accumulate, int batch, hipStream_t st);
+// HPS_AUTOTUNE: the level tiling of this operator class, measured on the device the first
+// time the class is built (hps_tune.hip)
+int tune_level_tiling(const hps_grid *grid, const hps_coeffs *coeffs, const hps_coeffs *coeffs_im, double gamma_dt,
+                      int flags, hipStream_t st, int *mwg, int *compose);
 
 // One internal level of the tree (level 0 = root), all nodes of the same shape.
 struct Level {
@@ -61,13 +77,34 @@ struct Level {
     int *cnt_up64 = nullptr, *cnt_dn64 = nullptr, *cnt_up32 = nullptr, *cnt_dn32 = nullptr;  // split-K arrivals
 };
 
+// Host copy of one level's index maps (every node of a level has the same local maps):
+// node boundary = [alpha's boundary at a1; beta's boundary at b2] (n1 + n2 entries), the
+// shared edge J3 at a3 in alpha's boundary and at b3 in beta's; j3i: interface index of
+// every J3 node, [nodes][n3].
+struct HostLevel {
+    int n1 = 0, n2 = 0, n3 = 0, nbc = 0;
+    std::vector<int> a1, a3, b2, b3;
+    std::vector<int> j3i;   // [nodes][n3]
+};
+
+// Two adjacent levels swept by one launch per direction (hps_compose.hip): l is the upper
+// level; l = 0 is the top pair (the root and level 1: one launch for both directions).
+struct PairOps {
+    int l = -1;
+    Panel up, dn;                 // composite operators, FP64 (the top pair: dn only)
+    int R_up = 0, C_up = 0, R_dn = 0, C_dn = 0;
+    int *tab = nullptr;           // device tables
+    int t_plus = 0, t_minus = 0, t_j3 = 0, t_fin_up = 0, t_fin_dn = 0, t_copy = 0;
+};
+
 // Optional per-kernel timing with HIP events recorded on the launch stream.
 enum KernelFamily {
     KF_LEAF_UP64, KF_LEAF_UP32, KF_LEAF_DOWN64, KF_LEAF_DOWN32, KF_LEAF_EVAL_UP64, KF_LEAF_EVAL_UP32,
     KF_LEAF_DOWN_UP64, KF_LEAF_DOWN_UP32, KF_LEAF_DOWN_UPDATE64, KF_LEAF_EVAL_UPDATE64,
     KF_LEVEL_UP64, KF_LEVEL_UP32, KF_LEVEL_DOWN64, KF_LEVEL_DOWN32, KF_RESIDUAL, KF_LINES,
     KF_LEAF2_EVAL_UP64, KF_LEAF2_DOWN_UP64, KF_LEAF2_DOWN_UPDATE64, KF_LEVEL2_UP64, KF_LEVEL2_DOWN64,
-    KF_LEAFC_EVAL_UP64, KF_LEAFC_DOWN_UP64, KF_LEAFC_DOWN_UPDATE64, KF_LEAFC_SOLVE64, KF_COUNT
+    KF_LEAFC_EVAL_UP64, KF_LEAFC_DOWN_UP64, KF_LEAFC_DOWN_UPDATE64, KF_LEAFC_SOLVE64,
+    KF_PAIR_UP64, KF_PAIR_TOP64, KF_PAIR_DOWN64, KF_COUNT
 };
 extern const char *const kKernelFamilyNames[KF_COUNT];
 
@@ -117,12 +154,20 @@ struct hps_op {
     // HPS_UNIFORM_COEFFS: every leaf, and every node of a level, has the same operators, so
     // the build computes one leaf and one node per level (the panels keep node 0 only)
     bool build_one = false;
+    int level_mwg = 0;                     // tuned minimum of workgroups per level (0: the fixed rule)
+    // FP64 sweeps of level pairs through composite operators (the per-level operators stay
+    // for every other consumer); pairs[k]: upper level 2k (k = 0: the top pair)
+    bool composed = false;
+    std::vector<hps::PairOps> pairs;
     // iterative refinement workspace (FP32_IR)
     double *ir_rhs = nullptr, *ir_r = nullptr, *ir_r3 = nullptr, *ir_du = nullptr, *ir_flux = nullptr;
     double *ir_norms = nullptr;            // [2] max|delta|, max|u| (as ordered bit patterns)
     int64_t operator_bytes = 0, total_bytes = 0;
     std::vector<void *> allocs;
     mutable hps::Profiler prof;
+    // solve buffers of right-hand sides 1..3 of a multi-right-hand-side hps_solve (made by
+    // its first call; right-hand side 0 uses the operator's own)
+    struct Workspace *mws[3] = {nullptr, nullptr, nullptr};
 };
 
 // The buffers one FP64 solve writes besides its outputs (leaf boundary values, particular
@@ -157,6 +202,13 @@ struct ark_ctx {
     double *Lu = nullptr, *F = nullptr;   // device [s][n_int] each
     double *rhs = nullptr;                // device [n_int] (FP32_IR stage right-hand side)
     double *stage_u = nullptr;            // device [N] (FP32_IR stage solution)
+    // FP32_IR stage formulation: corrections per stage in the captured step (0 until the
+    // first, host-checked step has measured them), the per-stage, per-pass correction
+    // norms of a replayed step ([s][IR_MAXIT][2], ordered bits), u^n kept for a redo, and
+    // the record of the last step
+    int ir_passes = 0;                    // -1: refinement failed for this operator, FP64 stages only
+    double *ir_stat = nullptr, *u_save = nullptr;
+    hps_info last{};
     double *qt_dev = nullptr;             // device [s]: time factors of a separable source
     // slope formulation (allocated on its first step): slopes k_j [s][N] and l_j [s][N]
     // (l only with g), L k_j and L l_j [s][n_int], L u^n [n_int], the stage right-hand
@@ -241,6 +293,8 @@ struct LeafPhase {
     double ca[8] = {0}, cf[8] = {0};
     double *rhs_copy = nullptr;
     double *unew = nullptr;                    // LU_UPDATE
+    double *norms = nullptr;                   // LD_IR_ADD: max|delta|, max|u| (ordered bits; null:
+                                               // the operator's pair)
 };
 // ws (FP64 only) redirects the solve buffers (leaf boundary values, particular solutions
 // and fluxes) from the operator's own to a workspace
@@ -260,11 +314,15 @@ int launch_residual(const hps_op *op, const double *u, const double *rhs, const 
 int launch_scatter_boundary(const hps_op *op, const double *f, double *u, hipStream_t st);
 int launch_zero(double *p, int64_t n, hipStream_t st);
 constexpr int kMaxLinComb = 24;
+constexpr int IR_MAXIT = 10;          // refinement corrections per solve at most
+constexpr double IR_TOL = 1e-11;      // stop when max|delta| <= IR_TOL max|u|
 int launch_lincomb(const double *const *v, const double *c, int nv, const double *q, const double *q_scale_ptr,
                    const GPoly *g, double *out, int64_t n, hipStream_t st);
 int launch_eval(const hps_op *op, const double *v, double *Lu, bool flux, hipStream_t st);
 int launch_flux_jump(const hps_op *op, double scale, double *r3, hipStream_t st);
 int ark_slope_workspace(ark_ctx *c);
+// device bytes of a stage-formulation context of s stages on op, with its own solve buffers
+int64_t ark_ctx_footprint(const hps_op *op, int s);
 // several operators per launch (FP64 stage formulation): argument records and launches
 size_t leaf_args_size();
 int fill_leaf_args(const hps_op *op, const LeafPhase &ph, void *dst, size_t *lds, const Workspace *ws);
@@ -294,6 +352,15 @@ int launch_leaf_sys(const hps_op *op, const LeafPhase &ph0, const LeafPhase &ph1
                     const Workspace *ws1, hipStream_t st);
 int launch_levels_sys(const hps_op *op, const Workspace *const ws[2], const double *const dir[2], hipStream_t st);
 int launch_set_values(double *dst, const double *vals, int n, hipStream_t st);   // n <= 8, vals on the host
+// nc = 2..4 right-hand sides of one FP64 operator per launch (hps_solve with nrhs > 1):
+// the leaf particular solves (up) or reconstructions (down) and the level sweeps; ws[c]:
+// right-hand side c's solve buffers (null: the operator's own)
+constexpr int MAX_MULTI = 4;
+int launch_leaf_multi(const hps_op *op, int nc, bool up, const double *const *body, double *const *u,
+                      const Workspace *const *ws, hipStream_t st);
+int launch_levels_multi(const hps_op *op, int nc, const Workspace *const *ws, const double *const *dir,
+                        const double *const *jump, hipStream_t st);
+bool levels_multi_fit(const hps_op *op, int nc);   // the level products' LDS for nc right-hand sides fits
 
 // build --------------------------------------------------------------------------------
 int launch_leaf_assemble(const hps_op *op, double *W, hipStream_t st);
@@ -316,6 +383,7 @@ int launch_dgemm(int M, int N, int K, const double *A, int lda, int64_t sA, cons
 // Pack a column-major operator (rows [0,rows0) from src0, rows [rows0,R) from src1) into a
 // Panel, as FP64 or FP32 according to pn.vw.
 int launch_pack(const Panel &pn, const double *src0, int ld0, int64_t stride0, int rows0,
-                const double *src1, int ld1, int64_t stride1, hipStream_t st);
+                const double *src1, int ld1, int64_t stride1, hipStream_t st, double scale = 1.0);
+int launch_copy(double *dst, const double *src, int64_t n, hipStream_t st);
 
 }  // namespace hps

@@ -530,6 +530,98 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5, 8))) void
 }
 
 // =======================================================================================
+// Several right-hand sides of one operator (hps_solve with nrhs > 1): one workgroup per
+// leaf streams A_ii^{-1} (up: particular solutions w and fluxes h) or S_leaf (down:
+// u = S_leaf u_b + w) once and applies every 16-byte load to all NC vectors.  Each
+// right-hand side sees exactly the arithmetic of the single-right-hand-side kernels.
+// =======================================================================================
+struct LeafMultiArgs {
+    LeafGeo geo;
+    const int *leaf_ij;
+    const double *D;
+    PanelView sl, ainv;
+    int xs_cap, part_cap;
+    const double *body[MAX_MULTI];   // up: right-hand sides (interior, canonical)
+    double *u_out[MAX_MULTI];        // down: solutions (canonical)
+    const double *ub[MAX_MULTI];     // leaf boundary values [leaf][4q]
+    double *w[MAX_MULTI];            // particular solutions [leaf][q2] (written up, read down)
+    double *h_out[MAX_MULTI];        // particular fluxes [leaf][4q]
+};
+
+template <int NC, bool UP>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_leaf_multi(LeafMultiArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT];
+    constexpr int VW = 2;
+    const int leaf = blockIdx.x;
+    const int q = a.geo.q, p = a.geo.p, q2 = q * q, nb = 4 * q;
+    const int li = a.leaf_ij[2 * leaf], lj = a.leaf_ij[2 * leaf + 1];
+    const int64_t base = ((int64_t)lj * a.geo.n1 + li) * q2;
+    Carve cv{smem};
+    double *xs = cv.take<double>((size_t)NC * a.xs_cap);
+    double *part = cv.take<double>((size_t)NC * a.part_cap);
+    double *D = cv.take<double>(p * p);
+    double *wv = cv.take<double>((size_t)NC * q2);
+    const PanelView &pv = UP ? a.ainv : a.sl;
+    PanelStream<double, LPF, LUNR> ps;
+    ps.start(reinterpret_cast<const double *>(pv.data) + (int64_t)leaf * pv.node_elems, pv.rp, pv.G, pv.S,
+             pv.node_elems == 0);
+    load_dmat(a.D, D, p * p);
+    const int SG = pv.S * pv.G, pst = pv.G * pv.rp * VW, rows = pv.rp * VW;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        for (int k = threadIdx.x; k < SG; k += NT) {
+            double x = 0.0;
+            if (UP) x = k < q2 ? a.body[c][base + k] : 0.0;
+            else x = k < nb ? a.ub[c][(int64_t)leaf * nb + k] : 0.0;
+            xs[c * SG + k] = x;
+        }
+        if (!UP)
+            for (int k = threadIdx.x; k < q2; k += NT) wv[c * q2 + k] = a.w[c][(int64_t)leaf * q2 + k];
+    }
+    __syncthreads();
+    ps.finish_n<NC>(xs, SG, part, pst);
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        reduce_rows<double>(part + c * pst, rows, pv.G, red, [&](int row, double y) {
+            if (row >= q2) return;
+            if (UP) {
+                wv[c * q2 + row] = y;
+                a.w[c][(int64_t)leaf * q2 + row] = y;
+            } else {
+                a.u_out[c][base + row] = y + wv[c * q2 + row];
+            }
+        });
+    }
+    if (UP) {
+        // particular fluxes h = flux rows . w (the interior part of the edge derivative)
+        for (int idx = threadIdx.x; idx < NC * nb; idx += NT) {
+            const int c = idx / nb, k = idx - c * nb;
+            const int e = k / q, m = k % q;
+            const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * p);
+            const double *w = wv + c * q2;
+            double h = 0.0;
+            if (e < 2) {
+                for (int cc = 1; cc <= q; ++cc) h = fma(dr[cc], w[m * q + cc - 1], h);
+            } else {
+                for (int cc = 1; cc <= q; ++cc) h = fma(dr[cc], w[(cc - 1) * q + m], h);
+            }
+            a.h_out[c][(int64_t)leaf * nb + k] = h;
+        }
+    } else {
+        // edge values: each edge node is written by exactly one leaf (left / bottom edges
+        // always, right / top edges only on the last column / row of leaves)
+        for (int idx = threadIdx.x; idx < NC * nb; idx += NT) {
+            const int c = idx / nb, k = idx - c * nb;
+            const int e = k / q, m = k % q;
+            const bool own = (e == 0 || e == 2) || (e == 1 && li == a.geo.n1 - 1) || (e == 3 && lj == a.geo.n2 - 1);
+            if (own) a.u_out[c][edge_index(a.geo, li, lj, e, m)] = a.ub[c][(int64_t)leaf * nb + k];
+        }
+    }
+}
+
+// =======================================================================================
 // launcher
 // =======================================================================================
 static int leaf_family(const LeafPhase &ph, bool fp32) {
@@ -567,7 +659,7 @@ static void make_leaf_args(const hps_op *op, bool fp32, const LeafPhase &ph, Lea
     a.q_scale = ph.q_scale;
     a.q_scale_ptr = ph.q_scale_ptr;
     a.g = ph.g;
-    a.norms = reinterpret_cast<unsigned long long *>(op->ir_norms);
+    a.norms = reinterpret_cast<unsigned long long *>(ph.norms ? ph.norms : op->ir_norms);
     a.body = ph.body;
     a.un = ph.un;
     a.Lu_in = ph.Lu_in;
@@ -620,6 +712,41 @@ int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st
 #undef HPS_LEAF_CASE
     hps_set_error("internal: unsupported leaf phase combination (%d, %d)", ph.down, ph.up);
     return HPS_EINVAL;
+}
+
+int launch_leaf_multi(const hps_op *op, int nc, bool up, const double *const *body, double *const *u,
+                      const Workspace *const *ws, hipStream_t st) {
+    ProfScope ps_(&op->prof, up ? KF_LEAF_UP64 : KF_LEAF_DOWN64, st);
+    LeafMultiArgs a{};
+    a.geo = geo_of(op);
+    a.leaf_ij = op->leaf_ij;
+    a.D = op->D;
+    a.sl = view(op->sleaf64);
+    a.ainv = view(op->ainv64);
+    a.xs_cap = std::max(op->sleaf64.S * op->sleaf64.G, op->ainv64.S * op->ainv64.G);
+    a.part_cap = std::max(op->sleaf64.G * op->sleaf64.rp, op->ainv64.G * op->ainv64.rp) * 2;
+    for (int c = 0; c < nc; ++c) {
+        const Workspace *w = ws[c];
+        a.body[c] = body ? body[c] : nullptr;
+        a.u_out[c] = u ? u[c] : nullptr;
+        a.ub[c] = w ? w->ub_leaf : op->ub_leaf;
+        a.w[c] = w ? w->w_leaf : op->w_leaf;
+        a.h_out[c] = w ? w->h_leaf : op->h_leaf;
+    }
+    const size_t lds = carve_bytes({(size_t)nc * a.xs_cap * 8, (size_t)nc * a.part_cap * 8, (size_t)op->p * op->p * 8,
+                                    (size_t)nc * op->q2 * 8});
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(op->nleaves), dim3(NT), lds, st, a); };
+    switch (nc * 2 + (up ? 1 : 0)) {
+        case 5: go(k_leaf_multi<2, true>); break;
+        case 4: go(k_leaf_multi<2, false>); break;
+        case 7: go(k_leaf_multi<3, true>); break;
+        case 6: go(k_leaf_multi<3, false>); break;
+        case 9: go(k_leaf_multi<4, true>); break;
+        case 8: go(k_leaf_multi<4, false>); break;
+        default: hps_set_error("internal: %d right-hand sides per leaf launch", nc); return HPS_EINVAL;
+    }
+    HPS_LAUNCHED();
+    return HPS_OK;
 }
 
 size_t leaf_args_size() { return sizeof(LeafArgs); }

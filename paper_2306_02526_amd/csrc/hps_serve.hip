@@ -26,9 +26,12 @@ namespace {
 using Clock = std::chrono::steady_clock;
 using Key = std::tuple<double, double, double, double, int, int, int, uint64_t, uint64_t, int>;
 
+constexpr size_t kMaxSpare = 4;   // contexts of finished jobs kept per operator
+
 struct CacheEntry {
     hps_op *op = nullptr;
-    int64_t bytes = 0;
+    int64_t bytes = 0;              // the operator's device bytes
+    int64_t ctx_bytes = 0;          // its contexts' bytes: running jobs' and kept ones
     int refs = 0;
     uint64_t last_use = 0;
     std::vector<ark_ctx *> spare;   // stepping contexts of finished jobs, reused by later ones
@@ -96,6 +99,8 @@ struct srv_server {
     void release_op(Job *j);
     int retire_oldest();
     void evict_entry(std::map<Key, CacheEntry>::iterator it);
+    int64_t held() const;
+    void update_held_stats();
 };
 
 void srv_server::evict_entry(std::map<Key, CacheEntry>::iterator it) {
@@ -104,13 +109,36 @@ void srv_server::evict_entry(std::map<Key, CacheEntry>::iterator it) {
     cache.erase(it);
 }
 
+// device bytes charged to the budget: operators and contexts
+int64_t srv_server::held() const {
+    int64_t b = 0;
+    for (auto &e : cache) b += e.second.bytes + e.second.ctx_bytes;
+    return b;
+}
+
+void srv_server::update_held_stats() {
+    int64_t ob = 0, cb = 0;
+    for (auto &e : cache) {
+        ob += e.second.bytes;
+        cb += e.second.ctx_bytes;
+    }
+    std::lock_guard<std::mutex> g(mu);
+    stats.cached_ops = (int64_t)cache.size();
+    stats.cached_bytes = ob;
+    stats.context_bytes = cb;
+}
+
 void srv_server::release_op(Job *j) {
     auto it = j->op ? cache.find(j->key) : cache.end();
     if (j->ctx) {
         // keep the context for the next job of this operator (freeing device memory would
-        // wait for the whole device)
-        if (it != cache.end()) it->second.spare.push_back(j->ctx);
-        else ark_free(j->ctx);
+        // wait for the whole device), a few per operator; it stays charged to the budget
+        if (it != cache.end() && it->second.spare.size() < kMaxSpare) {
+            it->second.spare.push_back(j->ctx);
+        } else {
+            if (it != cache.end()) it->second.ctx_bytes -= ark_ctx_footprint(j->op, j->ctx->s);
+            ark_free(j->ctx);
+        }
     }
     j->ctx = nullptr;
     if (it != cache.end()) {
@@ -120,6 +148,7 @@ void srv_server::release_op(Job *j) {
     j->op = nullptr;
     if (j->ready) (void)hipEventDestroy(j->ready);
     j->ready = nullptr;
+    update_held_stats();
 }
 
 void srv_server::finish(Job *j, int state, int err) {
@@ -139,25 +168,63 @@ void srv_server::finish(Job *j, int state, int err) {
 int srv_server::admit(Job *j) {
     auto it = cache.find(j->key);
     bool hit = it != cache.end();
-    if (!hit) {
-        const int64_t need = operator_footprint(j->spec.grid, j->spec.flags | HPS_WIDE_TILES);
-        if (need > cfg.cache_bytes) {
-            hps_set_error("operator of %lld bytes exceeds the cache budget", (long long)need);
-            return HPS_ENOMEM;
+    // the bytes this job adds: its operator when not cached, its context unless a kept one
+    // of the same step can be reused
+    bool reuse = false;
+    if (hit)
+        for (ark_ctx *c : it->second.spare) reuse = reuse || same_step(c, j);
+    const int64_t op_need = hit ? 0 : operator_footprint(j->spec.grid, j->spec.flags | HPS_WIDE_TILES);
+    int64_t ctx_need = 0;
+    if (!reuse) {
+        if (hit) {
+            ctx_need = ark_ctx_footprint(it->second.op, j->spec.tab.s);
+        } else {
+            // the context of an operator not built yet: sized from the grid (its workspace
+            // is a small multiple of N doubles, charged generously)
+            int64_t n_int = 0;
+            const int64_t N = hps_num_nodes(&j->spec.grid, &n_int, nullptr, nullptr);
+            ctx_need = 8 * (2LL * j->spec.tab.s * n_int + j->spec.tab.s + 3 * N + 20 * N);
         }
-        int64_t held = 0;
-        for (auto &e : cache) held += e.second.bytes;
-        while (held + need > cfg.cache_bytes) {
-            auto victim = cache.end();
-            for (auto e = cache.begin(); e != cache.end(); ++e)
-                if (e->second.refs == 0 && (victim == cache.end() || e->second.last_use < victim->second.last_use))
-                    victim = e;
-            if (victim == cache.end()) return 1;
-            held -= victim->second.bytes;
-            evict_entry(victim);
+    }
+    const int64_t need = op_need + ctx_need;
+    if (need > cfg.cache_bytes) {
+        hps_set_error("operator and stepping context of %lld bytes exceed the cache budget", (long long)need);
+        return HPS_ENOMEM;
+    }
+    int64_t h = held();
+    // make room: kept contexts first (least recently used operators first), then
+    // unreferenced operators
+    while (h + need > cfg.cache_bytes) {
+        auto donor = cache.end();
+        for (auto e = cache.begin(); e != cache.end(); ++e)
+            if (!e->second.spare.empty() && !(hit && e == it && reuse) &&
+                (donor == cache.end() || e->second.last_use < donor->second.last_use))
+                donor = e;
+        if (donor != cache.end()) {
+            ark_ctx *c = donor->second.spare.back();
+            donor->second.spare.pop_back();
+            const int64_t cb = ark_ctx_footprint(donor->second.op, c->s);
+            donor->second.ctx_bytes -= cb;
+            h -= cb;
+            ark_free(c);
+            continue;
+        }
+        auto victim = cache.end();
+        for (auto e = cache.begin(); e != cache.end(); ++e)
+            if (e->second.refs == 0 && !(hit && e == it) &&
+                (victim == cache.end() || e->second.last_use < victim->second.last_use))
+                victim = e;
+        if (victim == cache.end()) {
             std::lock_guard<std::mutex> g(mu);
-            stats.evictions++;
+            stats.waits++;
+            return 1;
         }
+        h -= victim->second.bytes + victim->second.ctx_bytes;
+        evict_entry(victim);
+        std::lock_guard<std::mutex> g(mu);
+        stats.evictions++;
+    }
+    if (!hit) {
         // the coefficient arrays were prepared on the caller's stream
         if (hipStreamWaitEvent(stream, j->ready, 0) != hipSuccess) {
             hps_set_error("hipStreamWaitEvent failed");
@@ -191,18 +258,18 @@ int srv_server::admit(Job *j) {
         }
     if (!j->ctx) {
         ark_tableau tab{j->spec.tab.s, j->A.data(), j->b.data(), j->c.data(), j->Ah.data(), j->bh.data()};
-        if (int rc = ark_create(j->op, &tab, j->spec.dt, &j->spec.g, &j->ctx)) return rc;
+        if (int rc = ark_create(j->op, &tab, j->spec.dt, &j->spec.g, &j->ctx)) {
+            it->second.refs--;
+            j->op = nullptr;
+            return rc;
+        }
+        it->second.ctx_bytes += ark_ctx_footprint(j->op, j->spec.tab.s);
     }
+    update_held_stats();
     std::lock_guard<std::mutex> g(mu);
     j->st.cache_hit = hit ? 1 : 0;
     j->st.state = SRV_ACTIVE;
     j->st.start_s = now();
-    {
-        int64_t bytes = 0;
-        for (auto &e : cache) bytes += e.second.bytes;
-        stats.cached_ops = (int64_t)cache.size();
-        stats.cached_bytes = bytes;
-    }
     return 0;
 }
 

@@ -293,17 +293,153 @@ __global__ __launch_bounds__(NT) void k_level_group(const LevelArgs *args, const
 }
 
 // =======================================================================================
+// composed level pairs: two adjacent tree levels swept by one launch per direction
+// =======================================================================================
+// The products of two adjacent levels are linear maps, so their composition is one matrix
+// per node of the upper level (built once, hps_compose.hip).  Upward it takes the
+// interface differences d of both children and of the node to both levels' w3 and the
+// node's particular fluxes h; downward it takes the node's boundary values and w3 to the
+// shared-edge values of the node and of both children.  The top pair (the root and its
+// children) is one kernel from the Dirichlet data and the differences below it to the
+// shared-edge values of both levels.  Every input and output position comes from a table
+// built on the host from the two levels' index maps, relative to the node's four
+// grandchildren (whose boundary vectors are contiguous).
+enum { PAIR_UP = 0, PAIR_DOWN = 1, PAIR_TOP = 2 };
+
+struct PairArgs {
+    PanelView pn;
+    int R, C;                    // rows and input columns of the composite operator
+    int n3t, n12t, n3c, nbcc;    // |J3|, |J12| of the upper level; |J3| of the lower; grandchild boundary length
+    const int *tab;              // the pair's tables
+    int t_plus, t_minus, t_j3, t_fin, t_copy;   // their offsets in tab
+    const double *hg;            // grandchildren's particular fluxes [4 per node][nbcc]
+    const double *r3;            // interface jumps or null
+    const int *j3i_t, *j3i_c;    // J3 interface indices of the upper and lower level
+    double *h_t, *w3_t, *w3_c;   // upward outputs (downward: w3 is read)
+    const double *ub_t;          // the upper level's boundary values [nodes][n12t]
+    double *ubg;                 // grandchildren's boundary values [4 per node][nbcc]
+    const double *dir;           // top: Dirichlet data (boundary-indexed) or null
+    const int *root_map;         // top: root boundary position -> boundary index
+};
+
+// input column k of the upward / top gathers: a difference of two grandchild fluxes plus
+// the interface jump of the J3 node the column belongs to
+__device__ __forceinline__ double pair_diff(const PairArgs &a, int node, int64_t gbase, int k) {
+    const int *t = a.tab;
+    double x = a.hg[gbase + t[a.t_plus + k]] - a.hg[gbase + t[a.t_minus + k]];
+    if (a.r3) {
+        const int jc = t[a.t_j3 + k];
+        x += jc >= 0 ? a.r3[a.j3i_c[(int64_t)node * 2 * a.n3c + jc]] : a.r3[a.j3i_t[(int64_t)node * a.n3t - jc - 1]];
+    }
+    return x;
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ void pair_body(const PairArgs &a, int blk, unsigned char *smem, double *red) {
+    constexpr int VW = 16 / sizeof(T);
+    const int ntile = a.pn.ntile;
+    const int tile = blk % ntile;
+    const int node = blk / ntile;
+    const int SG = a.pn.S * a.pn.G;
+    Carve cv{smem};
+    T *xs = cv.take<T>(SG);
+    T *part = cv.take<T>((size_t)a.pn.G * a.pn.rp * VW);
+    PanelStream<T, PF, UNR> ps;
+    ps.start(reinterpret_cast<const T *>(a.pn.data) + (int64_t)node * a.pn.node_elems + (int64_t)tile * a.pn.tile_elems,
+             a.pn.rp, a.pn.G, a.pn.S);
+    const int rows = a.pn.rp * VW;   // at most NT: one row per thread
+    const int myrow = tile * rows + threadIdx.x;
+    const int64_t gbase = (int64_t)node * 4 * a.nbcc;
+    const int *tab = a.tab;
+    // operands of the finalisation, loaded before the stream is consumed
+    int kind = -1, idx = 0, p1 = -1, p2 = -1;
+    double base = 0.0;
+    if ((int)threadIdx.x < rows && myrow < a.R) {
+        if (MODE == PAIR_UP) {
+            kind = tab[a.t_fin + 3 * myrow];
+            idx = tab[a.t_fin + 3 * myrow + 1];
+            if (kind == 2) base = a.hg[gbase + tab[a.t_fin + 3 * myrow + 2]];
+        } else {
+            kind = tab[a.t_fin + 4 * myrow];
+            idx = tab[a.t_fin + 4 * myrow + 1];
+            p1 = tab[a.t_fin + 4 * myrow + 2];
+            p2 = tab[a.t_fin + 4 * myrow + 3];
+            if (kind == 1) base = a.w3_t[(int64_t)node * a.n3t + idx];
+            else if (kind == 0) base = a.w3_c[(int64_t)node * 2 * a.n3c + idx];
+        }
+    }
+    for (int k = threadIdx.x; k < SG; k += NT) {
+        double x = 0.0;
+        if (k < a.C) {
+            if (MODE == PAIR_UP) {
+                x = pair_diff(a, node, gbase, k);
+            } else if (MODE == PAIR_DOWN) {
+                x = k < a.n12t ? a.ub_t[(int64_t)node * a.n12t + k] : a.w3_t[(int64_t)node * a.n3t + k - a.n12t];
+            } else {
+                x = k < a.n12t ? (a.dir ? a.dir[a.root_map[k]] : 0.0) : pair_diff(a, 0, 0, k);
+            }
+        }
+        xs[k] = (T)x;
+    }
+    if (MODE != PAIR_UP) {
+        // the node's own boundary values go to the grandchildren unchanged; the node's row
+        // tiles copy one slice each
+        const int per = (a.n12t + ntile - 1) / ntile;
+        const int m1 = min(a.n12t, (tile + 1) * per);
+        for (int m = tile * per + threadIdx.x; m < m1; m += NT) {
+            const double v = MODE == PAIR_DOWN ? a.ub_t[(int64_t)node * a.n12t + m]
+                                               : (a.dir ? a.dir[a.root_map[m]] : 0.0);
+            a.ubg[gbase + tab[a.t_copy + m]] = v;
+        }
+    }
+    __syncthreads();
+    ps.finish(xs, part);
+    __syncthreads();
+    const int G = a.pn.G;
+    const int nsl = min(G, NT / rows);
+    const int t = threadIdx.x;
+    const int row = t % rows, sl = t / rows;
+    if (sl < nsl) {
+        T y = T(0);
+        for (int gg = sl; gg < G; gg += nsl) y += part[gg * rows + row];
+        red[sl * rows + row] = (double)y;
+    }
+    __syncthreads();
+    const double y = slice_sum(red, red + NT, nsl, rows);
+    if (t < rows && myrow < a.R) {
+        if (MODE == PAIR_UP) {
+            if (kind == 0) a.w3_c[(int64_t)node * 2 * a.n3c + idx] = y;
+            else if (kind == 1) a.w3_t[(int64_t)node * a.n3t + idx] = y;
+            else a.h_t[(int64_t)node * a.n12t + idx] = base + y;
+        } else {
+            const double u3 = y + base;
+            a.ubg[gbase + p1] = u3;
+            if (p2 >= 0) a.ubg[gbase + p2] = u3;
+        }
+    }
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(NT) void k_pair(PairArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT + 64];
+    pair_body<T, MODE>(a, blockIdx.x, smem, red);
+}
+
+// =======================================================================================
 // two-component level products (FP64): both components of one (node, row tile, column
 // chunk) in one workgroup, the operator block streamed once for both
 // =======================================================================================
-struct LevelSysArgs {
-    LevelArgs c[2];   // per component; the operator fields of c[0] and c[1] are the same
+template <int NC>
+struct LevelSysArgsN {
+    LevelArgs c[NC];   // per component (right-hand side); the operator fields are the same in all
 };
+using LevelSysArgs = LevelSysArgsN<2>;
 
-template <bool UP>
-__device__ __forceinline__ void level_sys_body(const LevelSysArgs &A, int blk, unsigned char *smem, double *red,
+template <int NC, bool UP>
+__device__ __forceinline__ void level_sys_body(const LevelSysArgsN<NC> &A, int blk, unsigned char *smem, double *red,
                                                int *s_last) {
-    constexpr int NC = 2, VW = 2;
+    constexpr int VW = 2;
     const LevelArgs &a = A.c[0];
     const int kch = a.pn.kch, ntile = a.pn.ntile;
     const int chunk = blk % kch;
@@ -320,7 +456,9 @@ __device__ __forceinline__ void level_sys_body(const LevelSysArgs &A, int blk, u
              a.pn.rp, a.pn.G, a.pn.S);
     const int rows = a.pn.rp * VW;
     const int myrow = tile * rows + threadIdx.x;
-    double fin[NC] = {0.0, 0.0};
+    double fin[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) fin[c] = 0.0;
     int64_t ia = -1, ib = -1;
     if (kch == 1 && (int)threadIdx.x < rows) {
         if (UP) {
@@ -441,12 +579,12 @@ __device__ __forceinline__ void level_sys_body(const LevelSysArgs &A, int blk, u
     if (threadIdx.x == 0) a.cnt[node * ntile + tile] = 0;
 }
 
-template <bool UP>
-__global__ __launch_bounds__(NT) void k_level_sys(LevelSysArgs a) {
+template <int NC, bool UP>
+__global__ __launch_bounds__(NT) void k_level_sys(LevelSysArgsN<NC> a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[NT + 64];
     __shared__ int s_last;
-    level_sys_body<UP>(a, blockIdx.x, smem, red, &s_last);
+    level_sys_body<NC, UP>(a, blockIdx.x, smem, red, &s_last);
 }
 
 // =======================================================================================
@@ -783,6 +921,11 @@ __global__ void k_zero(double *p, int64_t n) {
     if (k < n) p[k] = 0.0;
 }
 
+__global__ void k_copy(double *dst, const double *src, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) dst[k] = src[k];
+}
+
 // ---- profiling ---------------------------------------------------------------------------
 const char *const kKernelFamilyNames[KF_COUNT] = {
     "leaf_up_fp64", "leaf_up_fp32", "leaf_down_fp64", "leaf_down_fp32", "leaf_eval_up_fp64",
@@ -790,7 +933,7 @@ const char *const kKernelFamilyNames[KF_COUNT] = {
     "leaf_eval_update", "level_up_fp64", "level_up_fp32", "level_down_fp64", "level_down_fp32",
     "residual", "lines", "leaf2_eval_up_fp64", "leaf2_down_up_fp64", "leaf2_down_update_fp64",
     "level2_up_fp64", "level2_down_fp64", "leafc_eval_up_fp64", "leafc_down_up_fp64", "leafc_down_update_fp64",
-    "leafc_solve_fp64"};
+    "leafc_solve_fp64", "pair_up_fp64", "pair_top_fp64", "pair_down_fp64"};
 
 hipEvent_t Profiler::get() {
     if (!pool.empty()) {
@@ -948,10 +1091,11 @@ __global__ __launch_bounds__(NT) void k_root_group(const LevelArgs *ups, const L
     root_body<T>(ups[lo], dns[lo], w - base[lo], smem, red);
 }
 
-// The fused root for two components: u_3 = S u_12 + X d for each.
-__device__ __forceinline__ void root_sys_body(const LevelSysArgs &U, const LevelSysArgs &Dn, int tile,
+// The fused root for NC components: u_3 = S u_12 + X d for each.
+template <int NC>
+__device__ __forceinline__ void root_sys_body(const LevelSysArgsN<NC> &U, const LevelSysArgsN<NC> &Dn, int tile,
                                               unsigned char *smem, double *red) {
-    constexpr int NC = 2, VW = 2;
+    constexpr int VW = 2;
     const LevelArgs &up = U.c[0], &dn = Dn.c[0];
     const int SG1 = up.pn.S * up.pn.G, SG2 = dn.pn.S * dn.pn.G;
     const int pst1 = up.pn.G * up.pn.rp * VW, pst2 = dn.pn.G * dn.pn.rp * VW;
@@ -1022,10 +1166,11 @@ __device__ __forceinline__ void root_sys_body(const LevelSysArgs &U, const Level
     }
 }
 
-__global__ __launch_bounds__(NT) void k_root_sys(LevelSysArgs up, LevelSysArgs dn) {
+template <int NC>
+__global__ __launch_bounds__(NT) void k_root_sys(LevelSysArgsN<NC> up, LevelSysArgsN<NC> dn) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[NT + 64];
-    root_sys_body(up, dn, blockIdx.x, smem, red);
+    root_sys_body<NC>(up, dn, blockIdx.x, smem, red);
 }
 
 static size_t level_lds(const Panel &pn) {
@@ -1049,8 +1194,96 @@ __global__ void k_root_leaf_ub(const double *dir, const int *root_map, double *u
 
 static void use_workspace(const hps_op *op, int l, bool up, const Workspace *ws, LevelArgs &a);
 
+// FP64 sweeps through the composite level pairs: the top pair (root and level 1) in one
+// launch, pairs (l, l + 1) for even l >= 2 one launch per direction, and an odd number of
+// levels leaves the bottom level to the single-level kernels.
+static int launch_pairs(const hps_op *op, const double *jump, const double *dirichlet, hipStream_t st,
+                        const Workspace *ws) {
+    const int L = op->L;
+    auto hbuf = [&](int l) -> double * {
+        if (l == L) return ws ? ws->h_leaf : op->h_leaf;
+        return ws ? ws->lv[l].h : op->lv[l].h;
+    };
+    auto ubbuf = [&](int l) -> double * {
+        if (l == L) return ws ? ws->ub_leaf : op->ub_leaf;
+        return ws ? ws->lv[l].ub : op->lv[l].ub;
+    };
+    auto w3buf = [&](int l) -> double * { return ws ? ws->lv[l].w3 : op->lv[l].w3; };
+    auto pair_args = [&](int l, bool up) {
+        const PairOps &P = op->pairs[l / 2];
+        const Level &T = op->lv[l], &Cl = op->lv[l + 1];
+        PairArgs a{};
+        a.pn = view(up ? P.up : P.dn);
+        a.R = up ? P.R_up : P.R_dn;
+        a.C = up ? P.C_up : P.C_dn;
+        a.n3t = T.n3;
+        a.n12t = T.n12;
+        a.n3c = Cl.n3;
+        a.nbcc = Cl.nbc;
+        a.tab = P.tab;
+        a.t_plus = P.t_plus;
+        a.t_minus = P.t_minus;
+        a.t_j3 = P.t_j3;
+        a.t_fin = up ? P.t_fin_up : P.t_fin_dn;
+        a.t_copy = P.t_copy;
+        a.hg = hbuf(l + 2);
+        a.r3 = jump;
+        a.j3i_t = T.j3i;
+        a.j3i_c = Cl.j3i;
+        a.h_t = hbuf(l);
+        a.w3_t = w3buf(l);
+        a.w3_c = w3buf(l + 1);
+        a.ub_t = ubbuf(l);
+        a.ubg = ubbuf(l + 2);
+        a.dir = dirichlet;
+        a.root_map = op->root_map;
+        return a;
+    };
+    auto single = [&](int l, bool up) {
+        LevelArgs a = level_args(op, l, false, up);
+        use_workspace(op, l, up, ws, a);
+        a.r3 = jump;
+        a.dir = dirichlet;
+        const Panel &pn = up ? op->lv[l].xu64 : op->lv[l].s64;
+        const unsigned nb = (unsigned)(op->lv[l].nodes * a.pn.ntile * a.pn.kch);
+        if (up) launch_level<double, true>(a, nb, level_lds(pn), st);
+        else launch_level<double, false>(a, nb, level_lds(pn), st);
+        HPS_LAUNCHED();
+    };
+    const int top_low = (L % 2 == 1) ? L - 3 : L - 2;   // the lowest pair's upper level
+    {
+        ProfScope ps_(&op->prof, KF_PAIR_UP64, st);
+        if (L % 2 == 1) single(L - 1, true);
+        for (int l = top_low; l >= 2; l -= 2) {
+            const PairArgs a = pair_args(l, true);
+            const Panel &pn = op->pairs[l / 2].up;
+            hipLaunchKernelGGL((k_pair<double, PAIR_UP>), dim3((unsigned)(op->lv[l].nodes * pn.ntile)), dim3(NT),
+                               level_lds(pn), st, a);
+            HPS_LAUNCHED();
+        }
+    }
+    {
+        ProfScope ps_(&op->prof, KF_PAIR_TOP64, st);
+        const PairArgs a = pair_args(0, false);
+        const Panel &pn = op->pairs[0].dn;
+        hipLaunchKernelGGL((k_pair<double, PAIR_TOP>), dim3((unsigned)pn.ntile), dim3(NT), level_lds(pn), st, a);
+        HPS_LAUNCHED();
+    }
+    ProfScope ps_(&op->prof, KF_PAIR_DOWN64, st);
+    for (int l = 2; l <= top_low; l += 2) {
+        const PairArgs a = pair_args(l, false);
+        const Panel &pn = op->pairs[l / 2].dn;
+        hipLaunchKernelGGL((k_pair<double, PAIR_DOWN>), dim3((unsigned)(op->lv[l].nodes * pn.ntile)), dim3(NT),
+                           level_lds(pn), st, a);
+        HPS_LAUNCHED();
+    }
+    if (L % 2 == 1) single(L - 1, false);
+    return HPS_OK;
+}
+
 int launch_levels(const hps_op *op, bool fp32, const double *jump, const double *dirichlet, hipStream_t st,
                   const Workspace *ws) {
+    if (!fp32 && op->composed) return launch_pairs(op, jump, dirichlet, st, ws);
     const bool rootf = root_fusable(op, fp32);
     {
         ProfScope ps_(&op->prof, fp32 ? KF_LEVEL_UP32 : KF_LEVEL_UP64, st);
@@ -1100,17 +1333,17 @@ int launch_levels(const hps_op *op, bool fp32, const double *jump, const double 
 
 // ---- two components on one operator (FP64) ----
 
-static size_t sys_level_lds(const Panel &pn) {
-    return carve_bytes({(size_t)2 * pn.S * pn.G * 8, (size_t)2 * pn.G * pn.rp * pn.vw * 8});
+static size_t sys_level_lds(const Panel &pn, int nc) {
+    return carve_bytes({(size_t)nc * pn.S * pn.G * 8, (size_t)nc * pn.G * pn.rp * pn.vw * 8});
 }
 
-static size_t sys_root_lds(const hps_op *op) {
+static size_t sys_root_lds(const hps_op *op, int nc) {
     const Panel &x = op->lv[0].xu64, &sp = op->lv[0].s64;
-    return carve_bytes({(size_t)2 * x.S * x.G * 8, (size_t)2 * sp.S * sp.G * 8, (size_t)2 * x.G * x.rp * x.vw * 8,
-                        (size_t)2 * sp.G * sp.rp * sp.vw * 8}) + 32;
+    return carve_bytes({(size_t)nc * x.S * x.G * 8, (size_t)nc * sp.S * sp.G * 8, (size_t)nc * x.G * x.rp * x.vw * 8,
+                        (size_t)nc * sp.G * sp.rp * sp.vw * 8}) + 32;
 }
 
-// Dynamic LDS a two-component level kernel may take on the current device (the kernels'
+// Dynamic LDS a multi-component level kernel may take on the current device (the kernels'
 // static arrays take the rest).
 static size_t sys_lds_limit() {
     int dev = 0, v = 0;
@@ -1122,59 +1355,87 @@ static size_t sys_lds_limit() {
     return (size_t)v - 4096;
 }
 
-int launch_levels_sys(const hps_op *op, const Workspace *const ws[2], const double *const dir[2], hipStream_t st) {
+bool levels_multi_fit(const hps_op *op, int nc) {
+    const size_t lim = sys_lds_limit();
+    for (int l = 0; l < op->L; ++l)
+        if (sys_level_lds(op->lv[l].xu64, nc) > lim || sys_level_lds(op->lv[l].s64, nc) > lim) return false;
+    return true;
+}
+
+// The level sweeps of NC right-hand sides at once (FP64): every operator block is read
+// once for all of them.  ws[c], dir[c], jump[c]: component c's solve buffers (null: the
+// operator's own), Dirichlet data and interface jumps (null: zero).
+template <int NC>
+static int levels_multi(const hps_op *op, const Workspace *const *ws, const double *const *dir,
+                        const double *const *jump, hipStream_t st, int fam_up, int fam_dn) {
     const size_t lim = sys_lds_limit();
     auto comp_args = [&](int l, bool up, int c) {
         LevelArgs a = level_args(op, l, false, up);
         use_workspace(op, l, up, ws[c], a);
-        a.dir = dir[c];
+        a.dir = dir ? dir[c] : nullptr;
+        a.r3 = jump ? jump[c] : nullptr;
         return a;
     };
     auto run_level = [&](int l, bool up) -> int {
         const Panel &pn = up ? op->lv[l].xu64 : op->lv[l].s64;
         const unsigned nb = (unsigned)(op->lv[l].nodes * pn.ntile * pn.kch);
-        // at most 2 * XS_BYTES of input vectors plus the partial sums: within the LDS of a
-        // gfx950 workgroup (160 KiB)
-        const size_t lds2 = sys_level_lds(pn);
-        if (lds2 > lim) {
-            hps_set_error("two-component level product needs %zu bytes of LDS, the device allows %zu", lds2, lim);
+        // at most NC * XS_BYTES of input vectors plus the partial sums: within the LDS of a
+        // gfx950 workgroup (160 KiB) for the sizes callers pass
+        const size_t lds = sys_level_lds(pn, NC);
+        if (lds > lim) {
+            hps_set_error("%d-component level product needs %zu bytes of LDS, the device allows %zu", NC, lds, lim);
             return HPS_EDEVICE;
         }
-        LevelSysArgs A;
-        A.c[0] = comp_args(l, up, 0);
-        A.c[1] = comp_args(l, up, 1);
-        if (up) hipLaunchKernelGGL(k_level_sys<true>, dim3(nb), dim3(NT), lds2, st, A);
-        else hipLaunchKernelGGL(k_level_sys<false>, dim3(nb), dim3(NT), lds2, st, A);
+        LevelSysArgsN<NC> A;
+        for (int c = 0; c < NC; ++c) A.c[c] = comp_args(l, up, c);
+        if (up) hipLaunchKernelGGL((k_level_sys<NC, true>), dim3(nb), dim3(NT), lds, st, A);
+        else hipLaunchKernelGGL((k_level_sys<NC, false>), dim3(nb), dim3(NT), lds, st, A);
         HPS_LAUNCHED();
         return HPS_OK;
     };
     // the fused root only while two workgroups fit on a compute unit: above that the
     // separate up and down root launches are faster (measured at 64x64 leaves, p = 16)
-    const bool rootf = root_fusable(op, false) && sys_root_lds(op) <= std::min<size_t>(lim, 65536);
+    const bool rootf = root_fusable(op, false) && sys_root_lds(op, NC) <= std::min<size_t>(lim, 65536);
     {
-        ProfScope ps_(&op->prof, KF_LEVEL2_UP64, st);
+        ProfScope ps_(&op->prof, fam_up, st);
         for (int l = op->L - 1; l >= (rootf ? 1 : 0); --l) TRY(run_level(l, true));
     }
-    ProfScope ps_(&op->prof, KF_LEVEL2_DOWN64, st);
+    ProfScope ps_(&op->prof, fam_dn, st);
     if (op->L == 0) {
-        for (int c = 0; c < 2; ++c) {
-            hipLaunchKernelGGL(k_root_leaf_ub, dim3(1), dim3(NT), 0, st, dir[c], (const int *)op->root_map,
-                               ws[c] ? ws[c]->ub_leaf : op->ub_leaf, 4 * op->q);
+        for (int c = 0; c < NC; ++c) {
+            hipLaunchKernelGGL(k_root_leaf_ub, dim3(1), dim3(NT), 0, st, dir ? dir[c] : nullptr,
+                               (const int *)op->root_map, ws[c] ? ws[c]->ub_leaf : op->ub_leaf, 4 * op->q);
             HPS_LAUNCHED();
         }
         return HPS_OK;
     }
     if (rootf) {
-        LevelSysArgs U, Dn;
-        for (int c = 0; c < 2; ++c) {
+        LevelSysArgsN<NC> U, Dn;
+        for (int c = 0; c < NC; ++c) {
             U.c[c] = comp_args(0, true, c);
             Dn.c[c] = comp_args(0, false, c);
         }
-        hipLaunchKernelGGL(k_root_sys, dim3(op->lv[0].xu64.ntile), dim3(NT), sys_root_lds(op), st, U, Dn);
+        hipLaunchKernelGGL(k_root_sys<NC>, dim3(op->lv[0].xu64.ntile), dim3(NT), sys_root_lds(op, NC), st, U, Dn);
         HPS_LAUNCHED();
     }
     for (int l = rootf ? 1 : 0; l < op->L; ++l) TRY(run_level(l, false));
     return HPS_OK;
+}
+
+int launch_levels_sys(const hps_op *op, const Workspace *const ws[2], const double *const dir[2], hipStream_t st) {
+    return levels_multi<2>(op, ws, dir, nullptr, st, KF_LEVEL2_UP64, KF_LEVEL2_DOWN64);
+}
+
+int launch_levels_multi(const hps_op *op, int nc, const Workspace *const *ws, const double *const *dir,
+                        const double *const *jump, hipStream_t st) {
+    switch (nc) {
+        case 2: return levels_multi<2>(op, ws, dir, jump, st, KF_LEVEL_UP64, KF_LEVEL_DOWN64);
+        case 3: return levels_multi<3>(op, ws, dir, jump, st, KF_LEVEL_UP64, KF_LEVEL_DOWN64);
+        case 4: return levels_multi<4>(op, ws, dir, jump, st, KF_LEVEL_UP64, KF_LEVEL_DOWN64);
+        default: break;
+    }
+    hps_set_error("internal: %d right-hand sides per level sweep", nc);
+    return HPS_EINVAL;
 }
 
 // ---- argument records and launches for several operators at once (FP64) ----
@@ -1412,6 +1673,13 @@ int launch_flux_jump(const hps_op *op, double scale, double *r3, hipStream_t st)
 int launch_zero(double *p, int64_t n, hipStream_t st) {
     if (n <= 0) return HPS_OK;
     hipLaunchKernelGGL(k_zero, dim3(nblk(n)), dim3(NT), 0, st, p, n);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+int launch_copy(double *dst, const double *src, int64_t n, hipStream_t st) {
+    if (n <= 0) return HPS_OK;
+    hipLaunchKernelGGL(k_copy, dim3(nblk(n)), dim3(NT), 0, st, dst, src, n);
     HPS_LAUNCHED();
     return HPS_OK;
 }

@@ -17,12 +17,15 @@ HPS_FP64 = 0
 HPS_FP32_IR = 1
 HPS_WIDE_TILES = 2
 HPS_UNIFORM_COEFFS = 4
+HPS_IR_STRICT = 8
+HPS_TEST_FP32_SKEW = 16
+HPS_AUTOTUNE = 32
 ERRORS = {-1: "HPS_EINVAL", -2: "HPS_ENOMEM", -3: "HPS_EDEVICE", -4: "HPS_ESINGULAR",
           -5: "HPS_ENOTCONVERGED"}
 
 # every entry point declared in include/hps.h, include/hps_batch.h and include/hps_serve.h
 EXPORTED = ["hps_last_error", "hps_num_nodes", "hps_nodes", "hps_build", "hps_op_bytes",
-            "hps_solve", "hps_solve_noalloc", "hps_free", "hps_build_complex", "hps_profile_enable", "hps_profile_read", "ark_create", "ark_step", "ark_stage_solves_per_step",
+            "hps_solve", "hps_solve_noalloc", "hps_free", "hps_build_complex", "hps_profile_enable", "hps_profile_read", "ark_create", "ark_step", "ark_info", "ark_stage_solves_per_step",
             "ark_free", "ark_step_slope", "ark_step_burgers", "hps_solve_batched", "ark_step_batched", "hps_batch_streams",
             "srv_create", "srv_submit", "srv_poll", "srv_wait", "srv_release", "srv_get_stats", "srv_destroy"]
 
@@ -44,7 +47,12 @@ class HpsCoeffs(ctypes.Structure):
 
 
 class HpsInfo(ctypes.Structure):
-    _fields_ = [("ir_iterations", ctypes.c_int32), ("last_correction", ctypes.c_double)]
+    _fields_ = [("ir_iterations", ctypes.c_int32), ("last_correction", ctypes.c_double),
+                ("fp64_fallbacks", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"ir_iterations": self.ir_iterations, "last_correction": self.last_correction,
+                "fp64_fallbacks": self.fp64_fallbacks}
 
 
 class ArkTableau(ctypes.Structure):
@@ -77,7 +85,7 @@ class SrvStatus(ctypes.Structure):
 class SrvStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in ("submitted", "completed", "failed", "builds", "cache_hits",
                                               "evictions", "cached_ops", "cached_bytes", "iterations",
-                                              "job_steps")]
+                                              "job_steps", "context_bytes", "waits")]
 
 
 SRV_QUEUED, SRV_ACTIVE, SRV_DONE, SRV_FAILED = 0, 1, 2, 3
@@ -127,6 +135,8 @@ def lib():
     L.ark_step_burgers.argtypes = [vp, vp, dbl, vp, vp, vp, vp, vp]
     L.ark_stage_solves_per_step.restype = i32
     L.ark_stage_solves_per_step.argtypes = [vp]
+    L.ark_info.restype = i32
+    L.ark_info.argtypes = [vp, P(HpsInfo)]
     L.ark_free.restype = None
     L.ark_free.argtypes = [vp]
     L.hps_solve_batched.restype = i32
@@ -316,7 +326,7 @@ def hps_solve(op, body, dirichlet=None, jump=None, u=None, stream=None, info=Fal
                            _dptr(jump, nrhs * op.n_iface, "jump"), _dptr(u, nrhs * op.N, "u"),
                            _stream(stream), ctypes.byref(inf) if info else None))
     if info:
-        return u, {"ir_iterations": inf.ir_iterations, "last_correction": inf.last_correction}
+        return u, inf.as_dict()
     return u
 
 
@@ -394,6 +404,13 @@ def ark_step_burgers(cu, cv, t, u, v, fu_stages=None, fv_stages=None, stream=Non
     return u, v
 
 
+def ark_info(ctx):
+    """Refinement record of the last ark_step (FP32_IR operators; zeros for FP64)."""
+    inf = HpsInfo()
+    _check(lib().ark_info(ctx.handle, ctypes.byref(inf)))
+    return inf.as_dict()
+
+
 def ark_stage_solves_per_step(ctx):
     return _check(lib().ark_stage_solves_per_step(ctx.handle))
 
@@ -436,7 +453,7 @@ def hps_solve_batched(ops, body, dirichlet=None, jump=None, u=None, stream=None,
                                    _ptr_array(jump, [o.n_iface for o in ops], "jump"),
                                    _ptr_array(u, [o.N for o in ops], "u", True), _stream(stream), inf))
     if info:
-        return u, [{"ir_iterations": i.ir_iterations, "last_correction": i.last_correction} for i in inf]
+        return u, [i.as_dict() for i in inf]
     return u
 
 

@@ -1,0 +1,89 @@
+"""hps_solve with several right-hand sides (Algorithm 1 of Sec. 2.1 applied to many data):
+FP64 operators take up to four right-hand sides per leaf launch and per level sweep, every
+operator block read once for all of them.  Each right-hand side must equal the oracle's
+solve (1e-11) and the single-right-hand-side solve bit for bit (the same arithmetic in the
+same order)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.grid import Grid
+from oracle.hps import HPS
+from paper_2306_02526_amd import hps
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    return _t
+
+
+def rel(a, b):
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def coefs(x, y):
+    return dict(cxx=1.0 + 0.3 * np.sin(x + 2 * y), cyy=1.2 + 0.2 * np.cos(3 * x),
+                cx=0.5 * np.sin(y), cy=-0.4 * np.cos(x), c0=0.3 * np.sin(x * y))
+
+
+def build(torch, n1, n2, p, gdt, flags=hps.HPS_FP64):
+    h = 1.0 / max(n1, n2)
+    g = hps.make_grid(0.0, n1 * h, 0.0, n2 * h, n1, n2, p)
+    og = Grid(0.0, n1 * h, 0.0, n2 * h, n1, n2, p)
+    x, y = hps.hps_nodes(g)
+    co = coefs(x[: og.n_int], y[: og.n_int])
+    op = hps.hps_build(g, {k: torch.tensor(v, device="cuda") for k, v in co.items()}, gdt, flags)
+    return og, co, op
+
+
+def solve_both(torch, op, og, nrhs, seed):
+    rng = np.random.default_rng(seed)
+    body = rng.standard_normal((nrhs, og.n_int))
+    dirv = rng.standard_normal((nrhs, op.n_bdry))
+    jump = rng.standard_normal((nrhs, op.n_iface)) if op.n_iface else None
+    T = lambda a: None if a is None else torch.tensor(a, device="cuda")
+    um = hps.hps_solve(op, T(body), T(dirv), T(jump)).cpu().numpy()
+    us = np.stack([hps.hps_solve(op, T(body[r]), T(dirv[r]), None if jump is None else T(jump[r])).cpu().numpy()
+                   for r in range(nrhs)])
+    return body, dirv, jump, um, us
+
+
+@pytest.mark.parametrize("n1,n2,p,nrhs", [(4, 4, 8, 2), (8, 4, 10, 3), (8, 8, 12, 4), (16, 8, 7, 5),
+                                          (2, 16, 9, 7), (1, 1, 6, 3), (2, 1, 24, 4), (16, 16, 16, 4)])
+def test_multi_rhs_equals_single_and_oracle(torch, n1, n2, p, nrhs):
+    say(f"[multi-rhs] {n1}x{n2} p={p} nrhs={nrhs}")
+    gdt = 0.01
+    og, co, op = build(torch, n1, n2, p, gdt)
+    body, dirv, jump, um, us = solve_both(torch, op, og, nrhs, 40 + nrhs + n1)
+    H = HPS(og, co, gdt)
+    for r in range(nrhs):
+        assert np.array_equal(um[r], us[r]), (r, np.abs(um[r] - us[r]).max())
+        e = rel(um[r], H.solve(body[r], dirv[r], None if jump is None else jump[r]))
+        say(f"   rhs {r}: bitwise equal to the single solve; rel err vs oracle {e:.2e}")
+        assert e <= TOL64
+    op.free()
+
+
+def test_multi_rhs_at_full_size(torch):
+    """64x64 leaves, p = 16 (the benchmark grid), four right-hand sides: each equals its
+    single-right-hand-side solve bit for bit."""
+    say("[multi-rhs] 64x64 p=16, nrhs=4")
+    gdt = 2.5e-4
+    og, co, op = build(torch, 64, 64, 16, gdt)
+    _, _, _, um, us = solve_both(torch, op, og, 4, 3)
+    for r in range(4):
+        say(f"   rhs {r}: max |difference| from the single solve {np.abs(um[r] - us[r]).max():.1e}")
+        assert np.array_equal(um[r], us[r])
+    op.free()

@@ -395,6 +395,16 @@ def test_full_size_allen_cahn_step_matches_oracle(torch, full_size_case):
     assert e <= FLOOR_FACTOR * full_size_case["spread"]
 
 
+def test_full_size_composed_step_matches_oracle(torch, full_size_case, monkeypatch):
+    """The same step with the composite level-pair sweeps (HPS_COMPOSE=1): the same bar."""
+    monkeypatch.setenv("HPS_COMPOSE", "1")
+    say("[full size] Allen-Cahn 64x64 p=16, FP64, composite level pairs")
+    e = rel(_full_size_gpu_step(torch, full_size_case, hps.HPS_FP64), full_size_case["ref"])
+    say(f"   rel err {e:.2e} ({e / full_size_case['spread']:.2f} x the oracle spread)")
+    assert e <= TOL_FULL
+    assert e <= FLOOR_FACTOR * full_size_case["spread"]
+
+
 def test_full_size_fp32_ir_step_matches_oracle(torch, full_size_case):
     """The FP32+IR configuration at its own size (64x64 leaves, p = 16, FP32 operators with
     FP64 iterative refinement): one full step element by element against the oracle, to

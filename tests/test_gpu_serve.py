@@ -138,6 +138,43 @@ def test_cache_eviction_keeps_results(torch):
         assert rel(u.cpu().numpy(), P.oracle(3)) <= TOL64
 
 
+def test_tight_budget_makes_jobs_wait_not_fail(torch):
+    """A budget with room for one operator and its contexts, four jobs of two keys stepped
+    at most four at a time: jobs whose operator cannot be cached yet wait in arrival order
+    for running jobs to release theirs; none fails and every result equals the oracle's."""
+    say("[serve] tight budget: jobs wait for memory instead of failing")
+    P1 = Problem(torch, "allen_cahn", 4, 4, 8, 1e-3, 12)
+    P2 = Problem(torch, "heat", 4, 8, 8, 1e-3, 13)
+    op = hps.hps_build(P2.grid, P2.dco, P2.gdt, hps.HPS_WIDE_TILES)
+    budget = int(op.bytes()[0] * 1.6)
+    op.free()
+    srv = hps.Server(cache_bytes=budget, max_active=4)
+    res = [(P, *P.submit(torch, srv, 4)) for P in (P1, P2, P1, P2)]
+    sts = [srv.wait(jid) for _, jid, _ in res]
+    stats = srv.stats()
+    srv.close()
+    say(f"   {stats}")
+    assert all(st["state"] == hps.SRV_DONE for st in sts), sts
+    assert stats["failed"] == 0 and stats["waits"] >= 1 and stats["evictions"] >= 1
+    for P, jid, u in res:
+        assert rel(u.cpu().numpy(), P.oracle(4)) <= TOL64
+
+
+def test_contexts_are_charged_to_the_budget(torch):
+    """A budget that holds the operator but not a job's stepping context: the job can never
+    fit and fails with HPS_ENOMEM (the context is charged, not only the operator)."""
+    say("[serve] budget below operator + context")
+    P = Problem(torch, "allen_cahn", 4, 4, 8, 1e-3, 14)
+    op = hps.hps_build(P.grid, P.dco, P.gdt, hps.HPS_WIDE_TILES)
+    budget = int(op.bytes()[0]) + 4096
+    op.free()
+    srv = hps.Server(cache_bytes=budget, max_active=2)
+    jid, _ = P.submit(torch, srv, 2)
+    st = srv.wait(jid)
+    srv.close()
+    assert st["state"] == hps.SRV_FAILED and st["error"] == -2, st
+
+
 def test_server_rejects_bad_jobs(torch):
     P = Problem(torch, "allen_cahn", 2, 2, 6, 1e-3, 20)
     srv = hps.Server()

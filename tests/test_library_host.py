@@ -76,10 +76,12 @@ def test_null_handles_are_rejected():
     assert L.ark_step_burgers(None, None, 0.0, None, None, None, None, None) == -1
 
 
-@pytest.mark.parametrize("flags", [8, -1, 16 | hps.HPS_FP32_IR])
+@pytest.mark.parametrize("flags", [64, -1, 128 | hps.HPS_FP32_IR, hps.HPS_IR_STRICT, hps.HPS_TEST_FP32_SKEW,
+                                   hps.HPS_IR_STRICT | hps.HPS_WIDE_TILES, hps.HPS_AUTOTUNE | hps.HPS_WIDE_TILES])
 def test_unknown_build_flags_are_rejected(flags):
-    """Only HPS_FP32_IR, HPS_WIDE_TILES and HPS_UNIFORM_COEFFS may be set; the check comes
-    before any device use."""
+    """Only HPS_FP32_IR, HPS_WIDE_TILES, HPS_UNIFORM_COEFFS, HPS_AUTOTUNE (not with
+    HPS_WIDE_TILES) and, with HPS_FP32_IR, HPS_IR_STRICT and HPS_TEST_FP32_SKEW may be set;
+    the check comes before any device use."""
     g = hps.make_grid(0.0, 1.0, 0.0, 1.0, 2, 2, 6)
     fake = ctypes.c_void_p(4096)
     co = hps.HpsCoeffs(fake, fake, fake, fake, fake)
