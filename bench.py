@@ -430,12 +430,17 @@ def main():
     # the level sweeps of one stage solve: the operator bytes outside the leaf panels (A_ii^-1
     # and S_leaf, q2 x q2 and q2 x 4q per leaf) over the up and down sweep times
     level_bytes = op.bytes()[1] - n * n * (q * q * q * q + q * q * 4 * q) * 8
-    level_us = sum(1e3 * prof[k][1] / prof[k][0] for k in ("level_up_fp64", "level_down_fp64") if k in prof)
+    level_fams = ("level_up_fp64", "level_down_fp64", "pair_up_fp64", "pair_top_fp64", "pair_down_fp64")
+    level_us = sum(1e3 * prof[k][1] / prof[k][0] for k in level_fams if k in prof)
+    n_levels = int(math.log2(n * n))
+    composed = "pair_top_fp64" in prof
     levels = {"bytes_per_stage": int(level_bytes), "us_per_stage": round(level_us, 2),
               "achieved_GBps": round(level_bytes / (level_us * 1e-6) / 1e9, 1),
               "frac": round(level_bytes / (level_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
-              "launches_per_stage": 2 * (int(math.log2(n * n)) - 1) + 1,
-              "note": "latency-bound: one dependent launch per tree level and direction"}
+              "launches_per_stage": (2 * (n_levels // 2 - 1) + 1 + 2 * (n_levels % 2)) if composed
+              else 2 * (n_levels - 1) + 1,
+              "composite_level_pairs": composed,
+              "note": "latency-bound: one dependent launch per tree level (level pair, if composed) and direction"}
     traffic = None
     tr_path = os.path.join(ROOT, "profiles", "leaf_down_up_fp64_traffic.json")
     if os.path.exists(tr_path):
@@ -492,6 +497,13 @@ def main():
         torch.cuda.synchronize()
         ms = float(np.median([a.elapsed_time(b) for a, b in evm]))
         multi[str(nrhs)] = {"ms_per_solve_call": round(ms, 4), "rhs_per_s": round(nrhs / (ms * 1e-3), 1)}
+        # where the time goes (HIP events per kernel family, one call, outside the timing)
+        hps.hps_profile_enable(op, True)
+        hps.hps_profile_read(op)
+        hps.hps_solve(op, bm, u=um)
+        torch.cuda.synchronize()
+        multi[str(nrhs)]["us_per_family"] = {k: round(1e3 * v[1], 1) for k, v in hps.hps_profile_read(op).items()}
+        hps.hps_profile_enable(op, False)
     for k in multi:
         multi[k]["time_vs_one_rhs"] = round(multi[k]["ms_per_solve_call"] / multi["1"]["ms_per_solve_call"], 3)
     log(f"multi-rhs hps_solve: {multi}")
@@ -624,11 +636,12 @@ def main():
         log("cpu oracle: one BLAS thread")
         cpu = cpu_baseline(n, p, dt, args.cpu_stage_solves, threads=1, limit_s=240)
         log(f"cpu oracle: {cpu}")
-        # all host cores as BLAS threads (the oracle is many small dense operations per leaf
-        # and node; reported as measured, whether or not threads help)
-        nth = min(os.cpu_count() or 1, 16)
-        log(f"cpu oracle: {nth} BLAS threads")
-        cpu["all_cores"] = cpu_baseline(n, p, dt, args.cpu_stage_solves, threads=nth, limit_s=90)
+        # all host cores: one single-threaded oracle per core, all running the same sample at
+        # once (threaded BLAS does not help the oracle's many small dense operations: with
+        # 16 threads it did not finish the sample within 90 s)
+        nproc = min(os.cpu_count() or 1, 16)
+        log(f"cpu oracle: {nproc} concurrent single-threaded processes")
+        cpu["all_cores"] = cpu_baseline(n, p, dt, args.cpu_stage_solves, threads=1, limit_s=150, procs=nproc)
         log(f"cpu oracle, all cores: {cpu['all_cores']}")
         cpu["config1"] = config1_oracle()
         log(f"cpu oracle, config 1: {cpu['config1']}")
@@ -966,10 +979,12 @@ print(json.dumps(dict(build_s=tb, times=times, err=err)))
             "max_err_vs_exact_at_T": d["err"]}
 
 
-def cpu_baseline(n, p, dt, n_solves, threads=1, limit_s=150):
+def cpu_baseline(n, p, dt, n_solves, threads=1, limit_s=150, procs=1):
     """The oracle (plain NumPy FP64) on this host with `threads` BLAS threads: its build on
     the full grid (timed, not counted), then n_solves implicit stages of the same step
-    timed; value = stage-solves/s on those stages."""
+    timed; value = stage-solves/s on those stages.  procs > 1: that many copies run at once
+    (one per core), value = all their stages over the wall-clock span from the first
+    stage's start to the last stage's end."""
     import subprocess
     code = f"""
 import os, sys, time, json
@@ -987,6 +1002,10 @@ co = dict(cxx=cxx, cyy=cyy, cx=cx, cy=cy, c0=c0)
 tab = tableau_float(ark436l2sa()); dt = {dt}
 t0 = time.perf_counter(); H = HPS(g, co, tab['gamma'] * dt); tb = time.perf_counter() - t0
 print(f"   oracle build {{tb:.1f}} s", file=sys.stderr, flush=True)
+bar, nbar = os.environ.get("ORACLE_BARRIER"), int(os.environ.get("ORACLE_BARRIER_N", "1"))
+if bar:   # concurrent copies: every copy has built before any times its stages
+    open(os.path.join(bar, str(os.getpid())), "w").close()
+    while len(os.listdir(bar)) < nbar: time.sleep(0.005)
 u = wl.u0(x, y); n_int = g.n_int
 A, Ah = tab['A'], tab['Ahat']
 Lu = [apply_L(g, co, u)]; F = [poly_g(workloads.AllenCahn.gpoly, u[:n_int])]
@@ -999,30 +1018,58 @@ for i in range(1, 1 + {n_solves}):
     ui = H.solve(rhs)
     Lu.append(apply_L(g, co, ui)); F.append(poly_g(workloads.AllenCahn.gpoly, ui[:n_int]))
     times.append(time.perf_counter() - t0)
+    if i == 1: start = time.time() - times[-1]
     print(f"   oracle stage {{i}}: {{times[-1]:.1f}} s", file=sys.stderr, flush=True)
-print(json.dumps(dict(build_s=tb, times=times)))
+print(json.dumps(dict(build_s=tb, times=times, start=start, end=time.time())))
 """
     t0 = time.perf_counter()
     th = str(threads)
-    try:
-        # progress lines go straight to stderr; the result is the last stdout line
-        r = subprocess.run([sys.executable, "-c", code], stdout=subprocess.PIPE, text=True, timeout=limit_s,
-                           env=dict(os.environ, OPENBLAS_NUM_THREADS=th, OMP_NUM_THREADS=th, MKL_NUM_THREADS=th))
-    except subprocess.TimeoutExpired:
-        return {"error": f"not finished within {limit_s} s with {threads} BLAS threads"}
-    if r.returncode != 0:
-        return {"error": f"exit status {r.returncode}"}
-    d = json.loads(r.stdout.strip().splitlines()[-1])
-    ts = d["times"]
+    import tempfile
+    bar = tempfile.mkdtemp(prefix="oracle_barrier_")
+    env = dict(os.environ, OPENBLAS_NUM_THREADS=th, OMP_NUM_THREADS=th, MKL_NUM_THREADS=th)
+    if procs > 1:
+        env.update(ORACLE_BARRIER=bar, ORACLE_BARRIER_N=str(procs))
+    # progress lines go straight to stderr; each result is its process's last stdout line
+    ps = [subprocess.Popen([sys.executable, "-c", code], stdout=subprocess.PIPE, text=True, env=env)
+          for _ in range(procs)]
+    outs, err = [], None
+    for pr in ps:
+        try:
+            out, _ = pr.communicate(timeout=max(1.0, limit_s - (time.perf_counter() - t0)))
+            if pr.returncode != 0:
+                err = err or {"error": f"exit status {pr.returncode}"}
+            else:
+                outs.append(json.loads(out.strip().splitlines()[-1]))
+        except subprocess.TimeoutExpired:
+            err = {"error": f"not finished within {limit_s} s ({procs} process(es), {threads} BLAS thread(s) each)"}
+            break
+    for pr in ps:   # nothing is left running
+        if pr.poll() is None:
+            pr.kill()
+        pr.wait()
+    import shutil
+    shutil.rmtree(bar, ignore_errors=True)
+    if err:
+        return err
     try:
         model = [ln.split(":", 1)[1].strip() for ln in open("/proc/cpuinfo") if ln.startswith("model name")][0]
     except Exception:
         model = "unknown"
-    return {"value": round(len(ts) / sum(ts), 4), "unit": "stage-solves/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle build on the full {n}x{n} p={p} grid ({d['build_s']:.1f} s, not counted), then "
-                      f"{len(ts)} implicit stages of one step (rhs assembly, HPS solve, L u_i, F_i) timed",
-            "build_s": round(d["build_s"], 2), "host_cpu": model, "host_nproc": os.cpu_count(),
-            "wall_s": round(time.perf_counter() - t0, 1)}
+    d = outs[0]
+    ts = d["times"]
+    res = {"value": round(len(ts) / sum(ts), 4), "unit": "stage-solves/s", "cores": threads, "kind": "oracle",
+           "sample": f"oracle build on the full {n}x{n} p={p} grid ({d['build_s']:.1f} s, not counted), then "
+                     f"{len(ts)} implicit stages of one step (rhs assembly, HPS solve, L u_i, F_i) timed",
+           "build_s": round(d["build_s"], 2), "host_cpu": model, "host_nproc": os.cpu_count(),
+           "wall_s": round(time.perf_counter() - t0, 1)}
+    if procs > 1:
+        span = max(o["end"] for o in outs) - min(o["start"] for o in outs)
+        total = sum(len(o["times"]) for o in outs)
+        res.update(value=round(total / span, 4), cores=procs * threads, processes=procs,
+                   sample=f"{procs} concurrent copies of: " + res["sample"],
+                   stage_span_s=round(span, 2), build_s_max=round(max(o["build_s"] for o in outs), 2),
+                   per_process_stage_solves_per_s=round(sum(len(o["times"]) / sum(o["times"]) for o in outs) / procs, 4))
+    return res
 
 
 if __name__ == "__main__":

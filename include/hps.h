@@ -57,7 +57,16 @@ extern "C" {
 #define HPS_ENOTCONVERGED  -5   /* iterative refinement did not reach its tolerance  */
 
 /* hps_build flags */
-#define HPS_FP64     0   /* stored operators and their application in FP64          */
+#define HPS_FP64     0   /* stored operators and their application in FP64.  With at
+                            least two tree levels, the level sweeps of such an operator
+                            (real, without HPS_WIDE_TILES) go through composite
+                            operators of level pairs built with it: the two levels'
+                            products multiplied out once per node of the upper level,
+                            one launch per pair and direction instead of one per
+                            level, for about 1.4 times the level operators' memory.
+                            The environment variable HPS_COMPOSE=0 at build time turns
+                            them off (HPS_COMPOSE=1 forces them where the tuner chose
+                            against them); results differ by rounding only.          */
 #define HPS_FP32_IR  1   /* FP64 build; operators applied in FP32 inside an FP64
                             iterative-refinement loop (residual in FP64): corrections
                             until ||delta||_inf <= 1e-11 ||u||_inf, at most 10; a solve

@@ -798,7 +798,7 @@ static int build_op(const hps_grid *grid, const hps_coeffs *coeffs, const hps_co
               "flags HPS_IR_STRICT and HPS_TEST_FP32_SKEW apply to HPS_FP32_IR operators only");
     CHECK_ARG(!((flags & HPS_AUTOTUNE) && (flags & HPS_WIDE_TILES)),
               "flags HPS_AUTOTUNE and HPS_WIDE_TILES exclude each other (the tuner times one problem per launch)");
-    int mwg = 0, compose = 0;
+    int mwg = 0, compose = 1;
     if (flags & HPS_AUTOTUNE) {
         flags &= ~HPS_AUTOTUNE;
         TRY(tune_level_tiling(grid, coeffs, coeffs_im, gamma_dt, flags, (hipStream_t)stream, &mwg, &compose));
@@ -845,7 +845,8 @@ int hps::build_op_tiled(const hps_grid *grid, const hps_coeffs *coeffs, const hp
     op->flags = flags;
     op->ncomp = ncomp;
     op->level_mwg = mwg;
-    // composite pair sweeps: chosen by the tuner, or forced on with HPS_COMPOSE=1 (off with 0)
+    // composite pair sweeps where the operator allows them (the tuner may choose against
+    // them); HPS_COMPOSE=0 turns them off, HPS_COMPOSE=1 on whatever the tuner chose
     const char *cenv = getenv("HPS_COMPOSE");
     op->composed = cenv && cenv[0] ? cenv[0] == '1' : compose != 0;
     int rc = build_impl(op, coeffs, coeffs_im, (hipStream_t)stream);

@@ -136,7 +136,8 @@ void unref(SharedEvent *ev) {
 
 struct GroupPlan {
     struct Launch {
-        int kind;            // 0 leaf phase, 1 level up, 2 level down, 3 roots, 4 boundary, 5 lines
+        int kind;            // 0 leaf phase, 1 level up, 2 level down, 3 roots, 4 boundary, 5 lines,
+                             // 6 / 7 / 8 composite pairs up / down / top
         size_t a, a2, base;  // offsets of the records (a2: downward root records) and bases
         int cnt, total;
         size_t lds;
@@ -313,7 +314,42 @@ int build_plan(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, const
     // one sweep: upward levels aligned at the roots, the fused roots, downward levels
     int Lmax = 0;
     for (int b = 0; b < n; ++b) Lmax = std::max(Lmax, ctx[b]->op->L);
-    const size_t ls = level_record_size();
+    const size_t ls = level_record_size(), prs = pair_record_size();
+    // operators with composite level pairs sweep pair (l, l + 1) at its upper level l and
+    // only the bottom level of an odd tree with the single-level kernels
+    auto single_here = [&](const hps_op *op, int l) -> bool {
+        if (l >= op->L) return false;
+        if (op->composed) return (op->L % 2 == 1) && l == op->L - 1;
+        return !(l == 0 && root_fused64(op));
+    };
+    auto pair_here = [&](const hps_op *op, int l, int mode) -> bool {
+        if (!op->composed) return false;
+        if (mode == 2) return l == 0;
+        return l >= 2 && l % 2 == 0 && l <= pair_lowest(op);
+    };
+    auto pair_launch = [&](int l, int mode) -> int {   // mode 0 up, 1 down, 2 the top pairs
+        GroupPlan::Launch L{};
+        L.kind = 6 + mode;
+        std::vector<unsigned char> recs;
+        std::vector<int> bs(1, 0);
+        for (int b = 0; b < n; ++b) {
+            const hps_op *op = ctx[b]->op;
+            if (!pair_here(op, l, mode)) continue;
+            recs.resize(recs.size() + prs);
+            int blocks = 0;
+            size_t lds = 0;
+            pair_record(op, l, mode, nullptr, recs.data() + recs.size() - prs, &blocks, &lds, ws[b]);
+            L.lds = std::max(L.lds, lds);
+            bs.push_back(bs.back() + blocks);
+        }
+        L.cnt = (int)bs.size() - 1;
+        if (L.cnt == 0) return HPS_OK;
+        L.a = T.put(recs.data(), recs.size());
+        L.base = T.put(bs.data(), sizeof(int) * bs.size());
+        L.total = bs.back();
+        P->sweep.push_back(L);
+        return HPS_OK;
+    };
     auto level_launch = [&](int l, bool up) -> int {
         GroupPlan::Launch L{};
         L.kind = up ? 1 : 2;
@@ -321,7 +357,7 @@ int build_plan(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, const
         std::vector<int> bs(1, 0);
         for (int b = 0; b < n; ++b) {
             const hps_op *op = ctx[b]->op;
-            if (l >= op->L || (l == 0 && root_fused64(op))) continue;
+            if (!single_here(op, l)) continue;
             recs.resize(recs.size() + ls);
             int blocks = 0;
             size_t lds = 0;
@@ -337,7 +373,11 @@ int build_plan(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, const
         P->sweep.push_back(L);
         return HPS_OK;
     };
-    for (int l = Lmax - 1; l >= 0; --l) TRY(level_launch(l, true));
+    for (int l = Lmax - 1; l >= 0; --l) {
+        TRY(level_launch(l, true));
+        TRY(pair_launch(l, 0));
+    }
+    TRY(pair_launch(0, 2));
     {
         GroupPlan::Launch L{};
         L.kind = 3;
@@ -345,7 +385,7 @@ int build_plan(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, const
         std::vector<int> bs(1, 0);
         for (int b = 0; b < n; ++b) {
             const hps_op *op = ctx[b]->op;
-            if (!root_fused64(op)) continue;
+            if (op->composed || !root_fused64(op)) continue;
             ups.resize(ups.size() + ls);
             dns.resize(dns.size() + ls);
             int blocks = 0;
@@ -363,7 +403,10 @@ int build_plan(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, const
             P->sweep.push_back(L);
         }
     }
-    for (int l = 0; l < Lmax; ++l) TRY(level_launch(l, false));
+    for (int l = 0; l < Lmax; ++l) {
+        TRY(pair_launch(l, 1));
+        TRY(level_launch(l, false));
+    }
     // boundary values (zero) and interface line solves of the update
     {
         const size_t zs = scatter_record_size(), lr = line_record_size();
@@ -396,6 +439,7 @@ int enqueue_plan(const GroupPlan *P, hipStream_t st) {
     auto run_sweep = [&]() -> int {
         for (const GroupPlan::Launch &L : P->sweep) {
             if (L.kind == 3) TRY(launch_root_group(d + L.a, d + L.a2, basep(L), L.cnt, L.total, L.lds, st));
+            else if (L.kind >= 6) TRY(launch_pair_group(d + L.a, basep(L), L.cnt, L.total, L.lds, L.kind - 6, st));
             else TRY(launch_level_group(d + L.a, basep(L), L.cnt, L.total, L.lds, L.kind == 1, st));
         }
         return HPS_OK;

@@ -114,21 +114,43 @@ int64_t level_nodes(int l) { return int64_t(1) << l; }
 
 }  // namespace
 
-static int pair_min_wg(const hps_op *op) { return op->level_mwg > 0 ? op->level_mwg : 1024; }
+// Workgroups a composite's launch is cut into: about two per compute unit.  A composite
+// holds two levels' products, so thin tiles (the level panels' rule, at most 16 loads per
+// lane) would take two rounds of workgroups; with two per compute unit every workgroup is
+// resident at once and streams its longer rows (measured at 64x64 leaves, p = 16: 181 µs
+// for both sweeps of a stage against 210 µs with the thin-tile rule and 210 µs per level).
+static int pair_target() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                                hipSuccess || cus <= 0) {
+        (void)hipGetLastError();
+        cus = 256;
+    }
+    return 2 * cus;
+}
+
+// The packing of a composite: rows cut into tiles so that the launch has about `target`
+// workgroups (at most NT / 2 row vectors per tile: one row per thread)
+static Panel pair_panel(int R, int C, int nodes, int target) {
+    const int RV = (R + 1) / 2;
+    const int per = std::max(1, (target + nodes - 1) / nodes);   // row tiles per node
+    const int rp_max = std::min(NT / 2, std::max(1, (RV + per - 1) / per));
+    return plan_panel(R, C, 2, nodes, rp_max, 0);
+}
 
 // Composites need one workgroup's input vector in LDS (no split-K), FP64 real per-node
 // operators and at least the root and one level below it.
 bool hps::compose_eligible(const hps_op *op, const std::vector<HostLevel> &hl) {
-    if (op->ncomp != 1 || op->build_one || (op->flags & (HPS_FP32_IR | HPS_WIDE_TILES)) || op->L < 2) return false;
+    if (op->ncomp != 1 || (op->flags & (HPS_FP32_IR | HPS_WIDE_TILES)) || op->L < 2) return false;
     // the top pair (0, 1), then (2, 3), (4, 5), ... while the lower level exists
     for (int l = 0; l + 1 < op->L; l += 2) {
         const HostLevel &t = hl[l], &c = hl[l + 1];
         const int n12t = t.n1 + t.n2, nt = (int)level_nodes(l);
         const int CV = 2 * c.n3 + t.n3;
         if (l == 0) {
-            if (plan_panel(t.n3 + 2 * c.n3, n12t + CV, 2, 1, 64, pair_min_wg(op)).kch != 1) return false;
-        } else if (plan_panel(CV + n12t, CV, 2, nt, 64, pair_min_wg(op)).kch != 1 ||
-                   plan_panel(t.n3 + 2 * c.n3, n12t + t.n3, 2, nt, 64, pair_min_wg(op)).kch != 1) {
+            if (pair_panel(t.n3 + 2 * c.n3, n12t + CV, 1, pair_target()).kch != 1) return false;
+        } else if (pair_panel(CV + n12t, CV, nt, pair_target()).kch != 1 ||
+                   pair_panel(t.n3 + 2 * c.n3, n12t + t.n3, nt, pair_target()).kch != 1) {
             return false;
         }
     }
@@ -144,8 +166,10 @@ int hps::compose_pair(hps_op *op, int l, const std::vector<HostLevel> &hl, const
     const int nbcc = Cl.nbc;
     const Pos pos{Cl, nbcc};
     const int nt = (int)level_nodes(l);
+    // uniform coefficients: one node's operators (children equal), composites stored once
+    const bool uni = op->build_one;
+    const int nb = uni ? 1 : nt;   // nodes whose composites are computed
     const bool top = (l == 0);
-    const int mwg = pair_min_wg(op);
     DevScratch tmp;
     // index vectors on the device: the upper level's maps, padded to its boundary length
     std::vector<int> a1pad(n12t, -1), b2pad(n12t, -1);
@@ -157,58 +181,59 @@ int hps::compose_pair(hps_op *op, int l, const std::vector<HostLevel> &hl, const
     TRY(tmp.upload(&d_a1pad, a1pad, st));
     TRY(tmp.upload(&d_b2pad, b2pad, st));
     const int64_t sX = (int64_t)n3c * n3c, sU = (int64_t)n12c * n3c, sS = (int64_t)n3c * n12c;   // per child
-    const double *Xa = Xc, *Xb = Xc + sX, *Ua = Uc, *Ub = Uc + sU, *Sa = Sc, *Sb = Sc + sS;
+    const int64_t cb = uni ? 0 : 1;   // the second child's operators follow the first's
+    const double *Xa = Xc, *Xb = Xc + cb * sX, *Ua = Uc, *Ub = Uc + cb * sU, *Sa = Sc, *Sb = Sc + cb * sS;
 
     PairOps P;
     P.l = l;
     // V = [-U_a[a3,:] | U_b[b3,:] | I]  (n3t x (2 n3c + n3t)) per node
     const int CV = 2 * n3c + n3t;
     double *V;
-    TRY(tmp.get(&V, (int64_t)n3t * CV * nt));
+    TRY(tmp.get(&V, (int64_t)n3t * CV * nb));
     const int64_t sV = (int64_t)n3t * CV;
-    TRY(launch_place(V, n3t, sV, 0, 0, n3t, n3c, Ua, n12c, 2 * sU, d_a3, nullptr, -1.0, false, nt, st));
-    TRY(launch_place(V, n3t, sV, 0, n3c, n3t, n3c, Ub, n12c, 2 * sU, d_b3, nullptr, 1.0, false, nt, st));
-    TRY(launch_place(V, n3t, sV, 0, 2 * n3c, n3t, n3t, nullptr, 0, 0, nullptr, nullptr, 1.0, false, nt, st));
+    TRY(launch_place(V, n3t, sV, 0, 0, n3t, n3c, Ua, n12c, 2 * sU, d_a3, nullptr, -1.0, false, nb, st));
+    TRY(launch_place(V, n3t, sV, 0, n3c, n3t, n3c, Ub, n12c, 2 * sU, d_b3, nullptr, 1.0, false, nb, st));
+    TRY(launch_place(V, n3t, sV, 0, 2 * n3c, n3t, n3t, nullptr, 0, 0, nullptr, nullptr, 1.0, false, nb, st));
     // the children's S restricted to the upper node's J3 columns
     double *Sa3, *Sb3;
-    TRY(tmp.get(&Sa3, (int64_t)n3c * n3t * nt));
-    TRY(tmp.get(&Sb3, (int64_t)n3c * n3t * nt));
+    TRY(tmp.get(&Sa3, (int64_t)n3c * n3t * nb));
+    TRY(tmp.get(&Sb3, (int64_t)n3c * n3t * nb));
     const int64_t s3 = (int64_t)n3c * n3t;
-    TRY(launch_place(Sa3, n3c, s3, 0, 0, n3c, n3t, Sa, n3c, 2 * sS, nullptr, d_a3, 1.0, false, nt, st));
-    TRY(launch_place(Sb3, n3c, s3, 0, 0, n3c, n3t, Sb, n3c, 2 * sS, nullptr, d_b3, 1.0, false, nt, st));
+    TRY(launch_place(Sa3, n3c, s3, 0, 0, n3c, n3t, Sa, n3c, 2 * sS, nullptr, d_a3, 1.0, false, nb, st));
+    TRY(launch_place(Sb3, n3c, s3, 0, 0, n3c, n3t, Sb, n3c, 2 * sS, nullptr, d_b3, 1.0, false, nb, st));
 
     double *Mup = nullptr, *Mdn = nullptr;
     if (!top) {
         // ---- upward composite [w3_a; w3_b; w3_tau; h_tau] x [d_a; d_b; e] ----
         const int R = 2 * n3c + n3t + n12t, C = CV;
         const int64_t sM = (int64_t)R * C;
-        TRY(tmp.get(&Mup, sM * nt));
-        TRY(launch_zero(Mup, sM * nt, st));
-        TRY(launch_place(Mup, R, sM, 0, 0, n3c, n3c, Xa, n3c, 2 * sX, nullptr, nullptr, 1.0, false, nt, st));
-        TRY(launch_place(Mup, R, sM, n3c, n3c, n3c, n3c, Xb, n3c, 2 * sX, nullptr, nullptr, 1.0, false, nt, st));
-        TRY(launch_dgemm(n3t, C, n3t, Xt, n3t, (int64_t)n3t * n3t, V, n3t, sV, Mup + 2 * n3c, R, sM, nt, 1.0, 0.0, st));
+        TRY(tmp.get(&Mup, sM * nb));
+        TRY(launch_zero(Mup, sM * nb, st));
+        TRY(launch_place(Mup, R, sM, 0, 0, n3c, n3c, Xa, n3c, 2 * sX, nullptr, nullptr, 1.0, false, nb, st));
+        TRY(launch_place(Mup, R, sM, n3c, n3c, n3c, n3c, Xb, n3c, 2 * sX, nullptr, nullptr, 1.0, false, nb, st));
+        TRY(launch_dgemm(n3t, C, n3t, Xt, n3t, (int64_t)n3t * n3t, V, n3t, sV, Mup + 2 * n3c, R, sM, nb, 1.0, 0.0, st));
         const int h0 = 2 * n3c + n3t;
-        TRY(launch_place(Mup, R, sM, h0, 0, n12t, n3c, Ua, n12c, 2 * sU, d_a1pad, nullptr, 1.0, false, nt, st));
-        TRY(launch_place(Mup, R, sM, h0, n3c, n12t, n3c, Ub, n12c, 2 * sU, d_b2pad, nullptr, 1.0, false, nt, st));
-        TRY(launch_dgemm(n12t, C, n3t, Ut, n12t, (int64_t)n12t * n3t, V, n3t, sV, Mup + h0, R, sM, nt, 1.0, 1.0, st));
+        TRY(launch_place(Mup, R, sM, h0, 0, n12t, n3c, Ua, n12c, 2 * sU, d_a1pad, nullptr, 1.0, false, nb, st));
+        TRY(launch_place(Mup, R, sM, h0, n3c, n12t, n3c, Ub, n12c, 2 * sU, d_b2pad, nullptr, 1.0, false, nb, st));
+        TRY(launch_dgemm(n12t, C, n3t, Ut, n12t, (int64_t)n12t * n3t, V, n3t, sV, Mup + h0, R, sM, nb, 1.0, 1.0, st));
         P.R_up = R;
         P.C_up = C;
         // ---- downward composite [u3_tau; u3_a; u3_b] x [u12; w3_tau] ----
         const int Rd = n3t + 2 * n3c, Cd = n12t + n3t;
         const int64_t sD = (int64_t)Rd * Cd;
         double *W;
-        TRY(tmp.get(&W, (int64_t)n3t * Cd * nt));
+        TRY(tmp.get(&W, (int64_t)n3t * Cd * nb));
         const int64_t sW = (int64_t)n3t * Cd;
-        TRY(launch_place(W, n3t, sW, 0, 0, n3t, n12t, St, n3t, (int64_t)n3t * n12t, nullptr, nullptr, 1.0, false, nt, st));
-        TRY(launch_place(W, n3t, sW, 0, n12t, n3t, n3t, nullptr, 0, 0, nullptr, nullptr, 1.0, false, nt, st));
-        TRY(tmp.get(&Mdn, sD * nt));
-        TRY(launch_zero(Mdn, sD * nt, st));
-        TRY(launch_place(Mdn, Rd, sD, 0, 0, n3t, n12t, St, n3t, (int64_t)n3t * n12t, nullptr, nullptr, 1.0, false, nt,
+        TRY(launch_place(W, n3t, sW, 0, 0, n3t, n12t, St, n3t, (int64_t)n3t * n12t, nullptr, nullptr, 1.0, false, nb, st));
+        TRY(launch_place(W, n3t, sW, 0, n12t, n3t, n3t, nullptr, 0, 0, nullptr, nullptr, 1.0, false, nb, st));
+        TRY(tmp.get(&Mdn, sD * nb));
+        TRY(launch_zero(Mdn, sD * nb, st));
+        TRY(launch_place(Mdn, Rd, sD, 0, 0, n3t, n12t, St, n3t, (int64_t)n3t * n12t, nullptr, nullptr, 1.0, false, nb,
                          st));
-        TRY(launch_place(Mdn, Rd, sD, n3t, 0, n3c, n12t, Sa, n3c, 2 * sS, nullptr, d_a1pad, 1.0, false, nt, st));
-        TRY(launch_place(Mdn, Rd, sD, n3t + n3c, 0, n3c, n12t, Sb, n3c, 2 * sS, nullptr, d_b2pad, 1.0, false, nt, st));
-        TRY(launch_dgemm(n3c, Cd, n3t, Sa3, n3c, s3, W, n3t, sW, Mdn + n3t, Rd, sD, nt, 1.0, 1.0, st));
-        TRY(launch_dgemm(n3c, Cd, n3t, Sb3, n3c, s3, W, n3t, sW, Mdn + n3t + n3c, Rd, sD, nt, 1.0, 1.0, st));
+        TRY(launch_place(Mdn, Rd, sD, n3t, 0, n3c, n12t, Sa, n3c, 2 * sS, nullptr, d_a1pad, 1.0, false, nb, st));
+        TRY(launch_place(Mdn, Rd, sD, n3t + n3c, 0, n3c, n12t, Sb, n3c, 2 * sS, nullptr, d_b2pad, 1.0, false, nb, st));
+        TRY(launch_dgemm(n3c, Cd, n3t, Sa3, n3c, s3, W, n3t, sW, Mdn + n3t, Rd, sD, nb, 1.0, 1.0, st));
+        TRY(launch_dgemm(n3c, Cd, n3t, Sb3, n3c, s3, W, n3t, sW, Mdn + n3t + n3c, Rd, sD, nb, 1.0, 1.0, st));
         P.R_dn = Rd;
         P.C_dn = Cd;
     } else {
@@ -231,8 +256,10 @@ int hps::compose_pair(hps_op *op, int l, const std::vector<HostLevel> &hl, const
     }
 
     // ---- pack (streaming layout, FP64) ----
+    const int target = pair_target();
     auto pack = [&](Panel &pn, const double *M, int R, int C) -> int {
-        pn = plan_panel(R, C, 2, nt, 64, mwg);
+        pn = pair_panel(R, C, nt, target);
+        if (uni) pn = shared_panel(pn);
         double *d;
         if (hipMalloc(&d, sizeof(double) * pn.node_elems * pn.nodes) != hipSuccess) {
             (void)hipGetLastError();

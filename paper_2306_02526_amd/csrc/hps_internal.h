@@ -335,6 +335,12 @@ void level_record(const hps_op *op, int l, bool up, const double *dir, void *dst
 bool root_fused64(const hps_op *op);
 void root_records(const hps_op *op, const double *dir, void *up_dst, void *dn_dst, int *blocks, size_t *lds,
                   const Workspace *ws);
+// composite level pairs in grouped launches: mode 0 upward, 1 downward, 2 the top pair
+size_t pair_record_size();
+int pair_lowest(const hps_op *op);
+void pair_record(const hps_op *op, int l, int mode, const double *dir, void *dst, int *blocks, size_t *lds,
+                 const Workspace *ws);
+int launch_pair_group(const void *args, const int *base, int n, int total, size_t lds, int mode, hipStream_t st);
 size_t line_record_size();
 void line_record(const hps_op *op, double *u, void *dst, int *systems, const Workspace *ws);
 size_t scatter_record_size();

@@ -78,6 +78,41 @@ __device__ __forceinline__ double slice_sum(const double *red, double *red2, int
     return y;
 }
 
+// slice_sum for NC right-hand sides at once: component c's slices at red + c * rstride,
+// its group sums at red2 + c * 64.  The same additions in the same order as slice_sum, for
+// every component, with the barriers shared.  Every thread calls it; y[c] is valid in
+// threads t < rows.
+template <int NC>
+__device__ __forceinline__ void slice_sum_n(const double *red, int rstride, double *red2, int nsl, int rows,
+                                            double y[NC]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) y[c] = 0.0;
+    if (nsl <= 16) {
+        if (t < rows)
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                for (int s2 = 0; s2 < nsl; ++s2) y[c] += red[c * rstride + s2 * rows + t];
+        return;
+    }
+    const int ng = (nsl + 7) / 8;   // ng * rows <= NT / 8 + rows <= 64
+    if (t < ng * rows) {
+        const int g = t / rows, r = t % rows;
+        const int s1 = min(nsl, g * 8 + 8);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double z = 0.0;
+            for (int s2 = g * 8; s2 < s1; ++s2) z += red[c * rstride + s2 * rows + r];
+            red2[c * 64 + g * rows + r] = z;
+        }
+    }
+    __syncthreads();
+    if (t < rows)
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            for (int g = 0; g < ng; ++g) y[c] += red2[c * 64 + g * rows + t];
+}
+
 // =======================================================================================
 // level kernels (upward: w3 = X d, h = [h1; h2] + U d; downward: u3 = S u12 + w3)
 // =======================================================================================
@@ -426,6 +461,159 @@ __global__ __launch_bounds__(NT) void k_pair(PairArgs a) {
     pair_body<T, MODE>(a, blockIdx.x, smem, red);
 }
 
+// A composite product for NC right-hand sides (component c's buffers in A.c[c]; the panel
+// and tables of A.c[0]): the operator block is streamed once for all of them, and every
+// component's arithmetic is pair_body's, in the same order.
+template <int NC>
+struct PairArgsN {
+    PairArgs c[NC];
+};
+
+template <int NC, int MODE>
+__device__ __forceinline__ void pair_sys_body(const PairArgsN<NC> &A, int blk, unsigned char *smem) {
+    constexpr int VW = 2;
+    const PairArgs &a = A.c[0];
+    const int ntile = a.pn.ntile;
+    const int tile = blk % ntile;
+    const int node = blk / ntile;
+    const int SG = a.pn.S * a.pn.G;
+    const int pst = a.pn.G * a.pn.rp * VW;
+    Carve cv{smem};
+    double *xs = cv.take<double>((size_t)NC * SG);
+    double *part = cv.take<double>((size_t)NC * pst);
+    double *redn = cv.take<double>((size_t)NC * NT);
+    double *red2n = cv.take<double>((size_t)NC * 64);
+    PanelStream<double, PF, UNR> ps;
+    ps.start(reinterpret_cast<const double *>(a.pn.data) + (int64_t)node * a.pn.node_elems + (int64_t)tile * a.pn.tile_elems,
+             a.pn.rp, a.pn.G, a.pn.S);
+    const int rows = a.pn.rp * VW;
+    const int myrow = tile * rows + threadIdx.x;
+    const int64_t gbase = MODE == PAIR_TOP ? 0 : (int64_t)node * 4 * a.nbcc;
+    const int *tab = a.tab;
+    int kind = -1, idx = 0, p1 = -1, p2 = -1;
+    double base[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) base[c] = 0.0;
+    if ((int)threadIdx.x < rows && myrow < a.R) {
+        if (MODE == PAIR_UP) {
+            kind = tab[a.t_fin + 3 * myrow];
+            idx = tab[a.t_fin + 3 * myrow + 1];
+            if (kind == 2) {
+                const int pass = tab[a.t_fin + 3 * myrow + 2];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) base[c] = A.c[c].hg[gbase + pass];
+            }
+        } else {
+            kind = tab[a.t_fin + 4 * myrow];
+            idx = tab[a.t_fin + 4 * myrow + 1];
+            p1 = tab[a.t_fin + 4 * myrow + 2];
+            p2 = tab[a.t_fin + 4 * myrow + 3];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                if (kind == 1) base[c] = A.c[c].w3_t[(int64_t)node * a.n3t + idx];
+                else if (kind == 0) base[c] = A.c[c].w3_c[(int64_t)node * 2 * a.n3c + idx];
+            }
+        }
+    }
+    for (int k = threadIdx.x; k < SG; k += NT) {
+        double x[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) x[c] = 0.0;
+        if (k < a.C) {
+            if (MODE == PAIR_DOWN) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    x[c] = k < a.n12t ? A.c[c].ub_t[(int64_t)node * a.n12t + k]
+                                      : A.c[c].w3_t[(int64_t)node * a.n3t + k - a.n12t];
+            } else if (MODE == PAIR_TOP && k < a.n12t) {
+                const int rm = a.root_map[k];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) x[c] = A.c[c].dir ? A.c[c].dir[rm] : 0.0;
+            } else {
+                const int tp = tab[a.t_plus + k], tm = tab[a.t_minus + k];
+                const int jc = tab[a.t_j3 + k];
+                const int64_t j = jc >= 0 ? a.j3i_c[(int64_t)node * 2 * a.n3c + jc] : a.j3i_t[(int64_t)node * a.n3t - jc - 1];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    x[c] = A.c[c].hg[gbase + tp] - A.c[c].hg[gbase + tm];
+                    if (A.c[c].r3) x[c] += A.c[c].r3[j];
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) xs[c * SG + k] = x[c];
+    }
+    if (MODE != PAIR_UP) {
+        const int per = (a.n12t + ntile - 1) / ntile;
+        const int m1 = min(a.n12t, (tile + 1) * per);
+        for (int m = tile * per + threadIdx.x; m < m1; m += NT) {
+            const int dst = tab[a.t_copy + m];
+            const int rm = MODE == PAIR_TOP ? a.root_map[m] : 0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double v = MODE == PAIR_DOWN ? A.c[c].ub_t[(int64_t)node * a.n12t + m]
+                                                   : (A.c[c].dir ? A.c[c].dir[rm] : 0.0);
+                A.c[c].ubg[gbase + dst] = v;
+            }
+        }
+    }
+    __syncthreads();
+    ps.template finish_n<NC>(xs, SG, part, pst);
+    __syncthreads();
+    const int G = a.pn.G;
+    const int nsl = min(G, NT / rows);
+    const int t = threadIdx.x;
+    const int row = t % rows, sl = t / rows;
+    if (sl < nsl) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double y = 0.0;
+            for (int gg = sl; gg < G; gg += nsl) y += part[c * pst + gg * rows + row];
+            redn[c * NT + sl * rows + row] = y;
+        }
+    }
+    __syncthreads();
+    double y[NC];
+    slice_sum_n<NC>(redn, NT, red2n, nsl, rows, y);
+    if (t < rows && myrow < a.R) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const PairArgs &ac = A.c[c];
+            if (MODE == PAIR_UP) {
+                if (kind == 0) ac.w3_c[(int64_t)node * 2 * a.n3c + idx] = y[c];
+                else if (kind == 1) ac.w3_t[(int64_t)node * a.n3t + idx] = y[c];
+                else ac.h_t[(int64_t)node * a.n12t + idx] = base[c] + y[c];
+            } else {
+                const double u3 = y[c] + base[c];
+                ac.ubg[gbase + p1] = u3;
+                if (p2 >= 0) ac.ubg[gbase + p2] = u3;
+            }
+        }
+    }
+}
+
+template <int NC, int MODE>
+__global__ __launch_bounds__(NT) void k_pair_sys(PairArgsN<NC> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    pair_sys_body<NC, MODE>(a, blockIdx.x, smem);
+}
+
+// One composite product of several operators in one launch: workgroup w belongs to entry
+// e, base[e] <= w < base[e + 1].
+template <int MODE>
+__global__ __launch_bounds__(NT) void k_pair_group(const PairArgs *args, const int *base, int n) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT + 64];
+    const int w = blockIdx.x;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    pair_body<double, MODE>(args[lo], w - base[lo], smem, red);
+}
+
 // =======================================================================================
 // two-component level products (FP64): both components of one (node, row tile, column
 // chunk) in one workgroup, the operator block streamed once for both
@@ -436,7 +624,11 @@ struct LevelSysArgsN {
 };
 using LevelSysArgs = LevelSysArgsN<2>;
 
-template <int NC, bool UP>
+// One (node, row tile, column chunk) of a level product for NC right-hand sides: the
+// operator block is streamed once for all of them.  The input gathers of all components
+// share one chain of index loads, and the row sums of all components share their barriers;
+// every component's arithmetic is that of level_body, in the same order.
+template <int NC, bool UP, int PFX = PF, int UNRX = UNR>
 __device__ __forceinline__ void level_sys_body(const LevelSysArgsN<NC> &A, int blk, unsigned char *smem, double *red,
                                                int *s_last) {
     constexpr int VW = 2;
@@ -450,7 +642,9 @@ __device__ __forceinline__ void level_sys_body(const LevelSysArgsN<NC> &A, int b
     Carve cv{smem};
     double *xs = cv.take<double>((size_t)NC * SG);
     double *part = cv.take<double>((size_t)NC * pst);
-    PanelStream<double, PF, UNR> ps;
+    double *redn = cv.take<double>((size_t)NC * NT);   // slice partials of every component
+    double *red2n = cv.take<double>((size_t)NC * 64);  // their group sums
+    PanelStream<double, PFX, UNRX> ps;
     ps.start(reinterpret_cast<const double *>(a.pn.data) + (int64_t)node * a.pn.node_elems +
                  (int64_t)(tile * kch + chunk) * a.pn.tile_elems,
              a.pn.rp, a.pn.G, a.pn.S);
@@ -477,64 +671,83 @@ __device__ __forceinline__ void level_sys_body(const LevelSysArgsN<NC> &A, int b
         }
     }
     const int cols = UP ? a.n3 : a.n12;
+    for (int k = threadIdx.x; k < SG; k += NT) {
+        const int kg = chunk * SG + k;
+        double x[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        const LevelArgs &ac = A.c[c];
-        for (int k = threadIdx.x; k < SG; k += NT) {
-            const int kg = chunk * SG + k;
-            double x = 0.0;
-            if (kg < cols) {
-                if (UP) {
-                    const double *ha = ac.hc + (int64_t)(2 * node) * a.nbc;
-                    const double *hb = ac.hc + (int64_t)(2 * node + 1) * a.nbc;
-                    x = hb[a.b3[kg]] - ha[a.a3[kg]];
-                    if (ac.r3) x += ac.r3[a.j3i[(int64_t)node * a.n3 + kg]];
-                } else {
-                    x = down_input(ac, ac.dir, node, kg);
+        for (int c = 0; c < NC; ++c) x[c] = 0.0;
+        if (kg < cols) {
+            if (UP) {
+                const int64_t pb = (int64_t)(2 * node + 1) * a.nbc + a.b3[kg];
+                const int64_t pa = (int64_t)(2 * node) * a.nbc + a.a3[kg];
+                const int64_t j = a.j3i[(int64_t)node * a.n3 + kg];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    x[c] = A.c[c].hc[pb] - A.c[c].hc[pa];
+                    if (A.c[c].r3) x[c] += A.c[c].r3[j];
                 }
+            } else if (a.root) {
+                const int rm = a.root_map[kg];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) x[c] = A.c[c].dir ? A.c[c].dir[rm] : 0.0;
+            } else {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) x[c] = A.c[c].ub[(int64_t)node * a.n12 + kg];
             }
-            xs[c * SG + k] = x;
         }
-        if (!UP) {
-            const int nblk_node = ntile * kch, me = tile * kch + chunk;
-            const int per = (a.n12 + nblk_node - 1) / nblk_node;
-            const int m1 = min(a.n12, (me + 1) * per);
-            for (int m = me * per + threadIdx.x; m < m1; m += NT) {
-                const double v = down_input(ac, ac.dir, node, m);
-                if (m < a.n1) ac.ubc[(int64_t)(2 * node) * a.nbc + a.a1[m]] = v;
-                else ac.ubc[(int64_t)(2 * node + 1) * a.nbc + a.b2[m - a.n1]] = v;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) xs[c * SG + k] = x[c];
+    }
+    if (!UP) {
+        // the J1 / J2 parts of the children's boundary data are the parent's own; the
+        // workgroups of the node copy one slice each
+        const int nblk_node = ntile * kch, me = tile * kch + chunk;
+        const int per = (a.n12 + nblk_node - 1) / nblk_node;
+        const int m1 = min(a.n12, (me + 1) * per);
+        for (int m = me * per + threadIdx.x; m < m1; m += NT) {
+            const int64_t dst = (m < a.n1) ? (int64_t)(2 * node) * a.nbc + a.a1[m]
+                                           : (int64_t)(2 * node + 1) * a.nbc + a.b2[m - a.n1];
+            const int rm = a.root ? a.root_map[m] : 0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const LevelArgs &ac = A.c[c];
+                const double v = a.root ? (ac.dir ? ac.dir[rm] : 0.0) : ac.ub[(int64_t)node * a.n12 + m];
+                ac.ubc[dst] = v;
             }
         }
     }
     __syncthreads();
-    ps.finish_n<NC>(xs, SG, part, pst);
+    ps.template finish_n<NC>(xs, SG, part, pst);
     __syncthreads();
     if (kch == 1) {
         const int G = a.pn.G;
         const int nsl = min(G, NT / rows);
         const int t = threadIdx.x;
         const int row = t % rows, sl = t / rows;
+        if (sl < nsl) {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const LevelArgs &ac = A.c[c];
-            if (sl < nsl) {
+            for (int c = 0; c < NC; ++c) {
                 double y = 0.0;
                 for (int gg = sl; gg < G; gg += nsl) y += part[c * pst + gg * rows + row];
-                red[sl * rows + row] = y;
+                redn[c * NT + sl * rows + row] = y;
             }
-            __syncthreads();
-            const double y = slice_sum(red, red + NT, nsl, rows);
-            if (t < rows) {
+        }
+        __syncthreads();
+        double y[NC];
+        slice_sum_n<NC>(redn, NT, red2n, nsl, rows, y);
+        if (t < rows) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const LevelArgs &ac = A.c[c];
                 if (UP) {
-                    if (myrow < a.n3) ac.w3[(int64_t)node * a.n3 + myrow] = y;
-                    else if (!a.root && myrow < a.n3 + a.n12) ac.h[(int64_t)node * a.n12 + myrow - a.n3] = fin[c] + y;
+                    if (myrow < a.n3) ac.w3[(int64_t)node * a.n3 + myrow] = y[c];
+                    else if (!a.root && myrow < a.n3 + a.n12) ac.h[(int64_t)node * a.n12 + myrow - a.n3] = fin[c] + y[c];
                 } else if (myrow < a.n3) {
-                    const double u3 = y + fin[c];
+                    const double u3 = y[c] + fin[c];
                     ac.ubc[ia] = u3;
                     ac.ubc[ib] = u3;
                 }
             }
-            __syncthreads();
         }
         return;
     }
@@ -585,6 +798,16 @@ __global__ __launch_bounds__(NT) void k_level_sys(LevelSysArgsN<NC> a) {
     __shared__ double red[NT + 64];
     __shared__ int s_last;
     level_sys_body<NC, UP>(a, blockIdx.x, smem, red, &s_last);
+}
+
+// Panels with S <= PF_SMALL: the same products with fewer registers.
+template <int NC, bool UP>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_level_sys_small(
+    LevelSysArgsN<NC> a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT + 64];
+    __shared__ int s_last;
+    level_sys_body<NC, UP, PF_SMALL, PF_SMALL>(a, blockIdx.x, smem, red, &s_last);
 }
 
 // =======================================================================================
@@ -1197,48 +1420,61 @@ static void use_workspace(const hps_op *op, int l, bool up, const Workspace *ws,
 // FP64 sweeps through the composite level pairs: the top pair (root and level 1) in one
 // launch, pairs (l, l + 1) for even l >= 2 one launch per direction, and an odd number of
 // levels leaves the bottom level to the single-level kernels.
+// The arguments of composite pair l's kernel (mode PAIR_UP / PAIR_DOWN / PAIR_TOP), on the
+// operator's solve buffers or on workspace ws.
+static PairArgs pair_args(const hps_op *op, int l, int mode, const double *jump, const double *dirichlet,
+                          const Workspace *ws) {
+    const int L = op->L;
+    auto hbuf = [&](int k) -> double * {
+        if (k == L) return ws ? ws->h_leaf : op->h_leaf;
+        return ws ? ws->lv[k].h : op->lv[k].h;
+    };
+    auto ubbuf = [&](int k) -> double * {
+        if (k == L) return ws ? ws->ub_leaf : op->ub_leaf;
+        return ws ? ws->lv[k].ub : op->lv[k].ub;
+    };
+    auto w3buf = [&](int k) -> double * { return ws ? ws->lv[k].w3 : op->lv[k].w3; };
+    const bool up = (mode == PAIR_UP);
+    const PairOps &P = op->pairs[l / 2];
+    const Level &T = op->lv[l], &Cl = op->lv[l + 1];
+    PairArgs a{};
+    a.pn = view(up ? P.up : P.dn);
+    a.R = up ? P.R_up : P.R_dn;
+    a.C = up ? P.C_up : P.C_dn;
+    a.n3t = T.n3;
+    a.n12t = T.n12;
+    a.n3c = Cl.n3;
+    a.nbcc = Cl.nbc;
+    a.tab = P.tab;
+    a.t_plus = P.t_plus;
+    a.t_minus = P.t_minus;
+    a.t_j3 = P.t_j3;
+    a.t_fin = up ? P.t_fin_up : P.t_fin_dn;
+    a.t_copy = P.t_copy;
+    a.hg = hbuf(l + 2);
+    a.r3 = jump;
+    a.j3i_t = T.j3i;
+    a.j3i_c = Cl.j3i;
+    a.h_t = hbuf(l);
+    a.w3_t = w3buf(l);
+    a.w3_c = w3buf(l + 1);
+    a.ub_t = ubbuf(l);
+    a.ubg = ubbuf(l + 2);
+    a.dir = dirichlet;
+    a.root_map = op->root_map;
+    return a;
+}
+
+// The upper level of the lowest composite pair (an odd number of levels leaves the bottom
+// level to the single-level kernels).
+static int lowest_pair(const hps_op *op) { return (op->L % 2 == 1) ? op->L - 3 : op->L - 2; }
+
+// FP64 sweeps through the composite level pairs: the top pair (root and level 1) in one
+// launch, pairs (l, l + 1) for even l >= 2 one launch per direction, and an odd number of
+// levels leaves the bottom level to the single-level kernels.
 static int launch_pairs(const hps_op *op, const double *jump, const double *dirichlet, hipStream_t st,
                         const Workspace *ws) {
     const int L = op->L;
-    auto hbuf = [&](int l) -> double * {
-        if (l == L) return ws ? ws->h_leaf : op->h_leaf;
-        return ws ? ws->lv[l].h : op->lv[l].h;
-    };
-    auto ubbuf = [&](int l) -> double * {
-        if (l == L) return ws ? ws->ub_leaf : op->ub_leaf;
-        return ws ? ws->lv[l].ub : op->lv[l].ub;
-    };
-    auto w3buf = [&](int l) -> double * { return ws ? ws->lv[l].w3 : op->lv[l].w3; };
-    auto pair_args = [&](int l, bool up) {
-        const PairOps &P = op->pairs[l / 2];
-        const Level &T = op->lv[l], &Cl = op->lv[l + 1];
-        PairArgs a{};
-        a.pn = view(up ? P.up : P.dn);
-        a.R = up ? P.R_up : P.R_dn;
-        a.C = up ? P.C_up : P.C_dn;
-        a.n3t = T.n3;
-        a.n12t = T.n12;
-        a.n3c = Cl.n3;
-        a.nbcc = Cl.nbc;
-        a.tab = P.tab;
-        a.t_plus = P.t_plus;
-        a.t_minus = P.t_minus;
-        a.t_j3 = P.t_j3;
-        a.t_fin = up ? P.t_fin_up : P.t_fin_dn;
-        a.t_copy = P.t_copy;
-        a.hg = hbuf(l + 2);
-        a.r3 = jump;
-        a.j3i_t = T.j3i;
-        a.j3i_c = Cl.j3i;
-        a.h_t = hbuf(l);
-        a.w3_t = w3buf(l);
-        a.w3_c = w3buf(l + 1);
-        a.ub_t = ubbuf(l);
-        a.ubg = ubbuf(l + 2);
-        a.dir = dirichlet;
-        a.root_map = op->root_map;
-        return a;
-    };
     auto single = [&](int l, bool up) {
         LevelArgs a = level_args(op, l, false, up);
         use_workspace(op, l, up, ws, a);
@@ -1250,12 +1486,12 @@ static int launch_pairs(const hps_op *op, const double *jump, const double *diri
         else launch_level<double, false>(a, nb, level_lds(pn), st);
         HPS_LAUNCHED();
     };
-    const int top_low = (L % 2 == 1) ? L - 3 : L - 2;   // the lowest pair's upper level
+    const int top_low = lowest_pair(op);
     {
         ProfScope ps_(&op->prof, KF_PAIR_UP64, st);
         if (L % 2 == 1) single(L - 1, true);
         for (int l = top_low; l >= 2; l -= 2) {
-            const PairArgs a = pair_args(l, true);
+            const PairArgs a = pair_args(op, l, PAIR_UP, jump, dirichlet, ws);
             const Panel &pn = op->pairs[l / 2].up;
             hipLaunchKernelGGL((k_pair<double, PAIR_UP>), dim3((unsigned)(op->lv[l].nodes * pn.ntile)), dim3(NT),
                                level_lds(pn), st, a);
@@ -1264,14 +1500,14 @@ static int launch_pairs(const hps_op *op, const double *jump, const double *diri
     }
     {
         ProfScope ps_(&op->prof, KF_PAIR_TOP64, st);
-        const PairArgs a = pair_args(0, false);
+        const PairArgs a = pair_args(op, 0, PAIR_TOP, jump, dirichlet, ws);
         const Panel &pn = op->pairs[0].dn;
         hipLaunchKernelGGL((k_pair<double, PAIR_TOP>), dim3((unsigned)pn.ntile), dim3(NT), level_lds(pn), st, a);
         HPS_LAUNCHED();
     }
     ProfScope ps_(&op->prof, KF_PAIR_DOWN64, st);
     for (int l = 2; l <= top_low; l += 2) {
-        const PairArgs a = pair_args(l, false);
+        const PairArgs a = pair_args(op, l, PAIR_DOWN, jump, dirichlet, ws);
         const Panel &pn = op->pairs[l / 2].dn;
         hipLaunchKernelGGL((k_pair<double, PAIR_DOWN>), dim3((unsigned)(op->lv[l].nodes * pn.ntile)), dim3(NT),
                            level_lds(pn), st, a);
@@ -1334,7 +1570,8 @@ int launch_levels(const hps_op *op, bool fp32, const double *jump, const double 
 // ---- two components on one operator (FP64) ----
 
 static size_t sys_level_lds(const Panel &pn, int nc) {
-    return carve_bytes({(size_t)nc * pn.S * pn.G * 8, (size_t)nc * pn.G * pn.rp * pn.vw * 8});
+    return carve_bytes({(size_t)nc * pn.S * pn.G * 8, (size_t)nc * pn.G * pn.rp * pn.vw * 8, (size_t)nc * NT * 8,
+                        (size_t)nc * 64 * 8});
 }
 
 static size_t sys_root_lds(const hps_op *op, int nc) {
@@ -1362,12 +1599,113 @@ bool levels_multi_fit(const hps_op *op, int nc) {
     return true;
 }
 
+// One level's product for NC right-hand sides (component c: workspace ws[c], Dirichlet
+// data dir[c], interface jumps jump[c]; null: the operator's own / zero).
+template <int NC>
+static int level_multi_launch(const hps_op *op, int l, bool up, const Workspace *const *ws,
+                              const double *const *dir, const double *const *jump, size_t lim, hipStream_t st) {
+    const Panel &pn = up ? op->lv[l].xu64 : op->lv[l].s64;
+    const unsigned nb = (unsigned)(op->lv[l].nodes * pn.ntile * pn.kch);
+    // at most NC * XS_BYTES of input vectors plus the partial sums: within the LDS of a
+    // gfx950 workgroup (160 KiB) for the sizes callers pass
+    const size_t lds = sys_level_lds(pn, NC);
+    if (lds > lim) {
+        hps_set_error("%d-component level product needs %zu bytes of LDS, the device allows %zu", NC, lds, lim);
+        return HPS_EDEVICE;
+    }
+    LevelSysArgsN<NC> A;
+    for (int c = 0; c < NC; ++c) {
+        A.c[c] = level_args(op, l, false, up);
+        use_workspace(op, l, up, ws[c], A.c[c]);
+        A.c[c].dir = dir ? dir[c] : nullptr;
+        A.c[c].r3 = jump ? jump[c] : nullptr;
+    }
+    if (pn.S <= PF_SMALL) {
+        if (up) hipLaunchKernelGGL((k_level_sys_small<NC, true>), dim3(nb), dim3(NT), lds, st, A);
+        else hipLaunchKernelGGL((k_level_sys_small<NC, false>), dim3(nb), dim3(NT), lds, st, A);
+    } else {
+        if (up) hipLaunchKernelGGL((k_level_sys<NC, true>), dim3(nb), dim3(NT), lds, st, A);
+        else hipLaunchKernelGGL((k_level_sys<NC, false>), dim3(nb), dim3(NT), lds, st, A);
+    }
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+static size_t pair_sys_lds(const Panel &pn, int nc) {
+    return carve_bytes({(size_t)nc * pn.S * pn.G * 8, (size_t)nc * pn.G * pn.rp * pn.vw * 8, (size_t)nc * NT * 8,
+                        (size_t)nc * 64 * 8});
+}
+
+template <int K, int MODE>
+static void pair_sys_launch(const hps_op *op, int l, const PairArgs *cs, hipStream_t st) {
+    const Panel &pn = MODE == PAIR_UP ? op->pairs[l / 2].up : op->pairs[l / 2].dn;
+    const unsigned nb = (unsigned)(op->lv[l].nodes * pn.ntile);
+    if (K == 1) {   // the single-problem kernel (the same arithmetic, fewer registers)
+        hipLaunchKernelGGL((k_pair<double, MODE>), dim3(nb), dim3(NT), level_lds(pn), st, cs[0]);
+    } else {
+        PairArgsN<K> A;
+        for (int c = 0; c < K; ++c) A.c[c] = cs[c];
+        hipLaunchKernelGGL((k_pair_sys<K, MODE>), dim3(nb), dim3(NT), pair_sys_lds(pn, K), st, A);
+    }
+}
+
+// Composite pair l (mode PAIR_UP / PAIR_DOWN / PAIR_TOP) for components cs[0..n): as many
+// components per launch as the LDS holds (the top pair's input vectors are the longest).
+template <int MODE>
+static int pair_multi_launch(const hps_op *op, int l, const PairArgs *cs, int n, size_t lim, hipStream_t st) {
+    const Panel &pn = MODE == PAIR_UP ? op->pairs[l / 2].up : op->pairs[l / 2].dn;
+    int k = n;
+    while (k > 1 && pair_sys_lds(pn, k) > lim) --k;
+    for (int c0 = 0; c0 < n; c0 += k) {
+        switch (std::min(k, n - c0)) {
+            case 1: pair_sys_launch<1, MODE>(op, l, cs + c0, st); break;
+            case 2: pair_sys_launch<2, MODE>(op, l, cs + c0, st); break;
+            case 3: pair_sys_launch<3, MODE>(op, l, cs + c0, st); break;
+            default: pair_sys_launch<4, MODE>(op, l, cs + c0, st); break;
+        }
+        HPS_LAUNCHED();
+    }
+    return HPS_OK;
+}
+
+// The sweeps of an operator with composite pairs for NC right-hand sides: each composite
+// (and the single bottom level of an odd tree) streamed once for all of them.
+template <int NC>
+static int pairs_multi(const hps_op *op, const Workspace *const *ws, const double *const *dir,
+                       const double *const *jump, hipStream_t st, int fam_up, int fam_dn) {
+    const size_t lim = sys_lds_limit();
+    const int L = op->L, top_low = lowest_pair(op);
+    PairArgs cs[NC];
+    auto fill = [&](int l, int mode) {
+        for (int c = 0; c < NC; ++c)
+            cs[c] = pair_args(op, l, mode, jump ? jump[c] : nullptr, dir ? dir[c] : nullptr, ws[c]);
+    };
+    {
+        ProfScope ps_(&op->prof, fam_up, st);
+        if (L % 2 == 1) TRY(level_multi_launch<NC>(op, L - 1, true, ws, dir, jump, lim, st));
+        for (int l = top_low; l >= 2; l -= 2) {
+            fill(l, PAIR_UP);
+            TRY(pair_multi_launch<PAIR_UP>(op, l, cs, NC, lim, st));
+        }
+    }
+    ProfScope ps_(&op->prof, fam_dn, st);
+    fill(0, PAIR_TOP);
+    TRY(pair_multi_launch<PAIR_TOP>(op, 0, cs, NC, lim, st));
+    for (int l = 2; l <= top_low; l += 2) {
+        fill(l, PAIR_DOWN);
+        TRY(pair_multi_launch<PAIR_DOWN>(op, l, cs, NC, lim, st));
+    }
+    if (L % 2 == 1) TRY(level_multi_launch<NC>(op, L - 1, false, ws, dir, jump, lim, st));
+    return HPS_OK;
+}
+
 // The level sweeps of NC right-hand sides at once (FP64): every operator block is read
 // once for all of them.  ws[c], dir[c], jump[c]: component c's solve buffers (null: the
 // operator's own), Dirichlet data and interface jumps (null: zero).
 template <int NC>
 static int levels_multi(const hps_op *op, const Workspace *const *ws, const double *const *dir,
                         const double *const *jump, hipStream_t st, int fam_up, int fam_dn) {
+    if (op->composed) return pairs_multi<NC>(op, ws, dir, jump, st, fam_up, fam_dn);
     const size_t lim = sys_lds_limit();
     auto comp_args = [&](int l, bool up, int c) {
         LevelArgs a = level_args(op, l, false, up);
@@ -1376,29 +1714,12 @@ static int levels_multi(const hps_op *op, const Workspace *const *ws, const doub
         a.r3 = jump ? jump[c] : nullptr;
         return a;
     };
-    auto run_level = [&](int l, bool up) -> int {
-        const Panel &pn = up ? op->lv[l].xu64 : op->lv[l].s64;
-        const unsigned nb = (unsigned)(op->lv[l].nodes * pn.ntile * pn.kch);
-        // at most NC * XS_BYTES of input vectors plus the partial sums: within the LDS of a
-        // gfx950 workgroup (160 KiB) for the sizes callers pass
-        const size_t lds = sys_level_lds(pn, NC);
-        if (lds > lim) {
-            hps_set_error("%d-component level product needs %zu bytes of LDS, the device allows %zu", NC, lds, lim);
-            return HPS_EDEVICE;
-        }
-        LevelSysArgsN<NC> A;
-        for (int c = 0; c < NC; ++c) A.c[c] = comp_args(l, up, c);
-        if (up) hipLaunchKernelGGL((k_level_sys<NC, true>), dim3(nb), dim3(NT), lds, st, A);
-        else hipLaunchKernelGGL((k_level_sys<NC, false>), dim3(nb), dim3(NT), lds, st, A);
-        HPS_LAUNCHED();
-        return HPS_OK;
-    };
     // the fused root only while two workgroups fit on a compute unit: above that the
     // separate up and down root launches are faster (measured at 64x64 leaves, p = 16)
     const bool rootf = root_fusable(op, false) && sys_root_lds(op, NC) <= std::min<size_t>(lim, 65536);
     {
         ProfScope ps_(&op->prof, fam_up, st);
-        for (int l = op->L - 1; l >= (rootf ? 1 : 0); --l) TRY(run_level(l, true));
+        for (int l = op->L - 1; l >= (rootf ? 1 : 0); --l) TRY(level_multi_launch<NC>(op, l, true, ws, dir, jump, lim, st));
     }
     ProfScope ps_(&op->prof, fam_dn, st);
     if (op->L == 0) {
@@ -1418,7 +1739,7 @@ static int levels_multi(const hps_op *op, const Workspace *const *ws, const doub
         hipLaunchKernelGGL(k_root_sys<NC>, dim3(op->lv[0].xu64.ntile), dim3(NT), sys_root_lds(op, NC), st, U, Dn);
         HPS_LAUNCHED();
     }
-    for (int l = rootf ? 1 : 0; l < op->L; ++l) TRY(run_level(l, false));
+    for (int l = rootf ? 1 : 0; l < op->L; ++l) TRY(level_multi_launch<NC>(op, l, false, ws, dir, jump, lim, st));
     return HPS_OK;
 }
 
@@ -1464,6 +1785,28 @@ void level_record(const hps_op *op, int l, bool up, const double *dir, void *dst
 }
 
 bool root_fused64(const hps_op *op) { return root_fusable(op, false); }
+
+size_t pair_record_size() { return sizeof(PairArgs); }
+
+int pair_lowest(const hps_op *op) { return lowest_pair(op); }
+
+void pair_record(const hps_op *op, int l, int mode, const double *dir, void *dst, int *blocks, size_t *lds,
+                 const Workspace *ws) {
+    *reinterpret_cast<PairArgs *>(dst) = pair_args(op, l, mode, nullptr, dir, ws);
+    const Panel &pn = mode == PAIR_UP ? op->pairs[l / 2].up : op->pairs[l / 2].dn;
+    *blocks = (int)(op->lv[l].nodes * pn.ntile);
+    *lds = level_lds(pn);
+}
+
+int launch_pair_group(const void *args, const int *base, int n, int total, size_t lds, int mode, hipStream_t st) {
+    if (total <= 0) return HPS_OK;
+    const PairArgs *a = reinterpret_cast<const PairArgs *>(args);
+    if (mode == PAIR_UP) hipLaunchKernelGGL(k_pair_group<PAIR_UP>, dim3(total), dim3(NT), lds, st, a, base, n);
+    else if (mode == PAIR_DOWN) hipLaunchKernelGGL(k_pair_group<PAIR_DOWN>, dim3(total), dim3(NT), lds, st, a, base, n);
+    else hipLaunchKernelGGL(k_pair_group<PAIR_TOP>, dim3(total), dim3(NT), lds, st, a, base, n);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
 
 void root_records(const hps_op *op, const double *dir, void *up_dst, void *dn_dst, int *blocks, size_t *lds,
                   const Workspace *ws) {

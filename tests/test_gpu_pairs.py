@@ -1,4 +1,5 @@
-"""Composite level-pair sweeps (HPS_COMPOSE=1) through the C ABI.
+"""Composite level-pair sweeps through the C ABI (the default for FP64 real operators;
+the tests set HPS_COMPOSE=1 explicitly, HPS_COMPOSE=0 turns them off).
 
 The upward and downward products of two adjacent tree levels (the merge formulas after
 eqs. (7)-(8), Algorithm 1 of Sec. 2.1) are multiplied out at build time and swept by one
@@ -6,7 +7,8 @@ launch per pair and direction.  The result is the same solve, rounded differentl
 is held to the FP64 bar against the oracle on trees with an even and an odd number of
 levels (top pair only; top pair plus a single bottom level; several pairs), with
 Dirichlet data and interface jumps; through stepping, graph replay and the
-allocation-free entry point; and at the benchmark size in tests/test_gpu_parity.py.
+allocation-free entry point; and at the benchmark size in tests/test_gpu_parity.py
+(which also holds the per-level sweeps to the same bar there).
 """
 import sys
 
@@ -91,8 +93,8 @@ def test_pair_solve_matches_oracle(torch, monkeypatch, n1, n2, p):
 
 
 def test_pairs_not_used_where_they_do_not_apply(torch, monkeypatch):
-    """One tree level (no pair), FP32 operators and uniform coefficients keep the
-    single-level sweeps; the solve is still the oracle's."""
+    """One tree level (no pair) and FP32 operators keep the single-level sweeps; the solve
+    is still the oracle's."""
     monkeypatch.setenv("HPS_COMPOSE", "1")
     rng = np.random.default_rng(5)
     gdt = 0.01
@@ -166,3 +168,33 @@ def test_pair_noalloc_equals_solve(torch, monkeypatch):
     torch.cuda.synchronize()
     assert torch.equal(u1, u2)
     op.free()
+
+
+def test_uniform_operator_pairs_stored_once(torch, monkeypatch):
+    """Constant coefficients (HPS_UNIFORM_COEFFS): every node's composite is the same, so it
+    is computed and stored once; the sweeps use it and equal the per-node operator's bit
+    for bit."""
+    monkeypatch.setenv("HPS_COMPOSE", "1")
+    say("[pairs] uniform coefficients, 8x8 p=10")
+    const = lambda x, y: dict(cxx=1.3 + 0 * x, cyy=0.8 + 0 * x, cx=0.2 + 0 * x, cy=-0.1 + 0 * x, c0=0.05 + 0 * x)
+    h = 1.0 / 8
+    g = hps.make_grid(0.0, 1.0, 0.0, 1.0, 8, 8, 10)
+    og = Grid(0.0, 1.0, 0.0, 1.0, 8, 8, 10)
+    x, y = hps.hps_nodes(g)
+    co = const(x[: og.n_int], y[: og.n_int])
+    dco = {k: torch.tensor(v, device="cuda") for k, v in co.items()}
+    full = hps.hps_build(g, dco, 0.01, hps.HPS_FP64)
+    uni = hps.hps_build(g, dco, 0.01, hps.HPS_UNIFORM_COEFFS)
+    assert uni.bytes()[1] * 4 < full.bytes()[1]
+    rng = np.random.default_rng(8)
+    T = lambda a: torch.tensor(a, device="cuda")
+    body, dirv, jump = rng.standard_normal(og.n_int), rng.standard_normal(full.n_bdry), rng.standard_normal(full.n_iface)
+    a = hps.hps_solve(full, T(body), T(dirv), T(jump))
+    b, fam = families(uni, torch, lambda: hps.hps_solve(uni, T(body), T(dirv), T(jump)))
+    assert PAIR_FAMILIES & fam, fam
+    assert torch.equal(a, b)
+    e = rel(b.cpu().numpy(), HPS(og, co, 0.01).solve(body, dirv, jump))
+    say(f"   rel err vs oracle {e:.2e}")
+    assert e <= TOL64
+    full.free()
+    uni.free()

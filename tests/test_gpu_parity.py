@@ -395,10 +395,11 @@ def test_full_size_allen_cahn_step_matches_oracle(torch, full_size_case):
     assert e <= FLOOR_FACTOR * full_size_case["spread"]
 
 
-def test_full_size_composed_step_matches_oracle(torch, full_size_case, monkeypatch):
-    """The same step with the composite level-pair sweeps (HPS_COMPOSE=1): the same bar."""
-    monkeypatch.setenv("HPS_COMPOSE", "1")
-    say("[full size] Allen-Cahn 64x64 p=16, FP64, composite level pairs")
+def test_full_size_per_level_step_matches_oracle(torch, full_size_case, monkeypatch):
+    """The same step with one launch per tree level and direction (HPS_COMPOSE=0, the
+    sweeps of operators without composite level pairs): the same bar."""
+    monkeypatch.setenv("HPS_COMPOSE", "0")
+    say("[full size] Allen-Cahn 64x64 p=16, FP64, per-level sweeps")
     e = rel(_full_size_gpu_step(torch, full_size_case, hps.HPS_FP64), full_size_case["ref"])
     say(f"   rel err {e:.2e} ({e / full_size_case['spread']:.2f} x the oracle spread)")
     assert e <= TOL_FULL
