@@ -540,6 +540,26 @@ static int build_impl(hps_op *op, const hps_coeffs *co, const hps_coeffs *co_im,
     TRY(upload(op, &op->leaf_ij, leaf_ij, st));
     TRY(upload(op, &op->root_map, root_map, st));
     TRY(upload(op, &op->bnd_glob, bnd_glob, st));
+    {
+        // boundary index of the two end nodes of every interface line (the line kernel
+        // takes them from the boundary data), -1 for lines without unknowns
+        std::vector<int> glob_to_b(op->N, -1);
+        for (int64_t b = 0; b < op->n_bdry; ++b) glob_to_b[bnd_glob[b]] = (int)b;
+        const int nvs = op->grid.n2 * q, nhs = op->grid.n1 * q;
+        std::vector<int> ends(2 * (size_t)(nvs + nhs), -1);
+        for (int t = 0; t < nvs + nhs; ++t) {
+            const bool vert = t < nvs;
+            const int n = vert ? op->grid.n1 : op->grid.n2;
+            if (n < 2) continue;
+            const int line = vert ? t / q : (t - nvs) / q, m0 = (vert ? t : t - nvs) % q;
+            const int64_t stride = vert ? (int64_t)op->grid.n2 * q : (int64_t)op->grid.n1 * q;
+            const int64_t u0 = vert ? op->n_int + (int64_t)line * q + m0
+                                    : op->n_int + op->n_vert + (int64_t)line * q + m0;
+            ends[2 * t] = glob_to_b[u0];
+            ends[2 * t + 1] = glob_to_b[u0 + n * stride];
+        }
+        TRY(upload(op, &op->line_ends, ends, st));
+    }
     {   // Thomas factors of the interface-line systems (constant coefficients)
         const int nmax = std::max(g.n1, g.n2);
         const double lower = D[(size_t)(op->p - 1) * op->p + 0];

@@ -146,6 +146,8 @@ struct hps_op {
     int *leaf_ij = nullptr;                // device [nleaves][2] heap order -> (i, j)
     int *root_map = nullptr;               // device [n_bdry] root boundary -> boundary index
     int *bnd_glob = nullptr;               // device [n_bdry] boundary index -> canonical index
+    int *line_ends = nullptr;              // device [lines][2] boundary index of each interface
+                                           // line's end nodes (-1: a line without unknowns)
     double *tri_cp = nullptr;              // device: Thomas factors cp[k], then 1/den[k]
     int tri_stride = 0;                    // offset of the 1/den table in tri_cp
     hps::Panel ainv64, sleaf64, ainv32, sleaf32;

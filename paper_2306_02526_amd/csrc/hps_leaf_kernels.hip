@@ -84,6 +84,21 @@ __device__ __forceinline__ double poly_g(const GPoly &g, double u) {
     return g.g0 + u * (g.g1 + u * (g.g2 + u * g.g3));
 }
 
+// u^n + sum over the stages before `last` of (ca_j L u_j + cf_j F_j) at interior node
+// base + k: the part of a stage right-hand side (or of the step update) that does not
+// depend on the stage just solved, so its loads can be issued early.
+__device__ __forceinline__ double older_stages(const LeafArgs &a, int64_t base, int k, int last) {
+    const int64_t n_int = a.geo.n_int;
+    double r = a.un[base + k];
+    for (int j = 0; j < last; ++j) {
+        r += a.ca[j] * a.Lu_in[j * n_int + base + k];
+        r += a.cf[j] * a.F_in[j * n_int + base + k];
+    }
+    return r;
+}
+
+constexpr int HOIST = 1;   // interior nodes per thread whose older-stage sums are hoisted
+
 // One leaf (heap index `leaf`) of one operator: the down phase of the stage that ends here
 // and the up phase of the stage that starts here, as selected by DN and UPM.
 template <typename T, int DN, int UPM>
@@ -105,6 +120,20 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
     constexpr bool stream_down = DN == DOWN_WRITE_U || DN == DOWN_STAGE || DN == DOWN_IR_ADD;
     constexpr bool stream_up = UPM == UP_BODY || UPM == UP_STAGE;
     constexpr bool need_L = DN == DOWN_STAGE || DN == DOWN_EVAL;
+    // the older stages' part of the next right-hand side (or of the update), loaded while the
+    // down phase gathers its own inputs instead of after it
+    constexpr bool hoist = (UPM == UP_STAGE || UPM == UP_UPDATE) && DN != DOWN_NONE;
+    const int last_old = UPM == UP_STAGE ? a.nprev - 1 : a.nprev;
+    double older[HOIST];
+    auto load_older = [&]() {
+        if constexpr (hoist) {
+#pragma unroll
+            for (int i = 0; i < HOIST; ++i) {
+                const int k = threadIdx.x + i * NT;
+                older[i] = k < q2 ? older_stages(a, base, k, last_old) : 0.0;
+            }
+        }
+    };
     PanelStream<T, LPF, LUNR> ps;
     if constexpr (stream_down)
         ps.start(reinterpret_cast<const T *>(a.sl.data) + (int64_t)leaf * a.sl.node_elems, a.sl.rp, a.sl.G, a.sl.S,
@@ -125,6 +154,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
             const double *ubl = a.ub + (int64_t)leaf * nb;
             const int SG = a.sl.S * a.sl.G;
             for (int k = threadIdx.x; k < SG; k += NT) xs[k] = (T)(k < nb ? ubl[k] : 0.0);
+            load_older();
             __syncthreads();
             for (int k = threadIdx.x; k < nb; k += NT) tile[edge_tile_pos(p, q, k / q, k % q)] = ubl[k];
             ps.finish(xs, part);
@@ -138,6 +168,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
             });
         } else {
             // DOWN_EVAL: the tile of a given canonical vector
+            load_older();
             __syncthreads();
             for (int k = threadIdx.x; k < q2; k += NT) tile[(k / q + 1) * p + (k % q) + 1] = a.u_eval[base + k];
             for (int k = threadIdx.x; k < nb; k += NT)
@@ -228,12 +259,8 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
     if constexpr (UPM == UP_UPDATE) {
         // interior u^{n+1}; the newest stage's L u, F are in LDS
         const int last = a.nprev;
-        for (int k = threadIdx.x; k < q2; k += NT) {
-            double v = a.un[base + k];
-            for (int j = 0; j < last; ++j) {
-                v += a.ca[j] * a.Lu_in[j * n_int + base + k];
-                v += a.cf[j] * a.F_in[j * n_int + base + k];
-            }
+        for (int k = threadIdx.x, i = 0; k < q2; k += NT, ++i) {
+            double v = (hoist && i < HOIST) ? older[i] : older_stages(a, base, k, last);
             v += a.ca[last] * luv[k] + a.cf[last] * fv[k];
             a.unew[base + k] = v;
             tile[k] = v;   // reuse as the interior values, row-major
@@ -253,18 +280,14 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
         return;
     }
     const int SG = a.ainv.S * a.ainv.G;
-    for (int k = threadIdx.x; k < SG; k += NT) {
+    for (int k = threadIdx.x, i = 0; k < SG; k += NT, ++i) {
         double r = 0.0;
         if (k < q2) {
             if (UPM == UP_BODY) {
                 r = a.body[base + k];
             } else {
-                r = a.un[base + k];
                 const int last = a.nprev - 1;   // newest stage, held in LDS
-                for (int j = 0; j < last; ++j) {
-                    r += a.ca[j] * a.Lu_in[j * n_int + base + k];
-                    r += a.cf[j] * a.F_in[j * n_int + base + k];
-                }
+                r = (hoist && i < HOIST) ? older[i] : older_stages(a, base, k, last);
                 r += a.ca[last] * luv[k] + a.cf[last] * fv[k];
                 if (a.rhs_copy) a.rhs_copy[base + k] = r;
             }

@@ -933,6 +933,12 @@ struct LineArgs {
     const double *cp;         // Thomas factors: cp[k], k = 1..nmax-1
     const double *inv_den;    // 1 / (diag - lower cp[k-1])
     const double *jump;       // flux_alpha - flux_beta per interface node (interface order) or null
+    // the LDS kernel: the lines' end values come from the boundary data (f[ends[2t]],
+    // f[ends[2t+1]], zero without f), and its workgroups also write all nb boundary values
+    // of u (u[bnd_glob[k]] = f[k]) -- the boundary scatter in the same launch
+    const double *f;
+    const int *ends, *bnd_glob;
+    int64_t nb;
 };
 
 // The arithmetic of one line system, shared by both line kernels so that they give the
@@ -1047,7 +1053,7 @@ __device__ __forceinline__ void line_body(const LineArgs &a, int t) {
 // LINES lines per workgroup of LINE_NT threads: all waves first load the lines' right-hand
 // sides (every equation of every line at once, no dependent chain) into LDS, then one
 // thread per line runs the recursion out of LDS and writes only the final values.
-constexpr int LINES = 64;
+constexpr int LINES = 16;
 constexpr int LINE_NT = 256;
 
 __global__ __launch_bounds__(LINE_NT) void k_interface_lines_lds(LineArgs a, int nmax) {
@@ -1068,10 +1074,17 @@ __global__ __launch_bounds__(LINE_NT) void k_interface_lines_lds(LineArgs a, int
         sid[k] = a.inv_den[k];
         scp[k] = a.cp[k];
     }
+    // the boundary values of u, a slice per workgroup
+    {
+        const int64_t per = (a.nb + gridDim.x - 1) / gridDim.x;
+        const int64_t k1 = min(a.nb, (int64_t)(blockIdx.x + 1) * per);
+        for (int64_t k = (int64_t)blockIdx.x * per + threadIdx.x; k < k1; k += LINE_NT)
+            a.u[a.bnd_glob[k]] = a.f ? a.f[k] : 0.0;
+    }
     double e0 = 0.0, en = 0.0;
     if (on) {
-        e0 = a.u[L.u0];
-        en = a.u[L.u0 + (int64_t)L.n * L.ustride];
+        e0 = a.f ? a.f[a.ends[2 * t]] : 0.0;
+        en = a.f ? a.f[a.ends[2 * t + 1]] : 0.0;
         for (int k = 1 + wv; k < L.n; k += NW)
             rr[k * LINES + lane] = line_rhs(a.fpart[L.l0 + k * L.lstride + L.elo * g.q],
                                             a.fpart[L.l0 + (k - 1) * L.lstride + L.ehi * g.q], a.jump,
@@ -1901,8 +1914,6 @@ int launch_residual(const hps_op *op, const double *u, const double *rhs, const 
 int launch_interface_lines(const hps_op *op, double *u, const double *f_end, hipStream_t st,
                            const double *jump, const double *fpart) {
     ProfScope ps_(&op->prof, KF_LINES, st);
-    int rc = launch_scatter_boundary(op, f_end, u, st);
-    if (rc) return rc;
     LineArgs la{};
     la.geo = geo_of(op);
     la.u = u;
@@ -1914,10 +1925,16 @@ int launch_interface_lines(const hps_op *op, double *u, const double *f_end, hip
     const int nsys = op->grid.n2 * op->q + op->grid.n1 * op->q;
     const int nmax = std::max(op->grid.n1, op->grid.n2);
     const size_t lds = ((size_t)nmax * LINES + 2 * (size_t)nmax) * sizeof(double);
-    if (lds <= sys_lds_limit())
+    if (lds <= sys_lds_limit()) {   // the boundary scatter in the same launch
+        la.f = f_end;
+        la.ends = op->line_ends;
+        la.bnd_glob = op->bnd_glob;
+        la.nb = op->n_bdry;
         hipLaunchKernelGGL(k_interface_lines_lds, dim3(nblk(nsys, LINES)), dim3(LINE_NT), lds, st, la, nmax);
-    else   // lines too long to stage in LDS: one thread per line, inputs read from memory
+    } else {   // lines too long to stage in LDS: one thread per line, inputs read from memory
+        TRY(launch_scatter_boundary(op, f_end, u, st));
         hipLaunchKernelGGL(k_interface_lines, dim3(nblk(nsys, 64)), dim3(64), 0, st, la);
+    }
     HPS_LAUNCHED();
     return HPS_OK;
 }
