@@ -55,6 +55,7 @@ extern "C" {
 #define HPS_EDEVICE        -3   /* HIP runtime or kernel launch error                */
 #define HPS_ESINGULAR      -4   /* zero pivot while building an inverse              */
 #define HPS_ENOTCONVERGED  -5   /* iterative refinement did not reach its tolerance  */
+#define HPS_EBUSY          -6   /* a bounded queue is full (srv_submit); retry later */
 
 /* hps_build flags */
 #define HPS_FP64     0   /* stored operators and their application in FP64.  With at

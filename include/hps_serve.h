@@ -44,6 +44,9 @@ typedef struct {
     int64_t cache_bytes;   /* device bytes the cached operators may hold; 0 = 3/4 of the
                               device memory free at srv_create                           */
     int32_t max_active;    /* jobs stepped together; 0 = 64, at most 4096                 */
+    int32_t max_queued;    /* jobs waiting for admission at most; srv_submit returns
+                              HPS_EBUSY (nothing queued) while that many wait; 0 = no
+                              bound                                                       */
 } srv_config;
 
 typedef struct {
@@ -91,7 +94,9 @@ HPS_API int srv_create(const srv_config *cfg, srv_server **out);
 
 /* Queue a job; *id receives its id (>= 0).  `stream` is the stream the caller
  * used to prepare the job's arrays: the job's first step waits for the work
- * enqueued on it so far.  Checks the arguments (HPS_EINVAL) before queuing. */
+ * enqueued on it so far.  Checks the arguments (HPS_EINVAL) before queuing;
+ * HPS_EBUSY when cfg.max_queued jobs are already waiting for admission (the job is
+ * not queued and the caller's arrays are not retained). */
 HPS_API int srv_submit(srv_server *srv, const srv_job *job, void *stream, int64_t *id);
 
 /* Current status of job id (HPS_EINVAL for an unknown id). */

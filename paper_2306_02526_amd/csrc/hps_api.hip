@@ -1000,6 +1000,10 @@ int64_t hps::workspace_layout(const hps_op *op, char *base, Workspace *w, int64_
     ws.ub_leaf = (double *)take(8 * nl * nb4);
     ws.w_leaf = (double *)take(8 * nl * q2);
     ws.flux = (double *)take(8 * nl * nb4);
+    if (op->flags & HPS_FP32_IR) {
+        ws.ir_r = (double *)take(8 * op->n_int);
+        ws.ir_r3 = (double *)take(8 * std::max<int64_t>(op->n_iface, 1));
+    }
     ws.lv.resize(op->L);
     for (int l = 0; l < op->L; ++l) {
         const Level &L = op->lv[l];

@@ -1,7 +1,8 @@
-// Batched entry points: many independent problems per call.  FP64 time steps run as
-// grouped launches (one launch per leaf phase and per tree level for all problems);
-// everything else runs each problem through the single-problem entry points on a pool of
-// library-owned HIP streams, so that small problems overlap.
+// Batched entry points: many independent problems per call.  Time steps of FP64 problems,
+// and refined steps of FP32_IR problems after their first step, run as grouped launches
+// (one launch per leaf phase and per tree level for all problems of a kind and stage
+// count); everything else runs each problem through the single-problem entry points on a
+// pool of library-owned HIP streams, so that small problems overlap.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -91,7 +92,8 @@ int tag_problem(int rc, int b) {
 // Runs fn(b, stream) for every problem on its assigned pool stream, in batch order per
 // stream, between a fork from and a join back to the caller's stream.
 template <class Fn>
-int run_batched(const std::vector<const hps_op *> &ops, hipStream_t caller, Fn fn) {
+int run_batched(const std::vector<const hps_op *> &ops, hipStream_t caller, Fn fn,
+                const std::vector<int> *ids = nullptr) {
     StreamPool *pool = nullptr;
     TRY(pool_for_current_device(&pool));
     std::lock_guard<std::mutex> g(pool->busy);
@@ -104,7 +106,7 @@ int run_batched(const std::vector<const hps_op *> &ops, hipStream_t caller, Fn f
     int rc = HPS_OK;
     for (int b = 0; b < (int)ops.size() && rc == HPS_OK; ++b) {
         rc = fn(b, pool->s[lane[b]]);
-        if (rc != HPS_OK) rc = tag_problem(rc, b);
+        if (rc != HPS_OK) rc = tag_problem(rc, ids ? (*ids)[b] : b);   // the caller's problem index
     }
     // join even after an error, so the caller's stream still orders after what ran
     for (int k = 0; k < kStreams; ++k) {
@@ -137,12 +139,20 @@ void unref(SharedEvent *ev) {
 struct GroupPlan {
     struct Launch {
         int kind;            // 0 leaf phase, 1 level up, 2 level down, 3 roots, 4 boundary, 5 lines,
-                             // 6 / 7 / 8 composite pairs up / down / top
-        size_t a, a2, base;  // offsets of the records (a2: downward root records) and bases
+                             // 6 / 7 / 8 composite pairs up / down / top, 9 copies and fills,
+                             // 10 refinement residuals
+        size_t a, a2, base;  // offsets of the records (a2: downward root records / jump
+                             // records) and bases
         int cnt, total;
         size_t lds;
         int down, up;
+        int fp32 = 0;        // FP32 operators (refined steps)
+        size_t base2 = 0;    // residuals: bases of the jump records
+        int total2 = 0;      // residuals: interface nodes; copies and fills: words (low 31 bits
+        int64_t words = 0;   // unused otherwise)
     };
+    bool ir = false;                     // refined FP32 steps: `seq` in order
+    std::vector<Launch> seq;
     std::vector<uintptr_t> key;
     int s = 0, n = 0;
     unsigned char *dmem = nullptr;       // the records (a block of the pool)
@@ -258,7 +268,6 @@ struct HostTables {
 bool groupable(ark_ctx *const *ctx, int nprob, const double *const *q_stages, const double *const *f_stages) {
     const char *env = getenv("HPS_GROUP");
     if (env && env[0] == '0') return false;
-    if (nprob < 2) return false;
     for (int b = 0; b < nprob; ++b) {
         const hps_op *op = ctx[b]->op;
         if ((op->flags & HPS_FP32_IR) || op->ncomp != 1) return false;
@@ -433,9 +442,274 @@ int build_plan(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, const
     return HPS_OK;
 }
 
+// Refined FP32 steps of several problems (FP32_IR operators whose contexts have made their
+// first, host-checked step): the launches of enqueue_step's fixed-pass refinement for all
+// problems at once -- each problem keeps its own number of passes (a pass's launches cover
+// the problems that still have that pass), so every problem runs exactly the kernels and
+// arithmetic of its single step.
+bool groupable_ir(ark_ctx *const *ctx, int nprob, const double *const *f_stages) {
+    const char *env = getenv("HPS_GROUP");
+    if (env && env[0] == '0') return false;
+    for (int b = 0; b < nprob; ++b) {
+        const hps_op *op = ctx[b]->op;
+        if (!(op->flags & HPS_FP32_IR) || op->ncomp != 1 || op->prof.on || op->L < 1) return false;
+        if (ctx[b]->s != ctx[0]->s || ctx[b]->ir_passes <= 0) return false;
+        if (f_stages && f_stages[b]) return false;
+        for (const Level &lv : op->lv)
+            if (lv.xu32.kch != 1 || lv.s32.kch != 1) return false;
+    }
+    return true;
+}
+
+int build_plan_ir(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, const double *const *q_stages,
+                  const double *const *q_space, hipStream_t st) {
+    P->n = n;
+    P->s = ctx[0]->s;
+    P->ir = true;
+    const int s = P->s;
+    std::map<const hps_op *, int> uses;
+    for (int b = 0; b < n; ++b) uses[ctx[b]->op]++;
+    std::vector<const Workspace *> ws(n, nullptr);
+    for (int b = 0; b < n; ++b)
+        if (uses[ctx[b]->op] > 1) {
+            TRY(ctx_workspace(ctx[b]));
+            ws[b] = ctx[b]->ws;
+        }
+    TRY(take_block(sizeof(double) * 8 * n, st, &P->qblk, &P->qbytes));
+    P->qt = reinterpret_cast<double *>(P->qblk);
+    TRY(launch_zero(P->qt, 8 * (int64_t)n, st));
+    HostTables T;
+    std::vector<int> all(n);
+    std::iota(all.begin(), all.end(), 0);
+    auto r_of = [&](int b) { return ws[b] ? ws[b]->ir_r : ctx[b]->op->ir_r; };
+    auto r3_of = [&](int b) -> double * {
+        if (!ctx[b]->op->n_iface) return nullptr;
+        return ws[b] ? ws[b]->ir_r3 : ctx[b]->op->ir_r3;
+    };
+    auto flux_of = [&](int b) { return ws[b] ? ws[b]->flux : ctx[b]->op->ir_flux; };
+    // one leaf phase (the same kinds for all listed problems)
+    auto leaf = [&](const std::vector<int> &probs, auto phase) -> int {
+        GroupPlan::Launch L{};
+        L.kind = 0;
+        L.fp32 = 1;
+        const size_t rs = leaf_args_size();
+        std::vector<unsigned char> recs(rs * probs.size());
+        std::vector<int> base(probs.size() + 1, 0);
+        for (size_t i = 0; i < probs.size(); ++i) {
+            const int b = probs[i];
+            LeafPhase ph;
+            phase(b, ph);
+            size_t lds = 0;
+            TRY(fill_leaf_args(ctx[b]->op, ph, recs.data() + rs * i, &lds, ws[b], true));
+            L.lds = std::max(L.lds, lds);
+            L.down = ph.down;
+            L.up = ph.up;
+            base[i + 1] = base[i] + ctx[b]->op->nleaves;
+        }
+        L.a = T.put(recs.data(), recs.size());
+        L.base = T.put(base.data(), sizeof(int) * base.size());
+        L.cnt = (int)probs.size();
+        L.total = base.back();
+        P->seq.push_back(L);
+        return HPS_OK;
+    };
+    // the FP32 level sweeps (upward levels aligned at the roots, the fused roots, downward)
+    const size_t ls = level_record_size();
+    auto sweep = [&](const std::vector<int> &probs, bool with_r3) -> int {
+        int Lmax = 0;
+        for (int b : probs) Lmax = std::max(Lmax, ctx[b]->op->L);
+        auto level = [&](int l, bool up) -> int {
+            GroupPlan::Launch L{};
+            L.kind = up ? 1 : 2;
+            L.fp32 = 1;
+            std::vector<unsigned char> recs;
+            std::vector<int> bs(1, 0);
+            for (int b : probs) {
+                const hps_op *op = ctx[b]->op;
+                if (l >= op->L || (l == 0 && root_fused(op, true))) continue;
+                recs.resize(recs.size() + ls);
+                int blocks = 0;
+                size_t lds = 0;
+                level_record(op, l, up, nullptr, recs.data() + recs.size() - ls, &blocks, &lds, ws[b], true,
+                             with_r3 ? r3_of(b) : nullptr);
+                L.lds = std::max(L.lds, lds);
+                bs.push_back(bs.back() + blocks);
+            }
+            L.cnt = (int)bs.size() - 1;
+            if (L.cnt == 0) return HPS_OK;
+            L.a = T.put(recs.data(), recs.size());
+            L.base = T.put(bs.data(), sizeof(int) * bs.size());
+            L.total = bs.back();
+            P->seq.push_back(L);
+            return HPS_OK;
+        };
+        for (int l = Lmax - 1; l >= 0; --l) TRY(level(l, true));
+        {
+            GroupPlan::Launch L{};
+            L.kind = 3;
+            L.fp32 = 1;
+            std::vector<unsigned char> ups, dns;
+            std::vector<int> bs(1, 0);
+            for (int b : probs) {
+                const hps_op *op = ctx[b]->op;
+                if (!root_fused(op, true)) continue;
+                ups.resize(ups.size() + ls);
+                dns.resize(dns.size() + ls);
+                int blocks = 0;
+                size_t lds = 0;
+                root_records(op, nullptr, ups.data() + ups.size() - ls, dns.data() + dns.size() - ls, &blocks, &lds,
+                             ws[b], true, with_r3 ? r3_of(b) : nullptr);
+                L.lds = std::max(L.lds, lds);
+                bs.push_back(bs.back() + blocks);
+            }
+            L.cnt = (int)bs.size() - 1;
+            if (L.cnt > 0) {
+                L.a = T.put(ups.data(), ups.size());
+                L.a2 = T.put(dns.data(), dns.size());
+                L.base = T.put(bs.data(), sizeof(int) * bs.size());
+                L.total = bs.back();
+                P->seq.push_back(L);
+            }
+        }
+        for (int l = 0; l < Lmax; ++l) TRY(level(l, false));
+        return HPS_OK;
+    };
+    auto residual = [&](const std::vector<int> &probs) {
+        GroupPlan::Launch L{};
+        L.kind = 10;
+        const size_t es = eval_record_size(), js = jump_record_size();
+        std::vector<unsigned char> ev(es * probs.size()), jp(js * probs.size());
+        std::vector<int> eb(probs.size() + 1, 0), jb(probs.size() + 1, 0);
+        for (size_t i = 0; i < probs.size(); ++i) {
+            const int b = probs[i];
+            int leaves = 0, iface = 0;
+            residual_records(ctx[b]->op, ctx[b]->stage_u, ctx[b]->rhs, r_of(b), r3_of(b), flux_of(b),
+                             ev.data() + es * i, jp.data() + js * i, &leaves, &iface);
+            if (!r3_of(b)) iface = 0;
+            eb[i + 1] = eb[i] + leaves;
+            jb[i + 1] = jb[i] + iface;
+        }
+        L.a = T.put(ev.data(), ev.size());
+        L.a2 = T.put(jp.data(), jp.size());
+        L.base = T.put(eb.data(), sizeof(int) * eb.size());
+        L.base2 = T.put(jb.data(), sizeof(int) * jb.size());
+        L.cnt = (int)probs.size();
+        L.total = eb.back();
+        L.total2 = jb.back();
+        P->seq.push_back(L);
+    };
+    // keep u^n for a redo, clear the correction norms
+    {
+        std::vector<MemOp> ops;
+        for (int b = 0; b < n; ++b) {
+            ops.push_back(MemOp{ctx[b]->u_save, u[b], ctx[b]->op->N});
+            ops.push_back(MemOp{ctx[b]->ir_stat, nullptr, (int64_t)s * IR_MAXIT * 2});
+        }
+        std::vector<int64_t> ob(ops.size() + 1, 0);
+        for (size_t i = 0; i < ops.size(); ++i) ob[i + 1] = ob[i] + ops[i].words;
+        GroupPlan::Launch L{};
+        L.kind = 9;
+        L.a = T.put(ops.data(), sizeof(MemOp) * ops.size());
+        L.base = T.put(ob.data(), sizeof(int64_t) * ob.size());
+        L.cnt = (int)ops.size();
+        L.words = ob.back();
+        P->seq.push_back(L);
+    }
+    for (int k = 0; k < s; ++k) {
+        if (k > 0) {
+            TRY(sweep(all, false));
+            TRY(leaf(all, [&](int b, LeafPhase &ph) {
+                ph.down = LD_WRITE_U;
+                ph.u_out = ctx[b]->stage_u;
+            }));
+            int kmax = 0;
+            for (int b = 0; b < n; ++b) kmax = std::max(kmax, ctx[b]->ir_passes);
+            for (int j = 0; j < kmax; ++j) {
+                std::vector<int> probs;
+                for (int b = 0; b < n; ++b)
+                    if (ctx[b]->ir_passes > j) probs.push_back(b);
+                residual(probs);
+                TRY(leaf(probs, [&](int b, LeafPhase &ph) {
+                    ph.up = LU_BODY;
+                    ph.body = r_of(b);
+                }));
+                TRY(sweep(probs, true));
+                TRY(leaf(probs, [&](int b, LeafPhase &ph) {
+                    ph.down = LD_IR_ADD;
+                    ph.u_out = ctx[b]->stage_u;
+                    ph.norms = ctx[b]->ir_stat + ((int64_t)k * IR_MAXIT + j) * 2;
+                }));
+            }
+        }
+        TRY(leaf(all, [&](int b, LeafPhase &ph) {
+            step_phase(ctx[b], k, u[b], q_stages ? q_stages[b] : nullptr, q_space ? q_space[b] : nullptr,
+                       P->qt + 8 * b, ph);
+            if (k > 0) {
+                ph.down = LD_EVAL;
+                ph.u_eval = ctx[b]->stage_u;
+            }
+            if (k + 1 < s) ph.rhs_copy = ctx[b]->rhs;
+        }));
+    }
+    // boundary values (zero) and interface line solves of the update
+    {
+        const size_t zs = scatter_record_size(), lr = line_record_size();
+        std::vector<unsigned char> zrec(zs * n), lrec(lr * n);
+        std::vector<int> zb(n + 1, 0), lb(n + 1, 0);
+        for (int b = 0; b < n; ++b) {
+            int cnt = 0, sys = 0;
+            scatter_record(ctx[b]->op, u[b], zrec.data() + zs * b, &cnt);
+            line_record(ctx[b]->op, u[b], lrec.data() + lr * b, &sys, ws[b]);
+            zb[b + 1] = zb[b] + cnt;
+            lb[b + 1] = lb[b] + sys;
+        }
+        P->zb = GroupPlan::Launch{4, T.put(zrec.data(), zrec.size()), 0, T.put(zb.data(), sizeof(int) * (n + 1)),
+                                  n, zb[n], 0, 0, 0};
+        P->lines = GroupPlan::Launch{5, T.put(lrec.data(), lrec.size()), 0, T.put(lb.data(), sizeof(int) * (n + 1)),
+                                     n, lb[n], 0, 0, 0};
+    }
+    P->host.swap(T.bytes);
+    TRY(take_block(std::max<size_t>(P->host.size(), 256), st, &P->dmem, &P->dbytes));
+    HPS_HIP(hipMemcpyAsync(P->dmem, P->host.data(), P->host.size(), hipMemcpyHostToDevice, st));
+    P->done = new SharedEvent();
+    P->done->refs = 1;
+    HPS_HIP(hipEventCreateWithFlags(&P->done->e, hipEventDisableTiming));
+    return HPS_OK;
+}
+
 int enqueue_plan(const GroupPlan *P, hipStream_t st) {
     unsigned char *d = P->dmem;
     auto basep = [&](const GroupPlan::Launch &L) { return reinterpret_cast<const int *>(d + L.base); };
+    if (P->ir) {
+        for (const GroupPlan::Launch &L : P->seq) {
+            switch (L.kind) {
+                case 0:
+                    TRY(launch_leaf_group(d + L.a, basep(L), L.cnt, L.total, L.lds, L.down, L.up, st, true));
+                    break;
+                case 1:
+                case 2:
+                    TRY(launch_level_group(d + L.a, basep(L), L.cnt, L.total, L.lds, L.kind == 1, st, true));
+                    break;
+                case 3:
+                    TRY(launch_root_group(d + L.a, d + L.a2, basep(L), L.cnt, L.total, L.lds, st, true));
+                    break;
+                case 9:
+                    TRY(launch_memop_group(reinterpret_cast<const MemOp *>(d + L.a),
+                                           reinterpret_cast<const int64_t *>(d + L.base), L.cnt, L.words, st));
+                    break;
+                case 10:
+                    TRY(launch_residual_group(d + L.a, basep(L), d + L.a2, reinterpret_cast<const int *>(d + L.base2),
+                                              L.cnt, L.total, L.total2, st));
+                    break;
+                default:
+                    hps_set_error("internal: launch kind %d in a refined plan", L.kind);
+                    return HPS_EINVAL;
+            }
+        }
+        TRY(launch_zero_boundary_group(d + P->zb.a, basep(P->zb), P->zb.cnt, P->zb.total, st));
+        TRY(launch_lines_group(d + P->lines.a, basep(P->lines), P->lines.cnt, P->lines.total, st));
+        return HPS_OK;
+    }
     auto run_sweep = [&]() -> int {
         for (const GroupPlan::Launch &L : P->sweep) {
             if (L.kind == 3) TRY(launch_root_group(d + L.a, d + L.a2, basep(L), L.cnt, L.total, L.lds, st));
@@ -455,14 +729,17 @@ int enqueue_plan(const GroupPlan *P, hipStream_t st) {
 }
 
 int grouped_step(ark_ctx *const *ctx, int n, double *const *u, const double *const *q_stages,
-                 const double *const *q_space, const double *const *q_time, hipStream_t st) {
+                 const double *const *q_space, const double *const *q_time, hipStream_t st, bool ir = false,
+                 const int *ids = nullptr) {
     std::vector<uintptr_t> key;
+    key.push_back(ir ? 1 : 0);
     for (int b = 0; b < n; ++b) {
         key.push_back((uintptr_t)ctx[b]);
         key.push_back((uintptr_t)ctx[b]->uid);
         key.push_back((uintptr_t)u[b]);
         key.push_back((uintptr_t)(q_stages ? q_stages[b] : nullptr));
         key.push_back((uintptr_t)(q_space ? q_space[b] : nullptr));
+        if (ir) key.push_back((uintptr_t)ctx[b]->ir_passes);
     }
     std::lock_guard<std::mutex> g(g_plans_mu);
     reap_retired();
@@ -478,7 +755,8 @@ int grouped_step(ark_ctx *const *ctx, int n, double *const *u, const double *con
         }
         P = new GroupPlan();
         P->key = key;
-        if (int rc = build_plan(P, ctx, n, u, q_stages, q_space, st)) {
+        if (int rc = ir ? build_plan_ir(P, ctx, n, u, q_stages, q_space, st)
+                        : build_plan(P, ctx, n, u, q_stages, q_space, st)) {
             retire_plan(P);
             return rc;
         }
@@ -519,7 +797,22 @@ int grouped_step(ark_ctx *const *ctx, int n, double *const *u, const double *con
         HPS_HIP(hipGraphLaunch(P->gexec, st));
     }
     HPS_HIP(hipEventRecord(P->done->e, st));
-    return HPS_OK;
+    if (!ir) return HPS_OK;
+    // every problem's correction norms, one wait for all; a problem whose refinement missed
+    // the tolerance is redone alone (from its saved u^n, host-checked)
+    const size_t per = (size_t)P->s * IR_MAXIT * 2;
+    std::vector<unsigned long long> stats(per * n);
+    for (int b = 0; b < n; ++b)
+        HPS_HIP(hipMemcpyAsync(stats.data() + per * b, ctx[b]->ir_stat, per * sizeof(unsigned long long),
+                               hipMemcpyDeviceToHost, st));
+    HPS_HIP(hipStreamSynchronize(st));
+    int rc = HPS_OK;
+    for (int b = 0; b < n; ++b) {
+        const int r = ir_step_finish(ctx[b], u[b], q_stages ? q_stages[b] : nullptr, q_space ? q_space[b] : nullptr,
+                                     q_time ? q_time[b] : nullptr, nullptr, st, stats.data() + per * b);
+        if (r && !rc) rc = tag_problem(r, ids ? ids[b] : b);   // the caller's problem index
+    }
+    return rc;
 }
 
 }  // namespace
@@ -572,11 +865,48 @@ extern "C" int ark_step_batched(ark_ctx *const *ctx, int nprob, const double *t,
         if (q_space && q_space[b]) CHECK_ARG(q_time && q_time[b], "problem %d: q_space needs q_time", b);
         CHECK_ARG(!(q_stages && q_stages[b] && q_space && q_space[b]), "problem %d: q_stages or q_space, not both", b);
     }
-    if (groupable(ctx, nprob, q_stages, f_stages)) return grouped_step(ctx, nprob, u, q_stages, q_space, q_time,
-                                                                       (hipStream_t)stream);
-    return run_batched(v, (hipStream_t)stream, [&](int b, hipStream_t st) {
-        return ark_step(ctx[b], t[b], u[b], q_stages ? q_stages[b] : nullptr,
-                        q_space ? q_space[b] : nullptr, q_time ? q_time[b] : nullptr,
-                        f_stages ? f_stages[b] : nullptr, st);
-    });
+    // problems that can share launches, by kind (FP64 / refined FP32) and stage count; each
+    // such set of two or more runs as one grouped step, the others one by one on the pool
+    std::map<std::pair<int, int>, std::vector<int>> sets;
+    std::vector<int> rest;
+    for (int b = 0; b < nprob; ++b) {
+        ark_ctx *const one[1] = {ctx[b]};
+        const double *const fb[1] = {f_stages ? f_stages[b] : nullptr};
+        if (groupable(one, 1, nullptr, fb)) sets[{0, ctx[b]->s}].push_back(b);
+        else if (groupable_ir(one, 1, fb)) sets[{1, ctx[b]->s}].push_back(b);
+        else rest.push_back(b);
+    }
+    const hipStream_t st = (hipStream_t)stream;
+    for (auto &kv : sets) {
+        const std::vector<int> &m = kv.second;
+        if (m.size() < 2) {
+            rest.insert(rest.end(), m.begin(), m.end());
+            continue;
+        }
+        std::vector<ark_ctx *> c(m.size());
+        std::vector<double *> uu(m.size());
+        std::vector<const double *> qs(m.size()), qp(m.size()), qt(m.size());
+        for (size_t i = 0; i < m.size(); ++i) {
+            c[i] = ctx[m[i]];
+            uu[i] = u[m[i]];
+            qs[i] = q_stages ? q_stages[m[i]] : nullptr;
+            qp[i] = q_space ? q_space[m[i]] : nullptr;
+            qt[i] = q_time ? q_time[m[i]] : nullptr;
+        }
+        const int rc = grouped_step(c.data(), (int)m.size(), uu.data(), qs.data(), qp.data(), qt.data(), st,
+                                    kv.first.first == 1, m.data());
+        if (rc) return rc;
+    }
+    if (rest.empty()) return HPS_OK;
+    std::sort(rest.begin(), rest.end());
+    std::vector<const hps_op *> rv(rest.size());
+    for (size_t i = 0; i < rest.size(); ++i) rv[i] = v[rest[i]];
+    return run_batched(
+        rv, st,
+        [&](int i, hipStream_t s2) {
+            const int b = rest[i];
+            return ark_step(ctx[b], t[b], u[b], q_stages ? q_stages[b] : nullptr, q_space ? q_space[b] : nullptr,
+                            q_time ? q_time[b] : nullptr, f_stages ? f_stages[b] : nullptr, s2);
+        },
+        &rest);
 }

@@ -539,12 +539,23 @@ static int run_step_ir(ark_ctx *c, double *u, const double *q_stages, const doub
     std::vector<unsigned long long> nb((size_t)s * IR_MAXIT * 2);
     HPS_HIP(hipMemcpyAsync(nb.data(), c->ir_stat, nb.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
     HPS_HIP(hipStreamSynchronize(st));
+    return ir_step_finish(c, u, q_stages, q_space, q_time, f, st, nb.data());
+}
+
+// After a step with c->ir_passes fixed corrections per stage (stats: the step's correction
+// norms, copied from c->ir_stat once the step has completed): record the step, and if a
+// stage missed the tolerance redo the step from the saved u^n on the host-checked loop
+// (HPS_IR_STRICT: HPS_ENOTCONVERGED); later steps then run one correction more.
+int hps::ir_step_finish(ark_ctx *c, double *u, const double *q_stages, const double *q_space, const double *q_time,
+                        const double *f, hipStream_t st, const unsigned long long *stats) {
+    hps_op *op = c->op;
+    const int s = c->s, K = c->ir_passes;
     hps_info rec{};
     rec.ir_iterations = K;
     bool all = true;
     for (int k = 1; k < s; ++k) {
         double rel = 0.0;
-        all = ir_converged(&nb[((size_t)k * IR_MAXIT + K - 1) * 2], &rel) && all;
+        all = ir_converged(&stats[((size_t)k * IR_MAXIT + K - 1) * 2], &rel) && all;
         rec.last_correction = std::max(rec.last_correction, rel);
     }
     c->last = rec;
@@ -556,8 +567,13 @@ static int run_step_ir(ark_ctx *c, double *u, const double *q_stages, const doub
     }
     // redo the step from u^n with host-checked refinement
     TRY(launch_copy(u, c->u_save, op->N, st));
-    TRY(eager());
-    if (c->ir_passes >= 0) c->ir_passes = std::min(IR_MAXIT, std::max(c->ir_passes, K + 1));
+    hps_info redo{};
+    IrStep irs;
+    irs.rec = &redo;
+    TRY(enqueue_step(c, u, q_stages, q_space, q_time, f, st, irs));
+    c->last = redo;
+    if (redo.fp64_fallbacks > 0) c->ir_passes = -1;
+    else c->ir_passes = std::min(IR_MAXIT, std::max(K + 1, redo.ir_iterations));
     return HPS_OK;
 }
 

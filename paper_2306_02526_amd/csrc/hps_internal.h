@@ -182,6 +182,7 @@ struct Workspace {
         int *cnt_up = nullptr, *cnt_dn = nullptr;
     };
     double *h_leaf = nullptr, *ub_leaf = nullptr, *w_leaf = nullptr, *flux = nullptr;
+    double *ir_r = nullptr, *ir_r3 = nullptr;   // FP32_IR operators: the refinement residual
     std::vector<Lv> lv;
     std::vector<void *> allocs;
 };
@@ -325,18 +326,38 @@ int launch_flux_jump(const hps_op *op, double scale, double *r3, hipStream_t st)
 int ark_slope_workspace(ark_ctx *c);
 // device bytes of a stage-formulation context of s stages on op, with its own solve buffers
 int64_t ark_ctx_footprint(const hps_op *op, int s);
+// the host's part of a refined step that ran a fixed number of corrections per stage
+int ir_step_finish(ark_ctx *c, double *u, const double *q_stages, const double *q_space, const double *q_time,
+                   const double *f, hipStream_t st, const unsigned long long *stats);
 // several operators per launch (FP64 stage formulation): argument records and launches
 size_t leaf_args_size();
-int fill_leaf_args(const hps_op *op, const LeafPhase &ph, void *dst, size_t *lds, const Workspace *ws);
+int fill_leaf_args(const hps_op *op, const LeafPhase &ph, void *dst, size_t *lds, const Workspace *ws,
+                   bool fp32 = false);
 int ctx_workspace(ark_ctx *c);
 int launch_leaf_group(const void *args, const int *base, int nprob, int total, size_t lds, int down, int up,
-                      hipStream_t st);
+                      hipStream_t st, bool fp32 = false);
 size_t level_record_size();
 void level_record(const hps_op *op, int l, bool up, const double *dir, void *dst, int *blocks, size_t *lds,
-                  const Workspace *ws);
+                  const Workspace *ws, bool fp32 = false, const double *r3 = nullptr);
 bool root_fused64(const hps_op *op);
+bool root_fused(const hps_op *op, bool fp32);
 void root_records(const hps_op *op, const double *dir, void *up_dst, void *dn_dst, int *blocks, size_t *lds,
-                  const Workspace *ws);
+                  const Workspace *ws, bool fp32 = false, const double *r3 = nullptr);
+// refinement residual of several operators: per-problem leaf evaluation records (one
+// workgroup per leaf) and interface-jump records (one thread per interface node)
+size_t eval_record_size();
+size_t jump_record_size();
+void residual_records(const hps_op *op, const double *u, const double *rhs, double *r_int, double *r3, double *flux,
+                      void *eval_dst, void *jump_dst, int *leaves, int *iface);
+int launch_residual_group(const void *evals, const int *ebase, const void *jumps, const int *jbase, int n,
+                          int total_leaves, int total_iface, hipStream_t st);
+// copies (src != null) and zero fills of several buffers in one launch
+struct MemOp {
+    void *dst;
+    const void *src;
+    int64_t words;   // 8-byte words
+};
+int launch_memop_group(const MemOp *ops, const int64_t *base, int n, int64_t total, hipStream_t st);
 // composite level pairs in grouped launches: mode 0 upward, 1 downward, 2 the top pair
 size_t pair_record_size();
 int pair_lowest(const hps_op *op);
@@ -347,9 +368,10 @@ size_t line_record_size();
 void line_record(const hps_op *op, double *u, void *dst, int *systems, const Workspace *ws);
 size_t scatter_record_size();
 void scatter_record(const hps_op *op, double *u, void *dst, int *count);
-int launch_level_group(const void *args, const int *base, int n, int total, size_t lds, bool up, hipStream_t st);
+int launch_level_group(const void *args, const int *base, int n, int total, size_t lds, bool up, hipStream_t st,
+                       bool fp32 = false);
 int launch_root_group(const void *ups, const void *dns, const int *base, int n, int total, size_t lds,
-                      hipStream_t st);
+                      hipStream_t st, bool fp32 = false);
 int launch_lines_group(const void *args, const int *base, int n, int total, hipStream_t st);
 int launch_zero_boundary_group(const void *args, const int *base, int n, int total, hipStream_t st);
 void step_phase(const ark_ctx *c, int k, double *u, const double *q_stages, const double *q_space,

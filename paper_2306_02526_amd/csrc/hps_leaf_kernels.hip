@@ -774,27 +774,35 @@ int launch_leaf_multi(const hps_op *op, int nc, bool up, const double *const *bo
 
 size_t leaf_args_size() { return sizeof(LeafArgs); }
 
-int fill_leaf_args(const hps_op *op, const LeafPhase &ph, void *dst, size_t *lds, const Workspace *ws) {
+int fill_leaf_args(const hps_op *op, const LeafPhase &ph, void *dst, size_t *lds, const Workspace *ws, bool fp32) {
     LeafArgs &a = *reinterpret_cast<LeafArgs *>(dst);
-    make_leaf_args(op, false, ph, a, *lds);
+    make_leaf_args(op, fp32, ph, a, *lds);
     use_leaf_workspace(a, ws);
     return HPS_OK;
 }
 
 int launch_leaf_group(const void *args, const int *base, int nprob, int total, size_t lds, int down, int up,
-                      hipStream_t st) {
+                      hipStream_t st, bool fp32) {
     if (total <= 0) return HPS_OK;
     const LeafArgs *a = reinterpret_cast<const LeafArgs *>(args);
     auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(total), dim3(NT), lds, st, a, base, nprob); };
-#define HPS_LEAF_GROUP_CASE(DNV, UPV)                                               \
+#define HPS_LEAF_GROUP_CASE(T, DNV, UPV)                                            \
     if (down == DNV && up == UPV) {                                                 \
-        go(k_leaf_group<double, DNV, UPV>);                                         \
+        go(k_leaf_group<T, DNV, UPV>);                                              \
         HPS_LAUNCHED();                                                             \
         return HPS_OK;                                                              \
     }
-    HPS_LEAF_GROUP_CASE(DOWN_EVAL, UP_STAGE)
-    HPS_LEAF_GROUP_CASE(DOWN_STAGE, UP_STAGE)
-    HPS_LEAF_GROUP_CASE(DOWN_STAGE, UP_UPDATE)
+    if (!fp32) {
+        HPS_LEAF_GROUP_CASE(double, DOWN_EVAL, UP_STAGE)
+        HPS_LEAF_GROUP_CASE(double, DOWN_STAGE, UP_STAGE)
+        HPS_LEAF_GROUP_CASE(double, DOWN_STAGE, UP_UPDATE)
+    } else {   // the phases of a refined FP32 step
+        HPS_LEAF_GROUP_CASE(float, DOWN_EVAL, UP_STAGE)
+        HPS_LEAF_GROUP_CASE(float, DOWN_EVAL, UP_UPDATE)
+        HPS_LEAF_GROUP_CASE(float, DOWN_WRITE_U, UP_NONE)
+        HPS_LEAF_GROUP_CASE(float, DOWN_NONE, UP_BODY)
+        HPS_LEAF_GROUP_CASE(float, DOWN_IR_ADD, UP_NONE)
+    }
 #undef HPS_LEAF_GROUP_CASE
     hps_set_error("internal: unsupported grouped leaf phase (%d, %d)", down, up);
     return HPS_EINVAL;

@@ -390,6 +390,7 @@ extern "C" int srv_create(const srv_config *cfg, srv_server **out) {
     if (cfg) c = *cfg;
     CHECK_ARG(c.cache_bytes >= 0, "cache_bytes must be >= 0");
     CHECK_ARG(c.max_active >= 0 && c.max_active <= 4096, "max_active must be in [0, 4096]");
+    CHECK_ARG(c.max_queued >= 0, "max_queued must be >= 0");
     if (c.max_active == 0) c.max_active = 64;
     int dev = 0;
     HPS_HIP(hipGetDevice(&dev));
@@ -460,6 +461,12 @@ extern "C" int srv_submit(srv_server *srv, const srv_job *job, void *stream, int
         delete j;
         hps_set_error("server is shutting down");
         return HPS_EINVAL;
+    }
+    if (srv->cfg.max_queued > 0 && (int64_t)srv->queue.size() >= srv->cfg.max_queued) {
+        (void)hipEventDestroy(j->ready);
+        delete j;
+        hps_set_error("%d jobs are already waiting for admission", srv->cfg.max_queued);
+        return HPS_EBUSY;
     }
     j->id = srv->next_id++;
     j->st.state = SRV_QUEUED;

@@ -379,9 +379,14 @@ __device__ __forceinline__ void pair_body(const PairArgs &a, int blk, unsigned c
     Carve cv{smem};
     T *xs = cv.take<T>(SG);
     T *part = cv.take<T>((size_t)a.pn.G * a.pn.rp * VW);
+    // without Dirichlet data the top pair's first n12t input columns are zero: the column
+    // steps s < n12t / G hold only those columns and are not streamed (their products are
+    // zeros, so the sums are the same)
+    const int s0 = (MODE == PAIR_TOP && !a.dir) ? a.n12t / a.pn.G : 0;
     PanelStream<T, PF, UNR> ps;
-    ps.start(reinterpret_cast<const T *>(a.pn.data) + (int64_t)node * a.pn.node_elems + (int64_t)tile * a.pn.tile_elems,
-             a.pn.rp, a.pn.G, a.pn.S);
+    ps.start(reinterpret_cast<const T *>(a.pn.data) + (int64_t)node * a.pn.node_elems + (int64_t)tile * a.pn.tile_elems +
+                 (int64_t)s0 * a.pn.rp * a.pn.G * VW,
+             a.pn.rp, a.pn.G, a.pn.S - s0);
     const int rows = a.pn.rp * VW;   // at most NT: one row per thread
     const int myrow = tile * rows + threadIdx.x;
     const int64_t gbase = (int64_t)node * 4 * a.nbcc;
@@ -428,7 +433,7 @@ __device__ __forceinline__ void pair_body(const PairArgs &a, int blk, unsigned c
         }
     }
     __syncthreads();
-    ps.finish(xs, part);
+    ps.finish(xs + s0 * a.pn.G, part);
     __syncthreads();
     const int G = a.pn.G;
     const int nsl = min(G, NT / rows);
@@ -483,9 +488,14 @@ __device__ __forceinline__ void pair_sys_body(const PairArgsN<NC> &A, int blk, u
     double *part = cv.take<double>((size_t)NC * pst);
     double *redn = cv.take<double>((size_t)NC * NT);
     double *red2n = cv.take<double>((size_t)NC * 64);
+    bool nodir = MODE == PAIR_TOP;   // as in pair_body: zero Dirichlet data for every component
+#pragma unroll
+    for (int c = 0; c < NC; ++c) nodir = nodir && !A.c[c].dir;
+    const int s0 = nodir ? a.n12t / a.pn.G : 0;
     PanelStream<double, PF, UNR> ps;
-    ps.start(reinterpret_cast<const double *>(a.pn.data) + (int64_t)node * a.pn.node_elems + (int64_t)tile * a.pn.tile_elems,
-             a.pn.rp, a.pn.G, a.pn.S);
+    ps.start(reinterpret_cast<const double *>(a.pn.data) + (int64_t)node * a.pn.node_elems +
+                 (int64_t)tile * a.pn.tile_elems + (int64_t)s0 * a.pn.rp * a.pn.G * VW,
+             a.pn.rp, a.pn.G, a.pn.S - s0);
     const int rows = a.pn.rp * VW;
     const int myrow = tile * rows + threadIdx.x;
     const int64_t gbase = MODE == PAIR_TOP ? 0 : (int64_t)node * 4 * a.nbcc;
@@ -558,7 +568,7 @@ __device__ __forceinline__ void pair_sys_body(const PairArgsN<NC> &A, int blk, u
         }
     }
     __syncthreads();
-    ps.template finish_n<NC>(xs, SG, part, pst);
+    ps.template finish_n<NC>(xs + s0 * a.pn.G, SG, part, pst);
     __syncthreads();
     const int G = a.pn.G;
     const int nsl = min(G, NT / rows);
@@ -838,11 +848,8 @@ struct EvalArgs {
     double *r_int, *flux;
 };
 
-// one workgroup per leaf in canonical order (blockIdx.x = j*n1 + i)
-__global__ __launch_bounds__(NT) void k_eval(EvalArgs a) {
-    __shared__ double tile[PMAX * PMAX];
-    __shared__ double D[PMAX * PMAX], D2[PMAX * PMAX];
-    const int cl = blockIdx.x;
+// leaf cl in canonical order (cl = j*n1 + i), one workgroup
+__device__ __forceinline__ void eval_body(const EvalArgs &a, int cl, double *tile, double *D, double *D2) {
     const int li = cl % a.geo.n1, lj = cl / a.geo.n1;
     const int q = a.geo.q, p = a.geo.p, q2 = q * q;
     load_dmat(a.D, D, p * p);
@@ -876,11 +883,15 @@ __global__ __launch_bounds__(NT) void k_eval(EvalArgs a) {
     }
 }
 
+__global__ __launch_bounds__(NT) void k_eval(EvalArgs a) {
+    __shared__ double tile[PMAX * PMAX];
+    __shared__ double D[PMAX * PMAX], D2[PMAX * PMAX];
+    eval_body(a, blockIdx.x, tile, D, D2);
+}
+
 // interface residual r3 = jump - (flux_alpha - flux_beta), interface-indexed
-__global__ void k_jump(LeafGeo g, const double *flux, const double *jump, double scale, double *r3,
-                       int64_t n_iface) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_iface) return;
+__device__ __forceinline__ void jump_body(const LeafGeo &g, const double *flux, const double *jump, double scale,
+                                          double *r3, int64_t t) {
     const int q = g.q;
     const int64_t nv = (int64_t)(g.n1 - 1) * g.n2 * q;
     int ia, ja, ib, jb, ea, eb, m;
@@ -903,6 +914,65 @@ __global__ void k_jump(LeafGeo g, const double *flux, const double *jump, double
     const double fa = flux[((int64_t)ja * g.n1 + ia) * 4 * q + ea * q + m];
     const double fb = flux[((int64_t)jb * g.n1 + ib) * 4 * q + eb * q + m];
     r3[t] = scale * ((jump ? jump[t] : 0.0) - (fa - fb));
+}
+
+__global__ void k_jump(LeafGeo g, const double *flux, const double *jump, double scale, double *r3,
+                       int64_t n_iface) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n_iface) jump_body(g, flux, jump, scale, r3, t);
+}
+
+struct JumpArgs {
+    LeafGeo g;
+    const double *flux, *jump;
+    double scale;
+    double *r3;
+    int64_t n_iface;
+};
+
+// first entry e with base[e] <= w < base[e + 1] (bisection)
+__device__ __forceinline__ int group_entry(const int *base, int n, int w) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// the refinement residuals of several operators, in two launches (the jumps read the edge
+// fluxes the evaluations write): leaf evaluations (workgroup w -> leaf w - ebase[e] of
+// problem e), then the interface jumps (thread -> interface node of problem e by jbase)
+__global__ __launch_bounds__(NT) void k_eval_group(const EvalArgs *ev, const int *ebase, int n) {
+    __shared__ double tile[PMAX * PMAX];
+    __shared__ double D[PMAX * PMAX], D2[PMAX * PMAX];
+    const int w = blockIdx.x;
+    const int e = group_entry(ebase, n, w);
+    eval_body(ev[e], w - ebase[e], tile, D, D2);
+}
+
+__global__ void k_jump_group(const JumpArgs *jp, const int *jbase, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= jbase[n]) return;
+    const int e = group_entry(jbase, n, t);
+    const JumpArgs &j = jp[e];
+    jump_body(j.g, j.flux, j.jump, j.scale, j.r3, t - jbase[e]);
+}
+
+__global__ void k_memop_group(const MemOp *ops, const int64_t *base, int n) {
+    const int64_t total = base[n];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (base[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const int64_t i = t - base[lo];
+        double *d = reinterpret_cast<double *>(ops[lo].dst);
+        d[i] = ops[lo].src ? reinterpret_cast<const double *>(ops[lo].src)[i] : 0.0;
+    }
 }
 
 // =======================================================================================
@@ -1788,16 +1858,18 @@ static void use_workspace(const hps_op *op, int l, bool up, const Workspace *ws,
 }
 
 void level_record(const hps_op *op, int l, bool up, const double *dir, void *dst, int *blocks, size_t *lds,
-                  const Workspace *ws) {
-    LevelArgs a = level_args(op, l, false, up);
+                  const Workspace *ws, bool fp32, const double *r3) {
+    LevelArgs a = level_args(op, l, fp32, up);
     use_workspace(op, l, up, ws, a);
     a.dir = dir;
+    a.r3 = r3;
     *reinterpret_cast<LevelArgs *>(dst) = a;
     *blocks = op->lv[l].nodes * a.pn.ntile * a.pn.kch;
-    *lds = level_lds(up ? op->lv[l].xu64 : op->lv[l].s64);
+    *lds = level_lds(up ? (fp32 ? op->lv[l].xu32 : op->lv[l].xu64) : (fp32 ? op->lv[l].s32 : op->lv[l].s64));
 }
 
 bool root_fused64(const hps_op *op) { return root_fusable(op, false); }
+bool root_fused(const hps_op *op, bool fp32) { return root_fusable(op, fp32); }
 
 size_t pair_record_size() { return sizeof(PairArgs); }
 
@@ -1822,15 +1894,61 @@ int launch_pair_group(const void *args, const int *base, int n, int total, size_
 }
 
 void root_records(const hps_op *op, const double *dir, void *up_dst, void *dn_dst, int *blocks, size_t *lds,
-                  const Workspace *ws) {
-    LevelArgs up = level_args(op, 0, false, true), dn = level_args(op, 0, false, false);
+                  const Workspace *ws, bool fp32, const double *r3) {
+    LevelArgs up = level_args(op, 0, fp32, true), dn = level_args(op, 0, fp32, false);
     use_workspace(op, 0, true, ws, up);
     use_workspace(op, 0, false, ws, dn);
+    up.r3 = r3;
     dn.dir = dir;
     *reinterpret_cast<LevelArgs *>(up_dst) = up;
     *reinterpret_cast<LevelArgs *>(dn_dst) = dn;
-    *blocks = op->lv[0].xu64.ntile;
-    *lds = level_lds(op->lv[0].xu64) + level_lds(op->lv[0].s64) + 32;
+    const Panel &x = fp32 ? op->lv[0].xu32 : op->lv[0].xu64, &sp = fp32 ? op->lv[0].s32 : op->lv[0].s64;
+    *blocks = x.ntile;
+    *lds = level_lds(x) + level_lds(sp) + 32;
+}
+
+size_t eval_record_size() { return sizeof(EvalArgs); }
+size_t jump_record_size() { return sizeof(JumpArgs); }
+
+void residual_records(const hps_op *op, const double *u, const double *rhs, double *r_int, double *r3, double *flux,
+                      void *eval_dst, void *jump_dst, int *leaves, int *iface) {
+    EvalArgs a{};
+    a.geo = geo_of(op);
+    a.u = u;
+    a.D = op->D;
+    a.D2 = op->D2;
+    a.coef = op->coef;
+    a.rhs = rhs;
+    a.gamma_dt = op->gamma_dt;
+    a.r_int = r_int;
+    a.flux = flux;
+    *reinterpret_cast<EvalArgs *>(eval_dst) = a;
+    *reinterpret_cast<JumpArgs *>(jump_dst) = JumpArgs{geo_of(op), flux, nullptr, 1.0, r3, op->n_iface};
+    *leaves = op->nleaves;
+    *iface = (int)op->n_iface;
+}
+
+int launch_residual_group(const void *evals, const int *ebase, const void *jumps, const int *jbase, int n,
+                          int total_leaves, int total_iface, hipStream_t st) {
+    if (total_leaves > 0) {
+        hipLaunchKernelGGL(k_eval_group, dim3(total_leaves), dim3(NT), 0, st, reinterpret_cast<const EvalArgs *>(evals),
+                           ebase, n);
+        HPS_LAUNCHED();
+    }
+    if (total_iface > 0) {
+        hipLaunchKernelGGL(k_jump_group, dim3(nblk(total_iface)), dim3(NT), 0, st,
+                           reinterpret_cast<const JumpArgs *>(jumps), jbase, n);
+        HPS_LAUNCHED();
+    }
+    return HPS_OK;
+}
+
+int launch_memop_group(const MemOp *ops, const int64_t *base, int n, int64_t total, hipStream_t st) {
+    if (total <= 0) return HPS_OK;
+    const unsigned gx = (unsigned)std::min<int64_t>(nblk(total), 4096);
+    hipLaunchKernelGGL(k_memop_group, dim3(gx), dim3(NT), 0, st, ops, base, n);
+    HPS_LAUNCHED();
+    return HPS_OK;
 }
 
 size_t line_record_size() { return sizeof(LineArgs); }
@@ -1854,20 +1972,27 @@ void scatter_record(const hps_op *op, double *u, void *dst, int *count) {
     *count = (int)op->n_bdry;
 }
 
-int launch_level_group(const void *args, const int *base, int n, int total, size_t lds, bool up, hipStream_t st) {
+int launch_level_group(const void *args, const int *base, int n, int total, size_t lds, bool up, hipStream_t st,
+                       bool fp32) {
     if (total <= 0) return HPS_OK;
     const LevelArgs *a = reinterpret_cast<const LevelArgs *>(args);
-    if (up) hipLaunchKernelGGL((k_level_group<double, true>), dim3(total), dim3(NT), lds, st, a, base, n);
-    else hipLaunchKernelGGL((k_level_group<double, false>), dim3(total), dim3(NT), lds, st, a, base, n);
+    if (fp32) {
+        if (up) hipLaunchKernelGGL((k_level_group<float, true>), dim3(total), dim3(NT), lds, st, a, base, n);
+        else hipLaunchKernelGGL((k_level_group<float, false>), dim3(total), dim3(NT), lds, st, a, base, n);
+    } else {
+        if (up) hipLaunchKernelGGL((k_level_group<double, true>), dim3(total), dim3(NT), lds, st, a, base, n);
+        else hipLaunchKernelGGL((k_level_group<double, false>), dim3(total), dim3(NT), lds, st, a, base, n);
+    }
     HPS_LAUNCHED();
     return HPS_OK;
 }
 
 int launch_root_group(const void *ups, const void *dns, const int *base, int n, int total, size_t lds,
-                      hipStream_t st) {
+                      hipStream_t st, bool fp32) {
     if (total <= 0) return HPS_OK;
-    hipLaunchKernelGGL(k_root_group<double>, dim3(total), dim3(NT), lds, st, reinterpret_cast<const LevelArgs *>(ups),
-                       reinterpret_cast<const LevelArgs *>(dns), base, n);
+    const LevelArgs *u = reinterpret_cast<const LevelArgs *>(ups), *d = reinterpret_cast<const LevelArgs *>(dns);
+    if (fp32) hipLaunchKernelGGL(k_root_group<float>, dim3(total), dim3(NT), lds, st, u, d, base, n);
+    else hipLaunchKernelGGL(k_root_group<double>, dim3(total), dim3(NT), lds, st, u, d, base, n);
     HPS_LAUNCHED();
     return HPS_OK;
 }

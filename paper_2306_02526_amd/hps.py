@@ -21,7 +21,7 @@ HPS_IR_STRICT = 8
 HPS_TEST_FP32_SKEW = 16
 HPS_AUTOTUNE = 32
 ERRORS = {-1: "HPS_EINVAL", -2: "HPS_ENOMEM", -3: "HPS_EDEVICE", -4: "HPS_ESINGULAR",
-          -5: "HPS_ENOTCONVERGED"}
+          -5: "HPS_ENOTCONVERGED", -6: "HPS_EBUSY"}
 
 # every entry point declared in include/hps.h, include/hps_batch.h and include/hps_serve.h
 EXPORTED = ["hps_last_error", "hps_num_nodes", "hps_nodes", "hps_build", "hps_op_bytes",
@@ -66,7 +66,7 @@ class ArkG(ctypes.Structure):
 
 
 class SrvConfig(ctypes.Structure):
-    _fields_ = [("cache_bytes", ctypes.c_int64), ("max_active", ctypes.c_int32)]
+    _fields_ = [("cache_bytes", ctypes.c_int64), ("max_active", ctypes.c_int32), ("max_queued", ctypes.c_int32)]
 
 
 class SrvJob(ctypes.Structure):
@@ -495,9 +495,9 @@ class Server:
     """Owns an srv_server handle (srv_destroy drains it).  Keeps every array of a job
     alive until the job is released."""
 
-    def __init__(self, cache_bytes=0, max_active=0):
+    def __init__(self, cache_bytes=0, max_active=0, max_queued=0):
         h = ctypes.c_void_p()
-        cfg = SrvConfig(int(cache_bytes), int(max_active))
+        cfg = SrvConfig(int(cache_bytes), int(max_active), int(max_queued))
         _check(lib().srv_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h
         self._keep = {}

@@ -143,13 +143,19 @@ def test_batched_rejects_missing_entries(torch):
     assert hps.hps_solve_batched([], []) == []
 
 
-@pytest.mark.parametrize("flags", [hps.HPS_FP64, hps.HPS_WIDE_TILES], ids=["thin", "wide"])
+@pytest.mark.parametrize("flags", [hps.HPS_FP64, hps.HPS_WIDE_TILES, hps.HPS_FP32_IR,
+                                   hps.HPS_FP32_IR | hps.HPS_WIDE_TILES],
+                         ids=["thin", "wide", "fp32ir_thin", "fp32ir_wide"])
 def test_grouped_batched_steps_match_single_steps_and_oracle(torch, monkeypatch, flags):
-    """FP64 problems with at least two leaves run as grouped launches (one launch per leaf
+    """Problems with at least two leaves run as grouped launches (one launch per leaf
     phase and per tree level for all problems; two of them share one operator and use
     workspaces of their own): the same bits as single steps, and the oracle's result; the
     plan and its graph are reused on later steps.  Both level tilings (thin tiles for one
-    problem, wide tiles for many)."""
+    problem, wide tiles for many), FP64 and FP32+IR (after each context's first,
+    host-checked step, the refined steps of all problems are grouped too: each problem
+    keeps its own number of corrections per stage)."""
+    ir = bool(flags & hps.HPS_FP32_IR)
+    tol = TOL32IR if ir else TOL64
     mix = workloads.batched_mix(n_problems=7, stream=6, sides=(2, 4, 8), orders=(6, 8, 10))
     tab = product_tableau()
     otab = tableau_float(ark436l2sa())
@@ -186,7 +192,7 @@ def test_grouped_batched_steps_match_single_steps_and_oracle(torch, monkeypatch,
         qsp = [torch.tensor(m["problem"].q_space(x[: og.n_int], y[: og.n_int]), device="cuda")
                if m["kind"] == "heat" else None for m, x, y, og, dt in probs]
         out = []
-        for n in range(3):
+        for n in range(4 if ir else 3):
             ts = [n * dt for *_, dt in probs]
             qt = [[workloads.HeatManufactured.q_time(t + c * dt) for c in tab["c"]] if m["kind"] == "heat" else None
                   for (m, _, _, _, dt), t in zip(probs, ts)]
@@ -201,9 +207,11 @@ def test_grouped_batched_steps_match_single_steps_and_oracle(torch, monkeypatch,
                         q_st = np.array([v * qs for v in qt[b]])
                     refs[b] = orcs[b].step(refs[b], q_stages=q_st)
                     e = rel(us[b].cpu().numpy(), refs[b])
-                    assert e <= TOL64, (n, b, e)
+                    assert e <= tol, (n, b, e)
         res[mode] = out
-        say(f"   {mode}: {len(ctxs)} problems ({len(mix)} operators), 3 steps")
+        if ir:
+            say(f"   refinement records: {[hps.ark_info(c) for c in ctxs[:3]]}")
+        say(f"   {mode}: {len(ctxs)} problems ({len(mix)} operators), {len(out)} steps")
     for a, b in zip(res["grouped"], res["streams"]):
         for x, y in zip(a, b):
             assert torch.equal(x, y)

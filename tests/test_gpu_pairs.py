@@ -198,3 +198,27 @@ def test_uniform_operator_pairs_stored_once(torch, monkeypatch):
     assert e <= TOL64
     full.free()
     uni.free()
+
+
+def test_zero_dirichlet_data_skips_nothing_that_matters(torch, monkeypatch):
+    """Without Dirichlet data the top pair does not stream the columns that multiply the
+    (zero) boundary values: the solve equals the one given explicit zeros bit for bit, for
+    one right-hand side and for several."""
+    monkeypatch.setenv("HPS_COMPOSE", "1")
+    say("[pairs] no Dirichlet data vs explicit zeros, 8x8 p=12")
+    rng = np.random.default_rng(10)
+    g, og, x, y, co, op = setup(torch, 8, 8, 12, 0.01)
+    T = lambda a: torch.tensor(a, device="cuda")
+    body, jump = rng.standard_normal(og.n_int), rng.standard_normal(op.n_iface)
+    zeros = torch.zeros(op.n_bdry, dtype=torch.float64, device="cuda")
+    a = hps.hps_solve(op, T(body), None, T(jump))
+    b = hps.hps_solve(op, T(body), zeros, T(jump))
+    assert torch.equal(a, b)
+    bodies = T(rng.standard_normal((3, og.n_int)))
+    am = hps.hps_solve(op, bodies)
+    bm = hps.hps_solve(op, bodies, torch.zeros((3, op.n_bdry), dtype=torch.float64, device="cuda"))
+    assert torch.equal(am, bm)
+    e = rel(a.cpu().numpy(), HPS(og, co, 0.01).solve(body, None, jump))
+    say(f"   rel err vs oracle {e:.2e}")
+    assert e <= TOL64
+    op.free()

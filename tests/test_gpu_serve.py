@@ -190,6 +190,37 @@ def test_server_rejects_bad_jobs(torch):
     srv.close()
 
 
+def test_full_queue_returns_busy(torch):
+    """max_queued bounds the jobs waiting for admission: with one job running (max_active =
+    1) and one waiting, a third submission returns HPS_EBUSY and queues nothing; the other
+    two complete and equal the oracle."""
+    say("[serve] bounded queue: HPS_EBUSY")
+    import time
+    P = Problem(torch, "allen_cahn", 2, 2, 6, 1e-3, 21)
+    srv = hps.Server(max_active=1, max_queued=1)
+    long_steps = 400
+    ja, ua = P.submit(torch, srv, long_steps)
+    t0 = time.time()
+    while srv.poll(ja)["state"] == hps.SRV_QUEUED and time.time() - t0 < 30:
+        time.sleep(0.001)
+    jb, ub = P.submit(torch, srv, 2)            # waits behind the running job
+    assert srv.poll(ja)["state"] == hps.SRV_ACTIVE or srv.poll(jb)["state"] != hps.SRV_QUEUED
+    busy = srv.poll(jb)["state"] == hps.SRV_QUEUED
+    if busy:
+        with pytest.raises(hps.HPSError) as e:
+            P.submit(torch, srv, 2)
+        assert e.value.code == -6
+    sa, sb = srv.wait(ja), srv.wait(jb)
+    stats = srv.stats()
+    srv.close()
+    say(f"   third submission rejected while the queue was full: {busy}; {stats}")
+    assert busy, "the first job finished before the queue could fill; lengthen it"
+    assert sa["state"] == hps.SRV_DONE and sb["state"] == hps.SRV_DONE
+    assert stats["submitted"] == 2
+    assert rel(ua.cpu().numpy(), P.oracle(long_steps)) <= TOL64
+    assert rel(ub.cpu().numpy(), P.oracle(2)) <= TOL64
+
+
 def test_served_jobs_with_both_tableaux(torch):
     """Jobs stepping with ARK4(3)6L[2]SA and with ARK5(4)8L[2]SA (8 stages) in one server:
     each equals its oracle run."""
