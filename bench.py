@@ -396,6 +396,17 @@ def main():
     build_s = time.perf_counter() - t0
     total_bytes, op_bytes = op.bytes()
     log(f"build FP64: {build_s:.3f} s, operators {op_bytes / 1e9:.3f} GB")
+    # the method's own operator bytes (one operator per tree level): what the roofline
+    # counts; the composite level pairs the default sweeps stream instead are larger
+    prev = os.environ.get("HPS_COMPOSE")
+    os.environ["HPS_COMPOSE"] = "0"
+    op_lv = hps.hps_build(g, coefs, gdt, hps.HPS_FP64 | tiles)
+    per_level_op_bytes = op_lv.bytes()[1]
+    op_lv.free()
+    if prev is None:
+        del os.environ["HPS_COMPOSE"]
+    else:
+        os.environ["HPS_COMPOSE"] = prev
     ctx = hps.ark_create(op, tab, dt, g=workloads.AllenCahn.gpoly)
 
     u = u0.clone()
@@ -457,12 +468,18 @@ def main():
     # the time is the measured step time over its stage solves (the step completion's
     # interface lines and stage 1's evaluation included)
     leaf_op_bytes = n * n * (q ** 4 + q * q * 4 * q) * 8
-    stage_bytes = op_bytes + (alg - leaf_op_bytes)
+    # algorithmic bytes: the per-level operators (not the larger composites) plus fields
+    stage_bytes = per_level_op_bytes + (alg - leaf_op_bytes)
     stage_us = 1e3 * ms_per_step / stages
     stage_roof = {"bound": "hbm", "bytes_per_stage_solve": int(stage_bytes), "us_per_stage_solve": round(stage_us, 2),
                   "achieved": round(stage_bytes / (stage_us * 1e-6) / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                   "frac": round(stage_bytes / (stage_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
-                  "stage_solves_per_s_at_0.6_peak": round(0.6 * HBM_PEAK_GBS * 1e9 / stage_bytes, 1)}
+                  "stage_solves_per_s_at_0.6_peak": round(0.6 * HBM_PEAK_GBS * 1e9 / stage_bytes, 1),
+                  "bytes_counted": "the method's per-level operators (leaf A_ii^-1 and S_leaf, every level's [X; U] "
+                                   "and S) once, plus the fused leaf kernel's field traffic",
+                  "operator_bytes_streamed": int(op_bytes),
+                  "note": "the default sweeps stream composite level-pair operators instead of the per-level ones "
+                          "(operator_bytes_streamed); without Dirichlet data the top pair skips its boundary columns"}
     log(f"stage solve: {stage_roof}")
 
     # ---- single stage-solve latency (hps_solve: one full up/down sweep) ----

@@ -1313,10 +1313,15 @@ __device__ __forceinline__ void root_body(const LevelArgs &up, const LevelArgs &
     T *xs2 = cv.take<T>(SG2);
     T *part1 = cv.take<T>((size_t)up.pn.G * up.pn.rp * VW);
     T *part2 = cv.take<T>((size_t)dn.pn.G * dn.pn.rp * VW);
-    // both operators' first loads are issued before the inputs are gathered
+    // both operators' first loads are issued before the inputs are gathered; without
+    // Dirichlet data S u_12 is zero and S is not read (the sum of its zero products is +0,
+    // so u_3 = 0 + X d is the same either way)
+    const bool with_s = dn.dir != nullptr;
     PanelStream<T, PF, UNR> ps, ps2;
     ps.start(reinterpret_cast<const T *>(up.pn.data) + (int64_t)tile * up.pn.tile_elems, up.pn.rp, up.pn.G, up.pn.S);
-    ps2.start(reinterpret_cast<const T *>(dn.pn.data) + (int64_t)tile * dn.pn.tile_elems, dn.pn.rp, dn.pn.G, dn.pn.S);
+    if (with_s)
+        ps2.start(reinterpret_cast<const T *>(dn.pn.data) + (int64_t)tile * dn.pn.tile_elems, dn.pn.rp, dn.pn.G,
+                  dn.pn.S);
     const int rows = up.pn.rp * VW;   // the same row tiling for X and S
     const int myrow = tile * rows + threadIdx.x;
     int64_t ia = -1, ib = -1;
@@ -1345,7 +1350,7 @@ __device__ __forceinline__ void root_body(const LevelArgs &up, const LevelArgs &
     }
     __syncthreads();
     ps.finish(xs1, part1);
-    ps2.finish(xs2, part2);
+    if (with_s) ps2.finish(xs2, part2);
     __syncthreads();
     // deterministic sums over the column groups of both products, then u_3 = S u_12 + X d
     const int nsl1 = min(up.pn.G, NT / rows), nsl2 = min(dn.pn.G, NT / rows);
@@ -1356,7 +1361,7 @@ __device__ __forceinline__ void root_body(const LevelArgs &up, const LevelArgs &
         for (int gg = sl; gg < up.pn.G; gg += nsl1) y += part1[gg * rows + row];
         y1 = (double)y;
     }
-    if (sl < nsl2) {
+    if (with_s && sl < nsl2) {
         T y = T(0);
         for (int gg = sl; gg < dn.pn.G; gg += nsl2) y += part2[gg * rows + row];
         y2 = (double)y;
