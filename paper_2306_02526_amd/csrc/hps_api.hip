@@ -786,7 +786,8 @@ static int build_impl(hps_op *op, const hps_coeffs *co, const hps_coeffs *co_im,
             hps_set_error("internal: composite pair %zu is for level %d", k, op->pairs[k].l);
             return HPS_EDEVICE;
         }
-        pair_bytes += op->pairs[k].up.bytes() + op->pairs[k].dn.bytes();
+        pair_bytes += op->pairs[k].up.bytes() + op->pairs[k].dn.bytes() + op->pairs[k].up32.bytes() +
+                      op->pairs[k].dn32.bytes();
     }
     if (op->operator_bytes - pair_bytes != plan_operator_bytes(op->grid, op->flags, m, op->level_mwg)) {
         hps_set_error("internal: operator size plan %lld != allocated %lld",
@@ -900,8 +901,11 @@ extern "C" int64_t hps_op_bytes(const hps_op *op, int64_t *operator_bytes) {
         const bool f32 = (op->flags & HPS_FP32_IR) != 0;
         b += (f32 ? op->ainv32 : op->ainv64).bytes() + (f32 ? op->sleaf32 : op->sleaf64).bytes();
         if (op->composed) {   // the composites, and the single bottom level of an odd tree
-            for (const PairOps &P : op->pairs) b += P.up.bytes() + P.dn.bytes();
-            if (op->L % 2 == 1) b += op->lv[op->L - 1].xu64.bytes() + op->lv[op->L - 1].s64.bytes();
+            for (const PairOps &P : op->pairs) b += f32 ? P.up32.bytes() + P.dn32.bytes() : P.up.bytes() + P.dn.bytes();
+            if (op->L % 2 == 1) {
+                const Level &B = op->lv[op->L - 1];
+                b += f32 ? B.xu32.bytes() + B.s32.bytes() : B.xu64.bytes() + B.s64.bytes();
+            }
         } else {
             for (const Level &L : op->lv) b += (f32 ? L.xu32 : L.xu64).bytes() + (f32 ? L.s32 : L.s64).bytes();
         }

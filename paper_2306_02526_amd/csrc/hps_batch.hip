@@ -513,11 +513,47 @@ int build_plan_ir(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, co
         P->seq.push_back(L);
         return HPS_OK;
     };
-    // the FP32 level sweeps (upward levels aligned at the roots, the fused roots, downward)
-    const size_t ls = level_record_size();
+    // the FP32 level sweeps (upward levels aligned at the roots, the fused roots and top
+    // pairs, downward); operators with composite pairs take them at the pair's upper level
+    const size_t ls = level_record_size(), prs = pair_record_size();
+    auto single_here = [&](const hps_op *op, int l) -> bool {
+        if (l >= op->L) return false;
+        if (op->composed) return (op->L % 2 == 1) && l == op->L - 1;
+        return !(l == 0 && root_fused(op, true));
+    };
+    auto pair_here = [&](const hps_op *op, int l, int mode) -> bool {
+        if (!op->composed) return false;
+        if (mode == 2) return l == 0;
+        return l >= 2 && l % 2 == 0 && l <= pair_lowest(op);
+    };
     auto sweep = [&](const std::vector<int> &probs, bool with_r3) -> int {
         int Lmax = 0;
         for (int b : probs) Lmax = std::max(Lmax, ctx[b]->op->L);
+        auto pairs = [&](int l, int mode) -> int {
+            GroupPlan::Launch L{};
+            L.kind = 6 + mode;
+            L.fp32 = 1;
+            std::vector<unsigned char> recs;
+            std::vector<int> bs(1, 0);
+            for (int b : probs) {
+                const hps_op *op = ctx[b]->op;
+                if (!pair_here(op, l, mode)) continue;
+                recs.resize(recs.size() + prs);
+                int blocks = 0;
+                size_t lds = 0;
+                pair_record(op, l, mode, nullptr, recs.data() + recs.size() - prs, &blocks, &lds, ws[b], true,
+                            with_r3 ? r3_of(b) : nullptr);
+                L.lds = std::max(L.lds, lds);
+                bs.push_back(bs.back() + blocks);
+            }
+            L.cnt = (int)bs.size() - 1;
+            if (L.cnt == 0) return HPS_OK;
+            L.a = T.put(recs.data(), recs.size());
+            L.base = T.put(bs.data(), sizeof(int) * bs.size());
+            L.total = bs.back();
+            P->seq.push_back(L);
+            return HPS_OK;
+        };
         auto level = [&](int l, bool up) -> int {
             GroupPlan::Launch L{};
             L.kind = up ? 1 : 2;
@@ -526,7 +562,7 @@ int build_plan_ir(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, co
             std::vector<int> bs(1, 0);
             for (int b : probs) {
                 const hps_op *op = ctx[b]->op;
-                if (l >= op->L || (l == 0 && root_fused(op, true))) continue;
+                if (!single_here(op, l)) continue;
                 recs.resize(recs.size() + ls);
                 int blocks = 0;
                 size_t lds = 0;
@@ -543,7 +579,11 @@ int build_plan_ir(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, co
             P->seq.push_back(L);
             return HPS_OK;
         };
-        for (int l = Lmax - 1; l >= 0; --l) TRY(level(l, true));
+        for (int l = Lmax - 1; l >= 0; --l) {
+            TRY(level(l, true));
+            TRY(pairs(l, 0));
+        }
+        TRY(pairs(0, 2));
         {
             GroupPlan::Launch L{};
             L.kind = 3;
@@ -552,7 +592,7 @@ int build_plan_ir(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, co
             std::vector<int> bs(1, 0);
             for (int b : probs) {
                 const hps_op *op = ctx[b]->op;
-                if (!root_fused(op, true)) continue;
+                if (op->composed || !root_fused(op, true)) continue;
                 ups.resize(ups.size() + ls);
                 dns.resize(dns.size() + ls);
                 int blocks = 0;
@@ -571,7 +611,10 @@ int build_plan_ir(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, co
                 P->seq.push_back(L);
             }
         }
-        for (int l = 0; l < Lmax; ++l) TRY(level(l, false));
+        for (int l = 0; l < Lmax; ++l) {
+            TRY(pairs(l, 1));
+            TRY(level(l, false));
+        }
         return HPS_OK;
     };
     auto residual = [&](const std::vector<int> &probs) {
@@ -700,6 +743,11 @@ int enqueue_plan(const GroupPlan *P, hipStream_t st) {
                 case 10:
                     TRY(launch_residual_group(d + L.a, basep(L), d + L.a2, reinterpret_cast<const int *>(d + L.base2),
                                               L.cnt, L.total, L.total2, st));
+                    break;
+                case 6:
+                case 7:
+                case 8:
+                    TRY(launch_pair_group(d + L.a, basep(L), L.cnt, L.total, L.lds, L.kind - 6, st, true));
                     break;
                 default:
                     hps_set_error("internal: launch kind %d in a refined plan", L.kind);

@@ -130,18 +130,19 @@ static int pair_target() {
 }
 
 // The packing of a composite: rows cut into tiles so that the launch has about `target`
-// workgroups (at most NT / 2 row vectors per tile: one row per thread)
-static Panel pair_panel(int R, int C, int nodes, int target) {
-    const int RV = (R + 1) / 2;
+// workgroups (at most NT / vw row vectors per tile: one row per thread); vw = 2 (FP64) or
+// 4 (FP32)
+static Panel pair_panel(int R, int C, int nodes, int target, int vw = 2) {
+    const int RV = (R + vw - 1) / vw;
     const int per = std::max(1, (target + nodes - 1) / nodes);   // row tiles per node
-    const int rp_max = std::min(NT / 2, std::max(1, (RV + per - 1) / per));
-    return plan_panel(R, C, 2, nodes, rp_max, 0);
+    const int rp_max = std::min(NT / vw, std::max(1, (RV + per - 1) / per));
+    return plan_panel(R, C, vw, nodes, rp_max, 0);
 }
 
 // Composites need one workgroup's input vector in LDS (no split-K), FP64 real per-node
 // operators and at least the root and one level below it.
 bool hps::compose_eligible(const hps_op *op, const std::vector<HostLevel> &hl) {
-    if (op->ncomp != 1 || (op->flags & (HPS_FP32_IR | HPS_WIDE_TILES)) || op->L < 2) return false;
+    if (op->ncomp != 1 || (op->flags & HPS_WIDE_TILES) || op->L < 2) return false;
     // the top pair (0, 1), then (2, 3), (4, 5), ... while the lower level exists
     for (int l = 0; l + 1 < op->L; l += 2) {
         const HostLevel &t = hl[l], &c = hl[l + 1];
@@ -257,11 +258,11 @@ int hps::compose_pair(hps_op *op, int l, const std::vector<HostLevel> &hl, const
 
     // ---- pack (streaming layout, FP64) ----
     const int target = pair_target();
-    auto pack = [&](Panel &pn, const double *M, int R, int C) -> int {
-        pn = pair_panel(R, C, nt, target);
+    auto pack = [&](Panel &pn, const double *M, int R, int C, int vw) -> int {
+        pn = pair_panel(R, C, nt, target, vw);
         if (uni) pn = shared_panel(pn);
-        double *d;
-        if (hipMalloc(&d, sizeof(double) * pn.node_elems * pn.nodes) != hipSuccess) {
+        void *d;
+        if (hipMalloc(&d, (vw == 2 ? 8 : 4) * pn.node_elems * pn.nodes) != hipSuccess) {
             (void)hipGetLastError();
             hps_set_error("hipMalloc for a composite operator failed");
             return HPS_ENOMEM;
@@ -276,8 +277,12 @@ int hps::compose_pair(hps_op *op, int l, const std::vector<HostLevel> &hl, const
         }
         return launch_pack(pn, M, R, (int64_t)R * C, R, nullptr, 0, 0, st);
     };
-    if (!top) TRY(pack(P.up, Mup, P.R_up, P.C_up));
-    TRY(pack(P.dn, Mdn, P.R_dn, P.C_dn));
+    if (!top) TRY(pack(P.up, Mup, P.R_up, P.C_up, 2));
+    TRY(pack(P.dn, Mdn, P.R_dn, P.C_dn, 2));
+    if (op->flags & HPS_FP32_IR) {   // the FP32 sweeps' copies, rounded from the same products
+        if (!top) TRY(pack(P.up32, Mup, P.R_up, P.C_up, 4));
+        TRY(pack(P.dn32, Mdn, P.R_dn, P.C_dn, 4));
+    }
 
     // ---- index tables ----
     std::vector<int> tab;

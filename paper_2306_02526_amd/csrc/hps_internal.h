@@ -92,6 +92,7 @@ struct HostLevel {
 struct PairOps {
     int l = -1;
     Panel up, dn;                 // composite operators, FP64 (the top pair: dn only)
+    Panel up32, dn32;             // FP32 copies (FP32_IR operators)
     int R_up = 0, C_up = 0, R_dn = 0, C_dn = 0;
     int *tab = nullptr;           // device tables
     int t_plus = 0, t_minus = 0, t_j3 = 0, t_fin_up = 0, t_fin_dn = 0, t_copy = 0;
@@ -104,7 +105,7 @@ enum KernelFamily {
     KF_LEVEL_UP64, KF_LEVEL_UP32, KF_LEVEL_DOWN64, KF_LEVEL_DOWN32, KF_RESIDUAL, KF_LINES,
     KF_LEAF2_EVAL_UP64, KF_LEAF2_DOWN_UP64, KF_LEAF2_DOWN_UPDATE64, KF_LEVEL2_UP64, KF_LEVEL2_DOWN64,
     KF_LEAFC_EVAL_UP64, KF_LEAFC_DOWN_UP64, KF_LEAFC_DOWN_UPDATE64, KF_LEAFC_SOLVE64,
-    KF_PAIR_UP64, KF_PAIR_TOP64, KF_PAIR_DOWN64, KF_COUNT
+    KF_PAIR_UP64, KF_PAIR_TOP64, KF_PAIR_DOWN64, KF_PAIR_UP32, KF_PAIR_TOP32, KF_PAIR_DOWN32, KF_COUNT
 };
 extern const char *const kKernelFamilyNames[KF_COUNT];
 
@@ -362,8 +363,9 @@ int launch_memop_group(const MemOp *ops, const int64_t *base, int n, int64_t tot
 size_t pair_record_size();
 int pair_lowest(const hps_op *op);
 void pair_record(const hps_op *op, int l, int mode, const double *dir, void *dst, int *blocks, size_t *lds,
-                 const Workspace *ws);
-int launch_pair_group(const void *args, const int *base, int n, int total, size_t lds, int mode, hipStream_t st);
+                 const Workspace *ws, bool fp32 = false, const double *r3 = nullptr);
+int launch_pair_group(const void *args, const int *base, int n, int total, size_t lds, int mode, hipStream_t st,
+                      bool fp32 = false);
 size_t line_record_size();
 void line_record(const hps_op *op, double *u, void *dst, int *systems, const Workspace *ws);
 size_t scatter_record_size();

@@ -610,7 +610,7 @@ __global__ __launch_bounds__(NT) void k_pair_sys(PairArgsN<NC> a) {
 
 // One composite product of several operators in one launch: workgroup w belongs to entry
 // e, base[e] <= w < base[e + 1].
-template <int MODE>
+template <typename T, int MODE>
 __global__ __launch_bounds__(NT) void k_pair_group(const PairArgs *args, const int *base, int n) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[NT + 64];
@@ -621,7 +621,7 @@ __global__ __launch_bounds__(NT) void k_pair_group(const PairArgs *args, const i
         if (base[mid] <= w) lo = mid;
         else hi = mid - 1;
     }
-    pair_body<double, MODE>(args[lo], w - base[lo], smem, red);
+    pair_body<T, MODE>(args[lo], w - base[lo], smem, red);
 }
 
 // =======================================================================================
@@ -1239,7 +1239,8 @@ const char *const kKernelFamilyNames[KF_COUNT] = {
     "leaf_eval_update", "level_up_fp64", "level_up_fp32", "level_down_fp64", "level_down_fp32",
     "residual", "lines", "leaf2_eval_up_fp64", "leaf2_down_up_fp64", "leaf2_down_update_fp64",
     "level2_up_fp64", "level2_down_fp64", "leafc_eval_up_fp64", "leafc_down_up_fp64", "leafc_down_update_fp64",
-    "leafc_solve_fp64", "pair_up_fp64", "pair_top_fp64", "pair_down_fp64"};
+    "leafc_solve_fp64", "pair_up_fp64", "pair_top_fp64", "pair_down_fp64", "pair_up_fp32", "pair_top_fp32",
+    "pair_down_fp32"};
 
 hipEvent_t Profiler::get() {
     if (!pool.empty()) {
@@ -1511,7 +1512,7 @@ static void use_workspace(const hps_op *op, int l, bool up, const Workspace *ws,
 // The arguments of composite pair l's kernel (mode PAIR_UP / PAIR_DOWN / PAIR_TOP), on the
 // operator's solve buffers or on workspace ws.
 static PairArgs pair_args(const hps_op *op, int l, int mode, const double *jump, const double *dirichlet,
-                          const Workspace *ws) {
+                          const Workspace *ws, bool fp32 = false) {
     const int L = op->L;
     auto hbuf = [&](int k) -> double * {
         if (k == L) return ws ? ws->h_leaf : op->h_leaf;
@@ -1526,7 +1527,7 @@ static PairArgs pair_args(const hps_op *op, int l, int mode, const double *jump,
     const PairOps &P = op->pairs[l / 2];
     const Level &T = op->lv[l], &Cl = op->lv[l + 1];
     PairArgs a{};
-    a.pn = view(up ? P.up : P.dn);
+    a.pn = view(up ? (fp32 ? P.up32 : P.up) : (fp32 ? P.dn32 : P.dn));
     a.R = up ? P.R_up : P.R_dn;
     a.C = up ? P.C_up : P.C_dn;
     a.n3t = T.n3;
@@ -1560,46 +1561,50 @@ static int lowest_pair(const hps_op *op) { return (op->L % 2 == 1) ? op->L - 3 :
 // FP64 sweeps through the composite level pairs: the top pair (root and level 1) in one
 // launch, pairs (l, l + 1) for even l >= 2 one launch per direction, and an odd number of
 // levels leaves the bottom level to the single-level kernels.
-static int launch_pairs(const hps_op *op, const double *jump, const double *dirichlet, hipStream_t st,
+static int launch_pairs(const hps_op *op, bool fp32, const double *jump, const double *dirichlet, hipStream_t st,
                         const Workspace *ws) {
     const int L = op->L;
     auto single = [&](int l, bool up) {
-        LevelArgs a = level_args(op, l, false, up);
+        LevelArgs a = level_args(op, l, fp32, up);
         use_workspace(op, l, up, ws, a);
         a.r3 = jump;
         a.dir = dirichlet;
-        const Panel &pn = up ? op->lv[l].xu64 : op->lv[l].s64;
+        const Panel &pn = up ? (fp32 ? op->lv[l].xu32 : op->lv[l].xu64) : (fp32 ? op->lv[l].s32 : op->lv[l].s64);
         const unsigned nb = (unsigned)(op->lv[l].nodes * a.pn.ntile * a.pn.kch);
-        if (up) launch_level<double, true>(a, nb, level_lds(pn), st);
-        else launch_level<double, false>(a, nb, level_lds(pn), st);
+        if (fp32) {
+            if (up) launch_level<float, true>(a, nb, level_lds(pn), st);
+            else launch_level<float, false>(a, nb, level_lds(pn), st);
+        } else {
+            if (up) launch_level<double, true>(a, nb, level_lds(pn), st);
+            else launch_level<double, false>(a, nb, level_lds(pn), st);
+        }
+        HPS_LAUNCHED();
+    };
+    auto pair = [&](auto kern, int l, int mode) {
+        const PairArgs a = pair_args(op, l, mode, jump, dirichlet, ws, fp32);
+        const PairOps &P = op->pairs[l / 2];
+        const Panel &pn = mode == PAIR_UP ? (fp32 ? P.up32 : P.up) : (fp32 ? P.dn32 : P.dn);
+        hipLaunchKernelGGL(kern, dim3((unsigned)(op->lv[l].nodes * pn.ntile)), dim3(NT), level_lds(pn), st, a);
         HPS_LAUNCHED();
     };
     const int top_low = lowest_pair(op);
     {
-        ProfScope ps_(&op->prof, KF_PAIR_UP64, st);
+        ProfScope ps_(&op->prof, fp32 ? KF_PAIR_UP32 : KF_PAIR_UP64, st);
         if (L % 2 == 1) single(L - 1, true);
         for (int l = top_low; l >= 2; l -= 2) {
-            const PairArgs a = pair_args(op, l, PAIR_UP, jump, dirichlet, ws);
-            const Panel &pn = op->pairs[l / 2].up;
-            hipLaunchKernelGGL((k_pair<double, PAIR_UP>), dim3((unsigned)(op->lv[l].nodes * pn.ntile)), dim3(NT),
-                               level_lds(pn), st, a);
-            HPS_LAUNCHED();
+            if (fp32) pair(k_pair<float, PAIR_UP>, l, PAIR_UP);
+            else pair(k_pair<double, PAIR_UP>, l, PAIR_UP);
         }
     }
     {
-        ProfScope ps_(&op->prof, KF_PAIR_TOP64, st);
-        const PairArgs a = pair_args(op, 0, PAIR_TOP, jump, dirichlet, ws);
-        const Panel &pn = op->pairs[0].dn;
-        hipLaunchKernelGGL((k_pair<double, PAIR_TOP>), dim3((unsigned)pn.ntile), dim3(NT), level_lds(pn), st, a);
-        HPS_LAUNCHED();
+        ProfScope ps_(&op->prof, fp32 ? KF_PAIR_TOP32 : KF_PAIR_TOP64, st);
+        if (fp32) pair(k_pair<float, PAIR_TOP>, 0, PAIR_TOP);
+        else pair(k_pair<double, PAIR_TOP>, 0, PAIR_TOP);
     }
-    ProfScope ps_(&op->prof, KF_PAIR_DOWN64, st);
+    ProfScope ps_(&op->prof, fp32 ? KF_PAIR_DOWN32 : KF_PAIR_DOWN64, st);
     for (int l = 2; l <= top_low; l += 2) {
-        const PairArgs a = pair_args(op, l, PAIR_DOWN, jump, dirichlet, ws);
-        const Panel &pn = op->pairs[l / 2].dn;
-        hipLaunchKernelGGL((k_pair<double, PAIR_DOWN>), dim3((unsigned)(op->lv[l].nodes * pn.ntile)), dim3(NT),
-                           level_lds(pn), st, a);
-        HPS_LAUNCHED();
+        if (fp32) pair(k_pair<float, PAIR_DOWN>, l, PAIR_DOWN);
+        else pair(k_pair<double, PAIR_DOWN>, l, PAIR_DOWN);
     }
     if (L % 2 == 1) single(L - 1, false);
     return HPS_OK;
@@ -1607,7 +1612,7 @@ static int launch_pairs(const hps_op *op, const double *jump, const double *diri
 
 int launch_levels(const hps_op *op, bool fp32, const double *jump, const double *dirichlet, hipStream_t st,
                   const Workspace *ws) {
-    if (!fp32 && op->composed) return launch_pairs(op, jump, dirichlet, st, ws);
+    if (op->composed) return launch_pairs(op, fp32, jump, dirichlet, st, ws);
     const bool rootf = root_fusable(op, fp32);
     {
         ProfScope ps_(&op->prof, fp32 ? KF_LEVEL_UP32 : KF_LEVEL_UP64, st);
@@ -1881,19 +1886,28 @@ size_t pair_record_size() { return sizeof(PairArgs); }
 int pair_lowest(const hps_op *op) { return lowest_pair(op); }
 
 void pair_record(const hps_op *op, int l, int mode, const double *dir, void *dst, int *blocks, size_t *lds,
-                 const Workspace *ws) {
-    *reinterpret_cast<PairArgs *>(dst) = pair_args(op, l, mode, nullptr, dir, ws);
-    const Panel &pn = mode == PAIR_UP ? op->pairs[l / 2].up : op->pairs[l / 2].dn;
+                 const Workspace *ws, bool fp32, const double *r3) {
+    *reinterpret_cast<PairArgs *>(dst) = pair_args(op, l, mode, r3, dir, ws, fp32);
+    const PairOps &P = op->pairs[l / 2];
+    const Panel &pn = mode == PAIR_UP ? (fp32 ? P.up32 : P.up) : (fp32 ? P.dn32 : P.dn);
     *blocks = (int)(op->lv[l].nodes * pn.ntile);
     *lds = level_lds(pn);
 }
 
-int launch_pair_group(const void *args, const int *base, int n, int total, size_t lds, int mode, hipStream_t st) {
+int launch_pair_group(const void *args, const int *base, int n, int total, size_t lds, int mode, hipStream_t st,
+                      bool fp32) {
     if (total <= 0) return HPS_OK;
     const PairArgs *a = reinterpret_cast<const PairArgs *>(args);
-    if (mode == PAIR_UP) hipLaunchKernelGGL(k_pair_group<PAIR_UP>, dim3(total), dim3(NT), lds, st, a, base, n);
-    else if (mode == PAIR_DOWN) hipLaunchKernelGGL(k_pair_group<PAIR_DOWN>, dim3(total), dim3(NT), lds, st, a, base, n);
-    else hipLaunchKernelGGL(k_pair_group<PAIR_TOP>, dim3(total), dim3(NT), lds, st, a, base, n);
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(total), dim3(NT), lds, st, a, base, n); };
+    if (fp32) {
+        if (mode == PAIR_UP) go(k_pair_group<float, PAIR_UP>);
+        else if (mode == PAIR_DOWN) go(k_pair_group<float, PAIR_DOWN>);
+        else go(k_pair_group<float, PAIR_TOP>);
+    } else {
+        if (mode == PAIR_UP) go(k_pair_group<double, PAIR_UP>);
+        else if (mode == PAIR_DOWN) go(k_pair_group<double, PAIR_DOWN>);
+        else go(k_pair_group<double, PAIR_TOP>);
+    }
     HPS_LAUNCHED();
     return HPS_OK;
 }

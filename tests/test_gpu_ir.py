@@ -78,13 +78,10 @@ def test_replayed_fp32_ir_steps_match_oracle(torch):
 def test_failed_refinement_falls_back_to_fp64_bitwise(torch, monkeypatch):
     """With refinement made to fail, every stage is re-solved with the operator's FP64
     copy: the steps equal those of a plain FP64 operator bit for bit, and the record says
-    so; hps_solve likewise.  The FP64 copy an FP32+IR operator keeps is swept level by
-    level, so the plain operator is built without composite level pairs."""
+    so; hps_solve likewise.  (Both operators sweep the same FP64 composite level pairs.)"""
     say("[ir] forced refinement failure, 8x8 p=10, 3 steps")
     dt = 1e-3
-    monkeypatch.setenv("HPS_COMPOSE", "0")
     og, co, op64, c64, u0, gdt = allen_cahn(torch, 8, 10, dt, hps.HPS_FP64)
-    monkeypatch.delenv("HPS_COMPOSE")
     _, _, opsk, csk, _, _ = allen_cahn(torch, 8, 10, dt, hps.HPS_FP32_IR | hps.HPS_TEST_FP32_SKEW)
     a, b = torch.tensor(u0, device="cuda"), torch.tensor(u0, device="cuda")
     for n in range(3):

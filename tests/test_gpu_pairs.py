@@ -92,18 +92,40 @@ def test_pair_solve_matches_oracle(torch, monkeypatch, n1, n2, p):
     op.free()
 
 
+PAIR_FAMILIES32 = {"pair_up_fp32", "pair_top_fp32", "pair_down_fp32"}
+
+
+@pytest.mark.parametrize("n1,n2,p", [(4, 2, 6), (8, 8, 10), (16, 8, 7)], ids=["4x2_p6", "8x8_p10", "16x8_p7"])
+def test_pair_fp32_ir_solve_matches_oracle(torch, monkeypatch, n1, n2, p):
+    """FP32+IR operators sweep FP32 copies of the composites (each pass of the refinement),
+    with Dirichlet data and interface jumps: the refined solve meets the 1e-10 bar."""
+    monkeypatch.setenv("HPS_COMPOSE", "1")
+    say(f"[pairs] FP32+IR solve {n1}x{n2} p={p}")
+    rng = np.random.default_rng(4100 + 100 * n1 + 10 * n2 + p)
+    gdt = 0.01
+    g, og, x, y, co, op = setup(torch, n1, n2, p, gdt, hps.HPS_FP32_IR)
+    body, dirv, jump = rng.standard_normal(og.n_int), rng.standard_normal(op.n_bdry), rng.standard_normal(op.n_iface)
+    T = lambda a: torch.tensor(a, device="cuda")
+    u, fam = families(op, torch, lambda: hps.hps_solve(op, T(body), T(dirv), T(jump)))
+    assert PAIR_FAMILIES32 & fam, fam
+    e = rel(u.cpu().numpy(), HPS(og, co, gdt).solve(body, dirv, jump))
+    say(f"   kernels {sorted(fam)}; rel err vs oracle {e:.2e}")
+    assert e <= 1e-10
+    op.free()
+
+
 def test_pairs_not_used_where_they_do_not_apply(torch, monkeypatch):
-    """One tree level (no pair) and FP32 operators keep the single-level sweeps; the solve
-    is still the oracle's."""
+    """One tree level (no pair) and wide tiles keep the single-level sweeps; the solve is
+    still the oracle's."""
     monkeypatch.setenv("HPS_COMPOSE", "1")
     rng = np.random.default_rng(5)
     gdt = 0.01
-    for (n1, n2, p, flags, tol) in [(2, 1, 8, hps.HPS_FP64, TOL64), (8, 8, 10, hps.HPS_FP32_IR, 1e-10)]:
+    for (n1, n2, p, flags, tol) in [(2, 1, 8, hps.HPS_FP64, TOL64), (8, 8, 10, hps.HPS_WIDE_TILES, TOL64)]:
         say(f"[pairs] not applicable: {n1}x{n2} p={p} flags={flags}")
         g, og, x, y, co, op = setup(torch, n1, n2, p, gdt, flags)
         body = rng.standard_normal(og.n_int)
         u, fam = families(op, torch, lambda: hps.hps_solve(op, torch.tensor(body, device="cuda")))
-        assert not (PAIR_FAMILIES & fam), fam
+        assert not ((PAIR_FAMILIES | PAIR_FAMILIES32) & fam), fam
         e = rel(u.cpu().numpy(), HPS(og, co, gdt).solve(body))
         say(f"   rel err {e:.2e}")
         assert e <= tol
