@@ -69,8 +69,10 @@ def families(op, torch, fn):
 
 
 # (n1, n2, p): tree levels L = log2(n1 n2) = 2 (the top pair only), 3 (top pair and a
-# single bottom level), 4, 5, 6, 7 and 10
-SHAPES = [(2, 2, 8), (4, 2, 6), (4, 4, 8), (8, 4, 10), (4, 8, 7), (8, 8, 12), (16, 8, 7), (32, 32, 6)]
+# single bottom level), 4, 5, 6, 7 and 10; the smallest and largest orders (p = 3: one
+# interior node per leaf; p = 24)
+SHAPES = [(2, 2, 8), (4, 2, 6), (4, 4, 8), (8, 4, 10), (4, 8, 7), (8, 8, 12), (16, 8, 7), (32, 32, 6),
+          (4, 4, 3), (2, 4, 24)]
 
 
 @pytest.mark.parametrize("n1,n2,p", SHAPES, ids=[f"{a}x{b}_p{c}" for a, b, c in SHAPES])
