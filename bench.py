@@ -608,10 +608,20 @@ def main():
             hps.ark_step(ctx64, k * dt, u64)
         torch.cuda.synchronize()
         rel32 = float((u32 - u64).abs().max() / u64.abs().max())
+        # where an FP32+IR step's time goes (HIP events per kernel family; the profiled
+        # steps run eagerly, outside the timing)
+        hps.hps_profile_enable(op32, True)
+        hps.hps_profile_read(op32)
+        for k in range(2):
+            hps.ark_step(ctx32, (args.fp32_steps + 1 + k) * dt, u32.clone())
+        torch.cuda.synchronize()
+        kern32 = {k: round(1e3 * v[1] / 2, 1) for k, v in hps.hps_profile_read(op32).items()}
+        hps.hps_profile_enable(op32, False)
         fp32 = {"stage_solves_per_s": round(stages * args.fp32_steps / el32, 1),
                 "ms_per_step": round(1e3 * el32 / args.fp32_steps, 3),
                 "rel_err_vs_fp64_after_steps": rel32, "steps": args.fp32_steps + 1,
                 "build_s": round(b32, 3), "refinement_last_step": hps.ark_info(ctx32),
+                "us_per_step_by_family": kern32,
                 "note": "first step host-checked, later steps replayed from a HIP graph with a fixed "
                         "number of corrections per stage and one stream wait per step"}
         log(f"FP32+IR: {fp32}")
