@@ -769,6 +769,7 @@ static int build_impl(hps_op *op, const hps_coeffs *co, const hps_coeffs *co_im,
         TRY(dev_alloc(op, &op->ir_r, op->n_int));
         TRY(dev_alloc(op, &op->ir_r3, std::max<int64_t>(op->n_iface, 1)));
         TRY(dev_alloc(op, &op->ir_norms, 2));
+        TRY(dev_alloc(op, &op->ir_part, 2 * (int64_t)op->nleaves));
     }
     HPS_HIP(hipStreamSynchronize(st));
     int hsing = 0;
@@ -1007,6 +1008,7 @@ int64_t hps::workspace_layout(const hps_op *op, char *base, Workspace *w, int64_
     if (op->flags & HPS_FP32_IR) {
         ws.ir_r = (double *)take(8 * op->n_int);
         ws.ir_r3 = (double *)take(8 * std::max<int64_t>(op->n_iface, 1));
+        ws.ir_part = (double *)take(8 * 2 * nl);
     }
     ws.lv.resize(op->L);
     for (int l = 0; l < op->L; ++l) {

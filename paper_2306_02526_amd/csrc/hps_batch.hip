@@ -140,7 +140,7 @@ struct GroupPlan {
     struct Launch {
         int kind;            // 0 leaf phase, 1 level up, 2 level down, 3 roots, 4 boundary, 5 lines,
                              // 6 / 7 / 8 composite pairs up / down / top, 9 copies and fills,
-                             // 10 refinement residuals
+                             // 10 refinement residuals, 11 correction-norm folds
         size_t a, a2, base;  // offsets of the records (a2: downward root records / jump
                              // records) and bases
         int cnt, total;
@@ -487,6 +487,7 @@ int build_plan_ir(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, co
         return ws[b] ? ws[b]->ir_r3 : ctx[b]->op->ir_r3;
     };
     auto flux_of = [&](int b) { return ws[b] ? ws[b]->flux : ctx[b]->op->ir_flux; };
+    auto part_of = [&](int b) { return ws[b] ? ws[b]->ir_part : ctx[b]->op->ir_part; };
     // one leaf phase (the same kinds for all listed problems)
     auto leaf = [&](const std::vector<int> &probs, auto phase) -> int {
         GroupPlan::Launch L{};
@@ -680,8 +681,19 @@ int build_plan_ir(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, co
                 TRY(leaf(probs, [&](int b, LeafPhase &ph) {
                     ph.down = LD_IR_ADD;
                     ph.u_out = ctx[b]->stage_u;
-                    ph.norms = ctx[b]->ir_stat + ((int64_t)k * IR_MAXIT + j) * 2;
+                    ph.norm_part = part_of(b);
                 }));
+                std::vector<NormFold> folds;
+                for (int b : probs)
+                    folds.push_back(NormFold{part_of(b),
+                                             reinterpret_cast<unsigned long long *>(
+                                                 ctx[b]->ir_stat + ((int64_t)k * IR_MAXIT + j) * 2),
+                                             (int)ctx[b]->op->nleaves});
+                GroupPlan::Launch L{};
+                L.kind = 11;
+                L.a = T.put(folds.data(), sizeof(NormFold) * folds.size());
+                L.cnt = (int)folds.size();
+                P->seq.push_back(L);
             }
         }
         TRY(leaf(all, [&](int b, LeafPhase &ph) {
@@ -743,6 +755,9 @@ int enqueue_plan(const GroupPlan *P, hipStream_t st) {
                 case 10:
                     TRY(launch_residual_group(d + L.a, basep(L), d + L.a2, reinterpret_cast<const int *>(d + L.base2),
                                               L.cnt, L.total, L.total2, st));
+                    break;
+                case 11:
+                    TRY(launch_norm_fold_group(reinterpret_cast<const NormFold *>(d + L.a), L.cnt, st));
                     break;
                 case 6:
                 case 7:

@@ -30,8 +30,8 @@ static double ordered_bits_to_double(unsigned long long v) {
 // One correction pass of FP64 iterative refinement around the FP32 operators:
 // r = FP64 residual of the global system (interior rows rhs - (I - gamma dt L) u and the
 // interface flux jumps), delta = HPS32(r) with zero boundary data, u += delta.  The pass's
-// max|delta| and max|u| are accumulated into norms[0..1] (ordered bit patterns of
-// non-negative doubles, zero beforehand).
+// max|delta| and max|u| go to norms[0..1] (ordered bit patterns of non-negative doubles),
+// folded from the leaves' values in op->ir_part.
 static int ir_pass(hps_op *op, const double *rhs, const double *jump, double *u, double *norms, hipStream_t st) {
     TRY(launch_residual(op, u, rhs, jump, op->ir_r, op->ir_r3, st));
     LeafPhase up;
@@ -42,8 +42,9 @@ static int ir_pass(hps_op *op, const double *rhs, const double *jump, double *u,
     LeafPhase dn;
     dn.down = LD_IR_ADD;
     dn.u_out = u;
-    dn.norms = norms;
-    return launch_leaf(op, true, dn, st);
+    dn.norm_part = op->ir_part;
+    TRY(launch_leaf(op, true, dn, st));
+    return launch_norm_fold(op->ir_part, (int)op->nleaves, norms, st);
 }
 
 // max|delta| / max|u| of one pass from its two ordered-bit words; converged when
@@ -60,7 +61,6 @@ static int ir_adaptive(hps_op *op, const double *rhs, const double *jump, double
                        double *rel, bool *ok) {
     *ok = false;
     for (int it = 1; it <= IR_MAXIT; ++it) {
-        TRY(launch_zero(op->ir_norms, 2, st));
         TRY(ir_pass(op, rhs, jump, u, op->ir_norms, st));
         unsigned long long nb[2];
         HPS_HIP(hipMemcpyAsync(nb, op->ir_norms, sizeof(nb), hipMemcpyDeviceToHost, st));

@@ -165,6 +165,7 @@ struct hps_op {
     // iterative refinement workspace (FP32_IR)
     double *ir_rhs = nullptr, *ir_r = nullptr, *ir_r3 = nullptr, *ir_du = nullptr, *ir_flux = nullptr;
     double *ir_norms = nullptr;            // [2] max|delta|, max|u| (as ordered bit patterns)
+    double *ir_part = nullptr;             // [nleaves][2] per-leaf max|delta|, max|u| of a pass
     int64_t operator_bytes = 0, total_bytes = 0;
     std::vector<void *> allocs;
     mutable hps::Profiler prof;
@@ -184,6 +185,7 @@ struct Workspace {
     };
     double *h_leaf = nullptr, *ub_leaf = nullptr, *w_leaf = nullptr, *flux = nullptr;
     double *ir_r = nullptr, *ir_r3 = nullptr;   // FP32_IR operators: the refinement residual
+    double *ir_part = nullptr;                  // FP32_IR operators: per-leaf correction norms
     std::vector<Lv> lv;
     std::vector<void *> allocs;
 };
@@ -297,8 +299,9 @@ struct LeafPhase {
     double ca[8] = {0}, cf[8] = {0};
     double *rhs_copy = nullptr;
     double *unew = nullptr;                    // LU_UPDATE
-    double *norms = nullptr;                   // LD_IR_ADD: max|delta|, max|u| (ordered bits; null:
-                                               // the operator's pair)
+    double *norm_part = nullptr;               // LD_IR_ADD: per-leaf max|delta|, max|u| ([leaf][2];
+                                               // null: the operator's ir_part), folded by
+                                               // launch_norm_fold
 };
 // ws (FP64 only) redirects the solve buffers (leaf boundary values, particular solutions
 // and fluxes) from the operator's own to a workspace
@@ -352,6 +355,16 @@ void residual_records(const hps_op *op, const double *u, const double *rhs, doub
                       void *eval_dst, void *jump_dst, int *leaves, int *iface);
 int launch_residual_group(const void *evals, const int *ebase, const void *jumps, const int *jbase, int n,
                           int total_leaves, int total_iface, hipStream_t st);
+// max|delta| and max|u| of a refinement pass from the per-leaf values the LD_IR_ADD phase
+// writes (part[2 leaf], part[2 leaf + 1]) into out[0], out[1] as ordered bit patterns of the
+// non-negative doubles; one workgroup per fold, no atomics
+struct NormFold {
+    const double *part;
+    unsigned long long *out;
+    int leaves;
+};
+int launch_norm_fold(const double *part, int leaves, double *out, hipStream_t st);
+int launch_norm_fold_group(const NormFold *folds, int n, hipStream_t st);
 // copies (src != null) and zero fills of several buffers in one launch
 struct MemOp {
     void *dst;

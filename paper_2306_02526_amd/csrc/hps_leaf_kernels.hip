@@ -66,7 +66,7 @@ struct LeafArgs {
     double q_scale;
     const double *q_scale_ptr;   // device scalar replacing q_scale when set
     GPoly g;
-    unsigned long long *norms;   // DOWN_IR_ADD: max|delta|, max|u|
+    double *norm_part;           // DOWN_IR_ADD: this leaf's max|delta|, max|u| at [2 leaf], [2 leaf + 1]
     // up phase
     PanelView ainv;
     const double *body;          // UP_BODY
@@ -245,9 +245,10 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
                         dd = fmax(dd, nred[0][w]);
                         uu = fmax(uu, nred[1][w]);
                     }
-                    // non-negative doubles order like their bit patterns
-                    atomicMax(&a.norms[0], (unsigned long long)__double_as_longlong(dd));
-                    atomicMax(&a.norms[1], (unsigned long long)__double_as_longlong(uu));
+                    // one slot per leaf, folded by a later launch: thousands of atomics on
+                    // one address serialise at the memory side
+                    a.norm_part[2 * leaf] = dd;
+                    a.norm_part[2 * leaf + 1] = uu;
                 }
             }
         }
@@ -682,7 +683,7 @@ static void make_leaf_args(const hps_op *op, bool fp32, const LeafPhase &ph, Lea
     a.q_scale = ph.q_scale;
     a.q_scale_ptr = ph.q_scale_ptr;
     a.g = ph.g;
-    a.norms = reinterpret_cast<unsigned long long *>(ph.norms ? ph.norms : op->ir_norms);
+    a.norm_part = ph.norm_part ? ph.norm_part : op->ir_part;
     a.body = ph.body;
     a.un = ph.un;
     a.Lu_in = ph.Lu_in;

@@ -960,6 +960,39 @@ __global__ void k_jump_group(const JumpArgs *jp, const int *jbase, int n) {
     jump_body(j.g, j.flux, j.jump, j.scale, j.r3, t - jbase[e]);
 }
 
+// max over the leaves of a refinement pass's per-leaf max|delta| and max|u| (one workgroup;
+// max is exact, so the order does not matter)
+__device__ __forceinline__ void norm_fold_body(const NormFold &f) {
+    __shared__ double wm[2][NT / 64];
+    double d = 0.0, u = 0.0;
+    for (int i = threadIdx.x; i < f.leaves; i += NT) {
+        d = fmax(d, f.part[2 * i]);
+        u = fmax(u, f.part[2 * i + 1]);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        d = fmax(d, __shfl_xor(d, off));
+        u = fmax(u, __shfl_xor(u, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        wm[0][threadIdx.x >> 6] = d;
+        wm[1][threadIdx.x >> 6] = u;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < NT / 64; ++w) {
+            d = fmax(d, wm[0][w]);
+            u = fmax(u, wm[1][w]);
+        }
+        // non-negative doubles order like their bit patterns
+        f.out[0] = (unsigned long long)__double_as_longlong(d);
+        f.out[1] = (unsigned long long)__double_as_longlong(u);
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_norm_fold(NormFold f) { norm_fold_body(f); }
+
+__global__ __launch_bounds__(NT) void k_norm_fold_group(const NormFold *folds) { norm_fold_body(folds[blockIdx.x]); }
+
 __global__ void k_memop_group(const MemOp *ops, const int64_t *base, int n) {
     const int64_t total = base[n];
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
@@ -1579,6 +1612,7 @@ static int launch_pairs(const hps_op *op, bool fp32, const double *jump, const d
             else launch_level<double, false>(a, nb, level_lds(pn), st);
         }
         HPS_LAUNCHED();
+        return HPS_OK;
     };
     auto pair = [&](auto kern, int l, int mode) {
         const PairArgs a = pair_args(op, l, mode, jump, dirichlet, ws, fp32);
@@ -1586,27 +1620,28 @@ static int launch_pairs(const hps_op *op, bool fp32, const double *jump, const d
         const Panel &pn = mode == PAIR_UP ? (fp32 ? P.up32 : P.up) : (fp32 ? P.dn32 : P.dn);
         hipLaunchKernelGGL(kern, dim3((unsigned)(op->lv[l].nodes * pn.ntile)), dim3(NT), level_lds(pn), st, a);
         HPS_LAUNCHED();
+        return HPS_OK;
     };
     const int top_low = lowest_pair(op);
     {
         ProfScope ps_(&op->prof, fp32 ? KF_PAIR_UP32 : KF_PAIR_UP64, st);
-        if (L % 2 == 1) single(L - 1, true);
+        if (L % 2 == 1) TRY(single(L - 1, true));
         for (int l = top_low; l >= 2; l -= 2) {
-            if (fp32) pair(k_pair<float, PAIR_UP>, l, PAIR_UP);
-            else pair(k_pair<double, PAIR_UP>, l, PAIR_UP);
+            if (fp32) TRY(pair(k_pair<float, PAIR_UP>, l, PAIR_UP));
+            else TRY(pair(k_pair<double, PAIR_UP>, l, PAIR_UP));
         }
     }
     {
         ProfScope ps_(&op->prof, fp32 ? KF_PAIR_TOP32 : KF_PAIR_TOP64, st);
-        if (fp32) pair(k_pair<float, PAIR_TOP>, 0, PAIR_TOP);
-        else pair(k_pair<double, PAIR_TOP>, 0, PAIR_TOP);
+        if (fp32) TRY(pair(k_pair<float, PAIR_TOP>, 0, PAIR_TOP));
+        else TRY(pair(k_pair<double, PAIR_TOP>, 0, PAIR_TOP));
     }
     ProfScope ps_(&op->prof, fp32 ? KF_PAIR_DOWN32 : KF_PAIR_DOWN64, st);
     for (int l = 2; l <= top_low; l += 2) {
-        if (fp32) pair(k_pair<float, PAIR_DOWN>, l, PAIR_DOWN);
-        else pair(k_pair<double, PAIR_DOWN>, l, PAIR_DOWN);
+        if (fp32) TRY(pair(k_pair<float, PAIR_DOWN>, l, PAIR_DOWN));
+        else TRY(pair(k_pair<double, PAIR_DOWN>, l, PAIR_DOWN));
     }
-    if (L % 2 == 1) single(L - 1, false);
+    if (L % 2 == 1) TRY(single(L - 1, false));
     return HPS_OK;
 }
 
@@ -1959,6 +1994,20 @@ int launch_residual_group(const void *evals, const int *ebase, const void *jumps
                            reinterpret_cast<const JumpArgs *>(jumps), jbase, n);
         HPS_LAUNCHED();
     }
+    return HPS_OK;
+}
+
+int launch_norm_fold(const double *part, int leaves, double *out, hipStream_t st) {
+    NormFold f{part, reinterpret_cast<unsigned long long *>(out), leaves};
+    hipLaunchKernelGGL(k_norm_fold, dim3(1), dim3(NT), 0, st, f);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+int launch_norm_fold_group(const NormFold *folds, int n, hipStream_t st) {
+    if (n <= 0) return HPS_OK;
+    hipLaunchKernelGGL(k_norm_fold_group, dim3(n), dim3(NT), 0, st, folds);
+    HPS_LAUNCHED();
     return HPS_OK;
 }
 
