@@ -194,6 +194,19 @@ __device__ __forceinline__ void load_dmat(const double *src, double *dst, int n)
     for (int k = threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
 }
 
+// Row stride of a p x p differentiation matrix kept in LDS for tile derivatives: lanes of
+// a wave read one row each (one per interior column of the tile), and with stride p + 1
+// those rows fall in different banks instead of all in one
+__host__ __device__ constexpr int dmat_ld(int p) { return p + 1; }
+
+__device__ __forceinline__ void load_dmat_ld(const double *src, double *dst, int p) {
+    const int ld = dmat_ld(p);
+    for (int k = threadIdx.x; k < p * p; k += blockDim.x) {
+        const int r = k / p;
+        dst[r * ld + (k - r * p)] = src[k];
+    }
+}
+
 static inline unsigned nblk(int64_t n, int t = NT) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace hps

@@ -105,7 +105,7 @@ template <typename T, int DN, int UPM>
 __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned char *smem, double *red,
                                           double (*nred)[NT / 64]) {
     constexpr int VW = 16 / sizeof(T);
-    const int q = a.geo.q, p = a.geo.p, q2 = q * q, nb = 4 * q;
+    const int q = a.geo.q, p = a.geo.p, q2 = q * q, nb = 4 * q, ld = dmat_ld(p);
     const int li = a.leaf_ij[2 * leaf], lj = a.leaf_ij[2 * leaf + 1];
     const int64_t base = ((int64_t)lj * a.geo.n1 + li) * q2;
     const int64_t n_int = a.geo.n_int;
@@ -113,8 +113,8 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
     T *xs = cv.take<T>(a.xs_cap);
     T *part = cv.take<T>(a.part_cap);
     double *tile = cv.take<double>(p * p);
-    double *D = cv.take<double>(p * p);
-    double *D2 = cv.take<double>(p * p);
+    double *D = cv.take<double>(p * ld);
+    double *D2 = cv.take<double>(p * ld);
     double *luv = cv.take<double>(q2);
     double *fv = cv.take<double>(q2);
     constexpr bool stream_down = DN == DOWN_WRITE_U || DN == DOWN_STAGE || DN == DOWN_IR_ADD;
@@ -141,8 +141,8 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
     else if constexpr (stream_up)
         ps.start(reinterpret_cast<const T *>(a.ainv.data) + (int64_t)leaf * a.ainv.node_elems, a.ainv.rp, a.ainv.G,
                  a.ainv.S, a.ainv.node_elems == 0);
-    load_dmat(a.D, D, p * p);
-    if (need_L) load_dmat(a.D2, D2, p * p);
+    load_dmat_ld(a.D, D, p);
+    if (need_L) load_dmat_ld(a.D2, D2, p);
 
     // ---------------- down phase ----------------
     if constexpr (DN != DOWN_NONE) {
@@ -184,10 +184,10 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
                     for (int m = 0; m < p; ++m) {
                         const double xr = tile[bb * p + m];
                         const double yc = tile[m * p + aa];
-                        ux = fma(D[aa * p + m], xr, ux);
-                        uxx = fma(D2[aa * p + m], xr, uxx);
-                        uy = fma(D[bb * p + m], yc, uy);
-                        uyy = fma(D2[bb * p + m], yc, uyy);
+                        ux = fma(D[aa * ld + m], xr, ux);
+                        uxx = fma(D2[aa * ld + m], xr, uxx);
+                        uy = fma(D[bb * ld + m], yc, uy);
+                        uyy = fma(D2[bb * ld + m], yc, uyy);
                     }
                     const double u = tile[bb * p + aa];
                     // L u = cxx u_xx + cyy u_yy + cx u_x + cy u_y + c0 u (eq. 3 for L, c12 = 0)
@@ -269,7 +269,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
         __syncthreads();
         for (int k = threadIdx.x; k < nb; k += NT) {
             const int e = k / q, m = k % q;
-            const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * p);
+            const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * ld);
             double f = 0.0;
             if (e < 2) {
                 for (int c = 1; c <= q; ++c) f = fma(dr[c], tile[m * q + c - 1], f);
@@ -307,7 +307,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
     });
     for (int k = threadIdx.x; k < nb; k += NT) {
         const int e = k / q, m = k % q;
-        const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * p);
+        const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * ld);
         double h = 0.0;
         if (e < 2) {
             for (int c = 1; c <= q; ++c) h = fma(dr[c], wv[m * q + c - 1], h);
@@ -699,8 +699,8 @@ static void make_leaf_args(const hps_op *op, bool fp32, const LeafPhase &ph, Lea
     a.unew = ph.unew;
     a.fpart = op->ir_flux;
     const size_t es = fp32 ? 4 : 8;
-    const size_t pp = (size_t)op->p * op->p * 8, q2b = (size_t)op->q2 * 8;
-    lds = carve_bytes({(size_t)a.xs_cap * es, (size_t)a.part_cap * es, pp, pp, pp, q2b, q2b});
+    const size_t pp = (size_t)op->p * op->p * 8, pd = (size_t)op->p * dmat_ld(op->p) * 8, q2b = (size_t)op->q2 * 8;
+    lds = carve_bytes({(size_t)a.xs_cap * es, (size_t)a.part_cap * es, pp, pd, pd, q2b, q2b});
 }
 
 static void use_leaf_workspace(LeafArgs &a, const Workspace *ws) {

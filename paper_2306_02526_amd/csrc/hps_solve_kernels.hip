@@ -27,27 +27,6 @@ constexpr int UNR = 8;   // operator loads in flight in the streaming loop
 // fewer load registers, so that 8 waves per SIMD fit and the grid runs in one round.
 constexpr int PF_SMALL = 4;
 
-// L u at interior node k of the tile: cxx u_xx + cyy u_yy + cx u_x + cy u_y + c0 u (eq. 3
-// written for L, c12 = 0), derivatives along the tile row / column through the node.
-__device__ __forceinline__ double tile_L(const double *tile, const double *D, const double *D2,
-                                         int p, int q, const double *coef, int64_t n_int,
-                                         int64_t gidx, int k) {
-    const int a = k % q + 1;
-    const int b = k / q + 1;
-    double ux = 0, uxx = 0, uy = 0, uyy = 0;
-    for (int m = 0; m < p; ++m) {
-        const double xr = tile[b * p + m];
-        const double yc = tile[m * p + a];
-        ux = fma(D[a * p + m], xr, ux);
-        uxx = fma(D2[a * p + m], xr, uxx);
-        uy = fma(D[b * p + m], yc, uy);
-        uyy = fma(D2[b * p + m], yc, uyy);
-    }
-    const double u = tile[b * p + a];
-    return coef[gidx] * uxx + coef[n_int + gidx] * uyy + coef[2 * n_int + gidx] * ux +
-           coef[3 * n_int + gidx] * uy + coef[4 * n_int + gidx] * u;
-}
-
 __device__ __forceinline__ double gpoly(const GPoly &g, double u) {
     if (g.kind == 0) return 0.0;
     return g.g0 + u * (g.g1 + u * (g.g2 + u * g.g3));
@@ -823,20 +802,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(6, 8))) void
 // =======================================================================================
 // stage-1 evaluation (L u^n, F_1) and the refinement residual, from a canonical vector
 // =======================================================================================
-__device__ void tile_from_canonical(const LeafGeo &g, int li, int lj, const double *u,
-                                    double *tile) {
-    const int q = g.q, p = g.p, q2 = q * q;
-    const int64_t base = ((int64_t)lj * g.n1 + li) * q2;
-    for (int k = threadIdx.x; k < p * p; k += NT) tile[k] = 0.0;
-    __syncthreads();
-    for (int k = threadIdx.x; k < q2; k += NT) tile[(k / q + 1) * p + (k % q) + 1] = u[base + k];
-    for (int k = threadIdx.x; k < 4 * q; k += NT) {
-        const int e = k / q, m = k % q;
-        tile[edge_tile_pos(p, q, e, m)] = u[edge_index(g, li, lj, e, m)];
-    }
-    __syncthreads();
-}
-
 struct EvalArgs {
     LeafGeo geo;
     const double *u;
@@ -848,21 +813,51 @@ struct EvalArgs {
     double *r_int, *flux;
 };
 
-// leaf cl in canonical order (cl = j*n1 + i), one workgroup
+// leaf cl in canonical order (cl = j*n1 + i), one workgroup.  Every global load (D, D2,
+// the leaf's values, the first node's coefficients and right-hand side) is issued before
+// the one barrier.  The tile's corners are never read (no mixed derivative), so they are
+// not filled.
 __device__ __forceinline__ void eval_body(const EvalArgs &a, int cl, double *tile, double *D, double *D2) {
     const int li = cl % a.geo.n1, lj = cl / a.geo.n1;
-    const int q = a.geo.q, p = a.geo.p, q2 = q * q;
-    load_dmat(a.D, D, p * p);
-    load_dmat(a.D2, D2, p * p);
-    tile_from_canonical(a.geo, li, lj, a.u, tile);
+    const int q = a.geo.q, p = a.geo.p, q2 = q * q, ld = dmat_ld(p);
+    const int64_t n_int = a.geo.n_int;
     const int64_t base = (int64_t)cl * q2;
-    for (int k = threadIdx.x; k < q2; k += NT) {
+    load_dmat_ld(a.D, D, p);
+    load_dmat_ld(a.D2, D2, p);
+    for (int k = threadIdx.x; k < q2; k += NT) tile[(k / q + 1) * p + (k % q) + 1] = a.u[base + k];
+    for (int k = threadIdx.x; k < 4 * q; k += NT) {
+        const int e = k / q, m = k % q;
+        tile[edge_tile_pos(p, q, e, m)] = a.u[edge_index(a.geo, li, lj, e, m)];
+    }
+    const bool res = a.rhs != nullptr;
+    double cf[5] = {0, 0, 0, 0, 0}, rh = 0.0;
+    auto node_data = [&](int k) {
         const int64_t gi = base + k;
-        const double Lu = tile_L(tile, D, D2, p, q, a.coef, a.geo.n_int, gi, k);
-        const double u = tile[(k / q + 1) * p + (k % q) + 1];
-        if (a.rhs) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) cf[c] = a.coef[c * n_int + gi];
+        if (res) rh = a.rhs[gi];
+    };
+    if ((int)threadIdx.x < q2) node_data(threadIdx.x);
+    __syncthreads();
+    for (int k = threadIdx.x; k < q2; k += NT) {
+        if (k != (int)threadIdx.x) node_data(k);
+        const int ca = k % q + 1, cb = k / q + 1;
+        double ux = 0, uxx = 0, uy = 0, uyy = 0;
+        for (int m = 0; m < p; ++m) {
+            const double xr = tile[cb * p + m];
+            const double yc = tile[m * p + ca];
+            ux = fma(D[ca * ld + m], xr, ux);
+            uxx = fma(D2[ca * ld + m], xr, uxx);
+            uy = fma(D[cb * ld + m], yc, uy);
+            uyy = fma(D2[cb * ld + m], yc, uyy);
+        }
+        const double u = tile[cb * p + ca];
+        // L u = cxx u_xx + cyy u_yy + cx u_x + cy u_y + c0 u (eq. 3 for L, c12 = 0)
+        const double Lu = cf[0] * uxx + cf[1] * uyy + cf[2] * ux + cf[3] * uy + cf[4] * u;
+        const int64_t gi = base + k;
+        if (res) {
             // refinement residual of (I - gamma_dt L) u = rhs at interior nodes
-            a.r_int[gi] = a.rhs[gi] - (u - a.gamma_dt * Lu);
+            a.r_int[gi] = rh - (u - a.gamma_dt * Lu);
         } else if (a.Lu) {
             a.Lu[gi] = Lu;
         }
@@ -871,7 +866,7 @@ __device__ __forceinline__ void eval_body(const EvalArgs &a, int cl, double *til
         // coordinate-direction fluxes on the four leaf edges, [leaf][e][m]
         for (int k = threadIdx.x; k < 4 * q; k += NT) {
             const int e = k / q, m = k % q;
-            const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * p);
+            const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * ld);
             double f = 0.0;
             if (e < 2) {
                 for (int c = 0; c < p; ++c) f = fma(dr[c], tile[(m + 1) * p + c], f);
@@ -885,7 +880,7 @@ __device__ __forceinline__ void eval_body(const EvalArgs &a, int cl, double *til
 
 __global__ __launch_bounds__(NT) void k_eval(EvalArgs a) {
     __shared__ double tile[PMAX * PMAX];
-    __shared__ double D[PMAX * PMAX], D2[PMAX * PMAX];
+    __shared__ double D[PMAX * dmat_ld(PMAX)], D2[PMAX * dmat_ld(PMAX)];
     eval_body(a, blockIdx.x, tile, D, D2);
 }
 
@@ -946,7 +941,7 @@ __device__ __forceinline__ int group_entry(const int *base, int n, int w) {
 // problem e), then the interface jumps (thread -> interface node of problem e by jbase)
 __global__ __launch_bounds__(NT) void k_eval_group(const EvalArgs *ev, const int *ebase, int n) {
     __shared__ double tile[PMAX * PMAX];
-    __shared__ double D[PMAX * PMAX], D2[PMAX * PMAX];
+    __shared__ double D[PMAX * dmat_ld(PMAX)], D2[PMAX * dmat_ld(PMAX)];
     const int w = blockIdx.x;
     const int e = group_entry(ebase, n, w);
     eval_body(ev[e], w - ebase[e], tile, D, D2);
