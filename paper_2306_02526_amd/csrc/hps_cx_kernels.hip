@@ -82,8 +82,9 @@ __device__ __forceinline__ void leaf_cx_body(const LeafCxArgs &a, int leaf, unsi
     double *xs = cv.take<double>(a.xs_cap);
     double *part = cv.take<double>(a.part_cap);
     double *tile = cv.take<double>(2 * (size_t)pp);   // [part][p*p]
-    double *D = cv.take<double>(pp);
-    double *D2 = cv.take<double>(pp);
+    const int ld = dmat_ld(p);
+    double *D = cv.take<double>((size_t)p * ld);
+    double *D2 = cv.take<double>((size_t)p * ld);
     double *luv = cv.take<double>(2 * (size_t)q2);    // [part][q2]
     double *fv = cv.take<double>(2 * (size_t)q2);
     constexpr bool stream_down = DN == LD_WRITE_U || DN == LD_STAGE;
@@ -96,8 +97,8 @@ __device__ __forceinline__ void leaf_cx_body(const LeafCxArgs &a, int leaf, unsi
     else if constexpr (stream_up)
         ps.start(reinterpret_cast<const double *>(a.ainv.data) + (int64_t)leaf * a.ainv.node_elems, a.ainv.rp,
                  a.ainv.G, a.ainv.S, a.ainv.node_elems == 0);
-    load_dmat(a.D, D, pp);
-    if (need_L) load_dmat(a.D2, D2, pp);
+    load_dmat_ld(a.D, D, p);
+    if (need_L) load_dmat_ld(a.D2, D2, p);
 
     // ---------------- down phase ----------------
     if constexpr (DN != LD_NONE) {
@@ -144,10 +145,10 @@ __device__ __forceinline__ void leaf_cx_body(const LeafCxArgs &a, int leaf, unsi
                     for (int m = 0; m < p; ++m) {
                         const double xr = tc[bb * p + m];
                         const double yc = tc[m * p + aa];
-                        ux = fma(D[aa * p + m], xr, ux);
-                        uxx = fma(D2[aa * p + m], xr, uxx);
-                        uy = fma(D[bb * p + m], yc, uy);
-                        uyy = fma(D2[bb * p + m], yc, uyy);
+                        ux = fma(D[aa * ld + m], xr, ux);
+                        uxx = fma(D2[aa * ld + m], xr, uxx);
+                        uy = fma(D[bb * ld + m], yc, uy);
+                        uyy = fma(D2[bb * ld + m], yc, uyy);
                     }
                     d[c][0] = uxx; d[c][1] = uyy; d[c][2] = ux; d[c][3] = uy; d[c][4] = tc[bb * p + aa];
                 }
@@ -222,7 +223,7 @@ __device__ __forceinline__ void leaf_cx_body(const LeafCxArgs &a, int leaf, unsi
             const double *vals = tile + c * pp;
             for (int k = threadIdx.x; k < nb; k += NT) {
                 const int e = k / q, m = k % q;
-                const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * p);
+                const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * ld);
                 double f = 0.0;
                 if (e < 2) {
                     for (int cc = 1; cc <= q; ++cc) f = fma(dr[cc], vals[m * q + cc - 1], f);
@@ -266,7 +267,7 @@ __device__ __forceinline__ void leaf_cx_body(const LeafCxArgs &a, int leaf, unsi
     for (int k = threadIdx.x; k < nbl; k += NT) {
         const int c = k / nb, kk = k % nb;
         const int e = kk / q, m = kk % q;
-        const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * p);
+        const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * ld);
         const double *w = wv + c * q2;
         double h = 0.0;
         if (e < 2) {
@@ -323,8 +324,8 @@ int launch_leaf_cx(const hps_op *op, const LeafPhase &ph, hipStream_t st) {
     a.h_out = op->h_leaf;
     a.unew = ph.unew;
     a.fpart = op->ir_flux;
-    const size_t pp = (size_t)op->p * op->p * 8, q2b = (size_t)op->q2 * 8;
-    const size_t lds = carve_bytes({(size_t)a.xs_cap * 8, (size_t)a.part_cap * 8, 2 * pp, pp, pp, 2 * q2b, 2 * q2b});
+    const size_t pp = (size_t)op->p * op->p * 8, pd = (size_t)op->p * dmat_ld(op->p) * 8, q2b = (size_t)op->q2 * 8;
+    const size_t lds = carve_bytes({(size_t)a.xs_cap * 8, (size_t)a.part_cap * 8, 2 * pp, pd, pd, 2 * q2b, 2 * q2b});
     auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(op->nleaves), dim3(NT), lds, st, a); };
 #define HPS_LEAF_CX_CASE(DNV, UPV)                      \
     if (ph.down == DNV && ph.up == UPV) {               \

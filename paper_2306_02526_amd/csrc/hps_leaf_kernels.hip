@@ -369,8 +369,9 @@ __device__ __forceinline__ void leaf_sys_body(const LeafSysArgs &A, int leaf, un
     double *xs = cv.take<double>((size_t)NC * xcap);
     double *part = cv.take<double>((size_t)NC * pcap);
     double *tile = cv.take<double>((size_t)NC * pp);
-    double *D = cv.take<double>(pp);
-    double *D2 = cv.take<double>(pp);
+    const int ld = dmat_ld(p);
+    double *D = cv.take<double>((size_t)p * ld);
+    double *D2 = cv.take<double>((size_t)p * ld);
     double *luv = cv.take<double>((size_t)NC * q2);
     double *fv = cv.take<double>((size_t)NC * q2);
     constexpr bool stream_down = DN == DOWN_STAGE;
@@ -381,8 +382,8 @@ __device__ __forceinline__ void leaf_sys_body(const LeafSysArgs &A, int leaf, un
     else if constexpr (UPM == UP_STAGE)
         ps.start(reinterpret_cast<const double *>(a.ainv.data) + (int64_t)leaf * a.ainv.node_elems, a.ainv.rp,
                  a.ainv.G, a.ainv.S, a.ainv.node_elems == 0);
-    load_dmat(a.D, D, pp);
-    load_dmat(a.D2, D2, pp);
+    load_dmat_ld(a.D, D, p);
+    load_dmat_ld(a.D2, D2, p);
 
     // ---------------- down phase: the tiles of u_i and v_i ----------------
     for (int k = threadIdx.x; k < NC * pp; k += NT) tile[k] = 0.0;
@@ -438,10 +439,10 @@ __device__ __forceinline__ void leaf_sys_body(const LeafSysArgs &A, int leaf, un
                 for (int m = 0; m < p; ++m) {
                     const double xr = tc[bb * p + m];
                     const double yc = tc[m * p + aa];
-                    ux = fma(D[aa * p + m], xr, ux);
-                    uxx = fma(D2[aa * p + m], xr, uxx);
-                    uy = fma(D[bb * p + m], yc, uy);
-                    uyy = fma(D2[bb * p + m], yc, uyy);
+                    ux = fma(D[aa * ld + m], xr, ux);
+                    uxx = fma(D2[aa * ld + m], xr, uxx);
+                    uy = fma(D[bb * ld + m], yc, uy);
+                    uyy = fma(D2[bb * ld + m], yc, uyy);
                 }
                 val[c] = tc[bb * p + aa];
                 dx[c] = ux;
@@ -486,7 +487,7 @@ __device__ __forceinline__ void leaf_sys_body(const LeafSysArgs &A, int leaf, un
             const double *vals = tile + c * pp;
             for (int k = threadIdx.x; k < nb; k += NT) {
                 const int e = k / q, m = k % q;
-                const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * p);
+                const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * ld);
                 double f = 0.0;
                 if (e < 2) {
                     for (int cc = 1; cc <= q; ++cc) f = fma(dr[cc], vals[m * q + cc - 1], f);
@@ -534,7 +535,7 @@ __device__ __forceinline__ void leaf_sys_body(const LeafSysArgs &A, int leaf, un
         const double *wv = luv + c * q2;
         for (int k = threadIdx.x; k < nb; k += NT) {
             const int e = k / q, m = k % q;
-            const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * p);
+            const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * ld);
             double h = 0.0;
             if (e < 2) {
                 for (int cc = 1; cc <= q; ++cc) h = fma(dr[cc], wv[m * q + cc - 1], h);
@@ -821,8 +822,8 @@ int launch_leaf_sys(const hps_op *op, const LeafPhase &ph0, const LeafPhase &ph1
     size_t l0 = 0, l1 = 0;
     TRY(fill_leaf_args(op, ph0, &A.c[0], &l0, ws0));
     TRY(fill_leaf_args(op, ph1, &A.c[1], &l1, ws1));
-    const size_t pp = (size_t)op->p * op->p * 8, q2b = (size_t)op->q2 * 8;
-    const size_t lds = carve_bytes({2 * (size_t)A.c[0].xs_cap * 8, 2 * (size_t)A.c[0].part_cap * 8, 2 * pp, pp, pp,
+    const size_t pp = (size_t)op->p * op->p * 8, pd = (size_t)op->p * dmat_ld(op->p) * 8, q2b = (size_t)op->q2 * 8;
+    const size_t lds = carve_bytes({2 * (size_t)A.c[0].xs_cap * 8, 2 * (size_t)A.c[0].part_cap * 8, 2 * pp, pd, pd,
                                     2 * q2b, 2 * q2b});
     auto go = [&](auto kern) { hipLaunchKernelGGL(kern, dim3(op->nleaves), dim3(NT), lds, st, A); };
     if (ph0.down != ph1.down || ph0.up != ph1.up) {
