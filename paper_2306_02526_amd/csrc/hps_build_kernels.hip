@@ -292,7 +292,7 @@ __global__ __launch_bounds__(NT) void k_gj_pivot(double *W, int n, int k, unsign
     bi[threadIdx.x] = besti;
     __syncthreads();
     for (int off = NT / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) {
+        if ((int)threadIdx.x < off) {
             const double v2 = bv[threadIdx.x + off];
             const int i2 = bi[threadIdx.x + off];
             if (v2 > bv[threadIdx.x] || (v2 == bv[threadIdx.x] && i2 < bi[threadIdx.x])) {
