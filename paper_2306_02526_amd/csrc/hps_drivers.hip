@@ -267,7 +267,7 @@ void hps::step_phase(const ark_ctx *c, int k, double *u, const double *q_stages,
 }
 
 // FP32_IR stage solves inside the step: `fixed` > 0 runs that many corrections per stage
-// with no host involvement (stage k's pass j accumulates its norms into
+// with no host involvement (stage k's pass j writes its folded norms to
 // c->ir_stat[(k * IR_MAXIT + j) * 2]); fixed == 0 refines each stage on the host-checked
 // loop and redoes a stage that does not converge with the FP64 operators (rec: the
 // record of the step).
