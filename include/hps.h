@@ -59,10 +59,10 @@ extern "C" {
 
 /* hps_build flags */
 #define HPS_FP64     0   /* stored operators and their application in FP64.  With at
-                            least two tree levels, the level sweeps of a real operator
-                            without HPS_WIDE_TILES (FP64 or FP32_IR: FP32 copies for
-                            the FP32 passes) go through composite operators of level
-                            pairs built with it: the two levels'
+                            least two tree levels, the level sweeps of an operator
+                            without HPS_WIDE_TILES (FP64, complex, or FP32_IR: FP32
+                            copies for the FP32 passes) go through composite operators
+                            of level pairs built with it: the two levels'
                             products multiplied out once per node of the upper level,
                             one launch per pair and direction instead of one per
                             level, for about 1.4 times the level operators' memory.

@@ -139,10 +139,12 @@ static Panel pair_panel(int R, int C, int nodes, int target, int vw = 2) {
     return plan_panel(R, C, vw, nodes, rp_max, 0);
 }
 
-// Composites need one workgroup's input vector in LDS (no split-K), FP64 real per-node
-// operators and at least the root and one level below it.
+// Composites need one workgroup's input vector in LDS (no split-K), narrow level tiles
+// and at least the root and one level below it.  Complex operators qualify too: their
+// levels are the real embedding with two-component maps (the maps in hl are already
+// doubled), which the composites multiply out like any real level pair.
 bool hps::compose_eligible(const hps_op *op, const std::vector<HostLevel> &hl) {
-    if (op->ncomp != 1 || (op->flags & HPS_WIDE_TILES) || op->L < 2) return false;
+    if ((op->flags & HPS_WIDE_TILES) || op->L < 2) return false;
     // the top pair (0, 1), then (2, 3), (4, 5), ... while the lower level exists
     for (int l = 0; l + 1 < op->L; l += 2) {
         const HostLevel &t = hl[l], &c = hl[l + 1];

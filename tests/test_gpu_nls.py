@@ -60,10 +60,14 @@ def build(torch, og, co, gdt, flags=hps.HPS_FP64):
     return g, hps.hps_build_complex(g, re, im, gdt, flags)
 
 
-@pytest.mark.parametrize("n1,n2,p", [(1, 1, 8), (2, 2, 6), (4, 2, 9), (8, 8, 12), (16, 8, 10)],
-                         ids=["1x1_p8", "2x2_p6", "4x2_p9", "8x8_p12", "16x8_p10"])
-def test_complex_solve_matches_oracle(torch, n1, n2, p):
-    say(f"[complex] hps_solve {n1}x{n2} p={p}, varying complex coefficients")
+@pytest.mark.parametrize("compose", ["1", "0"], ids=["pairs", "levels"])
+@pytest.mark.parametrize("n1,n2,p", [(1, 1, 8), (2, 2, 6), (4, 2, 9), (8, 8, 12), (16, 8, 10), (8, 4, 7)],
+                         ids=["1x1_p8", "2x2_p6", "4x2_p9", "8x8_p12", "16x8_p10", "8x4_p7"])
+def test_complex_solve_matches_oracle(torch, monkeypatch, n1, n2, p, compose):
+    """Composite level pairs (the default; odd trees keep one single bottom level) and one
+    launch per level (HPS_COMPOSE=0) on the real embedding of the complex operator."""
+    monkeypatch.setenv("HPS_COMPOSE", compose)
+    say(f"[complex] hps_solve {n1}x{n2} p={p}, varying complex coefficients, compose={compose}")
     h = 1.0 / max(n1, n2)
     og = Grid(0, n1 * h, 0, n2 * h, n1, n2, p)
     x, y = og.coordinates()
@@ -89,7 +93,9 @@ def test_uniform_complex_operator_equals_per_node(torch):
     co = {k: re[k] + 1j * im[k] for k in re}
     _, full = build(torch, og, co, 1e-3)
     _, uni = build(torch, og, co, 1e-3, hps.HPS_UNIFORM_COEFFS)
-    assert uni.bytes()[1] * 8 < full.bytes()[1]
+    # one leaf and one node per level instead of 64 and 63 (the composite level pairs, one
+    # per pair, and the few large top-level nodes stay): 7.5x fewer operator bytes here
+    assert uni.bytes()[1] * 6 < full.bytes()[1]
     rng = np.random.default_rng(2)
     body = planes(torch, rng.standard_normal(og.n_int) + 1j * rng.standard_normal(og.n_int))
     a = hps.hps_solve_complex(full, body)
