@@ -770,6 +770,7 @@ static int build_impl(hps_op *op, const hps_coeffs *co, const hps_coeffs *co_im,
         TRY(dev_alloc(op, &op->ir_r3, std::max<int64_t>(op->n_iface, 1)));
         TRY(dev_alloc(op, &op->ir_norms, 2));
         TRY(dev_alloc(op, &op->ir_part, 2 * (int64_t)op->nleaves));
+        TRY(dev_alloc(op, &op->ir_ubc, 4 * (int64_t)op->q * op->nleaves));
     }
     HPS_HIP(hipStreamSynchronize(st));
     int hsing = 0;

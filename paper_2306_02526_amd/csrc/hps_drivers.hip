@@ -314,11 +314,33 @@ static int enqueue_step(ark_ctx *c, double *u, const double *q_stages, const dou
                 LeafPhase w;
                 w.down = LD_WRITE_U;
                 w.u_out = c->stage_u;
-                TRY(launch_leaf(op, true, w, st));
                 if (irs.fixed > 0) {
-                    for (int j = 0; j < irs.fixed; ++j)
-                        TRY(ir_pass(op, c->rhs, nullptr, c->stage_u, c->ir_stat + ((int64_t)k * IR_MAXIT + j) * 2, st));
+                    // the passes of ir_pass, each residual evaluated in the leaf kernel that
+                    // writes u (or adds the previous correction) and whose up phase starts
+                    // the next correction's FP32 solve: the same arithmetic in fewer launches
+                    w.res_rhs = c->rhs;
+                    w.up = LU_BODY;
+                    TRY(launch_leaf(op, true, w, st));
+                    for (int j = 0; j < irs.fixed; ++j) {
+                        if (op->n_iface) {
+                            ProfScope ps_(&op->prof, KF_RESIDUAL, st);
+                            TRY(launch_flux_jump(op, 1.0, op->ir_r3, st));
+                        }
+                        TRY(levels(op, true, op->n_iface ? op->ir_r3 : nullptr, nullptr, st));
+                        LeafPhase dn;
+                        dn.down = LD_IR_ADD;
+                        dn.u_out = c->stage_u;
+                        dn.norm_part = op->ir_part;
+                        if (j + 1 < irs.fixed) {
+                            dn.res_rhs = c->rhs;
+                            dn.up = LU_BODY;
+                        }
+                        TRY(launch_leaf(op, true, dn, st));
+                        TRY(launch_norm_fold(op->ir_part, (int)op->nleaves, c->ir_stat + ((int64_t)k * IR_MAXIT + j) * 2,
+                                             st));
+                    }
                 } else {
+                    TRY(launch_leaf(op, true, w, st));
                     TRY(ir_finish(op, c->rhs, fk, nullptr, c->stage_u, st, irs.rec));
                 }
                 ph.down = LD_EVAL;

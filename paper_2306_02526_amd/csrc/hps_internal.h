@@ -166,6 +166,7 @@ struct hps_op {
     double *ir_rhs = nullptr, *ir_r = nullptr, *ir_r3 = nullptr, *ir_du = nullptr, *ir_flux = nullptr;
     double *ir_norms = nullptr;            // [2] max|delta|, max|u| (as ordered bit patterns)
     double *ir_part = nullptr;             // [nleaves][2] per-leaf max|delta|, max|u| of a pass
+    double *ir_ubc = nullptr;              // [nleaves][4q] running boundary values of a refined solve
     int64_t operator_bytes = 0, total_bytes = 0;
     std::vector<void *> allocs;
     mutable hps::Profiler prof;
@@ -299,6 +300,10 @@ struct LeafPhase {
     double ca[8] = {0}, cf[8] = {0};
     double *rhs_copy = nullptr;
     double *unew = nullptr;                    // LU_UPDATE
+    // LD_WRITE_U / LD_IR_ADD with LU_BODY, FP32 operators: the up phase solves for the
+    // refinement residual of the u just written, rhs - (I - gamma dt L) u, evaluated in the
+    // same kernel (edge fluxes to op->ir_flux for the interface jumps)
+    const double *res_rhs = nullptr;
     double *norm_part = nullptr;               // LD_IR_ADD: per-leaf max|delta|, max|u| ([leaf][2];
                                                // null: the operator's ir_part), folded by
                                                // launch_norm_fold

@@ -48,6 +48,12 @@ __device__ __forceinline__ void reduce_rows(const T *part, int rows, int G, doub
 }
 
 enum { DOWN_NONE = 0, DOWN_WRITE_U = 1, DOWN_STAGE = 2, DOWN_IR_ADD = 3, DOWN_EVAL = 4 };
+// DOWN_WRITE_U / DOWN_IR_ADD followed by the refinement residual of the new u at the leaf's
+// interior nodes (into LDS, where the UP_BODY phase takes it as its right-hand side) and the
+// coordinate fluxes on its edges (for the interface jumps): the arithmetic of the separate
+// residual evaluation, with the edge values from the leaf's own running copy of its boundary
+// values (which equals u there bit for bit: both add up the same sweep outputs)
+enum { DOWN_WRITE_U_RES = 5, DOWN_IR_ADD_RES = 6 };
 enum { UP_NONE = 0, UP_BODY = 1, UP_STAGE = 2, UP_UPDATE = 3 };
 
 struct LeafArgs {
@@ -67,6 +73,11 @@ struct LeafArgs {
     const double *q_scale_ptr;   // device scalar replacing q_scale when set
     GPoly g;
     double *norm_part;           // DOWN_IR_ADD: this leaf's max|delta|, max|u| at [2 leaf], [2 leaf + 1]
+    // DOWN_*_RES: the right-hand side of the refined system, gamma dt, the leaf's running
+    // boundary values [leaf][4q] and the edge fluxes (canonical leaf order) [leaf][4q]
+    const double *res_rhs;
+    double gamma_dt;
+    double *ubc, *res_flux;
     // up phase
     PanelView ainv;
     const double *body;          // UP_BODY
@@ -105,6 +116,8 @@ template <typename T, int DN, int UPM>
 __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned char *smem, double *red,
                                           double (*nred)[NT / 64]) {
     constexpr int VW = 16 / sizeof(T);
+    constexpr bool res = DN == DOWN_WRITE_U_RES || DN == DOWN_IR_ADD_RES;
+    constexpr int DB = DN == DOWN_WRITE_U_RES ? DOWN_WRITE_U : DN == DOWN_IR_ADD_RES ? DOWN_IR_ADD : DN;
     const int q = a.geo.q, p = a.geo.p, q2 = q * q, nb = 4 * q, ld = dmat_ld(p);
     const int li = a.leaf_ij[2 * leaf], lj = a.leaf_ij[2 * leaf + 1];
     const int64_t base = ((int64_t)lj * a.geo.n1 + li) * q2;
@@ -117,12 +130,12 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
     double *D2 = cv.take<double>(p * ld);
     double *luv = cv.take<double>(q2);
     double *fv = cv.take<double>(q2);
-    constexpr bool stream_down = DN == DOWN_WRITE_U || DN == DOWN_STAGE || DN == DOWN_IR_ADD;
+    constexpr bool stream_down = DB == DOWN_WRITE_U || DB == DOWN_STAGE || DB == DOWN_IR_ADD;
     constexpr bool stream_up = UPM == UP_BODY || UPM == UP_STAGE;
-    constexpr bool need_L = DN == DOWN_STAGE || DN == DOWN_EVAL;
+    constexpr bool need_L = DB == DOWN_STAGE || DB == DOWN_EVAL;
     // the older stages' part of the next right-hand side (or of the update), loaded while the
     // down phase gathers its own inputs instead of after it
-    constexpr bool hoist = (UPM == UP_STAGE || UPM == UP_UPDATE) && DN != DOWN_NONE;
+    constexpr bool hoist = (UPM == UP_STAGE || UPM == UP_UPDATE) && DB != DOWN_NONE;
     const int last_old = UPM == UP_STAGE ? a.nprev - 1 : a.nprev;
     double older[HOIST];
     auto load_older = [&]() {
@@ -142,10 +155,10 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
         ps.start(reinterpret_cast<const T *>(a.ainv.data) + (int64_t)leaf * a.ainv.node_elems, a.ainv.rp, a.ainv.G,
                  a.ainv.S, a.ainv.node_elems == 0);
     load_dmat_ld(a.D, D, p);
-    if (need_L) load_dmat_ld(a.D2, D2, p);
+    if (need_L || res) load_dmat_ld(a.D2, D2, p);
 
     // ---------------- down phase ----------------
-    if constexpr (DN != DOWN_NONE) {
+    if constexpr (DB != DOWN_NONE) {
         // particular solution w of this leaf, staged in LDS before the stream is consumed
         if (stream_down)
             for (int k = threadIdx.x; k < q2; k += NT) fv[k] = a.w_in[(int64_t)leaf * q2 + k];
@@ -201,7 +214,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
                     a.F_out[base + k] = F;
                 }
             }
-        } else if constexpr (DN == DOWN_WRITE_U || DN == DOWN_IR_ADD) {
+        } else if constexpr (DB == DOWN_WRITE_U || DB == DOWN_IR_ADD) {
             double dmax = 0.0, umax = 0.0;
             const double *ubl = a.ub + (int64_t)leaf * nb;
             for (int k = threadIdx.x; k < q2 + nb; k += NT) {
@@ -218,18 +231,26 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
                     own = (e == 0 || e == 2) || (e == 1 && li == a.geo.n1 - 1) || (e == 3 && lj == a.geo.n2 - 1);
                     gi = edge_index(a.geo, li, lj, e, m);
                     v = ubl[k - q2];
+                    if constexpr (res) {
+                        // every edge node, owned or not: the leaf's running boundary value
+                        double *bc = a.ubc + (int64_t)leaf * nb + (k - q2);
+                        const double nbv = DB == DOWN_WRITE_U ? v : *bc + v;
+                        *bc = nbv;
+                        tile[edge_tile_pos(p, q, e, m)] = nbv;
+                    }
                 }
                 if (!own) continue;
-                if (DN == DOWN_WRITE_U) {
+                if (DB == DOWN_WRITE_U) {
                     a.u_out[gi] = v;
                 } else {
                     const double nu = a.u_out[gi] + v;
                     a.u_out[gi] = nu;
                     dmax = fmax(dmax, fabs(v));
                     umax = fmax(umax, fabs(nu));
+                    if (res && k < q2) tile[(k / q + 1) * p + (k % q) + 1] = nu;
                 }
             }
-            if (DN == DOWN_IR_ADD) {
+            if (DB == DOWN_IR_ADD) {
                 for (int off = 32; off > 0; off >>= 1) {
                     dmax = fmax(dmax, __shfl_xor(dmax, off));
                     umax = fmax(umax, __shfl_xor(umax, off));
@@ -253,6 +274,44 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
             }
         }
         __syncthreads();
+        if constexpr (res) {
+            // refinement residual rhs - (u - gamma dt L u) of the new u (into luv, the up
+            // phase's right-hand side) and the edge fluxes, as the residual evaluation does
+            for (int k = threadIdx.x; k < q2; k += NT) {
+                const int64_t gi = base + k;
+                double cf[5];
+#pragma unroll
+                for (int c = 0; c < 5; ++c) cf[c] = a.coef[c * n_int + gi];
+                const double rh = a.res_rhs[gi];
+                const int ca = k % q + 1, cb = k / q + 1;
+                double ux = 0, uxx = 0, uy = 0, uyy = 0;
+                for (int m = 0; m < p; ++m) {
+                    const double xr = tile[cb * p + m];
+                    const double yc = tile[m * p + ca];
+                    ux = fma(D[ca * ld + m], xr, ux);
+                    uxx = fma(D2[ca * ld + m], xr, uxx);
+                    uy = fma(D[cb * ld + m], yc, uy);
+                    uyy = fma(D2[cb * ld + m], yc, uyy);
+                }
+                const double u = tile[cb * p + ca];
+                // the residual evaluation's rounding (explicit fused multiply-adds)
+                const double Lu = fma(cf[4], u, fma(cf[3], uy, fma(cf[2], ux, fma(cf[1], uyy, cf[0] * uxx))));
+                luv[k] = rh - fma(-a.gamma_dt, Lu, u);
+            }
+            const int64_t cl = (int64_t)lj * a.geo.n1 + li;
+            for (int k = threadIdx.x; k < nb; k += NT) {
+                const int e = k / q, m = k % q;
+                const double *dr = D + ((e == 0 || e == 2) ? 0 : (p - 1) * ld);
+                double f = 0.0;
+                if (e < 2) {
+                    for (int c = 0; c < p; ++c) f = fma(dr[c], tile[(m + 1) * p + c], f);
+                } else {
+                    for (int c = 0; c < p; ++c) f = fma(dr[c], tile[c * p + m + 1], f);
+                }
+                a.res_flux[cl * nb + k] = f;
+            }
+            __syncthreads();
+        }
     }
 
     // ---------------- up phase ----------------
@@ -285,7 +344,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
         double r = 0.0;
         if (k < q2) {
             if (UPM == UP_BODY) {
-                r = a.body[base + k];
+                r = res ? luv[k] : a.body[base + k];
             } else {
                 const int last = a.nprev - 1;   // newest stage, held in LDS
                 r = (hoist && i < HOIST) ? older[i] : older_stages(a, base, k, last);
@@ -685,6 +744,10 @@ static void make_leaf_args(const hps_op *op, bool fp32, const LeafPhase &ph, Lea
     a.q_scale_ptr = ph.q_scale_ptr;
     a.g = ph.g;
     a.norm_part = ph.norm_part ? ph.norm_part : op->ir_part;
+    a.res_rhs = ph.res_rhs;
+    a.gamma_dt = op->gamma_dt;
+    a.ubc = op->ir_ubc;
+    a.res_flux = op->ir_flux;
     a.body = ph.body;
     a.un = ph.un;
     a.Lu_in = ph.Lu_in;
@@ -735,6 +798,12 @@ int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st
     HPS_LEAF_CASE(DOWN_WRITE_U, UP_NONE)
     HPS_LEAF_CASE(DOWN_IR_ADD, UP_NONE)
 #undef HPS_LEAF_CASE
+    if (ph.res_rhs && fp32 && ph.up == LU_BODY && (ph.down == LD_WRITE_U || ph.down == LD_IR_ADD)) {
+        if (ph.down == LD_WRITE_U) go(k_leaf<float, DOWN_WRITE_U_RES, UP_BODY>);
+        else go(k_leaf<float, DOWN_IR_ADD_RES, UP_BODY>);
+        HPS_LAUNCHED();
+        return HPS_OK;
+    }
     hps_set_error("internal: unsupported leaf phase combination (%d, %d)", ph.down, ph.up);
     return HPS_EINVAL;
 }
