@@ -194,6 +194,14 @@ __device__ __forceinline__ void load_dmat(const double *src, double *dst, int n)
     for (int k = threadIdx.x; k < n; k += blockDim.x) dst[k] = src[k];
 }
 
+// L u = cxx u_xx + cyy u_yy + cx u_x + cy u_y + c0 u at one node (eq. 3 for L, c12 = 0), the
+// coefficients c[0..4] in that order, as explicit fused multiply-adds: every kernel that
+// evaluates L u (stage vectors, refinement residuals) rounds it the same way
+__device__ __forceinline__ double apply_L_point(const double *c, double uxx, double uyy, double ux, double uy,
+                                                double u) {
+    return fma(c[4], u, fma(c[3], uy, fma(c[2], ux, fma(c[1], uyy, c[0] * uxx))));
+}
+
 // Row stride of a p x p differentiation matrix kept in LDS for tile derivatives: lanes of
 // a wave read one row each (one per interior column of the tile), and with stride p + 1
 // those rows fall in different banks instead of all in one

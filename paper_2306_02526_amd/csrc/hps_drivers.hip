@@ -308,6 +308,7 @@ static int enqueue_step(ark_ctx *c, double *u, const double *q_stages, const dou
         if (k > 0) TRY(levels(op, ir, nullptr, fk, st));
         LeafPhase ph;
         step_phase(c, k, u, q_stages, q_space, c->qt_dev, ph);
+        int fold_last = -1;   // a fused last correction: its norms are folded after the launch
         if (ir) {
             if (k > 0) {
                 // FP32 stage solve, refined in FP64, then L u_i and F_i from the refined u_i
@@ -317,7 +318,9 @@ static int enqueue_step(ark_ctx *c, double *u, const double *q_stages, const dou
                 if (irs.fixed > 0) {
                     // the passes of ir_pass, each residual evaluated in the leaf kernel that
                     // writes u (or adds the previous correction) and whose up phase starts
-                    // the next correction's FP32 solve: the same arithmetic in fewer launches
+                    // the next correction's FP32 solve, the last correction added in the
+                    // kernel that evaluates L u_i, F_i and opens the next stage: the same
+                    // arithmetic in fewer launches
                     w.res_rhs = c->rhs;
                     w.up = LU_BODY;
                     TRY(launch_leaf(op, true, w, st));
@@ -327,28 +330,36 @@ static int enqueue_step(ark_ctx *c, double *u, const double *q_stages, const dou
                             TRY(launch_flux_jump(op, 1.0, op->ir_r3, st));
                         }
                         TRY(levels(op, true, op->n_iface ? op->ir_r3 : nullptr, nullptr, st));
+                        if (j + 1 == irs.fixed) {
+                            fold_last = j;
+                            break;
+                        }
                         LeafPhase dn;
                         dn.down = LD_IR_ADD;
                         dn.u_out = c->stage_u;
                         dn.norm_part = op->ir_part;
-                        if (j + 1 < irs.fixed) {
-                            dn.res_rhs = c->rhs;
-                            dn.up = LU_BODY;
-                        }
+                        dn.res_rhs = c->rhs;
+                        dn.up = LU_BODY;
                         TRY(launch_leaf(op, true, dn, st));
                         TRY(launch_norm_fold(op->ir_part, (int)op->nleaves, c->ir_stat + ((int64_t)k * IR_MAXIT + j) * 2,
                                              st));
                     }
+                    ph.down = LD_IR_ADD;
+                    ph.ir_eval = true;
+                    ph.u_out = c->stage_u;
+                    ph.norm_part = op->ir_part;
                 } else {
                     TRY(launch_leaf(op, true, w, st));
                     TRY(ir_finish(op, c->rhs, fk, nullptr, c->stage_u, st, irs.rec));
+                    ph.down = LD_EVAL;
+                    ph.u_eval = c->stage_u;
                 }
-                ph.down = LD_EVAL;
-                ph.u_eval = c->stage_u;
             }
             if (k + 1 < s) ph.rhs_copy = c->rhs;
         }
         TRY(launch_leaf(op, ir, ph, st));
+        if (fold_last >= 0)
+            TRY(launch_norm_fold(op->ir_part, (int)op->nleaves, c->ir_stat + ((int64_t)k * IR_MAXIT + fold_last) * 2, st));
     }
     const double *fend = f_stages ? f_stages + (int64_t)s * op->n_bdry : nullptr;
     TRY(launch_interface_lines(op, u, fend, st));

@@ -304,6 +304,9 @@ struct LeafPhase {
     // refinement residual of the u just written, rhs - (I - gamma dt L) u, evaluated in the
     // same kernel (edge fluxes to op->ir_flux for the interface jumps)
     const double *res_rhs = nullptr;
+    // LD_IR_ADD with LU_STAGE / LU_UPDATE, FP32 operators: after adding the correction, L u_i
+    // and F_i of the corrected u (LD_EVAL's outputs) in the same kernel
+    bool ir_eval = false;
     double *norm_part = nullptr;               // LD_IR_ADD: per-leaf max|delta|, max|u| ([leaf][2];
                                                // null: the operator's ir_part), folded by
                                                // launch_norm_fold

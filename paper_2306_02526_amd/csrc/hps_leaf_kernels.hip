@@ -54,6 +54,9 @@ enum { DOWN_NONE = 0, DOWN_WRITE_U = 1, DOWN_STAGE = 2, DOWN_IR_ADD = 3, DOWN_EV
 // residual evaluation, with the edge values from the leaf's own running copy of its boundary
 // values (which equals u there bit for bit: both add up the same sweep outputs)
 enum { DOWN_WRITE_U_RES = 5, DOWN_IR_ADD_RES = 6 };
+// DOWN_IR_ADD followed by DOWN_EVAL's evaluation of L u_i and F_i on the corrected tile (the
+// stage's last refinement pass fused with the phase that closes the stage)
+enum { DOWN_IR_ADD_EVAL = 7 };
 enum { UP_NONE = 0, UP_BODY = 1, UP_STAGE = 2, UP_UPDATE = 3 };
 
 struct LeafArgs {
@@ -117,7 +120,10 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
                                           double (*nred)[NT / 64]) {
     constexpr int VW = 16 / sizeof(T);
     constexpr bool res = DN == DOWN_WRITE_U_RES || DN == DOWN_IR_ADD_RES;
-    constexpr int DB = DN == DOWN_WRITE_U_RES ? DOWN_WRITE_U : DN == DOWN_IR_ADD_RES ? DOWN_IR_ADD : DN;
+    constexpr bool eval_after = DN == DOWN_IR_ADD_EVAL;
+    constexpr bool track = res || eval_after;   // running boundary copy, tile of the new u
+    constexpr int DB = DN == DOWN_WRITE_U_RES ? DOWN_WRITE_U
+                       : (DN == DOWN_IR_ADD_RES || DN == DOWN_IR_ADD_EVAL) ? DOWN_IR_ADD : DN;
     const int q = a.geo.q, p = a.geo.p, q2 = q * q, nb = 4 * q, ld = dmat_ld(p);
     const int li = a.leaf_ij[2 * leaf], lj = a.leaf_ij[2 * leaf + 1];
     const int64_t base = ((int64_t)lj * a.geo.n1 + li) * q2;
@@ -155,7 +161,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
         ps.start(reinterpret_cast<const T *>(a.ainv.data) + (int64_t)leaf * a.ainv.node_elems, a.ainv.rp, a.ainv.G,
                  a.ainv.S, a.ainv.node_elems == 0);
     load_dmat_ld(a.D, D, p);
-    if (need_L || res) load_dmat_ld(a.D2, D2, p);
+    if (need_L || track) load_dmat_ld(a.D2, D2, p);
 
     // ---------------- down phase ----------------
     if constexpr (DB != DOWN_NONE) {
@@ -188,32 +194,34 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
                 tile[edge_tile_pos(p, q, k / q, k % q)] = a.u_eval[edge_index(a.geo, li, lj, k / q, k % q)];
             __syncthreads();
         }
-        if constexpr (need_L) {
+        // L u_i and F_i = q + g(u_i) at the interior nodes from the tile (eq. 9)
+        auto eval_stage = [&]() {
             const double qs = a.q_scale_ptr ? *a.q_scale_ptr : a.q_scale;
             for (int k = threadIdx.x; k < q2; k += NT) {
-                {
-                    const int aa = k % q + 1, bb = k / q + 1;
-                    double ux = 0, uxx = 0, uy = 0, uyy = 0;
-                    for (int m = 0; m < p; ++m) {
-                        const double xr = tile[bb * p + m];
-                        const double yc = tile[m * p + aa];
-                        ux = fma(D[aa * ld + m], xr, ux);
-                        uxx = fma(D2[aa * ld + m], xr, uxx);
-                        uy = fma(D[bb * ld + m], yc, uy);
-                        uyy = fma(D2[bb * ld + m], yc, uyy);
-                    }
-                    const double u = tile[bb * p + aa];
-                    // L u = cxx u_xx + cyy u_yy + cx u_x + cy u_y + c0 u (eq. 3 for L, c12 = 0)
-                    const double *cf = a.coef + base + k;
-                    const double Lu = cf[0] * uxx + cf[n_int] * uyy + cf[2 * n_int] * ux + cf[3 * n_int] * uy +
-                                      cf[4 * n_int] * u;
-                    const double F = (a.q_src ? qs * a.q_src[base + k] : 0.0) + poly_g(a.g, u);
-                    luv[k] = Lu;
-                    fv[k] = F;
-                    a.Lu_out[base + k] = Lu;
-                    a.F_out[base + k] = F;
+                const int aa = k % q + 1, bb = k / q + 1;
+                double ux = 0, uxx = 0, uy = 0, uyy = 0;
+                for (int m = 0; m < p; ++m) {
+                    const double xr = tile[bb * p + m];
+                    const double yc = tile[m * p + aa];
+                    ux = fma(D[aa * ld + m], xr, ux);
+                    uxx = fma(D2[aa * ld + m], xr, uxx);
+                    uy = fma(D[bb * ld + m], yc, uy);
+                    uyy = fma(D2[bb * ld + m], yc, uyy);
                 }
+                const double u = tile[bb * p + aa];
+                double cf[5];
+#pragma unroll
+                for (int c = 0; c < 5; ++c) cf[c] = a.coef[c * n_int + base + k];
+                const double Lu = apply_L_point(cf, uxx, uyy, ux, uy, u);
+                const double F = (a.q_src ? qs * a.q_src[base + k] : 0.0) + poly_g(a.g, u);
+                luv[k] = Lu;
+                fv[k] = F;
+                a.Lu_out[base + k] = Lu;
+                a.F_out[base + k] = F;
             }
+        };
+        if constexpr (need_L) {
+            eval_stage();
         } else if constexpr (DB == DOWN_WRITE_U || DB == DOWN_IR_ADD) {
             double dmax = 0.0, umax = 0.0;
             const double *ubl = a.ub + (int64_t)leaf * nb;
@@ -231,7 +239,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
                     own = (e == 0 || e == 2) || (e == 1 && li == a.geo.n1 - 1) || (e == 3 && lj == a.geo.n2 - 1);
                     gi = edge_index(a.geo, li, lj, e, m);
                     v = ubl[k - q2];
-                    if constexpr (res) {
+                    if constexpr (track) {
                         // every edge node, owned or not: the leaf's running boundary value
                         double *bc = a.ubc + (int64_t)leaf * nb + (k - q2);
                         const double nbv = DB == DOWN_WRITE_U ? v : *bc + v;
@@ -247,7 +255,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
                     a.u_out[gi] = nu;
                     dmax = fmax(dmax, fabs(v));
                     umax = fmax(umax, fabs(nu));
-                    if (res && k < q2) tile[(k / q + 1) * p + (k % q) + 1] = nu;
+                    if (track && k < q2) tile[(k / q + 1) * p + (k % q) + 1] = nu;
                 }
             }
             if (DB == DOWN_IR_ADD) {
@@ -274,6 +282,10 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
             }
         }
         __syncthreads();
+        if constexpr (eval_after) {
+            eval_stage();
+            __syncthreads();
+        }
         if constexpr (res) {
             // refinement residual rhs - (u - gamma dt L u) of the new u (into luv, the up
             // phase's right-hand side) and the edge fluxes, as the residual evaluation does
@@ -294,8 +306,7 @@ __device__ __forceinline__ void leaf_body(const LeafArgs &a, int leaf, unsigned 
                     uyy = fma(D2[cb * ld + m], yc, uyy);
                 }
                 const double u = tile[cb * p + ca];
-                // the residual evaluation's rounding (explicit fused multiply-adds)
-                const double Lu = fma(cf[4], u, fma(cf[3], uy, fma(cf[2], ux, fma(cf[1], uyy, cf[0] * uxx))));
+                const double Lu = apply_L_point(cf, uxx, uyy, ux, uy, u);
                 luv[k] = rh - fma(-a.gamma_dt, Lu, u);
             }
             const int64_t cl = (int64_t)lj * a.geo.n1 + li;
@@ -798,6 +809,12 @@ int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st
     HPS_LEAF_CASE(DOWN_WRITE_U, UP_NONE)
     HPS_LEAF_CASE(DOWN_IR_ADD, UP_NONE)
 #undef HPS_LEAF_CASE
+    if (ph.ir_eval && fp32 && ph.down == LD_IR_ADD && (ph.up == LU_STAGE || ph.up == LU_UPDATE)) {
+        if (ph.up == LU_STAGE) go(k_leaf<float, DOWN_IR_ADD_EVAL, UP_STAGE>);
+        else go(k_leaf<float, DOWN_IR_ADD_EVAL, UP_UPDATE>);
+        HPS_LAUNCHED();
+        return HPS_OK;
+    }
     if (ph.res_rhs && fp32 && ph.up == LU_BODY && (ph.down == LD_WRITE_U || ph.down == LD_IR_ADD)) {
         if (ph.down == LD_WRITE_U) go(k_leaf<float, DOWN_WRITE_U_RES, UP_BODY>);
         else go(k_leaf<float, DOWN_IR_ADD_RES, UP_BODY>);

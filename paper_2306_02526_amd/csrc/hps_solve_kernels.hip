@@ -852,10 +852,7 @@ __device__ __forceinline__ void eval_body(const EvalArgs &a, int cl, double *til
             uyy = fma(D2[cb * ld + m], yc, uyy);
         }
         const double u = tile[cb * p + ca];
-        // L u = cxx u_xx + cyy u_yy + cx u_x + cy u_y + c0 u (eq. 3 for L, c12 = 0), with
-        // explicit fused multiply-adds: the FP32 leaf kernels evaluate the same residual and
-        // must round it the same way
-        const double Lu = fma(cf[4], u, fma(cf[3], uy, fma(cf[2], ux, fma(cf[1], uyy, cf[0] * uxx))));
+        const double Lu = apply_L_point(cf, uxx, uyy, ux, uy, u);
         const int64_t gi = base + k;
         if (res) {
             // refinement residual of (I - gamma_dt L) u = rhs at interior nodes
