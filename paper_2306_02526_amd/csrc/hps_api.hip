@@ -1010,6 +1010,7 @@ int64_t hps::workspace_layout(const hps_op *op, char *base, Workspace *w, int64_
         ws.ir_r = (double *)take(8 * op->n_int);
         ws.ir_r3 = (double *)take(8 * std::max<int64_t>(op->n_iface, 1));
         ws.ir_part = (double *)take(8 * 2 * nl);
+        ws.ir_ubc = (double *)take(8 * nl * nb4);
     }
     ws.lv.resize(op->L);
     for (int l = 0; l < op->L; ++l) {

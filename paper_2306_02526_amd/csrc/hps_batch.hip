@@ -503,7 +503,7 @@ int build_plan_ir(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, co
             size_t lds = 0;
             TRY(fill_leaf_args(ctx[b]->op, ph, recs.data() + rs * i, &lds, ws[b], true));
             L.lds = std::max(L.lds, lds);
-            L.down = ph.down;
+            L.down = leaf_kernel_mode(ph, true);
             L.up = ph.up;
             base[i + 1] = base[i] + ctx[b]->op->nleaves;
         }
@@ -618,7 +618,8 @@ int build_plan_ir(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, co
         }
         return HPS_OK;
     };
-    auto residual = [&](const std::vector<int> &probs) {
+    // jumps_only: the leaf kernels evaluated the interior residual and the edge fluxes
+    auto residual = [&](const std::vector<int> &probs, bool jumps_only) {
         GroupPlan::Launch L{};
         L.kind = 10;
         const size_t es = eval_record_size(), js = jump_record_size();
@@ -630,6 +631,7 @@ int build_plan_ir(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, co
             residual_records(ctx[b]->op, ctx[b]->stage_u, ctx[b]->rhs, r_of(b), r3_of(b), flux_of(b),
                              ev.data() + es * i, jp.data() + js * i, &leaves, &iface);
             if (!r3_of(b)) iface = 0;
+            if (jumps_only) leaves = 0;
             eb[i + 1] = eb[i] + leaves;
             jb[i + 1] = jb[i] + iface;
         }
@@ -659,52 +661,71 @@ int build_plan_ir(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, co
         L.words = ob.back();
         P->seq.push_back(L);
     }
+    // per stage: the FP32 sweep; the leaf kernel that writes u, evaluates the refinement
+    // residual and starts the first correction's FP32 solve; per correction the interface
+    // jumps, the FP32 sweep, and the leaf kernel that adds the correction and either starts
+    // the next correction (residual, FP32 solve) or, for the problem's last correction,
+    // evaluates L u_i, F_i and opens the next stage; the norm folds.  The passes of the
+    // single-problem replayed step, kernel for kernel.
+    auto fold = [&](const std::vector<int> &probs, int k, int j) {
+        std::vector<NormFold> folds;
+        for (int b : probs)
+            folds.push_back(NormFold{part_of(b),
+                                     reinterpret_cast<unsigned long long *>(ctx[b]->ir_stat +
+                                                                            ((int64_t)k * IR_MAXIT + j) * 2),
+                                     (int)ctx[b]->op->nleaves});
+        GroupPlan::Launch L{};
+        L.kind = 11;
+        L.a = T.put(folds.data(), sizeof(NormFold) * folds.size());
+        L.cnt = (int)folds.size();
+        P->seq.push_back(L);
+    };
+    auto stage_phase = [&](int b, int k, LeafPhase &ph) {
+        step_phase(ctx[b], k, u[b], q_stages ? q_stages[b] : nullptr, q_space ? q_space[b] : nullptr, P->qt + 8 * b,
+                   ph);
+        if (k + 1 < s) ph.rhs_copy = ctx[b]->rhs;
+    };
     for (int k = 0; k < s; ++k) {
-        if (k > 0) {
-            TRY(sweep(all, false));
-            TRY(leaf(all, [&](int b, LeafPhase &ph) {
-                ph.down = LD_WRITE_U;
-                ph.u_out = ctx[b]->stage_u;
-            }));
-            int kmax = 0;
-            for (int b = 0; b < n; ++b) kmax = std::max(kmax, ctx[b]->ir_passes);
-            for (int j = 0; j < kmax; ++j) {
-                std::vector<int> probs;
-                for (int b = 0; b < n; ++b)
-                    if (ctx[b]->ir_passes > j) probs.push_back(b);
-                residual(probs);
-                TRY(leaf(probs, [&](int b, LeafPhase &ph) {
-                    ph.up = LU_BODY;
-                    ph.body = r_of(b);
-                }));
-                TRY(sweep(probs, true));
-                TRY(leaf(probs, [&](int b, LeafPhase &ph) {
+        if (k == 0) {
+            TRY(leaf(all, [&](int b, LeafPhase &ph) { stage_phase(b, 0, ph); }));
+            continue;
+        }
+        TRY(sweep(all, false));
+        TRY(leaf(all, [&](int b, LeafPhase &ph) {
+            ph.down = LD_WRITE_U;
+            ph.u_out = ctx[b]->stage_u;
+            ph.res_rhs = ctx[b]->rhs;
+            ph.up = LU_BODY;
+        }));
+        int kmax = 0;
+        for (int b = 0; b < n; ++b) kmax = std::max(kmax, ctx[b]->ir_passes);
+        for (int j = 0; j < kmax; ++j) {
+            std::vector<int> probs, more, last;
+            for (int b = 0; b < n; ++b)
+                if (ctx[b]->ir_passes > j) {
+                    probs.push_back(b);
+                    (ctx[b]->ir_passes > j + 1 ? more : last).push_back(b);
+                }
+            residual(probs, true);
+            TRY(sweep(probs, true));
+            if (!more.empty())
+                TRY(leaf(more, [&](int b, LeafPhase &ph) {
                     ph.down = LD_IR_ADD;
                     ph.u_out = ctx[b]->stage_u;
                     ph.norm_part = part_of(b);
+                    ph.res_rhs = ctx[b]->rhs;
+                    ph.up = LU_BODY;
                 }));
-                std::vector<NormFold> folds;
-                for (int b : probs)
-                    folds.push_back(NormFold{part_of(b),
-                                             reinterpret_cast<unsigned long long *>(
-                                                 ctx[b]->ir_stat + ((int64_t)k * IR_MAXIT + j) * 2),
-                                             (int)ctx[b]->op->nleaves});
-                GroupPlan::Launch L{};
-                L.kind = 11;
-                L.a = T.put(folds.data(), sizeof(NormFold) * folds.size());
-                L.cnt = (int)folds.size();
-                P->seq.push_back(L);
-            }
+            if (!last.empty())
+                TRY(leaf(last, [&](int b, LeafPhase &ph) {
+                    stage_phase(b, k, ph);
+                    ph.down = LD_IR_ADD;
+                    ph.ir_eval = true;
+                    ph.u_out = ctx[b]->stage_u;
+                    ph.norm_part = part_of(b);
+                }));
+            fold(probs, k, j);
         }
-        TRY(leaf(all, [&](int b, LeafPhase &ph) {
-            step_phase(ctx[b], k, u[b], q_stages ? q_stages[b] : nullptr, q_space ? q_space[b] : nullptr,
-                       P->qt + 8 * b, ph);
-            if (k > 0) {
-                ph.down = LD_EVAL;
-                ph.u_eval = ctx[b]->stage_u;
-            }
-            if (k + 1 < s) ph.rhs_copy = ctx[b]->rhs;
-        }));
     }
     // boundary values (zero) and interface line solves of the update
     {

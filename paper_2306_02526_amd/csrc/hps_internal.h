@@ -187,6 +187,7 @@ struct Workspace {
     double *h_leaf = nullptr, *ub_leaf = nullptr, *w_leaf = nullptr, *flux = nullptr;
     double *ir_r = nullptr, *ir_r3 = nullptr;   // FP32_IR operators: the refinement residual
     double *ir_part = nullptr;                  // FP32_IR operators: per-leaf correction norms
+    double *ir_ubc = nullptr;                   // FP32_IR operators: running leaf boundary values
     std::vector<Lv> lv;
     std::vector<void *> allocs;
 };
@@ -314,6 +315,10 @@ struct LeafPhase {
 // ws (FP64 only) redirects the solve buffers (leaf boundary values, particular solutions
 // and fluxes) from the operator's own to a workspace
 int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st, const Workspace *ws = nullptr);
+// the leaf kernel's down mode for a phase (the LD_ value, or the fused refinement modes:
+// residual after LD_WRITE_U / LD_IR_ADD, L u_i and F_i after LD_IR_ADD); grouped launches
+// select their kernel with it
+int leaf_kernel_mode(const LeafPhase &ph, bool fp32);
 // the same phases for a complex operator (FP64; vectors in real / imaginary planes)
 int launch_leaf_cx(const hps_op *op, const LeafPhase &ph, hipStream_t st);
 // upward sweep over the levels, the root, then the downward sweep (jump and dirichlet

@@ -785,6 +785,17 @@ static void use_leaf_workspace(LeafArgs &a, const Workspace *ws) {
     a.w_out = ws->w_leaf;
     a.h_out = ws->h_leaf;
     a.fpart = ws->flux;
+    a.res_flux = ws->flux;
+    a.ubc = ws->ir_ubc;
+}
+
+int leaf_kernel_mode(const LeafPhase &ph, bool fp32) {
+    if (fp32 && ph.ir_eval && ph.down == LD_IR_ADD && (ph.up == LU_STAGE || ph.up == LU_UPDATE)) return DOWN_IR_ADD_EVAL;
+    if (fp32 && ph.res_rhs && ph.up == LU_BODY) {
+        if (ph.down == LD_WRITE_U) return DOWN_WRITE_U_RES;
+        if (ph.down == LD_IR_ADD) return DOWN_IR_ADD_RES;
+    }
+    return ph.down;
 }
 
 int launch_leaf(const hps_op *op, bool fp32, const LeafPhase &ph, hipStream_t st, const Workspace *ws) {
@@ -890,6 +901,10 @@ int launch_leaf_group(const void *args, const int *base, int nprob, int total, s
         HPS_LEAF_GROUP_CASE(float, DOWN_WRITE_U, UP_NONE)
         HPS_LEAF_GROUP_CASE(float, DOWN_NONE, UP_BODY)
         HPS_LEAF_GROUP_CASE(float, DOWN_IR_ADD, UP_NONE)
+        HPS_LEAF_GROUP_CASE(float, DOWN_WRITE_U_RES, UP_BODY)
+        HPS_LEAF_GROUP_CASE(float, DOWN_IR_ADD_RES, UP_BODY)
+        HPS_LEAF_GROUP_CASE(float, DOWN_IR_ADD_EVAL, UP_STAGE)
+        HPS_LEAF_GROUP_CASE(float, DOWN_IR_ADD_EVAL, UP_UPDATE)
     }
 #undef HPS_LEAF_GROUP_CASE
     hps_set_error("internal: unsupported grouped leaf phase (%d, %d)", down, up);
