@@ -1,6 +1,6 @@
 """hps_solve with several right-hand sides (Algorithm 1 of Sec. 2.1 applied to many data):
 FP64 operators take up to four right-hand sides per leaf launch and per level sweep, every
-operator block read once for all of them.  Each right-hand side must equal the oracle's
+operator block read once for all of them (more right-hand sides: passes of four).  Each right-hand side must equal the oracle's
 solve (1e-11) and the single-right-hand-side solve bit for bit (the same arithmetic in the
 same order)."""
 import sys
@@ -61,7 +61,9 @@ def solve_both(torch, op, og, nrhs, seed):
 
 
 @pytest.mark.parametrize("n1,n2,p,nrhs", [(4, 4, 8, 2), (8, 4, 10, 3), (8, 8, 12, 4), (16, 8, 7, 5),
-                                          (2, 16, 9, 7), (1, 1, 6, 3), (2, 1, 24, 4), (16, 16, 16, 4)])
+                                          (2, 16, 9, 7), (1, 1, 6, 3), (2, 1, 24, 4), (16, 16, 16, 4),
+                                          (8, 8, 10, 8), (16, 8, 8, 11), (4, 8, 16, 12), (2, 2, 24, 8),
+                                          (32, 16, 12, 8)])
 def test_multi_rhs_equals_single_and_oracle(torch, n1, n2, p, nrhs):
     say(f"[multi-rhs] {n1}x{n2} p={p} nrhs={nrhs}")
     gdt = 0.01
@@ -76,14 +78,15 @@ def test_multi_rhs_equals_single_and_oracle(torch, n1, n2, p, nrhs):
     op.free()
 
 
-def test_multi_rhs_at_full_size(torch):
-    """64x64 leaves, p = 16 (the benchmark grid), four right-hand sides: each equals its
-    single-right-hand-side solve bit for bit."""
-    say("[multi-rhs] 64x64 p=16, nrhs=4")
+@pytest.mark.parametrize("nrhs", [4, 8])
+def test_multi_rhs_at_full_size(torch, nrhs):
+    """64x64 leaves, p = 16 (the benchmark grid), four right-hand sides and eight (two passes):
+    each equals its single-right-hand-side solve bit for bit."""
+    say(f"[multi-rhs] 64x64 p=16, nrhs={nrhs}")
     gdt = 2.5e-4
     og, co, op = build(torch, 64, 64, 16, gdt)
-    _, _, _, um, us = solve_both(torch, op, og, 4, 3)
-    for r in range(4):
+    _, _, _, um, us = solve_both(torch, op, og, nrhs, 3)
+    for r in range(nrhs):
         say(f"   rhs {r}: max |difference| from the single solve {np.abs(um[r] - us[r]).max():.1e}")
         assert np.array_equal(um[r], us[r])
     op.free()
