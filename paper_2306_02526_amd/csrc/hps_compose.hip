@@ -133,6 +133,10 @@ static int pair_target() {
 // workgroups (at most NT / vw row vectors per tile: one row per thread); vw = 2 (FP64) or
 // 4 (FP32)
 static Panel pair_panel(int R, int C, int nodes, int target, int vw = 2) {
+    // FP32 copies hold half the bytes per row: twice the workgroups (four per compute unit)
+    // keep as many loads in flight (measured at 64x64 leaves, p = 16: FP32 sweeps of a
+    // refined step 2.07 -> 1.92 ms; two, three, six, eight per unit were slower)
+    if (vw == 4) target *= 2;
     const int RV = (R + vw - 1) / vw;
     const int per = std::max(1, (target + nodes - 1) / nodes);   // row tiles per node
     const int rp_max = std::min(NT / vw, std::max(1, (RV + per - 1) / per));
