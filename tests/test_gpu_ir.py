@@ -75,6 +75,46 @@ def test_replayed_fp32_ir_steps_match_oracle(torch):
     op.free()
 
 
+@pytest.mark.parametrize("n1,n2,p,extra", [(1, 1, 8, 0), (2, 1, 6, 0), (4, 2, 9, 0),
+                                          (8, 4, 7, hps.HPS_WIDE_TILES), (8, 8, 8, hps.HPS_UNIFORM_COEFFS)],
+                         ids=["1x1_p8", "2x1_p6", "4x2_p9", "8x4_p7_wide", "8x8_p8_uniform"])
+def test_replayed_steps_on_small_and_odd_trees(torch, n1, n2, p, extra):
+    """Replayed refined steps run the fused passes (residual in the leaf kernel that adds the
+    previous correction, the last correction fused with the evaluation of L u_i, F_i): one
+    leaf, odd trees (a single bottom level below the composite pairs), wide level tiles
+    (no composites) and shared operators, against the oracle over four steps."""
+    say(f"[ir] replayed fused passes, {n1}x{n2} p={p}, flags {hps.HPS_FP32_IR | extra}")
+    tab = product_tableau()
+    dt = 2e-3
+    gdt = tab["gamma"] * dt
+    h = 1.0 / max(n1, n2)
+    g = hps.make_grid(0, n1 * h, 0, n2 * h, n1, n2, p)
+    og = Grid(0, n1 * h, 0, n2 * h, n1, n2, p)
+    x, y = hps.hps_nodes(g)
+    wl = workloads.AllenCahn(workloads.rng_for(3))
+    if extra & hps.HPS_UNIFORM_COEFFS:
+        one = np.ones(og.n_int)
+        co = dict(cxx=1.3 * one, cyy=0.8 * one, cx=0.2 * one, cy=-0.1 * one, c0=0.05 * one)
+    else:
+        cxx, cyy, cx, cy, c0 = wl.L_coeffs(x[: og.n_int], y[: og.n_int])
+        co = dict(cxx=cxx, cyy=cyy, cx=cx, cy=cy, c0=c0)
+    op = hps.hps_build(g, {k: torch.tensor(v, device="cuda") for k, v in co.items()}, gdt,
+                       hps.HPS_FP32_IR | extra)
+    ctx = hps.ark_create(op, tab, dt, g=workloads.AllenCahn.gpoly)
+    orc = ARK(HPS(og, co, gdt), co, tableau_float(ark436l2sa()), dt, workloads.AllenCahn.gpoly)
+    u = wl.u0(x, y)
+    ug = torch.tensor(u, device="cuda")
+    for n in range(4):
+        hps.ark_step(ctx, n * dt, ug)
+        info = hps.ark_info(ctx)
+        u = orc.step(u)
+        e = rel(ug.cpu().numpy(), u)
+        say(f"   step {n}: rel err {e:.2e}, {info}")
+        assert e <= TOL32IR and info["fp64_fallbacks"] == 0
+    del ctx
+    op.free()
+
+
 def test_failed_refinement_falls_back_to_fp64_bitwise(torch, monkeypatch):
     """With refinement made to fail, every stage is re-solved with the operator's FP64
     copy: the steps equal those of a plain FP64 operator bit for bit, and the record says
