@@ -11,7 +11,11 @@
 //         interior step update u^{n+1} = u^n + dt sum_j (b_j L u_j + bhat_j F_j) and the
 //         interior part of the edge fluxes for the interface-line solves.
 // Everything the two phases exchange is leaf-local, so fusing them saves a launch per
-// stage and overlaps the tail of one stream with the start of the next.
+// stage and overlaps the tail of one stream with the start of the next.  The FP32
+// refinement passes fuse the same way: the kernel that writes u (or adds a correction)
+// evaluates the FP64 residual of the new u on its tile and starts the next correction's
+// solve from it, or, after a stage's last correction, evaluates L u_i, F_i and opens the
+// next stage.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
