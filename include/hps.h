@@ -68,7 +68,12 @@ extern "C" {
                             level, for about 1.4 times the level operators' memory.
                             The environment variable HPS_COMPOSE=0 at build time turns
                             them off (HPS_COMPOSE=1 forces them where the tuner chose
-                            against them); results differ by rounding only.          */
+                            against them); results differ by rounding only.  A small
+                            FP64 tree (the matrix below at most 2 MiB) also gets its
+                            whole sweep without Dirichlet or jump data as one product:
+                            interface values = M h_leaf, M taken at build time from the
+                            operator's own sweeps of unit vectors (HPS_DIRECT=0 at build
+                            time turns it off; results differ by rounding only).    */
 #define HPS_FP32_IR  1   /* FP64 build; operators applied in FP32 inside an FP64
                             iterative-refinement loop (residual in FP64): corrections
                             until ||delta||_inf <= 1e-11 ||u||_inf, at most 10; a solve

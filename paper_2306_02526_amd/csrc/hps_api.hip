@@ -797,7 +797,8 @@ static int build_impl(hps_op *op, const hps_coeffs *co, const hps_coeffs *co_im,
                       (long long)(op->operator_bytes - pair_bytes));
         return HPS_EDEVICE;
     }
-    return HPS_OK;
+    // small trees: the whole sweep as one product (on top of the plan, like the composites)
+    return build_direct(op, st);
 }
 
 extern "C" void hps_free(hps_op *op) {

@@ -385,3 +385,112 @@ int hps::compose_pair(hps_op *op, int l, const std::vector<HostLevel> &hl, const
     op->pairs.push_back(P);
     return HPS_OK;
 }
+
+// ---------------------------------------------------------------------------------------
+// The direct sweep of a small tree.  With no boundary or jump data the interface values
+// the level sweeps produce are a linear function of the leaves' particular fluxes h alone
+// (Algorithm 1 of Sec. 2.1: every merge and every downward step is linear in h), so for a
+// small tree the whole sweep -- 2 L - 1 or its composite-pair launches -- is one product
+// M h.  M is taken column by column from the operator's own sweeps of unit vectors, so it
+// is the map the sweeps compute, up to rounding.
+// ---------------------------------------------------------------------------------------
+namespace {
+
+__global__ void k_unit(double *v, int64_t n, int64_t k) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+        v[t] = t == k ? 1.0 : 0.0;
+}
+
+// column c of M: the interface values, read at each row's first leaf-boundary slot
+__global__ void k_take_col(const double *ub, const int *rows, int R, double *col) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < R) col[r] = ub[rows[2 * r]];
+}
+
+constexpr int64_t kDirectMaxBytes = int64_t(2) << 20;   // M of at most 2 MiB
+
+}  // namespace
+
+int hps::build_direct(hps_op *op, hipStream_t st) {
+    const char *env = std::getenv("HPS_DIRECT");
+    if (env && env[0] == '0') return HPS_OK;
+    if (op->ncomp != 1 || (op->flags & (HPS_FP32_IR | HPS_WIDE_TILES)) || op->L < 2 || op->n_iface <= 0) return HPS_OK;
+    const int q = op->q, n1 = op->grid.n1, n2 = op->grid.n2, nb = 4 * q;
+    const int64_t R = op->n_iface, C = (int64_t)op->nleaves * nb;
+    if (R * C * 8 > kDirectMaxBytes) return HPS_OK;
+    // leaf-boundary slots: heap leaf of each leaf (i, j), the two slots of each interface
+    // node (canonical interface order: vertical lines first), the domain-boundary slots
+    std::vector<int> ij(2 * (size_t)op->nleaves), heap((size_t)n1 * n2);
+    HPS_HIP(hipMemcpy(ij.data(), op->leaf_ij, sizeof(int) * ij.size(), hipMemcpyDeviceToHost));
+    for (int h = 0; h < op->nleaves; ++h) heap[(size_t)ij[2 * h + 1] * n1 + ij[2 * h]] = h;
+    auto slot = [&](int i, int j, int e, int m) { return heap[(size_t)j * n1 + i] * nb + e * q + m; };
+    std::vector<int> rows(2 * (size_t)R), zero;
+    const int64_t nv = (int64_t)(n1 - 1) * n2 * q;
+    for (int64_t t = 0; t < R; ++t) {
+        if (t < nv) {
+            const int k = (int)(t / ((int64_t)n2 * q)) + 1, rem = (int)(t % ((int64_t)n2 * q));
+            rows[2 * t] = slot(k - 1, rem / q, 1, rem % q);
+            rows[2 * t + 1] = slot(k, rem / q, 0, rem % q);
+        } else {
+            const int64_t u = t - nv;
+            const int k = (int)(u / ((int64_t)n1 * q)) + 1, rem = (int)(u % ((int64_t)n1 * q));
+            rows[2 * t] = slot(rem / q, k - 1, 3, rem % q);
+            rows[2 * t + 1] = slot(rem / q, k, 2, rem % q);
+        }
+    }
+    for (int j = 0; j < n2; ++j)
+        for (int i = 0; i < n1; ++i)
+            for (int m = 0; m < q; ++m) {
+                if (i == 0) zero.push_back(slot(i, j, 0, m));
+                if (i == n1 - 1) zero.push_back(slot(i, j, 1, m));
+                if (j == 0) zero.push_back(slot(i, j, 2, m));
+                if (j == n2 - 1) zero.push_back(slot(i, j, 3, m));
+            }
+    // the streaming layout: about two row tiles' workgroups per compute unit; a row longer
+    // than one workgroup's LDS holds keeps the level sweeps
+    Panel pn = pair_panel((int)R, (int)C, 1, pair_target(), 2);
+    if (pn.kch != 1 || pn.rp * pn.vw > NT) return HPS_OK;
+    // the slot tables, kept with the operator
+    auto keep = [&](const std::vector<int> &v, int **out) -> int {
+        if (hipMalloc(out, sizeof(int) * std::max<size_t>(v.size(), 1)) != hipSuccess) {
+            (void)hipGetLastError();
+            hps_set_error("hipMalloc for the direct sweep tables failed");
+            return HPS_ENOMEM;
+        }
+        op->allocs.push_back(*out);
+        op->total_bytes += (int64_t)(sizeof(int) * v.size());
+        if (!v.empty()) HPS_HIP(hipMemcpyAsync(*out, v.data(), sizeof(int) * v.size(), hipMemcpyHostToDevice, st));
+        return HPS_OK;
+    };
+    TRY(keep(rows, &op->d_rows));
+    TRY(keep(zero, &op->d_zero));
+    op->n_zero = (int)zero.size();
+    void *d = nullptr;
+    if (hipMalloc(&d, 8 * pn.node_elems) != hipSuccess) {
+        (void)hipGetLastError();
+        hps_set_error("hipMalloc for the direct sweep operator failed");
+        return HPS_ENOMEM;
+    }
+    op->allocs.push_back(d);
+    op->operator_bytes += pn.bytes();
+    op->total_bytes += pn.bytes();
+    pn.data = d;
+    // M column by column: the operator's FP64 sweep of each unit flux vector
+    DevScratch tmp;
+    double *M = nullptr;
+    TRY(tmp.get(&M, R * C));
+    const unsigned gz = (unsigned)std::min<int64_t>((C + NT - 1) / NT, 1024), gr = (unsigned)((R + NT - 1) / NT);
+    for (int64_t c = 0; c < C; ++c) {
+        hipLaunchKernelGGL(k_unit, dim3(gz), dim3(NT), 0, st, op->h_leaf, C, c);
+        HPS_LAUNCHED();
+        TRY(launch_levels(op, false, nullptr, nullptr, st));
+        hipLaunchKernelGGL(k_take_col, dim3(gr), dim3(NT), 0, st, (const double *)op->ub_leaf,
+                           (const int *)op->d_rows, (int)R, M + c * R);
+        HPS_LAUNCHED();
+    }
+    TRY(launch_pack(pn, M, (int)R, R * C, (int)R, nullptr, 0, 0, st));
+    HPS_HIP(hipStreamSynchronize(st));   // the scratch M is freed on return
+    op->dpn = pn;
+    op->direct = true;
+    return HPS_OK;
+}

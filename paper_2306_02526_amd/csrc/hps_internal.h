@@ -55,6 +55,10 @@ struct HostLevel;
 bool compose_eligible(const hps_op *op, const std::vector<HostLevel> &hl);
 int compose_pair(hps_op *op, int l, const std::vector<HostLevel> &hl, const double *Xc, const double *Uc,
                  const double *Sc, const double *Xt, const double *Ut, const double *St, hipStream_t st);
+// the direct sweep of a small tree (hps_compose.hip), built after everything else; and its
+// launch (hps_solve_kernels.hip)
+int build_direct(hps_op *op, hipStream_t st);
+int launch_direct(const hps_op *op, hipStream_t st);
 int launch_place(double *dst, int ldd, int64_t dstr, int r0, int c0, int rows, int cols, const double *src, int lds,
                  int64_t sstr, const int *ri, const int *cj, double scale, bool accumulate, int batch, hipStream_t st);
 // HPS_AUTOTUNE: the level tiling of this operator class, measured on the device the first
@@ -105,7 +109,7 @@ enum KernelFamily {
     KF_LEVEL_UP64, KF_LEVEL_UP32, KF_LEVEL_DOWN64, KF_LEVEL_DOWN32, KF_RESIDUAL, KF_LINES,
     KF_LEAF2_EVAL_UP64, KF_LEAF2_DOWN_UP64, KF_LEAF2_DOWN_UPDATE64, KF_LEVEL2_UP64, KF_LEVEL2_DOWN64,
     KF_LEAFC_EVAL_UP64, KF_LEAFC_DOWN_UP64, KF_LEAFC_DOWN_UPDATE64, KF_LEAFC_SOLVE64,
-    KF_PAIR_UP64, KF_PAIR_TOP64, KF_PAIR_DOWN64, KF_PAIR_UP32, KF_PAIR_TOP32, KF_PAIR_DOWN32, KF_COUNT
+    KF_PAIR_UP64, KF_PAIR_TOP64, KF_PAIR_DOWN64, KF_PAIR_UP32, KF_PAIR_TOP32, KF_PAIR_DOWN32, KF_DIRECT64, KF_COUNT
 };
 extern const char *const kKernelFamilyNames[KF_COUNT];
 
@@ -162,6 +166,14 @@ struct hps_op {
     // for every other consumer); pairs[k]: upper level 2k (k = 0: the top pair)
     bool composed = false;
     std::vector<hps::PairOps> pairs;
+    // small trees: the whole FP64 level sweep without boundary or jump data as one product
+    // (build_direct): interface values = M h_leaf, each written to the two leaf-boundary
+    // slots it belongs to; the domain-boundary slots get zeros
+    bool direct = false;
+    hps::Panel dpn;                        // M: [n_iface rows] x [nleaves * 4q columns]
+    int *d_rows = nullptr;                 // device [n_iface][2] leaf-boundary slots of each row
+    int *d_zero = nullptr;                 // device leaf-boundary slots on the domain boundary
+    int n_zero = 0;
     // iterative refinement workspace (FP32_IR)
     double *ir_rhs = nullptr, *ir_r = nullptr, *ir_r3 = nullptr, *ir_du = nullptr, *ir_flux = nullptr;
     double *ir_norms = nullptr;            // [2] max|delta|, max|u| (as ordered bit patterns)

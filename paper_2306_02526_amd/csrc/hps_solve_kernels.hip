@@ -1267,7 +1267,7 @@ const char *const kKernelFamilyNames[KF_COUNT] = {
     "residual", "lines", "leaf2_eval_up_fp64", "leaf2_down_up_fp64", "leaf2_down_update_fp64",
     "level2_up_fp64", "level2_down_fp64", "leafc_eval_up_fp64", "leafc_down_up_fp64", "leafc_down_update_fp64",
     "leafc_solve_fp64", "pair_up_fp64", "pair_top_fp64", "pair_down_fp64", "pair_up_fp32", "pair_top_fp32",
-    "pair_down_fp32"};
+    "pair_down_fp32", "direct_fp64"};
 
 hipEvent_t Profiler::get() {
     if (!pool.empty()) {
@@ -1512,6 +1512,54 @@ __global__ __launch_bounds__(NT) void k_root_sys(LevelSysArgsN<NC> up, LevelSysA
     root_sys_body<NC>(up, dn, blockIdx.x, smem, red);
 }
 
+// The whole level sweep of a small tree as one product: interface values y = M h for the
+// leaves' particular fluxes h (no boundary or jump data), each written to the two leaf
+// boundary slots it belongs to, and zeros to the slots on the domain boundary.  One
+// workgroup per row tile of M; the arithmetic of pair_body's product and row sums.
+struct DirectArgs {
+    PanelView pn;
+    int R, C;
+    const double *h;
+    double *ub;
+    const int *rows, *zero;
+    int nzero;
+};
+
+__global__ __launch_bounds__(NT) void k_direct(DirectArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT + 64];
+    constexpr int VW = 2;
+    const int tile = blockIdx.x;
+    const int SG = a.pn.S * a.pn.G;
+    Carve cv{smem};
+    double *xs = cv.take<double>(SG);
+    double *part = cv.take<double>((size_t)a.pn.G * a.pn.rp * VW);
+    PanelStream<double, PF, UNR> ps;
+    ps.start(reinterpret_cast<const double *>(a.pn.data) + (int64_t)tile * a.pn.tile_elems, a.pn.rp, a.pn.G, a.pn.S);
+    for (int k = threadIdx.x; k < SG; k += NT) xs[k] = k < a.C ? a.h[k] : 0.0;
+    for (int z = blockIdx.x * NT + threadIdx.x; z < a.nzero; z += gridDim.x * NT) a.ub[a.zero[z]] = 0.0;
+    __syncthreads();
+    ps.finish(xs, part);
+    __syncthreads();
+    const int rows = a.pn.rp * VW;
+    const int G = a.pn.G;
+    const int nsl = min(G, NT / rows);
+    const int t = threadIdx.x;
+    const int row = t % rows, sl = t / rows;
+    if (sl < nsl) {
+        double y = 0.0;
+        for (int gg = sl; gg < G; gg += nsl) y += part[gg * rows + row];
+        red[sl * rows + row] = y;
+    }
+    __syncthreads();
+    const double y = slice_sum(red, red + NT, nsl, rows);
+    const int myrow = tile * rows + t;
+    if (t < rows && myrow < a.R) {
+        a.ub[a.rows[2 * myrow]] = y;
+        a.ub[a.rows[2 * myrow + 1]] = y;
+    }
+}
+
 static size_t level_lds(const Panel &pn) {
     const size_t es = pn.vw == 2 ? 8 : 4;
     return carve_bytes({(size_t)pn.S * pn.G * es, (size_t)pn.G * pn.rp * pn.vw * es});
@@ -1639,8 +1687,17 @@ static int launch_pairs(const hps_op *op, bool fp32, const double *jump, const d
     return HPS_OK;
 }
 
+int launch_direct(const hps_op *op, hipStream_t st) {
+    ProfScope ps_(&op->prof, KF_DIRECT64, st);
+    DirectArgs a{view(op->dpn), op->dpn.R, op->dpn.C, op->h_leaf, op->ub_leaf, op->d_rows, op->d_zero, op->n_zero};
+    hipLaunchKernelGGL(k_direct, dim3((unsigned)op->dpn.ntile), dim3(NT), level_lds(op->dpn), st, a);
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
 int launch_levels(const hps_op *op, bool fp32, const double *jump, const double *dirichlet, hipStream_t st,
                   const Workspace *ws) {
+    if (op->direct && !fp32 && !jump && !dirichlet && !ws) return launch_direct(op, st);
     if (op->composed) return launch_pairs(op, fp32, jump, dirichlet, st, ws);
     const bool rootf = root_fusable(op, fp32);
     {
