@@ -140,7 +140,8 @@ struct GroupPlan {
     struct Launch {
         int kind;            // 0 leaf phase, 1 level up, 2 level down, 3 roots, 4 boundary, 5 lines,
                              // 6 / 7 / 8 composite pairs up / down / top, 9 copies and fills,
-                             // 10 refinement residuals, 11 correction-norm folds
+                             // 10 refinement residuals, 11 correction-norm folds, 12 direct
+                             // products of small trees
         size_t a, a2, base;  // offsets of the records (a2: downward root records / jump
                              // records) and bases
         int cnt, total;
@@ -326,13 +327,14 @@ int build_plan(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, const
     const size_t ls = level_record_size(), prs = pair_record_size();
     // operators with composite level pairs sweep pair (l, l + 1) at its upper level l and
     // only the bottom level of an odd tree with the single-level kernels
+    // small trees with a direct product sweep in one launch of their own, as a single step does
     auto single_here = [&](const hps_op *op, int l) -> bool {
-        if (l >= op->L) return false;
+        if (l >= op->L || op->direct) return false;
         if (op->composed) return (op->L % 2 == 1) && l == op->L - 1;
         return !(l == 0 && root_fused64(op));
     };
     auto pair_here = [&](const hps_op *op, int l, int mode) -> bool {
-        if (!op->composed) return false;
+        if (!op->composed || op->direct) return false;
         if (mode == 2) return l == 0;
         return l >= 2 && l % 2 == 0 && l <= pair_lowest(op);
     };
@@ -382,6 +384,30 @@ int build_plan(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, const
         P->sweep.push_back(L);
         return HPS_OK;
     };
+    {
+        GroupPlan::Launch L{};
+        L.kind = 12;
+        const size_t ds = direct_record_size();
+        std::vector<unsigned char> recs;
+        std::vector<int> bs(1, 0);
+        for (int b = 0; b < n; ++b) {
+            const hps_op *op = ctx[b]->op;
+            if (!op->direct) continue;
+            recs.resize(recs.size() + ds);
+            int blocks = 0;
+            size_t lds = 0;
+            direct_record(op, recs.data() + recs.size() - ds, &blocks, &lds, ws[b]);
+            L.lds = std::max(L.lds, lds);
+            bs.push_back(bs.back() + blocks);
+        }
+        L.cnt = (int)bs.size() - 1;
+        if (L.cnt > 0) {
+            L.a = T.put(recs.data(), recs.size());
+            L.base = T.put(bs.data(), sizeof(int) * bs.size());
+            L.total = bs.back();
+            P->sweep.push_back(L);
+        }
+    }
     for (int l = Lmax - 1; l >= 0; --l) {
         TRY(level_launch(l, true));
         TRY(pair_launch(l, 0));
@@ -394,7 +420,7 @@ int build_plan(GroupPlan *P, ark_ctx *const *ctx, int n, double *const *u, const
         std::vector<int> bs(1, 0);
         for (int b = 0; b < n; ++b) {
             const hps_op *op = ctx[b]->op;
-            if (op->composed || !root_fused64(op)) continue;
+            if (op->composed || op->direct || !root_fused64(op)) continue;
             ups.resize(ups.size() + ls);
             dns.resize(dns.size() + ls);
             int blocks = 0;
@@ -797,6 +823,7 @@ int enqueue_plan(const GroupPlan *P, hipStream_t st) {
     auto run_sweep = [&]() -> int {
         for (const GroupPlan::Launch &L : P->sweep) {
             if (L.kind == 3) TRY(launch_root_group(d + L.a, d + L.a2, basep(L), L.cnt, L.total, L.lds, st));
+            else if (L.kind == 12) TRY(launch_direct_group(d + L.a, basep(L), L.cnt, L.total, L.lds, st));
             else if (L.kind >= 6) TRY(launch_pair_group(d + L.a, basep(L), L.cnt, L.total, L.lds, L.kind - 6, st));
             else TRY(launch_level_group(d + L.a, basep(L), L.cnt, L.total, L.lds, L.kind == 1, st));
         }

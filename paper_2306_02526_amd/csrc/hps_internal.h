@@ -55,10 +55,8 @@ struct HostLevel;
 bool compose_eligible(const hps_op *op, const std::vector<HostLevel> &hl);
 int compose_pair(hps_op *op, int l, const std::vector<HostLevel> &hl, const double *Xc, const double *Uc,
                  const double *Sc, const double *Xt, const double *Ut, const double *St, hipStream_t st);
-// the direct sweep of a small tree (hps_compose.hip), built after everything else; and its
-// launch (hps_solve_kernels.hip)
+// the direct sweep of a small tree (hps_compose.hip), built after everything else
 int build_direct(hps_op *op, hipStream_t st);
-int launch_direct(const hps_op *op, hipStream_t st);
 int launch_place(double *dst, int ldd, int64_t dstr, int r0, int c0, int rows, int cols, const double *src, int lds,
                  int64_t sstr, const int *ri, const int *cj, double scale, bool accumulate, int batch, hipStream_t st);
 // HPS_AUTOTUNE: the level tiling of this operator class, measured on the device the first
@@ -404,6 +402,12 @@ void pair_record(const hps_op *op, int l, int mode, const double *dir, void *dst
                  const Workspace *ws, bool fp32 = false, const double *r3 = nullptr);
 int launch_pair_group(const void *args, const int *base, int n, int total, size_t lds, int mode, hipStream_t st,
                       bool fp32 = false);
+// the direct product of a small tree (FP64) on the operator's or a workspace's leaf buffers,
+// and in grouped launches
+int launch_direct(const hps_op *op, hipStream_t st, const Workspace *ws = nullptr);
+size_t direct_record_size();
+void direct_record(const hps_op *op, void *dst, int *blocks, size_t *lds, const Workspace *ws);
+int launch_direct_group(const void *args, const int *base, int n, int total, size_t lds, hipStream_t st);
 size_t line_record_size();
 void line_record(const hps_op *op, double *u, void *dst, int *systems, const Workspace *ws);
 size_t scatter_record_size();

@@ -1525,11 +1525,10 @@ struct DirectArgs {
     int nzero;
 };
 
-__global__ __launch_bounds__(NT) void k_direct(DirectArgs a) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ double red[NT + 64];
+// one row tile of the direct product (tile of ntiles); the tiles also clear the zero slots
+__device__ __forceinline__ void direct_body(const DirectArgs &a, int tile, int ntiles, unsigned char *smem,
+                                            double *red) {
     constexpr int VW = 2;
-    const int tile = blockIdx.x;
     const int SG = a.pn.S * a.pn.G;
     Carve cv{smem};
     double *xs = cv.take<double>(SG);
@@ -1537,7 +1536,7 @@ __global__ __launch_bounds__(NT) void k_direct(DirectArgs a) {
     PanelStream<double, PF, UNR> ps;
     ps.start(reinterpret_cast<const double *>(a.pn.data) + (int64_t)tile * a.pn.tile_elems, a.pn.rp, a.pn.G, a.pn.S);
     for (int k = threadIdx.x; k < SG; k += NT) xs[k] = k < a.C ? a.h[k] : 0.0;
-    for (int z = blockIdx.x * NT + threadIdx.x; z < a.nzero; z += gridDim.x * NT) a.ub[a.zero[z]] = 0.0;
+    for (int z = tile * NT + threadIdx.x; z < a.nzero; z += ntiles * NT) a.ub[a.zero[z]] = 0.0;
     __syncthreads();
     ps.finish(xs, part);
     __syncthreads();
@@ -1558,6 +1557,26 @@ __global__ __launch_bounds__(NT) void k_direct(DirectArgs a) {
         a.ub[a.rows[2 * myrow]] = y;
         a.ub[a.rows[2 * myrow + 1]] = y;
     }
+}
+
+__global__ __launch_bounds__(NT) void k_direct(DirectArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT + 64];
+    direct_body(a, blockIdx.x, gridDim.x, smem, red);
+}
+
+// several problems' direct products in one launch: base[b] is problem b's first workgroup
+__global__ __launch_bounds__(NT) void k_direct_group(const DirectArgs *args, const int *base, int n) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[NT + 64];
+    const int w = blockIdx.x;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (base[mid] <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    direct_body(args[lo], w - base[lo], base[lo + 1] - base[lo], smem, red);
 }
 
 static size_t level_lds(const Panel &pn) {
@@ -1687,17 +1706,38 @@ static int launch_pairs(const hps_op *op, bool fp32, const double *jump, const d
     return HPS_OK;
 }
 
-int launch_direct(const hps_op *op, hipStream_t st) {
+static DirectArgs direct_args(const hps_op *op, const Workspace *ws) {
+    return DirectArgs{view(op->dpn),  op->dpn.R, op->dpn.C, ws ? ws->h_leaf : op->h_leaf, ws ? ws->ub_leaf : op->ub_leaf,
+                      op->d_rows,     op->d_zero, op->n_zero};
+}
+
+int launch_direct(const hps_op *op, hipStream_t st, const Workspace *ws) {
     ProfScope ps_(&op->prof, KF_DIRECT64, st);
-    DirectArgs a{view(op->dpn), op->dpn.R, op->dpn.C, op->h_leaf, op->ub_leaf, op->d_rows, op->d_zero, op->n_zero};
-    hipLaunchKernelGGL(k_direct, dim3((unsigned)op->dpn.ntile), dim3(NT), level_lds(op->dpn), st, a);
+    hipLaunchKernelGGL(k_direct, dim3((unsigned)op->dpn.ntile), dim3(NT), level_lds(op->dpn), st,
+                       direct_args(op, ws));
+    HPS_LAUNCHED();
+    return HPS_OK;
+}
+
+size_t direct_record_size() { return sizeof(DirectArgs); }
+
+void direct_record(const hps_op *op, void *dst, int *blocks, size_t *lds, const Workspace *ws) {
+    *reinterpret_cast<DirectArgs *>(dst) = direct_args(op, ws);
+    *blocks = (int)op->dpn.ntile;
+    *lds = level_lds(op->dpn);
+}
+
+int launch_direct_group(const void *args, const int *base, int n, int total, size_t lds, hipStream_t st) {
+    if (total <= 0) return HPS_OK;
+    hipLaunchKernelGGL(k_direct_group, dim3(total), dim3(NT), lds, st, reinterpret_cast<const DirectArgs *>(args),
+                       base, n);
     HPS_LAUNCHED();
     return HPS_OK;
 }
 
 int launch_levels(const hps_op *op, bool fp32, const double *jump, const double *dirichlet, hipStream_t st,
                   const Workspace *ws) {
-    if (op->direct && !fp32 && !jump && !dirichlet && !ws) return launch_direct(op, st);
+    if (op->direct && !fp32 && !jump && !dirichlet) return launch_direct(op, st, ws);
     if (op->composed) return launch_pairs(op, fp32, jump, dirichlet, st, ws);
     const bool rootf = root_fusable(op, fp32);
     {

@@ -157,3 +157,56 @@ def test_direct_steps_match_oracle_and_replay_exactly(torch, monkeypatch):
     say(f"   10 steps: rel err vs oracle {e:.2e}")
     del ctx_g, ctx_e
     op.free()
+
+
+def test_grouped_batch_and_noalloc_take_the_direct_product(torch, monkeypatch):
+    """Grouped batched steps (HPS_GROUP=1) of Allen-Cahn problems: two contexts on one small
+    operator (each with a workspace of its own), another small operator and a tree too large
+    for the direct product, each equal to its single step bit for bit and to the oracle; and
+    the allocation-free solve without boundary or jump data equal to hps_solve."""
+    say("[direct] grouped batch with small and large trees; allocation-free solve")
+    tab = product_tableau()
+    dt = 2e-3
+    gdt = tab["gamma"] * dt
+    built = {}
+    for n1, n2, p in [(4, 4, 8), (8, 4, 6), (16, 16, 10)]:
+        og, co, op = setup(torch, monkeypatch, n1, n2, p, gdt, True)
+        built[(n1, n2, p)] = (og, co, op)
+    keys = [(4, 4, 8), (4, 4, 8), (8, 4, 6), (16, 16, 10)]
+    ctxs = [hps.ark_create(built[k][2], tab, dt, g=workloads.AllenCahn.gpoly) for k in keys]
+    singles = [hps.ark_create(built[k][2], tab, dt, g=workloads.AllenCahn.gpoly) for k in keys]
+    arks = {k: ARK(HPS(og, co, gdt), co, tableau_float(ark436l2sa()), dt, workloads.AllenCahn.gpoly)
+            for k, (og, co, _) in built.items()}
+    us, refs = [], []
+    for b, k in enumerate(keys):
+        h = 1.0 / max(k[0], k[1])
+        x, y = hps.hps_nodes(hps.make_grid(0.0, k[0] * h, 0.0, k[1] * h, *k))
+        u0 = np.sin(3 * x + b) * np.cos(2 * y)
+        us.append(torch.tensor(u0, device="cuda"))
+        refs.append(u0)
+    want = [u.clone() for u in us]
+    monkeypatch.setenv("HPS_GROUP", "1")
+    for n in range(2):
+        hps.ark_step_batched(ctxs, [n * dt] * len(keys), us)
+        for b in range(len(keys)):
+            hps.ark_step(singles[b], n * dt, want[b])
+            refs[b] = arks[keys[b]].step(refs[b])
+        torch.cuda.synchronize()
+        for b in range(len(keys)):
+            assert torch.equal(us[b], want[b]), (n, b)
+            e = rel(us[b].cpu().numpy(), refs[b])
+            say(f"   step {n} problem {b} {keys[b]}: bitwise equal to its single step, rel err {e:.2e}")
+            assert e <= TOL64
+    monkeypatch.delenv("HPS_GROUP")
+    del ctxs, singles
+    rng = np.random.default_rng(23)
+    for k in [(4, 4, 8), (8, 4, 6)]:
+        og, co, op = built[k]
+        body = torch.tensor(rng.standard_normal(og.n_int), device="cuda")
+        u_na = hps.hps_solve_noalloc(op, body)
+        torch.cuda.synchronize()
+        u_ref = hps.hps_solve(op, body)
+        torch.cuda.synchronize()
+        assert torch.equal(u_na, u_ref), k
+    for _, _, op in built.values():
+        op.free()
