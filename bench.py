@@ -87,7 +87,39 @@ def parse():
     ap.add_argument("--counter-run", action="store_true",
                     help="short run for hardware-counter passes: build, 2 steps, then a plain "
                          "1 GiB device copy whose counters calibrate the byte counts")
+    ap.add_argument("--build-runs", type=int, default=0,
+                    help="only build the benchmark operator (FP64) this many times and print the "
+                         "wall time of each build")
     return ap.parse_args()
+
+
+def build_run(args):
+    """Operator builds alone: the benchmark grid's FP64 operator built --build-runs times
+    (the first includes one-time set-up), each timed from a synchronized start to a
+    synchronized end."""
+    import torch
+
+    from paper_2306_02526_amd import hps, workloads
+    from paper_2306_02526_amd.tableau import ark436l2sa
+
+    dev = torch.device("cuda:0")
+    n, p, dt = args.n, args.p, args.dt
+    g = hps.make_grid(0.0, 1.0, 0.0, 1.0, n, n, p)
+    N, n_int, _, _ = hps.hps_num_nodes(g)
+    x, y = hps.hps_nodes(g)
+    wl = workloads.AllenCahn(workloads.rng_for(2))
+    cxx, cyy, cx, cy, _ = wl.L_coeffs(x[:n_int], y[:n_int])
+    coefs = {k: torch.tensor(v, device=dev) for k, v in dict(cxx=cxx, cyy=cyy, cx=cx, cy=cy).items()}
+    times = []
+    for _ in range(args.build_runs):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op = hps.hps_build(g, coefs, ark436l2sa()["gamma"] * dt, hps.HPS_FP64)
+        torch.cuda.synchronize()
+        times.append(round(time.perf_counter() - t0, 4))
+        log(f"build {n}x{n} p={p}: {times[-1]:.4f} s")
+        op.free()
+    print(json.dumps({"workload": f"operator_build_{n}x{n}_leaves_p{p}", "build_s": times}), flush=True)
 
 
 def counter_run(args):
@@ -357,6 +389,9 @@ def main():
         sys.exit(2)
     if args.counter_run:
         counter_run(args)
+        return
+    if args.build_runs > 0:
+        build_run(args)
         return
     if args.workload == "batched":
         batched_run(args)

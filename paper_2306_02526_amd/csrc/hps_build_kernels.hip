@@ -355,24 +355,31 @@ __global__ void k_gj_unpermute(const double *W, double *out, int n, int nb, cons
 // r + GJ_TR a (a < RA) and columns c + GJ_TC b (b < CB), n <= GJ_TR RA and n <= GJ_TC CB, so
 // every step touches the matrix in registers instead of streaming the whole batch through
 // memory twice per step (512 threads: up to 256 registers per lane, 13 x 7 doubles each
-// at n = 196).  Each step performs
-// exactly the operations of k_gj_pivot / k_gj_update (same pivot rule, same products and
-// fused multiply-adds), so the result is bitwise that of the batched kernels; the
-// unpermutation is done on the way out.
+// at n = 196).  Each step performs exactly the operations of k_gj_pivot / k_gj_update (same
+// pivot rule, same products and fused multiply-adds), so the result is bitwise that of the
+// batched kernels; the unpermutation is done on the way out.
+//
+// Two barriers per step.  Every wave finds the pivot itself from the column in LDS (the
+// same deterministic search, so all waves agree; each keeps the used-row flags of its
+// lanes' rows in a register), the owners of the pivot row publish it scaled, and after the
+// barrier every element takes one fused multiply-add, the pivot row and column k being
+// overwritten afterwards; the owners of column k + 1 publish it into the other half of a
+// double-buffered column in the same phase.
 constexpr int GJ_TR = 16, GJ_TC = 32;   // thread grid: rows x columns
 constexpr int GJ_NT = GJ_TR * GJ_TC;
+constexpr int GJ_MAXN = 256;            // rows a wave's pivot search covers (4 per lane)
+
+static size_t gj_reg_lds(int n) { return (size_t)n * (3 * sizeof(double) + 2 * sizeof(int)); }
 
 template <int RA, int CB>
 __global__ __launch_bounds__(GJ_NT) void k_gj_reg(const double *W, double *out, int n, int *sing) {
+    static_assert(GJ_TR * RA <= GJ_MAXN, "the pivot search covers at most GJ_MAXN rows");
     extern __shared__ __align__(16) unsigned char gsm[];
-    double *colbuf = reinterpret_cast<double *>(gsm);        // [n]
-    double *rowbuf = colbuf + n;                              // [n]
+    double *colbuf = reinterpret_cast<double *>(gsm);        // [2][n] column k, by step parity
+    double *rowbuf = colbuf + 2 * n;                          // [n] scaled pivot row
     int *order = reinterpret_cast<int *>(rowbuf + n);         // [n] pivot row of step k
     int *pinv = order + n;                                    // [n] step of pivot row i
-    unsigned char *used = reinterpret_cast<unsigned char *>(pinv + n);   // [n]
-    __shared__ int s_pr;
-    __shared__ double s_ip;
-    const int t = threadIdx.x, b = blockIdx.x;
+    const int t = threadIdx.x, b = blockIdx.x, lane = t & 63;
     const int r = t % GJ_TR, c = t / GJ_TR;
     const int64_t nn = (int64_t)n * n;
     const double *Wb = W + b * nn;
@@ -385,64 +392,54 @@ __global__ __launch_bounds__(GJ_NT) void k_gj_reg(const double *W, double *out, 
             w[a][bb] = (i < n && j < n) ? Wb[(int64_t)j * n + i] : 0.0;
         }
     for (int i = t; i < n; i += GJ_NT) {
-        used[i] = 0;
         order[i] = i;   // complete permutations even if a singular step repeats a row
         pinv[i] = i;
     }
+    if (c == 0)
+#pragma unroll
+        for (int a = 0; a < RA; ++a) {
+            const int i = r + GJ_TR * a;
+            if (i < n) colbuf[i] = w[a][0];
+        }
+    unsigned used = 0;   // bit m: row lane + 64 m is a pivot row already
     __syncthreads();
     for (int k = 0; k < n; ++k) {
-        // column k of every row (thread column c == k % GJ_TC holds it)
-        if (c == k % GJ_TC) {
-            const int bk = k / GJ_TC;
+        const double *col = colbuf + (k & 1) * n;
+        // unused row with the largest |W[i][k]|, ties to the smallest i (every wave)
+        double best = -1.0;
+        int besti = n;
 #pragma unroll
-            for (int bb = 0; bb < CB; ++bb)
-                if (bb == bk)
-#pragma unroll
-                    for (int a = 0; a < RA; ++a) {
-                        const int i = r + GJ_TR * a;
-                        if (i < n) colbuf[i] = w[a][bb];
-                    }
-        }
-        __syncthreads();
-        if (t < 64) {
-            // unused row with the largest |W[i][k]|, ties to the smallest i
-            double best = -1.0;
-            int besti = n;
-            for (int i = t; i < n; i += 64) {
-                if (!used[i]) {
-                    const double v = fabs(colbuf[i]);
-                    if (v > best || (v == best && i < besti)) {
-                        best = v;
-                        besti = i;
-                    }
+        for (int m = 0; m < GJ_MAXN / 64; ++m) {
+            const int i = lane + 64 * m;
+            if (i < n && !((used >> m) & 1u)) {
+                const double v = fabs(col[i]);
+                if (v > best || (v == best && i < besti)) {
+                    best = v;
+                    besti = i;
                 }
-            }
-            for (int off = 32; off > 0; off >>= 1) {
-                const double v2 = __shfl_xor(best, off);
-                const int i2 = __shfl_xor(besti, off);
-                if (v2 > best || (v2 == best && i2 < besti)) {
-                    best = v2;
-                    besti = i2;
-                }
-            }
-            if (t == 0) {
-                int pr = besti;
-                double piv = pr < n ? colbuf[pr] : 0.0;
-                if (pr >= n || piv == 0.0 || !isfinite(piv)) {
-                    atomicExch(sing, 1);
-                    if (pr >= n) pr = 0;
-                    piv = 1.0;
-                }
-                used[pr] = 1;
-                order[k] = pr;
-                pinv[pr] = k;
-                s_pr = pr;
-                s_ip = 1.0 / piv;
             }
         }
-        __syncthreads();
-        const int pr = s_pr;
-        const double ip = s_ip;
+        for (int off = 32; off > 0; off >>= 1) {
+            const double v2 = __shfl_xor(best, off);
+            const int i2 = __shfl_xor(besti, off);
+            if (v2 > best || (v2 == best && i2 < besti)) {
+                best = v2;
+                besti = i2;
+            }
+        }
+        int pr = besti;
+        double piv = pr < n ? col[pr] : 0.0;
+        if (pr >= n || piv == 0.0 || !isfinite(piv)) {
+            if (t == 0) atomicExch(sing, 1);
+            if (pr >= n) pr = 0;
+            piv = 1.0;
+        }
+        const double ip = 1.0 / piv;
+        if (lane == (pr & 63)) used |= 1u << (pr >> 6);
+        if (t == 0) {
+            order[k] = pr;
+            pinv[pr] = k;
+        }
         // the pivot row, scaled (thread row r == pr % GJ_TR holds it)
         if (r == pr % GJ_TR) {
             const int ap = pr / GJ_TR;
@@ -460,7 +457,7 @@ __global__ __launch_bounds__(GJ_NT) void k_gj_reg(const double *W, double *out, 
 #pragma unroll
         for (int a = 0; a < RA; ++a) {
             const int i = r + GJ_TR * a;
-            cb[a] = i < n ? colbuf[i] : 0.0;
+            cb[a] = i < n ? col[i] : 0.0;
         }
 #pragma unroll
         for (int bb = 0; bb < CB; ++bb) {
@@ -468,17 +465,41 @@ __global__ __launch_bounds__(GJ_NT) void k_gj_reg(const double *W, double *out, 
             rb[bb] = j < n ? rowbuf[j] : 0.0;
         }
         const double rbk = rowbuf[k];
+        // padding rows and columns (cb or rb zero) keep zeros and are never read
 #pragma unroll
         for (int a = 0; a < RA; ++a)
 #pragma unroll
-            for (int bb = 0; bb < CB; ++bb) {
-                const int i = r + GJ_TR * a, j = c + GJ_TC * bb;
-                if (i < n && j < n) {
-                    if (i == pr) w[a][bb] = rb[bb];
-                    else if (j == k) w[a][bb] = -cb[a] * rbk;
-                    else w[a][bb] = fma(-cb[a], rb[bb], w[a][bb]);
-                }
-            }
+            for (int bb = 0; bb < CB; ++bb) w[a][bb] = fma(-cb[a], rb[bb], w[a][bb]);
+        if (c == k % GJ_TC) {   // column k of the rows other than the pivot row
+            const int bk = k / GJ_TC;
+#pragma unroll
+            for (int bb = 0; bb < CB; ++bb)
+                if (bb == bk)
+#pragma unroll
+                    for (int a = 0; a < RA; ++a) w[a][bb] = -cb[a] * rbk;
+        }
+        if (r == pr % GJ_TR) {   // the pivot row
+            const int ap = pr / GJ_TR;
+#pragma unroll
+            for (int a = 0; a < RA; ++a)
+                if (a == ap)
+#pragma unroll
+                    for (int bb = 0; bb < CB; ++bb) w[a][bb] = rb[bb];
+        }
+        // column k + 1 for the next step (thread column c == (k + 1) % GJ_TC holds it)
+        const int k1 = k + 1;
+        if (k1 < n && c == k1 % GJ_TC) {
+            const int bk = k1 / GJ_TC;
+            double *nxt = colbuf + (k1 & 1) * n;
+#pragma unroll
+            for (int bb = 0; bb < CB; ++bb)
+                if (bb == bk)
+#pragma unroll
+                    for (int a = 0; a < RA; ++a) {
+                        const int i = r + GJ_TR * a;
+                        if (i < n) nxt[i] = w[a][bb];
+                    }
+        }
         __syncthreads();
     }
     // inv(A)[k][order[j]] = W[order[k]][j]: element (i, j) goes to row pinv[i], column order[j]
@@ -670,7 +691,7 @@ int launch_merge_gather(const Level &L, int nodes, int64_t child_stride, bool ro
 
 int gj_invert(double *W, double *out, int n, int nb, unsigned char *used, int *order,
               double *colbuf, double *rowbuf, int *sing, hipStream_t st) {
-    const size_t lds = (size_t)n * (2 * sizeof(double) + 2 * sizeof(int) + 1);
+    const size_t lds = gj_reg_lds(n);
     const char *env = getenv("HPS_GJ_REG");   // "0": always the batched kernels
     const bool reg = !(env && env[0] == '0') && nb > 0 && n >= 1;
 #define HPS_GJ_REG_CASE(RA, CB)                                                           \
