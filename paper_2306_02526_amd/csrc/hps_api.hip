@@ -607,8 +607,8 @@ static int build_impl(hps_op *op, const hps_coeffs *co, const hps_coeffs *co_im,
     auto gj_scratch = [&](int n, int nb, unsigned char **used, int **order, double **cb, double **rb) -> int {
         TRY(tmp.get(used, (int64_t)n * nb));
         TRY(tmp.get(order, (int64_t)n * nb));
-        TRY(tmp.get(cb, (int64_t)n * nb));
-        TRY(tmp.get(rb, (int64_t)n * nb));
+        TRY(tmp.get(cb, 2 * (int64_t)n * nb));
+        TRY(tmp.get(rb, 2 * (int64_t)n * nb));
         return HPS_OK;
     };
     // ---- leaves (Sec. 2.1, eqs. 5-6) ----

@@ -338,6 +338,92 @@ __global__ __launch_bounds__(NT) void k_gj_update(double *W, int n, int nb, int 
     else W[idx] = fma(-cb[i], rb[j], W[idx]);
 }
 
+// Update of step k and pivot of step k + 1 in one launch: the batch is read from Ws and
+// written to Wd (two copies in turn), so the first nb workgroups (`npiv`, one per matrix;
+// none after the last step) can compute step k's result for column k + 1 and for the new
+// pivot row themselves, with the same operations as the update, while the other
+// workgroups write every element.  Step k's column and row come from cbk / rbk, step
+// k + 1's go to cbn / rbn.  Bitwise the same as k_gj_update followed by k_gj_pivot.
+__global__ __launch_bounds__(NT) void k_gj_step(const double *Ws, double *Wd, int n, int nb, int k, int npiv,
+                                                unsigned char *used, int *order, const double *cbk,
+                                                const double *rbk, double *cbn, double *rbn, int *sing) {
+    const int64_t nn = (int64_t)n * n;
+    if ((int)blockIdx.x >= npiv) {
+        const int64_t idx = (int64_t)(blockIdx.x - npiv) * NT + threadIdx.x;
+        if (idx >= nn * nb) return;
+        const int b = (int)(idx / nn);
+        const int64_t rem = idx - b * nn;
+        const int j = (int)(rem / n), i = (int)(rem % n);
+        const int pr = order[(int64_t)b * n + k];
+        const double *cb = cbk + (int64_t)b * n;
+        const double *rb = rbk + (int64_t)b * n;
+        if (i == pr) Wd[idx] = rb[j];
+        else if (j == k) Wd[idx] = -cb[i] * rb[k];
+        else Wd[idx] = fma(-cb[i], rb[j], Ws[idx]);
+        return;
+    }
+    __shared__ double bv[NT];
+    __shared__ int bi[NT];
+    const int b = blockIdx.x, k1 = k + 1;
+    const double *Wb = Ws + (int64_t)b * nn;
+    const double *cb = cbk + (int64_t)b * n;
+    const double *rb = rbk + (int64_t)b * n;
+    double *cn = cbn + (int64_t)b * n;
+    unsigned char *ub = used + (int64_t)b * n;
+    const int pk = order[(int64_t)b * n + k];
+    // column k + 1 after step k (never column k itself)
+    double best = -1.0;
+    int besti = n;
+    for (int i = threadIdx.x; i < n; i += NT) {
+        const double v = (i == pk) ? rb[k1] : fma(-cb[i], rb[k1], Wb[(int64_t)k1 * n + i]);
+        cn[i] = v;
+        if (!ub[i]) {
+            const double a = fabs(v);
+            if (a > best || (a == best && i < besti)) {
+                best = a;
+                besti = i;
+            }
+        }
+    }
+    bv[threadIdx.x] = best;
+    bi[threadIdx.x] = besti;
+    __syncthreads();
+    for (int off = NT / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            const double v2 = bv[threadIdx.x + off];
+            const int i2 = bi[threadIdx.x + off];
+            if (v2 > bv[threadIdx.x] || (v2 == bv[threadIdx.x] && i2 < bi[threadIdx.x])) {
+                bv[threadIdx.x] = v2;
+                bi[threadIdx.x] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    int pr = bi[0];
+    double piv = 0.0;
+    if (pr < n) piv = cn[pr];
+    if (pr >= n || piv == 0.0 || !isfinite(piv)) {
+        if (threadIdx.x == 0) atomicExch(sing, 1);
+        if (pr >= n) pr = 0;
+        piv = 1.0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        ub[pr] = 1;
+        order[(int64_t)b * n + k1] = pr;
+    }
+    const double ip = 1.0 / piv;
+    double *rn = rbn + (int64_t)b * n;
+    // the new pivot row after step k, scaled
+    for (int j = threadIdx.x; j < n; j += NT) {
+        double v;
+        if (pr == pk) v = rb[j];
+        else if (j == k) v = -cb[pr] * rb[k];
+        else v = fma(-cb[pr], rb[j], Wb[(int64_t)j * n + pr]);
+        rn[j] = (j == k1) ? ip : v * ip;
+    }
+}
+
 __global__ void k_gj_unpermute(const double *W, double *out, int n, int nb, const int *order) {
     const int64_t nn = (int64_t)n * n;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -707,12 +793,33 @@ int gj_invert(double *W, double *out, int n, int nb, unsigned char *used, int *o
 #undef HPS_GJ_REG_CASE
     HPS_HIP(hipMemsetAsync(used, 0, (size_t)n * nb, st));
     const int64_t tot = (int64_t)n * n * nb;
-    for (int k = 0; k < n; ++k) {
-        hipLaunchKernelGGL(k_gj_pivot, dim3(nb), dim3(NT), 0, st, W, n, k, used, order, colbuf, rowbuf, sing);
+    const char *fenv = getenv("HPS_GJ_FUSED");   // "0": one pivot and one update launch per step
+    if (fenv && fenv[0] == '0') {
+        for (int k = 0; k < n; ++k) {
+            hipLaunchKernelGGL(k_gj_pivot, dim3(nb), dim3(NT), 0, st, W, n, k, used, order, colbuf, rowbuf, sing);
+            HPS_LAUNCHED();
+            hipLaunchKernelGGL(k_gj_update, dim3(nblk(tot)), dim3(NT), 0, st, W, n, nb, k,
+                               (const int *)order, (const double *)colbuf, (const double *)rowbuf);
+            HPS_LAUNCHED();
+        }
+    } else {
+        // the batch alternates between W and out (out holds no data before the end); the
+        // column and row buffers hold two halves of n * nb, one per step parity
+        const int64_t half = (int64_t)n * nb;
+        hipLaunchKernelGGL(k_gj_pivot, dim3(nb), dim3(NT), 0, st, W, n, 0, used, order, colbuf, rowbuf, sing);
         HPS_LAUNCHED();
-        hipLaunchKernelGGL(k_gj_update, dim3(nblk(tot)), dim3(NT), 0, st, W, n, nb, k,
-                           (const int *)order, (const double *)colbuf, (const double *)rowbuf);
-        HPS_LAUNCHED();
+        double *buf[2] = {W, out};
+        for (int k = 0; k < n; ++k) {
+            const int npiv = k + 1 < n ? nb : 0;
+            const int h = k & 1;
+            hipLaunchKernelGGL(k_gj_step, dim3((unsigned)(npiv + nblk(tot))), dim3(NT), 0, st,
+                               (const double *)buf[h], buf[h ^ 1], n, nb, k, npiv, used, order,
+                               (const double *)(colbuf + h * half), (const double *)(rowbuf + h * half),
+                               colbuf + (h ^ 1) * half, rowbuf + (h ^ 1) * half, sing);
+            HPS_LAUNCHED();
+        }
+        // after n steps the batch is in buf[n & 1]; the unpermutation reads W
+        if (n & 1) HPS_HIP(hipMemcpyAsync(W, out, sizeof(double) * tot, hipMemcpyDeviceToDevice, st));
     }
     hipLaunchKernelGGL(k_gj_unpermute, dim3(nblk(tot)), dim3(NT), 0, st, (const double *)W, out, n, nb,
                        (const int *)order);

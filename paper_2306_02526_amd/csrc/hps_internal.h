@@ -445,6 +445,10 @@ int launch_leaf_T_cx(const hps_op *op, const double *S, double *T, hipStream_t s
 // sets *flag (device int, zero beforehand) when some coefficient differs from its value at
 // node 0
 int launch_coef_uniform(const double *coef, int64_t n, int *flag, hipStream_t st);
+// out = inverse of each of the nb n x n matrices in W (column-major, partial pivoting; W is
+// overwritten, out serves as the second copy of the batch while the pivot steps run);
+// scratch: used [n nb] bytes, order [n nb], colbuf and rowbuf [2 n nb] each; *sing is set
+// when a pivot is zero or not finite
 int gj_invert(double *W, double *out, int n, int nb, unsigned char *used, int *order,
               double *colbuf, double *rowbuf, int *sing, hipStream_t st);
 int launch_leaf_S(const hps_op *op, const double *ainv, double *S, hipStream_t st);

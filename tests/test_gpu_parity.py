@@ -450,18 +450,21 @@ def test_graph_replay_equals_eager_steps(torch, monkeypatch):
                          ids=["8x8_p10", "16x16_p16", "4x8_p12", "2x2_p24", "32x8_p7"])
 def test_register_gauss_jordan_equals_batched(torch, monkeypatch, n1, n2, p):
     """The build inverts with one matrix per workgroup held in registers when it fits
-    (n <= 208) and with the batched kernels otherwise; both perform the same operations in
-    the same order, so operators built either way give bitwise equal solves."""
+    (n <= 208) and with the batched kernels otherwise, whose pivot steps run as one launch
+    each (update and next pivot fused, the batch in two copies) or as two; all perform the
+    same operations in the same order, so operators built any way give bitwise equal
+    solves (odd and even orders, the batched path for every matrix or only above 208)."""
     say(f"[build] register vs batched Gauss-Jordan, {n1}x{n2} p={p}")
     rng = np.random.default_rng(n1 + 7 * p)
     outs = []
-    for mode in ("0", "1"):
+    for mode, fused in (("0", "0"), ("0", "1"), ("1", "1")):
         monkeypatch.setenv("HPS_GJ_REG", mode)
+        monkeypatch.setenv("HPS_GJ_FUSED", fused)
         g, og, x, y, co, op = setup(torch, n1, n2, p, 2e-3)
-        if mode == "0":
+        if not outs:
             body = torch.tensor(rng.standard_normal(og.n_int), device="cuda")
             dirichlet = torch.tensor(rng.standard_normal(op.n_bdry), device="cuda")
         outs.append(hps.hps_solve(op, body, dirichlet))
         torch.cuda.synchronize()
         op.free()
-    assert torch.equal(outs[0], outs[1])
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
