@@ -249,29 +249,67 @@ static int dev_alloc(hps_op *op, T **ptr, int64_t n, bool track = true) {
     return HPS_OK;
 }
 
-template <typename T>
-static int upload(hps_op *op, T **ptr, const std::vector<T> &v, hipStream_t st) {
-    TRY(dev_alloc(op, ptr, (int64_t)v.size()));
-    if (!v.empty())
-        HPS_HIP(hipMemcpyAsync(*ptr, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+hps::HostStage::~HostStage() {
+    if (!chunks.empty()) (void)hipStreamSynchronize(st);
+    for (void *c : chunks) (void)hipHostFree(c);
+}
+
+int hps::HostStage::copy(void *dst, const void *src, size_t bytes) {
+    if (bytes == 0) return HPS_OK;
+    if (chunks.empty() || used + bytes > cap) {
+        const size_t want = std::max<size_t>(bytes, size_t(8) << 20);
+        void *c = nullptr;
+        if (hipHostMalloc(&c, want, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            hps_set_error("hipHostMalloc of %zu bytes for the build's staging failed", want);
+            return HPS_ENOMEM;
+        }
+        chunks.push_back(c);
+        used = 0;
+        cap = want;
+    }
+    unsigned char *p = static_cast<unsigned char *>(chunks.back()) + used;
+    std::memcpy(p, src, bytes);
+    used += (bytes + 255) & ~size_t(255);
+    HPS_HIP(hipMemcpyAsync(dst, p, bytes, hipMemcpyHostToDevice, st));
     return HPS_OK;
 }
 
-struct TempBuf {   // device scratch freed at scope exit
+template <typename T>
+static int upload(hps_op *op, T **ptr, const std::vector<T> &v, hipStream_t st) {
+    TRY(dev_alloc(op, ptr, (int64_t)v.size()));
+    if (v.empty()) return HPS_OK;
+    if (op->stage) return op->stage->copy(*ptr, v.data(), sizeof(T) * v.size());
+    HPS_HIP(hipMemcpyAsync(*ptr, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+    return HPS_OK;
+}
+
+// device scratch of the build, allocated and freed in stream order (a plain hipFree would
+// wait for the whole device), freed at scope exit at the latest
+struct TempBuf {
+    hipStream_t st;
     std::vector<void *> ptrs;
+    explicit TempBuf(hipStream_t s) : st(s) {}
     ~TempBuf() {
-        for (void *p : ptrs) (void)hipFree(p);
+        for (void *p : ptrs) (void)hipFreeAsync(p, st);
     }
     template <typename T>
     int get(T **ptr, int64_t n) {
-        TRY(dev_alloc<T>(nullptr, ptr, n, false));
+        *ptr = nullptr;
+        const size_t bytes = sizeof(T) * (size_t)std::max<int64_t>(n, 1);
+        if (hipMallocAsync((void **)ptr, bytes, st) != hipSuccess) {
+            (void)hipGetLastError();
+            *ptr = nullptr;
+            hps_set_error("hipMallocAsync of %zu bytes of build scratch failed", bytes);
+            return HPS_ENOMEM;
+        }
         ptrs.push_back(*ptr);
         return HPS_OK;
     }
     void release(void *p) {
         auto it = std::find(ptrs.begin(), ptrs.end(), p);
         if (it != ptrs.end()) {
-            (void)hipFree(*it);
+            (void)hipFreeAsync(*it, st);
             ptrs.erase(it);
         }
     }
@@ -603,7 +641,7 @@ static int build_impl(hps_op *op, const hps_coeffs *co, const hps_coeffs *co_im,
         CHECK_ARG(hdiff == 0, "HPS_UNIFORM_COEFFS: the coefficients of L vary over the nodes");
     }
 
-    TempBuf tmp;
+    TempBuf tmp(st);
     auto gj_scratch = [&](int n, int nb, unsigned char **used, int **order, double **cb, double **rb) -> int {
         TRY(tmp.get(used, (int64_t)n * nb));
         TRY(tmp.get(order, (int64_t)n * nb));
@@ -873,7 +911,13 @@ int hps::build_op_tiled(const hps_grid *grid, const hps_coeffs *coeffs, const hp
     // them); HPS_COMPOSE=0 turns them off, HPS_COMPOSE=1 on whatever the tuner chose
     const char *cenv = getenv("HPS_COMPOSE");
     op->composed = cenv && cenv[0] ? cenv[0] == '1' : compose != 0;
-    int rc = build_impl(op, coeffs, coeffs_im, (hipStream_t)stream);
+    int rc;
+    {
+        HostStage stage((hipStream_t)stream);   // synchronizes and frees at scope exit
+        op->stage = &stage;
+        rc = build_impl(op, coeffs, coeffs_im, (hipStream_t)stream);
+        op->stage = nullptr;
+    }
     if (rc) {
         (void)hipDeviceSynchronize();
         hps_free(op);

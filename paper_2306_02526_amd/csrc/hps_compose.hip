@@ -85,17 +85,30 @@ struct Pos {
     int b(int j) const { return j < c.n1 ? 2 * nbcc + c.a1[j] : 3 * nbcc + c.b2[j - c.n1]; }
 };
 
+// host table to device memory: through the build's pinned staging when there is one (the
+// copy stays in flight), else a plain copy that the caller waits for before the table dies
+template <typename T>
+int table_copy(const hps_op *op, T *dst, const std::vector<T> &v, hipStream_t st) {
+    if (v.empty()) return HPS_OK;
+    if (op->stage) return op->stage->copy(dst, v.data(), sizeof(T) * v.size());
+    HPS_HIP(hipMemcpyAsync(dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
+    return HPS_OK;
+}
+
+// scratch allocated and freed in the stream's order (no device-wide wait)
 struct DevScratch {
+    hipStream_t st;
     std::vector<void *> p;
+    explicit DevScratch(hipStream_t s) : st(s) {}
     ~DevScratch() {
-        for (void *q : p) (void)hipFree(q);
+        for (void *q : p) (void)hipFreeAsync(q, st);
     }
     template <typename T>
     int get(T **out, int64_t n) {
         void *q = nullptr;
-        if (hipMalloc(&q, sizeof(T) * std::max<int64_t>(n, 1)) != hipSuccess) {
+        if (hipMallocAsync(&q, sizeof(T) * std::max<int64_t>(n, 1), st) != hipSuccess) {
             (void)hipGetLastError();
-            hps_set_error("hipMalloc of %lld bytes for composite operators failed", (long long)(sizeof(T) * n));
+            hps_set_error("hipMallocAsync of %lld bytes for composite operators failed", (long long)(sizeof(T) * n));
             return HPS_ENOMEM;
         }
         p.push_back(q);
@@ -103,12 +116,13 @@ struct DevScratch {
         return HPS_OK;
     }
     template <typename T>
-    int upload(T **out, const std::vector<T> &v, hipStream_t st) {
+    int upload(const hps_op *op, T **out, const std::vector<T> &v) {
         TRY(get(out, (int64_t)v.size()));
-        HPS_HIP(hipMemcpyAsync(*out, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, st));
-        return HPS_OK;
+        return table_copy(op, *out, v, st);
     }
 };
+
+
 
 int64_t level_nodes(int l) { return int64_t(1) << l; }
 
@@ -177,16 +191,16 @@ int hps::compose_pair(hps_op *op, int l, const std::vector<HostLevel> &hl, const
     const bool uni = op->build_one;
     const int nb = uni ? 1 : nt;   // nodes whose composites are computed
     const bool top = (l == 0);
-    DevScratch tmp;
+    DevScratch tmp(st);
     // index vectors on the device: the upper level's maps, padded to its boundary length
     std::vector<int> a1pad(n12t, -1), b2pad(n12t, -1);
     for (int m = 0; m < n1t; ++m) a1pad[m] = T.a1[m];
     for (int m = n1t; m < n12t; ++m) b2pad[m] = T.b2[m - n1t];
     int *d_a3, *d_b3, *d_a1pad, *d_b2pad;
-    TRY(tmp.upload(&d_a3, T.a3, st));
-    TRY(tmp.upload(&d_b3, T.b3, st));
-    TRY(tmp.upload(&d_a1pad, a1pad, st));
-    TRY(tmp.upload(&d_b2pad, b2pad, st));
+    TRY(tmp.upload(op, &d_a3, T.a3));
+    TRY(tmp.upload(op, &d_b3, T.b3));
+    TRY(tmp.upload(op, &d_a1pad, a1pad));
+    TRY(tmp.upload(op, &d_b2pad, b2pad));
     const int64_t sX = (int64_t)n3c * n3c, sU = (int64_t)n12c * n3c, sS = (int64_t)n3c * n12c;   // per child
     const int64_t cb = uni ? 0 : 1;   // the second child's operators follow the first's
     const double *Xa = Xc, *Xb = Xc + cb * sX, *Ua = Uc, *Ub = Uc + cb * sU, *Sa = Sc, *Sb = Sc + cb * sS;
@@ -378,10 +392,11 @@ int hps::compose_pair(hps_op *op, int l, const std::vector<HostLevel> &hl, const
         return HPS_ENOMEM;
     }
     op->allocs.push_back(d_tab);
-    HPS_HIP(hipMemcpyAsync(d_tab, tab.data(), sizeof(int) * tab.size(), hipMemcpyHostToDevice, st));
+    TRY(table_copy(op, d_tab, tab, st));
     P.tab = d_tab;
-    // the scratch above is freed at return: the stream must be done with it
-    HPS_HIP(hipStreamSynchronize(st));
+    // without the build's staging the host tables above die at return while their copies
+    // may still be in flight (the device scratch is freed in stream order either way)
+    if (!op->stage) HPS_HIP(hipStreamSynchronize(st));
     op->pairs.push_back(P);
     return HPS_OK;
 }
@@ -476,7 +491,7 @@ int hps::build_direct(hps_op *op, hipStream_t st) {
     op->total_bytes += pn.bytes();
     pn.data = d;
     // M column by column: the operator's FP64 sweep of each unit flux vector
-    DevScratch tmp;
+    DevScratch tmp(st);
     double *M = nullptr;
     TRY(tmp.get(&M, R * C));
     const unsigned gz = (unsigned)std::min<int64_t>((C + NT - 1) / NT, 1024), gr = (unsigned)((R + NT - 1) / NT);

@@ -132,6 +132,22 @@ struct ProfScope {
     ~ProfScope();
 };
 
+// Pinned host staging for the build's host-to-device copies: a copy from pageable memory
+// is not asynchronous and waits for the stream to drain, which would leave the GPU idle
+// while the host prepares the next level.  copy() puts the data into pinned chunks and
+// enqueues the copy on the stream; the destructor synchronizes the stream, then frees the
+// chunks.
+struct HostStage {
+    hipStream_t st = nullptr;
+    std::vector<void *> chunks;
+    size_t used = 0, cap = 0;
+    explicit HostStage(hipStream_t s) : st(s) {}
+    HostStage(const HostStage &) = delete;
+    HostStage &operator=(const HostStage &) = delete;
+    ~HostStage();
+    int copy(void *dst, const void *src, size_t bytes);
+};
+
 }  // namespace hps
 
 struct hps_op {
@@ -179,6 +195,7 @@ struct hps_op {
     double *ir_ubc = nullptr;              // [nleaves][4q] running boundary values of a refined solve
     int64_t operator_bytes = 0, total_bytes = 0;
     std::vector<void *> allocs;
+    hps::HostStage *stage = nullptr;   // during the build: staging of host tables
     mutable hps::Profiler prof;
     // solve buffers of right-hand sides 1..3 of a multi-right-hand-side hps_solve (made by
     // its first call; right-hand side 0 uses the operator's own)
