@@ -601,7 +601,8 @@ __global__ __launch_bounds__(GJ_NT) void k_gj_reg(const double *W, double *out, 
 
 // ---- batched FP64 GEMM on the matrix cores ----------------------------------------------
 // C = alpha A B + beta C, column-major, 64x64 tile per workgroup, each wave a 32x32
-// sub-tile of 2x2 v_mfma_f64_16x16x4 blocks; K staged through LDS 16 at a time.
+// sub-tile of 2x2 v_mfma_f64_16x16x4 blocks; K staged through LDS 16 at a time, the next
+// 16 loaded into registers while the current ones are multiplied (one barrier per step).
 typedef double dvec4 __attribute__((ext_vector_type(4)));
 
 struct GemmArgs {
@@ -614,8 +615,12 @@ struct GemmArgs {
 
 __global__ __launch_bounds__(NT) void k_dgemm(GemmArgs g) {
     constexpr int TM = 64, TN = 64, TK = 16;
-    __shared__ double As[TK][TM + 1];
-    __shared__ double Bs[TK][TN + 1];
+    constexpr int LA = TM * TK / NT, LB = TN * TK / NT;   // elements per thread and tile
+    static_assert(NT == 256 && LA == 4 && LB == 4, "tile loads assume 256 threads");
+    // two LDS buffers: the tile in use and the next one; the next tile's global loads are
+    // in flight in registers while the matrix cores work on the current one
+    __shared__ double As[2][TK][TM + 1];
+    __shared__ double Bs[2][TK][TN + 1];
     const int bz = blockIdx.z;
     const double *A = g.A + bz * g.sA;
     const double *B = g.B + bz * g.sB;
@@ -623,36 +628,48 @@ __global__ __launch_bounds__(NT) void k_dgemm(GemmArgs g) {
     const int m0 = blockIdx.x * TM, n0 = blockIdx.y * TN;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int wm = wave & 1, wn = wave >> 1;
+    // this thread's tile elements: A rows ai, k rows ak + 4 r; B k row bk, columns bj + 16 r
+    const int ai = t % TM, ak = t / TM, bk = t % TK, bj = t / TK;
+    double ra[LA], rb[LB];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < LA; ++r) {
+            const int gm = m0 + ai, gk = k0 + ak + 4 * r;
+            ra[r] = (gm < g.M && gk < g.K) ? A[(int64_t)gk * g.lda + gm] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < LB; ++r) {
+            const int gn = n0 + bj + 16 * r, gk = k0 + bk;
+            rb[r] = (gn < g.N && gk < g.K) ? B[(int64_t)gn * g.ldb + gk] : 0.0;
+        }
+    };
     dvec4 acc[2][2];
     for (int x = 0; x < 2; ++x)
         for (int y = 0; y < 2; ++y) acc[x][y] = dvec4{0.0, 0.0, 0.0, 0.0};
+    load(0);
+    int buf = 0;
     for (int k0 = 0; k0 < g.K; k0 += TK) {
-        for (int e = t; e < TM * TK; e += NT) {
-            const int i = e % TM, kk = e / TM;
-            const int gm = m0 + i, gk = k0 + kk;
-            As[kk][i] = (gm < g.M && gk < g.K) ? A[(int64_t)gk * g.lda + gm] : 0.0;
-        }
-        for (int e = t; e < TN * TK; e += NT) {
-            const int kk = e % TK, j = e / TK;
-            const int gn = n0 + j, gk = k0 + kk;
-            Bs[kk][j] = (gn < g.N && gk < g.K) ? B[(int64_t)gn * g.ldb + gk] : 0.0;
-        }
+#pragma unroll
+        for (int r = 0; r < LA; ++r) As[buf][ak + 4 * r][ai] = ra[r];
+#pragma unroll
+        for (int r = 0; r < LB; ++r) Bs[buf][bk][bj + 16 * r] = rb[r];
         __syncthreads();
+        if (k0 + TK < g.K) load(k0 + TK);
         const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
         for (int kk = 0; kk < TK; kk += 4) {
             double av[2], bv[2];
 #pragma unroll
-            for (int x = 0; x < 2; ++x) av[x] = As[kk + lk][wm * 32 + x * 16 + li];
+            for (int x = 0; x < 2; ++x) av[x] = As[buf][kk + lk][wm * 32 + x * 16 + li];
 #pragma unroll
-            for (int y = 0; y < 2; ++y) bv[y] = Bs[kk + lk][wn * 32 + y * 16 + li];
+            for (int y = 0; y < 2; ++y) bv[y] = Bs[buf][kk + lk][wn * 32 + y * 16 + li];
 #pragma unroll
             for (int x = 0; x < 2; ++x)
 #pragma unroll
                 for (int y = 0; y < 2; ++y)
                     acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[x], bv[y], acc[x][y], 0, 0, 0);
         }
-        __syncthreads();
+        buf ^= 1;
     }
     // v_mfma_f64_16x16x4: lane l, register r holds D[l/16 + 4r][l%16]
     const int cj = lane & 15, ci = lane >> 4;
